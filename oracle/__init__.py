@@ -1,0 +1,218 @@
+"""CPU oracle for the quasi-static slice step -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It wraps ``liboracle_wandqs.so`` (plain
+FP64 C++, single threaded, see ``wandqs_oracle.cpp``) with numpy arrays.  It
+shares no code with the GPU library in ``paper_2012_00881_amd``.
+
+Every function is pinned by ``tests/test_oracle_*.py`` against facts fixed by the
+paper or by mathematics (closed forms, dense direct solves, invariants).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle_wandqs.so")
+_lib = None
+
+FIELDS = ("psi", "Ez", "Bz", "Bx", "By")
+MOMENTS = ("n", "jx", "jy", "Txx", "Txy", "Tyy")
+EXTRA = ("k2", "fBx", "fBy", "jz")
+
+OK, INVALID, NOCONV, NONPHYS = 0, -1, -4, -5
+
+_dp = C.POINTER(C.c_double)
+
+
+class Beam(C.Structure):
+    _fields_ = [("kind", C.c_int), ("amp", C.c_double), ("sigma_r", C.c_double),
+                ("sigma_z", C.c_double), ("xi_c", C.c_double), ("x0", C.c_double),
+                ("y0", C.c_double), ("n_bins", C.c_int), ("r_max", C.c_double),
+                ("bin_amp", _dp)]
+
+
+class Cfg(C.Structure):
+    _fields_ = [("n_cells", C.c_int), ("half_width", C.c_double), ("ppc", C.c_int),
+                ("n0", C.c_double), ("dxi0", C.c_double), ("adaptive", C.c_int),
+                ("refine_k", C.c_int), ("mg_rtol", C.c_double), ("mg_atol", C.c_double),
+                ("mg_max_cycles", C.c_int), ("nu_pre", C.c_int), ("nu_post", C.c_int),
+                ("n_beams", C.c_int), ("beams", C.POINTER(Beam))]
+
+
+class Info(C.Structure):
+    _fields_ = [("xi", C.c_double), ("dxi", C.c_double), ("dxi_next", C.c_double),
+                ("vmax", C.c_double), ("cycles", C.c_int * 5), ("rel_resid", C.c_double * 5),
+                ("invariant_err", C.c_double), ("status", C.c_int)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(_LIB_PATH)
+        L.oracle_next_dxi.restype = C.c_double
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Oracle:
+    """Holds one workload (a dict from ``wandqs_inputs.config``) as a C config."""
+
+    def __init__(self, cfg: dict):
+        self.cfg = cfg
+        self.N = int(cfg["n_cells"])
+        self.L = float(cfg["half_width"])
+        self.h = 2.0 * self.L / self.N
+        self.nn = (self.N + 1) ** 2
+        self._keep = []
+        beams = (Beam * max(1, len(cfg["beams"])))()
+        for k, b in enumerate(cfg["beams"]):
+            bb = beams[k]
+            bb.x0, bb.y0 = b.get("x0", 0.0), b.get("y0", 0.0)
+            bb.sigma_z, bb.xi_c = b["sigma_z"], b["xi_c"]
+            if b["kind"] == "gauss":
+                bb.kind, bb.amp, bb.sigma_r = 0, b["amp"], b["sigma_r"]
+            else:
+                amp = _f64(b["bin_amp"])
+                self._keep.append(amp)
+                bb.kind, bb.n_bins, bb.r_max, bb.bin_amp = 1, amp.size, b["r_max"], _p(amp)
+                bb.amp, bb.sigma_r = 1.0, 1.0
+        self._beams = beams
+        c = Cfg()
+        c.n_cells, c.half_width = self.N, self.L
+        c.ppc = int(cfg["ppc_side"]) ** 2
+        c.n0, c.dxi0 = cfg.get("n0", 1.0), cfg["dxi0"]
+        c.adaptive, c.refine_k = int(cfg["adaptive"]), int(cfg["refine_k"])
+        c.mg_rtol, c.mg_atol = cfg["mg_rtol"], cfg["mg_atol"]
+        c.mg_max_cycles, c.nu_pre, c.nu_post = cfg["mg_max_cycles"], cfg["nu_pre"], cfg["nu_post"]
+        c.n_beams, c.beams = len(cfg["beams"]), beams
+        self.c = c
+
+    # ---------------------------------------------------------------- pieces
+    def deposit(self, x, y, q=None):
+        x, y = _f64(x), _f64(y)
+        q = None if q is None else _f64(q)
+        out = np.zeros(self.nn)
+        lib().oracle_deposit(C.byref(self.c), x.size, _p(x), _p(y), _p(q), _p(out))
+        return out.reshape(self.N + 1, self.N + 1)
+
+    def gather(self, x, y, F):
+        x, y, F = _f64(x), _f64(y), _f64(F)
+        out = np.zeros(x.size)
+        lib().oracle_gather(C.byref(self.c), x.size, _p(x), _p(y), _p(F), _p(out))
+        return out
+
+    def beam_density(self, xi):
+        out = np.zeros(self.nn)
+        lib().oracle_beam_density(C.byref(self.c), C.c_double(xi), _p(out))
+        return out.reshape(self.N + 1, self.N + 1)
+
+    def assemble(self, xi, moments, psi, Ez, Bz):
+        mom = _f64(moments).reshape(6, -1)
+        out = np.zeros((4, self.nn))
+        st = lib().oracle_assemble(C.byref(self.c), C.c_double(xi), _p(mom), _p(_f64(psi)),
+                                   _p(_f64(Ez)), _p(_f64(Bz)), _p(out))
+        return st, out.reshape(4, self.N + 1, self.N + 1)
+
+    def next_dxi(self, vmax):
+        return lib().oracle_next_dxi(C.byref(self.c), C.c_double(vmax))
+
+    # ----------------------------------------------------------------- slice
+    def slice_step(self, state: dict, want_moments=False, carry_pz=False):
+        """Advance ``state`` (dict x, y, px, py, fields[5,N+1,N+1], xi, dxi[, pz]) in place."""
+        for k in ("x", "y", "px", "py"):
+            state[k] = _f64(state[k]).copy() if not state[k].flags.writeable else _f64(state[k])
+        state["fields"] = _f64(state["fields"]).reshape(5, self.N + 1, self.N + 1)
+        xi = C.c_double(state["xi"])
+        dxi = C.c_double(state["dxi"])
+        info = Info()
+        mom = np.zeros((6, self.nn)) if want_moments else None
+        extra = np.zeros((4, self.nn)) if want_moments else None
+        pz = None
+        if carry_pz:
+            if "pz" not in state:
+                state["pz"] = np.zeros_like(state["x"])
+            pz = state["pz"]
+        st = lib().oracle_slice_step(C.byref(self.c), state["x"].size, _p(state["x"]),
+                                     _p(state["y"]), _p(state["px"]), _p(state["py"]), _p(pz),
+                                     _p(state["fields"]), C.byref(xi), C.byref(dxi),
+                                     C.byref(info), _p(mom), _p(extra))
+        state["xi"], state["dxi"] = xi.value, dxi.value
+        out = dict(status=st, info=info)
+        if want_moments:
+            out["moments"] = mom.reshape(6, self.N + 1, self.N + 1)
+            out["extra"] = extra.reshape(4, self.N + 1, self.N + 1)
+        return out
+
+    def run(self, state: dict, n_slices: int, keep_fields=False, carry_pz=False):
+        infos = (Info * n_slices)()
+        hist = np.zeros((n_slices, 5, self.nn)) if keep_fields else None
+        state["fields"] = _f64(state["fields"]).reshape(5, self.N + 1, self.N + 1)
+        pz = None
+        if carry_pz:
+            if "pz" not in state:
+                state["pz"] = np.zeros_like(state["x"])
+            pz = state["pz"]
+        xi = C.c_double(state["xi"])
+        dxi = C.c_double(state["dxi"])
+        st = lib().oracle_run(C.byref(self.c), state["x"].size, _p(state["x"]), _p(state["y"]),
+                              _p(state["px"]), _p(state["py"]), _p(pz), _p(state["fields"]),
+                              C.byref(xi), C.byref(dxi), n_slices, _p(hist), infos)
+        state["xi"], state["dxi"] = xi.value, dxi.value
+        res = dict(status=st, infos=list(infos))
+        if keep_fields:
+            res["fields"] = hist.reshape(n_slices, 5, self.N + 1, self.N + 1)
+        return res
+
+
+def initial_state(cfg: dict) -> dict:
+    """Cold plasma at rest at xi = 0 with zero fields (uses the shared input generator)."""
+    import wandqs_inputs as wi
+    x, y, px, py = wi.plasma_lattice(cfg["n_cells"], cfg["half_width"], cfg["ppc_side"],
+                                     cfg["jitter"], cfg["seed"])
+    N = cfg["n_cells"]
+    return dict(x=x, y=y, px=px, py=py, fields=np.zeros((5, N + 1, N + 1)), xi=0.0,
+                dxi=float(cfg["dxi0"]))
+
+
+def apply(N, h, u, k2=None):
+    """L_h u - k2 u at interior nodes (zero on the boundary)."""
+    u = _f64(u)
+    out = np.zeros_like(u)
+    lib().oracle_apply(int(N), C.c_double(h), _p(None if k2 is None else _f64(k2)), _p(u),
+                       _p(out))
+    return out
+
+
+def mg_solve(N, h, f, u0=None, k2=None, rtol=1e-14, atol=1e-14, max_cycles=50, nu1=2, nu2=2):
+    """Multigrid solve of (L_h - k2) u = f with zero Dirichlet boundary."""
+    f = _f64(f)
+    u = np.zeros_like(f) if u0 is None else _f64(u0).copy()
+    cyc = C.c_int(0)
+    rel = C.c_double(0)
+    st = lib().oracle_mg_solve(int(N), C.c_double(h), _p(None if k2 is None else _f64(k2)),
+                               _p(f), _p(u), C.c_double(rtol), C.c_double(atol), int(max_cycles),
+                               int(nu1), int(nu2), C.byref(cyc), C.byref(rel))
+    return st, u, cyc.value, rel.value
+
+
+def push(L, dxi, g_i, gx, gy, Bx, By, Bz, x, y, px, py):
+    arrs = [_f64(a).copy() for a in (x, y, px, py)]
+    ins = [_f64(a) for a in (g_i, gx, gy, Bx, By, Bz)]
+    lib().oracle_push(C.c_double(L), C.c_double(dxi), arrs[0].size, *[_p(a) for a in ins],
+                      *[_p(a) for a in arrs])
+    return arrs

@@ -1,0 +1,660 @@
+/*
+ * wandqs oracle -- TEST INFRASTRUCTURE ONLY, NOT THE PRODUCT.
+ *
+ * A plain, slow, single-threaded FP64 CPU implementation of one quasi-static
+ * xi-slice step of plasma electrons driven by a frozen luminal beam, after
+ * T. Wang, V. Khudik, J. Kim, G. Shvets, "WAND-PIC: an accelerated
+ * three-dimensional quasi-static particle-in-cell code" (arXiv 2012.00881).
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg may load
+ * it.  It shares no code, header or constant with the GPU library.
+ *
+ * Units: time 1/omega_p, length 1/k_p, momenta mc, fields mc omega_p/e,
+ * density n0, current -e n0 c (paper Sec. III, opening paragraph).
+ *
+ * Discretisation (the paper is silent on these; the readings are listed in the
+ * design notes of the repository):
+ *  - vertex-centred transverse grid x_a = -L + a h, a = 0..N (same in y),
+ *    all five fields zero on the boundary nodes;
+ *  - cloud-in-cell (bilinear) deposit and gather;
+ *  - central differences at interior nodes, one-sided at boundary nodes only
+ *    for the gradient of psi used by the particle gather;
+ *  - 5-point Laplacian of Sec. VII.B, eq. (33);
+ *  - geometric multigrid: V(nu1,nu2) cycles, red-black Gauss-Seidel, full
+ *    weighting, bilinear prolongation, rediscretised coarse operators, exact
+ *    solve on the 2x2-cell grid (Sec. II item 4 and Sec. VII.A).
+ *
+ * Array layout: node (a, b) of an (N+1)x(N+1) array is element b*(N+1)+a
+ * (x index fastest).  Field order: psi, Ez, Bz, Bx, By.
+ *
+ * Parity status of each function is recorded in the design notes; every
+ * function here is pinned by a test in tests/test_oracle_*.py.
+ */
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+extern "C" {
+
+typedef struct {
+    int kind;             /* 0: Gaussian, 1: piecewise-constant radial bins */
+    double amp, sigma_r, sigma_z, xi_c, x0, y0;
+    int n_bins;           /* kind 1 only */
+    double r_max;         /* kind 1 only: bins of width r_max/n_bins on [0, r_max) */
+    const double* bin_amp;/* kind 1 only */
+} oracle_beam;
+
+typedef struct {
+    int n_cells;          /* N */
+    double half_width;    /* L: box [-L, L]^2 */
+    int ppc;              /* macroparticles per cell (weight n0 h^2 / ppc) */
+    double n0;            /* plasma (and ion background) density */
+    double dxi0;          /* initial step of Algorithm 1 */
+    int adaptive;         /* Step_Size_Refinement on/off */
+    int refine_k;         /* floor dxi >= dxi0/k (0: no floor) */
+    double mg_rtol, mg_atol;
+    int mg_max_cycles, nu_pre, nu_post;
+    int n_beams;
+    const oracle_beam* beams;
+} oracle_cfg;
+
+typedef struct {
+    double xi, dxi, dxi_next, vmax;
+    int cycles[5];
+    double rel_resid[5];
+    double invariant_err;  /* max |gamma - p_z - (1+psi)| when p_z is carried */
+    int status;            /* 0 ok, -4 multigrid did not converge, -5 1+psi <= 0 */
+} oracle_info;
+
+enum { ORC_OK = 0, ORC_INVALID = -1, ORC_NOCONV = -4, ORC_NONPHYS = -5 };
+
+} /* extern "C" */
+
+namespace {
+
+/* ------------------------------------------------------------------ grid -- */
+
+struct Grid {
+    int N;
+    double L, h;
+    Grid(int n, double l) : N(n), L(l), h(2.0 * l / n) {}
+    int nn() const { return (N + 1) * (N + 1); }
+    int id(int a, int b) const { return b * (N + 1) + a; }
+    double xa(int a) const { return -L + a * h; }
+};
+
+/* Cloud-in-cell shape: cell index c in [0, N-1] and offset d in [0, 1] so that
+ * the particle weights node c by (1 - d) and node c+1 by d. */
+void cic(const Grid& g, double x, int& c, double& d) {
+    double t = (x + g.L) / g.h;
+    int k = (int)std::floor(t);
+    if (k < 0) k = 0;
+    if (k > g.N - 1) k = g.N - 1;
+    c = k;
+    d = t - k;
+}
+
+/* deposit(q)[a,b] = sum_i w q_i W_a(x_i) W_b(y_i) / h^2 with w = n0 h^2 / ppc.
+ * With q = 1 this is the surface density n* of Sec. III.B (n* = int f* dP). */
+void deposit(const Grid& g, const oracle_cfg& c, int P, const double* x, const double* y,
+             const double* q, double* out) {
+    const double w = c.n0 * g.h * g.h / c.ppc;
+    std::fill(out, out + g.nn(), 0.0);
+    for (int i = 0; i < P; ++i) {
+        int a, b;
+        double dx, dy;
+        cic(g, x[i], a, dx);
+        cic(g, y[i], b, dy);
+        double s = w * (q ? q[i] : 1.0) / (g.h * g.h);
+        out[g.id(a, b)] += s * (1.0 - dx) * (1.0 - dy);
+        out[g.id(a + 1, b)] += s * dx * (1.0 - dy);
+        out[g.id(a, b + 1)] += s * (1.0 - dx) * dy;
+        out[g.id(a + 1, b + 1)] += s * dx * dy;
+    }
+}
+
+/* gather(F)_i = sum over the four cell corners of F W_a W_b. */
+double gather1(const Grid& g, const double* F, double x, double y) {
+    int a, b;
+    double dx, dy;
+    cic(g, x, a, dx);
+    cic(g, y, b, dy);
+    return F[g.id(a, b)] * (1.0 - dx) * (1.0 - dy) + F[g.id(a + 1, b)] * dx * (1.0 - dy) +
+           F[g.id(a, b + 1)] * (1.0 - dx) * dy + F[g.id(a + 1, b + 1)] * dx * dy;
+}
+
+/* Central differences D_x u, D_y u at interior nodes. */
+double Dx(const Grid& g, const double* u, int a, int b) {
+    return (u[g.id(a + 1, b)] - u[g.id(a - 1, b)]) / (2.0 * g.h);
+}
+double Dy(const Grid& g, const double* u, int a, int b) {
+    return (u[g.id(a, b + 1)] - u[g.id(a, b - 1)]) / (2.0 * g.h);
+}
+
+/* ------------------------------------------------------------- multigrid -- */
+
+/* One level of the hierarchy for  L_h u - k2 u = f  on the interior nodes,
+ * u = 0 on the boundary.  k2 == empty means the Poisson operator. */
+struct Level {
+    int N;
+    double h;
+    std::vector<double> u, f, k2;
+    int id(int a, int b) const { return b * (N + 1) + a; }
+};
+
+/* (L_h u - k2 u) at interior node (a, b); 5-point Laplacian, Sec. VII.B eq. (33). */
+double apply_at(const Level& lv, const double* u, int a, int b) {
+    double lap = (u[lv.id(a - 1, b)] + u[lv.id(a + 1, b)] + u[lv.id(a, b - 1)] +
+                  u[lv.id(a, b + 1)] - 4.0 * u[lv.id(a, b)]) / (lv.h * lv.h);
+    double k2 = lv.k2.empty() ? 0.0 : lv.k2[lv.id(a, b)];
+    return lap - k2 * u[lv.id(a, b)];
+}
+
+/* Red-black Gauss-Seidel half sweep: the nodes with (a+b) % 2 == color are set
+ * to the value that zeroes their own equation given their four neighbours. */
+void relax_color(Level& lv, int color) {
+    const double h2 = lv.h * lv.h;
+    for (int b = 1; b < lv.N; ++b)
+        for (int a = 1; a < lv.N; ++a) {
+            if (((a + b) & 1) != color) continue;
+            double nb = lv.u[lv.id(a - 1, b)] + lv.u[lv.id(a + 1, b)] + lv.u[lv.id(a, b - 1)] +
+                        lv.u[lv.id(a, b + 1)];
+            double k2 = lv.k2.empty() ? 0.0 : lv.k2[lv.id(a, b)];
+            lv.u[lv.id(a, b)] = (nb - h2 * lv.f[lv.id(a, b)]) / (4.0 + h2 * k2);
+        }
+}
+
+void smooth(Level& lv, int nu) {
+    for (int s = 0; s < nu; ++s) {
+        relax_color(lv, 0);
+        relax_color(lv, 1);
+    }
+}
+
+/* Residual r = f - A u at the interior nodes (zero on the boundary). */
+void residual(const Level& lv, std::vector<double>& r) {
+    r.assign((lv.N + 1) * (lv.N + 1), 0.0);
+    for (int b = 1; b < lv.N; ++b)
+        for (int a = 1; a < lv.N; ++a)
+            r[lv.id(a, b)] = lv.f[lv.id(a, b)] - apply_at(lv, lv.u.data(), a, b);
+}
+
+double norm2_interior(const Level& lv, const std::vector<double>& v) {
+    double s = 0.0;
+    for (int b = 1; b < lv.N; ++b)
+        for (int a = 1; a < lv.N; ++a) s += v[lv.id(a, b)] * v[lv.id(a, b)];
+    return std::sqrt(s);
+}
+
+/* Full weighting of a fine-grid node array onto the interior coarse nodes. */
+void full_weighting(const Level& fine, const std::vector<double>& r, Level& coarse,
+                    std::vector<double>& out) {
+    out.assign((coarse.N + 1) * (coarse.N + 1), 0.0);
+    for (int J = 1; J < coarse.N; ++J)
+        for (int I = 1; I < coarse.N; ++I) {
+            int a = 2 * I, b = 2 * J;
+            double s = 4.0 * r[fine.id(a, b)] +
+                       2.0 * (r[fine.id(a - 1, b)] + r[fine.id(a + 1, b)] + r[fine.id(a, b - 1)] +
+                              r[fine.id(a, b + 1)]) +
+                       (r[fine.id(a - 1, b - 1)] + r[fine.id(a + 1, b - 1)] +
+                        r[fine.id(a - 1, b + 1)] + r[fine.id(a + 1, b + 1)]);
+            out[coarse.id(I, J)] = s / 16.0;
+        }
+}
+
+/* u_fine += bilinear interpolation of u_coarse. */
+void prolong_add(const Level& coarse, Level& fine) {
+    for (int b = 1; b < fine.N; ++b)
+        for (int a = 1; a < fine.N; ++a) {
+            int I = a / 2, J = b / 2;
+            bool ox = a & 1, oy = b & 1;
+            const std::vector<double>& e = coarse.u;
+            double v;
+            if (!ox && !oy) v = e[coarse.id(I, J)];
+            else if (ox && !oy) v = 0.5 * (e[coarse.id(I, J)] + e[coarse.id(I + 1, J)]);
+            else if (!ox && oy) v = 0.5 * (e[coarse.id(I, J)] + e[coarse.id(I, J + 1)]);
+            else
+                v = 0.25 * (e[coarse.id(I, J)] + e[coarse.id(I + 1, J)] + e[coarse.id(I, J + 1)] +
+                            e[coarse.id(I + 1, J + 1)]);
+            fine.u[fine.id(a, b)] += v;
+        }
+}
+
+void vcycle(std::vector<Level>& lv, size_t l, int nu1, int nu2) {
+    Level& L = lv[l];
+    if (L.N == 2) { /* one interior node, four zero boundary neighbours: exact */
+        double k2 = L.k2.empty() ? 0.0 : L.k2[L.id(1, 1)];
+        L.u[L.id(1, 1)] = -L.f[L.id(1, 1)] / (4.0 / (L.h * L.h) + k2);
+        return;
+    }
+    smooth(L, nu1);
+    std::vector<double> r;
+    residual(L, r);
+    Level& C = lv[l + 1];
+    full_weighting(L, r, C, C.f);
+    std::fill(C.u.begin(), C.u.end(), 0.0);
+    vcycle(lv, l + 1, nu1, nu2);
+    prolong_add(C, L);
+    smooth(L, nu2);
+}
+
+/* Solve (L_h - k2) u = f for the interior nodes with u = 0 on the boundary,
+ * starting from the guess held in u.  Stops when ||r|| <= rtol ||f|| + atol sqrt(n)
+ * (n interior nodes), or at the rounding floor: a cycle after the second that
+ * reduces ||r|| by less than 2x while ||r|| <= 1e-9 ||f|| (the guard keeps a
+ * slowly converging solve from being taken for a converged one).  Otherwise
+ * returns ORC_NOCONV after max_cycles. */
+int mg_solve(int N, double h, const double* k2, const double* f, double* u, double rtol,
+             double atol, int max_cycles, int nu1, int nu2, int* cycles_out, double* rel_out) {
+    std::vector<Level> lv;
+    for (int n = N; n >= 2; n /= 2) {
+        Level l;
+        l.N = n;
+        l.h = h * (N / n);
+        l.u.assign((n + 1) * (n + 1), 0.0);
+        l.f.assign((n + 1) * (n + 1), 0.0);
+        lv.push_back(l);
+    }
+    Level& top = lv[0];
+    std::copy(f, f + top.u.size(), top.f.begin());
+    std::copy(u, u + top.u.size(), top.u.begin());
+    for (int b = 0; b <= N; ++b)  /* Dirichlet: boundary values are zero */
+        for (int a = 0; a <= N; ++a)
+            if (a == 0 || b == 0 || a == N || b == N) {
+                top.u[top.id(a, b)] = 0.0;
+                top.f[top.id(a, b)] = 0.0;
+            }
+    if (k2) {  /* coarse k2 by full weighting of the finer level */
+        top.k2.assign(k2, k2 + top.u.size());
+        for (size_t l = 1; l < lv.size(); ++l) full_weighting(lv[l - 1], lv[l - 1].k2, lv[l], lv[l].k2);
+    }
+    std::vector<double> r;
+    const double fnorm = norm2_interior(top, top.f);
+    const double tol = rtol * fnorm + atol * std::sqrt((double)(N - 1) * (N - 1));
+    residual(top, r);
+    double rn = norm2_interior(top, r), rprev = rn;
+    int c = 0, status = ORC_NOCONV;
+    if (rn <= tol) status = ORC_OK;
+    while (status != ORC_OK && c < max_cycles) {
+        vcycle(lv, 0, nu1, nu2);
+        ++c;
+        residual(top, r);
+        rprev = rn;
+        rn = norm2_interior(top, r);
+        if (rn <= tol) status = ORC_OK;
+        else if (c >= 2 && rn > 0.5 * rprev && rn <= 1e-9 * fnorm) status = ORC_OK; /* floor */
+    }
+    std::copy(top.u.begin(), top.u.end(), u);
+    if (cycles_out) *cycles_out = c;
+    if (rel_out) *rel_out = fnorm > 0 ? rn / fnorm : rn;
+    return (std::isfinite(rn) ? status : ORC_NOCONV);
+}
+
+/* --------------------------------------------------------------- drivers -- */
+
+/* Frozen luminal driver density n_b(x, y, xi); zero for xi < 0 (the xi axis
+ * starts at 0, Table 1 footnote).  Gaussian: amp exp(-r^2/sr^2 - (xi-xc)^2/sz^2)
+ * as in Sec. V.A; radial bins: bin_amp[floor(r/dr)] exp(-(xi-xc)^2/sz^2). */
+double beam_density(const oracle_cfg& c, double x, double y, double xi) {
+    if (xi < 0.0) return 0.0;
+    double s = 0.0;
+    for (int k = 0; k < c.n_beams; ++k) {
+        const oracle_beam& B = c.beams[k];
+        double rx = x - B.x0, ry = y - B.y0;
+        double r2 = rx * rx + ry * ry;
+        double lz = (xi - B.xi_c) * (xi - B.xi_c) / (B.sigma_z * B.sigma_z);
+        if (B.kind == 0) {
+            s += B.amp * std::exp(-r2 / (B.sigma_r * B.sigma_r) - lz);
+        } else {
+            double r = std::sqrt(r2);
+            double dr = B.r_max / B.n_bins;
+            int k2 = (int)std::floor(r / dr);
+            if (r < B.r_max && k2 < B.n_bins) s += B.bin_amp[k2] * std::exp(-lz);
+        }
+    }
+    return s;
+}
+
+/* ----------------------------------------------------------- slice step -- */
+
+struct Moments { /* node arrays deposited from the particles of one slice */
+    std::vector<double> n, jx, jy, txx, txy, tyy;
+};
+
+/* Assembly of the B-perp system (Sec. III.B eqs. (18)-(19) with A-hat = 0, i.e.
+ * rows 4-5 of eq. (30)):  G = n*<gamma> (eq. (9) and the gamma of Sec. III.A),
+ * plasma j_z = n*<p_z>/(1+psi) = G/g - n*, total j_z adds the beam, k2 = n* / g,
+ * and the right-hand sides
+ *   f_Bx =  S_y,  f_By = -S_x   (from -e_z x S),
+ *   S = grad j_z - div T + (e_z x j) Bz/g + G grad psi/g^2 - j Ez/g - T.grad psi/g.
+ * Returns ORC_NONPHYS if g <= 0 at a node that holds plasma. */
+int assemble(const Grid& g, const oracle_cfg& c, double xi, const Moments& m,
+             const double* psi, const double* Ez, const double* Bz, std::vector<double>& k2,
+             std::vector<double>& fBx, std::vector<double>& fBy, std::vector<double>* jz_out) {
+    const int nn = g.nn();
+    std::vector<double> G(nn, 0.0), jz(nn, 0.0);
+    int status = ORC_OK;
+    for (int b = 0; b <= g.N; ++b)
+        for (int a = 0; a <= g.N; ++a) {
+            int i = g.id(a, b);
+            double gg = 1.0 + psi[i];
+            double plasma_jz = 0.0;
+            if (m.n[i] > 0.0) {
+                if (gg <= 0.0) status = ORC_NONPHYS;
+                /* <gamma> = (1 + <p_perp^2> + g^2)/(2g) with <p_perp^2> = g^2 <V^2> */
+                G[i] = (m.n[i] * (1.0 + gg * gg) + gg * gg * (m.txx[i] + m.tyy[i])) / (2.0 * gg);
+                plasma_jz = G[i] / gg - m.n[i];
+            }
+            jz[i] = plasma_jz + beam_density(c, g.xa(a), g.xa(b), xi);
+        }
+    k2.assign(nn, 0.0);
+    fBx.assign(nn, 0.0);
+    fBy.assign(nn, 0.0);
+    for (int b = 1; b < g.N; ++b)
+        for (int a = 1; a < g.N; ++a) {
+            int i = g.id(a, b);
+            double gg = 1.0 + psi[i];
+            double px = Dx(g, psi, a, b), py = Dy(g, psi, a, b);
+            /* grad j_z - div T, written as the D-terms of rows 4-5 of eq. (30) */
+            double d_jz_tyy = (jz[g.id(a, b + 1)] - m.tyy[g.id(a, b + 1)] -
+                               (jz[g.id(a, b - 1)] - m.tyy[g.id(a, b - 1)])) / (2.0 * g.h);
+            double d_txx_jz = (m.txx[g.id(a + 1, b)] - jz[g.id(a + 1, b)] -
+                               (m.txx[g.id(a - 1, b)] - jz[g.id(a - 1, b)])) / (2.0 * g.h);
+            double fx = d_jz_tyy - Dx(g, m.txy.data(), a, b);
+            double fy = d_txx_jz + Dy(g, m.txy.data(), a, b);
+            if (m.n[i] > 0.0) {
+                k2[i] = m.n[i] / gg;
+                fx += (m.jx[i] * Bz[i] - m.jy[i] * Ez[i]) / gg +
+                      (G[i] / (gg * gg) - m.tyy[i] / gg) * py - (m.txy[i] / gg) * px;
+                fy += (m.jy[i] * Bz[i] + m.jx[i] * Ez[i]) / gg -
+                      (G[i] / (gg * gg) - m.txx[i] / gg) * px + (m.txy[i] / gg) * py;
+            }
+            fBx[i] = fx;
+            fBy[i] = fy;
+        }
+    if (jz_out) *jz_out = jz;
+    return status;
+}
+
+/* Node gradient of psi for the particle gather: central at interior nodes,
+ * one-sided on the boundary rows/columns. */
+void psi_gradient(const Grid& g, const double* psi, std::vector<double>& gx, std::vector<double>& gy) {
+    gx.assign(g.nn(), 0.0);
+    gy.assign(g.nn(), 0.0);
+    for (int b = 0; b <= g.N; ++b)
+        for (int a = 0; a <= g.N; ++a) {
+            int i = g.id(a, b);
+            if (a == 0) gx[i] = (psi[g.id(1, b)] - psi[g.id(0, b)]) / g.h;
+            else if (a == g.N) gx[i] = (psi[g.id(g.N, b)] - psi[g.id(g.N - 1, b)]) / g.h;
+            else gx[i] = (psi[g.id(a + 1, b)] - psi[g.id(a - 1, b)]) / (2.0 * g.h);
+            if (b == 0) gy[i] = (psi[g.id(a, 1)] - psi[g.id(a, 0)]) / g.h;
+            else if (b == g.N) gy[i] = (psi[g.id(a, g.N)] - psi[g.id(a, g.N - 1)]) / g.h;
+            else gy[i] = (psi[g.id(a, b + 1)] - psi[g.id(a, b - 1)]) / (2.0 * g.h);
+        }
+}
+
+/* Boris-like advance of one plasma electron over dxi with the fields frozen at
+ * the current slice (Sec. III.A eqs. (6)-(7), A-hat = 0):
+ *   dr/dxi = V = p/g,   dp/dxi = gamma grad psi/g + (e_z x V) Bz + e_z x B_perp,
+ *   gamma = (1 + p^2 + g^2)/(2g)  taken at the old momentum.
+ * Half kick with F = gamma grad psi/g + e_z x B_perp, rotation by the
+ * (e_z x V) Bz term (angle 2 atan(Bz dxi / 2g)), half kick, drift with the
+ * new momentum, specular reflection at the walls x, y = +-L. */
+void push_one(double L, double dxi, double g_i, double gx, double gy, double Bx, double By,
+              double Bz, double& x, double& y, double& px, double& py) {
+    double gamma = (1.0 + px * px + py * py + g_i * g_i) / (2.0 * g_i);
+    double Fx = gamma * gx / g_i - By;
+    double Fy = gamma * gy / g_i + Bx;
+    double mx = px + 0.5 * dxi * Fx;
+    double my = py + 0.5 * dxi * Fy;
+    double t = Bz * dxi / (2.0 * g_i);
+    double s = 2.0 * t / (1.0 + t * t);
+    double qx = mx - t * my;
+    double qy = my + t * mx;
+    double rx = mx - s * qy;
+    double ry = my + s * qx;
+    px = rx + 0.5 * dxi * Fx;
+    py = ry + 0.5 * dxi * Fy;
+    x = x + dxi * px / g_i;
+    y = y + dxi * py / g_i;
+    if (x > L) { x = 2.0 * L - x; px = -px; }
+    if (x < -L) { x = -2.0 * L - x; px = -px; }
+    if (y > L) { y = 2.0 * L - y; py = -py; }
+    if (y < -L) { y = -2.0 * L - y; py = -py; }
+}
+
+/* Step_Size_Refinement of Algorithm 1: V0 = dx/dxi0; dxi = dxi0 V0/Vmax if
+ * Vmax > V0 else dxi0; with refinement level k the step never drops below
+ * dxi0/k (Sec. V.A). */
+double next_dxi(const oracle_cfg& c, double h, double vmax) {
+    if (!c.adaptive) return c.dxi0;
+    double V0 = h / c.dxi0;
+    double d = c.dxi0;
+    if (vmax > V0) d = c.dxi0 * V0 / vmax;
+    if (c.refine_k > 0 && d < c.dxi0 / c.refine_k) d = c.dxi0 / c.refine_k;
+    return d;
+}
+
+} /* namespace */
+
+/* ================================================================ C API == */
+extern "C" {
+
+int oracle_deposit(const oracle_cfg* c, int P, const double* x, const double* y,
+                   const double* q, double* out) {
+    Grid g(c->n_cells, c->half_width);
+    deposit(g, *c, P, x, y, q, out);
+    return ORC_OK;
+}
+
+int oracle_gather(const oracle_cfg* c, int P, const double* x, const double* y,
+                  const double* F, double* out) {
+    Grid g(c->n_cells, c->half_width);
+    for (int i = 0; i < P; ++i) out[i] = gather1(g, F, x[i], y[i]);
+    return ORC_OK;
+}
+
+/* out = L_h u - k2 u at interior nodes, 0 on the boundary (k2 may be NULL). */
+int oracle_apply(int N, double h, const double* k2, const double* u, double* out) {
+    Level lv;
+    lv.N = N;
+    lv.h = h;
+    if (k2) lv.k2.assign(k2, k2 + (N + 1) * (N + 1));
+    std::fill(out, out + (N + 1) * (N + 1), 0.0);
+    for (int b = 1; b < N; ++b)
+        for (int a = 1; a < N; ++a) out[lv.id(a, b)] = apply_at(lv, u, a, b);
+    return ORC_OK;
+}
+
+int oracle_mg_solve(int N, double h, const double* k2, const double* f, double* u, double rtol,
+                    double atol, int max_cycles, int nu1, int nu2, int* cycles, double* rel) {
+    if (N < 2 || (N & (N - 1))) return ORC_INVALID;
+    return mg_solve(N, h, k2, f, u, rtol, atol, max_cycles, nu1, nu2, cycles, rel);
+}
+
+int oracle_beam_density(const oracle_cfg* c, double xi, double* out) {
+    Grid g(c->n_cells, c->half_width);
+    for (int b = 0; b <= g.N; ++b)
+        for (int a = 0; a <= g.N; ++a) out[g.id(a, b)] = beam_density(*c, g.xa(a), g.xa(b), xi);
+    return ORC_OK;
+}
+
+int oracle_push(double L, double dxi, int P, const double* g_i, const double* gx,
+                const double* gy, const double* Bx, const double* By, const double* Bz,
+                double* x, double* y, double* px, double* py) {
+    for (int i = 0; i < P; ++i)
+        push_one(L, dxi, g_i[i], gx[i], gy[i], Bx[i], By[i], Bz[i], x[i], y[i], px[i], py[i]);
+    return ORC_OK;
+}
+
+double oracle_next_dxi(const oracle_cfg* c, double vmax) {
+    return next_dxi(*c, 2.0 * c->half_width / c->n_cells, vmax);
+}
+
+/* Assembly given the node moments (layout [6][nn]: n*, jx, jy, Txx, Txy, Tyy)
+ * and the solved psi, Ez, Bz.  Output [4][nn]: k2, f_Bx, f_By, j_z. */
+int oracle_assemble(const oracle_cfg* c, double xi, const double* mom, const double* psi,
+                    const double* Ez, const double* Bz, double* out) {
+    Grid g(c->n_cells, c->half_width);
+    const int nn = g.nn();
+    Moments m;
+    m.n.assign(mom, mom + nn);
+    m.jx.assign(mom + nn, mom + 2 * nn);
+    m.jy.assign(mom + 2 * nn, mom + 3 * nn);
+    m.txx.assign(mom + 3 * nn, mom + 4 * nn);
+    m.txy.assign(mom + 4 * nn, mom + 5 * nn);
+    m.tyy.assign(mom + 5 * nn, mom + 6 * nn);
+    std::vector<double> k2, fBx, fBy, jz;
+    int st = assemble(g, *c, xi, m, psi, Ez, Bz, k2, fBx, fBy, &jz);
+    std::copy(k2.begin(), k2.end(), out);
+    std::copy(fBx.begin(), fBx.end(), out + nn);
+    std::copy(fBy.begin(), fBy.end(), out + 2 * nn);
+    std::copy(jz.begin(), jz.end(), out + 3 * nn);
+    return st;
+}
+
+/* One xi-slice (Algorithm 1 inner loop: Collect_Source, Solve_Wakefield,
+ * Push_Trajectory, Step_Size_Refinement).
+ *   in:  particles (x, y, px, py) at xi, fields[5][nn] = previous slice's fields
+ *        (multigrid initial guesses), *xi, *dxi (the step to take now);
+ *   out: fields at xi, particles at xi + dxi, *xi += dxi, *dxi = next step.
+ * moments_out ([6][nn], may be NULL) receives n*, jx, jy, Txx, Txy, Tyy and
+ * extra_out ([4][nn], may be NULL) receives k2, f_Bx, f_By, j_z.
+ * pz (may be NULL) carries p_z for the dynamic check of gamma - p_z = 1 + psi. */
+int oracle_slice_step(const oracle_cfg* c, int P, double* x, double* y, double* px, double* py,
+                      double* pz, double* fields, double* xi, double* dxi, oracle_info* info,
+                      double* moments_out, double* extra_out) {
+    Grid g(c->n_cells, c->half_width);
+    const int nn = g.nn();
+    double* psi = fields;
+    double* Ez = fields + nn;
+    double* Bz = fields + 2 * nn;
+    double* Bx = fields + 3 * nn;
+    double* By = fields + 4 * nn;
+    oracle_info inf;
+    std::memset(&inf, 0, sizeof(inf));
+    inf.xi = *xi;
+    inf.dxi = *dxi;
+    int status = ORC_OK;
+    auto solve = [&](int k, const std::vector<double>* k2, const std::vector<double>& f, double* u) {
+        int st = mg_solve(g.N, g.h, k2 ? k2->data() : nullptr, f.data(), u, c->mg_rtol, c->mg_atol,
+                          c->mg_max_cycles, c->nu_pre, c->nu_post, &inf.cycles[k], &inf.rel_resid[k]);
+        if (st != ORC_OK && status == ORC_OK) status = st;
+    };
+
+    /* 1. surface density n* (Collect_Source). */
+    Moments m;
+    m.n.assign(nn, 0.0);
+    deposit(g, *c, P, x, y, nullptr, m.n.data());
+
+    /* 2. psi: L_h psi = n* - n0 (Sec. III.B eq. (12)). */
+    std::vector<double> f(nn, 0.0);
+    for (int i = 0; i < nn; ++i) f[i] = m.n[i] - c->n0;
+    solve(0, nullptr, f, psi);
+
+    /* 3. per-particle g_i = 1 + psi(r_i) and V_i = p_i/g_i (eq. (6)); currents
+     *    j = n*<V> (eq. (9)) and pressure tensor T = n*<V V> (below eq. (16)). */
+    std::vector<double> gi(P), vx(P), vy(P), vxx(P), vxy(P), vyy(P);
+    double inv_err = 0.0;
+    for (int i = 0; i < P; ++i) {
+        gi[i] = 1.0 + gather1(g, psi, x[i], y[i]);
+        if (!(gi[i] > 0.0)) status = ORC_NONPHYS;
+        vx[i] = px[i] / gi[i];
+        vy[i] = py[i] / gi[i];
+        vxx[i] = vx[i] * vx[i];
+        vxy[i] = vx[i] * vy[i];
+        vyy[i] = vy[i] * vy[i];
+        if (pz) {
+            double gam = (1.0 + px[i] * px[i] + py[i] * py[i] + gi[i] * gi[i]) / (2.0 * gi[i]);
+            inv_err = std::max(inv_err, std::fabs(gam - pz[i] - gi[i]));
+        }
+    }
+    inf.invariant_err = inv_err;
+    m.jx.assign(nn, 0.0);
+    m.jy.assign(nn, 0.0);
+    m.txx.assign(nn, 0.0);
+    m.txy.assign(nn, 0.0);
+    m.tyy.assign(nn, 0.0);
+    deposit(g, *c, P, x, y, vx.data(), m.jx.data());
+    deposit(g, *c, P, x, y, vy.data(), m.jy.data());
+    deposit(g, *c, P, x, y, vxx.data(), m.txx.data());
+    deposit(g, *c, P, x, y, vxy.data(), m.txy.data());
+    deposit(g, *c, P, x, y, vyy.data(), m.tyy.data());
+
+    /* 4. Ez and Bz: L_h Ez = -div j (eq. (13)), L_h Bz = e_z.(curl j) (eq. (14)). */
+    std::vector<double> fE(nn, 0.0), fB(nn, 0.0);
+    for (int b = 1; b < g.N; ++b)
+        for (int a = 1; a < g.N; ++a) {
+            int i = g.id(a, b);
+            fE[i] = -(Dx(g, m.jx.data(), a, b) + Dy(g, m.jy.data(), a, b));
+            fB[i] = Dx(g, m.jy.data(), a, b) - Dy(g, m.jx.data(), a, b);
+        }
+    solve(1, nullptr, fE, Ez);
+    solve(2, nullptr, fB, Bz);
+
+    /* 5-6. B_perp: (L_h - n* / g) B_perp = -e_z x S (eqs. (18)-(19)). */
+    std::vector<double> k2, fBx, fBy, jz;
+    int st = assemble(g, *c, *xi, m, psi, Ez, Bz, k2, fBx, fBy, &jz);
+    if (st != ORC_OK && status == ORC_OK) status = st;
+    solve(3, &k2, fBx, Bx);
+    solve(4, &k2, fBy, By);
+
+    if (moments_out) {
+        const std::vector<double>* arr[6] = {&m.n, &m.jx, &m.jy, &m.txx, &m.txy, &m.tyy};
+        for (int k = 0; k < 6; ++k) std::copy(arr[k]->begin(), arr[k]->end(), moments_out + k * nn);
+    }
+    if (extra_out) {
+        const std::vector<double>* arr[4] = {&k2, &fBx, &fBy, &jz};
+        for (int k = 0; k < 4; ++k) std::copy(arr[k]->begin(), arr[k]->end(), extra_out + k * nn);
+    }
+
+    /* 7-8. gather grad psi, B and push (Push_Trajectory), Vmax after the push. */
+    std::vector<double> gx, gy;
+    psi_gradient(g, psi, gx, gy);
+    double vmax = 0.0;
+    for (int i = 0; i < P; ++i) {
+        double Gx = gather1(g, gx.data(), x[i], y[i]);
+        double Gy = gather1(g, gy.data(), x[i], y[i]);
+        double bx = gather1(g, Bx, x[i], y[i]);
+        double by = gather1(g, By, x[i], y[i]);
+        double bz = gather1(g, Bz, x[i], y[i]);
+        double ez = pz ? gather1(g, Ez, x[i], y[i]) : 0.0;
+        double p0x = px[i], p0y = py[i];
+        push_one(g.L, *dxi, gi[i], Gx, Gy, bx, by, bz, x[i], y[i], px[i], py[i]);
+        if (pz) { /* dp_z/dxi = -gamma Ez/g - Vx By + Vy Bx at the mean momentum */
+            double mx = 0.5 * (p0x + px[i]), my = 0.5 * (p0y + py[i]);
+            double gam = (1.0 + mx * mx + my * my + gi[i] * gi[i]) / (2.0 * gi[i]);
+            pz[i] += *dxi * (-gam * ez / gi[i] - (mx / gi[i]) * by + (my / gi[i]) * bx);
+        }
+        double v = std::sqrt(px[i] * px[i] + py[i] * py[i]) / gi[i];
+        if (v > vmax) vmax = v;
+    }
+
+    /* 9. Step_Size_Refinement for the next slice. */
+    inf.vmax = vmax;
+    inf.dxi_next = next_dxi(*c, g.h, vmax);
+    *xi = *xi + *dxi;
+    *dxi = inf.dxi_next;
+    inf.status = status;
+    if (info) *info = inf;
+    return status;
+}
+
+/* n_slices consecutive slices from the given state.  fields_hist (may be NULL)
+ * receives [n_slices][5][nn]; infos (may be NULL) receives one record per slice. */
+int oracle_run(const oracle_cfg* c, int P, double* x, double* y, double* px, double* py,
+               double* pz, double* fields, double* xi, double* dxi, int n_slices,
+               double* fields_hist, oracle_info* infos) {
+    const int nn = (c->n_cells + 1) * (c->n_cells + 1);
+    for (int j = 0; j < n_slices; ++j) {
+        oracle_info inf;
+        int st = oracle_slice_step(c, P, x, y, px, py, pz, fields, xi, dxi, &inf, nullptr, nullptr);
+        if (infos) infos[j] = inf;
+        if (fields_hist) std::copy(fields, fields + 5 * nn, fields_hist + (size_t)j * 5 * nn);
+        if (st != ORC_OK) return st;
+    }
+    return ORC_OK;
+}
+
+} /* extern "C" */

@@ -1,0 +1,329 @@
+"""Pins of the oracle's particle operations and of the whole slice (no GPU).
+
+Each check is independent of the oracle's code: closed forms, invariants fixed
+by the paper, special cases that reduce to exact arithmetic, and the paper's
+central identity (the explicit xi-derivative of the transverse current,
+Sec. III.B eqs. (15)-(19)) tested against finite differences of the particle
+motion itself.
+"""
+import numpy as np
+import pytest
+
+import linear_wake as lw
+import wandqs_inputs as wi
+
+
+def _rand_particles(cfg, P, seed):
+    rng = np.random.default_rng(seed)
+    L = cfg["half_width"]
+    return rng.uniform(-L, L, P), rng.uniform(-L, L, P)
+
+
+# ------------------------------------------------------------------ CIC -----
+
+def test_deposit_partition_of_unity(oracle_mod):
+    """Total charge: sum n* h^2 = P w exactly (continuity eq. (8): N is xi-independent)."""
+    cfg = wi.scaled(wi.config("C2"), n_cells=32)
+    o = oracle_mod.Oracle(cfg)
+    x, y = _rand_particles(cfg, 5000, 1)
+    x[:4] = [-8.0, 8.0, -8.0, 8.0]   # corners and edges are included
+    y[:4] = [-8.0, 8.0, 8.0, -8.0]
+    n = o.deposit(x, y)
+    w = cfg["n0"] * o.h ** 2 / cfg["ppc_side"] ** 2
+    assert abs(n.sum() * o.h ** 2 - x.size * w) <= 1e-13 * x.size * w
+
+
+def test_lattice_gives_uniform_density(oracle_mod):
+    """A cold plasma at rest on the lattice has n* = n0 at every interior node."""
+    for name in ("C1",):
+        cfg = wi.config(name)
+        st = oracle_mod.initial_state(cfg)
+        n = oracle_mod.Oracle(cfg).deposit(st["x"], st["y"])
+        assert np.abs(n[1:-1, 1:-1] - 1.0).max() <= 1e-14
+    cfg = wi.scaled(wi.config("C2"), n_cells=32, jitter=0.0)
+    st = oracle_mod.initial_state(cfg)
+    n = oracle_mod.Oracle(cfg).deposit(st["x"], st["y"])
+    assert np.abs(n[1:-1, 1:-1] - 1.0).max() <= 1e-14
+
+
+def test_gather_reproduces_bilinear_fields(oracle_mod):
+    cfg = wi.scaled(wi.config("C2"), n_cells=16)
+    o = oracle_mod.Oracle(cfg)
+    g = -o.L + o.h * np.arange(o.N + 1)
+    X, Y = np.meshgrid(g, g, indexing="xy")
+    F = 0.3 - 1.7 * X + 0.25 * Y + 0.8 * X * Y   # bilinear on every cell
+    x, y = _rand_particles(cfg, 2000, 2)
+    got = o.gather(x, y, F)
+    ref = 0.3 - 1.7 * x + 0.25 * y + 0.8 * x * y
+    assert np.abs(got - ref).max() <= 1e-12
+
+
+def test_deposit_is_adjoint_of_gather(oracle_mod):
+    """<deposit(q), F> h^2 = sum_i w q_i gather(F)_i."""
+    cfg = wi.scaled(wi.config("C2"), n_cells=32)
+    o = oracle_mod.Oracle(cfg)
+    rng = np.random.default_rng(3)
+    x, y = _rand_particles(cfg, 3000, 4)
+    q = rng.standard_normal(x.size)
+    F = rng.standard_normal((o.N + 1, o.N + 1))
+    w = cfg["n0"] * o.h ** 2 / cfg["ppc_side"] ** 2
+    lhs = (o.deposit(x, y, q) * F).sum() * o.h ** 2
+    rhs = (w * q * o.gather(x, y, F)).sum()
+    assert abs(lhs - rhs) <= 1e-12 * (np.abs(w * q).sum() * np.abs(F).max())
+
+
+# --------------------------------------------------------------- pusher -----
+
+def test_push_uniform_bz_is_exact_rotation(oracle_mod):
+    """Only (e_z x V) Bz acts: |p| is conserved and p turns counter-clockwise by
+    2 atan(Bz dxi / 2g) per step (eq. (7))."""
+    P = 7
+    rng = np.random.default_rng(5)
+    px, py = rng.standard_normal(P), rng.standard_normal(P)
+    g = rng.uniform(0.5, 2.0, P)
+    Bz = rng.uniform(-3, 3, P)
+    dxi = 0.05
+    z = np.zeros(P)
+    x, y, qx, qy = oracle_mod.push(1e9, dxi, g, z, z, z, z, Bz, z, z, px, py)
+    assert np.allclose(np.hypot(qx, qy), np.hypot(px, py), rtol=1e-14, atol=0)
+    turn = np.angle((qx + 1j * qy) / (px + 1j * py))
+    assert np.allclose(turn, 2 * np.arctan(Bz * dxi / (2 * g)), rtol=1e-12, atol=1e-14)
+
+
+def test_push_uniform_by_is_exact_drift(oracle_mod):
+    """Only e_z x B_perp with B = (0, By): dp_x/dxi = -By exactly, so after n
+    steps p_x = -By n dxi; the drift dx = dxi p_new/g is exact for this force."""
+    By, dxi, g = 0.7, 0.01, 1.3
+    x, y, px, py = (np.zeros(1) for _ in range(4))
+    one, z = np.ones(1), np.zeros(1)
+    xs = 0.0
+    for n in range(1, 51):
+        x, y, px, py = oracle_mod.push(1e9, dxi, g * one, z, z, z, By * one, z, x, y, px, py)
+        xs += dxi * (-By * n * dxi) / g
+        assert abs(px[0] + By * n * dxi) <= 1e-14 * n
+    assert abs(x[0] - xs) <= 1e-12
+
+
+def test_push_gradient_force_uses_gamma(oracle_mod):
+    """Only the wake-potential force gamma grad psi / g (eq. (7)) acts on a
+    particle at rest: one step gives p = dxi * gamma0 grad psi / g with
+    gamma0 = (1 + g^2)/(2g)."""
+    g, gx, gy, dxi = 1.2, 0.3, -0.4, 0.02
+    one, z = np.ones(1), np.zeros(1)
+    x, y, px, py = oracle_mod.push(1e9, dxi, g * one, gx * one, gy * one, z, z, z, z, z, z, z)
+    gam0 = (1 + g * g) / (2 * g)
+    assert abs(px[0] - dxi * gam0 * gx / g) <= 1e-16
+    assert abs(py[0] - dxi * gam0 * gy / g) <= 1e-16
+    assert abs(x[0] - dxi * px[0] / g) <= 1e-18
+
+
+def test_push_wall_reflection(oracle_mod):
+    L = 1.0
+    one, z = np.ones(1), np.zeros(1)
+    x, y, px, py = oracle_mod.push(L, 0.1, one, z, z, z, z, z, 0.99 * one, -0.99 * one,
+                                   0.3 * one, -0.3 * one)
+    assert np.isclose(x[0], 2 * L - 1.02) and np.isclose(px[0], -0.3)
+    assert np.isclose(y[0], -2 * L + 1.02) and np.isclose(py[0], 0.3)
+
+
+# ----------------------------------------------------------- Algorithm 1 -----
+
+def test_step_size_refinement_table(oracle_mod):
+    """Step_Size_Refinement (Algorithm 1) with the refinement floor of Sec. V.A."""
+    cfg = wi.scaled(wi.config("C2"), n_cells=256, half_width=8.0, dxi0=0.02, refine_k=8)
+    o = oracle_mod.Oracle(cfg)
+    V0 = o.h / 0.02
+    assert o.next_dxi(0.0) == 0.02
+    assert o.next_dxi(0.5 * V0) == 0.02
+    assert o.next_dxi(V0) == 0.02
+    assert np.isclose(o.next_dxi(2 * V0), 0.01, rtol=1e-15)
+    assert np.isclose(o.next_dxi(5 * V0), 0.004, rtol=1e-15)
+    assert np.isclose(o.next_dxi(100 * V0), 0.02 / 8, rtol=1e-15)
+    for v in (1.5 * V0, 3 * V0, 7.9 * V0):   # floor inactive: a step never crosses a cell
+        assert v * o.next_dxi(v) <= o.h * (1 + 1e-15)
+    o2 = oracle_mod.Oracle(wi.scaled(cfg, adaptive=0))
+    assert o2.next_dxi(100 * V0) == 0.02
+    o3 = oracle_mod.Oracle(wi.scaled(cfg, refine_k=0))
+    assert np.isclose(o3.next_dxi(100 * V0), 0.0002, rtol=1e-14)
+
+
+# ------------------------------------------------------------ invariants -----
+
+def test_qs_invariant_formula():
+    """gamma = (1 + p^2 + g^2)/(2g) and p_z = gamma - g satisfy the mass shell
+    gamma^2 - p_perp^2 - p_z^2 = 1 (Sec. III.A, H - P_z = 1)."""
+    rng = np.random.default_rng(9)
+    p = rng.standard_normal((2, 1000)) * 3
+    g = rng.uniform(0.05, 3.0, 1000)
+    gam = (1 + (p ** 2).sum(0) + g * g) / (2 * g)
+    pz = gam - g
+    assert np.allclose(gam ** 2 - (p ** 2).sum(0) - pz ** 2, 1.0, rtol=0, atol=1e-11 * gam ** 2)
+
+
+def test_qs_invariant_dynamic(oracle_mod):
+    """Carrying p_z with dp_z/dxi = -gamma Ez/g - Vx By + Vy Bx keeps
+    gamma - p_z = 1 + psi (exact in the continuum because Ez = d psi/dxi);
+    the discrete defect shrinks when the resolution is refined."""
+    errs = []
+    for N, dxi in ((64, 0.0625), (128, 0.03125)):
+        cfg = wi.scaled(wi.config("C1"), n_cells=N, dxi0=dxi)
+        cfg["beams"][0]["amp"] = 0.5
+        o = oracle_mod.Oracle(cfg)
+        st = oracle_mod.initial_state(cfg)
+        r = o.run(st, int(round(5.0 / dxi)), carry_pz=True)
+        assert r["status"] == 0
+        errs.append(max(i.invariant_err for i in r["infos"]))
+    assert errs[0] < 1e-2 and errs[1] < 0.6 * errs[0], errs
+
+
+def test_charge_conserved_over_run(oracle_mod):
+    cfg = wi.scaled(wi.config("C2"), n_cells=64, half_width=4.0)
+    o = oracle_mod.Oracle(cfg)
+    st = oracle_mod.initial_state(cfg)
+    n0 = o.deposit(st["x"], st["y"]).sum()
+    r = o.run(st, 150)
+    assert r["status"] == 0
+    assert np.all(np.abs(st["x"]) <= 4.0) and np.all(np.abs(st["y"]) <= 4.0)
+    assert abs(o.deposit(st["x"], st["y"]).sum() - n0) <= 1e-12 * n0
+
+
+# ------------------------------------------------------------ whole slice ----
+
+def _linear_error(oracle_mod, N, dxi, A):
+    cfg = wi.scaled(wi.config("C1"), n_cells=N, dxi0=dxi)
+    cfg["beams"][0]["amp"] = A
+    ns = int(round(8.0 / dxi)) + 1
+    o = oracle_mod.Oracle(cfg)
+    st = oracle_mod.initial_state(cfg)
+    r = o.run(st, ns, keep_fields=True)
+    assert r["status"] == 0
+    xis = np.arange(ns) * dxi
+    ez = r["fields"][:, 1, N // 2, N // 2] / A
+    lin = lw.ez_on_axis(xis, 1.0, 0.5, 1.0, 2.0)
+    return np.abs(ez - lin).max() / np.abs(lin).max(), r, cfg
+
+
+def test_linear_wake_closed_form(oracle_mod):
+    """On-axis Ez of a weak Gaussian driver against the closed-form linear wake,
+    and its convergence when h and dxi are halved (C1 and a refined C1)."""
+    e64, r, cfg = _linear_error(oracle_mod, 64, 0.0625, 0.1)
+    e128, _, _ = _linear_error(oracle_mod, 128, 0.03125, 0.01)
+    assert e64 < 0.2 and e128 < 0.06 and e64 / e128 > 2.5, (e64, e128)
+    # B_perp of the linear wake at a few points, refined case
+    N, dxi = 128, 0.03125
+    cfg = wi.scaled(wi.config("C1"), n_cells=N, dxi0=dxi)
+    cfg["beams"][0]["amp"] = 0.01
+    o = oracle_mod.Oracle(cfg)
+    st = oracle_mod.initial_state(cfg)
+    F = o.run(st, 100, keep_fields=True)["fields"]
+    h = 12.0 / N
+    err, ref = 0.0, 0.0
+    for j in range(40, 100, 10):
+        for a, b in ((N // 2, N // 2 + 5), (N // 2 + 8, N // 2), (N // 2 + 4, N // 2 + 4)):
+            bx, by = lw.bperp(-6 + a * h, -6 + b * h, j * dxi, 1.0, 0.5, 1.0, 2.0)
+            err = max(err, abs(F[j, 3, b, a] / 0.01 - bx), abs(F[j, 4, b, a] / 0.01 - by))
+            ref = max(ref, abs(bx), abs(by))
+    assert err < 0.01 * ref
+
+
+def test_bz_of_a_swirling_plasma(oracle_mod):
+    """Bz from eq. (14) for a weak Gaussian swirl of electron momentum
+    p = p0 (-(y-y0), x-x0) exp(-r^2/w^2): the continuum solution of
+    nabla^2 Bz = e_z.(curl j) with j = n* V ~ p is Bz = -(p0 w^2/2) exp(-r^2/w^2)
+    (negative: electrons circulating counter-clockwise are a clockwise current).
+    Second-order convergence when h is halved."""
+    errs = []
+    for N in (64, 128):
+        cfg = wi.scaled(wi.config("C1"), n_cells=N, beams=[])
+        p0, w = 0.05, 1.0
+        st = wi.vortex_state(cfg, p0, w, xi=0.5, x0=0.3, y0=-0.2)
+        assert oracle_mod.Oracle(cfg).slice_step(st)["status"] == 0
+        h = 12.0 / N
+        g = -6 + h * np.arange(N + 1)
+        X, Y = np.meshgrid(g, g, indexing="xy")
+        ref = -(p0 * w * w / 2) * np.exp(-((X - 0.3) ** 2 + (Y + 0.2) ** 2) / w ** 2)
+        errs.append(np.abs(st["fields"][2] - ref).max() / np.abs(ref).max())
+    assert errs[0] < 0.04 and errs[1] < 0.01 and errs[0] / errs[1] > 3.5, errs
+
+
+def test_d4_symmetry(oracle_mod):
+    """An axisymmetric driver on the symmetric lattice keeps the square's D4
+    symmetry: psi(x,y) = psi(-x,y) = psi(y,x), By(x,y) = -Bx(y,x), Bz = 0."""
+    cfg = wi.config("C1")
+    o = oracle_mod.Oracle(cfg)
+    st = oracle_mod.initial_state(cfg)
+    F = o.run(st, 80, keep_fields=True)["fields"][-1]
+    psi, Ez, Bz, Bx, By = F
+    s = np.abs(psi).max()
+    assert np.abs(psi - psi[:, ::-1]).max() <= 1e-12 * s
+    assert np.abs(psi - psi.T).max() <= 1e-12 * s
+    assert np.abs(Ez - Ez.T).max() <= 1e-12 * np.abs(Ez).max()
+    sb = np.abs(Bx).max()
+    assert np.abs(By - (-Bx.T)).max() <= 1e-12 * sb
+    # Bz is a pseudo-scalar: odd under each mirror of the square.  On the grid it
+    # is not identically zero (an O(h^2)-small octupole), but it must be odd.
+    assert np.abs(Bz + Bz[:, ::-1]).max() <= 1e-12 * sb
+    assert np.abs(Bz + Bz.T).max() <= 1e-12 * sb
+    assert np.abs(Bz).max() <= 0.1 * sb
+
+
+def _fluxpres_error(oracle_mod, cfg, state, n_ramp, dxi_fd):
+    """B_perp from the Helmholtz form (eqs. (18)-(19)) against B_perp from the
+    non-local form (eq. (15)) with d j_perp/d xi from central differences of
+    the deposited current over two particle pushes."""
+    o = oracle_mod.Oracle(cfg)
+    if n_ramp:
+        assert o.run(state, n_ramp)["status"] == 0
+    o2 = oracle_mod.Oracle(wi.scaled(cfg, dxi0=dxi_fd))
+    state["dxi"] = dxi_fd
+    r0 = o2.slice_step(state, want_moments=True)
+    r1 = o2.slice_step(state, want_moments=True)
+    F1 = state["fields"].copy()
+    r2 = o2.slice_step(state, want_moments=True)
+    N, h = o.N, o.h
+    djx = (r2["moments"][1] - r0["moments"][1]) / (2 * dxi_fd)
+    djy = (r2["moments"][2] - r0["moments"][2]) / (2 * dxi_fd)
+    jz = r1["extra"][3]
+    fx = np.zeros_like(jz)
+    fy = np.zeros_like(jz)
+    # -e_z x (grad j_z + d j_perp/d xi) = (w_y, -w_x)
+    fx[1:-1, 1:-1] = (jz[2:, 1:-1] - jz[:-2, 1:-1]) / (2 * h) + djy[1:-1, 1:-1]
+    fy[1:-1, 1:-1] = -((jz[1:-1, 2:] - jz[1:-1, :-2]) / (2 * h) + djx[1:-1, 1:-1])
+    _, bx, _, _ = oracle_mod.mg_solve(N, h, fx)
+    _, by, _, _ = oracle_mod.mg_solve(N, h, fy)
+    num = ((bx - F1[3]) ** 2 + (by - F1[4]) ** 2).sum()
+    den = (F1[3] ** 2 + F1[4] ** 2).sum()
+    return np.sqrt(num / den), F1
+
+
+def test_explicit_current_derivative_axisymmetric(oracle_mod):
+    """Nonlinear axisymmetric wake: every term of S that involves psi, Ez, T
+    or G contributes more than the tolerance here."""
+    cfg = wi.scaled(wi.config("C1"), n_cells=128, dxi0=0.02)
+    cfg["beams"][0]["amp"] = 4.0
+    st = oracle_mod.initial_state(cfg)
+    err, F = _fluxpres_error(oracle_mod, cfg, st, 149, 0.002)
+    assert err < 0.012, err
+
+
+def test_explicit_current_derivative_vortex(oracle_mod):
+    """A swirling plasma (curl j != 0) exercises the (e_z x j) Bz terms."""
+    cfg = wi.scaled(wi.config("C1"), n_cells=128, dxi0=0.004)
+    cfg["beams"][0]["amp"] = 1.0
+    st = wi.vortex_state(cfg, 0.8, 1.0, xi=1.8)
+    oracle_mod.Oracle(cfg).slice_step(st)
+    err, F = _fluxpres_error(oracle_mod, cfg, st, 0, 0.004)
+    assert np.abs(F[2]).max() > 0.1
+    assert err < 0.01, err
+
+
+def test_nonphysical_reported(oracle_mod):
+    """1 + psi <= 0 is an error, never clamped."""
+    cfg = wi.scaled(wi.config("C1"), n_cells=32)
+    cfg["beams"][0]["amp"] = 1e3
+    o = oracle_mod.Oracle(cfg)
+    st = oracle_mod.initial_state(cfg)
+    st["x"] = st["x"] * 0.0 + 0.01   # all electrons piled on the axis: psi << -1
+    st["y"] = st["y"] * 0.0 - 0.01
+    r = o.slice_step(st)
+    assert r["status"] == oracle_mod.NONPHYS
