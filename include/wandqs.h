@@ -1,0 +1,178 @@
+/*
+ * wandqs -- quasi-static xi-slice step of plasma electrons on one MI355X (gfx950).
+ *
+ * The library advances the plasma electrons of a quasi-static particle-in-cell
+ * model through xi-slices behind a frozen, luminal driver beam, following
+ * T. Wang et al., "WAND-PIC: an accelerated three-dimensional quasi-static
+ * particle-in-cell code" (arXiv 2012.00881):
+ *   Collect_Source   deposit n*, j_perp = n*<V> and T = n*<V V>     (Sec. III.B, eqs. (8)-(9), (16))
+ *   Solve_Wakefield  psi, Ez, Bz by Poisson solves (eqs. (12)-(14)) and B_perp by the
+ *                    explicit Helmholtz system (eqs. (18)-(19)), geometric multigrid
+ *   Push_Trajectory  gather and Boris-like push of (r_perp, p_perp) (Sec. III.A, eqs. (6)-(7))
+ *   Step_Size_Refinement  adaptive dxi (Algorithm 1, with the floor dxi0/k of Sec. V.A)
+ *
+ * Units are the paper's (Sec. III): lengths 1/k_p, densities n0, momenta mc,
+ * fields mc omega_p/e, currents -e n0 c.  Transverse grid: N cells per side on
+ * [-L, L]^2, vertex centred, nodes x_a = -L + a h, h = 2L/N, a = 0..N; all five
+ * fields vanish on the boundary nodes.  Node arrays passed across this
+ * interface are dense row-major [N+1][N+1] float64 with x fastest
+ * (element b*(N+1)+a is node (x_a, y_b)); field order is psi, Ez, Bz, Bx, By.
+ *
+ * Conventions
+ *  - Ownership: the caller owns all device memory (the workspace, inputs and
+ *    outputs) and the HIP stream.  The library never allocates device memory;
+ *    it allocates a few hundred bytes of pinned host memory per context.
+ *    "d_" pointers are device pointers, "h_" pointers host pointers.
+ *  - Streams: every call enqueues its work on the stream given to wandqs_init
+ *    and returns when that work is enqueued, except where noted (calls that
+ *    fill a host output synchronise the stream).
+ *  - Errors: every call returns a status; on any error other than
+ *    WANDQS_E_INVALID raised by argument checks, the context is marked failed
+ *    and further steps return WANDQS_E_STATE until wandqs_set_state.
+ *    wandqs_last_error gives a text message.
+ *  - Threads: a context is used by one host thread at a time.
+ */
+#ifndef WANDQS_H
+#define WANDQS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wandqs_ctx wandqs_ctx;
+
+typedef enum {
+    WANDQS_OK = 0,
+    WANDQS_E_INVALID = -1, /* bad argument or configuration (context unchanged) */
+    WANDQS_E_NOMEM = -2,   /* workspace smaller than wandqs_workspace_bytes */
+    WANDQS_E_HIP = -3,     /* a HIP runtime call failed */
+    WANDQS_E_NOCONV = -4,  /* a multigrid solve did not converge in mg_max_cycles */
+    WANDQS_E_NONPHYS = -5, /* 1 + psi <= 0 where plasma is present (never clamped) */
+    WANDQS_E_STATE = -6    /* context failed earlier, or no state for the request */
+} wandqs_status;
+
+typedef enum { WANDQS_FP64 = 0, WANDQS_MIXED = 1 } wandqs_precision;
+typedef enum { WANDQS_BEAM_GAUSS = 0, WANDQS_BEAM_RADIAL_BINS = 1 } wandqs_beam_kind;
+
+/* Frozen luminal driver (Sec. V.A).  It enters only through the longitudinal
+ * current j_z of the B_perp source (a luminal beam has rho_b = J_bz, so it drops
+ * out of the psi equation).  Density for xi >= 0, zero for xi < 0:
+ *   GAUSS:        amp * exp(-r^2/sigma_r^2 - (xi - xi_c)^2/sigma_z^2)
+ *   RADIAL_BINS:  bin_amp[floor(r / (r_max/n_bins))] * exp(-(xi - xi_c)^2/sigma_z^2), r < r_max
+ * with r measured from (x0, y0).  bin_amp is a host array copied at init. */
+typedef struct {
+    int32_t kind;
+    double amp, sigma_r, sigma_z, xi_c, x0, y0;
+    int32_t n_bins;
+    double r_max;
+    const double* bin_amp;
+} wandqs_beam;
+
+/* A probe is the mean of one field over the nodes within r_max of (x0, y0)
+ * and over the slices slice_begin <= j < slice_end of a wandqs_run call. */
+typedef struct {
+    int32_t field; /* 0 psi, 1 Ez, 2 Bz, 3 Bx, 4 By */
+    int32_t slice_begin, slice_end;
+    double r_max, x0, y0;
+} wandqs_probe;
+
+typedef struct {
+    int32_t n_cells;     /* N: power of two, 8 .. 4096 */
+    double half_width;   /* L > 0 */
+    int32_t ppc_side;    /* s = 1..4: s*s macroparticles per cell, weight n0 h^2 / s^2 */
+    double jitter;       /* J in cells, 0 <= J <= 0.5/s: uniform displacement of each lattice point */
+    uint64_t seed;       /* SplitMix64 seed of the jitter */
+    double n0;           /* plasma density and ion background (1 in the paper's units) */
+    double dxi0;         /* initial step of Algorithm 1 (> 0) */
+    int32_t adaptive;    /* 1: Step_Size_Refinement, 0: fixed dxi0 */
+    int32_t refine_k;    /* floor dxi >= dxi0 / k; 0 = no floor */
+    int32_t precision;   /* wandqs_precision */
+    double mg_rtol;      /* stop when ||r|| <= rtol ||f|| + atol sqrt(n) or at the rounding
+                            floor; rtol <= 0: exactly mg_max_cycles V-cycles, no host syncs */
+    double mg_atol;
+    int32_t mg_max_cycles; /* 1 .. 200 */
+    int32_t nu_pre, nu_post; /* red-black Gauss-Seidel sweeps per V-cycle, each 1 .. 3 */
+    int32_t n_beams;       /* 0 .. 8 */
+    const wandqs_beam* beams;
+    int32_t n_probes;      /* 0 .. 16 */
+    const wandqs_probe* probes;
+    int32_t checkpoint_every; /* K for the adjoint tape; 0 = no tape */
+} wandqs_config;
+
+typedef struct {
+    double xi;            /* slice position */
+    double dxi;           /* step taken from this slice to the next */
+    double vmax;          /* max |V_perp| after the push (Algorithm 1) */
+    int32_t vcycles[5];   /* V-cycles per field solve (psi, Ez, Bz, Bx, By); -1 if not tracked */
+    double rel_resid[5];  /* final ||r||/||f|| per field; -1 if not tracked */
+    int32_t flags;        /* bit 0: 1+psi <= 0 met */
+} wandqs_slice_info;
+
+/* Bytes of device workspace needed for cfg and runs of up to n_slices slices
+ * per wandqs_run call (n_slices >= 1; it sizes the per-slice record buffer). */
+wandqs_status wandqs_workspace_bytes(const wandqs_config* cfg, int32_t n_slices, size_t* bytes);
+
+/* Validate cfg, bind the caller's workspace (d_workspace, >= 256-byte aligned,
+ * at least wandqs_workspace_bytes), build the cold plasma at rest on the lattice
+ * (Sec. III.A: H = 1, P = 0 before the driver), zero the fields, xi = 0,
+ * dxi = dxi0.  hip_stream is a hipStream_t (NULL: the null stream).  Synchronises
+ * the stream once.  *out is NULL on error. */
+wandqs_status wandqs_init(const wandqs_config* cfg, int32_t n_slices, void* d_workspace,
+                          size_t bytes, void* hip_stream, wandqs_ctx** out);
+
+/* One xi-slice: sort, deposit, five solves, push, step update.  d_fields_out
+ * (device [5][N+1][N+1] or NULL) receives the fields of this slice; h_info
+ * (host, or NULL) its record (synchronises the stream). */
+wandqs_status wandqs_slice_step(wandqs_ctx* ctx, double* d_fields_out, wandqs_slice_info* h_info);
+
+/* n_slices consecutive slices.  d_probe_out (device [n_probes] or NULL)
+ * receives the probe means; h_infos (host [n_slices] or NULL) one record per
+ * slice.  Records are gathered on the device and copied once per call. */
+wandqs_status wandqs_run(wandqs_ctx* ctx, int32_t n_slices, double* d_probe_out,
+                         wandqs_slice_info* h_infos);
+
+/* Current state.  d_particles (device [4][P], rows x, y, px, py in particle-ID
+ * order, P = N^2 s^2), d_fields (device [5][N+1][N+1]: the last solved fields,
+ * used as the next slice's multigrid initial guesses) and h_xi_dxi (host [2])
+ * may each be NULL.  h_xi_dxi synchronises the stream. */
+wandqs_status wandqs_get_state(wandqs_ctx* ctx, double* d_particles, double* d_fields,
+                               double* h_xi_dxi);
+
+/* Replace the state (same layouts; NULL leaves that part unchanged).  Field
+ * boundary nodes are set to zero.  Clears a failed context. */
+wandqs_status wandqs_set_state(wandqs_ctx* ctx, const double* d_particles,
+                               const double* d_fields, const double* h_xi_dxi);
+
+/* Multigrid solve on the context's grid, the solver of Solve_Wakefield
+ * (Sec. II item 4, Sec. VII.A): (L_h - k2) u = f on the interior nodes with
+ * u = 0 on the boundary, L_h the 5-point Laplacian of eq. (33).  nrhs = 1 or 2
+ * right-hand sides share the operator.  d_k2 (device [N+1][N+1], k2 >= 0) or
+ * NULL for Poisson; d_f (device [nrhs][N+1][N+1]); d_u (device, same shape)
+ * holds the initial guess and receives the solution.  Uses the context's
+ * mg_* settings; h_cycles / h_rel (host, may be NULL) receive the V-cycle count
+ * and ||r||/||f|| per rhs.  Clobbers the context's multigrid scratch arrays and
+ * the stored fields used as initial guesses. */
+wandqs_status wandqs_mg_solve(wandqs_ctx* ctx, int32_t nrhs, const double* d_k2,
+                              const double* d_f, double* d_u, int32_t* h_cycles, double* h_rel);
+
+/* Diagnostic copy of the node arrays of the last slice (device [9][N+1][N+1]):
+ * n*, jx, jy, Txx, Txy, Tyy, k2 = n* / (1+psi), f_Bx, f_By. */
+wandqs_status wandqs_get_moments(wandqs_ctx* ctx, double* d_out);
+
+/* Number of plasma macroparticles P of the context (0 for NULL). */
+int64_t wandqs_num_particles(const wandqs_ctx* ctx);
+
+/* Releases host resources; does not free the caller's workspace.  NULL is a no-op. */
+void wandqs_destroy(wandqs_ctx* ctx);
+
+/* Message of the last error of ctx (or of the last failed wandqs_init when ctx is NULL). */
+const char* wandqs_last_error(const wandqs_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WANDQS_H */

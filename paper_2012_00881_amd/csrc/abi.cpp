@@ -1,0 +1,477 @@
+// C ABI of the wandqs library: configuration checks, workspace layout, plasma
+// initialisation and the slice loop (WAND-PIC Algorithm 1, inner xi loop).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "wq_common.h"
+
+namespace {
+
+thread_local std::string g_init_err;
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Returns an empty string when the configuration is valid.
+std::string check_config(const wandqs_config* c, int32_t n_slices) {
+    if (!c) return "config is NULL";
+    if (n_slices < 1) return "n_slices must be >= 1";
+    if (!is_pow2(c->n_cells) || c->n_cells < 8 || c->n_cells > 4096)
+        return "n_cells must be a power of two in [8, 4096]";
+    if (!(c->half_width > 0.0) || !std::isfinite(c->half_width)) return "half_width must be > 0";
+    if (c->ppc_side < 1 || c->ppc_side > 4) return "ppc_side must be in [1, 4]";
+    if (!(c->jitter >= 0.0) || c->jitter > 0.5 / c->ppc_side)
+        return "jitter must be in [0, 0.5/ppc_side]";
+    if (!(c->n0 > 0.0) || !std::isfinite(c->n0)) return "n0 must be > 0";
+    if (!(c->dxi0 > 0.0) || !std::isfinite(c->dxi0)) return "dxi0 must be > 0";
+    if (c->adaptive != 0 && c->adaptive != 1) return "adaptive must be 0 or 1";
+    if (c->refine_k < 0) return "refine_k must be >= 0";
+    if (c->precision != WANDQS_FP64) return "precision: only WANDQS_FP64 is available";
+    if (!std::isfinite(c->mg_rtol) || !(c->mg_atol >= 0.0)) return "bad mg_rtol / mg_atol";
+    if (c->mg_max_cycles < 1 || c->mg_max_cycles > 200) return "mg_max_cycles must be in [1, 200]";
+    if (c->nu_pre < 1 || c->nu_pre > 3 || c->nu_post < 1 || c->nu_post > 3)
+        return "nu_pre and nu_post must be in [1, 3]";
+    if (c->n_beams < 0 || c->n_beams > wq::kMaxBeams) return "n_beams must be in [0, 8]";
+    if (c->n_beams > 0 && !c->beams) return "beams is NULL";
+    for (int k = 0; k < c->n_beams; ++k) {
+        const wandqs_beam& b = c->beams[k];
+        if (!(b.sigma_z > 0.0)) return "beam sigma_z must be > 0";
+        if (b.kind == WANDQS_BEAM_GAUSS) {
+            if (!(b.sigma_r > 0.0)) return "beam sigma_r must be > 0";
+        } else if (b.kind == WANDQS_BEAM_RADIAL_BINS) {
+            if (b.n_bins < 1 || b.n_bins > 4096 || !(b.r_max > 0.0) || !b.bin_amp)
+                return "radial-bin beam needs 1..4096 bins, r_max > 0 and bin_amp";
+        } else {
+            return "unknown beam kind";
+        }
+    }
+    if (c->n_probes < 0 || c->n_probes > wq::kMaxProbes) return "n_probes must be in [0, 16]";
+    if (c->n_probes > 0 && !c->probes) return "probes is NULL";
+    for (int k = 0; k < c->n_probes; ++k) {
+        const wandqs_probe& p = c->probes[k];
+        if (p.field < 0 || p.field > 4 || p.slice_begin < 0 || p.slice_end <= p.slice_begin ||
+            !(p.r_max >= 0.0))
+            return "bad probe";
+    }
+    if (c->checkpoint_every < 0) return "checkpoint_every must be >= 0";
+    return "";
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014), counter form: draw k of stream `seed`.
+uint64_t splitmix64(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+double unit(uint64_t z) { return (double)(z >> 11) * 0x1.0p-53; }
+
+int total_bins(const wandqs_config* cfg) {
+    int t = 0;
+    for (int k = 0; k < cfg->n_beams; ++k)
+        if (cfg->beams[k].kind == WANDQS_BEAM_RADIAL_BINS) t += cfg->beams[k].n_bins;
+    return t;
+}
+
+void set_sizes(wandqs_ctx* c, const wandqs_config* cfg, int32_t n_slices) {
+    c->N = cfg->n_cells;
+    c->L = cfg->half_width;
+    c->h = 2.0 * c->L / c->N;
+    c->ppc = cfg->ppc_side * cfg->ppc_side;
+    c->P = (int64_t)c->N * c->N * c->ppc;
+    c->nlev = 0;
+    for (int n = c->N; n >= 2; n /= 2) {
+        wq::Level& L = c->lev[c->nlev];
+        L.N = n;
+        L.h = c->h * (double)(c->N / n);
+        L.pitch = ((n + 1) + 7) & ~7;
+        ++c->nlev;
+    }
+    // lc: first level with N <= kCoarseMax
+    c->lc = 0;
+    while (c->lev[c->lc].N > wq::kCoarseMax) ++c->lc;
+    const int t = (c->N + wq::kTile - 1) / wq::kTile;
+    c->max_tiles = t * t;
+    c->n_push_blocks = (int)((c->P + 255) / 256);
+    c->n_scan_blocks = (c->N * c->N + 2047) / 2048;
+    c->rec_cap = n_slices;
+    c->n_bins_total = total_bins(cfg);
+}
+
+wandqs_status fail(wandqs_ctx* c, wandqs_status s) {
+    if (s != WANDQS_OK && s != WANDQS_E_INVALID) c->failed = true;
+    return s;
+}
+
+// One slice (Algorithm 1 inner loop body).
+wandqs_status do_slice(wandqs_ctx* c, int rec_slot, int64_t probe_slice) {
+    using namespace wq;
+    wandqs_status s;
+    Level& L0 = c->lev[0];
+    if ((s = slice_sort(c)) != WANDQS_OK) return s;
+    if ((s = deposit_n(c)) != WANDQS_OK) return s;  // Collect_Source: n*
+    double* u1[2] = {c->fields[0], nullptr};
+    double* f1[2] = {L0.f[0], nullptr};
+    if ((s = mg_solve(c, kSolvePsi, 1, false, u1, f1, nullptr, &c->last[0])) != WANDQS_OK) return s;
+    if ((s = deposit_jT(c)) != WANDQS_OK) return s;  // Collect_Source: j, T
+    if ((s = rhs_EB(c)) != WANDQS_OK) return s;
+    double* u2[2] = {c->fields[1], c->fields[2]};
+    double* f2[2] = {L0.f[0], L0.f[1]};
+    if ((s = mg_solve(c, kSolveEB, 2, false, u2, f2, nullptr, &c->last[1])) != WANDQS_OK) return s;
+    if ((s = assemble(c)) != WANDQS_OK) return s;
+    double* u3[2] = {c->fields[3], c->fields[4]};
+    if ((s = mg_solve(c, kSolveBperp, 2, true, u3, f2, L0.k2, &c->last[2])) != WANDQS_OK) return s;
+    if (!c->probes.empty() && (s = probes_accumulate(c, probe_slice)) != WANDQS_OK) return s;
+    return push_and_step(c, rec_slot);  // Push_Trajectory + Step_Size_Refinement
+}
+
+void fill_info_host(const wandqs_ctx* c, wandqs_slice_info* info) {
+    const wq::SolveResult* r = c->last;
+    const int idx[5][2] = {{0, 0}, {1, 0}, {1, 1}, {2, 0}, {2, 1}};
+    for (int k = 0; k < 5; ++k) {
+        info->vcycles[k] = r[idx[k][0]].cycles;
+        info->rel_resid[k] = r[idx[k][0]].rel[idx[k][1]];
+    }
+}
+
+wandqs_status check_flags(wandqs_ctx* c) {
+    int32_t fl = 0;
+    WQ_HIP(hipMemcpyAsync(&fl, c->flags, sizeof(fl), hipMemcpyDeviceToHost, c->stream));
+    WQ_HIP(hipStreamSynchronize(c->stream));
+    if (fl & 1) {
+        c->err = "1 + psi <= 0 where plasma is present";
+        return WANDQS_E_NONPHYS;
+    }
+    return WANDQS_OK;
+}
+
+}  // namespace
+
+size_t wq::carve(wandqs_ctx* c, char* base) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        off = (off + 255) & ~(size_t)255;
+        char* p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    auto arr = [&](int l) {
+        return (double*)take(sizeof(double) * (size_t)(c->lev[l].N + 1) * c->lev[l].pitch);
+    };
+    Level& L0 = c->lev[0];
+    for (int k = 0; k < 5; ++k) c->fields[k] = arr(0);
+    for (int r = 0; r < 2; ++r) {
+        L0.um[r] = arr(0);
+        L0.f[r] = arr(0);
+    }
+    L0.k2 = arr(0);
+    for (int k = 0; k < 6; ++k) c->mom[k] = arr(0);
+    c->jz = arr(0);
+    for (int l = 1; l <= c->lc; ++l) {
+        Level& L = c->lev[l];
+        for (int r = 0; r < 2; ++r) {
+            L.u[r] = arr(l);
+            L.um[r] = l < c->lc ? arr(l) : nullptr;
+            L.f[r] = arr(l);
+        }
+        L.k2 = arr(l);
+    }
+    const size_t P = (size_t)c->P;
+    const size_t ncell = (size_t)c->N * c->N;
+    for (int s = 0; s < 2; ++s) {
+        for (int k = 0; k < 4; ++k) c->pa[s][k] = (double*)take(sizeof(double) * P);
+        c->pid[s] = (int32_t*)take(sizeof(int32_t) * P);
+    }
+    c->key = (int32_t*)take(sizeof(int32_t) * P);
+    c->perm = (int32_t*)take(sizeof(int32_t) * P);
+    c->cell_count = (int32_t*)take(sizeof(int32_t) * ncell);
+    c->cell_start = (int32_t*)take(sizeof(int32_t) * (ncell + 1));
+    c->scan_blk = (int32_t*)take(sizeof(int32_t) * c->n_scan_blocks);
+    c->st = (double*)take(sizeof(double) * 2);
+    c->vmax_part = (double*)take(sizeof(double) * c->n_push_blocks);
+    c->flags = (int32_t*)take(sizeof(int32_t) * 4);
+    c->norm_part = (double*)take(sizeof(double) * kMaxSlots * 4 * (size_t)c->max_tiles);
+    c->norm_red = (double*)take(sizeof(double) * kMaxSlots * 4);
+    c->rec = (double*)take(sizeof(double) * 4 * (size_t)c->rec_cap);
+    c->probe_acc = (double*)take(sizeof(double) * kMaxProbes);
+    c->bins_dev = (double*)take(sizeof(double) * (size_t)(c->n_bins_total + 1));
+    return (off + 255) & ~(size_t)255;
+}
+
+const char* wq::hip_err(hipError_t e) { return hipGetErrorString(e); }
+
+extern "C" {
+
+wandqs_status wandqs_workspace_bytes(const wandqs_config* cfg, int32_t n_slices, size_t* bytes) {
+    const std::string e = check_config(cfg, n_slices);
+    if (!e.empty() || !bytes) {
+        g_init_err = e.empty() ? "bytes is NULL" : e;
+        return WANDQS_E_INVALID;
+    }
+    wandqs_ctx tmp;
+    tmp.cfg = *cfg;
+    set_sizes(&tmp, cfg, n_slices);
+    *bytes = wq::carve(&tmp, nullptr);
+    return WANDQS_OK;
+}
+
+wandqs_status wandqs_init(const wandqs_config* cfg, int32_t n_slices, void* d_workspace,
+                          size_t bytes, void* hip_stream, wandqs_ctx** out) {
+    if (!out) {
+        g_init_err = "out is NULL";
+        return WANDQS_E_INVALID;
+    }
+    *out = nullptr;
+    const std::string e = check_config(cfg, n_slices);
+    if (!e.empty()) {
+        g_init_err = e;
+        return WANDQS_E_INVALID;
+    }
+    if (!d_workspace || ((uintptr_t)d_workspace & 255)) {
+        g_init_err = "workspace must be a 256-byte aligned device pointer";
+        return WANDQS_E_INVALID;
+    }
+    wandqs_ctx* c = new (std::nothrow) wandqs_ctx();
+    if (!c) {
+        g_init_err = "out of host memory";
+        return WANDQS_E_NOMEM;
+    }
+    c->cfg = *cfg;
+    c->beams.assign(cfg->beams, cfg->beams + cfg->n_beams);
+    c->probes.assign(cfg->probes, cfg->probes + cfg->n_probes);
+    c->cfg.beams = nullptr;
+    c->cfg.probes = nullptr;
+    for (auto& b : c->beams) {
+        if (b.kind == WANDQS_BEAM_RADIAL_BINS) c->bin_amp.emplace_back(b.bin_amp, b.bin_amp + b.n_bins);
+        else c->bin_amp.emplace_back();
+        b.bin_amp = nullptr;
+    }
+    c->stream = (hipStream_t)hip_stream;
+    set_sizes(c, cfg, n_slices);
+    const size_t need = wq::carve(c, nullptr);
+    if (bytes < need) {
+        g_init_err = "workspace too small: need " + std::to_string(need) + " bytes";
+        delete c;
+        return WANDQS_E_NOMEM;
+    }
+    wq::carve(c, (char*)d_workspace);
+
+    auto bail = [&](const std::string& msg) {
+        g_init_err = msg;
+        if (c->h_pin) (void)hipHostFree(c->h_pin);
+        delete c;
+        return WANDQS_E_HIP;
+    };
+    if (hipHostMalloc((void**)&c->h_pin, sizeof(double) * (wq::kMaxSlots * 4 + 8)) != hipSuccess)
+        return bail("hipHostMalloc failed");
+    if (hipMemsetAsync(d_workspace, 0, need, c->stream) != hipSuccess)
+        return bail("hipMemsetAsync of the workspace failed");
+
+    // beams: device copy of the bin amplitudes and the by-value descriptor
+    wq::BeamSet& B = c->beamset;
+    B.n = (int)c->beams.size();
+    size_t boff = 0;
+    std::vector<double> bins_host;
+    for (int k = 0; k < B.n; ++k) {
+        const wandqs_beam& b = c->beams[k];
+        B.kind[k] = b.kind;
+        B.amp[k] = b.amp;
+        B.sr[k] = b.sigma_r;
+        B.sz[k] = b.sigma_z;
+        B.xc[k] = b.xi_c;
+        B.x0[k] = b.x0;
+        B.y0[k] = b.y0;
+        B.rmax[k] = b.r_max;
+        B.nbins[k] = b.n_bins;
+        B.bins[k] = nullptr;
+        if (b.kind == WANDQS_BEAM_RADIAL_BINS) {
+            B.bins[k] = c->bins_dev + boff;
+            bins_host.insert(bins_host.end(), c->bin_amp[k].begin(), c->bin_amp[k].end());
+            boff += b.n_bins;
+        }
+    }
+
+    // cold plasma at rest on the jittered lattice (same generator and draw order
+    // as the test-side input module)
+    const int N = c->N, s = cfg->ppc_side;
+    const double L = c->L, h = c->h, J = cfg->jitter;
+    std::vector<double> host((size_t)c->P * 2);
+    std::vector<int32_t> ids((size_t)c->P);
+    size_t i = 0;
+    for (int b = 0; b < N; ++b)
+        for (int a = 0; a < N; ++a)
+            for (int sy = 0; sy < s; ++sy)
+                for (int sx = 0; sx < s; ++sx, ++i) {
+                    const double ux = unit(splitmix64(cfg->seed, 2 * i));
+                    const double uy = unit(splitmix64(cfg->seed, 2 * i + 1));
+                    host[i] = -L + h * (((double)a + ((double)sx + 0.5) / s) + J * (2.0 * ux - 1.0));
+                    host[c->P + i] = -L + h * (((double)b + ((double)sy + 0.5) / s) + J * (2.0 * uy - 1.0));
+                    ids[i] = (int32_t)i;
+                }
+    const double st0[2] = {0.0, cfg->dxi0};
+    bool ok = hipMemcpyAsync(c->pa[0][0], host.data(), sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+              hipMemcpyAsync(c->pa[0][1], host.data() + c->P, sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+              hipMemcpyAsync(c->pid[0], ids.data(), sizeof(int32_t) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+              hipMemcpyAsync(c->st, st0, sizeof(st0), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+              (bins_host.empty() || hipMemcpyAsync(c->bins_dev, bins_host.data(), sizeof(double) * bins_host.size(), hipMemcpyHostToDevice, c->stream) == hipSuccess) &&
+              hipStreamSynchronize(c->stream) == hipSuccess;
+    if (!ok) return bail("copying the initial state failed");
+    c->cur = 0;
+    *out = c;
+    return WANDQS_OK;
+}
+
+wandqs_status wandqs_slice_step(wandqs_ctx* c, double* d_fields_out, wandqs_slice_info* h_info) {
+    if (!c) return WANDQS_E_INVALID;
+    if (c->failed) {
+        c->err = "context failed earlier; call wandqs_set_state";
+        return WANDQS_E_STATE;
+    }
+    wandqs_status s = do_slice(c, 0, -1);
+    if (s != WANDQS_OK) return fail(c, s);
+    if (d_fields_out && (s = wq::pack_fields(c, c->fields, 5, d_fields_out)) != WANDQS_OK)
+        return fail(c, s);
+    if (h_info) {
+        double r[4];
+        if (hipMemcpyAsync(r, c->rec, sizeof(r), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess) {
+            c->err = "reading the slice record failed";
+            return fail(c, WANDQS_E_HIP);
+        }
+        h_info->xi = r[0];
+        h_info->dxi = r[1];
+        h_info->vmax = r[2];
+        h_info->flags = (int32_t)r[3];
+        fill_info_host(c, h_info);
+        if (h_info->flags & 1) {
+            c->err = "1 + psi <= 0 where plasma is present";
+            return fail(c, WANDQS_E_NONPHYS);
+        }
+    }
+    return WANDQS_OK;
+}
+
+wandqs_status wandqs_run(wandqs_ctx* c, int32_t n_slices, double* d_probe_out,
+                         wandqs_slice_info* h_infos) {
+    if (!c || n_slices < 0) return WANDQS_E_INVALID;
+    if (c->failed) {
+        c->err = "context failed earlier; call wandqs_set_state";
+        return WANDQS_E_STATE;
+    }
+    wandqs_status s;
+    if (!c->probes.empty() && (s = wq::fill_f64(c, c->probe_acc, wq::kMaxProbes, 0.0)) != WANDQS_OK)
+        return fail(c, s);
+    std::vector<double> rec;
+    int32_t chunk0 = 0;
+    auto flush = [&](int32_t upto) -> wandqs_status {
+        const int32_t n = upto - chunk0;
+        if (!h_infos || n <= 0) return WANDQS_OK;
+        rec.resize((size_t)4 * n);
+        WQ_HIP(hipMemcpyAsync(rec.data(), c->rec, sizeof(double) * 4 * n, hipMemcpyDeviceToHost, c->stream));
+        WQ_HIP(hipStreamSynchronize(c->stream));
+        for (int32_t j = 0; j < n; ++j) {
+            h_infos[chunk0 + j].xi = rec[4 * j];
+            h_infos[chunk0 + j].dxi = rec[4 * j + 1];
+            h_infos[chunk0 + j].vmax = rec[4 * j + 2];
+            h_infos[chunk0 + j].flags = (int32_t)rec[4 * j + 3];
+        }
+        chunk0 = upto;
+        return WANDQS_OK;
+    };
+    for (int32_t j = 0; j < n_slices; ++j) {
+        if (j - chunk0 == c->rec_cap && (s = flush(j)) != WANDQS_OK) return fail(c, s);
+        if ((s = do_slice(c, j - chunk0, j)) != WANDQS_OK) {
+            flush(j);
+            return fail(c, s);
+        }
+        if (h_infos) fill_info_host(c, &h_infos[j]);
+    }
+    if ((s = flush(n_slices)) != WANDQS_OK) return fail(c, s);
+    if (d_probe_out && !c->probes.empty()) {
+        if (hipMemcpyAsync(d_probe_out, c->probe_acc, sizeof(double) * c->probes.size(),
+                           hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
+            c->err = "copying the probes failed";
+            return fail(c, WANDQS_E_HIP);
+        }
+    }
+    if ((s = check_flags(c)) != WANDQS_OK) return fail(c, s);
+    return WANDQS_OK;
+}
+
+wandqs_status wandqs_get_state(wandqs_ctx* c, double* d_particles, double* d_fields,
+                               double* h_xi_dxi) {
+    if (!c) return WANDQS_E_INVALID;
+    wandqs_status s;
+    if (d_particles && (s = wq::particles_to_id_order(c, d_particles)) != WANDQS_OK) return fail(c, s);
+    if (d_fields && (s = wq::pack_fields(c, c->fields, 5, d_fields)) != WANDQS_OK) return fail(c, s);
+    if (h_xi_dxi) {
+        WQ_HIP(hipMemcpyAsync(h_xi_dxi, c->st, sizeof(double) * 2, hipMemcpyDeviceToHost, c->stream));
+        WQ_HIP(hipStreamSynchronize(c->stream));
+    }
+    return WANDQS_OK;
+}
+
+wandqs_status wandqs_set_state(wandqs_ctx* c, const double* d_particles, const double* d_fields,
+                               const double* h_xi_dxi) {
+    if (!c) return WANDQS_E_INVALID;
+    if (h_xi_dxi && (!std::isfinite(h_xi_dxi[0]) || !(h_xi_dxi[1] > 0.0))) {
+        c->err = "xi must be finite and dxi > 0";
+        return WANDQS_E_INVALID;
+    }
+    wandqs_status s;
+    if (d_particles && (s = wq::particles_from_id_order(c, d_particles)) != WANDQS_OK) return fail(c, s);
+    if (d_fields && (s = wq::unpack_fields(c, d_fields, 5, c->fields)) != WANDQS_OK) return fail(c, s);
+    if (h_xi_dxi) WQ_HIP(hipMemcpyAsync(c->st, h_xi_dxi, sizeof(double) * 2, hipMemcpyHostToDevice, c->stream));
+    WQ_HIP(hipMemsetAsync(c->flags, 0, sizeof(int32_t), c->stream));
+    WQ_HIP(hipStreamSynchronize(c->stream));
+    c->failed = false;
+    return WANDQS_OK;
+}
+
+wandqs_status wandqs_mg_solve(wandqs_ctx* c, int32_t nrhs, const double* d_k2, const double* d_f,
+                              double* d_u, int32_t* h_cycles, double* h_rel) {
+    if (!c || (nrhs != 1 && nrhs != 2) || !d_f || !d_u) return WANDQS_E_INVALID;
+    wandqs_status s;
+    wq::Level& L0 = c->lev[0];
+    if ((s = wq::unpack_fields(c, d_f, nrhs, L0.f)) != WANDQS_OK) return fail(c, s);
+    if ((s = wq::unpack_fields(c, d_u, nrhs, c->fields)) != WANDQS_OK) return fail(c, s);
+    if (d_k2 && (s = wq::unpack_fields(c, d_k2, 1, &L0.k2)) != WANDQS_OK) return fail(c, s);
+    wq::SolveResult res;
+    double* u[2] = {c->fields[0], nrhs > 1 ? c->fields[1] : nullptr};
+    double* f[2] = {L0.f[0], nrhs > 1 ? L0.f[1] : nullptr};
+    s = wq::mg_solve(c, 3, nrhs, d_k2 != nullptr, u, f, d_k2 ? L0.k2 : nullptr, &res);
+    if (s != WANDQS_OK && s != WANDQS_E_NOCONV) return fail(c, s);
+    wandqs_status s2 = wq::pack_fields(c, c->fields, nrhs, d_u);
+    if (s2 != WANDQS_OK) return fail(c, s2);
+    WQ_HIP(hipStreamSynchronize(c->stream));
+    if (h_cycles) *h_cycles = res.cycles;
+    if (h_rel)
+        for (int r = 0; r < nrhs; ++r) h_rel[r] = res.rel[r];
+    return s;
+}
+
+wandqs_status wandqs_get_moments(wandqs_ctx* c, double* d_out) {
+    if (!c || !d_out) return WANDQS_E_INVALID;
+    double* src[9] = {c->mom[0], c->mom[1], c->mom[2], c->mom[3], c->mom[4], c->mom[5],
+                      c->lev[0].k2, c->lev[0].f[0], c->lev[0].f[1]};
+    wandqs_status s = wq::pack_fields(c, src, 9, d_out);
+    return s == WANDQS_OK ? s : fail(c, s);
+}
+
+int64_t wandqs_num_particles(const wandqs_ctx* c) { return c ? c->P : 0; }
+
+void wandqs_destroy(wandqs_ctx* c) {
+    if (!c) return;
+    if (c->h_pin) (void)hipHostFree(c->h_pin);
+    delete c;
+}
+
+const char* wandqs_last_error(const wandqs_ctx* c) {
+    return c ? c->err.c_str() : g_init_err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,222 @@
+// Node-array kernels of one slice: the right-hand sides of the Ez and Bz
+// Poisson equations (WAND-PIC Sec. III.B eqs. (13)-(14)), the longitudinal
+// current with the frozen driver, the B_perp Helmholtz system (eqs. (18)-(19),
+// rows 4-5 of eq. (30) with the laser envelope absent), probes and layout
+// conversion between the padded internal arrays and the dense interface arrays.
+#include "wq_common.h"
+
+namespace wq {
+namespace {
+
+// f_Ez = -(D_x jx + D_y jy), f_Bz = D_x jy - D_y jx on the interior nodes.
+__global__ void k_rhs_EB(int N, double h, int pitch, const double* __restrict__ jx,
+                         const double* __restrict__ jy, double* __restrict__ fE,
+                         double* __restrict__ fB) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (a > N) return;
+    const size_t g = (size_t)b * pitch + a;
+    double e = 0.0, m = 0.0;
+    if (a >= 1 && b >= 1 && a <= N - 1 && b <= N - 1) {
+        const double i2h = 1.0 / (2.0 * h);
+        const double dxjx = (jx[g + 1] - jx[g - 1]) * i2h;
+        const double dyjy = (jy[g + pitch] - jy[g - pitch]) * i2h;
+        const double dxjy = (jy[g + 1] - jy[g - 1]) * i2h;
+        const double dyjx = (jx[g + pitch] - jx[g - pitch]) * i2h;
+        e = -(dxjx + dyjy);
+        m = dxjy - dyjx;
+    }
+    fE[g] = e;
+    fB[g] = m;
+}
+
+__device__ double beam_density(const BeamSet& B, double x, double y, double xi) {
+    if (xi < 0.0) return 0.0;
+    double s = 0.0;
+    for (int k = 0; k < B.n; ++k) {
+        const double rx = x - B.x0[k], ry = y - B.y0[k];
+        const double r2 = rx * rx + ry * ry;
+        const double lz = (xi - B.xc[k]) * (xi - B.xc[k]) / (B.sz[k] * B.sz[k]);
+        if (B.kind[k] == 0) {
+            s += B.amp[k] * exp(-r2 / (B.sr[k] * B.sr[k]) - lz);
+        } else {
+            const double r = sqrt(r2);
+            const double dr = B.rmax[k] / B.nbins[k];
+            const int kb = (int)floor(r / dr);
+            if (r < B.rmax[k] && kb < B.nbins[k]) s += B.bins[k][kb] * exp(-lz);
+        }
+    }
+    return s;
+}
+
+// Total j_z on every node: plasma n*<p_z>/g = G/g - n* with G = n*<gamma> =
+// [n*(1 + g^2) + g^2 (Txx + Tyy)]/(2g) (eq. (9) and the gamma of Sec. III.A,
+// <p_perp^2> = g^2 <V^2>), plus the driver density at xi (luminal beam current).
+__global__ void k_jz(int N, double L, double h, int pitch, const double* __restrict__ n,
+                     const double* __restrict__ txx, const double* __restrict__ tyy,
+                     const double* __restrict__ psi, const double* __restrict__ st, BeamSet beams,
+                     double* __restrict__ jz, int32_t* __restrict__ flags) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (a > N) return;
+    const size_t i = (size_t)b * pitch + a;
+    double v = 0.0;
+    if (n[i] > 0.0) {
+        const double g = 1.0 + psi[i];
+        if (!(g > 0.0)) atomicOr(flags, 1);
+        const double G = (n[i] * (1.0 + g * g) + g * g * (txx[i] + tyy[i])) / (2.0 * g);
+        v = G / g - n[i];
+    }
+    jz[i] = v + beam_density(beams, -L + a * h, -L + b * h, st[0]);
+}
+
+// k2 = n* / g and the B_perp right-hand sides on the interior nodes:
+//   f_Bx = D_y(j_z - Tyy) - D_x Txy + (jx Bz - jy Ez)/g + (G/g^2 - Tyy/g) psi_y - (Txy/g) psi_x
+//   f_By = D_x(Txx - j_z) + D_y Txy + (jy Bz + jx Ez)/g - (G/g^2 - Txx/g) psi_x + (Txy/g) psi_y
+__global__ void k_assemble(int N, double h, int pitch, const double* __restrict__ n,
+                           const double* __restrict__ jx, const double* __restrict__ jy,
+                           const double* __restrict__ txx, const double* __restrict__ txy,
+                           const double* __restrict__ tyy, const double* __restrict__ psi,
+                           const double* __restrict__ Ez, const double* __restrict__ Bz,
+                           const double* __restrict__ jz, double* __restrict__ k2,
+                           double* __restrict__ fBx, double* __restrict__ fBy) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (a > N) return;
+    const size_t i = (size_t)b * pitch + a;
+    double k = 0.0, fx = 0.0, fy = 0.0;
+    if (a >= 1 && b >= 1 && a <= N - 1 && b <= N - 1) {
+        const double i2h = 1.0 / (2.0 * h);
+        const size_t e = i + 1, w = i - 1, nn = i + pitch, s = i - pitch;
+        const double g = 1.0 + psi[i];
+        const double psx = (psi[e] - psi[w]) * i2h, psy = (psi[nn] - psi[s]) * i2h;
+        fx = ((jz[nn] - tyy[nn]) - (jz[s] - tyy[s])) * i2h - (txy[e] - txy[w]) * i2h;
+        fy = ((txx[e] - jz[e]) - (txx[w] - jz[w])) * i2h + (txy[nn] - txy[s]) * i2h;
+        if (n[i] > 0.0) {
+            const double G = (n[i] * (1.0 + g * g) + g * g * (txx[i] + tyy[i])) / (2.0 * g);
+            k = n[i] / g;
+            fx += (jx[i] * Bz[i] - jy[i] * Ez[i]) / g + (G / (g * g) - tyy[i] / g) * psy -
+                  (txy[i] / g) * psx;
+            fy += (jy[i] * Bz[i] + jx[i] * Ez[i]) / g - (G / (g * g) - txx[i] / g) * psx +
+                  (txy[i] / g) * psy;
+        }
+    }
+    k2[i] = k;
+    fBx[i] = fx;
+    fBy[i] = fy;
+}
+
+// Probe k adds the mean of its field over its disc (fixed summation order, one block).
+__global__ __launch_bounds__(256) void k_probe(int N, double L, double h, int pitch,
+                                               const double* __restrict__ F, double x0, double y0,
+                                               double rmax, double scale,
+                                               double* __restrict__ acc) {
+    __shared__ double red[2][4];
+    double s = 0.0, cnt = 0.0;
+    for (int i = threadIdx.x; i < (N + 1) * (N + 1); i += 256) {
+        const int b = i / (N + 1), a = i - b * (N + 1);
+        const double rx = -L + a * h - x0, ry = -L + b * h - y0;
+        if (rx * rx + ry * ry <= rmax * rmax) {
+            s += F[(size_t)b * pitch + a];
+            cnt += 1.0;
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        s += __shfl_xor(s, off, 64);
+        cnt += __shfl_xor(cnt, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = s;
+        red[1][threadIdx.x >> 6] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double S = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+        const double C = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+        if (C > 0) *acc += scale * S / C;
+    }
+}
+
+__global__ void k_pack(int N, int pitch, const double* __restrict__ src, double* __restrict__ dst) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (a > N) return;
+    dst[(size_t)b * (N + 1) + a] = src[(size_t)b * pitch + a];
+}
+
+__global__ void k_unpack(int N, int pitch, const double* __restrict__ src, double* __restrict__ dst) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (a > N) return;
+    const bool bnd = a == 0 || b == 0 || a == N || b == N;
+    dst[(size_t)b * pitch + a] = bnd ? 0.0 : src[(size_t)b * (N + 1) + a];
+}
+
+__global__ void k_fill(double* p, size_t n, double v) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+dim3 node_grid(int N) { return dim3((N + 1 + 127) / 128, N + 1); }
+
+}  // namespace
+
+wandqs_status rhs_EB(wandqs_ctx* c) {
+    const Level& L0 = c->lev[0];
+    hipLaunchKernelGGL(k_rhs_EB, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->h, L0.pitch,
+                       c->mom[1], c->mom[2], L0.f[0], L0.f[1]);
+    WQ_LAUNCH_CHECK();
+    return WANDQS_OK;
+}
+
+wandqs_status assemble(wandqs_ctx* c) {
+    const Level& L0 = c->lev[0];
+    hipLaunchKernelGGL(k_jz, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->L, c->h, L0.pitch,
+                       c->mom[0], c->mom[3], c->mom[5], c->fields[0], c->st, c->beamset, c->jz,
+                       c->flags);
+    hipLaunchKernelGGL(k_assemble, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->h, L0.pitch,
+                       c->mom[0], c->mom[1], c->mom[2], c->mom[3], c->mom[4], c->mom[5],
+                       c->fields[0], c->fields[1], c->fields[2], c->jz, L0.k2, L0.f[0], L0.f[1]);
+    WQ_LAUNCH_CHECK();
+    return WANDQS_OK;
+}
+
+wandqs_status probes_accumulate(wandqs_ctx* c, int64_t slice) {
+    for (size_t k = 0; k < c->probes.size(); ++k) {
+        const wandqs_probe& p = c->probes[k];
+        if (slice < p.slice_begin || slice >= p.slice_end) continue;
+        const double scale = 1.0 / (double)(p.slice_end - p.slice_begin);
+        hipLaunchKernelGGL(k_probe, dim3(1), dim3(256), 0, c->stream, c->N, c->L, c->h,
+                           c->lev[0].pitch, c->fields[p.field], p.x0, p.y0, p.r_max, scale,
+                           c->probe_acc + k);
+    }
+    WQ_LAUNCH_CHECK();
+    return WANDQS_OK;
+}
+
+wandqs_status pack_fields(wandqs_ctx* c, double* const* src, int n, double* dst) {
+    const size_t nn = (size_t)(c->N + 1) * (c->N + 1);
+    for (int k = 0; k < n; ++k)
+        hipLaunchKernelGGL(k_pack, node_grid(c->N), dim3(128), 0, c->stream, c->N,
+                           c->lev[0].pitch, src[k], dst + k * nn);
+    WQ_LAUNCH_CHECK();
+    return WANDQS_OK;
+}
+
+wandqs_status unpack_fields(wandqs_ctx* c, const double* src, int n, double* const* dst) {
+    const size_t nn = (size_t)(c->N + 1) * (c->N + 1);
+    for (int k = 0; k < n; ++k)
+        hipLaunchKernelGGL(k_unpack, node_grid(c->N), dim3(128), 0, c->stream, c->N,
+                           c->lev[0].pitch, src + k * nn, dst[k]);
+    WQ_LAUNCH_CHECK();
+    return WANDQS_OK;
+}
+
+wandqs_status fill_f64(wandqs_ctx* c, double* p, size_t n, double v) {
+    if (n == 0) return WANDQS_OK;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, p, n, v);
+    WQ_LAUNCH_CHECK();
+    return WANDQS_OK;
+}
+
+}  // namespace wq

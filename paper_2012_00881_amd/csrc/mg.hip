@@ -1,0 +1,731 @@
+// Geometric multigrid for (L_h - k2) u = f with u = 0 on the boundary, the
+// solver behind Solve_Wakefield (WAND-PIC, Sec. II item 4 and Sec. VII.A).
+// L_h is the 5-point Laplacian of Sec. VII.B eq. (33); psi, Ez and Bz use
+// k2 = 0 (eqs. (12)-(14)), B_perp uses k2 = n* / (1+psi) (eq. (18)).
+//
+// One V(nu1, nu2) cycle over levels N, N/2, ..., 2:
+//   * levels with N > 64 run two fused tile kernels per level:
+//       down: load a tile plus halo into LDS, nu1 red-black Gauss-Seidel sweeps,
+//             write the smoothed tile, residual, full-weighting restriction;
+//       up:   load a tile plus halo, add the bilinear prolongation of the coarse
+//             correction, nu2 sweeps, write the tile;
+//     the halo (2 nu + 2 nodes) makes the tile result identical to a global
+//     red-black sweep, so every node array is read and written once per pass;
+//   * the levels N <= 64 run inside one workgroup in LDS (one workgroup per
+//     right-hand side), the 2x2-cell grid solved exactly.
+// Two right-hand sides with one operator (Ez, Bz and Bx, By) share each pass.
+// All reductions (residual norms) have a fixed order: results are bitwise
+// reproducible.
+#include <cmath>
+#include <cstring>
+
+#include "wq_common.h"
+
+namespace wq {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kCoarseThreads = 1024;
+
+// Deterministic block sum of NV values; the result is valid in thread 0.
+template <int NV, int NT>
+__device__ void block_sum(double (&v)[NV], double* red) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], off, 64);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[wave * NV + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < NT / 64; ++w) s += red[w * NV + k];
+            v[k] = s;
+        }
+    }
+}
+
+// Red-black half sweep over the nodes of one colour inside an LDS tile whose
+// node (0, 0) is global node (ex0, ey0).  Nodes on the tile rim, on the domain
+// boundary or outside the domain are not updated.
+template <int R, bool HELM, int EX, int EY>
+__device__ __forceinline__ void rb_half_sweep(double (*su)[EX * EY], double (*sf)[EX * EY],
+                                              const double* sk, int ex0, int ey0, int N,
+                                              double h2, int color) {
+    constexpr int HALF = (EX - 1) / 2;
+    for (int i = threadIdx.x; i < (EY - 2) * HALF; i += kThreads) {
+        const int ly = 1 + i / HALF;
+        const int k = i - (ly - 1) * HALF;
+        const int gy = ey0 + ly;
+        const int lx = 1 + ((ex0 + 1 + gy + color) & 1) + 2 * k;
+        if (lx > EX - 2) continue;
+        const int gx = ex0 + lx;
+        if (gx < 1 || gx > N - 1 || gy < 1 || gy > N - 1) continue;
+        const int l = ly * EX + lx;
+        const double d = HELM ? 4.0 + h2 * sk[l] : 4.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double nb = su[r][l - 1] + su[r][l + 1] + su[r][l - EX] + su[r][l + EX];
+            su[r][l] = HELM ? (nb - h2 * sf[r][l]) / d : (nb - h2 * sf[r][l]) * 0.25;
+        }
+    }
+}
+
+struct DownArgs {
+    int N;
+    double h;
+    int pitch, pitch_c;
+    const double* u_in[2];  // nullptr: zero initial guess
+    const double* f[2];
+    const double* k2;
+    double* u_out[2];
+    double* f_c[2];
+    double* norm_part;      // nullptr or [R*2][nblk]: sum r^2, sum f^2 of the incoming u
+    int nblk;
+};
+
+template <int R, bool HELM, int NU, int TX, int TY>
+__global__ __launch_bounds__(kThreads) void k_mg_down(DownArgs a) {
+    constexpr int HL = 2 * NU + 2, HH = 2 * NU + 1;
+    constexpr int EX = TX + HL + HH, EY = TY + HL + HH, EN = EX * EY;
+    __shared__ double su[R][EN];
+    __shared__ double sf[R][EN];
+    __shared__ double sk[HELM ? EN : 1];
+    __shared__ double red[(kThreads / 64) * 2 * R];
+
+    const int tid = threadIdx.x;
+    const int N = a.N;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int ex0 = x0 - HL, ey0 = y0 - HL;
+    const double h2 = a.h * a.h, ih2 = 1.0 / h2;
+
+    for (int i = tid; i < EN; i += kThreads) {
+        const int ly = i / EX, lx = i - ly * EX;
+        const int gx = ex0 + lx, gy = ey0 + ly;
+        const bool in = gx >= 0 && gx <= N && gy >= 0 && gy <= N;
+        const size_t g = in ? (size_t)gy * a.pitch + gx : 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            su[r][i] = (in && a.u_in[r]) ? a.u_in[r][g] : 0.0;
+            sf[r][i] = in ? a.f[r][g] : 0.0;
+        }
+        if (HELM) sk[i] = in ? a.k2[g] : 0.0;
+    }
+    __syncthreads();
+
+    if (a.norm_part) {  // residual of the incoming iterate on the owned interior nodes
+        double acc[2 * R];
+#pragma unroll
+        for (int k = 0; k < 2 * R; ++k) acc[k] = 0.0;
+        for (int i = tid; i < TX * TY; i += kThreads) {
+            const int oy = i / TX, ox = i - oy * TX;
+            const int gx = x0 + ox, gy = y0 + oy;
+            if (gx < 1 || gx > N - 1 || gy < 1 || gy > N - 1) continue;
+            const int l = (oy + HL) * EX + ox + HL;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                double au = (su[r][l - 1] + su[r][l + 1] + su[r][l - EX] + su[r][l + EX] -
+                             4.0 * su[r][l]) * ih2;
+                if (HELM) au -= sk[l] * su[r][l];
+                const double rr = sf[r][l] - au;
+                acc[2 * r] += rr * rr;
+                acc[2 * r + 1] += sf[r][l] * sf[r][l];
+            }
+        }
+        block_sum<2 * R, kThreads>(acc, red);
+        if (tid == 0) {
+            const int b = blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll
+            for (int k = 0; k < 2 * R; ++k) a.norm_part[k * a.nblk + b] = acc[k];
+        }
+    }
+
+    for (int s = 0; s < NU; ++s)
+        for (int color = 0; color < 2; ++color) {
+            rb_half_sweep<R, HELM, EX, EY>(su, sf, sk, ex0, ey0, N, h2, color);
+            __syncthreads();
+        }
+
+    for (int i = tid; i < TX * TY; i += kThreads) {  // owned nodes x0..x0+TX-1 (< N)
+        const int oy = i / TX, ox = i - oy * TX;
+        const int gx = x0 + ox, gy = y0 + oy;
+        if (gx > N - 1 || gy > N - 1) continue;
+        const int l = (oy + HL) * EX + ox + HL;
+#pragma unroll
+        for (int r = 0; r < R; ++r) a.u_out[r][(size_t)gy * a.pitch + gx] = su[r][l];
+    }
+
+    // residual on [x0-1, x0+TX-1]^2, stored over f (each node reads only its own f)
+    for (int i = tid; i < (TX + 1) * (TY + 1); i += kThreads) {
+        const int oy = i / (TX + 1), ox = i - oy * (TX + 1);
+        const int gx = x0 - 1 + ox, gy = y0 - 1 + oy;
+        const int l = (oy + HL - 1) * EX + ox + HL - 1;
+        const bool interior = gx >= 1 && gx <= N - 1 && gy >= 1 && gy <= N - 1;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            double rr = 0.0;
+            if (interior) {
+                double au = (su[r][l - 1] + su[r][l + 1] + su[r][l - EX] + su[r][l + EX] -
+                             4.0 * su[r][l]) * ih2;
+                if (HELM) au -= sk[l] * su[r][l];
+                rr = sf[r][l] - au;
+            }
+            sf[r][l] = rr;
+        }
+    }
+    __syncthreads();
+
+    // full weighting onto coarse nodes x0/2 .. x0/2 + TX/2 - 1 (< N/2)
+    const int Nc = N / 2;
+    for (int i = tid; i < (TX / 2) * (TY / 2); i += kThreads) {
+        const int oy = i / (TX / 2), ox = i - oy * (TX / 2);
+        const int I = x0 / 2 + ox, J = y0 / 2 + oy;
+        if (I > Nc - 1 || J > Nc - 1) continue;
+        const bool interior = I >= 1 && J >= 1;
+        const int l = (2 * J - ey0) * EX + (2 * I - ex0);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            double v = 0.0;
+            if (interior) {
+                const double* q = sf[r];
+                v = (4.0 * q[l] + 2.0 * (q[l - 1] + q[l + 1] + q[l - EX] + q[l + EX]) +
+                     (q[l - EX - 1] + q[l - EX + 1] + q[l + EX - 1] + q[l + EX + 1])) *
+                    (1.0 / 16.0);
+            }
+            a.f_c[r][(size_t)J * a.pitch_c + I] = v;
+        }
+    }
+}
+
+struct UpArgs {
+    int N;
+    double h;
+    int pitch, pitch_c;
+    const double* u_mid[2];
+    const double* e_c[2];
+    const double* f[2];
+    const double* k2;
+    double* u_out[2];
+};
+
+template <int R, bool HELM, int NU, int TX, int TY>
+__global__ __launch_bounds__(kThreads) void k_mg_up(UpArgs a) {
+    constexpr int H = 2 * NU;
+    constexpr int EX = TX + 2 * H, EY = TY + 2 * H, EN = EX * EY;
+    constexpr int CX = EX / 2 + 1, CY = EY / 2 + 1;
+    __shared__ double su[R][EN];
+    __shared__ double sf[R][EN];
+    __shared__ double sk[HELM ? EN : 1];
+    __shared__ double se[R][CX * CY];
+
+    const int tid = threadIdx.x;
+    const int N = a.N, Nc = N / 2;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int ex0 = x0 - H, ey0 = y0 - H;  // even
+    const int cx0 = ex0 / 2, cy0 = ey0 / 2;
+    const double h2 = a.h * a.h;
+
+    for (int i = tid; i < EN; i += kThreads) {
+        const int ly = i / EX, lx = i - ly * EX;
+        const int gx = ex0 + lx, gy = ey0 + ly;
+        const bool in = gx >= 0 && gx <= N && gy >= 0 && gy <= N;
+        const size_t g = in ? (size_t)gy * a.pitch + gx : 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            su[r][i] = in ? a.u_mid[r][g] : 0.0;
+            sf[r][i] = in ? a.f[r][g] : 0.0;
+        }
+        if (HELM) sk[i] = in ? a.k2[g] : 0.0;
+    }
+    for (int i = tid; i < CX * CY; i += kThreads) {
+        const int cy = i / CX, cx = i - cy * CX;
+        const int I = cx0 + cx, J = cy0 + cy;
+        const bool in = I >= 0 && I <= Nc && J >= 0 && J <= Nc;
+#pragma unroll
+        for (int r = 0; r < R; ++r) se[r][i] = in ? a.e_c[r][(size_t)J * a.pitch_c + I] : 0.0;
+    }
+    __syncthreads();
+
+    for (int i = tid; i < EN; i += kThreads) {  // u += P e on every interior node of the tile
+        const int ly = i / EX, lx = i - ly * EX;
+        const int gx = ex0 + lx, gy = ey0 + ly;
+        if (gx < 1 || gx > N - 1 || gy < 1 || gy > N - 1) continue;
+        const int ci = (gx >> 1) - cx0, cj = (gy >> 1) - cy0;
+        const int c = cj * CX + ci;
+        const bool ox = gx & 1, oy = gy & 1;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double* e = se[r];
+            double v;
+            if (!ox && !oy) v = e[c];
+            else if (ox && !oy) v = 0.5 * (e[c] + e[c + 1]);
+            else if (!ox && oy) v = 0.5 * (e[c] + e[c + CX]);
+            else v = 0.25 * (e[c] + e[c + 1] + e[c + CX] + e[c + CX + 1]);
+            su[r][i] += v;
+        }
+    }
+    __syncthreads();
+
+    for (int s = 0; s < NU; ++s)
+        for (int color = 0; color < 2; ++color) {
+            rb_half_sweep<R, HELM, EX, EY>(su, sf, sk, ex0, ey0, N, h2, color);
+            __syncthreads();
+        }
+
+    for (int i = tid; i < TX * TY; i += kThreads) {
+        const int oy = i / TX, ox = i - oy * TX;
+        const int gx = x0 + ox, gy = y0 + oy;
+        if (gx > N - 1 || gy > N - 1) continue;
+        const int l = (oy + H) * EX + ox + H;
+#pragma unroll
+        for (int r = 0; r < R; ++r) a.u_out[r][(size_t)gy * a.pitch + gx] = su[r][l];
+    }
+}
+
+// ---------------------------------------------------------------- coarse --
+
+struct CoarseArgs {
+    int N;  // <= kCoarseMax
+    double h;
+    int pitch;
+    const double* f[2];
+    const double* u_init[2];  // nullptr: zero initial guess
+    const double* k2;
+    double* u_out[2];
+    int ncycles, nu1, nu2;
+};
+
+constexpr int coarse_nodes() {
+    int t = 0;
+    for (int n = kCoarseMax; n >= 2; n /= 2) t += (n + 1) * (n + 1);
+    return t;
+}
+
+template <bool HELM>
+__device__ void lds_smooth(double* u, const double* f, const double* k2, int n, double h,
+                           int nu) {
+    const double h2 = h * h;
+    const int m = n - 1;  // interior nodes per row
+    const int half = (m + 1) / 2;
+    for (int s = 0; s < nu; ++s)
+        for (int color = 0; color < 2; ++color) {
+            for (int i = threadIdx.x; i < m * half; i += kCoarseThreads) {
+                const int b = 1 + i / half;
+                const int k = i - (b - 1) * half;
+                const int a = 1 + ((1 + b + color) & 1) + 2 * k;
+                if (a > n - 1) continue;
+                const int l = b * (n + 1) + a;
+                const double nb = u[l - 1] + u[l + 1] + u[l - n - 1] + u[l + n + 1];
+                u[l] = HELM ? (nb - h2 * f[l]) / (4.0 + h2 * k2[l]) : (nb - h2 * f[l]) * 0.25;
+            }
+            __syncthreads();
+        }
+}
+
+template <bool HELM>
+__device__ __forceinline__ double lds_resid(const double* u, const double* f, const double* k2,
+                                            int n, double ih2, int l) {
+    double au = (u[l - 1] + u[l + 1] + u[l - n - 1] + u[l + n + 1] - 4.0 * u[l]) * ih2;
+    if (HELM) au -= k2[l] * u[l];
+    return f[l] - au;
+}
+
+template <bool HELM>
+__global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs a) {
+    constexpr int TOT = coarse_nodes();
+    __shared__ double su[TOT];
+    __shared__ double sf[TOT];
+    __shared__ double sk[HELM ? TOT : 1];
+    const int r = blockIdx.x;
+    const int tid = threadIdx.x;
+
+    int Ns[8], off[8], nl = 0, tot = 0;
+    for (int n = a.N; n >= 2; n /= 2) {
+        Ns[nl] = n;
+        off[nl] = tot;
+        tot += (n + 1) * (n + 1);
+        ++nl;
+    }
+    const int N = a.N;
+    for (int i = tid; i < (N + 1) * (N + 1); i += kCoarseThreads) {
+        const int y = i / (N + 1), x = i - y * (N + 1);
+        const bool bnd = x == 0 || y == 0 || x == N || y == N;
+        const size_t g = (size_t)y * a.pitch + x;
+        su[i] = (!bnd && a.u_init[r]) ? a.u_init[r][g] : 0.0;
+        sf[i] = bnd ? 0.0 : a.f[r][g];
+        if (HELM) sk[i] = bnd ? 0.0 : a.k2[g];
+    }
+    __syncthreads();
+    if (HELM) {  // coarse k2 by full weighting of the finer level
+        for (int l = 1; l < nl; ++l) {
+            const int n = Ns[l], nf = Ns[l - 1];
+            const double* kf = sk + off[l - 1];
+            double* kc = sk + off[l];
+            for (int i = tid; i < (n + 1) * (n + 1); i += kCoarseThreads) {
+                const int J = i / (n + 1), I = i - J * (n + 1);
+                double v = 0.0;
+                if (I >= 1 && J >= 1 && I <= n - 1 && J <= n - 1) {
+                    const int c = (2 * J) * (nf + 1) + 2 * I, w = nf + 1;
+                    v = (4.0 * kf[c] + 2.0 * (kf[c - 1] + kf[c + 1] + kf[c - w] + kf[c + w]) +
+                         (kf[c - w - 1] + kf[c - w + 1] + kf[c + w - 1] + kf[c + w + 1])) *
+                        (1.0 / 16.0);
+                }
+                kc[i] = v;
+            }
+            __syncthreads();
+        }
+    }
+
+    for (int cyc = 0; cyc < a.ncycles; ++cyc) {
+        for (int l = 0; l < nl - 1; ++l) {
+            const int n = Ns[l], nc = Ns[l + 1];
+            const double hl = a.h * (double)(1 << l);
+            double* u = su + off[l];
+            double* f = sf + off[l];
+            double* k2 = sk + (HELM ? off[l] : 0);
+            lds_smooth<HELM>(u, f, k2, n, hl, a.nu1);
+            const double ih2 = 1.0 / (hl * hl);
+            double* uc = su + off[l + 1];
+            double* fc = sf + off[l + 1];
+            for (int i = tid; i < (nc + 1) * (nc + 1); i += kCoarseThreads) {
+                const int J = i / (nc + 1), I = i - J * (nc + 1);
+                double v = 0.0;
+                if (I >= 1 && J >= 1 && I <= nc - 1 && J <= nc - 1) {
+                    const int c = (2 * J) * (n + 1) + 2 * I, w = n + 1;
+                    v = (4.0 * lds_resid<HELM>(u, f, k2, n, ih2, c) +
+                         2.0 * (lds_resid<HELM>(u, f, k2, n, ih2, c - 1) +
+                                lds_resid<HELM>(u, f, k2, n, ih2, c + 1) +
+                                lds_resid<HELM>(u, f, k2, n, ih2, c - w) +
+                                lds_resid<HELM>(u, f, k2, n, ih2, c + w)) +
+                         (lds_resid<HELM>(u, f, k2, n, ih2, c - w - 1) +
+                          lds_resid<HELM>(u, f, k2, n, ih2, c - w + 1) +
+                          lds_resid<HELM>(u, f, k2, n, ih2, c + w - 1) +
+                          lds_resid<HELM>(u, f, k2, n, ih2, c + w + 1))) *
+                        (1.0 / 16.0);
+                }
+                fc[i] = v;
+                uc[i] = 0.0;
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {  // 2x2 cells: one unknown, four zero neighbours
+            const int l = nl - 1;
+            const double hl = a.h * (double)(1 << l);
+            const int c = 1 * 3 + 1;
+            const double k2c = HELM ? sk[off[l] + c] : 0.0;
+            su[off[l] + c] = -sf[off[l] + c] / (4.0 / (hl * hl) + k2c);
+        }
+        __syncthreads();
+        for (int l = nl - 2; l >= 0; --l) {
+            const int n = Ns[l], nc = Ns[l + 1];
+            double* u = su + off[l];
+            const double* e = su + off[l + 1];
+            for (int i = tid; i < (n + 1) * (n + 1); i += kCoarseThreads) {
+                const int y = i / (n + 1), x = i - y * (n + 1);
+                if (x < 1 || y < 1 || x > n - 1 || y > n - 1) continue;
+                const int c = (y >> 1) * (nc + 1) + (x >> 1);
+                const bool ox = x & 1, oy = y & 1;
+                double v;
+                if (!ox && !oy) v = e[c];
+                else if (ox && !oy) v = 0.5 * (e[c] + e[c + 1]);
+                else if (!ox && oy) v = 0.5 * (e[c] + e[c + nc + 1]);
+                else v = 0.25 * (e[c] + e[c + 1] + e[c + nc + 1] + e[c + nc + 2]);
+                u[i] += v;
+            }
+            __syncthreads();
+            lds_smooth<HELM>(u, sf + off[l], sk + (HELM ? off[l] : 0), n, a.h * (double)(1 << l),
+                             a.nu2);
+        }
+    }
+    for (int i = tid; i < (N + 1) * (N + 1); i += kCoarseThreads) {
+        const int y = i / (N + 1), x = i - y * (N + 1);
+        a.u_out[r][(size_t)y * a.pitch + x] = su[i];
+    }
+}
+
+// Residual norms of the current iterate over the same tiles as the down pass.
+template <int R, bool HELM>
+__global__ __launch_bounds__(kThreads) void k_resnorm(int N, double h, int pitch,
+                                                      const double* u0, const double* u1,
+                                                      const double* f0, const double* f1,
+                                                      const double* k2, double* part, int nblk) {
+    __shared__ double red[(kThreads / 64) * 2 * R];
+    const double ih2 = 1.0 / (h * h);
+    const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
+    const double* u[2] = {u0, u1};
+    const double* f[2] = {f0, f1};
+    double acc[2 * R];
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) acc[k] = 0.0;
+    for (int i = threadIdx.x; i < kTile * kTile; i += kThreads) {
+        const int oy = i / kTile, ox = i - oy * kTile;
+        const int gx = x0 + ox, gy = y0 + oy;
+        if (gx < 1 || gx > N - 1 || gy < 1 || gy > N - 1) continue;
+        const size_t g = (size_t)gy * pitch + gx;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double* q = u[r];
+            double au = (q[g - 1] + q[g + 1] + q[g - pitch] + q[g + pitch] - 4.0 * q[g]) * ih2;
+            if (HELM) au -= k2[g] * q[g];
+            const double rr = f[r][g] - au;
+            acc[2 * r] += rr * rr;
+            acc[2 * r + 1] += f[r][g] * f[r][g];
+        }
+    }
+    block_sum<2 * R, kThreads>(acc, red);
+    if (threadIdx.x == 0) {
+        const int b = blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll
+        for (int k = 0; k < 2 * R; ++k) part[k * nblk + b] = acc[k];
+    }
+}
+
+// out[s*4 + k] = sum_b part[s][k][b]: one block per (slot, k), fixed order.
+__global__ __launch_bounds__(kThreads) void k_reduce_slots(const double* part, int stride,
+                                                           int nblk, int s0, int nvec,
+                                                           double* out) {
+    __shared__ double red[kThreads / 64];
+    const int s = s0 + blockIdx.x / nvec, k = blockIdx.x % nvec;
+    const double* p = part + (size_t)s * stride + (size_t)k * nblk;
+    double acc[1] = {0.0};
+    for (int b = threadIdx.x; b < nblk; b += kThreads) acc[0] += p[b];
+    block_sum<1, kThreads>(acc, red);
+    if (threadIdx.x == 0) out[s * 4 + k] = acc[0];
+}
+
+// Full weighting of a fine node array onto the interior coarse nodes (boundary 0).
+__global__ void k_restrict_fw(const double* fine, int pf, double* coarse, int pc, int Nc) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = blockIdx.y;
+    if (I > Nc) return;
+    double v = 0.0;
+    if (I >= 1 && J >= 1 && I <= Nc - 1 && J <= Nc - 1) {
+        const size_t c = (size_t)(2 * J) * pf + 2 * I;
+        v = (4.0 * fine[c] + 2.0 * (fine[c - 1] + fine[c + 1] + fine[c - pf] + fine[c + pf]) +
+             (fine[c - pf - 1] + fine[c - pf + 1] + fine[c + pf - 1] + fine[c + pf + 1])) *
+            (1.0 / 16.0);
+    }
+    coarse[(size_t)J * pc + I] = v;
+}
+
+// ------------------------------------------------------------- dispatch --
+
+template <int R, bool HELM>
+void launch_down(const DownArgs& a, int nu, dim3 grid, hipStream_t s) {
+    switch (nu) {
+        case 1: hipLaunchKernelGGL((k_mg_down<R, HELM, 1, kTile, kTile>), grid, dim3(kThreads), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_mg_down<R, HELM, 2, kTile, kTile>), grid, dim3(kThreads), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_mg_down<R, HELM, 3, kTile, kTile>), grid, dim3(kThreads), 0, s, a); break;
+    }
+}
+
+template <int R, bool HELM>
+void launch_up(const UpArgs& a, int nu, dim3 grid, hipStream_t s) {
+    switch (nu) {
+        case 1: hipLaunchKernelGGL((k_mg_up<R, HELM, 1, kTile, kTile>), grid, dim3(kThreads), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_mg_up<R, HELM, 2, kTile, kTile>), grid, dim3(kThreads), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_mg_up<R, HELM, 3, kTile, kTile>), grid, dim3(kThreads), 0, s, a); break;
+    }
+}
+
+void down(int R, bool helm, const DownArgs& a, int nu, dim3 g, hipStream_t s) {
+    if (R == 1) helm ? launch_down<1, true>(a, nu, g, s) : launch_down<1, false>(a, nu, g, s);
+    else helm ? launch_down<2, true>(a, nu, g, s) : launch_down<2, false>(a, nu, g, s);
+}
+
+void up(int R, bool helm, const UpArgs& a, int nu, dim3 g, hipStream_t s) {
+    if (R == 1) helm ? launch_up<1, true>(a, nu, g, s) : launch_up<1, false>(a, nu, g, s);
+    else helm ? launch_up<2, true>(a, nu, g, s) : launch_up<2, false>(a, nu, g, s);
+}
+
+dim3 tiles(int N) { return dim3((N + kTile - 1) / kTile, (N + kTile - 1) / kTile); }
+
+// Level-0 arrays of the current solve.
+struct Fine {
+    double* u[2];
+    double* f[2];
+    const double* k2;
+};
+
+// One V-cycle.  norm_slot >= 0 records the residual of the incoming iterate.
+void vcycle(wandqs_ctx* c, int R, bool helm, const Fine& fz, int norm_slot) {
+    hipStream_t s = c->stream;
+    const int lc = c->lc;
+    auto lev_u = [&](int l, int r) { return l == 0 ? fz.u[r] : c->lev[l].u[r]; };
+    auto lev_f = [&](int l, int r) { return l == 0 ? fz.f[r] : (double*)c->lev[l].f[r]; };
+    auto lev_k = [&](int l) { return l == 0 ? fz.k2 : (const double*)c->lev[l].k2; };
+    for (int l = 0; l < lc; ++l) {
+        const wq::Level& L = c->lev[l];
+        DownArgs a{};
+        a.N = L.N;
+        a.h = L.h;
+        a.pitch = L.pitch;
+        a.pitch_c = c->lev[l + 1].pitch;
+        for (int r = 0; r < R; ++r) {
+            a.u_in[r] = l == 0 ? fz.u[r] : nullptr;
+            a.f[r] = lev_f(l, r);
+            a.u_out[r] = L.um[r];
+            a.f_c[r] = c->lev[l + 1].f[r];
+        }
+        a.k2 = helm ? lev_k(l) : nullptr;
+        const dim3 g = tiles(L.N);
+        a.nblk = g.x * g.y;
+        a.norm_part = (l == 0 && norm_slot >= 0)
+                          ? c->norm_part + (size_t)norm_slot * 4 * c->max_tiles
+                          : nullptr;
+        down(R, helm, a, c->cfg.nu_pre, g, s);
+    }
+    {
+        const wq::Level& L = c->lev[lc];
+        CoarseArgs a{};
+        a.N = L.N;
+        a.h = L.h;
+        a.pitch = L.pitch;
+        for (int r = 0; r < R; ++r) {
+            a.f[r] = lev_f(lc, r);
+            a.u_init[r] = lc == 0 ? fz.u[r] : nullptr;
+            a.u_out[r] = lev_u(lc, r);
+        }
+        a.k2 = helm ? lev_k(lc) : nullptr;
+        a.ncycles = 1;
+        a.nu1 = c->cfg.nu_pre;
+        a.nu2 = c->cfg.nu_post;
+        if (helm) hipLaunchKernelGGL(k_mg_coarse<true>, dim3(R), dim3(kCoarseThreads), 0, s, a);
+        else hipLaunchKernelGGL(k_mg_coarse<false>, dim3(R), dim3(kCoarseThreads), 0, s, a);
+    }
+    for (int l = lc - 1; l >= 0; --l) {
+        const wq::Level& L = c->lev[l];
+        UpArgs a{};
+        a.N = L.N;
+        a.h = L.h;
+        a.pitch = L.pitch;
+        a.pitch_c = c->lev[l + 1].pitch;
+        for (int r = 0; r < R; ++r) {
+            a.u_mid[r] = L.um[r];
+            a.e_c[r] = c->lev[l + 1].u[r];
+            a.f[r] = lev_f(l, r);
+            a.u_out[r] = lev_u(l, r);
+        }
+        a.k2 = helm ? lev_k(l) : nullptr;
+        up(R, helm, a, c->cfg.nu_post, tiles(L.N), s);
+    }
+}
+
+void resnorm(wandqs_ctx* c, int R, bool helm, const Fine& fz, int slot) {
+    const wq::Level& L = c->lev[0];
+    const dim3 g = tiles(L.N);
+    double* part = c->norm_part + (size_t)slot * 4 * c->max_tiles;
+    const int nblk = g.x * g.y;
+    const double* u1 = R > 1 ? fz.u[1] : nullptr;
+    const double* f1 = R > 1 ? fz.f[1] : nullptr;
+    if (R == 1) {
+        if (helm) hipLaunchKernelGGL((k_resnorm<1, true>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, fz.u[0], u1, fz.f[0], f1, fz.k2, part, nblk);
+        else hipLaunchKernelGGL((k_resnorm<1, false>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, fz.u[0], u1, fz.f[0], f1, fz.k2, part, nblk);
+    } else {
+        if (helm) hipLaunchKernelGGL((k_resnorm<2, true>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, fz.u[0], u1, fz.f[0], f1, fz.k2, part, nblk);
+        else hipLaunchKernelGGL((k_resnorm<2, false>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, fz.u[0], u1, fz.f[0], f1, fz.k2, part, nblk);
+    }
+}
+
+}  // namespace
+
+// Solve with the context's stop rule.  Tolerance mode (mg_rtol > 0) runs a batch
+// of V-cycles sized by the previous slice's count for this solve, reads the
+// residual norms back once per batch and adds single cycles until every
+// right-hand side meets ||r|| <= rtol ||f|| + atol sqrt(n) or reaches the
+// rounding floor (a cycle that no longer halves ||r|| once ||r|| <= 1e-9 ||f||).
+// Fixed mode runs mg_max_cycles cycles without any host synchronisation.
+wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const u[2],
+                       double* const f[2], const double* k2, SolveResult* res) {
+    hipStream_t s = c->stream;
+    Fine fz{{u[0], R > 1 ? u[1] : nullptr}, {f[0], R > 1 ? f[1] : nullptr}, k2};
+    if (helm) {  // k2 on the tile levels 1..lc (the coarse kernel restricts further itself)
+        for (int l = 1; l <= c->lc; ++l) {
+            const wq::Level& F = c->lev[l - 1];
+            const wq::Level& C = c->lev[l];
+            const double* src = l == 1 ? k2 : F.k2;
+            hipLaunchKernelGGL(k_restrict_fw, dim3((C.N + 1 + 127) / 128, C.N + 1), dim3(128), 0, s,
+                               src, F.pitch, C.k2, C.pitch, C.N);
+        }
+    }
+    const int maxc = c->cfg.mg_max_cycles;
+    if (!(c->cfg.mg_rtol > 0.0)) {
+        for (int k = 0; k < maxc; ++k) vcycle(c, R, helm, fz, -1);
+        WQ_LAUNCH_CHECK();
+        if (res) *res = SolveResult{maxc, {-1.0, -1.0}};
+        return WANDQS_OK;
+    }
+    const int N = c->N;
+    const double atol = c->cfg.mg_atol * std::sqrt((double)(N - 1) * (N - 1));
+    const bool top_is_coarse = c->lc == 0;
+    const dim3 g = tiles(N);
+    const int nblk = g.x * g.y;
+    int done = 0;
+    int pred = c->pred[kind] < 1 ? 1 : c->pred[kind];
+    double* hr = c->h_pin;  // [kMaxSlots][4] + flags
+    if (top_is_coarse) resnorm(c, R, helm, fz, 0);
+    while (true) {
+        int b = done == 0 ? pred : 1;
+        if (done + b > maxc) b = maxc - done;
+        for (int k = 0; k < b; ++k) {
+            const int cyc = done + k;
+            vcycle(c, R, helm, fz, top_is_coarse ? -1 : cyc);
+            if (top_is_coarse) resnorm(c, R, helm, fz, cyc + 1);
+        }
+        if (!top_is_coarse) resnorm(c, R, helm, fz, done + b);
+        const int s0 = done == 0 ? 0 : done + 1;
+        const int ns = done + b + 1 - s0;
+        hipLaunchKernelGGL(k_reduce_slots, dim3(ns * 2 * R), dim3(kThreads), 0, s, c->norm_part,
+                           4 * c->max_tiles, nblk, s0, 2 * R, c->norm_red);
+        WQ_LAUNCH_CHECK();
+        WQ_HIP(hipMemcpyAsync(hr + 4 * s0, c->norm_red + 4 * s0, sizeof(double) * 4 * ns,
+                              hipMemcpyDeviceToHost, s));
+        WQ_HIP(hipMemcpyAsync(hr + 4 * kMaxSlots, c->flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        WQ_HIP(hipStreamSynchronize(s));
+        done += b;
+        int32_t fl;
+        std::memcpy(&fl, hr + 4 * kMaxSlots, sizeof(fl));
+        // first cycle count at which every rhs satisfies the stop rule
+        int need = -1;
+        for (int k = 0; k <= done && need < 0; ++k) {
+            bool all = true;
+            for (int r = 0; r < R; ++r) {
+                const double rr = std::sqrt(hr[4 * k + 2 * r]);
+                const double ff = std::sqrt(hr[4 * k + 2 * r + 1]);
+                bool ok = std::isfinite(rr) && rr <= c->cfg.mg_rtol * ff + atol;
+                if (!ok && k >= 2) {
+                    const double rp = std::sqrt(hr[4 * (k - 1) + 2 * r]);
+                    ok = std::isfinite(rr) && rr > 0.5 * rp && rr <= 1e-9 * ff;
+                }
+                all = all && ok;
+            }
+            if (all) need = k;
+        }
+        if (need >= 0 || done >= maxc || (fl & 1)) {
+            if (res) {
+                res->cycles = done;
+                for (int r = 0; r < R; ++r) {
+                    const double rr = std::sqrt(hr[4 * done + 2 * r]);
+                    const double ff = std::sqrt(hr[4 * done + 2 * r + 1]);
+                    res->rel[r] = ff > 0 ? rr / ff : rr;
+                }
+            }
+            if (fl & 1) {
+                c->err = "1 + psi <= 0 where plasma is present";
+                return WANDQS_E_NONPHYS;
+            }
+            if (need < 0) {
+                c->err = "multigrid did not converge within mg_max_cycles";
+                return WANDQS_E_NOCONV;
+            }
+            c->pred[kind] = need < 1 ? 1 : need;
+            return WANDQS_OK;
+        }
+    }
+}
+
+}  // namespace wq

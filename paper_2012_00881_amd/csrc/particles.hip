@@ -1,0 +1,506 @@
+// Plasma macroparticles: cell sort, deposits (Collect_Source), gather and push
+// (Push_Trajectory), adaptive step (Step_Size_Refinement) -- WAND-PIC Sec. III.A,
+// Sec. III.B and Algorithm 1.
+//
+// Particles are a structure of arrays x, y, px, py (float64) plus a permanent
+// int32 ID.  Every slice starts with a stable-by-ID counting sort by CIC cell:
+// histogram (integer atomics), exclusive scan, scatter, then each cell's
+// particles are ordered by ID, so the storage order -- and every floating-point
+// sum that follows -- is independent of thread timing.  Deposits are
+// atomics-free: a workgroup owns a tile of nodes, one thread per cell of the
+// tile (plus the one-cell rim shared with the neighbouring tiles) sums its
+// particles' corner weights in registers, and each node adds its four cells'
+// corners from LDS in a fixed order.
+#include "wq_common.h"
+
+namespace wq {
+namespace {
+
+constexpr int kPushThreads = 256;
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanBlock = kScanThreads * kScanItems;
+
+// Cloud-in-cell cell and offset, clamped so that x = L falls in the last cell.
+__device__ __forceinline__ void cic(double x, double L, double h, int N, int& c, double& d) {
+    const double t = (x + L) / h;
+    int k = (int)floor(t);
+    k = k < 0 ? 0 : (k > N - 1 ? N - 1 : k);
+    c = k;
+    d = t - k;
+}
+
+// Bilinear interpolation from the four corners of a cell.
+__device__ __forceinline__ double cic_gather(double f00, double f10, double f01, double f11,
+                                             double dx, double dy) {
+    return f00 * (1.0 - dx) * (1.0 - dy) + f10 * dx * (1.0 - dy) + f01 * (1.0 - dx) * dy +
+           f11 * dx * dy;
+}
+
+__global__ void k_cell_key(int64_t P, const double* __restrict__ x, const double* __restrict__ y,
+                           double L, double h, int N, int32_t* __restrict__ key,
+                           int32_t* __restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    int a, b;
+    double d;
+    cic(x[i], L, h, N, a, d);
+    cic(y[i], L, h, N, b, d);
+    const int k = b * N + a;
+    key[i] = k;
+    atomicAdd(&count[k], 1);
+}
+
+// Exclusive scan, phase 1: each block scans kScanBlock items and emits its total.
+__global__ __launch_bounds__(kScanThreads) void k_scan_blocks(const int32_t* __restrict__ in,
+                                                              int n, int32_t* __restrict__ out,
+                                                              int32_t* __restrict__ blk) {
+    __shared__ int32_t tot[kScanThreads];
+    const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+    int32_t v[kScanItems];
+    int32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0;
+        s += v[k];
+    }
+    tot[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {  // inclusive Hillis-Steele over totals
+        int32_t t = threadIdx.x >= off ? tot[threadIdx.x - off] : 0;
+        __syncthreads();
+        tot[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int32_t run = tot[threadIdx.x] - s;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == kScanThreads - 1) blk[blockIdx.x] = tot[kScanThreads - 1];
+}
+
+// Phase 2: one block scans the block totals (serial chunks per thread) and
+// writes the grand total to out[n].
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(int32_t* __restrict__ blk, int nb,
+                                                           int32_t* __restrict__ out, int n) {
+    __shared__ int32_t tot[kScanThreads];
+    const int per = (nb + kScanThreads - 1) / kScanThreads;
+    const int b0 = threadIdx.x * per;
+    int32_t s = 0;
+    for (int k = 0; k < per; ++k)
+        if (b0 + k < nb) s += blk[b0 + k];
+    tot[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        int32_t t = threadIdx.x >= off ? tot[threadIdx.x - off] : 0;
+        __syncthreads();
+        tot[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int32_t run = tot[threadIdx.x] - s;
+    for (int k = 0; k < per; ++k)
+        if (b0 + k < nb) {
+            const int32_t t = blk[b0 + k];
+            blk[b0 + k] = run;
+            run += t;
+        }
+    if (threadIdx.x == kScanThreads - 1) out[n] = tot[kScanThreads - 1];
+}
+
+__global__ void k_scan_add(int32_t* __restrict__ out, int n, const int32_t* __restrict__ blk) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += blk[i / kScanBlock];
+}
+
+// Scatter: count[] is consumed back to zero, ready for the next slice.
+__global__ void k_scatter(int64_t P, const int32_t* __restrict__ key,
+                          const int32_t* __restrict__ start, int32_t* __restrict__ count,
+                          int32_t* __restrict__ perm) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const int k = key[i];
+    const int slot = atomicSub(&count[k], 1) - 1;
+    perm[start[k] + slot] = (int32_t)i;
+}
+
+// Order each cell's particles by permanent ID (insertion sort; cells hold a few).
+__global__ void k_cell_sort(int ncell, const int32_t* __restrict__ start,
+                            int32_t* __restrict__ perm, const int32_t* __restrict__ id) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    const int s = start[c], e = start[c + 1];
+    for (int i = s + 1; i < e; ++i) {
+        const int32_t p = perm[i];
+        const int32_t pid = id[p];
+        int j = i - 1;
+        while (j >= s && id[perm[j]] > pid) {
+            perm[j + 1] = perm[j];
+            --j;
+        }
+        perm[j + 1] = p;
+    }
+}
+
+__global__ void k_permute(int64_t P, const int32_t* __restrict__ perm,
+                          const double* __restrict__ x, const double* __restrict__ y,
+                          const double* __restrict__ px, const double* __restrict__ py,
+                          const int32_t* __restrict__ id, double* __restrict__ x2,
+                          double* __restrict__ y2, double* __restrict__ px2,
+                          double* __restrict__ py2, int32_t* __restrict__ id2) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= P) return;
+    const int s = perm[j];
+    x2[j] = x[s];
+    y2[j] = y[s];
+    px2[j] = px[s];
+    py2[j] = py[s];
+    id2[j] = id[s];
+}
+
+// n* = deposit(1) (Sec. III.B: surface density) and the psi right-hand side
+// n* - n0 (eq. (12)) on the interior nodes.
+template <int TN>
+__global__ __launch_bounds__(256) void k_deposit_n(int N, double L, double h, double wdep,
+                                                   double n0, int pitch,
+                                                   const double* __restrict__ x,
+                                                   const double* __restrict__ y,
+                                                   const int32_t* __restrict__ start,
+                                                   double* __restrict__ nstar,
+                                                   double* __restrict__ fpsi) {
+    constexpr int TC = TN + 1;
+    __shared__ double corner[TC * TC][4];
+    const int a0 = blockIdx.x * TN, b0 = blockIdx.y * TN;
+    for (int c = threadIdx.x; c < TC * TC; c += blockDim.x) {
+        const int cy = c / TC, cx = c - cy * TC;
+        const int ga = a0 - 1 + cx, gb = b0 - 1 + cy;
+        double s00 = 0.0, s10 = 0.0, s01 = 0.0, s11 = 0.0;
+        if (ga >= 0 && ga < N && gb >= 0 && gb < N) {
+            const int cell = gb * N + ga;
+            for (int k = start[cell]; k < start[cell + 1]; ++k) {
+                const double dx = (x[k] + L) / h - ga;
+                const double dy = (y[k] + L) / h - gb;
+                s00 += (1.0 - dx) * (1.0 - dy);
+                s10 += dx * (1.0 - dy);
+                s01 += (1.0 - dx) * dy;
+                s11 += dx * dy;
+            }
+        }
+        corner[c][0] = s00;
+        corner[c][1] = s10;
+        corner[c][2] = s01;
+        corner[c][3] = s11;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < TN * TN; i += blockDim.x) {
+        const int ny = i / TN, nx = i - ny * TN;
+        const int ga = a0 + nx, gb = b0 + ny;
+        if (ga > N || gb > N) continue;
+        // node (ga, gb) is corner 11 of cell (ga-1, gb-1), 01 of (ga, gb-1),
+        // 10 of (ga-1, gb) and 00 of (ga, gb)
+        const double v = (corner[ny * TC + nx][3] + corner[ny * TC + nx + 1][2] +
+                          corner[(ny + 1) * TC + nx][1] + corner[(ny + 1) * TC + nx + 1][0]) *
+                         wdep;
+        const size_t g = (size_t)gb * pitch + ga;
+        nstar[g] = v;
+        const bool interior = ga >= 1 && gb >= 1 && ga <= N - 1 && gb <= N - 1;
+        fpsi[g] = interior ? v - n0 : 0.0;
+    }
+}
+
+// Gather psi to each particle: g_i = 1 + psi_i (> 0 or the NONPHYS flag),
+// V_i = p_i / g_i (eq. (6)); deposit j = n*<V> (eq. (9)) and T = n*<V V>
+// (below eq. (16)).  Output order: jx, jy, Txx, Txy, Tyy.
+template <int TN>
+__global__ __launch_bounds__(256) void k_deposit_jT(int N, double L, double h, double wdep,
+                                                    int pitch, const double* __restrict__ x,
+                                                    const double* __restrict__ y,
+                                                    const double* __restrict__ px,
+                                                    const double* __restrict__ py,
+                                                    const int32_t* __restrict__ start,
+                                                    const double* __restrict__ psi,
+                                                    double* __restrict__ jx,
+                                                    double* __restrict__ jy,
+                                                    double* __restrict__ txx,
+                                                    double* __restrict__ txy,
+                                                    double* __restrict__ tyy,
+                                                    int32_t* __restrict__ flags) {
+    constexpr int TC = TN + 1;
+    constexpr int M = 5;
+    __shared__ double corner[TC * TC][4 * M];
+    const int a0 = blockIdx.x * TN, b0 = blockIdx.y * TN;
+    bool bad = false;
+    for (int c = threadIdx.x; c < TC * TC; c += blockDim.x) {
+        const int cy = c / TC, cx = c - cy * TC;
+        const int ga = a0 - 1 + cx, gb = b0 - 1 + cy;
+        double s[4][M];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int m = 0; m < M; ++m) s[q][m] = 0.0;
+        if (ga >= 0 && ga < N && gb >= 0 && gb < N) {
+            const int cell = gb * N + ga;
+            const size_t g = (size_t)gb * pitch + ga;
+            const double p00 = psi[g], p10 = psi[g + 1], p01 = psi[g + pitch],
+                         p11 = psi[g + pitch + 1];
+            for (int k = start[cell]; k < start[cell + 1]; ++k) {
+                const double dx = (x[k] + L) / h - ga;
+                const double dy = (y[k] + L) / h - gb;
+                const double gi = 1.0 + cic_gather(p00, p10, p01, p11, dx, dy);
+                bad |= !(gi > 0.0);
+                const double vx = px[k] / gi, vy = py[k] / gi;
+                const double q[M] = {vx, vy, vx * vx, vx * vy, vy * vy};
+                const double w[4] = {(1.0 - dx) * (1.0 - dy), dx * (1.0 - dy), (1.0 - dx) * dy,
+                                     dx * dy};
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int m = 0; m < M; ++m) s[r][m] += w[r] * q[m];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int m = 0; m < M; ++m) corner[c][r * M + m] = s[r][m];
+    }
+    if (bad) atomicOr(flags, 1);
+    __syncthreads();
+    double* out[M] = {jx, jy, txx, txy, tyy};
+    for (int i = threadIdx.x; i < TN * TN; i += blockDim.x) {
+        const int ny = i / TN, nx = i - ny * TN;
+        const int ga = a0 + nx, gb = b0 + ny;
+        if (ga > N || gb > N) continue;
+        const size_t g = (size_t)gb * pitch + ga;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const double v = (corner[ny * TC + nx][3 * M + m] + corner[ny * TC + nx + 1][2 * M + m] +
+                              corner[(ny + 1) * TC + nx][1 * M + m] +
+                              corner[(ny + 1) * TC + nx + 1][0 * M + m]) *
+                             wdep;
+            out[m][g] = v;
+        }
+    }
+}
+
+// d psi / dx at node (a, b): central inside, one-sided on the boundary columns.
+__device__ __forceinline__ double grad_x(const double* psi, int pitch, int N, double h, int a,
+                                         int b) {
+    const size_t r = (size_t)b * pitch;
+    if (a == 0) return (psi[r + 1] - psi[r]) / h;
+    if (a == N) return (psi[r + N] - psi[r + N - 1]) / h;
+    return (psi[r + a + 1] - psi[r + a - 1]) / (2.0 * h);
+}
+
+__device__ __forceinline__ double grad_y(const double* psi, int pitch, int N, double h, int a,
+                                         int b) {
+    if (b == 0) return (psi[(size_t)pitch + a] - psi[a]) / h;
+    if (b == N) return (psi[(size_t)N * pitch + a] - psi[(size_t)(N - 1) * pitch + a]) / h;
+    return (psi[(size_t)(b + 1) * pitch + a] - psi[(size_t)(b - 1) * pitch + a]) / (2.0 * h);
+}
+
+// Boris-like push over dxi with the fields frozen at this slice (eqs. (6)-(7)):
+// half kick by F = gamma grad psi / g + e_z x B_perp with gamma from the old
+// momentum, rotation by the (e_z x V) Bz term through angle 2 atan(Bz dxi / 2g),
+// half kick, drift with the new momentum, specular walls.  Emits the block
+// maximum of |p_new| / g_i for Algorithm 1.
+__global__ __launch_bounds__(kPushThreads) void k_push(
+    int64_t P, int N, double L, double h, int pitch, const double* __restrict__ st,
+    const double* __restrict__ psi, const double* __restrict__ Bx, const double* __restrict__ By,
+    const double* __restrict__ Bz, double* __restrict__ x, double* __restrict__ y,
+    double* __restrict__ px, double* __restrict__ py, double* __restrict__ vmax_part) {
+    __shared__ double red[kPushThreads / 64];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v = 0.0;
+    if (i < P) {
+        const double dxi = st[1];
+        double xi_ = x[i], yi = y[i], pxi = px[i], pyi = py[i];
+        int a, b;
+        double dx, dy;
+        cic(xi_, L, h, N, a, dx);
+        cic(yi, L, h, N, b, dy);
+        const size_t g = (size_t)b * pitch + a;
+        const double g_i =
+            1.0 + cic_gather(psi[g], psi[g + 1], psi[g + pitch], psi[g + pitch + 1], dx, dy);
+        const double Gx = cic_gather(grad_x(psi, pitch, N, h, a, b), grad_x(psi, pitch, N, h, a + 1, b),
+                                     grad_x(psi, pitch, N, h, a, b + 1),
+                                     grad_x(psi, pitch, N, h, a + 1, b + 1), dx, dy);
+        const double Gy = cic_gather(grad_y(psi, pitch, N, h, a, b), grad_y(psi, pitch, N, h, a + 1, b),
+                                     grad_y(psi, pitch, N, h, a, b + 1),
+                                     grad_y(psi, pitch, N, h, a + 1, b + 1), dx, dy);
+        const double bx = cic_gather(Bx[g], Bx[g + 1], Bx[g + pitch], Bx[g + pitch + 1], dx, dy);
+        const double by = cic_gather(By[g], By[g + 1], By[g + pitch], By[g + pitch + 1], dx, dy);
+        const double bz = cic_gather(Bz[g], Bz[g + 1], Bz[g + pitch], Bz[g + pitch + 1], dx, dy);
+
+        const double gamma = (1.0 + pxi * pxi + pyi * pyi + g_i * g_i) / (2.0 * g_i);
+        const double Fx = gamma * Gx / g_i - by;
+        const double Fy = gamma * Gy / g_i + bx;
+        const double mx = pxi + 0.5 * dxi * Fx;
+        const double my = pyi + 0.5 * dxi * Fy;
+        const double t = bz * dxi / (2.0 * g_i);
+        const double s = 2.0 * t / (1.0 + t * t);
+        const double qx = mx - t * my;
+        const double qy = my + t * mx;
+        const double rx = mx - s * qy;
+        const double ry = my + s * qx;
+        pxi = rx + 0.5 * dxi * Fx;
+        pyi = ry + 0.5 * dxi * Fy;
+        xi_ = xi_ + dxi * pxi / g_i;
+        yi = yi + dxi * pyi / g_i;
+        if (xi_ > L) { xi_ = 2.0 * L - xi_; pxi = -pxi; }
+        if (xi_ < -L) { xi_ = -2.0 * L - xi_; pxi = -pxi; }
+        if (yi > L) { yi = 2.0 * L - yi; pyi = -pyi; }
+        if (yi < -L) { yi = -2.0 * L - yi; pyi = -pyi; }
+        x[i] = xi_;
+        y[i] = yi;
+        px[i] = pxi;
+        py[i] = pyi;
+        v = sqrt(pxi * pxi + pyi * pyi) / g_i;
+    }
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < kPushThreads / 64; ++w) m = fmax(m, red[w]);
+        vmax_part[blockIdx.x] = m;
+    }
+}
+
+// Step_Size_Refinement (Algorithm 1) with the floor dxi0/k (Sec. V.A); writes
+// the slice record (xi, dxi, vmax, flags) and advances xi.  One block.
+__global__ __launch_bounds__(256) void k_dxi(int nparts, const double* __restrict__ vmax_part,
+                                             double* __restrict__ st, double dxi0, double h,
+                                             int adaptive, int refine_k,
+                                             const int32_t* __restrict__ flags,
+                                             double* __restrict__ rec) {
+    __shared__ double red[4];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += 256) v = fmax(v, vmax_part[b]);
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double vmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    double d = dxi0;
+    if (adaptive) {
+        const double V0 = h / dxi0;
+        if (vmax > V0) d = dxi0 * V0 / vmax;
+        if (refine_k > 0 && d < dxi0 / refine_k) d = dxi0 / refine_k;
+    }
+    if (rec) {
+        rec[0] = st[0];
+        rec[1] = st[1];
+        rec[2] = vmax;
+        rec[3] = (double)flags[0];
+    }
+    st[0] = st[0] + st[1];
+    st[1] = d;
+}
+
+__global__ void k_to_id_order(int64_t P, const int32_t* __restrict__ id,
+                              const double* __restrict__ x, const double* __restrict__ y,
+                              const double* __restrict__ px, const double* __restrict__ py,
+                              double* __restrict__ out) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= P) return;
+    const int64_t k = id[j];
+    out[k] = x[j];
+    out[P + k] = y[j];
+    out[2 * P + k] = px[j];
+    out[3 * P + k] = py[j];
+}
+
+__global__ void k_from_id_order(int64_t P, const double* __restrict__ in, double* __restrict__ x,
+                                double* __restrict__ y, double* __restrict__ px,
+                                double* __restrict__ py, int32_t* __restrict__ id) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P) return;
+    x[k] = in[k];
+    y[k] = in[P + k];
+    px[k] = in[2 * P + k];
+    py[k] = in[3 * P + k];
+    id[k] = (int32_t)k;
+}
+
+unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+wandqs_status slice_sort(wandqs_ctx* c) {
+    hipStream_t s = c->stream;
+    const int a = c->cur, b = 1 - c->cur;
+    const int ncell = c->N * c->N;
+    hipLaunchKernelGGL(k_cell_key, dim3(blocks_for(c->P, 256)), dim3(256), 0, s, c->P,
+                       c->pa[a][0], c->pa[a][1], c->L, c->h, c->N, c->key, c->cell_count);
+    const int nb = (ncell + kScanBlock - 1) / kScanBlock;
+    hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(kScanThreads), 0, s, c->cell_count, ncell,
+                       c->cell_start, c->scan_blk);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, c->scan_blk, nb,
+                       c->cell_start, ncell);
+    hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(ncell, 256)), dim3(256), 0, s, c->cell_start,
+                       ncell, c->scan_blk);
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(c->P, 256)), dim3(256), 0, s, c->P, c->key,
+                       c->cell_start, c->cell_count, c->perm);
+    hipLaunchKernelGGL(k_cell_sort, dim3(blocks_for(ncell, 256)), dim3(256), 0, s, ncell,
+                       c->cell_start, c->perm, c->pid[a]);
+    hipLaunchKernelGGL(k_permute, dim3(blocks_for(c->P, 256)), dim3(256), 0, s, c->P, c->perm,
+                       c->pa[a][0], c->pa[a][1], c->pa[a][2], c->pa[a][3], c->pid[a], c->pa[b][0],
+                       c->pa[b][1], c->pa[b][2], c->pa[b][3], c->pid[b]);
+    WQ_LAUNCH_CHECK();
+    c->cur = b;
+    return WANDQS_OK;
+}
+
+wandqs_status deposit_n(wandqs_ctx* c) {
+    const int nt = (c->N + 1 + kDepTile - 1) / kDepTile;
+    const double wdep = c->cfg.n0 / c->ppc;
+    hipLaunchKernelGGL((k_deposit_n<kDepTile>), dim3(nt, nt), dim3(256), 0, c->stream, c->N, c->L,
+                       c->h, wdep, c->cfg.n0, c->lev[0].pitch, c->pa[c->cur][0], c->pa[c->cur][1],
+                       c->cell_start, c->mom[0], c->lev[0].f[0]);
+    WQ_LAUNCH_CHECK();
+    return WANDQS_OK;
+}
+
+wandqs_status deposit_jT(wandqs_ctx* c) {
+    const int nt = (c->N + 1 + kDepTile - 1) / kDepTile;
+    const double wdep = c->cfg.n0 / c->ppc;
+    const int k = c->cur;
+    hipLaunchKernelGGL((k_deposit_jT<kDepTile>), dim3(nt, nt), dim3(256), 0, c->stream, c->N, c->L,
+                       c->h, wdep, c->lev[0].pitch, c->pa[k][0], c->pa[k][1], c->pa[k][2],
+                       c->pa[k][3], c->cell_start, c->fields[0], c->mom[1], c->mom[2], c->mom[3],
+                       c->mom[4], c->mom[5], c->flags);
+    WQ_LAUNCH_CHECK();
+    return WANDQS_OK;
+}
+
+wandqs_status push_and_step(wandqs_ctx* c, int rec_slot) {
+    const int k = c->cur;
+    hipLaunchKernelGGL(k_push, dim3(c->n_push_blocks), dim3(kPushThreads), 0, c->stream, c->P,
+                       c->N, c->L, c->h, c->lev[0].pitch, c->st, c->fields[0], c->fields[3],
+                       c->fields[4], c->fields[2], c->pa[k][0], c->pa[k][1], c->pa[k][2],
+                       c->pa[k][3], c->vmax_part);
+    double* rec = rec_slot >= 0 ? c->rec + 4 * (size_t)rec_slot : nullptr;
+    hipLaunchKernelGGL(k_dxi, dim3(1), dim3(256), 0, c->stream, c->n_push_blocks, c->vmax_part,
+                       c->st, c->cfg.dxi0, c->h, c->cfg.adaptive, c->cfg.refine_k, c->flags, rec);
+    WQ_LAUNCH_CHECK();
+    return WANDQS_OK;
+}
+
+wandqs_status particles_to_id_order(wandqs_ctx* c, double* dst) {
+    const int k = c->cur;
+    hipLaunchKernelGGL(k_to_id_order, dim3(blocks_for(c->P, 256)), dim3(256), 0, c->stream, c->P,
+                       c->pid[k], c->pa[k][0], c->pa[k][1], c->pa[k][2], c->pa[k][3], dst);
+    WQ_LAUNCH_CHECK();
+    return WANDQS_OK;
+}
+
+wandqs_status particles_from_id_order(wandqs_ctx* c, const double* src) {
+    const int k = c->cur;
+    hipLaunchKernelGGL(k_from_id_order, dim3(blocks_for(c->P, 256)), dim3(256), 0, c->stream, c->P,
+                       src, c->pa[k][0], c->pa[k][1], c->pa[k][2], c->pa[k][3], c->pid[k]);
+    WQ_LAUNCH_CHECK();
+    return WANDQS_OK;
+}
+
+}  // namespace wq

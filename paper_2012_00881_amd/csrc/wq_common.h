@@ -1,0 +1,141 @@
+// Internal declarations of the wandqs library (gfx950).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "wandqs.h"
+
+namespace wq {
+
+constexpr int kMaxBeams = 8;
+constexpr int kMaxProbes = 16;
+constexpr int kMaxLevels = 13;
+constexpr int kCoarseMax = 64;  // levels with N <= 64 are solved inside one workgroup
+constexpr int kMaxSlots = 208;  // residual-norm records per solve (mg_max_cycles + batches)
+constexpr int kTile = 32;       // multigrid tile edge (fine nodes owned by one workgroup)
+constexpr int kDepTile = 16;    // deposit tile edge (nodes owned by one workgroup)
+
+// Driver beams as a by-value kernel argument.
+struct BeamSet {
+    int n;
+    int kind[kMaxBeams];
+    double amp[kMaxBeams], sr[kMaxBeams], sz[kMaxBeams], xc[kMaxBeams], x0[kMaxBeams],
+        y0[kMaxBeams], rmax[kMaxBeams];
+    int nbins[kMaxBeams];
+    const double* bins[kMaxBeams];
+};
+
+// One multigrid level.  Node arrays are row-major with a padded row pitch.
+struct Level {
+    int N = 0;
+    double h = 0;
+    int pitch = 0;
+    double* u[2] = {nullptr, nullptr};   // solution (level 0) or coarse correction
+    double* um[2] = {nullptr, nullptr};  // pre-smoothed iterate written by the down pass
+    double* f[2] = {nullptr, nullptr};   // right-hand side
+    double* k2 = nullptr;                // Helmholtz coefficient (restricted)
+};
+
+enum SolveKind { kSolvePsi = 0, kSolveEB = 1, kSolveBperp = 2 };
+
+struct SolveResult {
+    int cycles = -1;
+    double rel[2] = {-1.0, -1.0};
+};
+
+}  // namespace wq
+
+struct wandqs_ctx {
+    // configuration (deep copy)
+    wandqs_config cfg{};
+    std::vector<wandqs_beam> beams;
+    std::vector<std::vector<double>> bin_amp;
+    std::vector<wandqs_probe> probes;
+
+    int N = 0, ppc = 0, nlev = 0, lc = 0;
+    double L = 0, h = 0;
+    int64_t P = 0;
+    int rec_cap = 0;
+    int n_bins_total = 0;  // radial-bin amplitudes over all beams
+    hipStream_t stream = nullptr;
+
+    // device memory carved from the caller's workspace
+    wq::Level lev[wq::kMaxLevels];
+    double* fields[5] = {};
+    double* mom[6] = {};
+    double* jz = nullptr;
+    double* pa[2][4] = {};
+    int32_t* pid[2] = {};
+    int cur = 0;
+    int32_t *key = nullptr, *perm = nullptr, *cell_count = nullptr, *cell_start = nullptr,
+            *scan_blk = nullptr;
+    int n_scan_blocks = 0;
+    double* st = nullptr;         // [xi, dxi]
+    double* vmax_part = nullptr;  // per push block
+    int n_push_blocks = 0;
+    int32_t* flags = nullptr;
+    double* norm_part = nullptr;  // [kMaxSlots][4][max_tiles]
+    double* norm_red = nullptr;   // [kMaxSlots][4]
+    int max_tiles = 0;
+    double* rec = nullptr;        // [rec_cap][4] : xi, dxi, vmax, flags
+    double* probe_acc = nullptr;  // [kMaxProbes]
+    double* bins_dev = nullptr;
+    wq::BeamSet beamset{};
+
+    // host side
+    double* h_pin = nullptr;  // pinned readback buffer
+    int pred[4] = {1, 1, 1, 1};  // V-cycles of the last solve per kind (batch size)
+    bool failed = false;
+    std::string err;
+    wq::SolveResult last[3];
+};
+
+namespace wq {
+
+// layout of the workspace (offsets from the base, computed for any base)
+size_t carve(wandqs_ctx* c, char* base);
+
+// multigrid (mg.hip)
+wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const u[2],
+                       double* const f[2], const double* k2, SolveResult* res);
+
+// particles and fields (particles.hip, fields.hip)
+wandqs_status slice_sort(wandqs_ctx* c);
+wandqs_status deposit_n(wandqs_ctx* c);
+wandqs_status deposit_jT(wandqs_ctx* c);
+wandqs_status rhs_EB(wandqs_ctx* c);
+wandqs_status assemble(wandqs_ctx* c);
+wandqs_status push_and_step(wandqs_ctx* c, int rec_slot);
+wandqs_status probes_accumulate(wandqs_ctx* c, int64_t slice);
+wandqs_status pack_fields(wandqs_ctx* c, double* const* src, int n, double* dst);
+wandqs_status unpack_fields(wandqs_ctx* c, const double* src, int n, double* const* dst);
+wandqs_status particles_to_id_order(wandqs_ctx* c, double* dst);
+wandqs_status particles_from_id_order(wandqs_ctx* c, const double* src);
+wandqs_status fill_f64(wandqs_ctx* c, double* p, size_t n, double v);
+
+const char* hip_err(hipError_t e);
+
+}  // namespace wq
+
+#define WQ_HIP(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            c->err = std::string(#call) + ": " + hipGetErrorString(e_);               \
+            return WANDQS_E_HIP;                                                      \
+        }                                                                             \
+    } while (0)
+
+#define WQ_LAUNCH_CHECK()                                                             \
+    do {                                                                              \
+        hipError_t e_ = hipGetLastError();                                            \
+        if (e_ != hipSuccess) {                                                       \
+            c->err = std::string("kernel launch: ") + hipGetErrorString(e_);          \
+            return WANDQS_E_HIP;                                                      \
+        }                                                                             \
+    } while (0)

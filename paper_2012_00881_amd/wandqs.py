@@ -1,0 +1,258 @@
+"""ctypes binding of libwandqs.so (C ABI declared in include/wandqs.h).
+
+Argument marshalling only: every step of the slice runs in the HIP library.
+PyTorch provides the device workspace, the input/output buffers and the HIP
+stream.  There is no fallback: if the library is missing or no GPU is visible,
+the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwandqs.so")
+
+OK, E_INVALID, E_NOMEM, E_HIP, E_NOCONV, E_NONPHYS, E_STATE = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_HIP", -4: "E_NOCONV",
+                -5: "E_NONPHYS", -6: "E_STATE"}
+FP64, MIXED = 0, 1
+BEAM_GAUSS, BEAM_RADIAL_BINS = 0, 1
+
+_dp = C.POINTER(C.c_double)
+
+#: every symbol the header declares
+EXPORTS = ("wandqs_workspace_bytes", "wandqs_init", "wandqs_slice_step", "wandqs_run",
+           "wandqs_get_state", "wandqs_set_state", "wandqs_mg_solve", "wandqs_get_moments",
+           "wandqs_num_particles", "wandqs_destroy", "wandqs_last_error")
+
+
+class Beam(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("amp", C.c_double), ("sigma_r", C.c_double),
+                ("sigma_z", C.c_double), ("xi_c", C.c_double), ("x0", C.c_double),
+                ("y0", C.c_double), ("n_bins", C.c_int32), ("r_max", C.c_double),
+                ("bin_amp", _dp)]
+
+
+class Probe(C.Structure):
+    _fields_ = [("field", C.c_int32), ("slice_begin", C.c_int32), ("slice_end", C.c_int32),
+                ("r_max", C.c_double), ("x0", C.c_double), ("y0", C.c_double)]
+
+
+class Config(C.Structure):
+    _fields_ = [("n_cells", C.c_int32), ("half_width", C.c_double), ("ppc_side", C.c_int32),
+                ("jitter", C.c_double), ("seed", C.c_uint64), ("n0", C.c_double),
+                ("dxi0", C.c_double), ("adaptive", C.c_int32), ("refine_k", C.c_int32),
+                ("precision", C.c_int32), ("mg_rtol", C.c_double), ("mg_atol", C.c_double),
+                ("mg_max_cycles", C.c_int32), ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
+                ("n_beams", C.c_int32), ("beams", C.POINTER(Beam)), ("n_probes", C.c_int32),
+                ("probes", C.POINTER(Probe)), ("checkpoint_every", C.c_int32)]
+
+
+class SliceInfo(C.Structure):
+    _fields_ = [("xi", C.c_double), ("dxi", C.c_double), ("vmax", C.c_double),
+                ("vcycles", C.c_int32 * 5), ("rel_resid", C.c_double * 5), ("flags", C.c_int32)]
+
+    def as_dict(self):
+        return dict(xi=self.xi, dxi=self.dxi, vmax=self.vmax, vcycles=list(self.vcycles),
+                    rel_resid=list(self.rel_resid), flags=self.flags)
+
+
+_lib = None
+
+
+def load():
+    """Load libwandqs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, sz = C.c_void_p, C.c_int32, C.c_size_t
+    L.wandqs_workspace_bytes.argtypes = [C.POINTER(Config), i32, C.POINTER(sz)]
+    L.wandqs_init.argtypes = [C.POINTER(Config), i32, vp, sz, vp, C.POINTER(vp)]
+    L.wandqs_slice_step.argtypes = [vp, vp, C.POINTER(SliceInfo)]
+    L.wandqs_run.argtypes = [vp, i32, vp, C.POINTER(SliceInfo)]
+    L.wandqs_get_state.argtypes = [vp, vp, vp, _dp]
+    L.wandqs_set_state.argtypes = [vp, vp, vp, _dp]
+    L.wandqs_mg_solve.argtypes = [vp, i32, vp, vp, vp, C.POINTER(i32), _dp]
+    L.wandqs_get_moments.argtypes = [vp, vp]
+    L.wandqs_num_particles.argtypes = [vp]
+    L.wandqs_num_particles.restype = C.c_int64
+    L.wandqs_destroy.argtypes = [vp]
+    L.wandqs_destroy.restype = None
+    L.wandqs_last_error.argtypes = [vp]
+    L.wandqs_last_error.restype = C.c_char_p
+    for name in ("wandqs_workspace_bytes", "wandqs_init", "wandqs_slice_step", "wandqs_run",
+                 "wandqs_get_state", "wandqs_set_state", "wandqs_mg_solve",
+                 "wandqs_get_moments"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+class WandQSError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"wandqs {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def make_config(cfg: dict):
+    """C config from a workload dict (see wandqs_inputs.config).  Returns (Config, keep-alive)."""
+    keep = []
+    beams = (Beam * max(1, len(cfg["beams"])))()
+    for k, b in enumerate(cfg["beams"]):
+        bb = beams[k]
+        bb.sigma_z, bb.xi_c = b["sigma_z"], b["xi_c"]
+        bb.x0, bb.y0 = b.get("x0", 0.0), b.get("y0", 0.0)
+        if b["kind"] == "gauss":
+            bb.kind, bb.amp, bb.sigma_r = BEAM_GAUSS, b["amp"], b["sigma_r"]
+        else:
+            amp = np.ascontiguousarray(b["bin_amp"], dtype=np.float64)
+            keep.append(amp)
+            bb.kind, bb.n_bins, bb.r_max = BEAM_RADIAL_BINS, amp.size, b["r_max"]
+            bb.bin_amp = amp.ctypes.data_as(_dp)
+            bb.amp, bb.sigma_r = 1.0, 1.0
+    probes = (Probe * max(1, len(cfg["probes"])))()
+    for k, p in enumerate(cfg["probes"]):
+        probes[k] = Probe(p["field"], p["slice_begin"], p["slice_end"], p["r_max"],
+                          p.get("x0", 0.0), p.get("y0", 0.0))
+    keep += [beams, probes]
+    c = Config()
+    c.n_cells, c.half_width = cfg["n_cells"], cfg["half_width"]
+    c.ppc_side, c.jitter, c.seed = cfg["ppc_side"], cfg["jitter"], int(cfg["seed"])
+    c.n0, c.dxi0 = cfg.get("n0", 1.0), cfg["dxi0"]
+    c.adaptive, c.refine_k = int(cfg["adaptive"]), int(cfg["refine_k"])
+    c.precision = MIXED if cfg.get("precision", "fp64") == "mixed" else FP64
+    c.mg_rtol, c.mg_atol = cfg["mg_rtol"], cfg["mg_atol"]
+    c.mg_max_cycles, c.nu_pre, c.nu_post = cfg["mg_max_cycles"], cfg["nu_pre"], cfg["nu_post"]
+    c.n_beams, c.beams = len(cfg["beams"]), beams
+    c.n_probes, c.probes = len(cfg["probes"]), probes
+    c.checkpoint_every = cfg.get("checkpoint_every", 0)
+    return c, keep
+
+
+def workspace_bytes(cfg: dict, n_slices: int = 1) -> int:
+    L = load()
+    c, keep = make_config(cfg)
+    n = C.c_size_t(0)
+    st = L.wandqs_workspace_bytes(C.byref(c), int(n_slices), C.byref(n))
+    if st != OK:
+        raise WandQSError(st, L.wandqs_last_error(None).decode())
+    return n.value
+
+
+class Simulation:
+    """One context: plasma state, fields and workspace on one GPU."""
+
+    def __init__(self, cfg: dict, n_slices: int = 1, device: str = "cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.L = load()
+        self.cfg = cfg
+        self.N = int(cfg["n_cells"])
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._c, self._keep = make_config(cfg)
+        nbytes = workspace_bytes(cfg, n_slices)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = (self.ws.data_ptr() + 255) & ~255
+        ctx = C.c_void_p()
+        st = self.L.wandqs_init(C.byref(self._c), int(n_slices), C.c_void_p(base), nbytes,
+                                C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        if st != OK:
+            raise WandQSError(st, self.L.wandqs_last_error(None).decode())
+        self.ctx = ctx
+        self.P = int(self.L.wandqs_num_particles(ctx))
+
+    # ------------------------------------------------------------------ util
+    def _check(self, st):
+        if st != OK:
+            raise WandQSError(st, self.L.wandqs_last_error(self.ctx).decode())
+
+    def _nodes(self, k):
+        return self.torch.empty((k, self.N + 1, self.N + 1), dtype=self.torch.float64,
+                                device=self.device)
+
+    # ------------------------------------------------------------------- API
+    def step(self, fields: bool = False, info: bool = False):
+        out = self._nodes(5) if fields else None
+        inf = SliceInfo() if info else None
+        st = self.L.wandqs_slice_step(self.ctx, C.c_void_p(out.data_ptr()) if fields else None,
+                                      C.byref(inf) if info else None)
+        self._check(st)
+        return out, (inf.as_dict() if info else None)
+
+    def run(self, n_slices: int, infos: bool = False, probes: bool = False):
+        arr = (SliceInfo * max(1, n_slices))() if infos else None
+        pr = self.torch.zeros(max(1, len(self.cfg["probes"])), dtype=self.torch.float64,
+                              device=self.device) if probes else None
+        st = self.L.wandqs_run(self.ctx, int(n_slices),
+                               C.c_void_p(pr.data_ptr()) if probes else None, arr)
+        self._check(st)
+        return ([a.as_dict() for a in arr[:n_slices]] if infos else None), pr
+
+    def get_state(self):
+        parts = self.torch.empty((4, self.P), dtype=self.torch.float64, device=self.device)
+        flds = self._nodes(5)
+        xd = (C.c_double * 2)()
+        self._check(self.L.wandqs_get_state(self.ctx, C.c_void_p(parts.data_ptr()),
+                                            C.c_void_p(flds.data_ptr()), xd))
+        return dict(particles=parts, fields=flds, xi=xd[0], dxi=xd[1])
+
+    def set_state(self, particles=None, fields=None, xi=None, dxi=None):
+        t = self.torch
+        p = f = None
+        if particles is not None:
+            p = t.as_tensor(particles, dtype=t.float64).to(self.device).contiguous()
+            assert p.shape == (4, self.P)
+        if fields is not None:
+            f = t.as_tensor(fields, dtype=t.float64).to(self.device).contiguous()
+            assert f.shape == (5, self.N + 1, self.N + 1)
+        xd = None
+        if xi is not None or dxi is not None:
+            cur = self.get_state()
+            xd = (C.c_double * 2)(cur["xi"] if xi is None else xi,
+                                  cur["dxi"] if dxi is None else dxi)
+        self.stream.synchronize()
+        self._check(self.L.wandqs_set_state(self.ctx, C.c_void_p(p.data_ptr()) if p is not None else None,
+                                            C.c_void_p(f.data_ptr()) if f is not None else None, xd))
+
+    def mg_solve(self, f, u0=None, k2=None):
+        """Solve (L_h - k2) u = f for 1 or 2 right-hand sides on this grid."""
+        t = self.torch
+        f = t.as_tensor(f, dtype=t.float64).to(self.device).contiguous()
+        if f.dim() == 2:
+            f = f.unsqueeze(0)
+        nrhs = f.shape[0]
+        u = t.zeros_like(f) if u0 is None else t.as_tensor(u0, dtype=t.float64).to(self.device).reshape(f.shape).contiguous().clone()
+        kk = None if k2 is None else t.as_tensor(k2, dtype=t.float64).to(self.device).contiguous()
+        cyc = C.c_int32(0)
+        rel = (C.c_double * 2)()
+        self.stream.synchronize()
+        st = self.L.wandqs_mg_solve(self.ctx, nrhs, C.c_void_p(kk.data_ptr()) if kk is not None else None,
+                                    C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()),
+                                    C.byref(cyc), rel)
+        if st not in (OK, E_NOCONV):
+            self._check(st)
+        return st, u, cyc.value, list(rel)[:nrhs]
+
+    def moments(self):
+        out = self._nodes(9)
+        self._check(self.L.wandqs_get_moments(self.ctx, C.c_void_p(out.data_ptr())))
+        return out
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.L.wandqs_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
