@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Benchmark of the quasi-static xi-slice step on one MI355X.
+
+A step is one xi-slice of the whole hot path: cell sort, deposit of n*, the psi
+Poisson solve, deposit of j and T, the Ez/Bz Poisson solves, the B_perp
+Helmholtz assembly and solve, gather and push, adaptive step.  The workload is
+the scale case: 1024^2 cells over [-10, 10]^2, 4 particles per cell
+(4,194,304), Gaussian driver 20 n0 (sigma_r 0.25, sigma_z 0.6) plus a witness,
+adaptive dxi (dxi0 = 0.005, refinement k = 8), FP64, multigrid solved to the
+rounding floor.  Inputs are synthetic (the cold plasma lattice of the input
+module) and resident on the GPU before the timed region.
+
+Timed region: K slices of one job started at xi = 0 (default K = 4096, the
+whole job), after W warm-up slices on a separate context.  Printed value:
+particle-slice updates per second (P * K / wall time).  A second pass over the
+same K slices records every kernel launch with HIP events for the roofline of
+the dominant kernel.  The CPU oracle is timed on a bounded sample of the same
+job (its first slices) for the cpu_baseline record.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+WORKLOAD = ("C5 scale run: 1024x1024 cells over [-10,10]^2, 4 particles/cell (4194304), "
+            "driver n_b=20 sigma_r=0.25 sigma_z=0.6 at xi=2 + witness n_b=2 sigma_r=0.2 "
+            "sigma_z=0.3 at xi=6.5, adaptive dxi0=0.005 k=8, FP64, MG to rounding floor")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2012_00881_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".cpp", ".h")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when the counters were taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(cfg: dict, n_slices: int):
+    import oracle
+    orc = oracle.Oracle(cfg)
+    st = oracle.initial_state(cfg)
+    t0 = time.perf_counter()
+    r = orc.run(st, n_slices)
+    dt = time.perf_counter() - t0
+    P = st["x"].size
+    return dict(value=P * n_slices / dt, unit="particle-slice updates/s", cores=1, kind="oracle",
+                sample=f"first {n_slices} slices of the same job from xi=0 "
+                       f"(single-threaded FP64 oracle, {dt:.1f} s, status {r['status']})")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4096)
+    ap.add_argument("--warmup", type=int, default=64)
+    ap.add_argument("--workload", default="C5")
+    ap.add_argument("--cpu-slices", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile-pass", action="store_true")
+    ap.add_argument("--breakdown", default=None, help="write per-kernel stats (JSON) here")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the slice step is not sharded "
+              "across GPUs); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import wandqs_inputs as wi
+    from paper_2012_00881_amd import Simulation
+
+    cfg = wi.scaled(wi.config(args.workload), precision="fp64")
+    K, W = args.steps, args.warmup
+
+    print(f"[bench] warm-up: {W} slices", file=sys.stderr, flush=True)
+    sim = Simulation(cfg, n_slices=max(W, 1))
+    if W:
+        sim.run(W)
+    torch.cuda.synchronize()
+    sim.close()
+    del sim
+
+    print(f"[bench] timed: {K} slices", file=sys.stderr, flush=True)
+    sim = Simulation(cfg, n_slices=max(K, 1))
+    P = sim.P
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos, _ = sim.run(K, infos=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    final = sim.get_state()
+    sim.close()
+    del sim
+    value = P * K / dt
+    cyc = [sum(i["vcycles"][k] for i in infos) / max(1, len(infos)) for k in range(5)]
+    print(f"[bench] {K} slices in {dt:.3f} s: {value:.4e} particle-slice/s, xi_end={final['xi']:.4f}, "
+          f"mean V-cycles per solve {['%.2f' % c for c in cyc]}", file=sys.stderr, flush=True)
+
+    roof = None
+    stats = []
+    if not args.no_profile_pass:
+        print("[bench] profiled pass (HIP events per launch)", file=sys.stderr, flush=True)
+        sim = Simulation(cfg, n_slices=max(K, 1))
+        sim.profile(True)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        sim.run(K)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - tp
+        per_level = sorted(sim.kernel_stats(), key=lambda s: -s["total_ms"])
+        sim.close()
+        del sim
+        # group the per-level records by kernel (the unit a profiler reports)
+        groups = {}
+        for s in per_level:
+            g = groups.setdefault(s["name"].split("@")[0], dict(name=s["name"].split("@")[0],
+                                                                 launches=0, total_ms=0.0,
+                                                                 alg_bytes=0.0))
+            g["launches"] += s["launches"]
+            g["total_ms"] += s["total_ms"]
+            g["alg_bytes"] += s["alg_bytes"]
+        stats = sorted(groups.values(), key=lambda s: -s["total_ms"])
+        tot = sum(s["total_ms"] for s in stats)
+        for s in stats[:12]:
+            avg = s["total_ms"] / s["launches"]
+            print(f"[bench]   {s['name']:34s} {s['launches']:7d} launches {s['total_ms']:9.2f} ms "
+                  f"({100 * s['total_ms'] / tot:5.1f}%) avg {1e3 * avg:8.2f} us "
+                  f"{s['alg_bytes'] / (s['total_ms'] * 1e-3) / 1e9:8.1f} GB/s",
+                  file=sys.stderr, flush=True)
+        for s in per_level:
+            if "@" in s["name"] and s["total_ms"] > 0.02 * tot:
+                print(f"[bench]     level {s['name']:38s} avg {1e3 * s['total_ms'] / s['launches']:8.2f} us "
+                      f"{s['alg_bytes'] / (s['total_ms'] * 1e-3) / 1e9:8.1f} GB/s", file=sys.stderr,
+                      flush=True)
+        dom = stats[0]
+        avg_s = dom["total_ms"] * 1e-3 / dom["launches"]
+        bytes_per_launch = dom["alg_bytes"] / dom["launches"]
+        achieved = bytes_per_launch / avg_s / 1e9
+        traffic = measured_traffic(dom["name"])
+        roof = {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "alg_bytes_per_launch": round(bytes_per_launch),
+                "avg_launch_us": round(avg_s * 1e6, 2), "launches": dom["launches"],
+                "share_of_kernel_time": round(dom["total_ms"] / tot, 4),
+                "profiled_pass_s": round(tp, 3)}
+        if args.breakdown:
+            with open(args.breakdown, "w") as fh:
+                json.dump(dict(workload=args.workload, slices=K, particles=P, stats=stats,
+                               per_level=per_level, source_hash=kernel_source_hash()), fh,
+                          indent=1)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print(f"[bench] CPU oracle on {args.cpu_slices} slices", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(cfg, args.cpu_slices)
+
+    line = {"metric": "particle-slice updates/s", "value": value,
+            "unit": "particle-slice updates/s", "n_gpus": 1, "steps": K, "warmup": W,
+            "ms_per_step": 1e3 * dt / K, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": WORKLOAD if args.workload == "C5" else args.workload,
+                       "grid": cfg["n_cells"], "particles": P, "slices": K,
+                       "precision": "fp64", "xi_end": final["xi"],
+                       "mean_vcycles": [round(c, 3) for c in cyc]},
+            "roofline": roof, "cpu_baseline": cpu}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -90,9 +90,11 @@ typedef struct {
     int32_t adaptive;    /* 1: Step_Size_Refinement, 0: fixed dxi0 */
     int32_t refine_k;    /* floor dxi >= dxi0 / k; 0 = no floor */
     int32_t precision;   /* wandqs_precision */
-    double mg_rtol;      /* stop when ||r|| <= rtol ||f|| + atol sqrt(n) or at the rounding
-                            floor; rtol <= 0: exactly mg_max_cycles V-cycles, no host syncs */
-    double mg_atol;
+    double mg_rtol;      /* stop when ||r|| <= rtol ||f|| + atol sqrt(n) (n interior nodes) or
+                            at the rounding floor: a cycle that no longer halves ||r|| once
+                            ||r|| <= 1e-9 max(||f||, ||r_0||); rtol <= 0: exactly
+                            mg_max_cycles V-cycles, no host syncs */
+    double mg_atol;      /* >= 0; 0 recommended (an absolute floor loosens small fields) */
     int32_t mg_max_cycles; /* 1 .. 200 */
     int32_t nu_pre, nu_post; /* red-black Gauss-Seidel sweeps per V-cycle, each 1 .. 3 */
     int32_t n_beams;       /* 0 .. 8 */
@@ -161,6 +163,27 @@ wandqs_status wandqs_mg_solve(wandqs_ctx* ctx, int32_t nrhs, const double* d_k2,
 /* Diagnostic copy of the node arrays of the last slice (device [9][N+1][N+1]):
  * n*, jx, jy, Txx, Txy, Tyy, k2 = n* / (1+psi), f_Bx, f_By. */
 wandqs_status wandqs_get_moments(wandqs_ctx* ctx, double* d_out);
+
+/* Kernel timing for benchmarks and roofline reports.  While enabled, every
+ * kernel launch of the context is bracketed by a pair of HIP events on the
+ * context's stream; launches are grouped by kernel instantiation (multigrid
+ * tile kernels also by grid level, as "name@N").  alg_bytes
+ * is the algorithmic DRAM traffic of those launches (each array element the
+ * kernel must read or write, counted once). */
+typedef struct {
+    char name[56];
+    int64_t launches;
+    double total_ms;
+    double alg_bytes;
+} wandqs_kernel_stat;
+
+/* enable != 0 starts (and resets) the per-kernel timing; 0 stops it. */
+wandqs_status wandqs_profile(wandqs_ctx* ctx, int32_t enable);
+
+/* Copies up to max records (host array) and sets *h_n to the number of
+ * kernel groups; synchronises the stream. */
+wandqs_status wandqs_profile_stats(wandqs_ctx* ctx, wandqs_kernel_stat* h_out, int32_t max,
+                                   int32_t* h_n);
 
 /* Number of plasma macroparticles P of the context (0 for NULL). */
 int64_t wandqs_num_particles(const wandqs_ctx* ctx);

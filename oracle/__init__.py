@@ -198,7 +198,7 @@ def apply(N, h, u, k2=None):
     return out
 
 
-def mg_solve(N, h, f, u0=None, k2=None, rtol=1e-14, atol=1e-14, max_cycles=50, nu1=2, nu2=2):
+def mg_solve(N, h, f, u0=None, k2=None, rtol=1e-14, atol=0.0, max_cycles=50, nu1=2, nu2=2):
     """Multigrid solve of (L_h - k2) u = f with zero Dirichlet boundary."""
     f = _f64(f)
     u = np.zeros_like(f) if u0 is None else _f64(u0).copy()

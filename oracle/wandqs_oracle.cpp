@@ -242,8 +242,9 @@ void vcycle(std::vector<Level>& lv, size_t l, int nu1, int nu2) {
 /* Solve (L_h - k2) u = f for the interior nodes with u = 0 on the boundary,
  * starting from the guess held in u.  Stops when ||r|| <= rtol ||f|| + atol sqrt(n)
  * (n interior nodes), or at the rounding floor: a cycle after the second that
- * reduces ||r|| by less than 2x while ||r|| <= 1e-9 ||f|| (the guard keeps a
- * slowly converging solve from being taken for a converged one).  Otherwise
+ * reduces ||r|| by less than 2x while ||r|| <= 1e-9 max(||f||, ||r_0||) (the guard
+ * keeps a slowly converging solve from being taken for a converged one; r_0 is
+ * the initial residual, which sets the scale when f vanishes).  Otherwise
  * returns ORC_NOCONV after max_cycles. */
 int mg_solve(int N, double h, const double* k2, const double* f, double* u, double rtol,
              double atol, int max_cycles, int nu1, int nu2, int* cycles_out, double* rel_out) {
@@ -274,6 +275,7 @@ int mg_solve(int N, double h, const double* k2, const double* f, double* u, doub
     const double tol = rtol * fnorm + atol * std::sqrt((double)(N - 1) * (N - 1));
     residual(top, r);
     double rn = norm2_interior(top, r), rprev = rn;
+    const double scale = std::max(fnorm, rn);
     int c = 0, status = ORC_NOCONV;
     if (rn <= tol) status = ORC_OK;
     while (status != ORC_OK && c < max_cycles) {
@@ -283,7 +285,7 @@ int mg_solve(int N, double h, const double* k2, const double* f, double* u, doub
         rprev = rn;
         rn = norm2_interior(top, r);
         if (rn <= tol) status = ORC_OK;
-        else if (c >= 2 && rn > 0.5 * rprev && rn <= 1e-9 * fnorm) status = ORC_OK; /* floor */
+        else if (c >= 2 && rn > 0.5 * rprev && rn <= 1e-9 * scale) status = ORC_OK; /* floor */
     }
     std::copy(top.u.begin(), top.u.end(), u);
     if (cycles_out) *cycles_out = c;

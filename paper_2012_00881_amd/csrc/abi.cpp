@@ -466,6 +466,7 @@ int64_t wandqs_num_particles(const wandqs_ctx* c) { return c ? c->P : 0; }
 
 void wandqs_destroy(wandqs_ctx* c) {
     if (!c) return;
+    wq::prof_reset(c, false);
     if (c->h_pin) (void)hipHostFree(c->h_pin);
     delete c;
 }

@@ -163,20 +163,29 @@ dim3 node_grid(int N) { return dim3((N + 1 + 127) / 128, N + 1); }
 
 wandqs_status rhs_EB(wandqs_ctx* c) {
     const Level& L0 = c->lev[0];
-    hipLaunchKernelGGL(k_rhs_EB, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->h, L0.pitch,
-                       c->mom[1], c->mom[2], L0.f[0], L0.f[1]);
+    {
+        ProfScope ps(c, "k_rhs_EB", (double)(c->N + 1) * (c->N + 1) * 32.0);
+        hipLaunchKernelGGL(k_rhs_EB, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->h, L0.pitch,
+                           c->mom[1], c->mom[2], L0.f[0], L0.f[1]);
+    }
     WQ_LAUNCH_CHECK();
     return WANDQS_OK;
 }
 
 wandqs_status assemble(wandqs_ctx* c) {
     const Level& L0 = c->lev[0];
-    hipLaunchKernelGGL(k_jz, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->L, c->h, L0.pitch,
-                       c->mom[0], c->mom[3], c->mom[5], c->fields[0], c->st, c->beamset, c->jz,
-                       c->flags);
-    hipLaunchKernelGGL(k_assemble, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->h, L0.pitch,
-                       c->mom[0], c->mom[1], c->mom[2], c->mom[3], c->mom[4], c->mom[5],
-                       c->fields[0], c->fields[1], c->fields[2], c->jz, L0.k2, L0.f[0], L0.f[1]);
+    {
+        ProfScope ps(c, "k_jz", (double)(c->N + 1) * (c->N + 1) * 40.0);
+        hipLaunchKernelGGL(k_jz, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->L, c->h, L0.pitch,
+                           c->mom[0], c->mom[3], c->mom[5], c->fields[0], c->st, c->beamset, c->jz,
+                           c->flags);
+    }
+    {
+        ProfScope ps(c, "k_assemble", (double)(c->N + 1) * (c->N + 1) * 104.0);
+        hipLaunchKernelGGL(k_assemble, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->h, L0.pitch,
+                           c->mom[0], c->mom[1], c->mom[2], c->mom[3], c->mom[4], c->mom[5],
+                           c->fields[0], c->fields[1], c->fields[2], c->jz, L0.k2, L0.f[0], L0.f[1]);
+    }
     WQ_LAUNCH_CHECK();
     return WANDQS_OK;
 }
@@ -186,9 +195,12 @@ wandqs_status probes_accumulate(wandqs_ctx* c, int64_t slice) {
         const wandqs_probe& p = c->probes[k];
         if (slice < p.slice_begin || slice >= p.slice_end) continue;
         const double scale = 1.0 / (double)(p.slice_end - p.slice_begin);
-        hipLaunchKernelGGL(k_probe, dim3(1), dim3(256), 0, c->stream, c->N, c->L, c->h,
-                           c->lev[0].pitch, c->fields[p.field], p.x0, p.y0, p.r_max, scale,
-                           c->probe_acc + k);
+        {
+            ProfScope ps(c, "k_probe", (double)(c->N + 1) * (c->N + 1) * 8.0);
+            hipLaunchKernelGGL(k_probe, dim3(1), dim3(256), 0, c->stream, c->N, c->L, c->h,
+                               c->lev[0].pitch, c->fields[p.field], p.x0, p.y0, p.r_max, scale,
+                               c->probe_acc + k);
+        }
     }
     WQ_LAUNCH_CHECK();
     return WANDQS_OK;
@@ -197,8 +209,11 @@ wandqs_status probes_accumulate(wandqs_ctx* c, int64_t slice) {
 wandqs_status pack_fields(wandqs_ctx* c, double* const* src, int n, double* dst) {
     const size_t nn = (size_t)(c->N + 1) * (c->N + 1);
     for (int k = 0; k < n; ++k)
-        hipLaunchKernelGGL(k_pack, node_grid(c->N), dim3(128), 0, c->stream, c->N,
-                           c->lev[0].pitch, src[k], dst + k * nn);
+        {
+            ProfScope ps(c, "k_pack", (double)(c->N + 1) * (c->N + 1) * 16.0);
+            hipLaunchKernelGGL(k_pack, node_grid(c->N), dim3(128), 0, c->stream, c->N,
+                               c->lev[0].pitch, src[k], dst + k * nn);
+        }
     WQ_LAUNCH_CHECK();
     return WANDQS_OK;
 }
@@ -206,15 +221,21 @@ wandqs_status pack_fields(wandqs_ctx* c, double* const* src, int n, double* dst)
 wandqs_status unpack_fields(wandqs_ctx* c, const double* src, int n, double* const* dst) {
     const size_t nn = (size_t)(c->N + 1) * (c->N + 1);
     for (int k = 0; k < n; ++k)
-        hipLaunchKernelGGL(k_unpack, node_grid(c->N), dim3(128), 0, c->stream, c->N,
-                           c->lev[0].pitch, src + k * nn, dst[k]);
+        {
+            ProfScope ps(c, "k_unpack", (double)(c->N + 1) * (c->N + 1) * 16.0);
+            hipLaunchKernelGGL(k_unpack, node_grid(c->N), dim3(128), 0, c->stream, c->N,
+                               c->lev[0].pitch, src + k * nn, dst[k]);
+        }
     WQ_LAUNCH_CHECK();
     return WANDQS_OK;
 }
 
 wandqs_status fill_f64(wandqs_ctx* c, double* p, size_t n, double v) {
     if (n == 0) return WANDQS_OK;
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, p, n, v);
+    {
+        ProfScope ps(c, "k_fill", 8.0 * n);
+        hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, p, n, v);
+    }
     WQ_LAUNCH_CHECK();
     return WANDQS_OK;
 }

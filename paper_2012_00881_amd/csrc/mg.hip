@@ -16,7 +16,9 @@
 // Two right-hand sides with one operator (Ez, Bz and Bx, By) share each pass.
 // All reductions (residual norms) have a fixed order: results are bitwise
 // reproducible.
+#include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 
 #include "wq_common.h"
@@ -577,6 +579,13 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Fine& fz, int norm_slot) {
         a.norm_part = (l == 0 && norm_slot >= 0)
                           ? c->norm_part + (size_t)norm_slot * 4 * c->max_tiles
                           : nullptr;
+        // algorithmic bytes per owned node: u (level 0 only), f, k2, smoothed u, coarse f
+        const double nodes = (double)L.N * L.N;
+        char nm[56];
+        std::snprintf(nm, sizeof nm, "k_mg_down<%d, %s, %d, 32, 32>@%d", R,
+                      helm ? "true" : "false", c->cfg.nu_pre, L.N);
+        ProfScope ps(c, nm, nodes * ((l == 0 ? 8.0 * R : 0.0) + 8.0 * R + (helm ? 8.0 : 0.0) +
+                                     8.0 * R + 2.0 * R));
         down(R, helm, a, c->cfg.nu_pre, g, s);
     }
     {
@@ -594,6 +603,9 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Fine& fz, int norm_slot) {
         a.ncycles = 1;
         a.nu1 = c->cfg.nu_pre;
         a.nu2 = c->cfg.nu_post;
+        const double nodes = (double)(L.N + 1) * (L.N + 1);
+        ProfScope ps(c, helm ? "k_mg_coarse<true>" : "k_mg_coarse<false>",
+                     nodes * (8.0 * R + (lc == 0 ? 8.0 * R : 0.0) + (helm ? 8.0 : 0.0) + 8.0 * R));
         if (helm) hipLaunchKernelGGL(k_mg_coarse<true>, dim3(R), dim3(kCoarseThreads), 0, s, a);
         else hipLaunchKernelGGL(k_mg_coarse<false>, dim3(R), dim3(kCoarseThreads), 0, s, a);
     }
@@ -611,6 +623,12 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Fine& fz, int norm_slot) {
             a.u_out[r] = lev_u(l, r);
         }
         a.k2 = helm ? lev_k(l) : nullptr;
+        // per owned node: smoothed u, coarse correction (1/4), f, k2, corrected u
+        const double nodes = (double)L.N * L.N;
+        char nm[56];
+        std::snprintf(nm, sizeof nm, "k_mg_up<%d, %s, %d, 32, 32>@%d", R,
+                      helm ? "true" : "false", c->cfg.nu_post, L.N);
+        ProfScope ps(c, nm, nodes * (8.0 * R + 2.0 * R + 8.0 * R + (helm ? 8.0 : 0.0) + 8.0 * R));
         up(R, helm, a, c->cfg.nu_post, tiles(L.N), s);
     }
 }
@@ -622,6 +640,9 @@ void resnorm(wandqs_ctx* c, int R, bool helm, const Fine& fz, int slot) {
     const int nblk = g.x * g.y;
     const double* u1 = R > 1 ? fz.u[1] : nullptr;
     const double* f1 = R > 1 ? fz.f[1] : nullptr;
+    char nm[56];
+    std::snprintf(nm, sizeof nm, "k_resnorm<%d, %s>", R, helm ? "true" : "false");
+    ProfScope ps(c, nm, (double)L.N * L.N * (16.0 * R + (helm ? 8.0 : 0.0)));
     if (R == 1) {
         if (helm) hipLaunchKernelGGL((k_resnorm<1, true>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, fz.u[0], u1, fz.f[0], f1, fz.k2, part, nblk);
         else hipLaunchKernelGGL((k_resnorm<1, false>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, fz.u[0], u1, fz.f[0], f1, fz.k2, part, nblk);
@@ -637,7 +658,8 @@ void resnorm(wandqs_ctx* c, int R, bool helm, const Fine& fz, int slot) {
 // of V-cycles sized by the previous slice's count for this solve, reads the
 // residual norms back once per batch and adds single cycles until every
 // right-hand side meets ||r|| <= rtol ||f|| + atol sqrt(n) or reaches the
-// rounding floor (a cycle that no longer halves ||r|| once ||r|| <= 1e-9 ||f||).
+// rounding floor (a cycle that no longer halves ||r|| once
+// ||r|| <= 1e-9 max(||f||, ||r_0||), r_0 the initial residual).
 // Fixed mode runs mg_max_cycles cycles without any host synchronisation.
 wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const u[2],
                        double* const f[2], const double* k2, SolveResult* res) {
@@ -648,6 +670,7 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
             const wq::Level& F = c->lev[l - 1];
             const wq::Level& C = c->lev[l];
             const double* src = l == 1 ? k2 : F.k2;
+            ProfScope ps(c, "k_restrict_fw", 8.0 * ((double)(F.N + 1) * (F.N + 1) + (double)(C.N + 1) * (C.N + 1)));
             hipLaunchKernelGGL(k_restrict_fw, dim3((C.N + 1 + 127) / 128, C.N + 1), dim3(128), 0, s,
                                src, F.pitch, C.k2, C.pitch, C.N);
         }
@@ -679,8 +702,11 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
         if (!top_is_coarse) resnorm(c, R, helm, fz, done + b);
         const int s0 = done == 0 ? 0 : done + 1;
         const int ns = done + b + 1 - s0;
-        hipLaunchKernelGGL(k_reduce_slots, dim3(ns * 2 * R), dim3(kThreads), 0, s, c->norm_part,
-                           4 * c->max_tiles, nblk, s0, 2 * R, c->norm_red);
+        {
+            ProfScope ps(c, "k_reduce_slots", 8.0 * ns * 2 * R * (nblk + 1));
+            hipLaunchKernelGGL(k_reduce_slots, dim3(ns * 2 * R), dim3(kThreads), 0, s,
+                               c->norm_part, 4 * c->max_tiles, nblk, s0, 2 * R, c->norm_red);
+        }
         WQ_LAUNCH_CHECK();
         WQ_HIP(hipMemcpyAsync(hr + 4 * s0, c->norm_red + 4 * s0, sizeof(double) * 4 * ns,
                               hipMemcpyDeviceToHost, s));
@@ -699,7 +725,8 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
                 bool ok = std::isfinite(rr) && rr <= c->cfg.mg_rtol * ff + atol;
                 if (!ok && k >= 2) {
                     const double rp = std::sqrt(hr[4 * (k - 1) + 2 * r]);
-                    ok = std::isfinite(rr) && rr > 0.5 * rp && rr <= 1e-9 * ff;
+                    const double scale = std::max(ff, std::sqrt(hr[2 * r]));
+                    ok = std::isfinite(rr) && rr > 0.5 * rp && rr <= 1e-9 * scale;
                 }
                 all = all && ok;
             }

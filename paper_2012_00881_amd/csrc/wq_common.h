@@ -48,6 +48,22 @@ struct SolveResult {
     double rel[2] = {-1.0, -1.0};
 };
 
+// Optional per-kernel timing with HIP events (see wandqs_profile).
+struct ProfPending {
+    int cls;
+    hipEvent_t a, b;
+    double bytes;
+};
+
+struct Prof {
+    bool on = false;
+    std::vector<std::string> names;
+    std::vector<int64_t> launches;
+    std::vector<double> ms, bytes;
+    std::vector<hipEvent_t> free_ev, all_ev;
+    std::vector<ProfPending> pending;
+};
+
 }  // namespace wq
 
 struct wandqs_ctx {
@@ -93,6 +109,7 @@ struct wandqs_ctx {
     bool failed = false;
     std::string err;
     wq::SolveResult last[3];
+    wq::Prof prof;
 };
 
 namespace wq {
@@ -119,6 +136,21 @@ wandqs_status particles_from_id_order(wandqs_ctx* c, const double* src);
 wandqs_status fill_f64(wandqs_ctx* c, double* p, size_t n, double v);
 
 const char* hip_err(hipError_t e);
+
+// Brackets one kernel launch with timing events when profiling is on.
+class ProfScope {
+  public:
+    ProfScope(wandqs_ctx* c, const char* name, double bytes);
+    ~ProfScope();
+
+  private:
+    wandqs_ctx* c_;
+    int cls_ = -1;
+    hipEvent_t a_ = nullptr;
+    double bytes_ = 0;
+};
+void prof_harvest(wandqs_ctx* c);
+void prof_reset(wandqs_ctx* c, bool on);
 
 }  // namespace wq
 

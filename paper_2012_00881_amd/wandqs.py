@@ -26,7 +26,8 @@ _dp = C.POINTER(C.c_double)
 #: every symbol the header declares
 EXPORTS = ("wandqs_workspace_bytes", "wandqs_init", "wandqs_slice_step", "wandqs_run",
            "wandqs_get_state", "wandqs_set_state", "wandqs_mg_solve", "wandqs_get_moments",
-           "wandqs_num_particles", "wandqs_destroy", "wandqs_last_error")
+           "wandqs_num_particles", "wandqs_destroy", "wandqs_last_error", "wandqs_profile",
+           "wandqs_profile_stats")
 
 
 class Beam(C.Structure):
@@ -49,6 +50,11 @@ class Config(C.Structure):
                 ("mg_max_cycles", C.c_int32), ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
                 ("n_beams", C.c_int32), ("beams", C.POINTER(Beam)), ("n_probes", C.c_int32),
                 ("probes", C.POINTER(Probe)), ("checkpoint_every", C.c_int32)]
+
+
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 56), ("launches", C.c_int64), ("total_ms", C.c_double),
+                ("alg_bytes", C.c_double)]
 
 
 class SliceInfo(C.Structure):
@@ -83,13 +89,15 @@ def load():
     L.wandqs_get_moments.argtypes = [vp, vp]
     L.wandqs_num_particles.argtypes = [vp]
     L.wandqs_num_particles.restype = C.c_int64
+    L.wandqs_profile.argtypes = [vp, i32]
+    L.wandqs_profile_stats.argtypes = [vp, C.POINTER(KernelStat), i32, C.POINTER(i32)]
     L.wandqs_destroy.argtypes = [vp]
     L.wandqs_destroy.restype = None
     L.wandqs_last_error.argtypes = [vp]
     L.wandqs_last_error.restype = C.c_char_p
     for name in ("wandqs_workspace_bytes", "wandqs_init", "wandqs_slice_step", "wandqs_run",
                  "wandqs_get_state", "wandqs_set_state", "wandqs_mg_solve",
-                 "wandqs_get_moments"):
+                 "wandqs_get_moments", "wandqs_profile", "wandqs_profile_stats"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -245,6 +253,19 @@ class Simulation:
         out = self._nodes(9)
         self._check(self.L.wandqs_get_moments(self.ctx, C.c_void_p(out.data_ptr())))
         return out
+
+    def profile(self, enable: bool = True):
+        """Start (and reset) or stop per-kernel HIP-event timing."""
+        self._check(self.L.wandqs_profile(self.ctx, 1 if enable else 0))
+
+    def kernel_stats(self):
+        """Per kernel instantiation: launches, total ms, algorithmic bytes."""
+        n = C.c_int32(0)
+        self._check(self.L.wandqs_profile_stats(self.ctx, None, 0, C.byref(n)))
+        arr = (KernelStat * max(1, n.value))()
+        self._check(self.L.wandqs_profile_stats(self.ctx, arr, n.value, C.byref(n)))
+        return [dict(name=a.name.decode(), launches=a.launches, total_ms=a.total_ms,
+                     alg_bytes=a.alg_bytes) for a in arr[:n.value]]
 
     def close(self):
         if getattr(self, "ctx", None):

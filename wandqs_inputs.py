@@ -89,7 +89,7 @@ def radial_bins_beam(bin_amp, r_max, sigma_z, xi_c, x0=0.0, y0=0.0):
 def _base(**kw):
     cfg = dict(n_cells=64, half_width=6.0, ppc_side=1, jitter=0.0, seed=0, n0=1.0,
                dxi0=0.0625, adaptive=0, refine_k=0, precision="fp64",
-               mg_rtol=1e-14, mg_atol=1e-14, mg_max_cycles=50, nu_pre=2, nu_post=2,
+               mg_rtol=1e-14, mg_atol=0.0, mg_max_cycles=50, nu_pre=2, nu_post=2,
                beams=[], probes=[], checkpoint_every=0, n_slices=128)
     cfg.update(kw)
     return cfg
