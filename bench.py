@@ -83,6 +83,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile-pass", action="store_true")
     ap.add_argument("--breakdown", default=None, help="write per-kernel stats (JSON) here")
+    ap.add_argument("--nu", type=int, default=None, help="pre- and post-smoothing sweeps")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the slice step is not sharded "
@@ -94,6 +95,8 @@ def main():
     from paper_2012_00881_amd import Simulation
 
     cfg = wi.scaled(wi.config(args.workload), precision="fp64")
+    if args.nu is not None:
+        cfg.update(nu_pre=args.nu, nu_post=args.nu)
     K, W = args.steps, args.warmup
 
     print(f"[bench] warm-up: {W} slices", file=sys.stderr, flush=True)

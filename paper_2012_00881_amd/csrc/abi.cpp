@@ -112,6 +112,9 @@ wandqs_status do_slice(wandqs_ctx* c, int rec_slot, int64_t probe_slice) {
     using namespace wq;
     wandqs_status s;
     Level& L0 = c->lev[0];
+    // initial guesses: linear extrapolation of the last two slices' fields once
+    // two are known, else the previous slice's fields (Sec. VII.A)
+    if ((s = extrapolate_guess(c, c->n_guess >= 2)) != WANDQS_OK) return s;
     if ((s = slice_sort(c)) != WANDQS_OK) return s;
     if ((s = deposit_n(c)) != WANDQS_OK) return s;  // Collect_Source: n*
     double* u1[2] = {c->fields[0], nullptr};
@@ -126,7 +129,9 @@ wandqs_status do_slice(wandqs_ctx* c, int rec_slot, int64_t probe_slice) {
     double* u3[2] = {c->fields[3], c->fields[4]};
     if ((s = mg_solve(c, kSolveBperp, 2, true, u3, f2, L0.k2, &c->last[2])) != WANDQS_OK) return s;
     if (!c->probes.empty() && (s = probes_accumulate(c, probe_slice)) != WANDQS_OK) return s;
-    return push_and_step(c, rec_slot);  // Push_Trajectory + Step_Size_Refinement
+    if ((s = push_and_step(c, rec_slot)) != WANDQS_OK) return s;  // Push_Trajectory + Step_Size_Refinement
+    if (c->n_guess < 2) ++c->n_guess;
+    return WANDQS_OK;
 }
 
 void fill_info_host(const wandqs_ctx* c, wandqs_slice_info* info) {
@@ -164,6 +169,7 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
     };
     Level& L0 = c->lev[0];
     for (int k = 0; k < 5; ++k) c->fields[k] = arr(0);
+    for (int k = 0; k < 5; ++k) c->fields_prev[k] = arr(0);
     for (int r = 0; r < 2; ++r) {
         L0.um[r] = arr(0);
         L0.f[r] = arr(0);
@@ -171,6 +177,11 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
     L0.k2 = arr(0);
     for (int k = 0; k < 6; ++k) c->mom[k] = arr(0);
     c->jz = arr(0);
+    {
+        int tot = 0;
+        for (int n = c->lev[c->lc].N; n >= 2; n /= 2) tot += (n + 1) * (n + 1);
+        c->k2lev = (double*)take(sizeof(double) * (size_t)tot);
+    }
     for (int l = 1; l <= c->lc; ++l) {
         Level& L = c->lev[l];
         for (int r = 0; r < 2; ++r) {
@@ -191,7 +202,7 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
     c->cell_count = (int32_t*)take(sizeof(int32_t) * ncell);
     c->cell_start = (int32_t*)take(sizeof(int32_t) * (ncell + 1));
     c->scan_blk = (int32_t*)take(sizeof(int32_t) * c->n_scan_blocks);
-    c->st = (double*)take(sizeof(double) * 2);
+    c->st = (double*)take(sizeof(double) * 4);
     c->vmax_part = (double*)take(sizeof(double) * c->n_push_blocks);
     c->flags = (int32_t*)take(sizeof(int32_t) * 4);
     c->norm_part = (double*)take(sizeof(double) * kMaxSlots * 4 * (size_t)c->max_tiles);
@@ -312,7 +323,7 @@ wandqs_status wandqs_init(const wandqs_config* cfg, int32_t n_slices, void* d_wo
                     host[c->P + i] = -L + h * (((double)b + ((double)sy + 0.5) / s) + J * (2.0 * uy - 1.0));
                     ids[i] = (int32_t)i;
                 }
-    const double st0[2] = {0.0, cfg->dxi0};
+    const double st0[4] = {0.0, cfg->dxi0, 0.0, 0.0};
     bool ok = hipMemcpyAsync(c->pa[0][0], host.data(), sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
               hipMemcpyAsync(c->pa[0][1], host.data() + c->P, sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
               hipMemcpyAsync(c->pid[0], ids.data(), sizeof(int32_t) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
@@ -429,6 +440,7 @@ wandqs_status wandqs_set_state(wandqs_ctx* c, const double* d_particles, const d
     WQ_HIP(hipMemsetAsync(c->flags, 0, sizeof(int32_t), c->stream));
     WQ_HIP(hipStreamSynchronize(c->stream));
     c->failed = false;
+    c->n_guess = 0;
     return WANDQS_OK;
 }
 
@@ -443,6 +455,7 @@ wandqs_status wandqs_mg_solve(wandqs_ctx* c, int32_t nrhs, const double* d_k2, c
     wq::SolveResult res;
     double* u[2] = {c->fields[0], nrhs > 1 ? c->fields[1] : nullptr};
     double* f[2] = {L0.f[0], nrhs > 1 ? L0.f[1] : nullptr};
+    c->n_guess = 0;  // the stored fields no longer belong to the slice sequence
     s = wq::mg_solve(c, 3, nrhs, d_k2 != nullptr, u, f, d_k2 ? L0.k2 : nullptr, &res);
     if (s != WANDQS_OK && s != WANDQS_E_NOCONV) return fail(c, s);
     wandqs_status s2 = wq::pack_fields(c, c->fields, nrhs, d_u);

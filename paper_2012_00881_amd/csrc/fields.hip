@@ -152,6 +152,31 @@ __global__ void k_unpack(int N, int pitch, const double* __restrict__ src, doubl
     dst[(size_t)b * pitch + a] = bnd ? 0.0 : src[(size_t)b * (N + 1) + a];
 }
 
+// Initial guesses for the five solves of this slice.  prev <- u (fields of the
+// last slice) and, when extrapolating, u <- u + t (u - prev_old) with
+// t = (xi - xi_u) / (xi_u - xi_prev) from the device state.
+struct FieldPtrs {
+    double* u[5];
+    double* p[5];
+};
+
+__global__ void k_extrapolate(int N, int pitch, const double* __restrict__ st, FieldPtrs f,
+                              int extrapolate) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (a > N) return;
+    const size_t g = (size_t)b * pitch + a;
+    const double den = st[2] - st[3];
+    const double t = (extrapolate && den != 0.0) ? (st[0] - st[2]) / den : 0.0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const double u = f.u[k][g];
+        const double q = f.p[k][g];
+        f.p[k][g] = u;
+        f.u[k][g] = extrapolate ? u + t * (u - q) : u;
+    }
+}
+
 __global__ void k_fill(double* p, size_t n, double v) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -226,6 +251,19 @@ wandqs_status unpack_fields(wandqs_ctx* c, const double* src, int n, double* con
             hipLaunchKernelGGL(k_unpack, node_grid(c->N), dim3(128), 0, c->stream, c->N,
                                c->lev[0].pitch, src + k * nn, dst[k]);
         }
+    WQ_LAUNCH_CHECK();
+    return WANDQS_OK;
+}
+
+wandqs_status extrapolate_guess(wandqs_ctx* c, bool extrapolate) {
+    FieldPtrs f;
+    for (int k = 0; k < 5; ++k) {
+        f.u[k] = c->fields[k];
+        f.p[k] = c->fields_prev[k];
+    }
+    ProfScope ps(c, "k_extrapolate", (double)(c->N + 1) * (c->N + 1) * 5 * 32.0);
+    hipLaunchKernelGGL(k_extrapolate, node_grid(c->N), dim3(128), 0, c->stream, c->N,
+                       c->lev[0].pitch, c->st, f, extrapolate ? 1 : 0);
     WQ_LAUNCH_CHECK();
     return WANDQS_OK;
 }

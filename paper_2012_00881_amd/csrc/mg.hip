@@ -26,8 +26,9 @@
 namespace wq {
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kCoarseThreads = 1024;
+constexpr int kThreads = 256;      // norm and reduction kernels
+constexpr int kTileThreads = 512;  // tile kernels of the levels N > 64
+constexpr int kCoarseThreads = 512;
 
 // Deterministic block sum of NV values; the result is valid in thread 0.
 template <int NV, int NT>
@@ -51,28 +52,82 @@ __device__ void block_sum(double (&v)[NV], double* red) {
     }
 }
 
-// Red-black half sweep over the nodes of one colour inside an LDS tile whose
-// node (0, 0) is global node (ex0, ey0).  Nodes on the tile rim, on the domain
-// boundary or outside the domain are not updated.
+// ------------------------------------------------------------ tile engine --
+//
+// A tile kernel holds an EX x EY block of nodes whose node (0, 0) is global
+// node (ex0, ey0), ex0 even.  The iterate u lives in LDS; each thread owns
+// KP horizontal node pairs (x = 2p, 2p+1 of a row) and keeps their f and the
+// Gauss-Seidel diagonal D = 4 + h^2 k2 (and 1/D) in registers.  In a pair the
+// two nodes have opposite colours, so every thread updates exactly one node of
+// each of its pairs in every half sweep.
+// Value select (not an address select, so register arrays stay in registers).
+__device__ __forceinline__ double pick(int j, double a, double b) { return j ? b : a; }
+
 template <int R, bool HELM, int EX, int EY>
-__device__ __forceinline__ void rb_half_sweep(double (*su)[EX * EY], double (*sf)[EX * EY],
-                                              const double* sk, int ex0, int ey0, int N,
-                                              double h2, int color) {
-    constexpr int HALF = (EX - 1) / 2;
-    for (int i = threadIdx.x; i < (EY - 2) * HALF; i += kThreads) {
-        const int ly = 1 + i / HALF;
-        const int k = i - (ly - 1) * HALF;
-        const int gy = ey0 + ly;
-        const int lx = 1 + ((ex0 + 1 + gy + color) & 1) + 2 * k;
-        if (lx > EX - 2) continue;
-        const int gx = ex0 + lx;
-        if (gx < 1 || gx > N - 1 || gy < 1 || gy > N - 1) continue;
-        const int l = ly * EX + lx;
-        const double d = HELM ? 4.0 + h2 * sk[l] : 4.0;
+struct TileShape {
+    static constexpr int PW = EX / 2;
+    static constexpr int NP = PW * EY;
+    static constexpr int KP = (NP + kTileThreads - 1) / kTileThreads;
+    static constexpr int EN = EX * EY;
+    static_assert(EX % 2 == 0, "tile width must be even");
+};
+
+template <int R, bool HELM, int EX, int EY, int KP>
+__device__ __forceinline__ void tile_load(double (*su)[EX * EY], double (&fr)[R][KP][2],
+                                          double (&Dr)[KP][2], double (&iDr)[KP][2],
+                                          const double* const* u, const double* const* f,
+                                          const double* k2, int pitch, int ex0, int ey0, int N,
+                                          double h2) {
+    constexpr int PW = EX / 2, NP = PW * EY;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const double nb = su[r][l - 1] + su[r][l + 1] + su[r][l - EX] + su[r][l + EX];
-            su[r][l] = HELM ? (nb - h2 * sf[r][l]) / d : (nb - h2 * sf[r][l]) * 0.25;
+    for (int k = 0; k < KP; ++k) {
+        const int p = threadIdx.x + k * kTileThreads;
+        const int ly = p / PW, px = p - ly * PW;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int lx = 2 * px + j;
+            const int gx = ex0 + lx, gy = ey0 + ly;
+            const bool in = p < NP && gx >= 0 && gx <= N && gy >= 0 && gy <= N;
+            const size_t g = in ? (size_t)gy * pitch + gx : 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double uv = (in && u[r]) ? u[r][g] : 0.0;
+                if (p < NP) su[r][ly * EX + lx] = uv;
+                fr[r][k][j] = in ? f[r][g] : 0.0;
+            }
+            const double kk = (HELM && in) ? k2[g] : 0.0;
+            Dr[k][j] = 4.0 + h2 * kk;
+            iDr[k][j] = HELM ? 1.0 / Dr[k][j] : 0.25;
+        }
+    }
+}
+
+// One red-black half sweep: u <- (sum of 4 neighbours - h^2 f) / D on the nodes
+// of colour `color` ((gx + gy) % 2) that have all four neighbours in the tile
+// and lie inside the domain.
+template <int R, bool HELM, int EX, int EY, int KP>
+__device__ __forceinline__ void tile_sweep(double (*su)[EX * EY], const double (&fr)[R][KP][2],
+                                           const double (&iDr)[KP][2], int ex0, int ey0, int N,
+                                           double h2, int color) {
+    constexpr int PW = EX / 2, NP = PW * EY;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        const int p = threadIdx.x + k * kTileThreads;
+        const int ly = p / PW, px = p - ly * PW;
+        const int gy = ey0 + ly;
+        const int j = (gy + color) & 1;  // ex0 is even
+        const int lx = 2 * px + j;
+        const int gx = ex0 + lx;
+        if (p < NP && lx >= 1 && lx <= EX - 2 && ly >= 1 && ly <= EY - 2 && gx >= 1 &&
+            gx <= N - 1 && gy >= 1 && gy <= N - 1) {
+            const int l = ly * EX + lx;
+            const double id = pick(j, iDr[k][0], iDr[k][1]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double fv = pick(j, fr[r][k][0], fr[r][k][1]);
+                const double nb = su[r][l - 1] + su[r][l + 1] + su[r][l - EX] + su[r][l + EX];
+                su[r][l] = (nb - h2 * fv) * id;
+            }
         }
     }
 }
@@ -90,101 +145,116 @@ struct DownArgs {
     int nblk;
 };
 
-template <int R, bool HELM, int NU, int TX, int TY>
-__global__ __launch_bounds__(kThreads) void k_mg_down(DownArgs a) {
-    constexpr int HL = 2 * NU + 2, HH = 2 * NU + 1;
-    constexpr int EX = TX + HL + HH, EY = TY + HL + HH, EN = EX * EY;
+// Down pass of one level: nu1 sweeps on the tile, write the smoothed tile,
+// residual, full-weighting restriction onto the coarse tile.  Halo: 2 nu + 2
+// nodes on the low side (the residual at x0 - 1 needs the smoothed u at x0 - 2),
+// 2 nu + 2 on the high side (one more than needed, to keep the width even).
+template <int R, bool HELM, int NU, int T>
+__global__ __launch_bounds__(kTileThreads) void k_mg_down(DownArgs a) {
+    constexpr int HL = 2 * NU + 2, HH = 2 * NU + 2;
+    constexpr int EX = T + HL + HH, EY = EX;
+    using S = TileShape<R, HELM, EX, EY>;
+    constexpr int PW = S::PW, NP = S::NP, KP = S::KP, EN = S::EN;
     __shared__ double su[R][EN];
-    __shared__ double sf[R][EN];
-    __shared__ double sk[HELM ? EN : 1];
-    __shared__ double red[(kThreads / 64) * 2 * R];
+    __shared__ double red[(kTileThreads / 64) * 2 * R];
 
     const int tid = threadIdx.x;
     const int N = a.N;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int x0 = blockIdx.x * T, y0 = blockIdx.y * T;
     const int ex0 = x0 - HL, ey0 = y0 - HL;
     const double h2 = a.h * a.h, ih2 = 1.0 / h2;
 
-    for (int i = tid; i < EN; i += kThreads) {
-        const int ly = i / EX, lx = i - ly * EX;
-        const int gx = ex0 + lx, gy = ey0 + ly;
-        const bool in = gx >= 0 && gx <= N && gy >= 0 && gy <= N;
-        const size_t g = in ? (size_t)gy * a.pitch + gx : 0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            su[r][i] = (in && a.u_in[r]) ? a.u_in[r][g] : 0.0;
-            sf[r][i] = in ? a.f[r][g] : 0.0;
-        }
-        if (HELM) sk[i] = in ? a.k2[g] : 0.0;
-    }
+    double fr[R][KP][2], Dr[KP][2], iDr[KP][2];
+    tile_load<R, HELM, EX, EY, KP>(su, fr, Dr, iDr, a.u_in, a.f, a.k2, a.pitch, ex0, ey0, N, h2);
     __syncthreads();
+
+    auto residual = [&](int r, int k, int j, int l) {
+        const double u0 = su[r][l];
+        const double nb = su[r][l - 1] + su[r][l + 1] + su[r][l - EX] + su[r][l + EX];
+        const double D = pick(j, Dr[k][0], Dr[k][1]);
+        const double fv = pick(j, fr[r][k][0], fr[r][k][1]);
+        return fv - (nb - D * u0) * ih2;
+    };
 
     if (a.norm_part) {  // residual of the incoming iterate on the owned interior nodes
         double acc[2 * R];
 #pragma unroll
-        for (int k = 0; k < 2 * R; ++k) acc[k] = 0.0;
-        for (int i = tid; i < TX * TY; i += kThreads) {
-            const int oy = i / TX, ox = i - oy * TX;
-            const int gx = x0 + ox, gy = y0 + oy;
-            if (gx < 1 || gx > N - 1 || gy < 1 || gy > N - 1) continue;
-            const int l = (oy + HL) * EX + ox + HL;
+        for (int q = 0; q < 2 * R; ++q) acc[q] = 0.0;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                double au = (su[r][l - 1] + su[r][l + 1] + su[r][l - EX] + su[r][l + EX] -
-                             4.0 * su[r][l]) * ih2;
-                if (HELM) au -= sk[l] * su[r][l];
-                const double rr = sf[r][l] - au;
-                acc[2 * r] += rr * rr;
-                acc[2 * r + 1] += sf[r][l] * sf[r][l];
+        for (int k = 0; k < KP; ++k) {
+            const int p = tid + k * kTileThreads;
+            const int ly = p / PW, px = p - ly * PW;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int lx = 2 * px + j;
+                const int gx = ex0 + lx, gy = ey0 + ly;
+                if (p < NP && lx >= HL && lx < HL + T && ly >= HL && ly < HL + T && gx >= 1 &&
+                    gx <= N - 1 && gy >= 1 && gy <= N - 1) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const double rr = residual(r, k, j, ly * EX + lx);
+                        const double fv = pick(j, fr[r][k][0], fr[r][k][1]);
+                        acc[2 * r] += rr * rr;
+                        acc[2 * r + 1] += fv * fv;
+                    }
+                }
             }
         }
-        block_sum<2 * R, kThreads>(acc, red);
+        block_sum<2 * R, kTileThreads>(acc, red);
         if (tid == 0) {
             const int b = blockIdx.y * gridDim.x + blockIdx.x;
 #pragma unroll
-            for (int k = 0; k < 2 * R; ++k) a.norm_part[k * a.nblk + b] = acc[k];
+            for (int q = 0; q < 2 * R; ++q) a.norm_part[q * a.nblk + b] = acc[q];
         }
     }
 
     for (int s = 0; s < NU; ++s)
         for (int color = 0; color < 2; ++color) {
-            rb_half_sweep<R, HELM, EX, EY>(su, sf, sk, ex0, ey0, N, h2, color);
+            tile_sweep<R, HELM, EX, EY, KP>(su, fr, iDr, ex0, ey0, N, h2, color);
             __syncthreads();
         }
 
-    for (int i = tid; i < TX * TY; i += kThreads) {  // owned nodes x0..x0+TX-1 (< N)
-        const int oy = i / TX, ox = i - oy * TX;
-        const int gx = x0 + ox, gy = y0 + oy;
-        if (gx > N - 1 || gy > N - 1) continue;
-        const int l = (oy + HL) * EX + ox + HL;
+    // write the owned nodes; residual on [x0-1, x0+T-1]^2 into registers
+    double rr[R][KP][2];
 #pragma unroll
-        for (int r = 0; r < R; ++r) a.u_out[r][(size_t)gy * a.pitch + gx] = su[r][l];
+    for (int k = 0; k < KP; ++k) {
+        const int p = tid + k * kTileThreads;
+        const int ly = p / PW, px = p - ly * PW;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int lx = 2 * px + j;
+            const int gx = ex0 + lx, gy = ey0 + ly;
+            const int l = ly * EX + lx;
+            if (p < NP && lx >= HL && lx < HL + T && ly >= HL && ly < HL + T && gx <= N - 1 &&
+                gy <= N - 1)
+#pragma unroll
+                for (int r = 0; r < R; ++r) a.u_out[r][(size_t)gy * a.pitch + gx] = su[r][l];
+            const bool interior = p < NP && lx >= HL - 1 && lx <= HL + T - 1 && ly >= HL - 1 &&
+                                  ly <= HL + T - 1 && gx >= 1 && gx <= N - 1 && gy >= 1 &&
+                                  gy <= N - 1;
+#pragma unroll
+            for (int r = 0; r < R; ++r) rr[r][k][j] = interior ? residual(r, k, j, l) : 0.0;
+        }
     }
-
-    // residual on [x0-1, x0+TX-1]^2, stored over f (each node reads only its own f)
-    for (int i = tid; i < (TX + 1) * (TY + 1); i += kThreads) {
-        const int oy = i / (TX + 1), ox = i - oy * (TX + 1);
-        const int gx = x0 - 1 + ox, gy = y0 - 1 + oy;
-        const int l = (oy + HL - 1) * EX + ox + HL - 1;
-        const bool interior = gx >= 1 && gx <= N - 1 && gy >= 1 && gy <= N - 1;
+    __syncthreads();
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            double rr = 0.0;
-            if (interior) {
-                double au = (su[r][l - 1] + su[r][l + 1] + su[r][l - EX] + su[r][l + EX] -
-                             4.0 * su[r][l]) * ih2;
-                if (HELM) au -= sk[l] * su[r][l];
-                rr = sf[r][l] - au;
-            }
-            sf[r][l] = rr;
+    for (int k = 0; k < KP; ++k) {  // the residual replaces u in LDS
+        const int p = tid + k * kTileThreads;
+        const int ly = p / PW, px = p - ly * PW;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int lx = 2 * px + j;
+            if (p < NP && lx >= HL - 1 && lx <= HL + T - 1 && ly >= HL - 1 && ly <= HL + T - 1)
+#pragma unroll
+                for (int r = 0; r < R; ++r) su[r][ly * EX + lx] = rr[r][k][j];
         }
     }
     __syncthreads();
 
-    // full weighting onto coarse nodes x0/2 .. x0/2 + TX/2 - 1 (< N/2)
+    // full weighting onto coarse nodes x0/2 .. x0/2 + T/2 - 1 (< N/2)
     const int Nc = N / 2;
-    for (int i = tid; i < (TX / 2) * (TY / 2); i += kThreads) {
-        const int oy = i / (TX / 2), ox = i - oy * (TX / 2);
+    for (int i = tid; i < (T / 2) * (T / 2); i += kTileThreads) {
+        const int oy = i / (T / 2), ox = i - oy * (T / 2);
         const int I = x0 / 2 + ox, J = y0 / 2 + oy;
         if (I > Nc - 1 || J > Nc - 1) continue;
         const bool interior = I >= 1 && J >= 1;
@@ -193,7 +263,7 @@ __global__ __launch_bounds__(kThreads) void k_mg_down(DownArgs a) {
         for (int r = 0; r < R; ++r) {
             double v = 0.0;
             if (interior) {
-                const double* q = sf[r];
+                const double* q = su[r];
                 v = (4.0 * q[l] + 2.0 * (q[l - 1] + q[l + 1] + q[l - EX] + q[l + EX]) +
                      (q[l - EX - 1] + q[l - EX + 1] + q[l + EX - 1] + q[l + EX + 1])) *
                     (1.0 / 16.0);
@@ -214,36 +284,28 @@ struct UpArgs {
     double* u_out[2];
 };
 
-template <int R, bool HELM, int NU, int TX, int TY>
-__global__ __launch_bounds__(kThreads) void k_mg_up(UpArgs a) {
+// Up pass of one level: u += bilinear prolongation of the coarse correction on
+// the whole tile (halo 2 nu), nu2 sweeps, write the owned nodes.
+template <int R, bool HELM, int NU, int T>
+__global__ __launch_bounds__(kTileThreads) void k_mg_up(UpArgs a) {
     constexpr int H = 2 * NU;
-    constexpr int EX = TX + 2 * H, EY = TY + 2 * H, EN = EX * EY;
+    constexpr int EX = T + 2 * H, EY = EX;
+    using S = TileShape<R, HELM, EX, EY>;
+    constexpr int PW = S::PW, NP = S::NP, KP = S::KP, EN = S::EN;
     constexpr int CX = EX / 2 + 1, CY = EY / 2 + 1;
     __shared__ double su[R][EN];
-    __shared__ double sf[R][EN];
-    __shared__ double sk[HELM ? EN : 1];
     __shared__ double se[R][CX * CY];
 
     const int tid = threadIdx.x;
     const int N = a.N, Nc = N / 2;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int x0 = blockIdx.x * T, y0 = blockIdx.y * T;
     const int ex0 = x0 - H, ey0 = y0 - H;  // even
     const int cx0 = ex0 / 2, cy0 = ey0 / 2;
     const double h2 = a.h * a.h;
 
-    for (int i = tid; i < EN; i += kThreads) {
-        const int ly = i / EX, lx = i - ly * EX;
-        const int gx = ex0 + lx, gy = ey0 + ly;
-        const bool in = gx >= 0 && gx <= N && gy >= 0 && gy <= N;
-        const size_t g = in ? (size_t)gy * a.pitch + gx : 0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            su[r][i] = in ? a.u_mid[r][g] : 0.0;
-            sf[r][i] = in ? a.f[r][g] : 0.0;
-        }
-        if (HELM) sk[i] = in ? a.k2[g] : 0.0;
-    }
-    for (int i = tid; i < CX * CY; i += kThreads) {
+    double fr[R][KP][2], Dr[KP][2], iDr[KP][2];
+    tile_load<R, HELM, EX, EY, KP>(su, fr, Dr, iDr, a.u_mid, a.f, a.k2, a.pitch, ex0, ey0, N, h2);
+    for (int i = tid; i < CX * CY; i += kTileThreads) {
         const int cy = i / CX, cx = i - cy * CX;
         const int I = cx0 + cx, J = cy0 + cy;
         const bool in = I >= 0 && I <= Nc && J >= 0 && J <= Nc;
@@ -252,39 +314,51 @@ __global__ __launch_bounds__(kThreads) void k_mg_up(UpArgs a) {
     }
     __syncthreads();
 
-    for (int i = tid; i < EN; i += kThreads) {  // u += P e on every interior node of the tile
-        const int ly = i / EX, lx = i - ly * EX;
-        const int gx = ex0 + lx, gy = ey0 + ly;
-        if (gx < 1 || gx > N - 1 || gy < 1 || gy > N - 1) continue;
-        const int ci = (gx >> 1) - cx0, cj = (gy >> 1) - cy0;
-        const int c = cj * CX + ci;
-        const bool ox = gx & 1, oy = gy & 1;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const double* e = se[r];
-            double v;
-            if (!ox && !oy) v = e[c];
-            else if (ox && !oy) v = 0.5 * (e[c] + e[c + 1]);
-            else if (!ox && oy) v = 0.5 * (e[c] + e[c + CX]);
-            else v = 0.25 * (e[c] + e[c + 1] + e[c + CX] + e[c + CX + 1]);
-            su[r][i] += v;
+    for (int k = 0; k < KP; ++k) {  // each thread corrects the nodes of its own pairs
+        const int p = tid + k * kTileThreads;
+        const int ly = p / PW, px = p - ly * PW;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int lx = 2 * px + j;
+            const int gx = ex0 + lx, gy = ey0 + ly;
+            if (p >= NP || gx < 1 || gx > N - 1 || gy < 1 || gy > N - 1) continue;
+            const int c = ((gy >> 1) - cy0) * CX + (gx >> 1) - cx0;
+            const bool ox = gx & 1, oy = gy & 1;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double* e = se[r];
+                double v;
+                if (!ox && !oy) v = e[c];
+                else if (ox && !oy) v = 0.5 * (e[c] + e[c + 1]);
+                else if (!ox && oy) v = 0.5 * (e[c] + e[c + CX]);
+                else v = 0.25 * (e[c] + e[c + 1] + e[c + CX] + e[c + CX + 1]);
+                su[r][ly * EX + lx] += v;
+            }
         }
     }
     __syncthreads();
 
     for (int s = 0; s < NU; ++s)
         for (int color = 0; color < 2; ++color) {
-            rb_half_sweep<R, HELM, EX, EY>(su, sf, sk, ex0, ey0, N, h2, color);
+            tile_sweep<R, HELM, EX, EY, KP>(su, fr, iDr, ex0, ey0, N, h2, color);
             __syncthreads();
         }
 
-    for (int i = tid; i < TX * TY; i += kThreads) {
-        const int oy = i / TX, ox = i - oy * TX;
-        const int gx = x0 + ox, gy = y0 + oy;
-        if (gx > N - 1 || gy > N - 1) continue;
-        const int l = (oy + H) * EX + ox + H;
 #pragma unroll
-        for (int r = 0; r < R; ++r) a.u_out[r][(size_t)gy * a.pitch + gx] = su[r][l];
+    for (int k = 0; k < KP; ++k) {
+        const int p = tid + k * kTileThreads;
+        const int ly = p / PW, px = p - ly * PW;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int lx = 2 * px + j;
+            const int gx = ex0 + lx, gy = ey0 + ly;
+            if (p < NP && lx >= H && lx < H + T && ly >= H && ly < H + T && gx <= N - 1 &&
+                gy <= N - 1)
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    a.u_out[r][(size_t)gy * a.pitch + gx] = su[r][ly * EX + lx];
+        }
     }
 }
 
@@ -296,7 +370,7 @@ struct CoarseArgs {
     int pitch;
     const double* f[2];
     const double* u_init[2];  // nullptr: zero initial guess
-    const double* k2;
+    const double* k2lev;      // Helmholtz: k2 of every level N..2, dense, concatenated
     double* u_out[2];
     int ncycles, nu1, nu2;
 };
@@ -307,33 +381,85 @@ constexpr int coarse_nodes() {
     return t;
 }
 
-template <bool HELM>
-__device__ void lds_smooth(double* u, const double* f, const double* k2, int n, double h,
-                           int nu) {
-    const double h2 = h * h;
-    const int m = n - 1;  // interior nodes per row
-    const int half = (m + 1) / 2;
-    for (int s = 0; s < nu; ++s)
-        for (int color = 0; color < 2; ++color) {
-            for (int i = threadIdx.x; i < m * half; i += kCoarseThreads) {
-                const int b = 1 + i / half;
-                const int k = i - (b - 1) * half;
-                const int a = 1 + ((1 + b + color) & 1) + 2 * k;
-                if (a > n - 1) continue;
-                const int l = b * (n + 1) + a;
-                const double nb = u[l - 1] + u[l + 1] + u[l - n - 1] + u[l + n + 1];
-                u[l] = HELM ? (nb - h2 * f[l]) / (4.0 + h2 * k2[l]) : (nb - h2 * f[l]) * 0.25;
-            }
-            __syncthreads();
-        }
-}
+// Level operations with the level size as a compile-time constant.
+template <bool HELM, int n>
+struct LdsLevel {
+    static constexpr int W = n + 1;
+    static constexpr int HALF = n / 2;  // nodes of one colour per interior row (upper bound)
 
-template <bool HELM>
-__device__ __forceinline__ double lds_resid(const double* u, const double* f, const double* k2,
-                                            int n, double ih2, int l) {
-    double au = (u[l - 1] + u[l + 1] + u[l - n - 1] + u[l + n + 1] - 4.0 * u[l]) * ih2;
-    if (HELM) au -= k2[l] * u[l];
-    return f[l] - au;
+    static __device__ void smooth(double* u, const double* f, const double* k2, double h2, int nu) {
+        for (int s = 0; s < nu; ++s)
+            for (int color = 0; color < 2; ++color) {
+                for (int i = threadIdx.x; i < (n - 1) * HALF; i += kCoarseThreads) {
+                    const int b = 1 + i / HALF;
+                    const int a = 1 + ((1 + b + color) & 1) + 2 * (i - (b - 1) * HALF);
+                    if (a > n - 1) continue;
+                    const int l = b * W + a;
+                    const double nb = u[l - 1] + u[l + 1] + u[l - W] + u[l + W];
+                    u[l] = HELM ? (nb - h2 * f[l]) / (4.0 + h2 * k2[l]) : (nb - h2 * f[l]) * 0.25;
+                }
+                __syncthreads();
+            }
+    }
+
+    static __device__ double resid(const double* u, const double* f, const double* k2,
+                                   double ih2, int l) {
+        double au = (u[l - 1] + u[l + 1] + u[l - W] + u[l + W] - 4.0 * u[l]) * ih2;
+        if (HELM) au -= k2[l] * u[l];
+        return f[l] - au;
+    }
+
+    // f_c = full weighting of the residual; u_c = 0
+    static __device__ void restrict_to(const double* u, const double* f, const double* k2,
+                                       double ih2, double* uc, double* fc) {
+        constexpr int nc = n / 2, Wc = nc + 1;
+        for (int i = threadIdx.x; i < Wc * Wc; i += kCoarseThreads) {
+            const int J = i / Wc, I = i - J * Wc;
+            double v = 0.0;
+            if (I >= 1 && J >= 1 && I <= nc - 1 && J <= nc - 1) {
+                const int c = (2 * J) * W + 2 * I;
+                v = (4.0 * resid(u, f, k2, ih2, c) +
+                     2.0 * (resid(u, f, k2, ih2, c - 1) + resid(u, f, k2, ih2, c + 1) +
+                            resid(u, f, k2, ih2, c - W) + resid(u, f, k2, ih2, c + W)) +
+                     (resid(u, f, k2, ih2, c - W - 1) + resid(u, f, k2, ih2, c - W + 1) +
+                      resid(u, f, k2, ih2, c + W - 1) + resid(u, f, k2, ih2, c + W + 1))) *
+                    (1.0 / 16.0);
+            }
+            fc[i] = v;
+            uc[i] = 0.0;
+        }
+        __syncthreads();
+    }
+
+    // u += bilinear interpolation of the coarse correction uc
+    static __device__ void prolong_add(double* u, const double* uc) {
+        constexpr int nc = n / 2, Wc = nc + 1;
+        for (int i = threadIdx.x; i < W * W; i += kCoarseThreads) {
+            const int y = i / W, x = i - y * W;
+            if (x < 1 || y < 1 || x > n - 1 || y > n - 1) continue;
+            const int c = (y >> 1) * Wc + (x >> 1);
+            const bool ox = x & 1, oy = y & 1;
+            double v;
+            if (!ox && !oy) v = uc[c];
+            else if (ox && !oy) v = 0.5 * (uc[c] + uc[c + 1]);
+            else if (!ox && oy) v = 0.5 * (uc[c] + uc[c + Wc]);
+            else v = 0.25 * (uc[c] + uc[c + 1] + uc[c + Wc] + uc[c + Wc + 1]);
+            u[i] += v;
+        }
+        __syncthreads();
+    }
+};
+
+// Level dispatch: runtime level size -> compile-time specialisation.
+template <bool HELM, typename Fn>
+__device__ __forceinline__ void with_level(int n, Fn&& fn) {
+    switch (n) {
+        case 64: fn(LdsLevel<HELM, 64>{}); break;
+        case 32: fn(LdsLevel<HELM, 32>{}); break;
+        case 16: fn(LdsLevel<HELM, 16>{}); break;
+        case 8: fn(LdsLevel<HELM, 8>{}); break;
+        default: fn(LdsLevel<HELM, 4>{}); break;
+    }
 }
 
 template <bool HELM>
@@ -353,66 +479,55 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs a) {
         ++nl;
     }
     const int N = a.N;
-    for (int i = tid; i < (N + 1) * (N + 1); i += kCoarseThreads) {
-        const int y = i / (N + 1), x = i - y * (N + 1);
-        const bool bnd = x == 0 || y == 0 || x == N || y == N;
-        const size_t g = (size_t)y * a.pitch + x;
-        su[i] = (!bnd && a.u_init[r]) ? a.u_init[r][g] : 0.0;
-        sf[i] = bnd ? 0.0 : a.f[r][g];
-        if (HELM) sk[i] = bnd ? 0.0 : a.k2[g];
-    }
-    __syncthreads();
-    if (HELM) {  // coarse k2 by full weighting of the finer level
-        for (int l = 1; l < nl; ++l) {
-            const int n = Ns[l], nf = Ns[l - 1];
-            const double* kf = sk + off[l - 1];
-            double* kc = sk + off[l];
-            for (int i = tid; i < (n + 1) * (n + 1); i += kCoarseThreads) {
-                const int J = i / (n + 1), I = i - J * (n + 1);
-                double v = 0.0;
-                if (I >= 1 && J >= 1 && I <= n - 1 && J <= n - 1) {
-                    const int c = (2 * J) * (nf + 1) + 2 * I, w = nf + 1;
-                    v = (4.0 * kf[c] + 2.0 * (kf[c - 1] + kf[c + 1] + kf[c - w] + kf[c + w]) +
-                         (kf[c - w - 1] + kf[c - w + 1] + kf[c + w - 1] + kf[c + w + 1])) *
-                        (1.0 / 16.0);
-                }
-                kc[i] = v;
+    // loads in batches of kB per thread so that their latencies overlap
+    constexpr int kB = 8;
+    const int nt = (N + 1) * (N + 1);
+    for (int base = 0; base < nt; base += kB * kCoarseThreads) {
+        double uv[kB], fv[kB];
+#pragma unroll
+        for (int b = 0; b < kB; ++b) {
+            const int i = base + b * kCoarseThreads + tid;
+            const int y = i / (N + 1), x = i - y * (N + 1);
+            const bool ok = i < nt && x != 0 && y != 0 && x != N && y != N;
+            const size_t g = ok ? (size_t)y * a.pitch + x : 0;
+            uv[b] = (ok && a.u_init[r]) ? a.u_init[r][g] : 0.0;
+            fv[b] = ok ? a.f[r][g] : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < kB; ++b) {
+            const int i = base + b * kCoarseThreads + tid;
+            if (i < nt) {
+                su[i] = uv[b];
+                sf[i] = fv[b];
             }
-            __syncthreads();
         }
     }
+    if (HELM)
+        for (int base = 0; base < tot; base += kB * kCoarseThreads) {
+            double kv[kB];
+#pragma unroll
+            for (int b = 0; b < kB; ++b) {
+                const int i = base + b * kCoarseThreads + tid;
+                kv[b] = i < tot ? a.k2lev[i] : 0.0;
+            }
+#pragma unroll
+            for (int b = 0; b < kB; ++b) {
+                const int i = base + b * kCoarseThreads + tid;
+                if (i < tot) sk[i] = kv[b];
+            }
+        }
+    __syncthreads();
 
     for (int cyc = 0; cyc < a.ncycles; ++cyc) {
         for (int l = 0; l < nl - 1; ++l) {
-            const int n = Ns[l], nc = Ns[l + 1];
             const double hl = a.h * (double)(1 << l);
             double* u = su + off[l];
             double* f = sf + off[l];
-            double* k2 = sk + (HELM ? off[l] : 0);
-            lds_smooth<HELM>(u, f, k2, n, hl, a.nu1);
-            const double ih2 = 1.0 / (hl * hl);
-            double* uc = su + off[l + 1];
-            double* fc = sf + off[l + 1];
-            for (int i = tid; i < (nc + 1) * (nc + 1); i += kCoarseThreads) {
-                const int J = i / (nc + 1), I = i - J * (nc + 1);
-                double v = 0.0;
-                if (I >= 1 && J >= 1 && I <= nc - 1 && J <= nc - 1) {
-                    const int c = (2 * J) * (n + 1) + 2 * I, w = n + 1;
-                    v = (4.0 * lds_resid<HELM>(u, f, k2, n, ih2, c) +
-                         2.0 * (lds_resid<HELM>(u, f, k2, n, ih2, c - 1) +
-                                lds_resid<HELM>(u, f, k2, n, ih2, c + 1) +
-                                lds_resid<HELM>(u, f, k2, n, ih2, c - w) +
-                                lds_resid<HELM>(u, f, k2, n, ih2, c + w)) +
-                         (lds_resid<HELM>(u, f, k2, n, ih2, c - w - 1) +
-                          lds_resid<HELM>(u, f, k2, n, ih2, c - w + 1) +
-                          lds_resid<HELM>(u, f, k2, n, ih2, c + w - 1) +
-                          lds_resid<HELM>(u, f, k2, n, ih2, c + w + 1))) *
-                        (1.0 / 16.0);
-                }
-                fc[i] = v;
-                uc[i] = 0.0;
-            }
-            __syncthreads();
+            const double* k2 = sk + (HELM ? off[l] : 0);
+            with_level<HELM>(Ns[l], [&](auto L) {
+                L.smooth(u, f, k2, hl * hl, a.nu1);
+                L.restrict_to(u, f, k2, 1.0 / (hl * hl), su + off[l + 1], sf + off[l + 1]);
+            });
         }
         if (tid == 0) {  // 2x2 cells: one unknown, four zero neighbours
             const int l = nl - 1;
@@ -423,29 +538,49 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs a) {
         }
         __syncthreads();
         for (int l = nl - 2; l >= 0; --l) {
-            const int n = Ns[l], nc = Ns[l + 1];
+            const double hl = a.h * (double)(1 << l);
             double* u = su + off[l];
-            const double* e = su + off[l + 1];
-            for (int i = tid; i < (n + 1) * (n + 1); i += kCoarseThreads) {
-                const int y = i / (n + 1), x = i - y * (n + 1);
-                if (x < 1 || y < 1 || x > n - 1 || y > n - 1) continue;
-                const int c = (y >> 1) * (nc + 1) + (x >> 1);
-                const bool ox = x & 1, oy = y & 1;
-                double v;
-                if (!ox && !oy) v = e[c];
-                else if (ox && !oy) v = 0.5 * (e[c] + e[c + 1]);
-                else if (!ox && oy) v = 0.5 * (e[c] + e[c + nc + 1]);
-                else v = 0.25 * (e[c] + e[c + 1] + e[c + nc + 1] + e[c + nc + 2]);
-                u[i] += v;
-            }
-            __syncthreads();
-            lds_smooth<HELM>(u, sf + off[l], sk + (HELM ? off[l] : 0), n, a.h * (double)(1 << l),
-                             a.nu2);
+            with_level<HELM>(Ns[l], [&](auto L) {
+                L.prolong_add(u, su + off[l + 1]);
+                L.smooth(u, sf + off[l], sk + (HELM ? off[l] : 0), hl * hl, a.nu2);
+            });
         }
     }
     for (int i = tid; i < (N + 1) * (N + 1); i += kCoarseThreads) {
         const int y = i / (N + 1), x = i - y * (N + 1);
         a.u_out[r][(size_t)y * a.pitch + x] = su[i];
+    }
+}
+
+// k2 of the coarse-kernel levels: the top level (N <= 64, pitched) copied
+// densely, then full weighting level by level.  One block.
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_k2(int N, int pitch,
+                                                              const double* __restrict__ k2top,
+                                                              double* __restrict__ out) {
+    for (int i = threadIdx.x; i < (N + 1) * (N + 1); i += kCoarseThreads) {
+        const int y = i / (N + 1), x = i - y * (N + 1);
+        const bool bnd = x == 0 || y == 0 || x == N || y == N;
+        out[i] = bnd ? 0.0 : k2top[(size_t)y * pitch + x];
+    }
+    __syncthreads();
+    int off = 0;
+    for (int nf = N; nf > 2; nf /= 2) {
+        const int nc = nf / 2, w = nf + 1;
+        const double* kf = out + off;
+        double* kc = out + off + (nf + 1) * (nf + 1);
+        for (int i = threadIdx.x; i < (nc + 1) * (nc + 1); i += kCoarseThreads) {
+            const int J = i / (nc + 1), I = i - J * (nc + 1);
+            double v = 0.0;
+            if (I >= 1 && J >= 1 && I <= nc - 1 && J <= nc - 1) {
+                const int c = (2 * J) * w + 2 * I;
+                v = (4.0 * kf[c] + 2.0 * (kf[c - 1] + kf[c + 1] + kf[c - w] + kf[c + w]) +
+                     (kf[c - w - 1] + kf[c - w + 1] + kf[c + w - 1] + kf[c + w + 1])) *
+                    (1.0 / 16.0);
+            }
+            kc[i] = v;
+        }
+        __syncthreads();
+        off += (nf + 1) * (nf + 1);
     }
 }
 
@@ -519,18 +654,18 @@ __global__ void k_restrict_fw(const double* fine, int pf, double* coarse, int pc
 template <int R, bool HELM>
 void launch_down(const DownArgs& a, int nu, dim3 grid, hipStream_t s) {
     switch (nu) {
-        case 1: hipLaunchKernelGGL((k_mg_down<R, HELM, 1, kTile, kTile>), grid, dim3(kThreads), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_mg_down<R, HELM, 2, kTile, kTile>), grid, dim3(kThreads), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_mg_down<R, HELM, 3, kTile, kTile>), grid, dim3(kThreads), 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_mg_down<R, HELM, 1, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_mg_down<R, HELM, 2, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_mg_down<R, HELM, 3, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
     }
 }
 
 template <int R, bool HELM>
 void launch_up(const UpArgs& a, int nu, dim3 grid, hipStream_t s) {
     switch (nu) {
-        case 1: hipLaunchKernelGGL((k_mg_up<R, HELM, 1, kTile, kTile>), grid, dim3(kThreads), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_mg_up<R, HELM, 2, kTile, kTile>), grid, dim3(kThreads), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_mg_up<R, HELM, 3, kTile, kTile>), grid, dim3(kThreads), 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_mg_up<R, HELM, 1, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_mg_up<R, HELM, 2, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_mg_up<R, HELM, 3, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
     }
 }
 
@@ -582,7 +717,7 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Fine& fz, int norm_slot) {
         // algorithmic bytes per owned node: u (level 0 only), f, k2, smoothed u, coarse f
         const double nodes = (double)L.N * L.N;
         char nm[56];
-        std::snprintf(nm, sizeof nm, "k_mg_down<%d, %s, %d, 32, 32>@%d", R,
+        std::snprintf(nm, sizeof nm, "k_mg_down<%d, %s, %d, 32>@%d", R,
                       helm ? "true" : "false", c->cfg.nu_pre, L.N);
         ProfScope ps(c, nm, nodes * ((l == 0 ? 8.0 * R : 0.0) + 8.0 * R + (helm ? 8.0 : 0.0) +
                                      8.0 * R + 2.0 * R));
@@ -599,7 +734,7 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Fine& fz, int norm_slot) {
             a.u_init[r] = lc == 0 ? fz.u[r] : nullptr;
             a.u_out[r] = lev_u(lc, r);
         }
-        a.k2 = helm ? lev_k(lc) : nullptr;
+        a.k2lev = helm ? c->k2lev : nullptr;
         a.ncycles = 1;
         a.nu1 = c->cfg.nu_pre;
         a.nu2 = c->cfg.nu_post;
@@ -626,7 +761,7 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Fine& fz, int norm_slot) {
         // per owned node: smoothed u, coarse correction (1/4), f, k2, corrected u
         const double nodes = (double)L.N * L.N;
         char nm[56];
-        std::snprintf(nm, sizeof nm, "k_mg_up<%d, %s, %d, 32, 32>@%d", R,
+        std::snprintf(nm, sizeof nm, "k_mg_up<%d, %s, %d, 32>@%d", R,
                       helm ? "true" : "false", c->cfg.nu_post, L.N);
         ProfScope ps(c, nm, nodes * (8.0 * R + 2.0 * R + 8.0 * R + (helm ? 8.0 : 0.0) + 8.0 * R));
         up(R, helm, a, c->cfg.nu_post, tiles(L.N), s);
@@ -674,6 +809,15 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
             hipLaunchKernelGGL(k_restrict_fw, dim3((C.N + 1 + 127) / 128, C.N + 1), dim3(128), 0, s,
                                src, F.pitch, C.k2, C.pitch, C.N);
         }
+    }
+    if (helm) {  // k2 of the coarse-kernel levels, once per solve
+        const wq::Level& T = c->lev[c->lc];
+        const double* top = c->lc == 0 ? k2 : T.k2;
+        int tot = 0;
+        for (int n = T.N; n >= 2; n /= 2) tot += (n + 1) * (n + 1);
+        ProfScope ps(c, "k_coarse_k2", 16.0 * tot);
+        hipLaunchKernelGGL(k_coarse_k2, dim3(1), dim3(kCoarseThreads), 0, s, T.N, T.pitch, top,
+                           c->k2lev);
     }
     const int maxc = c->cfg.mg_max_cycles;
     if (!(c->cfg.mg_rtol > 0.0)) {

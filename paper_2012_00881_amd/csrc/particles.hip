@@ -37,18 +37,41 @@ __device__ __forceinline__ double cic_gather(double f00, double f10, double f01,
            f11 * dx * dy;
 }
 
+// Lanes of a wave holding the same key in consecutive lanes form a run (the
+// particles are stored in cell order from the previous slice, so most keys
+// repeat).  Returns the run's first lane and length; one atomic per run.
+__device__ __forceinline__ void key_run(int key, bool valid, int& head, int& len) {
+    const int lane = threadIdx.x & 63;
+    const int prev = __shfl_up(key, 1, 64);
+    const bool is_head = valid && (lane == 0 || prev != key);
+    const unsigned long long heads = __ballot(is_head);
+    const unsigned long long live = __ballot(valid);
+    // head: highest head lane <= lane; next head: lowest head lane > lane
+    const unsigned long long below = heads & (lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1));
+    head = 63 - __clzll(below);
+    const unsigned long long above = heads & ~(lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1));
+    const int end_live = 64 - __clzll(live);  // one past the last valid lane
+    const int next = above ? __ffsll(above) - 1 : end_live;
+    len = next - head;
+}
+
 __global__ void k_cell_key(int64_t P, const double* __restrict__ x, const double* __restrict__ y,
                            double L, double h, int N, int32_t* __restrict__ key,
                            int32_t* __restrict__ count) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P) return;
-    int a, b;
-    double d;
-    cic(x[i], L, h, N, a, d);
-    cic(y[i], L, h, N, b, d);
-    const int k = b * N + a;
-    key[i] = k;
-    atomicAdd(&count[k], 1);
+    const bool valid = i < P;
+    int k = -1;
+    if (valid) {
+        int a, b;
+        double d;
+        cic(x[i], L, h, N, a, d);
+        cic(y[i], L, h, N, b, d);
+        k = b * N + a;
+        key[i] = k;
+    }
+    int head, len;
+    key_run(k, valid, head, len);
+    if (valid && (threadIdx.x & 63) == head) atomicAdd(&count[k], len);
 }
 
 // Exclusive scan, phase 1: each block scans kScanBlock items and emits its total.
@@ -114,15 +137,21 @@ __global__ void k_scan_add(int32_t* __restrict__ out, int n, const int32_t* __re
     if (i < n) out[i] += blk[i / kScanBlock];
 }
 
-// Scatter: count[] is consumed back to zero, ready for the next slice.
+// Scatter: count[] is consumed back to zero, ready for the next slice.  One
+// atomic per run of equal keys; the run's lanes take consecutive slots.
 __global__ void k_scatter(int64_t P, const int32_t* __restrict__ key,
                           const int32_t* __restrict__ start, int32_t* __restrict__ count,
                           int32_t* __restrict__ perm) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P) return;
-    const int k = key[i];
-    const int slot = atomicSub(&count[k], 1) - 1;
-    perm[start[k] + slot] = (int32_t)i;
+    const bool valid = i < P;
+    const int k = valid ? key[i] : -1;
+    int head, len;
+    key_run(k, valid, head, len);
+    const int lane = threadIdx.x & 63;
+    int top = 0;
+    if (valid && lane == head) top = atomicSub(&count[k], len);
+    top = __shfl(top, head, 64);
+    if (valid) perm[start[k] + top - len + (lane - head)] = (int32_t)i;
 }
 
 // Order each cell's particles by permanent ID (insertion sort; cells hold a few).
@@ -394,6 +423,8 @@ __global__ __launch_bounds__(256) void k_dxi(int nparts, const double* __restric
         rec[2] = vmax;
         rec[3] = (double)flags[0];
     }
+    st[3] = st[2];  // the fields now stored belong to this slice
+    st[2] = st[0];
     st[0] = st[0] + st[1];
     st[1] = d;
 }

@@ -83,15 +83,17 @@ struct wandqs_ctx {
     // device memory carved from the caller's workspace
     wq::Level lev[wq::kMaxLevels];
     double* fields[5] = {};
+    double* fields_prev[5] = {};  // fields of the slice before (initial-guess extrapolation)
     double* mom[6] = {};
     double* jz = nullptr;
+    double* k2lev = nullptr;  // k2 of the coarse-kernel levels (dense, concatenated)
     double* pa[2][4] = {};
     int32_t* pid[2] = {};
     int cur = 0;
     int32_t *key = nullptr, *perm = nullptr, *cell_count = nullptr, *cell_start = nullptr,
             *scan_blk = nullptr;
     int n_scan_blocks = 0;
-    double* st = nullptr;         // [xi, dxi]
+    double* st = nullptr;         // [xi, dxi, xi of fields, xi of fields_prev]
     double* vmax_part = nullptr;  // per push block
     int n_push_blocks = 0;
     int32_t* flags = nullptr;
@@ -107,6 +109,7 @@ struct wandqs_ctx {
     double* h_pin = nullptr;  // pinned readback buffer
     int pred[4] = {1, 1, 1, 1};  // V-cycles of the last solve per kind (batch size)
     bool failed = false;
+    int n_guess = 0;  // slices since init/set_state (extrapolation needs two)
     std::string err;
     wq::SolveResult last[3];
     wq::Prof prof;
@@ -134,6 +137,7 @@ wandqs_status unpack_fields(wandqs_ctx* c, const double* src, int n, double* con
 wandqs_status particles_to_id_order(wandqs_ctx* c, double* dst);
 wandqs_status particles_from_id_order(wandqs_ctx* c, const double* src);
 wandqs_status fill_f64(wandqs_ctx* c, double* p, size_t n, double v);
+wandqs_status extrapolate_guess(wandqs_ctx* c, bool extrapolate);
 
 const char* hip_err(hipError_t e);
 
