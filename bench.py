@@ -84,6 +84,11 @@ def main():
     ap.add_argument("--no-profile-pass", action="store_true")
     ap.add_argument("--breakdown", default=None, help="write per-kernel stats (JSON) here")
     ap.add_argument("--nu", type=int, default=None, help="pre- and post-smoothing sweeps")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--rtol", type=float, default=None, help="multigrid rtol (default 1e-14)")
+    ap.add_argument("--inner", type=int, default=0, help="mixed: FP32 cycles per correction")
+    ap.add_argument("--forms-steps", type=int, default=1024,
+                    help="slices for the FP64-vs-mixed comparison at 1e-6 (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the slice step is not sharded "
@@ -94,9 +99,12 @@ def main():
     import wandqs_inputs as wi
     from paper_2012_00881_amd import Simulation
 
-    cfg = wi.scaled(wi.config(args.workload), precision="fp64")
+    cfg = wi.scaled(wi.config(args.workload), precision=args.precision,
+                    mg_inner_cycles=args.inner)
     if args.nu is not None:
         cfg.update(nu_pre=args.nu, nu_post=args.nu)
+    if args.rtol is not None:
+        cfg.update(mg_rtol=args.rtol)
     K, W = args.steps, args.warmup
 
     print(f"[bench] warm-up: {W} slices", file=sys.stderr, flush=True)
@@ -176,6 +184,32 @@ def main():
                                per_level=per_level, source_hash=kernel_source_hash()), fh,
                           indent=1)
 
+    forms = None
+    if args.forms_steps > 0:
+        # FP64 and mixed solved to the same loose tolerance (rtol 1e-9 keeps every
+        # field within 1e-6 of the oracle), timed over the same slices
+        forms = {}
+        for prec in ("fp64", "mixed"):
+            fc = wi.scaled(cfg, precision=prec, mg_rtol=1e-9)
+            print(f"[bench] form {prec} @1e-6: {args.forms_steps} slices", file=sys.stderr, flush=True)
+            sim = Simulation(fc, n_slices=args.forms_steps)
+            torch.cuda.synchronize()
+            tf = time.perf_counter()
+            fi, _ = sim.run(args.forms_steps, infos=True)
+            torch.cuda.synchronize()
+            tf = time.perf_counter() - tf
+            sim.close()
+            del sim
+            forms[prec + "@1e-6"] = {
+                "value": P * args.forms_steps / tf, "ms_per_step": 1e3 * tf / args.forms_steps,
+                "steps": args.forms_steps,
+                "mean_vcycles": [round(sum(i["vcycles"][k] for i in fi) / len(fi), 3)
+                                 for k in range(5)]}
+        forms["mixed_speedup"] = (forms["fp64@1e-6"]["ms_per_step"] /
+                                  forms["mixed@1e-6"]["ms_per_step"])
+        print(f"[bench] mixed speedup at 1e-6: {forms['mixed_speedup']:.3f}", file=sys.stderr,
+              flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         print(f"[bench] CPU oracle on {args.cpu_slices} slices", file=sys.stderr, flush=True)
@@ -184,12 +218,14 @@ def main():
     line = {"metric": "particle-slice updates/s", "value": value,
             "unit": "particle-slice updates/s", "n_gpus": 1, "steps": K, "warmup": W,
             "ms_per_step": 1e3 * dt / K, "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f64+f32",
+            "data": "synthetic",
             "config": {"workload": WORKLOAD if args.workload == "C5" else args.workload,
                        "grid": cfg["n_cells"], "particles": P, "slices": K,
-                       "precision": "fp64", "xi_end": final["xi"],
+                       "precision": args.precision, "mg_rtol": cfg["mg_rtol"],
+                       "xi_end": final["xi"],
                        "mean_vcycles": [round(c, 3) for c in cyc]},
-            "roofline": roof, "cpu_baseline": cpu}
+            "roofline": roof, "cpu_baseline": cpu, "forms": forms}
     print(json.dumps(line), flush=True)
 
 

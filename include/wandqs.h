@@ -102,6 +102,12 @@ typedef struct {
     int32_t n_probes;      /* 0 .. 16 */
     const wandqs_probe* probes;
     int32_t checkpoint_every; /* K for the adjoint tape; 0 = no tape */
+    int32_t mg_inner_cycles;  /* WANDQS_MIXED: FP32 V-cycles per FP64 defect correction
+                                 (0: 1, the fastest measured at C5).  The mixed form keeps the residual, the
+                                 correction sum u += e and the coarsest (2x2) solve in
+                                 FP64 and smooths/transfers the error equation in FP32;
+                                 particles stay FP64.  Each "V-cycle" counted in
+                                 wandqs_slice_info.vcycles is then one outer iteration. */
 } wandqs_config;
 
 typedef struct {

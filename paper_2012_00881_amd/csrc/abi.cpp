@@ -29,7 +29,8 @@ std::string check_config(const wandqs_config* c, int32_t n_slices) {
     if (!(c->dxi0 > 0.0) || !std::isfinite(c->dxi0)) return "dxi0 must be > 0";
     if (c->adaptive != 0 && c->adaptive != 1) return "adaptive must be 0 or 1";
     if (c->refine_k < 0) return "refine_k must be >= 0";
-    if (c->precision != WANDQS_FP64) return "precision: only WANDQS_FP64 is available";
+    if (c->precision != WANDQS_FP64 && c->precision != WANDQS_MIXED) return "unknown precision";
+    if (c->mg_inner_cycles < 0 || c->mg_inner_cycles > 8) return "mg_inner_cycles must be in [0, 8]";
     if (!std::isfinite(c->mg_rtol) || !(c->mg_atol >= 0.0)) return "bad mg_rtol / mg_atol";
     if (c->mg_max_cycles < 1 || c->mg_max_cycles > 200) return "mg_max_cycles must be in [1, 200]";
     if (c->nu_pre < 1 || c->nu_pre > 3 || c->nu_post < 1 || c->nu_post > 3)
@@ -190,6 +191,18 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
             L.f[r] = arr(l);
         }
         L.k2 = arr(l);
+    }
+    if (c->cfg.precision == WANDQS_MIXED) {
+        auto arr32 = [&](int l) {
+            return (float*)take(sizeof(float) * (size_t)(c->lev[l].N + 1) * c->lev[l].pitch);
+        };
+        for (int l = 0; l <= c->lc; ++l)
+            for (int r = 0; r < 2; ++r) {
+                Level& L = c->lev[l];
+                L.u32[r] = arr32(l);
+                L.um32[r] = l < c->lc ? arr32(l) : nullptr;
+                L.f32[r] = arr32(l);
+            }
     }
     const size_t P = (size_t)c->P;
     const size_t ncell = (size_t)c->N * c->N;

@@ -61,7 +61,8 @@ __device__ void block_sum(double (&v)[NV], double* red) {
 // two nodes have opposite colours, so every thread updates exactly one node of
 // each of its pairs in every half sweep.
 // Value select (not an address select, so register arrays stay in registers).
-__device__ __forceinline__ double pick(int j, double a, double b) { return j ? b : a; }
+template <typename T>
+__device__ __forceinline__ T pick(int j, T a, T b) { return j ? b : a; }
 
 template <int R, bool HELM, int EX, int EY>
 struct TileShape {
@@ -72,10 +73,12 @@ struct TileShape {
     static_assert(EX % 2 == 0, "tile width must be even");
 };
 
-template <int R, bool HELM, int EX, int EY, int KP>
-__device__ __forceinline__ void tile_load(double (*su)[EX * EY], double (&fr)[R][KP][2],
-                                          double (&Dr)[KP][2], double (&iDr)[KP][2],
-                                          const double* const* u, const double* const* f,
+// E is the element type of the iterate, f and the sweep arithmetic (double, or
+// float for the inner cycles of the mixed form); k2 is always read as double
+// and D = 4 + h^2 k2, 1/D are formed in double before rounding to E.
+template <typename E, int R, bool HELM, int EX, int EY, int KP>
+__device__ __forceinline__ void tile_load(E (*su)[EX * EY], E (&fr)[R][KP][2], E (&Dr)[KP][2],
+                                          E (&iDr)[KP][2], const E* const* u, const E* const* f,
                                           const double* k2, int pitch, int ex0, int ey0, int N,
                                           double h2) {
     constexpr int PW = EX / 2, NP = PW * EY;
@@ -91,13 +94,13 @@ __device__ __forceinline__ void tile_load(double (*su)[EX * EY], double (&fr)[R]
             const size_t g = in ? (size_t)gy * pitch + gx : 0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const double uv = (in && u[r]) ? u[r][g] : 0.0;
+                const E uv = (in && u[r]) ? u[r][g] : E(0);
                 if (p < NP) su[r][ly * EX + lx] = uv;
-                fr[r][k][j] = in ? f[r][g] : 0.0;
+                fr[r][k][j] = in ? f[r][g] : E(0);
             }
-            const double kk = (HELM && in) ? k2[g] : 0.0;
-            Dr[k][j] = 4.0 + h2 * kk;
-            iDr[k][j] = HELM ? 1.0 / Dr[k][j] : 0.25;
+            const double D = 4.0 + h2 * ((HELM && in) ? k2[g] : 0.0);
+            Dr[k][j] = (E)D;
+            iDr[k][j] = HELM ? (E)(1.0 / D) : E(0.25);
         }
     }
 }
@@ -105,10 +108,10 @@ __device__ __forceinline__ void tile_load(double (*su)[EX * EY], double (&fr)[R]
 // One red-black half sweep: u <- (sum of 4 neighbours - h^2 f) / D on the nodes
 // of colour `color` ((gx + gy) % 2) that have all four neighbours in the tile
 // and lie inside the domain.
-template <int R, bool HELM, int EX, int EY, int KP>
-__device__ __forceinline__ void tile_sweep(double (*su)[EX * EY], const double (&fr)[R][KP][2],
-                                           const double (&iDr)[KP][2], int ex0, int ey0, int N,
-                                           double h2, int color) {
+template <typename E, int R, bool HELM, int EX, int EY, int KP>
+__device__ __forceinline__ void tile_sweep(E (*su)[EX * EY], const E (&fr)[R][KP][2],
+                                           const E (&iDr)[KP][2], int ex0, int ey0, int N, E h2,
+                                           int color) {
     constexpr int PW = EX / 2, NP = PW * EY;
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
@@ -121,27 +124,28 @@ __device__ __forceinline__ void tile_sweep(double (*su)[EX * EY], const double (
         if (p < NP && lx >= 1 && lx <= EX - 2 && ly >= 1 && ly <= EY - 2 && gx >= 1 &&
             gx <= N - 1 && gy >= 1 && gy <= N - 1) {
             const int l = ly * EX + lx;
-            const double id = pick(j, iDr[k][0], iDr[k][1]);
+            const E id = pick(j, iDr[k][0], iDr[k][1]);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const double fv = pick(j, fr[r][k][0], fr[r][k][1]);
-                const double nb = su[r][l - 1] + su[r][l + 1] + su[r][l - EX] + su[r][l + EX];
+                const E fv = pick(j, fr[r][k][0], fr[r][k][1]);
+                const E nb = su[r][l - 1] + su[r][l + 1] + su[r][l - EX] + su[r][l + EX];
                 su[r][l] = (nb - h2 * fv) * id;
             }
         }
     }
 }
 
+template <typename E>
 struct DownArgs {
     int N;
     double h;
     int pitch, pitch_c;
-    const double* u_in[2];  // nullptr: zero initial guess
-    const double* f[2];
+    const E* u_in[2];  // nullptr: zero initial guess
+    const E* f[2];
     const double* k2;
-    double* u_out[2];
-    double* f_c[2];
-    double* norm_part;      // nullptr or [R*2][nblk]: sum r^2, sum f^2 of the incoming u
+    E* u_out[2];
+    E* f_c[2];
+    double* norm_part;  // (double only) nullptr or [R*2][nblk]: sum r^2, sum f^2 of the incoming u
     int nblk;
 };
 
@@ -149,30 +153,31 @@ struct DownArgs {
 // residual, full-weighting restriction onto the coarse tile.  Halo: 2 nu + 2
 // nodes on the low side (the residual at x0 - 1 needs the smoothed u at x0 - 2),
 // 2 nu + 2 on the high side (one more than needed, to keep the width even).
-template <int R, bool HELM, int NU, int T>
-__global__ __launch_bounds__(kTileThreads) void k_mg_down(DownArgs a) {
+template <typename E, int R, bool HELM, int NU, int T>
+__global__ __launch_bounds__(kTileThreads) void k_mg_down(DownArgs<E> a) {
     constexpr int HL = 2 * NU + 2, HH = 2 * NU + 2;
     constexpr int EX = T + HL + HH, EY = EX;
     using S = TileShape<R, HELM, EX, EY>;
     constexpr int PW = S::PW, NP = S::NP, KP = S::KP, EN = S::EN;
-    __shared__ double su[R][EN];
+    __shared__ E su[R][EN];
     __shared__ double red[(kTileThreads / 64) * 2 * R];
 
     const int tid = threadIdx.x;
     const int N = a.N;
     const int x0 = blockIdx.x * T, y0 = blockIdx.y * T;
     const int ex0 = x0 - HL, ey0 = y0 - HL;
-    const double h2 = a.h * a.h, ih2 = 1.0 / h2;
+    const E h2 = (E)(a.h * a.h), ih2 = (E)(1.0 / (a.h * a.h));
 
-    double fr[R][KP][2], Dr[KP][2], iDr[KP][2];
-    tile_load<R, HELM, EX, EY, KP>(su, fr, Dr, iDr, a.u_in, a.f, a.k2, a.pitch, ex0, ey0, N, h2);
+    E fr[R][KP][2], Dr[KP][2], iDr[KP][2];
+    tile_load<E, R, HELM, EX, EY, KP>(su, fr, Dr, iDr, a.u_in, a.f, a.k2, a.pitch, ex0, ey0, N,
+                                      a.h * a.h);
     __syncthreads();
 
     auto residual = [&](int r, int k, int j, int l) {
-        const double u0 = su[r][l];
-        const double nb = su[r][l - 1] + su[r][l + 1] + su[r][l - EX] + su[r][l + EX];
-        const double D = pick(j, Dr[k][0], Dr[k][1]);
-        const double fv = pick(j, fr[r][k][0], fr[r][k][1]);
+        const E u0 = su[r][l];
+        const E nb = su[r][l - 1] + su[r][l + 1] + su[r][l - EX] + su[r][l + EX];
+        const E D = pick(j, Dr[k][0], Dr[k][1]);
+        const E fv = pick(j, fr[r][k][0], fr[r][k][1]);
         return fv - (nb - D * u0) * ih2;
     };
 
@@ -210,12 +215,12 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_down(DownArgs a) {
 
     for (int s = 0; s < NU; ++s)
         for (int color = 0; color < 2; ++color) {
-            tile_sweep<R, HELM, EX, EY, KP>(su, fr, iDr, ex0, ey0, N, h2, color);
+            tile_sweep<E, R, HELM, EX, EY, KP>(su, fr, iDr, ex0, ey0, N, h2, color);
             __syncthreads();
         }
 
     // write the owned nodes; residual on [x0-1, x0+T-1]^2 into registers
-    double rr[R][KP][2];
+    E rr[R][KP][2];
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
         const int p = tid + k * kTileThreads;
@@ -233,7 +238,7 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_down(DownArgs a) {
                                   ly <= HL + T - 1 && gx >= 1 && gx <= N - 1 && gy >= 1 &&
                                   gy <= N - 1;
 #pragma unroll
-            for (int r = 0; r < R; ++r) rr[r][k][j] = interior ? residual(r, k, j, l) : 0.0;
+            for (int r = 0; r < R; ++r) rr[r][k][j] = interior ? residual(r, k, j, l) : E(0);
         }
     }
     __syncthreads();
@@ -261,56 +266,58 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_down(DownArgs a) {
         const int l = (2 * J - ey0) * EX + (2 * I - ex0);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            double v = 0.0;
+            E v = E(0);
             if (interior) {
-                const double* q = su[r];
-                v = (4.0 * q[l] + 2.0 * (q[l - 1] + q[l + 1] + q[l - EX] + q[l + EX]) +
+                const E* q = su[r];
+                v = (E(4) * q[l] + E(2) * (q[l - 1] + q[l + 1] + q[l - EX] + q[l + EX]) +
                      (q[l - EX - 1] + q[l - EX + 1] + q[l + EX - 1] + q[l + EX + 1])) *
-                    (1.0 / 16.0);
+                    E(1.0 / 16.0);
             }
             a.f_c[r][(size_t)J * a.pitch_c + I] = v;
         }
     }
 }
 
+template <typename E>
 struct UpArgs {
     int N;
     double h;
     int pitch, pitch_c;
-    const double* u_mid[2];
-    const double* e_c[2];
-    const double* f[2];
+    const E* u_mid[2];
+    const E* e_c[2];
+    const E* f[2];
     const double* k2;
-    double* u_out[2];
+    E* u_out[2];
 };
 
 // Up pass of one level: u += bilinear prolongation of the coarse correction on
 // the whole tile (halo 2 nu), nu2 sweeps, write the owned nodes.
-template <int R, bool HELM, int NU, int T>
-__global__ __launch_bounds__(kTileThreads) void k_mg_up(UpArgs a) {
+template <typename E, int R, bool HELM, int NU, int T>
+__global__ __launch_bounds__(kTileThreads) void k_mg_up(UpArgs<E> a) {
     constexpr int H = 2 * NU;
     constexpr int EX = T + 2 * H, EY = EX;
     using S = TileShape<R, HELM, EX, EY>;
     constexpr int PW = S::PW, NP = S::NP, KP = S::KP, EN = S::EN;
     constexpr int CX = EX / 2 + 1, CY = EY / 2 + 1;
-    __shared__ double su[R][EN];
-    __shared__ double se[R][CX * CY];
+    __shared__ E su[R][EN];
+    __shared__ E se[R][CX * CY];
 
     const int tid = threadIdx.x;
     const int N = a.N, Nc = N / 2;
     const int x0 = blockIdx.x * T, y0 = blockIdx.y * T;
     const int ex0 = x0 - H, ey0 = y0 - H;  // even
     const int cx0 = ex0 / 2, cy0 = ey0 / 2;
-    const double h2 = a.h * a.h;
+    const E h2 = (E)(a.h * a.h);
 
-    double fr[R][KP][2], Dr[KP][2], iDr[KP][2];
-    tile_load<R, HELM, EX, EY, KP>(su, fr, Dr, iDr, a.u_mid, a.f, a.k2, a.pitch, ex0, ey0, N, h2);
+    E fr[R][KP][2], Dr[KP][2], iDr[KP][2];
+    tile_load<E, R, HELM, EX, EY, KP>(su, fr, Dr, iDr, a.u_mid, a.f, a.k2, a.pitch, ex0, ey0, N,
+                                      a.h * a.h);
     for (int i = tid; i < CX * CY; i += kTileThreads) {
         const int cy = i / CX, cx = i - cy * CX;
         const int I = cx0 + cx, J = cy0 + cy;
         const bool in = I >= 0 && I <= Nc && J >= 0 && J <= Nc;
 #pragma unroll
-        for (int r = 0; r < R; ++r) se[r][i] = in ? a.e_c[r][(size_t)J * a.pitch_c + I] : 0.0;
+        for (int r = 0; r < R; ++r) se[r][i] = in ? a.e_c[r][(size_t)J * a.pitch_c + I] : E(0);
     }
     __syncthreads();
 
@@ -327,12 +334,12 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_up(UpArgs a) {
             const bool ox = gx & 1, oy = gy & 1;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const double* e = se[r];
-                double v;
+                const E* e = se[r];
+                E v;
                 if (!ox && !oy) v = e[c];
-                else if (ox && !oy) v = 0.5 * (e[c] + e[c + 1]);
-                else if (!ox && oy) v = 0.5 * (e[c] + e[c + CX]);
-                else v = 0.25 * (e[c] + e[c + 1] + e[c + CX] + e[c + CX + 1]);
+                else if (ox && !oy) v = E(0.5) * (e[c] + e[c + 1]);
+                else if (!ox && oy) v = E(0.5) * (e[c] + e[c + CX]);
+                else v = E(0.25) * (e[c] + e[c + 1] + e[c + CX] + e[c + CX + 1]);
                 su[r][ly * EX + lx] += v;
             }
         }
@@ -341,7 +348,7 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_up(UpArgs a) {
 
     for (int s = 0; s < NU; ++s)
         for (int color = 0; color < 2; ++color) {
-            tile_sweep<R, HELM, EX, EY, KP>(su, fr, iDr, ex0, ey0, N, h2, color);
+            tile_sweep<E, R, HELM, EX, EY, KP>(su, fr, iDr, ex0, ey0, N, h2, color);
             __syncthreads();
         }
 
@@ -364,14 +371,15 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_up(UpArgs a) {
 
 // ---------------------------------------------------------------- coarse --
 
+template <typename E>
 struct CoarseArgs {
     int N;  // <= kCoarseMax
     double h;
     int pitch;
-    const double* f[2];
-    const double* u_init[2];  // nullptr: zero initial guess
-    const double* k2lev;      // Helmholtz: k2 of every level N..2, dense, concatenated
-    double* u_out[2];
+    const E* f[2];
+    const E* u_init[2];   // nullptr: zero initial guess
+    const double* k2lev;  // Helmholtz: k2 of every level N..2, dense, concatenated
+    E* u_out[2];
     int ncycles, nu1, nu2;
 };
 
@@ -382,12 +390,12 @@ constexpr int coarse_nodes() {
 }
 
 // Level operations with the level size as a compile-time constant.
-template <bool HELM, int n>
+template <typename E, bool HELM, int n>
 struct LdsLevel {
     static constexpr int W = n + 1;
     static constexpr int HALF = n / 2;  // nodes of one colour per interior row (upper bound)
 
-    static __device__ void smooth(double* u, const double* f, const double* k2, double h2, int nu) {
+    static __device__ void smooth(E* u, const E* f, const double* k2, E h2, int nu) {
         for (int s = 0; s < nu; ++s)
             for (int color = 0; color < 2; ++color) {
                 for (int i = threadIdx.x; i < (n - 1) * HALF; i += kCoarseThreads) {
@@ -395,55 +403,55 @@ struct LdsLevel {
                     const int a = 1 + ((1 + b + color) & 1) + 2 * (i - (b - 1) * HALF);
                     if (a > n - 1) continue;
                     const int l = b * W + a;
-                    const double nb = u[l - 1] + u[l + 1] + u[l - W] + u[l + W];
-                    u[l] = HELM ? (nb - h2 * f[l]) / (4.0 + h2 * k2[l]) : (nb - h2 * f[l]) * 0.25;
+                    const E nb = u[l - 1] + u[l + 1] + u[l - W] + u[l + W];
+                    u[l] = HELM ? (nb - h2 * f[l]) / (E(4) + h2 * (E)k2[l])
+                                : (nb - h2 * f[l]) * E(0.25);
                 }
                 __syncthreads();
             }
     }
 
-    static __device__ double resid(const double* u, const double* f, const double* k2,
-                                   double ih2, int l) {
-        double au = (u[l - 1] + u[l + 1] + u[l - W] + u[l + W] - 4.0 * u[l]) * ih2;
-        if (HELM) au -= k2[l] * u[l];
+    static __device__ E resid(const E* u, const E* f, const double* k2, E ih2, int l) {
+        E au = (u[l - 1] + u[l + 1] + u[l - W] + u[l + W] - E(4) * u[l]) * ih2;
+        if (HELM) au -= (E)k2[l] * u[l];
         return f[l] - au;
     }
 
     // f_c = full weighting of the residual; u_c = 0
-    static __device__ void restrict_to(const double* u, const double* f, const double* k2,
-                                       double ih2, double* uc, double* fc) {
+    static __device__ void restrict_to(const E* u, const E* f, const double* k2, E ih2, E* uc,
+                                       E* fc) {
         constexpr int nc = n / 2, Wc = nc + 1;
         for (int i = threadIdx.x; i < Wc * Wc; i += kCoarseThreads) {
             const int J = i / Wc, I = i - J * Wc;
-            double v = 0.0;
+            E v = E(0);
             if (I >= 1 && J >= 1 && I <= nc - 1 && J <= nc - 1) {
                 const int c = (2 * J) * W + 2 * I;
-                v = (4.0 * resid(u, f, k2, ih2, c) +
-                     2.0 * (resid(u, f, k2, ih2, c - 1) + resid(u, f, k2, ih2, c + 1) +
-                            resid(u, f, k2, ih2, c - W) + resid(u, f, k2, ih2, c + W)) +
+                v = (E(4) * resid(u, f, k2, ih2, c) +
+                     E(2) * (resid(u, f, k2, ih2, c - 1) + resid(u, f, k2, ih2, c + 1) +
+                             resid(u, f, k2, ih2, c - W) + resid(u, f, k2, ih2, c + W)) +
                      (resid(u, f, k2, ih2, c - W - 1) + resid(u, f, k2, ih2, c - W + 1) +
                       resid(u, f, k2, ih2, c + W - 1) + resid(u, f, k2, ih2, c + W + 1))) *
-                    (1.0 / 16.0);
+                    E(1.0 / 16.0);
             }
             fc[i] = v;
-            uc[i] = 0.0;
+            uc[i] = E(0);
         }
         __syncthreads();
     }
 
     // u += bilinear interpolation of the coarse correction uc
-    static __device__ void prolong_add(double* u, const double* uc) {
+    static __device__ void prolong_add(E* u, const E* uc) {
         constexpr int nc = n / 2, Wc = nc + 1;
         for (int i = threadIdx.x; i < W * W; i += kCoarseThreads) {
             const int y = i / W, x = i - y * W;
             if (x < 1 || y < 1 || x > n - 1 || y > n - 1) continue;
             const int c = (y >> 1) * Wc + (x >> 1);
             const bool ox = x & 1, oy = y & 1;
-            double v;
+            E v;
             if (!ox && !oy) v = uc[c];
-            else if (ox && !oy) v = 0.5 * (uc[c] + uc[c + 1]);
-            else if (!ox && oy) v = 0.5 * (uc[c] + uc[c + Wc]);
-            else v = 0.25 * (uc[c] + uc[c + 1] + uc[c + Wc] + uc[c + Wc + 1]);
+            else if (ox && !oy) v = E(0.5) * (uc[c] + uc[c + 1]);
+            else if (!ox && oy) v = E(0.5) * (uc[c] + uc[c + Wc]);
+            else v = E(0.25) * (uc[c] + uc[c + 1] + uc[c + Wc] + uc[c + Wc + 1]);
             u[i] += v;
         }
         __syncthreads();
@@ -451,22 +459,24 @@ struct LdsLevel {
 };
 
 // Level dispatch: runtime level size -> compile-time specialisation.
-template <bool HELM, typename Fn>
+template <typename E, bool HELM, typename Fn>
 __device__ __forceinline__ void with_level(int n, Fn&& fn) {
     switch (n) {
-        case 64: fn(LdsLevel<HELM, 64>{}); break;
-        case 32: fn(LdsLevel<HELM, 32>{}); break;
-        case 16: fn(LdsLevel<HELM, 16>{}); break;
-        case 8: fn(LdsLevel<HELM, 8>{}); break;
-        default: fn(LdsLevel<HELM, 4>{}); break;
+        case 64: fn(LdsLevel<E, HELM, 64>{}); break;
+        case 32: fn(LdsLevel<E, HELM, 32>{}); break;
+        case 16: fn(LdsLevel<E, HELM, 16>{}); break;
+        case 8: fn(LdsLevel<E, HELM, 8>{}); break;
+        default: fn(LdsLevel<E, HELM, 4>{}); break;
     }
 }
 
-template <bool HELM>
-__global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs a) {
+// All levels N <= 64 in one workgroup per right-hand side; the 2x2-cell grid
+// is solved exactly in double.
+template <typename E, bool HELM>
+__global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
     constexpr int TOT = coarse_nodes();
-    __shared__ double su[TOT];
-    __shared__ double sf[TOT];
+    __shared__ E su[TOT];
+    __shared__ E sf[TOT];
     __shared__ double sk[HELM ? TOT : 1];
     const int r = blockIdx.x;
     const int tid = threadIdx.x;
@@ -483,15 +493,15 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs a) {
     constexpr int kB = 8;
     const int nt = (N + 1) * (N + 1);
     for (int base = 0; base < nt; base += kB * kCoarseThreads) {
-        double uv[kB], fv[kB];
+        E uv[kB], fv[kB];
 #pragma unroll
         for (int b = 0; b < kB; ++b) {
             const int i = base + b * kCoarseThreads + tid;
             const int y = i / (N + 1), x = i - y * (N + 1);
             const bool ok = i < nt && x != 0 && y != 0 && x != N && y != N;
             const size_t g = ok ? (size_t)y * a.pitch + x : 0;
-            uv[b] = (ok && a.u_init[r]) ? a.u_init[r][g] : 0.0;
-            fv[b] = ok ? a.f[r][g] : 0.0;
+            uv[b] = (ok && a.u_init[r]) ? a.u_init[r][g] : E(0);
+            fv[b] = ok ? a.f[r][g] : E(0);
         }
 #pragma unroll
         for (int b = 0; b < kB; ++b) {
@@ -521,12 +531,12 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs a) {
     for (int cyc = 0; cyc < a.ncycles; ++cyc) {
         for (int l = 0; l < nl - 1; ++l) {
             const double hl = a.h * (double)(1 << l);
-            double* u = su + off[l];
-            double* f = sf + off[l];
+            E* u = su + off[l];
+            E* f = sf + off[l];
             const double* k2 = sk + (HELM ? off[l] : 0);
-            with_level<HELM>(Ns[l], [&](auto L) {
-                L.smooth(u, f, k2, hl * hl, a.nu1);
-                L.restrict_to(u, f, k2, 1.0 / (hl * hl), su + off[l + 1], sf + off[l + 1]);
+            with_level<E, HELM>(Ns[l], [&](auto L) {
+                L.smooth(u, f, k2, (E)(hl * hl), a.nu1);
+                L.restrict_to(u, f, k2, (E)(1.0 / (hl * hl)), su + off[l + 1], sf + off[l + 1]);
             });
         }
         if (tid == 0) {  // 2x2 cells: one unknown, four zero neighbours
@@ -534,15 +544,15 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs a) {
             const double hl = a.h * (double)(1 << l);
             const int c = 1 * 3 + 1;
             const double k2c = HELM ? sk[off[l] + c] : 0.0;
-            su[off[l] + c] = -sf[off[l] + c] / (4.0 / (hl * hl) + k2c);
+            su[off[l] + c] = (E)(-(double)sf[off[l] + c] / (4.0 / (hl * hl) + k2c));
         }
         __syncthreads();
         for (int l = nl - 2; l >= 0; --l) {
             const double hl = a.h * (double)(1 << l);
-            double* u = su + off[l];
-            with_level<HELM>(Ns[l], [&](auto L) {
+            E* u = su + off[l];
+            with_level<E, HELM>(Ns[l], [&](auto L) {
                 L.prolong_add(u, su + off[l + 1]);
-                L.smooth(u, sf + off[l], sk + (HELM ? off[l] : 0), hl * hl, a.nu2);
+                L.smooth(u, sf + off[l], sk + (HELM ? off[l] : 0), (E)(hl * hl), a.nu2);
             });
         }
     }
@@ -585,32 +595,41 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_k2(int N, int pitch,
 }
 
 // Residual norms of the current iterate over the same tiles as the down pass.
+// With r_out set (mixed form), the FP64 residual is also stored, rounded to
+// float, as the right-hand side of the FP32 error equation (boundary 0).
 template <int R, bool HELM>
 __global__ __launch_bounds__(kThreads) void k_resnorm(int N, double h, int pitch,
                                                       const double* u0, const double* u1,
                                                       const double* f0, const double* f1,
-                                                      const double* k2, double* part, int nblk) {
+                                                      const double* k2, double* part, int nblk,
+                                                      float* r0, float* r1, int pitch32) {
     __shared__ double red[(kThreads / 64) * 2 * R];
     const double ih2 = 1.0 / (h * h);
     const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
     const double* u[2] = {u0, u1};
     const double* f[2] = {f0, f1};
+    float* ro[2] = {r0, r1};
     double acc[2 * R];
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k) acc[k] = 0.0;
     for (int i = threadIdx.x; i < kTile * kTile; i += kThreads) {
         const int oy = i / kTile, ox = i - oy * kTile;
         const int gx = x0 + ox, gy = y0 + oy;
-        if (gx < 1 || gx > N - 1 || gy < 1 || gy > N - 1) continue;
+        if (gx > N - 1 || gy > N - 1) continue;
+        const bool interior = gx >= 1 && gy >= 1;
         const size_t g = (size_t)gy * pitch + gx;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const double* q = u[r];
-            double au = (q[g - 1] + q[g + 1] + q[g - pitch] + q[g + pitch] - 4.0 * q[g]) * ih2;
-            if (HELM) au -= k2[g] * q[g];
-            const double rr = f[r][g] - au;
-            acc[2 * r] += rr * rr;
-            acc[2 * r + 1] += f[r][g] * f[r][g];
+            double rr = 0.0;
+            if (interior) {
+                const double* q = u[r];
+                double au = (q[g - 1] + q[g + 1] + q[g - pitch] + q[g + pitch] - 4.0 * q[g]) * ih2;
+                if (HELM) au -= k2[g] * q[g];
+                rr = f[r][g] - au;
+                acc[2 * r] += rr * rr;
+                acc[2 * r + 1] += f[r][g] * f[r][g];
+            }
+            if (ro[0]) ro[r][(size_t)gy * pitch32 + gx] = (float)rr;
         }
     }
     block_sum<2 * R, kThreads>(acc, red);
@@ -619,6 +638,17 @@ __global__ __launch_bounds__(kThreads) void k_resnorm(int N, double h, int pitch
 #pragma unroll
         for (int k = 0; k < 2 * R; ++k) part[k * nblk + b] = acc[k];
     }
+}
+
+// Mixed form: u += e on the interior nodes (the FP32 correction added in FP64).
+__global__ void k_correct(int N, int pitch, int pitch32, double* __restrict__ u0,
+                          double* __restrict__ u1, const float* __restrict__ e0,
+                          const float* __restrict__ e1) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (a < 1 || a > N - 1 || b < 1 || b > N - 1) return;
+    u0[(size_t)b * pitch + a] += (double)e0[(size_t)b * pitch32 + a];
+    if (u1) u1[(size_t)b * pitch + a] += (double)e1[(size_t)b * pitch32 + a];
 }
 
 // out[s*4 + k] = sum_b part[s][k][b]: one block per (slot, k), fixed order.
@@ -651,140 +681,181 @@ __global__ void k_restrict_fw(const double* fine, int pf, double* coarse, int pc
 
 // ------------------------------------------------------------- dispatch --
 
-template <int R, bool HELM>
-void launch_down(const DownArgs& a, int nu, dim3 grid, hipStream_t s) {
+template <typename E, int R, bool HELM>
+void launch_down(const DownArgs<E>& a, int nu, dim3 grid, hipStream_t s) {
     switch (nu) {
-        case 1: hipLaunchKernelGGL((k_mg_down<R, HELM, 1, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_mg_down<R, HELM, 2, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_mg_down<R, HELM, 3, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_mg_down<E, R, HELM, 1, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_mg_down<E, R, HELM, 2, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_mg_down<E, R, HELM, 3, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
     }
 }
 
-template <int R, bool HELM>
-void launch_up(const UpArgs& a, int nu, dim3 grid, hipStream_t s) {
+template <typename E, int R, bool HELM>
+void launch_up(const UpArgs<E>& a, int nu, dim3 grid, hipStream_t s) {
     switch (nu) {
-        case 1: hipLaunchKernelGGL((k_mg_up<R, HELM, 1, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_mg_up<R, HELM, 2, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_mg_up<R, HELM, 3, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_mg_up<E, R, HELM, 1, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_mg_up<E, R, HELM, 2, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_mg_up<E, R, HELM, 3, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
     }
 }
 
-void down(int R, bool helm, const DownArgs& a, int nu, dim3 g, hipStream_t s) {
-    if (R == 1) helm ? launch_down<1, true>(a, nu, g, s) : launch_down<1, false>(a, nu, g, s);
-    else helm ? launch_down<2, true>(a, nu, g, s) : launch_down<2, false>(a, nu, g, s);
+template <typename E>
+void down(int R, bool helm, const DownArgs<E>& a, int nu, dim3 g, hipStream_t s) {
+    if (R == 1) helm ? launch_down<E, 1, true>(a, nu, g, s) : launch_down<E, 1, false>(a, nu, g, s);
+    else helm ? launch_down<E, 2, true>(a, nu, g, s) : launch_down<E, 2, false>(a, nu, g, s);
 }
 
-void up(int R, bool helm, const UpArgs& a, int nu, dim3 g, hipStream_t s) {
-    if (R == 1) helm ? launch_up<1, true>(a, nu, g, s) : launch_up<1, false>(a, nu, g, s);
-    else helm ? launch_up<2, true>(a, nu, g, s) : launch_up<2, false>(a, nu, g, s);
+template <typename E>
+void up(int R, bool helm, const UpArgs<E>& a, int nu, dim3 g, hipStream_t s) {
+    if (R == 1) helm ? launch_up<E, 1, true>(a, nu, g, s) : launch_up<E, 1, false>(a, nu, g, s);
+    else helm ? launch_up<E, 2, true>(a, nu, g, s) : launch_up<E, 2, false>(a, nu, g, s);
 }
 
 dim3 tiles(int N) { return dim3((N + kTile - 1) / kTile, (N + kTile - 1) / kTile); }
 
-// Level-0 arrays of the current solve.
-struct Fine {
-    double* u[2];
-    double* f[2];
+const char* type_name(double) { return "double"; }
+const char* type_name(float) { return "float"; }
+
+// Arrays of one solve: level 0 (u, f, k2) and the per-level buffers of type E.
+template <typename E>
+struct Hier {
+    E* u0[2];
+    E* f0[2];
     const double* k2;
 };
 
-// One V-cycle.  norm_slot >= 0 records the residual of the incoming iterate.
-void vcycle(wandqs_ctx* c, int R, bool helm, const Fine& fz, int norm_slot) {
+template <typename E> E* lev_u(wq::Level& L, int r);
+template <> double* lev_u<double>(wq::Level& L, int r) { return L.u[r]; }
+template <> float* lev_u<float>(wq::Level& L, int r) { return L.u32[r]; }
+template <typename E> E* lev_um(wq::Level& L, int r);
+template <> double* lev_um<double>(wq::Level& L, int r) { return L.um[r]; }
+template <> float* lev_um<float>(wq::Level& L, int r) { return L.um32[r]; }
+template <typename E> E* lev_f(wq::Level& L, int r);
+template <> double* lev_f<double>(wq::Level& L, int r) { return L.f[r]; }
+template <> float* lev_f<float>(wq::Level& L, int r) { return L.f32[r]; }
+
+// One V-cycle on levels 0..L.  zero_guess: the level-0 iterate starts from 0.
+// norm_slot >= 0 (double only) records the residual of the incoming iterate.
+template <typename E>
+void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess, int norm_slot) {
     hipStream_t s = c->stream;
     const int lc = c->lc;
-    auto lev_u = [&](int l, int r) { return l == 0 ? fz.u[r] : c->lev[l].u[r]; };
-    auto lev_f = [&](int l, int r) { return l == 0 ? fz.f[r] : (double*)c->lev[l].f[r]; };
-    auto lev_k = [&](int l) { return l == 0 ? fz.k2 : (const double*)c->lev[l].k2; };
+    const double eb = sizeof(E);
+    auto U = [&](int l, int r) { return l == 0 ? hz.u0[r] : lev_u<E>(c->lev[l], r); };
+    auto F = [&](int l, int r) { return l == 0 ? hz.f0[r] : lev_f<E>(c->lev[l], r); };
+    auto K = [&](int l) { return l == 0 ? hz.k2 : (const double*)c->lev[l].k2; };
     for (int l = 0; l < lc; ++l) {
-        const wq::Level& L = c->lev[l];
-        DownArgs a{};
+        wq::Level& L = c->lev[l];
+        DownArgs<E> a{};
         a.N = L.N;
         a.h = L.h;
         a.pitch = L.pitch;
         a.pitch_c = c->lev[l + 1].pitch;
         for (int r = 0; r < R; ++r) {
-            a.u_in[r] = l == 0 ? fz.u[r] : nullptr;
-            a.f[r] = lev_f(l, r);
-            a.u_out[r] = L.um[r];
-            a.f_c[r] = c->lev[l + 1].f[r];
+            a.u_in[r] = (l == 0 && !zero_guess) ? hz.u0[r] : nullptr;
+            a.f[r] = F(l, r);
+            a.u_out[r] = lev_um<E>(L, r);
+            a.f_c[r] = F(l + 1, r);
         }
-        a.k2 = helm ? lev_k(l) : nullptr;
+        a.k2 = helm ? K(l) : nullptr;
         const dim3 g = tiles(L.N);
         a.nblk = g.x * g.y;
         a.norm_part = (l == 0 && norm_slot >= 0)
                           ? c->norm_part + (size_t)norm_slot * 4 * c->max_tiles
                           : nullptr;
-        // algorithmic bytes per owned node: u (level 0 only), f, k2, smoothed u, coarse f
+        // algorithmic bytes per owned node: u (when read), f, k2, smoothed u, coarse f
         const double nodes = (double)L.N * L.N;
-        char nm[56];
-        std::snprintf(nm, sizeof nm, "k_mg_down<%d, %s, %d, 32>@%d", R,
+        char nm[64];
+        std::snprintf(nm, sizeof nm, "k_mg_down<%s, %d, %s, %d, 32>@%d", type_name(E()), R,
                       helm ? "true" : "false", c->cfg.nu_pre, L.N);
-        ProfScope ps(c, nm, nodes * ((l == 0 ? 8.0 * R : 0.0) + 8.0 * R + (helm ? 8.0 : 0.0) +
-                                     8.0 * R + 2.0 * R));
-        down(R, helm, a, c->cfg.nu_pre, g, s);
+        ProfScope ps(c, nm, nodes * ((a.u_in[0] ? eb * R : 0.0) + eb * R + (helm ? 8.0 : 0.0) +
+                                     eb * R + eb * R / 4));
+        down<E>(R, helm, a, c->cfg.nu_pre, g, s);
     }
     {
-        const wq::Level& L = c->lev[lc];
-        CoarseArgs a{};
+        wq::Level& L = c->lev[lc];
+        CoarseArgs<E> a{};
         a.N = L.N;
         a.h = L.h;
         a.pitch = L.pitch;
         for (int r = 0; r < R; ++r) {
-            a.f[r] = lev_f(lc, r);
-            a.u_init[r] = lc == 0 ? fz.u[r] : nullptr;
-            a.u_out[r] = lev_u(lc, r);
+            a.f[r] = F(lc, r);
+            a.u_init[r] = (lc == 0 && !zero_guess) ? hz.u0[r] : nullptr;
+            a.u_out[r] = U(lc, r);
         }
         a.k2lev = helm ? c->k2lev : nullptr;
         a.ncycles = 1;
         a.nu1 = c->cfg.nu_pre;
         a.nu2 = c->cfg.nu_post;
         const double nodes = (double)(L.N + 1) * (L.N + 1);
-        ProfScope ps(c, helm ? "k_mg_coarse<true>" : "k_mg_coarse<false>",
-                     nodes * (8.0 * R + (lc == 0 ? 8.0 * R : 0.0) + (helm ? 8.0 : 0.0) + 8.0 * R));
-        if (helm) hipLaunchKernelGGL(k_mg_coarse<true>, dim3(R), dim3(kCoarseThreads), 0, s, a);
-        else hipLaunchKernelGGL(k_mg_coarse<false>, dim3(R), dim3(kCoarseThreads), 0, s, a);
+        char nm[64];
+        std::snprintf(nm, sizeof nm, "k_mg_coarse<%s, %s>", type_name(E()), helm ? "true" : "false");
+        ProfScope ps(c, nm, nodes * (eb * R + (a.u_init[0] ? eb * R : 0.0) + (helm ? 8.0 : 0.0) + eb * R));
+        if (helm) hipLaunchKernelGGL((k_mg_coarse<E, true>), dim3(R), dim3(kCoarseThreads), 0, s, a);
+        else hipLaunchKernelGGL((k_mg_coarse<E, false>), dim3(R), dim3(kCoarseThreads), 0, s, a);
     }
     for (int l = lc - 1; l >= 0; --l) {
-        const wq::Level& L = c->lev[l];
-        UpArgs a{};
+        wq::Level& L = c->lev[l];
+        UpArgs<E> a{};
         a.N = L.N;
         a.h = L.h;
         a.pitch = L.pitch;
         a.pitch_c = c->lev[l + 1].pitch;
         for (int r = 0; r < R; ++r) {
-            a.u_mid[r] = L.um[r];
-            a.e_c[r] = c->lev[l + 1].u[r];
-            a.f[r] = lev_f(l, r);
-            a.u_out[r] = lev_u(l, r);
+            a.u_mid[r] = lev_um<E>(L, r);
+            a.e_c[r] = U(l + 1, r);
+            a.f[r] = F(l, r);
+            a.u_out[r] = U(l, r);
         }
-        a.k2 = helm ? lev_k(l) : nullptr;
+        a.k2 = helm ? K(l) : nullptr;
         // per owned node: smoothed u, coarse correction (1/4), f, k2, corrected u
         const double nodes = (double)L.N * L.N;
-        char nm[56];
-        std::snprintf(nm, sizeof nm, "k_mg_up<%d, %s, %d, 32>@%d", R,
+        char nm[64];
+        std::snprintf(nm, sizeof nm, "k_mg_up<%s, %d, %s, %d, 32>@%d", type_name(E()), R,
                       helm ? "true" : "false", c->cfg.nu_post, L.N);
-        ProfScope ps(c, nm, nodes * (8.0 * R + 2.0 * R + 8.0 * R + (helm ? 8.0 : 0.0) + 8.0 * R));
-        up(R, helm, a, c->cfg.nu_post, tiles(L.N), s);
+        ProfScope ps(c, nm, nodes * (eb * R + eb * R / 4 + eb * R + (helm ? 8.0 : 0.0) + eb * R));
+        up<E>(R, helm, a, c->cfg.nu_post, tiles(L.N), s);
     }
 }
 
-void resnorm(wandqs_ctx* c, int R, bool helm, const Fine& fz, int slot) {
+// FP64 residual norms of the level-0 iterate into `slot`; with r32 set the
+// residual is also stored in float (the mixed form's defect).
+void resnorm(wandqs_ctx* c, int R, bool helm, const Hier<double>& hz, int slot,
+             float* const* r32) {
     const wq::Level& L = c->lev[0];
     const dim3 g = tiles(L.N);
     double* part = c->norm_part + (size_t)slot * 4 * c->max_tiles;
     const int nblk = g.x * g.y;
-    const double* u1 = R > 1 ? fz.u[1] : nullptr;
-    const double* f1 = R > 1 ? fz.f[1] : nullptr;
+    const double* u1 = R > 1 ? hz.u0[1] : nullptr;
+    const double* f1 = R > 1 ? hz.f0[1] : nullptr;
+    float* o0 = r32 ? r32[0] : nullptr;
+    float* o1 = (r32 && R > 1) ? r32[1] : nullptr;
     char nm[56];
-    std::snprintf(nm, sizeof nm, "k_resnorm<%d, %s>", R, helm ? "true" : "false");
-    ProfScope ps(c, nm, (double)L.N * L.N * (16.0 * R + (helm ? 8.0 : 0.0)));
+    std::snprintf(nm, sizeof nm, "k_resnorm<%d, %s>%s", R, helm ? "true" : "false",
+                  r32 ? "+defect" : "");
+    ProfScope ps(c, nm, (double)L.N * L.N * (16.0 * R + (helm ? 8.0 : 0.0) + (r32 ? 4.0 * R : 0.0)));
     if (R == 1) {
-        if (helm) hipLaunchKernelGGL((k_resnorm<1, true>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, fz.u[0], u1, fz.f[0], f1, fz.k2, part, nblk);
-        else hipLaunchKernelGGL((k_resnorm<1, false>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, fz.u[0], u1, fz.f[0], f1, fz.k2, part, nblk);
+        if (helm) hipLaunchKernelGGL((k_resnorm<1, true>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch);
+        else hipLaunchKernelGGL((k_resnorm<1, false>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch);
     } else {
-        if (helm) hipLaunchKernelGGL((k_resnorm<2, true>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, fz.u[0], u1, fz.f[0], f1, fz.k2, part, nblk);
-        else hipLaunchKernelGGL((k_resnorm<2, false>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, fz.u[0], u1, fz.f[0], f1, fz.k2, part, nblk);
+        if (helm) hipLaunchKernelGGL((k_resnorm<2, true>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch);
+        else hipLaunchKernelGGL((k_resnorm<2, false>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch);
     }
+}
+
+// One outer iteration of the mixed form: defect r = f - A u in FP64 (stored in
+// float, norms recorded in `slot`), `inner` FP32 V-cycles on A e = r from e = 0,
+// then u += e in FP64.
+void mixed_iteration(wandqs_ctx* c, int R, bool helm, const Hier<double>& hz, int slot) {
+    wq::Level& L0 = c->lev[0];
+    Hier<float> hf{{L0.u32[0], L0.u32[1]}, {L0.f32[0], L0.f32[1]}, hz.k2};
+    resnorm(c, R, helm, hz, slot, hf.f0);
+    const int inner = c->cfg.mg_inner_cycles > 0 ? c->cfg.mg_inner_cycles : 1;
+    for (int i = 0; i < inner; ++i) vcycle<float>(c, R, helm, hf, i == 0, -1);
+    ProfScope ps(c, "k_correct", (double)L0.N * L0.N * 20.0 * R);
+    hipLaunchKernelGGL(k_correct, dim3((L0.N + 1 + 127) / 128, L0.N + 1), dim3(128), 0, c->stream,
+                       L0.N, L0.pitch, L0.pitch, hz.u0[0], R > 1 ? hz.u0[1] : nullptr, L0.u32[0],
+                       R > 1 ? L0.u32[1] : nullptr);
 }
 
 }  // namespace
@@ -799,8 +870,9 @@ void resnorm(wandqs_ctx* c, int R, bool helm, const Fine& fz, int slot) {
 wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const u[2],
                        double* const f[2], const double* k2, SolveResult* res) {
     hipStream_t s = c->stream;
-    Fine fz{{u[0], R > 1 ? u[1] : nullptr}, {f[0], R > 1 ? f[1] : nullptr}, k2};
-    if (helm) {  // k2 on the tile levels 1..lc (the coarse kernel restricts further itself)
+    Hier<double> hz{{u[0], R > 1 ? u[1] : nullptr}, {f[0], R > 1 ? f[1] : nullptr}, k2};
+    const bool mixed = c->cfg.precision == WANDQS_MIXED;
+    if (helm) {  // k2 on the tile levels 1..lc
         for (int l = 1; l <= c->lc; ++l) {
             const wq::Level& F = c->lev[l - 1];
             const wq::Level& C = c->lev[l];
@@ -809,8 +881,7 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
             hipLaunchKernelGGL(k_restrict_fw, dim3((C.N + 1 + 127) / 128, C.N + 1), dim3(128), 0, s,
                                src, F.pitch, C.k2, C.pitch, C.N);
         }
-    }
-    if (helm) {  // k2 of the coarse-kernel levels, once per solve
+        // k2 of the coarse-kernel levels, once per solve
         const wq::Level& T = c->lev[c->lc];
         const double* top = c->lc == 0 ? k2 : T.k2;
         int tot = 0;
@@ -819,31 +890,41 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
         hipLaunchKernelGGL(k_coarse_k2, dim3(1), dim3(kCoarseThreads), 0, s, T.N, T.pitch, top,
                            c->k2lev);
     }
+    // one "cycle" is a V-cycle (FP64) or an outer defect-correction iteration (mixed)
+    auto cycle = [&](int slot) {
+        if (mixed) mixed_iteration(c, R, helm, hz, slot);
+        else vcycle<double>(c, R, helm, hz, false, c->lc == 0 ? -1 : slot);
+    };
+    // the down pass records the incoming residual itself unless the top level is
+    // the coarse kernel (FP64) ; the mixed defect kernel always records it
+    const bool separate_norm = !mixed && c->lc == 0;
     const int maxc = c->cfg.mg_max_cycles;
     if (!(c->cfg.mg_rtol > 0.0)) {
-        for (int k = 0; k < maxc; ++k) vcycle(c, R, helm, fz, -1);
+        for (int k = 0; k < maxc; ++k) {
+            if (mixed) mixed_iteration(c, R, helm, hz, 0);
+            else vcycle<double>(c, R, helm, hz, false, -1);
+        }
         WQ_LAUNCH_CHECK();
         if (res) *res = SolveResult{maxc, {-1.0, -1.0}};
         return WANDQS_OK;
     }
     const int N = c->N;
     const double atol = c->cfg.mg_atol * std::sqrt((double)(N - 1) * (N - 1));
-    const bool top_is_coarse = c->lc == 0;
     const dim3 g = tiles(N);
     const int nblk = g.x * g.y;
     int done = 0;
     int pred = c->pred[kind] < 1 ? 1 : c->pred[kind];
     double* hr = c->h_pin;  // [kMaxSlots][4] + flags
-    if (top_is_coarse) resnorm(c, R, helm, fz, 0);
+    if (separate_norm) resnorm(c, R, helm, hz, 0, nullptr);
     while (true) {
         int b = done == 0 ? pred : 1;
         if (done + b > maxc) b = maxc - done;
         for (int k = 0; k < b; ++k) {
             const int cyc = done + k;
-            vcycle(c, R, helm, fz, top_is_coarse ? -1 : cyc);
-            if (top_is_coarse) resnorm(c, R, helm, fz, cyc + 1);
+            cycle(cyc);
+            if (separate_norm) resnorm(c, R, helm, hz, cyc + 1, nullptr);
         }
-        if (!top_is_coarse) resnorm(c, R, helm, fz, done + b);
+        if (!separate_norm) resnorm(c, R, helm, hz, done + b, nullptr);
         const int s0 = done == 0 ? 0 : done + 1;
         const int ns = done + b + 1 - s0;
         {

@@ -39,6 +39,11 @@ struct Level {
     double* um[2] = {nullptr, nullptr};  // pre-smoothed iterate written by the down pass
     double* f[2] = {nullptr, nullptr};   // right-hand side
     double* k2 = nullptr;                // Helmholtz coefficient (restricted)
+    // float buffers of the mixed form's inner cycles (level 0: error e, its
+    // pre-smoothed copy and the defect r)
+    float* u32[2] = {nullptr, nullptr};
+    float* um32[2] = {nullptr, nullptr};
+    float* f32[2] = {nullptr, nullptr};
 };
 
 enum SolveKind { kSolvePsi = 0, kSolveEB = 1, kSolveBperp = 2 };

@@ -49,7 +49,8 @@ class Config(C.Structure):
                 ("precision", C.c_int32), ("mg_rtol", C.c_double), ("mg_atol", C.c_double),
                 ("mg_max_cycles", C.c_int32), ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
                 ("n_beams", C.c_int32), ("beams", C.POINTER(Beam)), ("n_probes", C.c_int32),
-                ("probes", C.POINTER(Probe)), ("checkpoint_every", C.c_int32)]
+                ("probes", C.POINTER(Probe)), ("checkpoint_every", C.c_int32),
+                ("mg_inner_cycles", C.c_int32)]
 
 
 class KernelStat(C.Structure):
@@ -141,6 +142,7 @@ def make_config(cfg: dict):
     c.n_beams, c.beams = len(cfg["beams"]), beams
     c.n_probes, c.probes = len(cfg["probes"]), probes
     c.checkpoint_every = cfg.get("checkpoint_every", 0)
+    c.mg_inner_cycles = cfg.get("mg_inner_cycles", 0)
     return c, keep
 
 
