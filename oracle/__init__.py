@@ -179,6 +179,76 @@ class Oracle:
         return res
 
 
+def theta_of(cfg: dict) -> np.ndarray:
+    """Driver parameters in the adjoint's order: per beam, amp or the bin amplitudes."""
+    out = []
+    for b in cfg["beams"]:
+        out += [b["amp"]] if b["kind"] == "gauss" else list(np.asarray(b["bin_amp"], float))
+    return np.array(out, dtype=np.float64)
+
+
+def with_theta(cfg: dict, theta) -> dict:
+    """Copy of cfg with the driver parameters replaced by theta."""
+    import wandqs_inputs as wi
+    out = wi.scaled(cfg)
+    k = 0
+    for b in out["beams"]:
+        if b["kind"] == "gauss":
+            b["amp"] = float(theta[k])
+            k += 1
+        else:
+            n = len(b["bin_amp"])
+            b["bin_amp"] = np.array(theta[k:k + n], dtype=np.float64)
+            k += n
+    return out
+
+
+def _probe_array(cfg):
+    pr = cfg["probes"]
+    a = np.array([[p["field"], p["slice_begin"], p["slice_end"], p["r_max"], p.get("x0", 0.0),
+                   p.get("y0", 0.0)] for p in pr], dtype=np.float64).reshape(-1, 6)
+    return a
+
+
+def _slice_adjoint(self, state, fields, out_bar, Fbar=None):
+    """Reverse of one slice: state = its input particles, fields = its solved
+    fields; out_bar = adjoints (x, y, px, py) of its output particles.  Returns
+    (adjoints of the input particles, theta_bar)."""
+    x, y, px, py = (_f64(state[k]) for k in ("x", "y", "px", "py"))
+    xb, yb, pxb, pyb = (_f64(a).copy() for a in out_bar)
+    nth = lib().oracle_theta_count(C.byref(self.c))
+    tb = np.zeros(max(1, nth))
+    Fb = None if Fbar is None else _f64(Fbar).reshape(5, -1)
+    st = lib().oracle_slice_adjoint(C.byref(self.c), x.size, _p(x), _p(y), _p(px), _p(py),
+                                    _p(_f64(fields)), C.c_double(state["xi"]),
+                                    C.c_double(state["dxi"]), _p(xb), _p(yb), _p(pxb), _p(pyb),
+                                    _p(Fb), _p(tb))
+    return st, (xb, yb, pxb, pyb), tb[:nth]
+
+
+def _run_loss(self, state, n_slices, weights=None, grad=False):
+    """Loss of an n-slice run from `state` (probes of the config); with grad,
+    also dL/dtheta by the reverse sweep.  Advances `state`."""
+    pr = _probe_array(self.cfg)
+    w = np.ones(len(pr)) if weights is None else _f64(weights)
+    state["fields"] = _f64(state["fields"]).reshape(5, self.N + 1, self.N + 1)
+    xi = C.c_double(state["xi"])
+    dxi = C.c_double(state["dxi"])
+    loss = C.c_double(0.0)
+    nth = lib().oracle_theta_count(C.byref(self.c))
+    tb = np.zeros(max(1, nth)) if grad else None
+    st = lib().oracle_run_loss(C.byref(self.c), state["x"].size, _p(state["x"]), _p(state["y"]),
+                               _p(state["px"]), _p(state["py"]), _p(state["fields"]),
+                               C.byref(xi), C.byref(dxi), int(n_slices), len(pr), _p(pr),
+                               _p(w), C.byref(loss), _p(tb))
+    state["xi"], state["dxi"] = xi.value, dxi.value
+    return st, loss.value, (tb[:nth] if grad else None)
+
+
+Oracle.slice_adjoint = _slice_adjoint
+Oracle.run_loss = _run_loss
+
+
 def initial_state(cfg: dict) -> dict:
     """Cold plasma at rest at xi = 0 with zero fields (uses the shared input generator)."""
     import wandqs_inputs as wi

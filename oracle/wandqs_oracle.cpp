@@ -660,3 +660,443 @@ int oracle_run(const oracle_cfg* c, int P, double* x, double* y, double* px, dou
 }
 
 } /* extern "C" */
+
+/* =========================================================== adjoint == */
+/*
+ * Reverse mode of the discrete slice map above (discretise, then
+ * differentiate): given the adjoints of a slice's outputs (the particles at
+ * xi + dxi and the five fields at xi) it returns the adjoints of its inputs
+ * (the particles at xi) and adds the adjoint of the driver parameters theta.
+ * theta lists, beam by beam, the Gaussian amplitude or the radial-bin
+ * amplitudes.  The step dxi is treated as a constant; at the kinks of the
+ * map (cell crossings, wall reflections) the branch actually taken is
+ * differentiated.  The elliptic operators are symmetric, so every adjoint
+ * solve uses the same multigrid as the forward solves.
+ */
+namespace {
+
+struct CicW {
+    int a, b;
+    double dx, dy;
+};
+
+CicW cicw(const Grid& g, double x, double y) {
+    CicW w;
+    cic(g, x, w.a, w.dx);
+    cic(g, y, w.b, w.dy);
+    return w;
+}
+
+/* Value and x/y derivatives of the bilinear interpolant of F in the particle's cell. */
+void interp_grad(const Grid& g, const double* F, const CicW& w, double& v, double& vx, double& vy) {
+    const double f00 = F[g.id(w.a, w.b)], f10 = F[g.id(w.a + 1, w.b)];
+    const double f01 = F[g.id(w.a, w.b + 1)], f11 = F[g.id(w.a + 1, w.b + 1)];
+    v = f00 * (1 - w.dx) * (1 - w.dy) + f10 * w.dx * (1 - w.dy) + f01 * (1 - w.dx) * w.dy +
+        f11 * w.dx * w.dy;
+    vx = ((f10 - f00) * (1 - w.dy) + (f11 - f01) * w.dy) / g.h;
+    vy = ((f01 - f00) * (1 - w.dx) + (f11 - f10) * w.dx) / g.h;
+}
+
+/* Adjoint of gather: Fbar[corners] += s * weights. */
+void scatter(const Grid& g, double* Fbar, const CicW& w, double s) {
+    Fbar[g.id(w.a, w.b)] += s * (1 - w.dx) * (1 - w.dy);
+    Fbar[g.id(w.a + 1, w.b)] += s * w.dx * (1 - w.dy);
+    Fbar[g.id(w.a, w.b + 1)] += s * (1 - w.dx) * w.dy;
+    Fbar[g.id(w.a + 1, w.b + 1)] += s * w.dx * w.dy;
+}
+
+/* d(beam density)/d(theta_k) at one node and slice position, k over all params. */
+void beam_dtheta(const oracle_cfg& c, double x, double y, double xi, std::vector<double>& out) {
+    out.clear();
+    for (int k = 0; k < c.n_beams; ++k) {
+        const oracle_beam& B = c.beams[k];
+        double rx = x - B.x0, ry = y - B.y0;
+        double r2 = rx * rx + ry * ry;
+        double lz = (xi - B.xi_c) * (xi - B.xi_c) / (B.sigma_z * B.sigma_z);
+        if (B.kind == 0) {
+            out.push_back(xi < 0.0 ? 0.0 : std::exp(-r2 / (B.sigma_r * B.sigma_r) - lz));
+        } else {
+            double r = std::sqrt(r2);
+            double dr = B.r_max / B.n_bins;
+            int kb = (int)std::floor(r / dr);
+            for (int m = 0; m < B.n_bins; ++m)
+                out.push_back((xi >= 0.0 && r < B.r_max && kb == m) ? std::exp(-lz) : 0.0);
+        }
+    }
+}
+
+int theta_count(const oracle_cfg& c) {
+    int n = 0;
+    for (int k = 0; k < c.n_beams; ++k) n += c.beams[k].kind == 0 ? 1 : c.beams[k].n_bins;
+    return n;
+}
+
+/* Zero the boundary entries of a node adjoint (the boundary values are fixed). */
+void zero_boundary(const Grid& g, std::vector<double>& v) {
+    for (int b = 0; b <= g.N; ++b)
+        for (int a = 0; a <= g.N; ++a)
+            if (a == 0 || b == 0 || a == g.N || b == g.N) v[g.id(a, b)] = 0.0;
+}
+
+/* ubar of an interior node array from the adjoint of D_x u (or D_y u) given at
+ * interior nodes: D^T. */
+void add_Dx_T(const Grid& g, const std::vector<double>& dbar, std::vector<double>& ubar) {
+    for (int b = 1; b < g.N; ++b)
+        for (int a = 1; a < g.N; ++a) {
+            double s = dbar[g.id(a, b)] / (2.0 * g.h);
+            ubar[g.id(a + 1, b)] += s;
+            ubar[g.id(a - 1, b)] -= s;
+        }
+}
+void add_Dy_T(const Grid& g, const std::vector<double>& dbar, std::vector<double>& ubar) {
+    for (int b = 1; b < g.N; ++b)
+        for (int a = 1; a < g.N; ++a) {
+            double s = dbar[g.id(a, b)] / (2.0 * g.h);
+            ubar[g.id(a, b + 1)] += s;
+            ubar[g.id(a, b - 1)] -= s;
+        }
+}
+
+int adjoint_solve(const Grid& g, const oracle_cfg& c, const std::vector<double>* k2,
+                  std::vector<double> rhs, std::vector<double>& lam) {
+    zero_boundary(g, rhs);
+    lam.assign(g.nn(), 0.0);
+    int cyc;
+    double rel;
+    return mg_solve(g.N, g.h, k2 ? k2->data() : nullptr, rhs.data(), lam.data(), c.mg_rtol, c.mg_atol,
+                    c.mg_max_cycles, c.nu_pre, c.nu_post, &cyc, &rel);
+}
+
+} /* namespace */
+
+extern "C" {
+
+int oracle_theta_count(const oracle_cfg* c) { return theta_count(*c); }
+
+/* Reverse of one slice.  Inputs: the slice's input particles (x, y, px, py),
+ * its solved fields [5][nn], xi and dxi; xb, yb, pxb, pyb: adjoints of the
+ * output particles (overwritten with the adjoints of the input particles);
+ * Fbar [5][nn] (may be NULL): adjoints of the fields; theta_bar: accumulated. */
+int oracle_slice_adjoint(const oracle_cfg* c, int P, const double* x, const double* y,
+                         const double* px, const double* py, const double* fields, double xi,
+                         double dxi, double* xb, double* yb, double* pxb, double* pyb,
+                         const double* Fbar, double* theta_bar) {
+    Grid g(c->n_cells, c->half_width);
+    const int nn = g.nn();
+    const double* psi = fields;
+    const double* Ez = fields + nn;
+    const double* Bz = fields + 2 * nn;
+    const double* Bx = fields + 3 * nn;
+    const double* By = fields + 4 * nn;
+    const double wd = c->n0 * g.h * g.h / c->ppc / (g.h * g.h);  /* deposit weight per particle */
+    int status = ORC_OK;
+
+    /* forward quantities recomputed from the slice input */
+    std::vector<CicW> W(P);
+    std::vector<double> gi(P), vx(P), vy(P);
+    Moments m;
+    m.n.assign(nn, 0.0);
+    deposit(g, *c, P, x, y, nullptr, m.n.data());
+    for (int i = 0; i < P; ++i) {
+        W[i] = cicw(g, x[i], y[i]);
+        gi[i] = 1.0 + gather1(g, psi, x[i], y[i]);
+        vx[i] = px[i] / gi[i];
+        vy[i] = py[i] / gi[i];
+    }
+    {
+        std::vector<double> q(P);
+        m.jx.assign(nn, 0.0); deposit(g, *c, P, x, y, vx.data(), m.jx.data());
+        m.jy.assign(nn, 0.0); deposit(g, *c, P, x, y, vy.data(), m.jy.data());
+        for (int i = 0; i < P; ++i) q[i] = vx[i] * vx[i];
+        m.txx.assign(nn, 0.0); deposit(g, *c, P, x, y, q.data(), m.txx.data());
+        for (int i = 0; i < P; ++i) q[i] = vx[i] * vy[i];
+        m.txy.assign(nn, 0.0); deposit(g, *c, P, x, y, q.data(), m.txy.data());
+        for (int i = 0; i < P; ++i) q[i] = vy[i] * vy[i];
+        m.tyy.assign(nn, 0.0); deposit(g, *c, P, x, y, q.data(), m.tyy.data());
+    }
+    std::vector<double> k2, fBx, fBy, jz;
+    assemble(g, *c, xi, m, psi, Ez, Bz, k2, fBx, fBy, &jz);
+    std::vector<double> gxn, gyn;
+    psi_gradient(g, psi, gxn, gyn);
+
+    /* node adjoints */
+    std::vector<double> psib(nn, 0.0), Ezb(nn, 0.0), Bzb(nn, 0.0), Bxb(nn, 0.0), Byb(nn, 0.0);
+    std::vector<double> gxb(nn, 0.0), gyb(nn, 0.0), gib(P, 0.0);
+    if (Fbar) {
+        for (int i = 0; i < nn; ++i) {
+            psib[i] += Fbar[i];
+            Ezb[i] += Fbar[nn + i];
+            Bzb[i] += Fbar[2 * nn + i];
+            Bxb[i] += Fbar[3 * nn + i];
+            Byb[i] += Fbar[4 * nn + i];
+        }
+    }
+
+    /* --- 7. push, reversed per particle (fields frozen, dxi constant) */
+    for (int i = 0; i < P; ++i) {
+        const CicW& w = W[i];
+        double Gx, Gxx, Gxy, Gy, Gyx, Gyy, bx, bxx, bxy, by, byx, byy, bz, bzx, bzy;
+        interp_grad(g, gxn.data(), w, Gx, Gxx, Gxy);
+        interp_grad(g, gyn.data(), w, Gy, Gyx, Gyy);
+        interp_grad(g, Bx, w, bx, bxx, bxy);
+        interp_grad(g, By, w, by, byx, byy);
+        interp_grad(g, Bz, w, bz, bzx, bzy);
+        const double G_ = gi[i], p0x = px[i], p0y = py[i], d = dxi, L = g.L;
+        /* forward replay */
+        const double gam = (1.0 + p0x * p0x + p0y * p0y + G_ * G_) / (2.0 * G_);
+        const double Fx = gam * Gx / G_ - by, Fy = gam * Gy / G_ + bx;
+        const double mx = p0x + 0.5 * d * Fx, my = p0y + 0.5 * d * Fy;
+        const double t = bz * d / (2.0 * G_), s = 2.0 * t / (1.0 + t * t);
+        const double qx = mx - t * my, qy = my + t * mx;
+        const double rx = mx - s * qy, ry = my + s * qx;
+        const double p1x = rx + 0.5 * d * Fx, p1y = ry + 0.5 * d * Fy;
+        const double x1 = x[i] + d * p1x / G_, y1 = y[i] + d * p1y / G_;
+        /* reverse */
+        double x1b = xb[i], y1b = yb[i], p1xb = pxb[i], p1yb = pyb[i];
+        if (x1 > L || x1 < -L) { x1b = -x1b; p1xb = -p1xb; }
+        if (y1 > L || y1 < -L) { y1b = -y1b; p1yb = -p1yb; }
+        double xbar = x1b, ybar = y1b, gb = 0.0;
+        p1xb += x1b * d / G_;
+        p1yb += y1b * d / G_;
+        gb += -(x1b * d * p1x + y1b * d * p1y) / (G_ * G_);
+        double rxb = p1xb, ryb = p1yb, Fxb = 0.5 * d * p1xb, Fyb = 0.5 * d * p1yb;
+        double mxb = rxb, myb = ryb, sb = -rxb * qy + ryb * qx;
+        double qyb = -rxb * s, qxb = ryb * s;
+        mxb += qxb + qyb * t;
+        myb += -qxb * t + qyb;
+        double tb = -qxb * my + qyb * mx;
+        tb += sb * 2.0 * (1.0 - t * t) / ((1.0 + t * t) * (1.0 + t * t));
+        double bzb = tb * d / (2.0 * G_);
+        gb += -tb * bz * d / (2.0 * G_ * G_);
+        double p0xb = mxb, p0yb = myb;
+        Fxb += 0.5 * d * mxb;
+        Fyb += 0.5 * d * myb;
+        double gamb = Fxb * Gx / G_ + Fyb * Gy / G_;
+        double Gxb = Fxb * gam / G_, Gyb = Fyb * gam / G_;
+        gb += -(Fxb * gam * Gx + Fyb * gam * Gy) / (G_ * G_);
+        double byb = -Fxb, bxb = Fyb;
+        p0xb += gamb * p0x / G_;
+        p0yb += gamb * p0y / G_;
+        gb += gamb * (G_ * G_ - 1.0 - p0x * p0x - p0y * p0y) / (2.0 * G_ * G_);
+        /* gathers of grad psi and B: node adjoints and position derivatives */
+        scatter(g, gxb.data(), w, Gxb);
+        scatter(g, gyb.data(), w, Gyb);
+        scatter(g, Bxb.data(), w, bxb);
+        scatter(g, Byb.data(), w, byb);
+        scatter(g, Bzb.data(), w, bzb);
+        xbar += Gxb * Gxx + Gyb * Gyx + bxb * bxx + byb * byx + bzb * bzx;
+        ybar += Gxb * Gxy + Gyb * Gyy + bxb * bxy + byb * byy + bzb * bzy;
+        xb[i] = xbar;
+        yb[i] = ybar;
+        pxb[i] = p0xb;
+        pyb[i] = p0yb;
+        gib[i] = gb;
+    }
+    /* node gradient of psi (central inside, one-sided on the boundary), reversed */
+    for (int b = 0; b <= g.N; ++b)
+        for (int a = 0; a <= g.N; ++a) {
+            double sx = gxb[g.id(a, b)], sy = gyb[g.id(a, b)];
+            if (a == 0) { psib[g.id(1, b)] += sx / g.h; psib[g.id(0, b)] -= sx / g.h; }
+            else if (a == g.N) { psib[g.id(g.N, b)] += sx / g.h; psib[g.id(g.N - 1, b)] -= sx / g.h; }
+            else { psib[g.id(a + 1, b)] += sx / (2 * g.h); psib[g.id(a - 1, b)] -= sx / (2 * g.h); }
+            if (b == 0) { psib[g.id(a, 1)] += sy / g.h; psib[g.id(a, 0)] -= sy / g.h; }
+            else if (b == g.N) { psib[g.id(a, g.N)] += sy / g.h; psib[g.id(a, g.N - 1)] -= sy / g.h; }
+            else { psib[g.id(a, b + 1)] += sy / (2 * g.h); psib[g.id(a, b - 1)] -= sy / (2 * g.h); }
+        }
+
+    /* --- 6. B_perp Helmholtz solves: lambda = (L_h - k2)^-1 Bbar, k2bar = lambda B */
+    std::vector<double> lx, ly;
+    if (adjoint_solve(g, *c, &k2, Bxb, lx) != ORC_OK) status = ORC_NOCONV;
+    if (adjoint_solve(g, *c, &k2, Byb, ly) != ORC_OK) status = ORC_NOCONV;
+
+    /* --- 5. assembly reversed (f_Bx = lx, f_By = ly, k2bar) */
+    std::vector<double> nb(nn, 0.0), jxb(nn, 0.0), jyb(nn, 0.0), txxb(nn, 0.0), txyb(nn, 0.0),
+        tyyb(nn, 0.0), jzb(nn, 0.0), psxb(nn, 0.0), psyb(nn, 0.0);
+    for (int b = 1; b < g.N; ++b)
+        for (int a = 1; a < g.N; ++a) {
+            const int i = g.id(a, b);
+            const double Lxb = lx[i], Lyb = ly[i];
+            const double s = 1.0 / (2.0 * g.h);
+            /* D_y(j_z - Tyy) - D_x Txy  and  D_x(Txx - j_z) + D_y Txy */
+            jzb[g.id(a, b + 1)] += Lxb * s; jzb[g.id(a, b - 1)] -= Lxb * s;
+            tyyb[g.id(a, b + 1)] -= Lxb * s; tyyb[g.id(a, b - 1)] += Lxb * s;
+            txyb[g.id(a + 1, b)] -= Lxb * s; txyb[g.id(a - 1, b)] += Lxb * s;
+            txxb[g.id(a + 1, b)] += Lyb * s; txxb[g.id(a - 1, b)] -= Lyb * s;
+            jzb[g.id(a + 1, b)] -= Lyb * s; jzb[g.id(a - 1, b)] += Lyb * s;
+            txyb[g.id(a, b + 1)] += Lyb * s; txyb[g.id(a, b - 1)] -= Lyb * s;
+            if (!(m.n[i] > 0.0)) continue;
+            const double gg = 1.0 + psi[i], n = m.n[i];
+            const double G = (n * (1.0 + gg * gg) + gg * gg * (m.txx[i] + m.tyy[i])) / (2.0 * gg);
+            const double psx = Dx(g, psi, a, b), psy = Dy(g, psi, a, b);
+            const double jx_ = m.jx[i], jy_ = m.jy[i], Txx = m.txx[i], Txy = m.txy[i], Tyy = m.tyy[i];
+            jxb[i] += (Lxb * Bz[i] + Lyb * Ez[i]) / gg;
+            jyb[i] += (-Lxb * Ez[i] + Lyb * Bz[i]) / gg;
+            Bzb[i] += (Lxb * jx_ + Lyb * jy_) / gg;
+            Ezb[i] += (-Lxb * jy_ + Lyb * jx_) / gg;
+            double Gb = (Lxb * psy - Lyb * psx) / (gg * gg);
+            tyyb[i] += -Lxb * psy / gg;
+            txxb[i] += Lyb * psx / gg;
+            txyb[i] += (-Lxb * psx + Lyb * psy) / gg;
+            psxb[i] += -Lxb * Txy / gg - Lyb * (G / (gg * gg) - Txx / gg);
+            psyb[i] += Lxb * (G / (gg * gg) - Tyy / gg) + Lyb * Txy / gg;
+            double ggb = Lxb * (-(jx_ * Bz[i] - jy_ * Ez[i]) / (gg * gg) +
+                                (-2.0 * G / (gg * gg * gg) + Tyy / (gg * gg)) * psy +
+                                (Txy / (gg * gg)) * psx) +
+                         Lyb * (-(jy_ * Bz[i] + jx_ * Ez[i]) / (gg * gg) -
+                                (-2.0 * G / (gg * gg * gg) + Txx / (gg * gg)) * psx -
+                                (Txy / (gg * gg)) * psy);
+            /* k2 = n / g with k2bar = lx Bx + ly By */
+            const double k2b = lx[i] * Bx[i] + ly[i] * By[i];
+            nb[i] += k2b / gg;
+            ggb += -k2b * n / (gg * gg);
+            /* G = [n (1 + g^2) + g^2 (Txx + Tyy)] / (2g) */
+            nb[i] += Gb * (1.0 + gg * gg) / (2.0 * gg);
+            txxb[i] += Gb * gg / 2.0;
+            tyyb[i] += Gb * gg / 2.0;
+            ggb += Gb * (n * (gg * gg - 1.0) / (2.0 * gg * gg) + (Txx + Tyy) / 2.0);
+            psib[i] += ggb;
+        }
+    add_Dx_T(g, psxb, psib);
+    add_Dy_T(g, psyb, psib);
+    /* j_z = G/g - n* + n_b(theta) on every node (plasma part where n* > 0) */
+    {
+        std::vector<double> dth;
+        const int nth = theta_count(*c);
+        for (int b = 0; b <= g.N; ++b)
+            for (int a = 0; a <= g.N; ++a) {
+                const int i = g.id(a, b);
+                const double s = jzb[i];
+                if (s == 0.0) continue;
+                if (m.n[i] > 0.0) {
+                    const double gg = 1.0 + psi[i], n = m.n[i];
+                    nb[i] += s * (1.0 - gg * gg) / (2.0 * gg * gg);
+                    txxb[i] += s * 0.5;
+                    tyyb[i] += s * 0.5;
+                    psib[i] += -s * n / (gg * gg * gg);
+                }
+                beam_dtheta(*c, g.xa(a), g.xa(b), xi, dth);
+                for (int k = 0; k < nth; ++k) theta_bar[k] += s * dth[k];
+            }
+    }
+
+    /* --- 4. Ez, Bz Poisson solves reversed */
+    std::vector<double> lE, lB;
+    if (adjoint_solve(g, *c, nullptr, Ezb, lE) != ORC_OK) status = ORC_NOCONV;
+    if (adjoint_solve(g, *c, nullptr, Bzb, lB) != ORC_OK) status = ORC_NOCONV;
+    {   /* f_Ez = -(Dx jx + Dy jy), f_Bz = Dx jy - Dy jx */
+        std::vector<double> t(nn);
+        for (int i = 0; i < nn; ++i) t[i] = -lE[i];
+        add_Dx_T(g, t, jxb);
+        add_Dy_T(g, t, jyb);
+        add_Dx_T(g, lB, jyb);
+        for (int i = 0; i < nn; ++i) t[i] = -lB[i];
+        add_Dy_T(g, t, jxb);
+    }
+
+    /* --- 3. deposits of j and T reversed, then g_i = 1 + gather(psi) */
+    for (int i = 0; i < P; ++i) {
+        const CicW& w = W[i];
+        double v, dvx, dvy;
+        const double q[5] = {vx[i], vy[i], vx[i] * vx[i], vx[i] * vy[i], vy[i] * vy[i]};
+        const std::vector<double>* A[5] = {&jxb, &jyb, &txxb, &txyb, &tyyb};
+        double qb[5];
+        double xbar = 0.0, ybar = 0.0;
+        for (int k = 0; k < 5; ++k) {
+            interp_grad(g, A[k]->data(), w, v, dvx, dvy);
+            qb[k] = wd * v;
+            xbar += wd * q[k] * dvx;
+            ybar += wd * q[k] * dvy;
+        }
+        const double vxb = qb[0] + 2.0 * vx[i] * qb[2] + vy[i] * qb[3];
+        const double vyb = qb[1] + vx[i] * qb[3] + 2.0 * vy[i] * qb[4];
+        pxb[i] += vxb / gi[i];
+        pyb[i] += vyb / gi[i];
+        const double gb = gib[i] - (vxb * vx[i] + vyb * vy[i]) / gi[i];
+        double pv, pvx, pvy;
+        interp_grad(g, psi, w, pv, pvx, pvy);
+        scatter(g, psib.data(), w, gb);
+        xbar += gb * pvx;
+        ybar += gb * pvy;
+        xb[i] += xbar;
+        yb[i] += ybar;
+    }
+
+    /* --- 2. psi solve reversed: f_psi = n* - n0 on interior nodes */
+    std::vector<double> lpsi;
+    if (adjoint_solve(g, *c, nullptr, psib, lpsi) != ORC_OK) status = ORC_NOCONV;
+    for (int b = 1; b < g.N; ++b)
+        for (int a = 1; a < g.N; ++a) nb[g.id(a, b)] += lpsi[g.id(a, b)];
+
+    /* --- 1. deposit of n* reversed (positions only) */
+    for (int i = 0; i < P; ++i) {
+        double v, dvx, dvy;
+        interp_grad(g, nb.data(), W[i], v, dvx, dvy);
+        xb[i] += wd * dvx;
+        yb[i] += wd * dvy;
+    }
+    return status;
+}
+
+/* Loss of a run: L = sum_k w_k * probe_k, probe_k = mean over the slices
+ * [s0_k, s1_k) of the mean of field f_k over the nodes within r_k of (x0_k, y0_k).
+ * probes: [n_probes][6] = field, s0, s1, r, x0, y0 (as doubles).  With
+ * theta_bar non-NULL the reverse sweep runs too (all slice states are kept). */
+int oracle_run_loss(const oracle_cfg* c, int P, double* x, double* y, double* px, double* py,
+                    double* fields, double* xi, double* dxi, int n_slices, int n_probes,
+                    const double* probes, const double* weights, double* loss,
+                    double* theta_bar) {
+    Grid g(c->n_cells, c->half_width);
+    const int nn = g.nn();
+    struct Rec { std::vector<double> x, y, px, py, F; double xi, dxi; };
+    std::vector<Rec> tape;
+    double Ls = 0.0;
+    int status = ORC_OK;
+    auto disc = [&](int k, std::vector<int>& nodes) {
+        const double* p = probes + 6 * k;
+        nodes.clear();
+        for (int b = 0; b <= g.N; ++b)
+            for (int a = 0; a <= g.N; ++a) {
+                double rx = g.xa(a) - p[4], ry = g.xa(b) - p[5];
+                if (rx * rx + ry * ry <= p[3] * p[3]) nodes.push_back(g.id(a, b));
+            }
+    };
+    std::vector<int> nodes;
+    for (int j = 0; j < n_slices; ++j) {
+        if (theta_bar)
+            tape.push_back(Rec{std::vector<double>(x, x + P), std::vector<double>(y, y + P),
+                               std::vector<double>(px, px + P), std::vector<double>(py, py + P),
+                               {}, *xi, *dxi});
+        oracle_info inf;
+        int st = oracle_slice_step(c, P, x, y, px, py, nullptr, fields, xi, dxi, &inf, nullptr, nullptr);
+        if (st != ORC_OK) status = st;
+        if (theta_bar) tape.back().F.assign(fields, fields + 5 * nn);
+        for (int k = 0; k < n_probes; ++k) {
+            const double* p = probes + 6 * k;
+            if (j < (int)p[1] || j >= (int)p[2]) continue;
+            disc(k, nodes);
+            double s = 0.0;
+            for (int i : nodes) s += fields[(int)p[0] * nn + i];
+            if (!nodes.empty()) Ls += weights[k] * s / nodes.size() / (p[2] - p[1]);
+        }
+    }
+    *loss = Ls;
+    if (!theta_bar || status != ORC_OK) return status;
+    std::vector<double> xb(P, 0.0), yb(P, 0.0), pxb(P, 0.0), pyb(P, 0.0), Fb(5 * nn);
+    for (int j = n_slices - 1; j >= 0; --j) {
+        std::fill(Fb.begin(), Fb.end(), 0.0);
+        for (int k = 0; k < n_probes; ++k) {
+            const double* p = probes + 6 * k;
+            if (j < (int)p[1] || j >= (int)p[2]) continue;
+            disc(k, nodes);
+            for (int i : nodes) Fb[(int)p[0] * nn + i] += weights[k] / nodes.size() / (p[2] - p[1]);
+        }
+        const Rec& r = tape[j];
+        int st = oracle_slice_adjoint(c, P, r.x.data(), r.y.data(), r.px.data(), r.py.data(),
+                                      r.F.data(), r.xi, r.dxi, xb.data(), yb.data(), pxb.data(),
+                                      pyb.data(), Fb.data(), theta_bar);
+        if (st != ORC_OK) status = st;
+    }
+    return status;
+}
+
+} /* extern "C" */
