@@ -90,7 +90,8 @@ typedef struct {
     int32_t adaptive;    /* 1: Step_Size_Refinement, 0: fixed dxi0 */
     int32_t refine_k;    /* floor dxi >= dxi0 / k; 0 = no floor */
     int32_t precision;   /* wandqs_precision */
-    double mg_rtol;      /* stop when ||r|| <= rtol ||f|| + atol sqrt(n) (n interior nodes) or
+    double mg_rtol;      /* stop when ||r|| <= rtol ||f|| + atol sqrt(n) (n interior nodes;
+                            ||r_0|| in place of ||f|| when f = 0) or
                             at the rounding floor: a cycle that no longer halves ||r|| once
                             ||r|| <= 1e-9 max(||f||, ||r_0||); rtol <= 0: exactly
                             mg_max_cycles V-cycles, no host syncs */
@@ -101,7 +102,10 @@ typedef struct {
     const wandqs_beam* beams;
     int32_t n_probes;      /* 0 .. 16 */
     const wandqs_probe* probes;
-    int32_t checkpoint_every; /* K for the adjoint tape; 0 = no tape */
+    int32_t checkpoint_every; /* K > 0: keep the adjoint tape (a checkpoint of the
+                                 state before every K-th slice since init or
+                                 set_state, up to the n_slices given at init, plus
+                                 K recompute slots); 0 = no tape */
     int32_t mg_inner_cycles;  /* WANDQS_MIXED: FP32 V-cycles per FP64 defect correction
                                  (0: 1, the fastest measured at C5).  The mixed form keeps the residual, the
                                  correction sum u += e and the coarsest (2x2) solve in
@@ -120,7 +124,10 @@ typedef struct {
 } wandqs_slice_info;
 
 /* Bytes of device workspace needed for cfg and runs of up to n_slices slices
- * per wandqs_run call (n_slices >= 1; it sizes the per-slice record buffer). */
+ * per wandqs_run call (n_slices >= 1; it sizes the per-slice record buffer and,
+ * with checkpoint_every = K > 0, the adjoint tape: ceil(n_slices/K) + 1
+ * checkpoints of the particles and two field sets, K slots of one slice's
+ * particles, fields and moments, and the adjoint work arrays). */
 wandqs_status wandqs_workspace_bytes(const wandqs_config* cfg, int32_t n_slices, size_t* bytes);
 
 /* Validate cfg, bind the caller's workspace (d_workspace, >= 256-byte aligned,
@@ -190,6 +197,41 @@ wandqs_status wandqs_profile(wandqs_ctx* ctx, int32_t enable);
  * kernel groups; synchronises the stream. */
 wandqs_status wandqs_profile_stats(wandqs_ctx* ctx, wandqs_kernel_stat* h_out, int32_t max,
                                    int32_t* h_n);
+
+/* Reverse-mode gradient of a loss through every slice run since init or the
+ * last wandqs_set_state (discretise-then-differentiate adjoint of the slice map
+ * of Sec. III and Algorithm 1; the step dxi is held at its forward values and at
+ * cell crossings and wall reflections the branch taken is differentiated).
+ * Needs checkpoint_every = K > 0 at init.  Each K-slice segment, last first, is
+ * recomputed from its checkpoint (bit-identical to the forward) and then
+ * reversed slice by slice; every adjoint elliptic solve is a multigrid solve
+ * with the context's mg_* settings.
+ *   h_dL_dprobe      host [n_probes] or NULL: dL/d(probe value) of the last
+ *                    wandqs_run call (its probes' slice windows are relative to
+ *                    that call's first slice)
+ *   d_dL_dfields     device [S][5][N+1][N+1] or NULL: dL/d(fields of tape slice
+ *                    j) for the S = wandqs_tape_slices slices (boundary entries
+ *                    are ignored: the boundary values are fixed)
+ *   d_dL_dparticles  device [4][P] or NULL: dL/d(final particles x, y, px, py),
+ *                    particle-ID order
+ *   h_dL_dtheta      host [wandqs_num_theta] or NULL (out): dL/dtheta, theta =
+ *                    for each beam in order its amp (GAUSS) or its bin_amp[]
+ *                    (RADIAL_BINS)
+ *   d_dL_dparticles0 device [4][P] or NULL (out): dL/d(particles at the tape
+ *                    start), particle-ID order
+ * The state (particles, fields, xi) is the same after the call as before.
+ * Synchronises the stream.  WANDQS_E_STATE without a tape, after
+ * wandqs_mg_solve, past the tape capacity (more slices than n_slices at init) or
+ * when probe adjoints are given but no wandqs_run has completed. */
+wandqs_status wandqs_backward(wandqs_ctx* ctx, const double* h_dL_dprobe,
+                              const double* d_dL_dfields, const double* d_dL_dparticles,
+                              double* h_dL_dtheta, double* d_dL_dparticles0);
+
+/* Number of driver parameters theta (0 for NULL). */
+int32_t wandqs_num_theta(const wandqs_ctx* ctx);
+
+/* Slices on the adjoint tape (-1 without a usable tape). */
+int64_t wandqs_tape_slices(const wandqs_ctx* ctx);
 
 /* Number of plasma macroparticles P of the context (0 for NULL). */
 int64_t wandqs_num_particles(const wandqs_ctx* ctx);

@@ -272,9 +272,10 @@ int mg_solve(int N, double h, const double* k2, const double* f, double* u, doub
     }
     std::vector<double> r;
     const double fnorm = norm2_interior(top, top.f);
-    const double tol = rtol * fnorm + atol * std::sqrt((double)(N - 1) * (N - 1));
     residual(top, r);
     double rn = norm2_interior(top, r), rprev = rn;
+    /* relative to ||f||; for f = 0 (solution 0) relative to the initial residual */
+    const double tol = rtol * (fnorm > 0 ? fnorm : rn) + atol * std::sqrt((double)(N - 1) * (N - 1));
     const double scale = std::max(fnorm, rn);
     int c = 0, status = ORC_NOCONV;
     if (rn <= tol) status = ORC_OK;

@@ -2,8 +2,10 @@
 // initialisation and the slice loop (WAND-PIC Algorithm 1, inner xi loop).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 #include <new>
 #include <string>
 
@@ -101,6 +103,23 @@ void set_sizes(wandqs_ctx* c, const wandqs_config* cfg, int32_t n_slices) {
     c->n_scan_blocks = (c->N * c->N + 2047) / 2048;
     c->rec_cap = n_slices;
     c->n_bins_total = total_bins(cfg);
+    c->n_bin_beams = 0;
+    c->n_theta = 0;
+    c->n_seg_cap = 0;
+    const int nn = (c->N + 1) * (c->N + 1);
+    const int segs_all = (nn + wq::kThetaSeg - 1) / wq::kThetaSeg;
+    for (int k = 0; k < cfg->n_beams; ++k) {
+        if (cfg->beams[k].kind == WANDQS_BEAM_RADIAL_BINS) {
+            ++c->n_bin_beams;
+            c->n_theta += cfg->beams[k].n_bins;
+            c->n_seg_cap += cfg->beams[k].n_bins + segs_all;
+        } else {
+            ++c->n_theta;
+            c->n_seg_cap += segs_all;
+        }
+    }
+    c->tape_K = cfg->checkpoint_every;
+    c->n_ckpt = c->tape_K > 0 ? (n_slices + c->tape_K - 1) / c->tape_K + 1 : 0;
 }
 
 wandqs_status fail(wandqs_ctx* c, wandqs_status s) {
@@ -108,15 +127,76 @@ wandqs_status fail(wandqs_ctx* c, wandqs_status s) {
     return s;
 }
 
-// One slice (Algorithm 1 inner loop body).
-wandqs_status do_slice(wandqs_ctx* c, int rec_slot, int64_t probe_slice) {
+size_t node_bytes(const wandqs_ctx* c) {
+    return sizeof(double) * (size_t)(c->N + 1) * c->lev[0].pitch;
+}
+
+// Checkpoint of the slice-loop state: particles (storage order), the fields
+// and the previous slice's fields (initial guesses), [xi, dxi, xi_u, xi_prev],
+// the batch predictions and the extrapolation count.  A recompute from it
+// repeats the same arithmetic, bit for bit.
+wandqs_status save_checkpoint(wandqs_ctx* c, wq::Checkpoint& k) {
+    using namespace wq;
+    wandqs_status s;
+    const size_t pb = sizeof(double) * (size_t)c->P, nb = node_bytes(c);
+    for (int q = 0; q < 4; ++q)
+        if ((s = copy_d2d(c, k.pa[q], c->pa[c->cur][q], pb)) != WANDQS_OK) return s;
+    if ((s = copy_d2d(c, k.pid, c->pid[c->cur], sizeof(int32_t) * (size_t)c->P)) != WANDQS_OK) return s;
+    for (int q = 0; q < 5; ++q) {
+        if ((s = copy_d2d(c, k.fields[q], c->fields[q], nb)) != WANDQS_OK) return s;
+        if ((s = copy_d2d(c, k.fields_prev[q], c->fields_prev[q], nb)) != WANDQS_OK) return s;
+    }
+    if ((s = copy_d2d(c, k.st, c->st, 4 * sizeof(double))) != WANDQS_OK) return s;
+    std::memcpy(k.pred, c->pred, sizeof(k.pred));
+    k.n_guess = c->n_guess;
+    return WANDQS_OK;
+}
+
+wandqs_status restore_checkpoint(wandqs_ctx* c, const wq::Checkpoint& k) {
+    using namespace wq;
+    wandqs_status s;
+    const size_t pb = sizeof(double) * (size_t)c->P, nb = node_bytes(c);
+    for (int q = 0; q < 4; ++q)
+        if ((s = copy_d2d(c, c->pa[c->cur][q], k.pa[q], pb)) != WANDQS_OK) return s;
+    if ((s = copy_d2d(c, c->pid[c->cur], k.pid, sizeof(int32_t) * (size_t)c->P)) != WANDQS_OK) return s;
+    for (int q = 0; q < 5; ++q) {
+        if ((s = copy_d2d(c, c->fields[q], k.fields[q], nb)) != WANDQS_OK) return s;
+        if ((s = copy_d2d(c, c->fields_prev[q], k.fields_prev[q], nb)) != WANDQS_OK) return s;
+    }
+    if ((s = copy_d2d(c, c->st, k.st, 4 * sizeof(double))) != WANDQS_OK) return s;
+    std::memcpy(c->pred, k.pred, sizeof(k.pred));
+    c->n_guess = k.n_guess;
+    return WANDQS_OK;
+}
+
+// One slice (Algorithm 1 inner loop body).  taping: the slice belongs to the
+// sequence the adjoint can reverse (a checkpoint is taken before every K-th);
+// rec (or NULL) receives what the reverse of this slice reads.
+wandqs_status do_slice(wandqs_ctx* c, int rec_slot, int64_t probe_slice, bool taping,
+                       const wq::TapeSlot* rec) {
     using namespace wq;
     wandqs_status s;
     Level& L0 = c->lev[0];
+    if (taping && c->tape_K > 0 && c->tape_n >= c->rec_cap) c->tape_ok = false;  // capacity
+    if (taping && c->tape_K > 0 && c->tape_ok && c->tape_n % c->tape_K == 0) {
+        const int64_t k = c->tape_n / c->tape_K;
+        if (k >= c->n_ckpt - 1) c->tape_ok = false;  // past the capacity given at init
+        else if ((s = save_checkpoint(c, c->ckpt[k])) != WANDQS_OK) return s;
+    }
     // initial guesses: linear extrapolation of the last two slices' fields once
     // two are known, else the previous slice's fields (Sec. VII.A)
     if ((s = extrapolate_guess(c, c->n_guess >= 2)) != WANDQS_OK) return s;
     if ((s = slice_sort(c)) != WANDQS_OK) return s;
+    if (rec) {
+        const size_t pb = sizeof(double) * (size_t)c->P;
+        for (int q = 0; q < 4; ++q)
+            if ((s = copy_d2d(c, rec->pa[q], c->pa[c->cur][q], pb)) != WANDQS_OK) return s;
+        if ((s = copy_d2d(c, rec->pid, c->pid[c->cur], sizeof(int32_t) * (size_t)c->P)) != WANDQS_OK)
+            return s;
+        if ((s = copy_d2d(c, rec->start, c->cell_start, sizeof(int32_t) * ((size_t)c->N * c->N + 1))) !=
+            WANDQS_OK)
+            return s;
+    }
     if ((s = deposit_n(c)) != WANDQS_OK) return s;  // Collect_Source: n*
     double* u1[2] = {c->fields[0], nullptr};
     double* f1[2] = {L0.f[0], nullptr};
@@ -129,9 +209,19 @@ wandqs_status do_slice(wandqs_ctx* c, int rec_slot, int64_t probe_slice) {
     if ((s = assemble(c)) != WANDQS_OK) return s;
     double* u3[2] = {c->fields[3], c->fields[4]};
     if ((s = mg_solve(c, kSolveBperp, 2, true, u3, f2, L0.k2, &c->last[2])) != WANDQS_OK) return s;
+    if (rec) {
+        const size_t nb = node_bytes(c);
+        for (int q = 0; q < 5; ++q)
+            if ((s = copy_d2d(c, rec->fields[q], c->fields[q], nb)) != WANDQS_OK) return s;
+        for (int q = 0; q < 6; ++q)
+            if ((s = copy_d2d(c, rec->mom[q], c->mom[q], nb)) != WANDQS_OK) return s;
+        if ((s = copy_d2d(c, rec->k2, L0.k2, nb)) != WANDQS_OK) return s;
+        if ((s = copy_d2d(c, rec->st, c->st, 2 * sizeof(double))) != WANDQS_OK) return s;
+    }
     if (!c->probes.empty() && (s = probes_accumulate(c, probe_slice)) != WANDQS_OK) return s;
     if ((s = push_and_step(c, rec_slot)) != WANDQS_OK) return s;  // Push_Trajectory + Step_Size_Refinement
     if (c->n_guess < 2) ++c->n_guess;
+    if (taping) ++c->tape_n;
     return WANDQS_OK;
 }
 
@@ -223,10 +313,53 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
     c->rec = (double*)take(sizeof(double) * 4 * (size_t)c->rec_cap);
     c->probe_acc = (double*)take(sizeof(double) * kMaxProbes);
     c->bins_dev = (double*)take(sizeof(double) * (size_t)(c->n_bins_total + 1));
+    const size_t nnd = (size_t)(c->N + 1) * (c->N + 1);
+    c->bin_map = (int32_t*)take(sizeof(int32_t) * nnd * (size_t)c->n_bin_beams);
+    if (c->tape_K > 0) {
+        c->ckpt.assign(c->n_ckpt, Checkpoint{});
+        for (auto& k : c->ckpt) {
+            for (int q = 0; q < 4; ++q) k.pa[q] = (double*)take(sizeof(double) * P);
+            k.pid = (int32_t*)take(sizeof(int32_t) * P);
+            for (int q = 0; q < 5; ++q) {
+                k.fields[q] = arr(0);
+                k.fields_prev[q] = arr(0);
+            }
+            k.st = (double*)take(sizeof(double) * 4);
+        }
+        c->slot.assign(std::min(c->tape_K, c->rec_cap), TapeSlot{});
+        for (auto& t : c->slot) {
+            for (int q = 0; q < 4; ++q) t.pa[q] = (double*)take(sizeof(double) * P);
+            t.pid = (int32_t*)take(sizeof(int32_t) * P);
+            t.start = (int32_t*)take(sizeof(int32_t) * (ncell + 1));
+            for (int q = 0; q < 5; ++q) t.fields[q] = arr(0);
+            for (int q = 0; q < 6; ++q) t.mom[q] = arr(0);
+            t.k2 = arr(0);
+            t.st = (double*)take(sizeof(double) * 2);
+        }
+        AdjBuffers& A = c->adj;
+        double** node[] = {&A.Gxb, &A.Gyb, &A.Bxb, &A.Byb, &A.Bzb, &A.Ezb, &A.psib, &A.lx, &A.ly,
+                           &A.lE, &A.lB, &A.lpsi, &A.nb, &A.jxb, &A.jyb, &A.txxb, &A.txyb, &A.tyyb,
+                           &A.psxb, &A.psyb, &A.gnb, &A.psib_dep, &A.jzb};
+        for (double** p : node) *p = arr(0);
+        double** part[] = {&A.xb, &A.yb, &A.pxb, &A.pyb, &A.gb};
+        for (double** p : part) *p = (double*)take(sizeof(double) * P);
+        A.adj_id = (double*)take(sizeof(double) * 4 * P);
+        A.theta_bar = (double*)take(sizeof(double) * (size_t)(c->n_theta + 1));
+        A.theta_part = (double*)take(sizeof(double) * (size_t)(c->n_seg_cap + 1));
+        A.seg = (int32_t*)take(sizeof(int32_t) * 4 * (size_t)(c->n_seg_cap + 1));
+        A.seg_first = (int32_t*)take(sizeof(int32_t) * (size_t)(c->n_theta + 1));
+        A.bin_nodes = (int32_t*)take(sizeof(int32_t) * nnd * (size_t)(c->n_bin_beams + 1));
+    }
     return (off + 255) & ~(size_t)255;
 }
 
 const char* wq::hip_err(hipError_t e) { return hipGetErrorString(e); }
+
+// (this file is compiled without floating-point contraction)
+bool wq::node_in_disc_host(double L, double h, int a, int b, double x0, double y0, double r) {
+    const double rx = (-L + a * h) - x0, ry = (-L + b * h) - y0;
+    return rx * rx + ry * ry <= r * r;
+}
 
 extern "C" {
 
@@ -319,6 +452,76 @@ wandqs_status wandqs_init(const wandqs_config* cfg, int32_t n_slices, void* d_wo
         }
     }
 
+    // radial-bin node maps: the bin of node (x_a, y_b) is floor(r / (r_max / n_bins))
+    // for r = |(x_a, y_b) - (x0, y0)| < r_max, decided once here for the forward
+    // density and for the adjoint's sums over bins
+    const size_t nnd = (size_t)(c->N + 1) * (c->N + 1);
+    std::vector<int32_t> bmap(nnd * (size_t)c->n_bin_beams, -1);
+    {
+        int q = 0;
+        for (int k = 0; k < B.n; ++k) {
+            B.bmap[k] = nullptr;
+            const wandqs_beam& b = c->beams[k];
+            if (b.kind != WANDQS_BEAM_RADIAL_BINS) continue;
+            int32_t* m = bmap.data() + (size_t)q * nnd;
+            const double dr = b.r_max / b.n_bins;
+            for (int jb = 0; jb <= c->N; ++jb)
+                for (int ja = 0; ja <= c->N; ++ja) {
+                    const double rx = (-c->L + ja * c->h) - b.x0, ry = (-c->L + jb * c->h) - b.y0;
+                    const double r = std::sqrt(rx * rx + ry * ry);
+                    const int kb = (int)std::floor(r / dr);
+                    m[(size_t)jb * (c->N + 1) + ja] = (r < b.r_max && kb < b.n_bins) ? kb : -1;
+                }
+            B.bmap[k] = c->bin_map + (size_t)q * nnd;
+            ++q;
+        }
+    }
+    // adjoint: segments of the sums over nodes behind dL/dtheta (theta in beam
+    // order; a Gaussian beam's amplitude sums over all nodes, a bin's amplitude
+    // over the nodes of its bin)
+    std::vector<int32_t> seg, seg_first, bin_nodes;
+    if (c->tape_K > 0) {
+        int t = 0, q = 0;
+        auto add = [&](int k, int i0, int i1) {
+            for (int i = i0; i < i1; i += wq::kThetaSeg) {
+                const int e = std::min(i1, i + wq::kThetaSeg);
+                seg.insert(seg.end(), {k, t, i, e});
+            }
+        };
+        for (int k = 0; k < B.n; ++k) {
+            const wandqs_beam& b = c->beams[k];
+            if (b.kind == WANDQS_BEAM_GAUSS) {
+                seg_first.push_back((int32_t)(seg.size() / 4));
+                add(k, 0, (int)nnd);
+                ++t;
+                continue;
+            }
+            const int32_t* m = bmap.data() + (size_t)q * nnd;
+            std::vector<std::vector<int32_t>> by(b.n_bins);
+            for (size_t i = 0; i < nnd; ++i)
+                if (m[i] >= 0) by[m[i]].push_back((int32_t)i);
+            for (int j = 0; j < b.n_bins; ++j) {
+                seg_first.push_back((int32_t)(seg.size() / 4));
+                const int off = (int)bin_nodes.size();
+                bin_nodes.insert(bin_nodes.end(), by[j].begin(), by[j].end());
+                add(k, off, (int)bin_nodes.size());
+                ++t;
+            }
+            ++q;
+        }
+        seg_first.push_back((int32_t)(seg.size() / 4));
+        c->n_seg = (int)(seg.size() / 4);
+        if (c->n_seg > c->n_seg_cap) return bail("internal: theta segment table overflow");
+    }
+    c->probe_count.clear();
+    for (const auto& p : c->probes) {
+        double n = 0.0;
+        for (int jb = 0; jb <= c->N; ++jb)
+            for (int ja = 0; ja <= c->N; ++ja)
+                n += wq::node_in_disc_host(c->L, c->h, ja, jb, p.x0, p.y0, p.r_max) ? 1.0 : 0.0;
+        c->probe_count.push_back(n);
+    }
+
     // cold plasma at rest on the jittered lattice (same generator and draw order
     // as the test-side input module)
     const int N = c->N, s = cfg->ppc_side;
@@ -342,6 +545,10 @@ wandqs_status wandqs_init(const wandqs_config* cfg, int32_t n_slices, void* d_wo
               hipMemcpyAsync(c->pid[0], ids.data(), sizeof(int32_t) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
               hipMemcpyAsync(c->st, st0, sizeof(st0), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
               (bins_host.empty() || hipMemcpyAsync(c->bins_dev, bins_host.data(), sizeof(double) * bins_host.size(), hipMemcpyHostToDevice, c->stream) == hipSuccess) &&
+              (bmap.empty() || hipMemcpyAsync(c->bin_map, bmap.data(), sizeof(int32_t) * bmap.size(), hipMemcpyHostToDevice, c->stream) == hipSuccess) &&
+              (seg.empty() || hipMemcpyAsync(c->adj.seg, seg.data(), sizeof(int32_t) * seg.size(), hipMemcpyHostToDevice, c->stream) == hipSuccess) &&
+              (seg_first.empty() || hipMemcpyAsync(c->adj.seg_first, seg_first.data(), sizeof(int32_t) * seg_first.size(), hipMemcpyHostToDevice, c->stream) == hipSuccess) &&
+              (bin_nodes.empty() || hipMemcpyAsync(c->adj.bin_nodes, bin_nodes.data(), sizeof(int32_t) * bin_nodes.size(), hipMemcpyHostToDevice, c->stream) == hipSuccess) &&
               hipStreamSynchronize(c->stream) == hipSuccess;
     if (!ok) return bail("copying the initial state failed");
     c->cur = 0;
@@ -355,7 +562,7 @@ wandqs_status wandqs_slice_step(wandqs_ctx* c, double* d_fields_out, wandqs_slic
         c->err = "context failed earlier; call wandqs_set_state";
         return WANDQS_E_STATE;
     }
-    wandqs_status s = do_slice(c, 0, -1);
+    wandqs_status s = do_slice(c, 0, -1, true, nullptr);
     if (s != WANDQS_OK) return fail(c, s);
     if (d_fields_out && (s = wq::pack_fields(c, c->fields, 5, d_fields_out)) != WANDQS_OK)
         return fail(c, s);
@@ -389,6 +596,8 @@ wandqs_status wandqs_run(wandqs_ctx* c, int32_t n_slices, double* d_probe_out,
     wandqs_status s;
     if (!c->probes.empty() && (s = wq::fill_f64(c, c->probe_acc, wq::kMaxProbes, 0.0)) != WANDQS_OK)
         return fail(c, s);
+    c->run_begin = c->tape_n;
+    c->run_len = -1;
     std::vector<double> rec;
     int32_t chunk0 = 0;
     auto flush = [&](int32_t upto) -> wandqs_status {
@@ -408,7 +617,7 @@ wandqs_status wandqs_run(wandqs_ctx* c, int32_t n_slices, double* d_probe_out,
     };
     for (int32_t j = 0; j < n_slices; ++j) {
         if (j - chunk0 == c->rec_cap && (s = flush(j)) != WANDQS_OK) return fail(c, s);
-        if ((s = do_slice(c, j - chunk0, j)) != WANDQS_OK) {
+        if ((s = do_slice(c, j - chunk0, j, true, nullptr)) != WANDQS_OK) {
             flush(j);
             return fail(c, s);
         }
@@ -423,6 +632,7 @@ wandqs_status wandqs_run(wandqs_ctx* c, int32_t n_slices, double* d_probe_out,
         }
     }
     if ((s = check_flags(c)) != WANDQS_OK) return fail(c, s);
+    c->run_len = n_slices;
     return WANDQS_OK;
 }
 
@@ -454,6 +664,9 @@ wandqs_status wandqs_set_state(wandqs_ctx* c, const double* d_particles, const d
     WQ_HIP(hipStreamSynchronize(c->stream));
     c->failed = false;
     c->n_guess = 0;
+    c->tape_n = 0;  // the tape restarts from this state
+    c->tape_ok = true;
+    c->run_len = -1;
     return WANDQS_OK;
 }
 
@@ -469,6 +682,7 @@ wandqs_status wandqs_mg_solve(wandqs_ctx* c, int32_t nrhs, const double* d_k2, c
     double* u[2] = {c->fields[0], nrhs > 1 ? c->fields[1] : nullptr};
     double* f[2] = {L0.f[0], nrhs > 1 ? L0.f[1] : nullptr};
     c->n_guess = 0;  // the stored fields no longer belong to the slice sequence
+    c->tape_ok = false;
     s = wq::mg_solve(c, 3, nrhs, d_k2 != nullptr, u, f, d_k2 ? L0.k2 : nullptr, &res);
     if (s != WANDQS_OK && s != WANDQS_E_NOCONV) return fail(c, s);
     wandqs_status s2 = wq::pack_fields(c, c->fields, nrhs, d_u);
@@ -489,6 +703,86 @@ wandqs_status wandqs_get_moments(wandqs_ctx* c, double* d_out) {
 }
 
 int64_t wandqs_num_particles(const wandqs_ctx* c) { return c ? c->P : 0; }
+
+int32_t wandqs_num_theta(const wandqs_ctx* c) { return c ? c->n_theta : 0; }
+
+int64_t wandqs_tape_slices(const wandqs_ctx* c) {
+    return c && c->tape_K > 0 && c->tape_ok ? c->tape_n : -1;
+}
+
+wandqs_status wandqs_backward(wandqs_ctx* c, const double* h_dL_dprobe, const double* d_dL_dfields,
+                              const double* d_dL_dparticles, double* h_dL_dtheta,
+                              double* d_dL_dparticles0) {
+    using namespace wq;
+    if (!c) return WANDQS_E_INVALID;
+    if (c->tape_K <= 0) {
+        c->err = "no adjoint tape: initialise with checkpoint_every > 0";
+        return WANDQS_E_STATE;
+    }
+    if (c->failed) {
+        c->err = "context failed earlier; call wandqs_set_state";
+        return WANDQS_E_STATE;
+    }
+    if (!c->tape_ok) {
+        c->err = "the tape is incomplete (more slices than given at init, or wandqs_mg_solve "
+                 "replaced the fields); call wandqs_set_state";
+        return WANDQS_E_STATE;
+    }
+    if (h_dL_dprobe && !c->probes.empty() && c->run_len < 0) {
+        c->err = "probe adjoints given but no wandqs_run completed since the tape start";
+        return WANDQS_E_STATE;
+    }
+    const int64_t S = c->tape_n, K = c->tape_K;
+    const size_t P = (size_t)c->P, nnd = (size_t)(c->N + 1) * (c->N + 1);
+    if (S > c->rec_cap || (S > 0 && (S - 1) / K >= c->n_ckpt - 1) ||
+        (int64_t)c->slot.size() < std::min(S, K)) {
+        c->err = "internal: tape larger than its buffers";
+        return WANDQS_E_STATE;
+    }
+    wandqs_status s;
+    Checkpoint& fin = c->ckpt[c->n_ckpt - 1];
+    if ((s = save_checkpoint(c, fin)) != WANDQS_OK) return fail(c, s);
+    if ((s = adj_zero_solutions(c)) != WANDQS_OK) return fail(c, s);
+    if (d_dL_dparticles)
+        s = copy_d2d(c, c->adj.adj_id, d_dL_dparticles, sizeof(double) * 4 * P);
+    else
+        s = fill_f64(c, c->adj.adj_id, 4 * P, 0.0);
+    if (s != WANDQS_OK) return fail(c, s);
+
+    std::vector<double> w(c->probes.size());
+    for (int64_t seg = (S + K - 1) / K - 1; seg >= 0; --seg) {
+        const int64_t j0 = seg * K, j1 = std::min(S, j0 + K);
+        if ((s = restore_checkpoint(c, c->ckpt[seg])) != WANDQS_OK) return fail(c, s);
+        for (int64_t j = j0; j < j1; ++j)
+            if ((s = do_slice(c, -1, -1, false, &c->slot[j - j0])) != WANDQS_OK) return fail(c, s);
+        for (int64_t j = j1 - 1; j >= j0; --j) {
+            // probe seeds: d(probe k)/d(field node) = 1 / (nodes in the disc * slices in the window)
+            bool any = false;
+            for (size_t k = 0; k < c->probes.size(); ++k) {
+                const wandqs_probe& p = c->probes[k];
+                const int64_t r = j - c->run_begin;
+                w[k] = 0.0;
+                if (h_dL_dprobe && c->run_len >= 0 && r >= 0 && r < c->run_len && r >= p.slice_begin &&
+                    r < p.slice_end && c->probe_count[k] > 0) {
+                    w[k] = h_dL_dprobe[k] / c->probe_count[k] / (double)(p.slice_end - p.slice_begin);
+                    any = true;
+                }
+            }
+            const double* fb = d_dL_dfields ? d_dL_dfields + (size_t)j * 5 * nnd : nullptr;
+            if ((s = slice_adjoint(c, c->slot[j - j0], fb, any ? w.data() : nullptr)) != WANDQS_OK)
+                return fail(c, s);
+        }
+    }
+    if (d_dL_dparticles0 &&
+        (s = copy_d2d(c, d_dL_dparticles0, c->adj.adj_id, sizeof(double) * 4 * P)) != WANDQS_OK)
+        return fail(c, s);
+    if ((s = restore_checkpoint(c, fin)) != WANDQS_OK) return fail(c, s);
+    if (h_dL_dtheta && c->n_theta > 0)
+        WQ_HIP(hipMemcpyAsync(h_dL_dtheta, c->adj.theta_bar, sizeof(double) * c->n_theta,
+                              hipMemcpyDeviceToHost, c->stream));
+    WQ_HIP(hipStreamSynchronize(c->stream));
+    return WANDQS_OK;
+}
 
 void wandqs_destroy(wandqs_ctx* c) {
     if (!c) return;

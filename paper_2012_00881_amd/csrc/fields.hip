@@ -30,23 +30,31 @@ __global__ void k_rhs_EB(int N, double h, int pitch, const double* __restrict__ 
     fB[g] = m;
 }
 
-__device__ double beam_density(const BeamSet& B, double x, double y, double xi) {
+// Driver density at node (a, b) = (x, y).  Radial-bin membership comes from the
+// node map built on the host, so bin edges are decided exactly once.
+__device__ double beam_density(const BeamSet& B, double x, double y, size_t node, double xi) {
     if (xi < 0.0) return 0.0;
     double s = 0.0;
     for (int k = 0; k < B.n; ++k) {
-        const double rx = x - B.x0[k], ry = y - B.y0[k];
-        const double r2 = rx * rx + ry * ry;
         const double lz = (xi - B.xc[k]) * (xi - B.xc[k]) / (B.sz[k] * B.sz[k]);
         if (B.kind[k] == 0) {
+            const double rx = x - B.x0[k], ry = y - B.y0[k];
+            const double r2 = rx * rx + ry * ry;
             s += B.amp[k] * exp(-r2 / (B.sr[k] * B.sr[k]) - lz);
         } else {
-            const double r = sqrt(r2);
-            const double dr = B.rmax[k] / B.nbins[k];
-            const int kb = (int)floor(r / dr);
-            if (r < B.rmax[k] && kb < B.nbins[k]) s += B.bins[k][kb] * exp(-lz);
+            const int kb = B.bmap[k][node];
+            if (kb >= 0) s += B.bins[k][kb] * exp(-lz);
         }
     }
     return s;
+}
+
+// Node (a, b) inside the disc of radius r around (x0, y0); every operation
+// rounded separately so that host and device agree on the edge.
+__device__ bool in_disc(double L, double h, int a, int b, double x0, double y0, double r) {
+#pragma clang fp contract(off)
+    const double rx = (-L + a * h) - x0, ry = (-L + b * h) - y0;
+    return rx * rx + ry * ry <= r * r;
 }
 
 // Total j_z on every node: plasma n*<p_z>/g = G/g - n* with G = n*<gamma> =
@@ -67,7 +75,7 @@ __global__ void k_jz(int N, double L, double h, int pitch, const double* __restr
         const double G = (n[i] * (1.0 + g * g) + g * g * (txx[i] + tyy[i])) / (2.0 * g);
         v = G / g - n[i];
     }
-    jz[i] = v + beam_density(beams, -L + a * h, -L + b * h, st[0]);
+    jz[i] = v + beam_density(beams, -L + a * h, -L + b * h, (size_t)b * (N + 1) + a, st[0]);
 }
 
 // k2 = n* / g and the B_perp right-hand sides on the interior nodes:
@@ -115,8 +123,7 @@ __global__ __launch_bounds__(256) void k_probe(int N, double L, double h, int pi
     double s = 0.0, cnt = 0.0;
     for (int i = threadIdx.x; i < (N + 1) * (N + 1); i += 256) {
         const int b = i / (N + 1), a = i - b * (N + 1);
-        const double rx = -L + a * h - x0, ry = -L + b * h - y0;
-        if (rx * rx + ry * ry <= rmax * rmax) {
+        if (in_disc(L, h, a, b, x0, y0, rmax)) {
             s += F[(size_t)b * pitch + a];
             cnt += 1.0;
         }
@@ -135,6 +142,16 @@ __global__ __launch_bounds__(256) void k_probe(int N, double L, double h, int pi
         const double C = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
         if (C > 0) *acc += scale * S / C;
     }
+}
+
+// Adjoint seed of a probe: Fb += w on the interior nodes of its disc (the
+// boundary values are fixed, their adjoints never propagate).
+__global__ void k_probe_seed(int N, double L, double h, int pitch, double x0, double y0,
+                             double rmax, double w, double* __restrict__ Fb) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (a < 1 || a > N - 1 || b < 1 || b > N - 1) return;
+    if (in_disc(L, h, a, b, x0, y0, rmax)) Fb[(size_t)b * pitch + a] += w;
 }
 
 __global__ void k_pack(int N, int pitch, const double* __restrict__ src, double* __restrict__ dst) {
@@ -231,6 +248,17 @@ wandqs_status probes_accumulate(wandqs_ctx* c, int64_t slice) {
     return WANDQS_OK;
 }
 
+wandqs_status probe_seed(wandqs_ctx* c, int k, double w, double* const* Fb) {
+    const wandqs_probe& p = c->probes[k];
+    {
+        ProfScope ps(c, "k_probe_seed", (double)(c->N + 1) * (c->N + 1) * 16.0);
+        hipLaunchKernelGGL(k_probe_seed, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->L, c->h,
+                           c->lev[0].pitch, p.x0, p.y0, p.r_max, w, Fb[p.field]);
+    }
+    WQ_LAUNCH_CHECK();
+    return WANDQS_OK;
+}
+
 wandqs_status pack_fields(wandqs_ctx* c, double* const* src, int n, double* dst) {
     const size_t nn = (size_t)(c->N + 1) * (c->N + 1);
     for (int k = 0; k < n; ++k)
@@ -265,6 +293,11 @@ wandqs_status extrapolate_guess(wandqs_ctx* c, bool extrapolate) {
     hipLaunchKernelGGL(k_extrapolate, node_grid(c->N), dim3(128), 0, c->stream, c->N,
                        c->lev[0].pitch, c->st, f, extrapolate ? 1 : 0);
     WQ_LAUNCH_CHECK();
+    return WANDQS_OK;
+}
+
+wandqs_status copy_d2d(wandqs_ctx* c, void* dst, const void* src, size_t bytes) {
+    WQ_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream));
     return WANDQS_OK;
 }
 

@@ -947,7 +947,9 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
             for (int r = 0; r < R; ++r) {
                 const double rr = std::sqrt(hr[4 * k + 2 * r]);
                 const double ff = std::sqrt(hr[4 * k + 2 * r + 1]);
-                bool ok = std::isfinite(rr) && rr <= c->cfg.mg_rtol * ff + atol;
+                // relative to ||f||; for f = 0 (solution 0) relative to ||r_0||
+                const double ref = ff > 0 ? ff : std::sqrt(hr[2 * r]);
+                bool ok = std::isfinite(rr) && rr <= c->cfg.mg_rtol * ref + atol;
                 if (!ok && k >= 2) {
                     const double rp = std::sqrt(hr[4 * (k - 1) + 2 * r]);
                     const double scale = std::max(ff, std::sqrt(hr[2 * r]));
@@ -971,7 +973,12 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
                 return WANDQS_E_NONPHYS;
             }
             if (need < 0) {
-                c->err = "multigrid did not converge within mg_max_cycles";
+                static const char* names[kPredKinds] = {"psi", "Ez/Bz", "B_perp", "user",
+                                                        "psi adjoint", "Ez/Bz adjoint",
+                                                        "B_perp adjoint", "?"};
+                c->err = std::string("multigrid did not converge within mg_max_cycles (") +
+                         names[kind & (kPredKinds - 1)] + " solve, ||r||/||f|| = " +
+                         std::to_string(res ? res->rel[0] : -1.0) + ")";
                 return WANDQS_E_NOCONV;
             }
             c->pred[kind] = need < 1 ? 1 : need;

@@ -19,6 +19,8 @@ constexpr int kCoarseMax = 64;  // levels with N <= 64 are solved inside one wor
 constexpr int kMaxSlots = 208;  // residual-norm records per solve (mg_max_cycles + batches)
 constexpr int kTile = 32;       // multigrid tile edge (fine nodes owned by one workgroup)
 constexpr int kDepTile = 16;    // deposit tile edge (nodes owned by one workgroup)
+constexpr int kPredKinds = 8;   // solve kinds with their own V-cycle batch prediction
+constexpr int kThetaSeg = 4096; // nodes per partial sum of the driver-parameter adjoint
 
 // Driver beams as a by-value kernel argument.
 struct BeamSet {
@@ -28,6 +30,7 @@ struct BeamSet {
         y0[kMaxBeams], rmax[kMaxBeams];
     int nbins[kMaxBeams];
     const double* bins[kMaxBeams];
+    const int32_t* bmap[kMaxBeams];  // radial bins: bin of each node (dense [N+1]^2), -1 outside
 };
 
 // One multigrid level.  Node arrays are row-major with a padded row pitch.
@@ -46,7 +49,55 @@ struct Level {
     float* f32[2] = {nullptr, nullptr};
 };
 
-enum SolveKind { kSolvePsi = 0, kSolveEB = 1, kSolveBperp = 2 };
+enum SolveKind {
+    kSolvePsi = 0,
+    kSolveEB = 1,
+    kSolveBperp = 2,
+    kSolveUser = 3,
+    kSolvePsiAdj = 4,
+    kSolveEBAdj = 5,
+    kSolveBperpAdj = 6
+};
+
+// Checkpoint of the slice loop state (the adjoint recomputes from it).
+struct Checkpoint {
+    double* pa[4] = {};
+    int32_t* pid = nullptr;
+    double* fields[5] = {};
+    double* fields_prev[5] = {};
+    double* st = nullptr;
+    int pred[kPredKinds] = {};
+    int n_guess = 0;
+};
+
+// What the reverse of one slice reads: its particles in cell order, the cell
+// offsets, the solved fields, the deposited moments, k2 and [xi, dxi].
+struct TapeSlot {
+    double* pa[4] = {};
+    int32_t* pid = nullptr;
+    int32_t* start = nullptr;
+    double* fields[5] = {};
+    double* mom[6] = {};
+    double* k2 = nullptr;
+    double* st = nullptr;
+};
+
+// Work arrays of the reverse sweep.  Node arrays use the padded level-0 layout.
+struct AdjBuffers {
+    double *Gxb = nullptr, *Gyb = nullptr, *Bxb = nullptr, *Byb = nullptr, *Bzb = nullptr,
+           *Ezb = nullptr, *psib = nullptr;
+    double *lx = nullptr, *ly = nullptr, *lE = nullptr, *lB = nullptr, *lpsi = nullptr;
+    double *nb = nullptr, *jxb = nullptr, *jyb = nullptr, *txxb = nullptr, *txyb = nullptr,
+           *tyyb = nullptr, *psxb = nullptr, *psyb = nullptr, *gnb = nullptr, *psib_dep = nullptr,
+           *jzb = nullptr;
+    double *xb = nullptr, *yb = nullptr, *pxb = nullptr, *pyb = nullptr, *gb = nullptr;  // slice order
+    double* adj_id = nullptr;      // [4][P] particle-ID order
+    double* theta_bar = nullptr;   // [n_theta]
+    double* theta_part = nullptr;  // [n_seg]
+    int32_t* seg = nullptr;        // [n_seg][4]: beam, theta, begin, end
+    int32_t* seg_first = nullptr;  // [n_theta + 1]
+    int32_t* bin_nodes = nullptr;  // radial-bin nodes grouped by bin
+};
 
 struct SolveResult {
     int cycles = -1;
@@ -83,6 +134,8 @@ struct wandqs_ctx {
     int64_t P = 0;
     int rec_cap = 0;
     int n_bins_total = 0;  // radial-bin amplitudes over all beams
+    int n_bin_beams = 0;   // beams of kind RADIAL_BINS
+    int n_theta = 0;       // driver parameters: one per Gaussian beam, n_bins per radial-bin beam
     hipStream_t stream = nullptr;
 
     // device memory carved from the caller's workspace
@@ -108,11 +161,27 @@ struct wandqs_ctx {
     double* rec = nullptr;        // [rec_cap][4] : xi, dxi, vmax, flags
     double* probe_acc = nullptr;  // [kMaxProbes]
     double* bins_dev = nullptr;
+    int32_t* bin_map = nullptr;  // [n_bin_beams][N+1]^2
     wq::BeamSet beamset{};
+
+    // adjoint tape (checkpoint_every = K > 0): a checkpoint before every K-th
+    // slice since init / set_state, one extra for the state at the start of a
+    // backward sweep, and K slots for the slices of one recomputed segment
+    int tape_K = 0;
+    int n_ckpt = 0;
+    int n_seg = 0, n_seg_cap = 0;
+    int64_t tape_n = 0;     // slices since the tape start
+    bool tape_ok = true;    // false after wandqs_mg_solve or past the capacity
+    int64_t run_begin = 0;  // tape index of the first slice of the last wandqs_run
+    int64_t run_len = -1;   // its slice count (-1: no completed run)
+    std::vector<wq::Checkpoint> ckpt;
+    std::vector<wq::TapeSlot> slot;
+    wq::AdjBuffers adj;
+    std::vector<double> probe_count;  // nodes in each probe disc
 
     // host side
     double* h_pin = nullptr;  // pinned readback buffer
-    int pred[4] = {1, 1, 1, 1};  // V-cycles of the last solve per kind (batch size)
+    int pred[wq::kPredKinds] = {1, 1, 1, 1, 1, 1, 1, 1};  // V-cycles of the last solve per kind (batch size)
     bool failed = false;
     int n_guess = 0;  // slices since init/set_state (extrapolation needs two)
     std::string err;
@@ -143,6 +212,19 @@ wandqs_status particles_to_id_order(wandqs_ctx* c, double* dst);
 wandqs_status particles_from_id_order(wandqs_ctx* c, const double* src);
 wandqs_status fill_f64(wandqs_ctx* c, double* p, size_t n, double v);
 wandqs_status extrapolate_guess(wandqs_ctx* c, bool extrapolate);
+wandqs_status copy_d2d(wandqs_ctx* c, void* dst, const void* src, size_t bytes);
+wandqs_status probe_seed(wandqs_ctx* c, int k, double w, double* const* Fb);
+
+// adjoint (adjoint.hip); tape slot t holds the slice, tape index j its place
+// in the slice sequence (for probe seeds)
+wandqs_status slice_adjoint(wandqs_ctx* c, const TapeSlot& ts, const double* d_field_bar,
+                            const double* probe_w);
+wandqs_status adj_zero_solutions(wandqs_ctx* c);
+wandqs_status adj_reduce_theta_init(wandqs_ctx* c);
+
+// node inside the disc |x - x0| <= r of a probe, in IEEE double without
+// contraction (the host and the device take the same decision)
+bool node_in_disc_host(double L, double h, int a, int b, double x0, double y0, double r);
 
 const char* hip_err(hipError_t e);
 

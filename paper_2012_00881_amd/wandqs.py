@@ -27,7 +27,7 @@ _dp = C.POINTER(C.c_double)
 EXPORTS = ("wandqs_workspace_bytes", "wandqs_init", "wandqs_slice_step", "wandqs_run",
            "wandqs_get_state", "wandqs_set_state", "wandqs_mg_solve", "wandqs_get_moments",
            "wandqs_num_particles", "wandqs_destroy", "wandqs_last_error", "wandqs_profile",
-           "wandqs_profile_stats")
+           "wandqs_profile_stats", "wandqs_backward", "wandqs_num_theta", "wandqs_tape_slices")
 
 
 class Beam(C.Structure):
@@ -92,13 +92,19 @@ def load():
     L.wandqs_num_particles.restype = C.c_int64
     L.wandqs_profile.argtypes = [vp, i32]
     L.wandqs_profile_stats.argtypes = [vp, C.POINTER(KernelStat), i32, C.POINTER(i32)]
+    L.wandqs_backward.argtypes = [vp, _dp, vp, vp, _dp, vp]
+    L.wandqs_num_theta.argtypes = [vp]
+    L.wandqs_num_theta.restype = C.c_int32
+    L.wandqs_tape_slices.argtypes = [vp]
+    L.wandqs_tape_slices.restype = C.c_int64
     L.wandqs_destroy.argtypes = [vp]
     L.wandqs_destroy.restype = None
     L.wandqs_last_error.argtypes = [vp]
     L.wandqs_last_error.restype = C.c_char_p
     for name in ("wandqs_workspace_bytes", "wandqs_init", "wandqs_slice_step", "wandqs_run",
                  "wandqs_get_state", "wandqs_set_state", "wandqs_mg_solve",
-                 "wandqs_get_moments", "wandqs_profile", "wandqs_profile_stats"):
+                 "wandqs_get_moments", "wandqs_profile", "wandqs_profile_stats",
+                 "wandqs_backward"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -144,6 +150,37 @@ def make_config(cfg: dict):
     c.checkpoint_every = cfg.get("checkpoint_every", 0)
     c.mg_inner_cycles = cfg.get("mg_inner_cycles", 0)
     return c, keep
+
+
+def theta_of(cfg: dict) -> np.ndarray:
+    """Driver parameters theta in the library's order: per beam its amp
+    (Gaussian) or its bin amplitudes (radial bins)."""
+    out = []
+    for b in cfg["beams"]:
+        if b["kind"] == "gauss":
+            out.append(float(b["amp"]))
+        else:
+            out.extend(float(v) for v in b["bin_amp"])
+    return np.asarray(out, dtype=np.float64)
+
+
+def with_theta(cfg: dict, theta) -> dict:
+    """Copy of cfg with the driver parameters replaced by theta."""
+    theta = np.asarray(theta, dtype=np.float64)
+    beams, k = [], 0
+    for b in cfg["beams"]:
+        b = dict(b)
+        if b["kind"] == "gauss":
+            b["amp"] = float(theta[k])
+            k += 1
+        else:
+            n = len(b["bin_amp"])
+            b["bin_amp"] = theta[k:k + n].copy()
+            k += n
+        beams.append(b)
+    if k != theta.size:
+        raise ValueError(f"theta has {theta.size} entries, the beams take {k}")
+    return dict(cfg, beams=beams)
 
 
 def workspace_bytes(cfg: dict, n_slices: int = 1) -> int:
@@ -269,6 +306,50 @@ class Simulation:
         return [dict(name=a.name.decode(), launches=a.launches, total_ms=a.total_ms,
                      alg_bytes=a.alg_bytes) for a in arr[:n.value]]
 
+    @property
+    def n_theta(self) -> int:
+        return int(self.L.wandqs_num_theta(self.ctx))
+
+    def tape_slices(self) -> int:
+        return int(self.L.wandqs_tape_slices(self.ctx))
+
+    def backward(self, dL_dprobe=None, dL_dfields=None, dL_dparticles=None,
+                 particles_grad: bool = False):
+        """Reverse sweep over the taped slices (needs checkpoint_every > 0).
+
+        dL_dprobe: [n_probes] (the last run's probes); dL_dfields: [S][5][N+1][N+1]
+        for the S taped slices; dL_dparticles: [4][P] adjoint of the final
+        particles (ID order).  Returns (dL/dtheta as numpy, dL/d(initial
+        particles) as a [4][P] device tensor or None)."""
+        t = self.torch
+        pr = None
+        if dL_dprobe is not None:
+            v = np.ascontiguousarray(np.asarray(dL_dprobe, dtype=np.float64).reshape(-1))
+            if v.size != len(self.cfg["probes"]):
+                raise ValueError("dL_dprobe needs one entry per probe")
+            pr = v
+        fb = None
+        if dL_dfields is not None:
+            fb = t.as_tensor(dL_dfields, dtype=t.float64).to(self.device).contiguous()
+            S = self.tape_slices()
+            if tuple(fb.shape) != (S, 5, self.N + 1, self.N + 1):
+                raise ValueError(f"dL_dfields must be [{S}][5][N+1][N+1]")
+        pb = None
+        if dL_dparticles is not None:
+            pb = t.as_tensor(dL_dparticles, dtype=t.float64).to(self.device).contiguous()
+            if tuple(pb.shape) != (4, self.P):
+                raise ValueError("dL_dparticles must be [4][P]")
+        th = np.zeros(max(1, self.n_theta), dtype=np.float64)
+        p0 = t.empty((4, self.P), dtype=t.float64, device=self.device) if particles_grad else None
+        self.stream.synchronize()
+        st = self.L.wandqs_backward(
+            self.ctx, pr.ctypes.data_as(_dp) if pr is not None else None,
+            C.c_void_p(fb.data_ptr()) if fb is not None else None,
+            C.c_void_p(pb.data_ptr()) if pb is not None else None,
+            th.ctypes.data_as(_dp), C.c_void_p(p0.data_ptr()) if p0 is not None else None)
+        self._check(st)
+        return th[:self.n_theta], p0
+
     def close(self):
         if getattr(self, "ctx", None):
             self.L.wandqs_destroy(self.ctx)
@@ -279,3 +360,37 @@ class Simulation:
             self.close()
         except Exception:
             pass
+
+
+_probe_fn = None
+
+
+def run_probes(theta, cfg: dict, n_slices: int, checkpoint_every: int = 32):
+    """Differentiable probe values of a run from the cold plasma: a torch
+    function of theta (the driver parameters, see theta_of) whose backward is
+    the library's reverse sweep.  Returns a float64 tensor [n_probes] on the
+    GPU."""
+    global _probe_fn
+    import torch
+    if _probe_fn is None:
+        class _ProbeRun(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, th, cfg, n, K):
+                c = with_theta(dict(cfg, checkpoint_every=int(K)), th.detach().cpu().numpy())
+                sim = Simulation(c, n_slices=n)
+                _, pr = sim.run(n, probes=True)
+                ctx.sim = sim
+                ctx.th_device = th.device
+                return pr[:len(cfg["probes"])].clone()
+
+            @staticmethod
+            def backward(ctx, g):
+                sim = ctx.sim
+                try:
+                    th, _ = sim.backward(dL_dprobe=g.detach().cpu().numpy())
+                finally:
+                    sim.close()
+                return (torch.as_tensor(th, dtype=torch.float64, device=ctx.th_device),
+                        None, None, None)
+        _probe_fn = _ProbeRun
+    return _probe_fn.apply(theta, cfg, int(n_slices), int(checkpoint_every))

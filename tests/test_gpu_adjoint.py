@@ -1,0 +1,213 @@
+"""GPU reverse sweep (wandqs_backward through the C ABI) against the oracle's
+adjoint, and against central finite differences of the GPU forward map.
+
+The oracle's adjoint is pinned by finite differences of the oracle forward
+(tests/test_oracle_adjoint.py).  Here the GPU gradients must match the
+oracle's to 1e-8 relative (both solve every system to the rounding floor, so
+the only differences are summation order and the multigrid's initial
+guesses), and the FD check on the full C4 case holds to 1e-5.
+"""
+import numpy as np
+import pytest
+
+import wandqs_inputs as wi
+
+pytestmark = pytest.mark.gpu
+
+ADJ_TOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _sim(cfg, n_slices):
+    from paper_2012_00881_amd import Simulation
+    print(f"[case] adjoint N={cfg['n_cells']} K={cfg.get('checkpoint_every')} slices={n_slices} "
+          f"beams={[b['kind'] for b in cfg['beams']]}", flush=True)
+    return Simulation(cfg, n_slices=n_slices)
+
+
+def _small_cfg(**kw):
+    """The oracle pin's small case: Gaussian driver plus a radial-bin beam."""
+    cfg = wi.scaled(wi.config("C2"), n_cells=32, half_width=4.0, jitter=0.25, dxi0=0.02,
+                    adaptive=0)
+    cfg["beams"][0].update(amp=2.0, sigma_r=0.5, sigma_z=0.7)
+    cfg["beams"].append(wi.radial_bins_beam([0.3, 0.7, 0.2], 1.2, 0.6, 2.1, x0=0.3))
+    return wi.scaled(cfg, **kw)
+
+
+def _c4_small(N=32, L=4.0, n_bins=8, **kw):
+    """Radial-bin driver (C4 recipe) on a small grid: 40 slices, a probe of the
+    mean Ez on a disc over slices 30..39."""
+    h = 2 * L / N
+    amps = 0.5 + 1.5 * wi.uniform01(40, n_bins)
+    cfg = wi.scaled(wi.config("C4"), n_cells=N, half_width=L, dxi0=0.05,
+                    beams=[wi.radial_bins_beam(amps, n_bins * h, 0.8, 1.0)],
+                    probes=[dict(field=1, slice_begin=30, slice_end=40, r_max=0.5, x0=0.0, y0=0.0)])
+    return wi.scaled(cfg, **kw)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_slice_adjoint_matches_oracle(torch_cuda, oracle_mod, seed):
+    """One taped slice from a synthetic state, random adjoints on every output
+    (particles and all five fields): input-particle and theta adjoints."""
+    cfg = _small_cfg(checkpoint_every=1)
+    N = cfg["n_cells"]
+    st0 = wi.synthetic_state(cfg, seed=3 + seed, p_max=0.3, xi=2.0)
+    P = st0["x"].size
+    orc = oracle_mod.Oracle(cfg)
+    ost = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in st0.items()}
+    assert orc.slice_step(ost)["status"] == 0
+    F0 = ost["fields"].copy()
+    rng = np.random.default_rng(seed)
+    abar = rng.standard_normal((4, P))
+    Fbar = rng.standard_normal((5, N + 1, N + 1))
+    Fbar[:, [0, -1], :] = 0
+    Fbar[:, :, [0, -1]] = 0
+    so, ib, tb = orc.slice_adjoint(st0, F0, abar, Fbar)
+    assert so == 0
+
+    sim = _sim(cfg, 1)
+    sim.set_state(particles=np.stack([st0["x"], st0["y"], st0["px"], st0["py"]]),
+                  fields=st0["fields"], xi=st0["xi"], dxi=st0["dxi"])
+    sim.step()
+    assert sim.tape_slices() == 1
+    th, p0 = sim.backward(dL_dfields=Fbar[None], dL_dparticles=abar, particles_grad=True)
+    p0 = p0.cpu().numpy()
+    errs = [_rel(p0[k], ib[k]) for k in range(4)]
+    print("slice adjoint rel errors x, y, px, py:", errs, "theta:", _rel(th, tb))
+    assert max(errs) <= ADJ_TOL, errs
+    assert _rel(th, tb) <= ADJ_TOL, (th, tb)
+    sim.close()
+
+
+@pytest.mark.parametrize("K", [1, 7, 16, 64])
+def test_run_gradient_matches_oracle(torch_cuda, oracle_mod, K):
+    """dL/dtheta of the probe loss through 40 slices from the cold plasma, for
+    checkpoint intervals that divide the run, do not divide it, and exceed it."""
+    cfg = _c4_small(checkpoint_every=K)
+    so, L0, g0 = oracle_mod.Oracle(cfg).run_loss(oracle_mod.initial_state(cfg), 40, grad=True)
+    assert so == 0
+    sim = _sim(cfg, 40)
+    _, pr = sim.run(40, probes=True)
+    val = float(pr[0])
+    th, _ = sim.backward(dL_dprobe=[1.0])
+    print(f"K={K} probe {val:.15e} oracle {L0:.15e}; grad rel err {_rel(th, g0):.3e}")
+    assert abs(val - L0) <= 1e-10 * max(1.0, abs(L0))
+    assert _rel(th, g0) <= ADJ_TOL, (th, g0)
+    sim.close()
+
+
+def test_run_gradient_gauss_and_bins_weighted(torch_cuda, oracle_mod):
+    """Two probes with weights, a Gaussian and a radial-bin beam, run from a
+    state whose tape starts at set_state."""
+    cfg = _small_cfg(checkpoint_every=5,
+                     probes=[dict(field=1, slice_begin=5, slice_end=20, r_max=0.6, x0=0.0, y0=0.0),
+                             dict(field=3, slice_begin=10, slice_end=25, r_max=1.0, x0=0.4, y0=-0.2)])
+    w = np.array([0.7, -1.3])
+    n = 25
+    so, L0, g0 = oracle_mod.Oracle(cfg).run_loss(oracle_mod.initial_state(cfg), n, weights=w,
+                                                  grad=True)
+    assert so == 0
+    sim = _sim(cfg, n)
+    _, pr = sim.run(n, probes=True)
+    th, _ = sim.backward(dL_dprobe=w)
+    val = float((pr[:2].cpu().numpy() * w).sum())
+    print("weighted probes", val, L0, "grad", th, g0)
+    assert abs(val - L0) <= 1e-10 * max(1.0, abs(L0))
+    assert _rel(th, g0) <= ADJ_TOL
+    sim.close()
+
+
+def test_backward_leaves_state_unchanged(torch_cuda):
+    """After a backward sweep the context continues exactly as without it."""
+    cfg = _c4_small(checkpoint_every=8)
+    outs = []
+    for do_bwd in (False, True):
+        sim = _sim(cfg, 60)
+        sim.run(40, probes=True)
+        if do_bwd:
+            before = sim.get_state()
+            sim.backward(dL_dprobe=[1.0])
+            after = sim.get_state()
+            assert torch_cuda.equal(before["particles"], after["particles"])
+            assert torch_cuda.equal(before["fields"], after["fields"])
+            assert before["xi"] == after["xi"] and before["dxi"] == after["dxi"]
+        sim.run(20)
+        g = sim.get_state()
+        outs.append((g["particles"].cpu().numpy(), g["fields"].cpu().numpy()))
+        sim.close()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_backward_errors(torch_cuda):
+    from paper_2012_00881_amd import WandQSError
+    cfg = _c4_small(checkpoint_every=0)
+    sim = _sim(cfg, 4)
+    sim.run(4, probes=True)
+    with pytest.raises(WandQSError) as e:
+        sim.backward(dL_dprobe=[1.0])
+    assert e.value.status == -6
+    sim.close()
+    cfg = _c4_small(checkpoint_every=2)
+    sim = _sim(cfg, 4)
+    sim.run(4)
+    with pytest.raises(WandQSError) as e:  # past the tape capacity
+        sim.run(2)
+        sim.backward(dL_dprobe=[1.0])
+    assert e.value.status == -6
+    sim.close()
+
+
+def test_autograd_function(torch_cuda, oracle_mod):
+    """run_probes as a torch function of theta: its gradient is the oracle's."""
+    from paper_2012_00881_amd import run_probes, theta_of
+    torch = torch_cuda
+    cfg = _c4_small()
+    th = torch.tensor(theta_of(cfg), dtype=torch.float64, device="cuda", requires_grad=True)
+    pr = run_probes(th, cfg, 40, checkpoint_every=16)
+    (2.0 * pr.sum()).backward()
+    _, _, g0 = oracle_mod.Oracle(cfg).run_loss(oracle_mod.initial_state(cfg), 40, grad=True)
+    assert _rel(th.grad.cpu().numpy(), 2.0 * g0) <= ADJ_TOL
+
+
+def test_c4_full_gradient_matches_finite_differences(torch_cuda):
+    """The radial-bin gradient case at full size (256^2, 4 particles per cell,
+    32 bin amplitudes, probe of mean Ez over slices 300..350 of a 351-slice
+    run, checkpoints every 32): adjoint directional derivatives against central
+    differences of the GPU forward along random directions, 1e-5 relative."""
+    from paper_2012_00881_amd import Simulation, theta_of, with_theta
+    cfg = wi.config("C4")
+    n = cfg["probes"][0]["slice_end"]
+    th0 = theta_of(cfg)
+
+    def probe(th):
+        print(f"[case] C4 forward {n} slices", flush=True)
+        s = Simulation(with_theta(dict(cfg, checkpoint_every=0), th), n_slices=n)
+        _, pr = s.run(n, probes=True)
+        v = float(pr[0])
+        s.close()
+        return v
+
+    sim = _sim(cfg, n)
+    _, pr = sim.run(n, probes=True)
+    g, _ = sim.backward(dL_dprobe=[1.0])
+    sim.close()
+    rng = np.random.default_rng(44)
+    eps = 1e-6
+    for _ in range(2):
+        d = rng.standard_normal(th0.size)
+        fd = (probe(th0 + eps * d) - probe(th0 - eps * d)) / (2 * eps)
+        ad = float(g @ d)
+        print(f"C4 directional derivative: adjoint {ad:.10e} FD {fd:.10e}")
+        assert abs(ad - fd) <= 1e-5 * np.abs(g * d).sum()

@@ -222,3 +222,44 @@ def test_nonphysical_is_an_error(torch_cuda):
         sim.step()
     assert e2.value.status == -6
     sim.close()
+
+
+def test_run_radial_bins_matches_oracle(torch_cuda, oracle_mod):
+    """Radial-bin driver (bin width = h, so bin edges pass through grid nodes)
+    over 60 slices, with a probe: fields, particles and the probe value."""
+    N, L = 64, 4.0
+    h = 2 * L / N
+    amps = 0.5 + 1.5 * wi.uniform01(40, 16)
+    cfg = wi.scaled(wi.config("C4"), n_cells=N, half_width=L, dxi0=0.05,
+                    beams=[wi.radial_bins_beam(amps, 16 * h, 0.8, 1.0)],
+                    probes=[dict(field=1, slice_begin=30, slice_end=60, r_max=4 * h, x0=0.0,
+                                 y0=0.0)])
+    n = 60
+    orc = oracle_mod.Oracle(cfg)
+    st = oracle_mod.initial_state(cfg)
+    so, L0, _ = orc.run_loss(st, n)
+    assert so == 0
+    sim = _sim(cfg, n)
+    _, pr = sim.run(n, probes=True)
+    got = sim.get_state()
+    errs = field_errors(got["fields"].cpu().numpy(), st["fields"])
+    print("radial-bin run errors", errs, "probe", float(pr[0]), L0)
+    assert np.all(errs <= FIELD_TOL), errs
+    assert np.abs(got["particles"].cpu().numpy() - _particles(st)).max() <= 1e-10
+    assert abs(float(pr[0]) - L0) <= 1e-10 * max(1.0, abs(L0))
+    sim.close()
+
+
+@pytest.mark.parametrize("N", [32, 256])
+@pytest.mark.parametrize("helm", [False, True])
+def test_mg_zero_rhs_nonzero_guess(torch_cuda, N, helm):
+    """f = 0 from a nonzero guess stops on the initial-residual rule with u ~ 0."""
+    L = 6.0
+    cfg = wi.scaled(wi.config("C1"), n_cells=N, half_width=L)
+    sim = _sim(cfg)
+    u0 = _rand_rhs(N, 300 + N, 2)
+    k2 = np.random.default_rng(8).uniform(0.0, 30.0, (N + 1, N + 1)) if helm else None
+    st, u, cyc, relres = sim.mg_solve(np.zeros_like(u0), u0=u0, k2=k2)
+    assert st == 0 and cyc < 30, (st, cyc)
+    assert float(u.abs().max()) <= 1e-12 * np.abs(u0).max()
+    sim.close()

@@ -145,3 +145,18 @@ def test_noconv_reported(oracle_mod):
     f[1:-1, 1:-1] = 1.0
     st, u, cyc, rel = oracle_mod.mg_solve(N, h, f, rtol=1e-30, atol=0.0, max_cycles=1)
     assert st == oracle_mod.NOCONV and cyc == 1
+
+
+@pytest.mark.parametrize("helm", [False, True])
+def test_zero_rhs_with_nonzero_guess(oracle_mod, helm):
+    """f = 0 has the solution 0: from a nonzero initial guess the solve must stop
+    (relative to the initial residual) with u ~ rtol * |u0|, not run out of cycles."""
+    N, L = 64, 6.0
+    h = 2 * L / N
+    rng = np.random.default_rng(5)
+    u0 = np.zeros((N + 1, N + 1))
+    u0[1:-1, 1:-1] = rng.standard_normal((N - 1, N - 1))
+    k2 = rng.uniform(0.0, 30.0, (N + 1, N + 1)) if helm else None
+    st, u, cyc, rel = oracle_mod.mg_solve(N, h, np.zeros_like(u0), u0=u0, k2=k2)
+    assert st == 0 and cyc < 30
+    assert np.abs(u).max() <= 1e-12 * np.abs(u0).max()
