@@ -73,6 +73,49 @@ def cpu_baseline(cfg: dict, n_slices: int):
                        f"(single-threaded FP64 oracle, {dt:.1f} s, status {r['status']})")
 
 
+def adjoint_timing(cfg: dict, S: int, K: int):
+    """Forward without tape, forward with the tape (checkpoint every K) and the
+    reverse sweep over the same S slices from the cold plasma.  Loss: the mean
+    Ez on a disc over the last S/4 slices plus a random linear function of the
+    final particles, so every slice carries nonzero adjoints."""
+    import numpy as np
+    import torch
+    from paper_2012_00881_amd import Simulation
+    probe = dict(field=1, slice_begin=S - S // 4, slice_end=S, r_max=0.5, x0=0.0, y0=0.0)
+    res = {"slices": S, "checkpoint_every": K}
+    for taped in (False, True):
+        c = dict(cfg, probes=[probe], checkpoint_every=K if taped else 0)
+        print(f"[bench] adjoint: forward {S} slices, tape {'on' if taped else 'off'}",
+              file=sys.stderr, flush=True)
+        sim = Simulation(c, n_slices=S)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.run(S, probes=True)
+        torch.cuda.synchronize()
+        res["forward_taped_s" if taped else "forward_s"] = time.perf_counter() - t0
+        if not taped:
+            sim.close()
+            del sim
+            continue
+        pbar = torch.as_tensor(np.random.default_rng(1).standard_normal((4, sim.P)),
+                               device="cuda")
+        print(f"[bench] adjoint: reverse sweep", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        th, _ = sim.backward(dL_dprobe=[1.0], dL_dparticles=pbar)
+        torch.cuda.synchronize()
+        res["backward_s"] = time.perf_counter() - t0
+        res["dL_dtheta"] = [float(v) for v in th]
+        sim.close()
+        del sim
+    res["backward_over_forward"] = res["backward_s"] / res["forward_s"]
+    res["ms_per_slice_backward"] = 1e3 * res["backward_s"] / S
+    res["tape_overhead"] = res["forward_taped_s"] / res["forward_s"] - 1.0
+    print(f"[bench] adjoint: forward {res['forward_s']:.3f} s, taped {res['forward_taped_s']:.3f} s, "
+          f"backward {res['backward_s']:.3f} s ({res['backward_over_forward']:.2f}x forward)",
+          file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +132,9 @@ def main():
     ap.add_argument("--inner", type=int, default=0, help="mixed: FP32 cycles per correction")
     ap.add_argument("--forms-steps", type=int, default=1024,
                     help="slices for the FP64-vs-mixed comparison at 1e-6 (0: skip)")
+    ap.add_argument("--adjoint-steps", type=int, default=512,
+                    help="slices of the taped forward + reverse sweep (0: skip)")
+    ap.add_argument("--checkpoint-every", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the slice step is not sharded "
@@ -210,6 +256,10 @@ def main():
         print(f"[bench] mixed speedup at 1e-6: {forms['mixed_speedup']:.3f}", file=sys.stderr,
               flush=True)
 
+    adjoint = None
+    if args.adjoint_steps > 0:
+        adjoint = adjoint_timing(cfg, args.adjoint_steps, args.checkpoint_every)
+
     cpu = None
     if not args.no_cpu_baseline:
         print(f"[bench] CPU oracle on {args.cpu_slices} slices", file=sys.stderr, flush=True)
@@ -225,7 +275,7 @@ def main():
                        "precision": args.precision, "mg_rtol": cfg["mg_rtol"],
                        "xi_end": final["xi"],
                        "mean_vcycles": [round(c, 3) for c in cyc]},
-            "roofline": roof, "cpu_baseline": cpu, "forms": forms}
+            "roofline": roof, "cpu_baseline": cpu, "forms": forms, "adjoint": adjoint}
     print(json.dumps(line), flush=True)
 
 
