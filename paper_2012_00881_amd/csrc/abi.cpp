@@ -132,7 +132,7 @@ size_t node_bytes(const wandqs_ctx* c) {
 }
 
 // Checkpoint of the slice-loop state: particles (storage order), the fields
-// and the previous slice's fields (initial guesses), [xi, dxi, xi_u, xi_prev],
+// and the two previous slices' fields (initial guesses), the xi state,
 // the batch predictions and the extrapolation count.  A recompute from it
 // repeats the same arithmetic, bit for bit.
 wandqs_status save_checkpoint(wandqs_ctx* c, wq::Checkpoint& k) {
@@ -145,8 +145,9 @@ wandqs_status save_checkpoint(wandqs_ctx* c, wq::Checkpoint& k) {
     for (int q = 0; q < 5; ++q) {
         if ((s = copy_d2d(c, k.fields[q], c->fields[q], nb)) != WANDQS_OK) return s;
         if ((s = copy_d2d(c, k.fields_prev[q], c->fields_prev[q], nb)) != WANDQS_OK) return s;
+        if ((s = copy_d2d(c, k.fields_prev2[q], c->fields_prev2[q], nb)) != WANDQS_OK) return s;
     }
-    if ((s = copy_d2d(c, k.st, c->st, 4 * sizeof(double))) != WANDQS_OK) return s;
+    if ((s = copy_d2d(c, k.st, c->st, 5 * sizeof(double))) != WANDQS_OK) return s;
     std::memcpy(k.pred, c->pred, sizeof(k.pred));
     k.n_guess = c->n_guess;
     return WANDQS_OK;
@@ -162,8 +163,9 @@ wandqs_status restore_checkpoint(wandqs_ctx* c, const wq::Checkpoint& k) {
     for (int q = 0; q < 5; ++q) {
         if ((s = copy_d2d(c, c->fields[q], k.fields[q], nb)) != WANDQS_OK) return s;
         if ((s = copy_d2d(c, c->fields_prev[q], k.fields_prev[q], nb)) != WANDQS_OK) return s;
+        if ((s = copy_d2d(c, c->fields_prev2[q], k.fields_prev2[q], nb)) != WANDQS_OK) return s;
     }
-    if ((s = copy_d2d(c, c->st, k.st, 4 * sizeof(double))) != WANDQS_OK) return s;
+    if ((s = copy_d2d(c, c->st, k.st, 5 * sizeof(double))) != WANDQS_OK) return s;
     std::memcpy(c->pred, k.pred, sizeof(k.pred));
     c->n_guess = k.n_guess;
     return WANDQS_OK;
@@ -183,9 +185,9 @@ wandqs_status do_slice(wandqs_ctx* c, int rec_slot, int64_t probe_slice, bool ta
         if (k >= c->n_ckpt - 1) c->tape_ok = false;  // past the capacity given at init
         else if ((s = save_checkpoint(c, c->ckpt[k])) != WANDQS_OK) return s;
     }
-    // initial guesses: linear extrapolation of the last two slices' fields once
-    // two are known, else the previous slice's fields (Sec. VII.A)
-    if ((s = extrapolate_guess(c, c->n_guess >= 2)) != WANDQS_OK) return s;
+    // initial guesses: the previous slice's fields (Sec. VII.A), extrapolated in
+    // xi through the last two or three slices once they are known
+    if ((s = extrapolate_guess(c, c->n_guess < 3 ? c->n_guess - 1 : 2)) != WANDQS_OK) return s;
     if ((s = slice_sort(c)) != WANDQS_OK) return s;
     if (rec) {
         const size_t pb = sizeof(double) * (size_t)c->P;
@@ -220,7 +222,7 @@ wandqs_status do_slice(wandqs_ctx* c, int rec_slot, int64_t probe_slice, bool ta
     }
     if (!c->probes.empty() && (s = probes_accumulate(c, probe_slice)) != WANDQS_OK) return s;
     if ((s = push_and_step(c, rec_slot)) != WANDQS_OK) return s;  // Push_Trajectory + Step_Size_Refinement
-    if (c->n_guess < 2) ++c->n_guess;
+    if (c->n_guess < 3) ++c->n_guess;
     if (taping) ++c->tape_n;
     return WANDQS_OK;
 }
@@ -261,6 +263,7 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
     Level& L0 = c->lev[0];
     for (int k = 0; k < 5; ++k) c->fields[k] = arr(0);
     for (int k = 0; k < 5; ++k) c->fields_prev[k] = arr(0);
+    for (int k = 0; k < 5; ++k) c->fields_prev2[k] = arr(0);
     for (int r = 0; r < 2; ++r) {
         L0.um[r] = arr(0);
         L0.f[r] = arr(0);
@@ -305,7 +308,7 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
     c->cell_count = (int32_t*)take(sizeof(int32_t) * ncell);
     c->cell_start = (int32_t*)take(sizeof(int32_t) * (ncell + 1));
     c->scan_blk = (int32_t*)take(sizeof(int32_t) * c->n_scan_blocks);
-    c->st = (double*)take(sizeof(double) * 4);
+    c->st = (double*)take(sizeof(double) * 8);
     c->vmax_part = (double*)take(sizeof(double) * c->n_push_blocks);
     c->flags = (int32_t*)take(sizeof(int32_t) * 4);
     c->norm_part = (double*)take(sizeof(double) * kMaxSlots * 4 * (size_t)c->max_tiles);
@@ -323,8 +326,9 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
             for (int q = 0; q < 5; ++q) {
                 k.fields[q] = arr(0);
                 k.fields_prev[q] = arr(0);
+                k.fields_prev2[q] = arr(0);
             }
-            k.st = (double*)take(sizeof(double) * 4);
+            k.st = (double*)take(sizeof(double) * 8);
         }
         c->slot.assign(std::min(c->tape_K, c->rec_cap), TapeSlot{});
         for (auto& t : c->slot) {
@@ -539,7 +543,7 @@ wandqs_status wandqs_init(const wandqs_config* cfg, int32_t n_slices, void* d_wo
                     host[c->P + i] = -L + h * (((double)b + ((double)sy + 0.5) / s) + J * (2.0 * uy - 1.0));
                     ids[i] = (int32_t)i;
                 }
-    const double st0[4] = {0.0, cfg->dxi0, 0.0, 0.0};
+    const double st0[5] = {0.0, cfg->dxi0, 0.0, 0.0, 0.0};
     bool ok = hipMemcpyAsync(c->pa[0][0], host.data(), sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
               hipMemcpyAsync(c->pa[0][1], host.data() + c->P, sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
               hipMemcpyAsync(c->pid[0], ids.data(), sizeof(int32_t) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&

@@ -568,11 +568,11 @@ wandqs_status adj_zero_solutions(wandqs_ctx* c) {
     double* arr[5] = {A.lx, A.ly, A.lE, A.lB, A.lpsi};
     for (double* p : arr) {
         ProfScope ps(c, "k_zero", 8.0 * nn);
-        hipLaunchKernelGGL(k_zero, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, c->stream, p, nn);
+        WQ_KLAUNCH(ps, k_zero, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, c->stream, p, nn);
     }
     if (c->n_theta > 0) {
         ProfScope ps(c, "k_zero", 8.0 * c->n_theta);
-        hipLaunchKernelGGL(k_zero, dim3((unsigned)((c->n_theta + 255) / 256)), dim3(256), 0, c->stream,
+        WQ_KLAUNCH(ps, k_zero, dim3((unsigned)((c->n_theta + 255) / 256)), dim3(256), 0, c->stream,
                            A.theta_bar, (size_t)c->n_theta);
     }
     WQ_LAUNCH_CHECK();
@@ -596,18 +596,18 @@ wandqs_status slice_adjoint(wandqs_ctx* c, const TapeSlot& ts, const double* d_f
                       ts.start, ts.fields[0], ts.fields[3], ts.fields[4], ts.fields[2], ts.st,
                       A.adj_id, A.xb, A.yb, A.pxb, A.pyb, A.gb, A.Gxb, A.Gyb, A.Bxb, A.Byb, A.Bzb};
         ProfScope ps(c, "k_push_adj<16>", P * 108.0 + nnd * 76.0);
-        hipLaunchKernelGGL(k_push_adj, dim3(nt, nt), dim3(256), 0, s, a);
+        WQ_KLAUNCH(ps, k_push_adj, dim3(nt, nt), dim3(256), 0, s, a);
     }
     {
         ProfScope ps(c, "k_grad_adj", nnd * 64.0);
-        hipLaunchKernelGGL(k_grad_adj, ng, dim3(128), 0, s, N, c->h, pitch, A.Gxb, A.Gyb, A.psib,
+        WQ_KLAUNCH(ps, k_grad_adj, ng, dim3(128), 0, s, N, c->h, pitch, A.Gxb, A.Gyb, A.psib,
                            A.Bxb, A.Byb, A.Bzb, A.Ezb);
     }
     double* Fb[5] = {A.psib, A.Ezb, A.Bzb, A.Bxb, A.Byb};
     if (d_field_bar) {
         FieldBar fb{{Fb[0], Fb[1], Fb[2], Fb[3], Fb[4]}};
         ProfScope ps(c, "k_field_seed", nnd * 120.0);
-        hipLaunchKernelGGL(k_field_seed, ng, dim3(128), 0, s, N, pitch, d_field_bar, fb);
+        WQ_KLAUNCH(ps, k_field_seed, ng, dim3(128), 0, s, N, pitch, d_field_bar, fb);
     }
     for (size_t k = 0; k < c->probes.size(); ++k)
         if (probe_w && probe_w[k] != 0.0 && (st = probe_seed(c, (int)k, probe_w[k], Fb)) != WANDQS_OK)
@@ -626,21 +626,21 @@ wandqs_status slice_adjoint(wandqs_ctx* c, const TapeSlot& ts, const double* d_f
                   A.Ezb, A.Bzb, A.psib, A.jzb};
     {
         ProfScope ps(c, "k_asm_adj_local", nnd * 200.0);
-        hipLaunchKernelGGL(k_asm_adj_local, ng, dim3(128), 0, s, aa);
+        WQ_KLAUNCH(ps, k_asm_adj_local, ng, dim3(128), 0, s, aa);
     }
     {
         ProfScope ps(c, "k_asm_adj_diff", nnd * 152.0);
-        hipLaunchKernelGGL(k_asm_adj_diff, ng, dim3(128), 0, s, aa);
+        WQ_KLAUNCH(ps, k_asm_adj_diff, ng, dim3(128), 0, s, aa);
     }
     if (c->n_seg > 0) {
         {
             ProfScope ps(c, "k_theta_seg", nnd * 8.0);
-            hipLaunchKernelGGL(k_theta_seg, dim3(c->n_seg), dim3(256), 0, s, N, c->L, c->h, pitch,
+            WQ_KLAUNCH(ps, k_theta_seg, dim3(c->n_seg), dim3(256), 0, s, N, c->L, c->h, pitch,
                                A.seg, A.bin_nodes, A.jzb, c->beamset, A.theta_part);
         }
         {
             ProfScope ps(c, "k_theta_reduce", 8.0 * c->n_seg + 16.0 * c->n_theta);
-            hipLaunchKernelGGL(k_theta_reduce, dim3((c->n_theta + 255) / 256), dim3(256), 0, s,
+            WQ_KLAUNCH(ps, k_theta_reduce, dim3((c->n_theta + 255) / 256), dim3(256), 0, s,
                                c->n_theta, A.seg, A.seg_first, A.theta_part, ts.st, c->beamset,
                                A.theta_bar);
         }
@@ -653,18 +653,18 @@ wandqs_status slice_adjoint(wandqs_ctx* c, const TapeSlot& ts, const double* d_f
     if ((st = mg_solve(c, kSolveEBAdj, 2, false, ue, fe, nullptr, &res)) != WANDQS_OK) return st;
     {
         ProfScope ps(c, "k_EB_adj", nnd * 48.0);
-        hipLaunchKernelGGL(k_EB_adj, ng, dim3(128), 0, s, N, c->h, pitch, A.lE, A.lB, A.jxb, A.jyb);
+        WQ_KLAUNCH(ps, k_EB_adj, ng, dim3(128), 0, s, N, c->h, pitch, A.lE, A.lB, A.jxb, A.jyb);
     }
     {
         DepAdjArgs d{N, c->L, c->h, wd, pitch, ts.pa[0], ts.pa[1], ts.pa[2], ts.pa[3], ts.start,
                      ts.fields[0], A.jxb, A.jyb, A.txxb, A.txyb, A.tyyb, A.gb, A.xb, A.yb, A.pxb,
                      A.pyb, A.psib_dep};
         ProfScope ps(c, "k_dep_adj<16>", P * 104.0 + nnd * 60.0);
-        hipLaunchKernelGGL(k_dep_adj, dim3(nt, nt), dim3(256), 0, s, d);
+        WQ_KLAUNCH(ps, k_dep_adj, dim3(nt, nt), dim3(256), 0, s, d);
     }
     {
         ProfScope ps(c, "k_add_interior", nnd * 24.0);
-        hipLaunchKernelGGL(k_add_interior, ng, dim3(128), 0, s, N, pitch, A.psib, A.psib_dep);
+        WQ_KLAUNCH(ps, k_add_interior, ng, dim3(128), 0, s, N, pitch, A.psib, A.psib_dep);
     }
     WQ_LAUNCH_CHECK();
 
@@ -674,7 +674,7 @@ wandqs_status slice_adjoint(wandqs_ctx* c, const TapeSlot& ts, const double* d_f
     if ((st = mg_solve(c, kSolvePsiAdj, 1, false, up, fp, nullptr, &res)) != WANDQS_OK) return st;
     {
         ProfScope ps(c, "k_n_adj_out", P * 84.0 + nnd * 16.0);
-        hipLaunchKernelGGL(k_n_adj_out, dim3((unsigned)((c->P + 255) / 256)), dim3(256), 0, s, c->P,
+        WQ_KLAUNCH(ps, k_n_adj_out, dim3((unsigned)((c->P + 255) / 256)), dim3(256), 0, s, c->P,
                            N, c->L, c->h, wd, pitch, ts.pa[0], ts.pa[1], ts.pid, A.nb, A.lpsi, A.xb,
                            A.yb, A.pxb, A.pyb, A.adj_id);
     }

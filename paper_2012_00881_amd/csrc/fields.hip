@@ -169,28 +169,40 @@ __global__ void k_unpack(int N, int pitch, const double* __restrict__ src, doubl
     dst[(size_t)b * pitch + a] = bnd ? 0.0 : src[(size_t)b * (N + 1) + a];
 }
 
-// Initial guesses for the five solves of this slice.  prev <- u (fields of the
-// last slice) and, when extrapolating, u <- u + t (u - prev_old) with
-// t = (xi - xi_u) / (xi_u - xi_prev) from the device state.
+// Initial guesses for the five solves of this slice: the fields u of the last
+// slice (at xi_u), extrapolated to xi through the slices before (p1 at xi_1,
+// p2 at xi_2) -- order 0: u; order 1: the line through u and p1; order 2: the
+// parabola through u, p1 and p2 (Lagrange form).  The guess goes to `out`
+// (p2's array, which the host then rotates into the field's place).
 struct FieldPtrs {
-    double* u[5];
-    double* p[5];
+    const double* u[5];
+    const double* p1[5];
+    const double* p2[5];
+    double* out[5];
 };
 
 __global__ void k_extrapolate(int N, int pitch, const double* __restrict__ st, FieldPtrs f,
-                              int extrapolate) {
+                              int order) {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
     if (a > N) return;
     const size_t g = (size_t)b * pitch + a;
-    const double den = st[2] - st[3];
-    const double t = (extrapolate && den != 0.0) ? (st[0] - st[2]) / den : 0.0;
+    const double xi = st[0], x0 = st[2], x1 = st[3], x2 = st[4];
+    if (order >= 2 && (x0 == x1 || x0 == x2 || x1 == x2)) order = 1;
+    if (order == 1 && x0 == x1) order = 0;
+    double t = 0.0, w1 = 0.0, w2 = 0.0;
+    if (order == 1) t = (xi - x0) / (x0 - x1);
+    if (order == 2) {
+        w1 = (xi - x0) * (xi - x2) / ((x1 - x0) * (x1 - x2));
+        w2 = (xi - x0) * (xi - x1) / ((x2 - x0) * (x2 - x1));
+    }
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
         const double u = f.u[k][g];
-        const double q = f.p[k][g];
-        f.p[k][g] = u;
-        f.u[k][g] = extrapolate ? u + t * (u - q) : u;
+        double v = u;
+        if (order == 1) v = u + t * (u - f.p1[k][g]);
+        if (order == 2) v = u + (w1 * (f.p1[k][g] - u) + w2 * (f.p2[k][g] - u));
+        f.out[k][g] = v;
     }
 }
 
@@ -207,7 +219,7 @@ wandqs_status rhs_EB(wandqs_ctx* c) {
     const Level& L0 = c->lev[0];
     {
         ProfScope ps(c, "k_rhs_EB", (double)(c->N + 1) * (c->N + 1) * 32.0);
-        hipLaunchKernelGGL(k_rhs_EB, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->h, L0.pitch,
+        WQ_KLAUNCH(ps, k_rhs_EB, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->h, L0.pitch,
                            c->mom[1], c->mom[2], L0.f[0], L0.f[1]);
     }
     WQ_LAUNCH_CHECK();
@@ -218,13 +230,13 @@ wandqs_status assemble(wandqs_ctx* c) {
     const Level& L0 = c->lev[0];
     {
         ProfScope ps(c, "k_jz", (double)(c->N + 1) * (c->N + 1) * 40.0);
-        hipLaunchKernelGGL(k_jz, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->L, c->h, L0.pitch,
+        WQ_KLAUNCH(ps, k_jz, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->L, c->h, L0.pitch,
                            c->mom[0], c->mom[3], c->mom[5], c->fields[0], c->st, c->beamset, c->jz,
                            c->flags);
     }
     {
         ProfScope ps(c, "k_assemble", (double)(c->N + 1) * (c->N + 1) * 104.0);
-        hipLaunchKernelGGL(k_assemble, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->h, L0.pitch,
+        WQ_KLAUNCH(ps, k_assemble, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->h, L0.pitch,
                            c->mom[0], c->mom[1], c->mom[2], c->mom[3], c->mom[4], c->mom[5],
                            c->fields[0], c->fields[1], c->fields[2], c->jz, L0.k2, L0.f[0], L0.f[1]);
     }
@@ -239,7 +251,7 @@ wandqs_status probes_accumulate(wandqs_ctx* c, int64_t slice) {
         const double scale = 1.0 / (double)(p.slice_end - p.slice_begin);
         {
             ProfScope ps(c, "k_probe", (double)(c->N + 1) * (c->N + 1) * 8.0);
-            hipLaunchKernelGGL(k_probe, dim3(1), dim3(256), 0, c->stream, c->N, c->L, c->h,
+            WQ_KLAUNCH(ps, k_probe, dim3(1), dim3(256), 0, c->stream, c->N, c->L, c->h,
                                c->lev[0].pitch, c->fields[p.field], p.x0, p.y0, p.r_max, scale,
                                c->probe_acc + k);
         }
@@ -252,7 +264,7 @@ wandqs_status probe_seed(wandqs_ctx* c, int k, double w, double* const* Fb) {
     const wandqs_probe& p = c->probes[k];
     {
         ProfScope ps(c, "k_probe_seed", (double)(c->N + 1) * (c->N + 1) * 16.0);
-        hipLaunchKernelGGL(k_probe_seed, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->L, c->h,
+        WQ_KLAUNCH(ps, k_probe_seed, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->L, c->h,
                            c->lev[0].pitch, p.x0, p.y0, p.r_max, w, Fb[p.field]);
     }
     WQ_LAUNCH_CHECK();
@@ -264,7 +276,7 @@ wandqs_status pack_fields(wandqs_ctx* c, double* const* src, int n, double* dst)
     for (int k = 0; k < n; ++k)
         {
             ProfScope ps(c, "k_pack", (double)(c->N + 1) * (c->N + 1) * 16.0);
-            hipLaunchKernelGGL(k_pack, node_grid(c->N), dim3(128), 0, c->stream, c->N,
+            WQ_KLAUNCH(ps, k_pack, node_grid(c->N), dim3(128), 0, c->stream, c->N,
                                c->lev[0].pitch, src[k], dst + k * nn);
         }
     WQ_LAUNCH_CHECK();
@@ -276,23 +288,34 @@ wandqs_status unpack_fields(wandqs_ctx* c, const double* src, int n, double* con
     for (int k = 0; k < n; ++k)
         {
             ProfScope ps(c, "k_unpack", (double)(c->N + 1) * (c->N + 1) * 16.0);
-            hipLaunchKernelGGL(k_unpack, node_grid(c->N), dim3(128), 0, c->stream, c->N,
+            WQ_KLAUNCH(ps, k_unpack, node_grid(c->N), dim3(128), 0, c->stream, c->N,
                                c->lev[0].pitch, src + k * nn, dst[k]);
         }
     WQ_LAUNCH_CHECK();
     return WANDQS_OK;
 }
 
-wandqs_status extrapolate_guess(wandqs_ctx* c, bool extrapolate) {
+wandqs_status extrapolate_guess(wandqs_ctx* c, int order) {
     FieldPtrs f;
     for (int k = 0; k < 5; ++k) {
         f.u[k] = c->fields[k];
-        f.p[k] = c->fields_prev[k];
+        f.p1[k] = c->fields_prev[k];
+        f.p2[k] = c->fields_prev2[k];
+        f.out[k] = c->fields_prev2[k];
     }
-    ProfScope ps(c, "k_extrapolate", (double)(c->N + 1) * (c->N + 1) * 5 * 32.0);
-    hipLaunchKernelGGL(k_extrapolate, node_grid(c->N), dim3(128), 0, c->stream, c->N,
-                       c->lev[0].pitch, c->st, f, extrapolate ? 1 : 0);
+    order = order < 0 ? 0 : (order > 2 ? 2 : order);
+    {
+        ProfScope ps(c, "k_extrapolate", (double)(c->N + 1) * (c->N + 1) * 5 * 8.0 * (order + 2));
+        WQ_KLAUNCH(ps, k_extrapolate, node_grid(c->N), dim3(128), 0, c->stream, c->N,
+                   c->lev[0].pitch, c->st, f, order);
+    }
     WQ_LAUNCH_CHECK();
+    for (int k = 0; k < 5; ++k) {  // prev2 <- prev, prev <- u, u <- guess
+        double* g = c->fields_prev2[k];
+        c->fields_prev2[k] = c->fields_prev[k];
+        c->fields_prev[k] = c->fields[k];
+        c->fields[k] = g;
+    }
     return WANDQS_OK;
 }
 
@@ -305,7 +328,7 @@ wandqs_status fill_f64(wandqs_ctx* c, double* p, size_t n, double v) {
     if (n == 0) return WANDQS_OK;
     {
         ProfScope ps(c, "k_fill", 8.0 * n);
-        hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, p, n, v);
+        WQ_KLAUNCH(ps, k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, p, n, v);
     }
     WQ_LAUNCH_CHECK();
     return WANDQS_OK;

@@ -682,33 +682,33 @@ __global__ void k_restrict_fw(const double* fine, int pf, double* coarse, int pc
 // ------------------------------------------------------------- dispatch --
 
 template <typename E, int R, bool HELM>
-void launch_down(const DownArgs<E>& a, int nu, dim3 grid, hipStream_t s) {
+void launch_down(const DownArgs<E>& a, int nu, dim3 grid, hipStream_t s, const ProfScope& ps) {
     switch (nu) {
-        case 1: hipLaunchKernelGGL((k_mg_down<E, R, HELM, 1, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_mg_down<E, R, HELM, 2, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_mg_down<E, R, HELM, 3, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
+        case 1: WQ_KLAUNCH(ps, (k_mg_down<E, R, HELM, 1, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
+        case 2: WQ_KLAUNCH(ps, (k_mg_down<E, R, HELM, 2, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
+        default: WQ_KLAUNCH(ps, (k_mg_down<E, R, HELM, 3, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
     }
 }
 
 template <typename E, int R, bool HELM>
-void launch_up(const UpArgs<E>& a, int nu, dim3 grid, hipStream_t s) {
+void launch_up(const UpArgs<E>& a, int nu, dim3 grid, hipStream_t s, const ProfScope& ps) {
     switch (nu) {
-        case 1: hipLaunchKernelGGL((k_mg_up<E, R, HELM, 1, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_mg_up<E, R, HELM, 2, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_mg_up<E, R, HELM, 3, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
+        case 1: WQ_KLAUNCH(ps, (k_mg_up<E, R, HELM, 1, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
+        case 2: WQ_KLAUNCH(ps, (k_mg_up<E, R, HELM, 2, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
+        default: WQ_KLAUNCH(ps, (k_mg_up<E, R, HELM, 3, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
     }
 }
 
 template <typename E>
-void down(int R, bool helm, const DownArgs<E>& a, int nu, dim3 g, hipStream_t s) {
-    if (R == 1) helm ? launch_down<E, 1, true>(a, nu, g, s) : launch_down<E, 1, false>(a, nu, g, s);
-    else helm ? launch_down<E, 2, true>(a, nu, g, s) : launch_down<E, 2, false>(a, nu, g, s);
+void down(int R, bool helm, const DownArgs<E>& a, int nu, dim3 g, hipStream_t s, const ProfScope& ps) {
+    if (R == 1) helm ? launch_down<E, 1, true>(a, nu, g, s, ps) : launch_down<E, 1, false>(a, nu, g, s, ps);
+    else helm ? launch_down<E, 2, true>(a, nu, g, s, ps) : launch_down<E, 2, false>(a, nu, g, s, ps);
 }
 
 template <typename E>
-void up(int R, bool helm, const UpArgs<E>& a, int nu, dim3 g, hipStream_t s) {
-    if (R == 1) helm ? launch_up<E, 1, true>(a, nu, g, s) : launch_up<E, 1, false>(a, nu, g, s);
-    else helm ? launch_up<E, 2, true>(a, nu, g, s) : launch_up<E, 2, false>(a, nu, g, s);
+void up(int R, bool helm, const UpArgs<E>& a, int nu, dim3 g, hipStream_t s, const ProfScope& ps) {
+    if (R == 1) helm ? launch_up<E, 1, true>(a, nu, g, s, ps) : launch_up<E, 1, false>(a, nu, g, s, ps);
+    else helm ? launch_up<E, 2, true>(a, nu, g, s, ps) : launch_up<E, 2, false>(a, nu, g, s, ps);
 }
 
 dim3 tiles(int N) { return dim3((N + kTile - 1) / kTile, (N + kTile - 1) / kTile); }
@@ -770,7 +770,7 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
                       helm ? "true" : "false", c->cfg.nu_pre, L.N);
         ProfScope ps(c, nm, nodes * ((a.u_in[0] ? eb * R : 0.0) + eb * R + (helm ? 8.0 : 0.0) +
                                      eb * R + eb * R / 4));
-        down<E>(R, helm, a, c->cfg.nu_pre, g, s);
+        down<E>(R, helm, a, c->cfg.nu_pre, g, s, ps);
     }
     {
         wq::Level& L = c->lev[lc];
@@ -791,8 +791,8 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
         char nm[64];
         std::snprintf(nm, sizeof nm, "k_mg_coarse<%s, %s>", type_name(E()), helm ? "true" : "false");
         ProfScope ps(c, nm, nodes * (eb * R + (a.u_init[0] ? eb * R : 0.0) + (helm ? 8.0 : 0.0) + eb * R));
-        if (helm) hipLaunchKernelGGL((k_mg_coarse<E, true>), dim3(R), dim3(kCoarseThreads), 0, s, a);
-        else hipLaunchKernelGGL((k_mg_coarse<E, false>), dim3(R), dim3(kCoarseThreads), 0, s, a);
+        if (helm) WQ_KLAUNCH(ps, (k_mg_coarse<E, true>), dim3(R), dim3(kCoarseThreads), 0, s, a);
+        else WQ_KLAUNCH(ps, (k_mg_coarse<E, false>), dim3(R), dim3(kCoarseThreads), 0, s, a);
     }
     for (int l = lc - 1; l >= 0; --l) {
         wq::Level& L = c->lev[l];
@@ -814,7 +814,7 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
         std::snprintf(nm, sizeof nm, "k_mg_up<%s, %d, %s, %d, 32>@%d", type_name(E()), R,
                       helm ? "true" : "false", c->cfg.nu_post, L.N);
         ProfScope ps(c, nm, nodes * (eb * R + eb * R / 4 + eb * R + (helm ? 8.0 : 0.0) + eb * R));
-        up<E>(R, helm, a, c->cfg.nu_post, tiles(L.N), s);
+        up<E>(R, helm, a, c->cfg.nu_post, tiles(L.N), s, ps);
     }
 }
 
@@ -835,11 +835,11 @@ void resnorm(wandqs_ctx* c, int R, bool helm, const Hier<double>& hz, int slot,
                   r32 ? "+defect" : "");
     ProfScope ps(c, nm, (double)L.N * L.N * (16.0 * R + (helm ? 8.0 : 0.0) + (r32 ? 4.0 * R : 0.0)));
     if (R == 1) {
-        if (helm) hipLaunchKernelGGL((k_resnorm<1, true>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch);
-        else hipLaunchKernelGGL((k_resnorm<1, false>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch);
+        if (helm) WQ_KLAUNCH(ps, (k_resnorm<1, true>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch);
+        else WQ_KLAUNCH(ps, (k_resnorm<1, false>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch);
     } else {
-        if (helm) hipLaunchKernelGGL((k_resnorm<2, true>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch);
-        else hipLaunchKernelGGL((k_resnorm<2, false>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch);
+        if (helm) WQ_KLAUNCH(ps, (k_resnorm<2, true>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch);
+        else WQ_KLAUNCH(ps, (k_resnorm<2, false>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch);
     }
 }
 
@@ -853,7 +853,7 @@ void mixed_iteration(wandqs_ctx* c, int R, bool helm, const Hier<double>& hz, in
     const int inner = c->cfg.mg_inner_cycles > 0 ? c->cfg.mg_inner_cycles : 1;
     for (int i = 0; i < inner; ++i) vcycle<float>(c, R, helm, hf, i == 0, -1);
     ProfScope ps(c, "k_correct", (double)L0.N * L0.N * 20.0 * R);
-    hipLaunchKernelGGL(k_correct, dim3((L0.N + 1 + 127) / 128, L0.N + 1), dim3(128), 0, c->stream,
+    WQ_KLAUNCH(ps, k_correct, dim3((L0.N + 1 + 127) / 128, L0.N + 1), dim3(128), 0, c->stream,
                        L0.N, L0.pitch, L0.pitch, hz.u0[0], R > 1 ? hz.u0[1] : nullptr, L0.u32[0],
                        R > 1 ? L0.u32[1] : nullptr);
 }
@@ -878,7 +878,7 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
             const wq::Level& C = c->lev[l];
             const double* src = l == 1 ? k2 : F.k2;
             ProfScope ps(c, "k_restrict_fw", 8.0 * ((double)(F.N + 1) * (F.N + 1) + (double)(C.N + 1) * (C.N + 1)));
-            hipLaunchKernelGGL(k_restrict_fw, dim3((C.N + 1 + 127) / 128, C.N + 1), dim3(128), 0, s,
+            WQ_KLAUNCH(ps, k_restrict_fw, dim3((C.N + 1 + 127) / 128, C.N + 1), dim3(128), 0, s,
                                src, F.pitch, C.k2, C.pitch, C.N);
         }
         // k2 of the coarse-kernel levels, once per solve
@@ -887,7 +887,7 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
         int tot = 0;
         for (int n = T.N; n >= 2; n /= 2) tot += (n + 1) * (n + 1);
         ProfScope ps(c, "k_coarse_k2", 16.0 * tot);
-        hipLaunchKernelGGL(k_coarse_k2, dim3(1), dim3(kCoarseThreads), 0, s, T.N, T.pitch, top,
+        WQ_KLAUNCH(ps, k_coarse_k2, dim3(1), dim3(kCoarseThreads), 0, s, T.N, T.pitch, top,
                            c->k2lev);
     }
     // one "cycle" is a V-cycle (FP64) or an outer defect-correction iteration (mixed)
@@ -929,7 +929,7 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
         const int ns = done + b + 1 - s0;
         {
             ProfScope ps(c, "k_reduce_slots", 8.0 * ns * 2 * R * (nblk + 1));
-            hipLaunchKernelGGL(k_reduce_slots, dim3(ns * 2 * R), dim3(kThreads), 0, s,
+            WQ_KLAUNCH(ps, k_reduce_slots, dim3(ns * 2 * R), dim3(kThreads), 0, s,
                                c->norm_part, 4 * c->max_tiles, nblk, s0, 2 * R, c->norm_red);
         }
         WQ_LAUNCH_CHECK();

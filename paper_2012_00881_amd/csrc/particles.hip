@@ -423,7 +423,8 @@ __global__ __launch_bounds__(256) void k_dxi(int nparts, const double* __restric
         rec[2] = vmax;
         rec[3] = (double)flags[0];
     }
-    st[3] = st[2];  // the fields now stored belong to this slice
+    st[4] = st[3];  // the fields now stored belong to this slice
+    st[3] = st[2];
     st[2] = st[0];
     st[0] = st[0] + st[1];
     st[1] = d;
@@ -464,38 +465,38 @@ wandqs_status slice_sort(wandqs_ctx* c) {
     const int ncell = c->N * c->N;
     {
         ProfScope ps(c, "k_cell_key", (double)c->P * 20.0 + (double)ncell * 8.0);
-        hipLaunchKernelGGL(k_cell_key, dim3(blocks_for(c->P, 256)), dim3(256), 0, s, c->P,
+        WQ_KLAUNCH(ps, k_cell_key, dim3(blocks_for(c->P, 256)), dim3(256), 0, s, c->P,
                            c->pa[a][0], c->pa[a][1], c->L, c->h, c->N, c->key, c->cell_count);
     }
     const int nb = (ncell + kScanBlock - 1) / kScanBlock;
     {
         ProfScope ps(c, "k_scan_blocks", (double)ncell * 8.0);
-        hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(kScanThreads), 0, s, c->cell_count, ncell,
+        WQ_KLAUNCH(ps, k_scan_blocks, dim3(nb), dim3(kScanThreads), 0, s, c->cell_count, ncell,
                            c->cell_start, c->scan_blk);
     }
     {
         ProfScope ps(c, "k_scan_top", 8.0 * nb);
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, c->scan_blk, nb,
+        WQ_KLAUNCH(ps, k_scan_top, dim3(1), dim3(kScanThreads), 0, s, c->scan_blk, nb,
                            c->cell_start, ncell);
     }
     {
         ProfScope ps(c, "k_scan_add", (double)ncell * 8.0);
-        hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(ncell, 256)), dim3(256), 0, s, c->cell_start,
+        WQ_KLAUNCH(ps, k_scan_add, dim3(blocks_for(ncell, 256)), dim3(256), 0, s, c->cell_start,
                            ncell, c->scan_blk);
     }
     {
         ProfScope ps(c, "k_scatter", (double)c->P * 12.0 + (double)ncell * 8.0);
-        hipLaunchKernelGGL(k_scatter, dim3(blocks_for(c->P, 256)), dim3(256), 0, s, c->P, c->key,
+        WQ_KLAUNCH(ps, k_scatter, dim3(blocks_for(c->P, 256)), dim3(256), 0, s, c->P, c->key,
                            c->cell_start, c->cell_count, c->perm);
     }
     {
         ProfScope ps(c, "k_cell_sort", (double)c->P * 12.0 + (double)ncell * 4.0);
-        hipLaunchKernelGGL(k_cell_sort, dim3(blocks_for(ncell, 256)), dim3(256), 0, s, ncell,
+        WQ_KLAUNCH(ps, k_cell_sort, dim3(blocks_for(ncell, 256)), dim3(256), 0, s, ncell,
                            c->cell_start, c->perm, c->pid[a]);
     }
     {
         ProfScope ps(c, "k_permute", (double)c->P * 76.0);
-        hipLaunchKernelGGL(k_permute, dim3(blocks_for(c->P, 256)), dim3(256), 0, s, c->P, c->perm,
+        WQ_KLAUNCH(ps, k_permute, dim3(blocks_for(c->P, 256)), dim3(256), 0, s, c->P, c->perm,
                            c->pa[a][0], c->pa[a][1], c->pa[a][2], c->pa[a][3], c->pid[a], c->pa[b][0],
                            c->pa[b][1], c->pa[b][2], c->pa[b][3], c->pid[b]);
     }
@@ -509,7 +510,7 @@ wandqs_status deposit_n(wandqs_ctx* c) {
     const double wdep = c->cfg.n0 / c->ppc;
     {
         ProfScope ps(c, "k_deposit_n<16>", (double)c->P * 16.0 + (double)c->N * c->N * 4.0 + (double)(c->N + 1) * (c->N + 1) * 16.0);
-        hipLaunchKernelGGL((k_deposit_n<kDepTile>), dim3(nt, nt), dim3(256), 0, c->stream, c->N, c->L,
+        WQ_KLAUNCH(ps, (k_deposit_n<kDepTile>), dim3(nt, nt), dim3(256), 0, c->stream, c->N, c->L,
                            c->h, wdep, c->cfg.n0, c->lev[0].pitch, c->pa[c->cur][0], c->pa[c->cur][1],
                            c->cell_start, c->mom[0], c->lev[0].f[0]);
     }
@@ -523,7 +524,7 @@ wandqs_status deposit_jT(wandqs_ctx* c) {
     const int k = c->cur;
     {
         ProfScope ps(c, "k_deposit_jT<16>", (double)c->P * 32.0 + (double)c->N * c->N * 4.0 + (double)(c->N + 1) * (c->N + 1) * 48.0);
-        hipLaunchKernelGGL((k_deposit_jT<kDepTile>), dim3(nt, nt), dim3(256), 0, c->stream, c->N, c->L,
+        WQ_KLAUNCH(ps, (k_deposit_jT<kDepTile>), dim3(nt, nt), dim3(256), 0, c->stream, c->N, c->L,
                            c->h, wdep, c->lev[0].pitch, c->pa[k][0], c->pa[k][1], c->pa[k][2],
                            c->pa[k][3], c->cell_start, c->fields[0], c->mom[1], c->mom[2], c->mom[3],
                            c->mom[4], c->mom[5], c->flags);
@@ -536,7 +537,7 @@ wandqs_status push_and_step(wandqs_ctx* c, int rec_slot) {
     const int k = c->cur;
     {
         ProfScope ps(c, "k_push", (double)c->P * 64.0 + (double)(c->N + 1) * (c->N + 1) * 32.0);
-        hipLaunchKernelGGL(k_push, dim3(c->n_push_blocks), dim3(kPushThreads), 0, c->stream, c->P,
+        WQ_KLAUNCH(ps, k_push, dim3(c->n_push_blocks), dim3(kPushThreads), 0, c->stream, c->P,
                            c->N, c->L, c->h, c->lev[0].pitch, c->st, c->fields[0], c->fields[3],
                            c->fields[4], c->fields[2], c->pa[k][0], c->pa[k][1], c->pa[k][2],
                            c->pa[k][3], c->vmax_part);
@@ -544,7 +545,7 @@ wandqs_status push_and_step(wandqs_ctx* c, int rec_slot) {
     double* rec = rec_slot >= 0 ? c->rec + 4 * (size_t)rec_slot : nullptr;
     {
         ProfScope ps(c, "k_dxi", 8.0 * c->n_push_blocks);
-        hipLaunchKernelGGL(k_dxi, dim3(1), dim3(256), 0, c->stream, c->n_push_blocks, c->vmax_part,
+        WQ_KLAUNCH(ps, k_dxi, dim3(1), dim3(256), 0, c->stream, c->n_push_blocks, c->vmax_part,
                            c->st, c->cfg.dxi0, c->h, c->cfg.adaptive, c->cfg.refine_k, c->flags, rec);
     }
     WQ_LAUNCH_CHECK();
@@ -555,7 +556,7 @@ wandqs_status particles_to_id_order(wandqs_ctx* c, double* dst) {
     const int k = c->cur;
     {
         ProfScope ps(c, "k_to_id_order", (double)c->P * 68.0);
-        hipLaunchKernelGGL(k_to_id_order, dim3(blocks_for(c->P, 256)), dim3(256), 0, c->stream, c->P,
+        WQ_KLAUNCH(ps, k_to_id_order, dim3(blocks_for(c->P, 256)), dim3(256), 0, c->stream, c->P,
                            c->pid[k], c->pa[k][0], c->pa[k][1], c->pa[k][2], c->pa[k][3], dst);
     }
     WQ_LAUNCH_CHECK();
@@ -566,7 +567,7 @@ wandqs_status particles_from_id_order(wandqs_ctx* c, const double* src) {
     const int k = c->cur;
     {
         ProfScope ps(c, "k_from_id_order", (double)c->P * 68.0);
-        hipLaunchKernelGGL(k_from_id_order, dim3(blocks_for(c->P, 256)), dim3(256), 0, c->stream, c->P,
+        WQ_KLAUNCH(ps, k_from_id_order, dim3(blocks_for(c->P, 256)), dim3(256), 0, c->stream, c->P,
                            src, c->pa[k][0], c->pa[k][1], c->pa[k][2], c->pa[k][3], c->pid[k]);
     }
     WQ_LAUNCH_CHECK();

@@ -37,16 +37,13 @@ ProfScope::ProfScope(wandqs_ctx* c, const char* name, double bytes) : c_(c), byt
     cls_ = class_of(p, name);
     a_ = p.free_ev.back();
     p.free_ev.pop_back();
-    (void)hipEventRecord(a_, c->stream);
+    b_ = p.free_ev.back();
+    p.free_ev.pop_back();
 }
 
 ProfScope::~ProfScope() {
     if (cls_ < 0) return;
-    Prof& p = c_->prof;
-    hipEvent_t b = p.free_ev.back();
-    p.free_ev.pop_back();
-    (void)hipEventRecord(b, c_->stream);
-    p.pending.push_back(ProfPending{cls_, a_, b, bytes_});
+    c_->prof.pending.push_back(ProfPending{cls_, a_, b_, bytes_});
 }
 
 void prof_harvest(wandqs_ctx* c) {

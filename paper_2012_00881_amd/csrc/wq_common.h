@@ -1,6 +1,7 @@
 // Internal declarations of the wandqs library (gfx950).  Not part of the C ABI.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -65,6 +66,7 @@ struct Checkpoint {
     int32_t* pid = nullptr;
     double* fields[5] = {};
     double* fields_prev[5] = {};
+    double* fields_prev2[5] = {};
     double* st = nullptr;
     int pred[kPredKinds] = {};
     int n_guess = 0;
@@ -141,7 +143,10 @@ struct wandqs_ctx {
     // device memory carved from the caller's workspace
     wq::Level lev[wq::kMaxLevels];
     double* fields[5] = {};
-    double* fields_prev[5] = {};  // fields of the slice before (initial-guess extrapolation)
+    // fields of the two slices before (initial-guess extrapolation); the three
+    // arrays of each field rotate by pointer
+    double* fields_prev[5] = {};
+    double* fields_prev2[5] = {};
     double* mom[6] = {};
     double* jz = nullptr;
     double* k2lev = nullptr;  // k2 of the coarse-kernel levels (dense, concatenated)
@@ -151,7 +156,7 @@ struct wandqs_ctx {
     int32_t *key = nullptr, *perm = nullptr, *cell_count = nullptr, *cell_start = nullptr,
             *scan_blk = nullptr;
     int n_scan_blocks = 0;
-    double* st = nullptr;         // [xi, dxi, xi of fields, xi of fields_prev]
+    double* st = nullptr;  // [xi, dxi, xi of fields, of fields_prev, of fields_prev2]
     double* vmax_part = nullptr;  // per push block
     int n_push_blocks = 0;
     int32_t* flags = nullptr;
@@ -183,7 +188,7 @@ struct wandqs_ctx {
     double* h_pin = nullptr;  // pinned readback buffer
     int pred[wq::kPredKinds] = {1, 1, 1, 1, 1, 1, 1, 1};  // V-cycles of the last solve per kind (batch size)
     bool failed = false;
-    int n_guess = 0;  // slices since init/set_state (extrapolation needs two)
+    int n_guess = 0;  // slices since init/set_state, up to 3 (extrapolation order + 1)
     std::string err;
     wq::SolveResult last[3];
     wq::Prof prof;
@@ -211,7 +216,7 @@ wandqs_status unpack_fields(wandqs_ctx* c, const double* src, int n, double* con
 wandqs_status particles_to_id_order(wandqs_ctx* c, double* dst);
 wandqs_status particles_from_id_order(wandqs_ctx* c, const double* src);
 wandqs_status fill_f64(wandqs_ctx* c, double* p, size_t n, double v);
-wandqs_status extrapolate_guess(wandqs_ctx* c, bool extrapolate);
+wandqs_status extrapolate_guess(wandqs_ctx* c, int order);
 wandqs_status copy_d2d(wandqs_ctx* c, void* dst, const void* src, size_t bytes);
 wandqs_status probe_seed(wandqs_ctx* c, int k, double w, double* const* Fb);
 
@@ -228,22 +233,37 @@ bool node_in_disc_host(double L, double h, int a, int b, double x0, double y0, d
 
 const char* hip_err(hipError_t e);
 
-// Brackets one kernel launch with timing events when profiling is on.
+// Timing of one kernel launch when profiling is on: a pair of events that the
+// launch itself records (WQ_KLAUNCH), so the interval is the kernel's dispatch,
+// with no event packets in between.
 class ProfScope {
   public:
     ProfScope(wandqs_ctx* c, const char* name, double bytes);
     ~ProfScope();
+    hipEvent_t start() const { return a_; }
+    hipEvent_t stop() const { return b_; }
 
   private:
     wandqs_ctx* c_;
     int cls_ = -1;
-    hipEvent_t a_ = nullptr;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
     double bytes_ = 0;
 };
 void prof_harvest(wandqs_ctx* c);
 void prof_reset(wandqs_ctx* c, bool on);
 
 }  // namespace wq
+
+// Kernel launch under a ProfScope: with profiling on, the dispatch records the
+// scope's start and stop events.
+#define WQ_KLAUNCH(ps, kernel, grid, block, shmem, stream, ...)                          \
+    do {                                                                                \
+        if ((ps).start())                                                               \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, (ps).start(),     \
+                                  (ps).stop(), 0, __VA_ARGS__);                         \
+        else                                                                            \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);        \
+    } while (0)
 
 #define WQ_HIP(call)                                                                  \
     do {                                                                              \
