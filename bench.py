@@ -135,6 +135,9 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=512,
                     help="slices of the taped forward + reverse sweep (0: skip)")
     ap.add_argument("--checkpoint-every", type=int, default=32)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB three times (the "
+                         "reference for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the slice step is not sharded "
@@ -152,6 +155,17 @@ def main():
     if args.rtol is not None:
         cfg.update(mg_rtol=args.rtol)
     K, W = args.steps, args.warmup
+
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * 2**20 // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: 3 x {args.copy_calibration_mib} MiB", file=sys.stderr,
+              flush=True)
+        del src, dst
 
     print(f"[bench] warm-up: {W} slices", file=sys.stderr, flush=True)
     sim = Simulation(cfg, n_slices=max(W, 1))
@@ -225,6 +239,7 @@ def main():
                 "share_of_kernel_time": round(dom["total_ms"] / tot, 4),
                 "profiled_pass_s": round(tp, 3)}
         if args.breakdown:
+            os.makedirs(os.path.dirname(os.path.abspath(args.breakdown)), exist_ok=True)
             with open(args.breakdown, "w") as fh:
                 json.dump(dict(workload=args.workload, slices=K, particles=P, stats=stats,
                                per_level=per_level, source_hash=kernel_source_hash()), fh,

@@ -52,6 +52,18 @@ __device__ void block_sum(double (&v)[NV], double* red) {
     }
 }
 
+// Tile of this workgroup.  Workgroups are dealt to the 8 XCDs round-robin in
+// dispatch order; the mapping gives each XCD a contiguous band of tiles, so the
+// halo a tile shares with its neighbours is mostly fetched once into that
+// XCD's L2 instead of once per tile.
+__device__ __forceinline__ void tile_of_block(int& bx, int& by) {
+    const int gx = gridDim.x, n = gx * gridDim.y;
+    int b = blockIdx.y * gx + blockIdx.x;
+    if ((n & 7) == 0) b = (b & 7) * (n >> 3) + (b >> 3);
+    by = b / gx;
+    bx = b - by * gx;
+}
+
 // ------------------------------------------------------------ tile engine --
 //
 // A tile kernel holds an EX x EY block of nodes whose node (0, 0) is global
@@ -164,7 +176,9 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_down(DownArgs<E> a) {
 
     const int tid = threadIdx.x;
     const int N = a.N;
-    const int x0 = blockIdx.x * T, y0 = blockIdx.y * T;
+    int bx, by;
+    tile_of_block(bx, by);
+    const int x0 = bx * T, y0 = by * T;
     const int ex0 = x0 - HL, ey0 = y0 - HL;
     const E h2 = (E)(a.h * a.h), ih2 = (E)(1.0 / (a.h * a.h));
 
@@ -207,7 +221,7 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_down(DownArgs<E> a) {
         }
         block_sum<2 * R, kTileThreads>(acc, red);
         if (tid == 0) {
-            const int b = blockIdx.y * gridDim.x + blockIdx.x;
+            const int b = by * gridDim.x + bx;
 #pragma unroll
             for (int q = 0; q < 2 * R; ++q) a.norm_part[q * a.nblk + b] = acc[q];
         }
@@ -304,7 +318,9 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_up(UpArgs<E> a) {
 
     const int tid = threadIdx.x;
     const int N = a.N, Nc = N / 2;
-    const int x0 = blockIdx.x * T, y0 = blockIdx.y * T;
+    int bx, by;
+    tile_of_block(bx, by);
+    const int x0 = bx * T, y0 = by * T;
     const int ex0 = x0 - H, ey0 = y0 - H;  // even
     const int cx0 = ex0 / 2, cy0 = ey0 / 2;
     const E h2 = (E)(a.h * a.h);
