@@ -97,7 +97,7 @@ void set_sizes(wandqs_ctx* c, const wandqs_config* cfg, int32_t n_slices) {
     // lc: first level with N <= kCoarseMax
     c->lc = 0;
     while (c->lev[c->lc].N > wq::kCoarseMax) ++c->lc;
-    const int t = (c->N + wq::kTile - 1) / wq::kTile;
+    const int t = (c->N + 15) / 16;  // norm partials: one per tile of the smallest tile size
     c->max_tiles = t * t;
     c->n_push_blocks = (int)((c->P + 255) / 256);
     c->n_scan_blocks = (c->N * c->N + 2047) / 2048;

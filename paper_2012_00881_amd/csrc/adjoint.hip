@@ -102,7 +102,9 @@ struct PushAdjArgs {
 __global__ __launch_bounds__(256) void k_push_adj(PushAdjArgs a) {
     constexpr int M = 5;
     __shared__ double corner[TC * TC][4 * M];
-    const int a0 = blockIdx.x * TN, b0 = blockIdx.y * TN;
+    int tbx, tby;
+    tile_of_block(tbx, tby);
+    const int a0 = tbx * TN, b0 = tby * TN;
     const int N = a.N, pitch = a.pitch;
     const double h = a.h, L = a.L, d = a.st[1];
     const int64_t P = a.P;
@@ -453,7 +455,9 @@ struct DepAdjArgs {
 // position derivatives; V = p / g), then the gather g = 1 + psi reversed.
 __global__ __launch_bounds__(256) void k_dep_adj(DepAdjArgs a) {
     __shared__ double corner[TC * TC][4];
-    const int a0 = blockIdx.x * TN, b0 = blockIdx.y * TN;
+    int tbx, tby;
+    tile_of_block(tbx, tby);
+    const int a0 = tbx * TN, b0 = tby * TN;
     const int N = a.N, pitch = a.pitch;
     const double h = a.h, L = a.L, wd = a.wd;
     for (int c = threadIdx.x; c < TC * TC; c += blockDim.x) {

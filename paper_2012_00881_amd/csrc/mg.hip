@@ -26,9 +26,23 @@
 namespace wq {
 namespace {
 
-constexpr int kThreads = 256;      // norm and reduction kernels
-constexpr int kTileThreads = 512;  // tile kernels of the levels N > 64
-constexpr int kCoarseThreads = 512;
+#ifndef WQ_COARSE_THREADS
+#define WQ_COARSE_THREADS 1024
+#endif
+#ifndef WQ_COARSE_F32
+#define WQ_COARSE_F32 1
+#endif
+#ifndef WQ_SMALL_TILE_MAX
+#define WQ_SMALL_TILE_MAX 256
+#endif
+constexpr int kThreads = 256;  // norm and reduction kernels
+constexpr int kCoarseThreads = WQ_COARSE_THREADS;
+// Tile kernels: 32 x 32 owned nodes with 512 threads, or 16 x 16 with 256
+// threads on the levels N <= WQ_SMALL_TILE_MAX (more workgroups and a shorter
+// chain of dependent LDS phases per workgroup where the grid is small).
+template <int T>
+constexpr int tile_threads() { return T >= 32 ? 512 : 256; }
+int tile_for(int N) { return N <= WQ_SMALL_TILE_MAX ? 16 : 32; }
 
 // Deterministic block sum of NV values; the result is valid in thread 0.
 template <int NV, int NT>
@@ -52,18 +66,6 @@ __device__ void block_sum(double (&v)[NV], double* red) {
     }
 }
 
-// Tile of this workgroup.  Workgroups are dealt to the 8 XCDs round-robin in
-// dispatch order; the mapping gives each XCD a contiguous band of tiles, so the
-// halo a tile shares with its neighbours is mostly fetched once into that
-// XCD's L2 instead of once per tile.
-__device__ __forceinline__ void tile_of_block(int& bx, int& by) {
-    const int gx = gridDim.x, n = gx * gridDim.y;
-    int b = blockIdx.y * gx + blockIdx.x;
-    if ((n & 7) == 0) b = (b & 7) * (n >> 3) + (b >> 3);
-    by = b / gx;
-    bx = b - by * gx;
-}
-
 // ------------------------------------------------------------ tile engine --
 //
 // A tile kernel holds an EX x EY block of nodes whose node (0, 0) is global
@@ -76,11 +78,11 @@ __device__ __forceinline__ void tile_of_block(int& bx, int& by) {
 template <typename T>
 __device__ __forceinline__ T pick(int j, T a, T b) { return j ? b : a; }
 
-template <int R, bool HELM, int EX, int EY>
+template <int R, bool HELM, int EX, int EY, int NT>
 struct TileShape {
     static constexpr int PW = EX / 2;
     static constexpr int NP = PW * EY;
-    static constexpr int KP = (NP + kTileThreads - 1) / kTileThreads;
+    static constexpr int KP = (NP + NT - 1) / NT;
     static constexpr int EN = EX * EY;
     static_assert(EX % 2 == 0, "tile width must be even");
 };
@@ -88,7 +90,7 @@ struct TileShape {
 // E is the element type of the iterate, f and the sweep arithmetic (double, or
 // float for the inner cycles of the mixed form); k2 is always read as double
 // and D = 4 + h^2 k2, 1/D are formed in double before rounding to E.
-template <typename E, int R, bool HELM, int EX, int EY, int KP>
+template <typename E, int R, bool HELM, int EX, int EY, int KP, int NT>
 __device__ __forceinline__ void tile_load(E (*su)[EX * EY], E (&fr)[R][KP][2], E (&Dr)[KP][2],
                                           E (&iDr)[KP][2], const E* const* u, const E* const* f,
                                           const double* k2, int pitch, int ex0, int ey0, int N,
@@ -96,7 +98,7 @@ __device__ __forceinline__ void tile_load(E (*su)[EX * EY], E (&fr)[R][KP][2], E
     constexpr int PW = EX / 2, NP = PW * EY;
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-        const int p = threadIdx.x + k * kTileThreads;
+        const int p = threadIdx.x + k * NT;
         const int ly = p / PW, px = p - ly * PW;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -120,14 +122,14 @@ __device__ __forceinline__ void tile_load(E (*su)[EX * EY], E (&fr)[R][KP][2], E
 // One red-black half sweep: u <- (sum of 4 neighbours - h^2 f) / D on the nodes
 // of colour `color` ((gx + gy) % 2) that have all four neighbours in the tile
 // and lie inside the domain.
-template <typename E, int R, bool HELM, int EX, int EY, int KP>
+template <typename E, int R, bool HELM, int EX, int EY, int KP, int NT>
 __device__ __forceinline__ void tile_sweep(E (*su)[EX * EY], const E (&fr)[R][KP][2],
                                            const E (&iDr)[KP][2], int ex0, int ey0, int N, E h2,
                                            int color) {
     constexpr int PW = EX / 2, NP = PW * EY;
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-        const int p = threadIdx.x + k * kTileThreads;
+        const int p = threadIdx.x + k * NT;
         const int ly = p / PW, px = p - ly * PW;
         const int gy = ey0 + ly;
         const int j = (gy + color) & 1;  // ex0 is even
@@ -166,13 +168,14 @@ struct DownArgs {
 // nodes on the low side (the residual at x0 - 1 needs the smoothed u at x0 - 2),
 // 2 nu + 2 on the high side (one more than needed, to keep the width even).
 template <typename E, int R, bool HELM, int NU, int T>
-__global__ __launch_bounds__(kTileThreads) void k_mg_down(DownArgs<E> a) {
+__global__ __launch_bounds__(tile_threads<T>()) void k_mg_down(DownArgs<E> a) {
+    constexpr int NT = tile_threads<T>();
     constexpr int HL = 2 * NU + 2, HH = 2 * NU + 2;
     constexpr int EX = T + HL + HH, EY = EX;
-    using S = TileShape<R, HELM, EX, EY>;
+    using S = TileShape<R, HELM, EX, EY, NT>;
     constexpr int PW = S::PW, NP = S::NP, KP = S::KP, EN = S::EN;
     __shared__ E su[R][EN];
-    __shared__ double red[(kTileThreads / 64) * 2 * R];
+    __shared__ double red[(NT / 64) * 2 * R];
 
     const int tid = threadIdx.x;
     const int N = a.N;
@@ -183,7 +186,7 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_down(DownArgs<E> a) {
     const E h2 = (E)(a.h * a.h), ih2 = (E)(1.0 / (a.h * a.h));
 
     E fr[R][KP][2], Dr[KP][2], iDr[KP][2];
-    tile_load<E, R, HELM, EX, EY, KP>(su, fr, Dr, iDr, a.u_in, a.f, a.k2, a.pitch, ex0, ey0, N,
+    tile_load<E, R, HELM, EX, EY, KP, NT>(su, fr, Dr, iDr, a.u_in, a.f, a.k2, a.pitch, ex0, ey0, N,
                                       a.h * a.h);
     __syncthreads();
 
@@ -201,7 +204,7 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_down(DownArgs<E> a) {
         for (int q = 0; q < 2 * R; ++q) acc[q] = 0.0;
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
-            const int p = tid + k * kTileThreads;
+            const int p = tid + k * NT;
             const int ly = p / PW, px = p - ly * PW;
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
@@ -219,7 +222,7 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_down(DownArgs<E> a) {
                 }
             }
         }
-        block_sum<2 * R, kTileThreads>(acc, red);
+        block_sum<2 * R, NT>(acc, red);
         if (tid == 0) {
             const int b = by * gridDim.x + bx;
 #pragma unroll
@@ -229,7 +232,7 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_down(DownArgs<E> a) {
 
     for (int s = 0; s < NU; ++s)
         for (int color = 0; color < 2; ++color) {
-            tile_sweep<E, R, HELM, EX, EY, KP>(su, fr, iDr, ex0, ey0, N, h2, color);
+            tile_sweep<E, R, HELM, EX, EY, KP, NT>(su, fr, iDr, ex0, ey0, N, h2, color);
             __syncthreads();
         }
 
@@ -237,7 +240,7 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_down(DownArgs<E> a) {
     E rr[R][KP][2];
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-        const int p = tid + k * kTileThreads;
+        const int p = tid + k * NT;
         const int ly = p / PW, px = p - ly * PW;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -258,7 +261,7 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_down(DownArgs<E> a) {
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < KP; ++k) {  // the residual replaces u in LDS
-        const int p = tid + k * kTileThreads;
+        const int p = tid + k * NT;
         const int ly = p / PW, px = p - ly * PW;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -272,7 +275,7 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_down(DownArgs<E> a) {
 
     // full weighting onto coarse nodes x0/2 .. x0/2 + T/2 - 1 (< N/2)
     const int Nc = N / 2;
-    for (int i = tid; i < (T / 2) * (T / 2); i += kTileThreads) {
+    for (int i = tid; i < (T / 2) * (T / 2); i += NT) {
         const int oy = i / (T / 2), ox = i - oy * (T / 2);
         const int I = x0 / 2 + ox, J = y0 / 2 + oy;
         if (I > Nc - 1 || J > Nc - 1) continue;
@@ -307,10 +310,11 @@ struct UpArgs {
 // Up pass of one level: u += bilinear prolongation of the coarse correction on
 // the whole tile (halo 2 nu), nu2 sweeps, write the owned nodes.
 template <typename E, int R, bool HELM, int NU, int T>
-__global__ __launch_bounds__(kTileThreads) void k_mg_up(UpArgs<E> a) {
+__global__ __launch_bounds__(tile_threads<T>()) void k_mg_up(UpArgs<E> a) {
+    constexpr int NT = tile_threads<T>();
     constexpr int H = 2 * NU;
     constexpr int EX = T + 2 * H, EY = EX;
-    using S = TileShape<R, HELM, EX, EY>;
+    using S = TileShape<R, HELM, EX, EY, NT>;
     constexpr int PW = S::PW, NP = S::NP, KP = S::KP, EN = S::EN;
     constexpr int CX = EX / 2 + 1, CY = EY / 2 + 1;
     __shared__ E su[R][EN];
@@ -326,9 +330,9 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_up(UpArgs<E> a) {
     const E h2 = (E)(a.h * a.h);
 
     E fr[R][KP][2], Dr[KP][2], iDr[KP][2];
-    tile_load<E, R, HELM, EX, EY, KP>(su, fr, Dr, iDr, a.u_mid, a.f, a.k2, a.pitch, ex0, ey0, N,
+    tile_load<E, R, HELM, EX, EY, KP, NT>(su, fr, Dr, iDr, a.u_mid, a.f, a.k2, a.pitch, ex0, ey0, N,
                                       a.h * a.h);
-    for (int i = tid; i < CX * CY; i += kTileThreads) {
+    for (int i = tid; i < CX * CY; i += NT) {
         const int cy = i / CX, cx = i - cy * CX;
         const int I = cx0 + cx, J = cy0 + cy;
         const bool in = I >= 0 && I <= Nc && J >= 0 && J <= Nc;
@@ -339,7 +343,7 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_up(UpArgs<E> a) {
 
 #pragma unroll
     for (int k = 0; k < KP; ++k) {  // each thread corrects the nodes of its own pairs
-        const int p = tid + k * kTileThreads;
+        const int p = tid + k * NT;
         const int ly = p / PW, px = p - ly * PW;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -364,13 +368,13 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_up(UpArgs<E> a) {
 
     for (int s = 0; s < NU; ++s)
         for (int color = 0; color < 2; ++color) {
-            tile_sweep<E, R, HELM, EX, EY, KP>(su, fr, iDr, ex0, ey0, N, h2, color);
+            tile_sweep<E, R, HELM, EX, EY, KP, NT>(su, fr, iDr, ex0, ey0, N, h2, color);
             __syncthreads();
         }
 
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-        const int p = tid + k * kTileThreads;
+        const int p = tid + k * NT;
         const int ly = p / PW, px = p - ly * PW;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -411,7 +415,7 @@ struct LdsLevel {
     static constexpr int W = n + 1;
     static constexpr int HALF = n / 2;  // nodes of one colour per interior row (upper bound)
 
-    static __device__ void smooth(E* u, const E* f, const double* k2, E h2, int nu) {
+    static __device__ void smooth(E* u, const E* f, const E* k2, E h2, int nu) {
         for (int s = 0; s < nu; ++s)
             for (int color = 0; color < 2; ++color) {
                 for (int i = threadIdx.x; i < (n - 1) * HALF; i += kCoarseThreads) {
@@ -427,14 +431,14 @@ struct LdsLevel {
             }
     }
 
-    static __device__ E resid(const E* u, const E* f, const double* k2, E ih2, int l) {
+    static __device__ E resid(const E* u, const E* f, const E* k2, E ih2, int l) {
         E au = (u[l - 1] + u[l + 1] + u[l - W] + u[l + W] - E(4) * u[l]) * ih2;
         if (HELM) au -= (E)k2[l] * u[l];
         return f[l] - au;
     }
 
     // f_c = full weighting of the residual; u_c = 0
-    static __device__ void restrict_to(const E* u, const E* f, const double* k2, E ih2, E* uc,
+    static __device__ void restrict_to(const E* u, const E* f, const E* k2, E ih2, E* uc,
                                        E* fc) {
         constexpr int nc = n / 2, Wc = nc + 1;
         for (int i = threadIdx.x; i < Wc * Wc; i += kCoarseThreads) {
@@ -487,13 +491,17 @@ __device__ __forceinline__ void with_level(int n, Fn&& fn) {
 }
 
 // All levels N <= 64 in one workgroup per right-hand side; the 2x2-cell grid
-// is solved exactly in double.
-template <typename E, bool HELM>
+// is solved exactly in double.  E is the type of the arrays in memory, C the
+// type of the LDS copy and of the sweep arithmetic: below a finer level the
+// result is only a coarse-grid correction, whose rounding never reaches the
+// fixed point (the finer levels' FP64 residual and smoothing set it), so it
+// runs in float there; when the coarse kernel is the whole solve, C = E.
+template <typename E, typename C, bool HELM>
 __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
     constexpr int TOT = coarse_nodes();
-    __shared__ E su[TOT];
-    __shared__ E sf[TOT];
-    __shared__ double sk[HELM ? TOT : 1];
+    __shared__ C su[TOT];
+    __shared__ C sf[TOT];
+    __shared__ C sk[HELM ? TOT : 1];
     const int r = blockIdx.x;
     const int tid = threadIdx.x;
 
@@ -523,8 +531,8 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
         for (int b = 0; b < kB; ++b) {
             const int i = base + b * kCoarseThreads + tid;
             if (i < nt) {
-                su[i] = uv[b];
-                sf[i] = fv[b];
+                su[i] = (C)uv[b];
+                sf[i] = (C)fv[b];
             }
         }
     }
@@ -539,7 +547,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
 #pragma unroll
             for (int b = 0; b < kB; ++b) {
                 const int i = base + b * kCoarseThreads + tid;
-                if (i < tot) sk[i] = kv[b];
+                if (i < tot) sk[i] = (C)kv[b];
             }
         }
     __syncthreads();
@@ -547,34 +555,34 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
     for (int cyc = 0; cyc < a.ncycles; ++cyc) {
         for (int l = 0; l < nl - 1; ++l) {
             const double hl = a.h * (double)(1 << l);
-            E* u = su + off[l];
-            E* f = sf + off[l];
-            const double* k2 = sk + (HELM ? off[l] : 0);
-            with_level<E, HELM>(Ns[l], [&](auto L) {
-                L.smooth(u, f, k2, (E)(hl * hl), a.nu1);
-                L.restrict_to(u, f, k2, (E)(1.0 / (hl * hl)), su + off[l + 1], sf + off[l + 1]);
+            C* u = su + off[l];
+            C* f = sf + off[l];
+            const C* k2 = sk + (HELM ? off[l] : 0);
+            with_level<C, HELM>(Ns[l], [&](auto L) {
+                L.smooth(u, f, k2, (C)(hl * hl), a.nu1);
+                L.restrict_to(u, f, k2, (C)(1.0 / (hl * hl)), su + off[l + 1], sf + off[l + 1]);
             });
         }
         if (tid == 0) {  // 2x2 cells: one unknown, four zero neighbours
             const int l = nl - 1;
             const double hl = a.h * (double)(1 << l);
             const int c = 1 * 3 + 1;
-            const double k2c = HELM ? sk[off[l] + c] : 0.0;
-            su[off[l] + c] = (E)(-(double)sf[off[l] + c] / (4.0 / (hl * hl) + k2c));
+            const double k2c = HELM ? (double)sk[off[l] + c] : 0.0;
+            su[off[l] + c] = (C)(-(double)sf[off[l] + c] / (4.0 / (hl * hl) + k2c));
         }
         __syncthreads();
         for (int l = nl - 2; l >= 0; --l) {
             const double hl = a.h * (double)(1 << l);
-            E* u = su + off[l];
-            with_level<E, HELM>(Ns[l], [&](auto L) {
+            C* u = su + off[l];
+            with_level<C, HELM>(Ns[l], [&](auto L) {
                 L.prolong_add(u, su + off[l + 1]);
-                L.smooth(u, sf + off[l], sk + (HELM ? off[l] : 0), (E)(hl * hl), a.nu2);
+                L.smooth(u, sf + off[l], sk + (HELM ? off[l] : 0), (C)(hl * hl), a.nu2);
             });
         }
     }
     for (int i = tid; i < (N + 1) * (N + 1); i += kCoarseThreads) {
         const int y = i / (N + 1), x = i - y * (N + 1);
-        a.u_out[r][(size_t)y * a.pitch + x] = su[i];
+        a.u_out[r][(size_t)y * a.pitch + x] = (E)su[i];
     }
 }
 
@@ -618,18 +626,18 @@ __global__ __launch_bounds__(kThreads) void k_resnorm(int N, double h, int pitch
                                                       const double* u0, const double* u1,
                                                       const double* f0, const double* f1,
                                                       const double* k2, double* part, int nblk,
-                                                      float* r0, float* r1, int pitch32) {
+                                                      float* r0, float* r1, int pitch32, int T) {
     __shared__ double red[(kThreads / 64) * 2 * R];
     const double ih2 = 1.0 / (h * h);
-    const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
+    const int x0 = blockIdx.x * T, y0 = blockIdx.y * T;
     const double* u[2] = {u0, u1};
     const double* f[2] = {f0, f1};
     float* ro[2] = {r0, r1};
     double acc[2 * R];
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k) acc[k] = 0.0;
-    for (int i = threadIdx.x; i < kTile * kTile; i += kThreads) {
-        const int oy = i / kTile, ox = i - oy * kTile;
+    for (int i = threadIdx.x; i < T * T; i += kThreads) {
+        const int oy = i / T, ox = i - oy * T;
         const int gx = x0 + ox, gy = y0 + oy;
         if (gx > N - 1 || gy > N - 1) continue;
         const bool interior = gx >= 1 && gy >= 1;
@@ -697,37 +705,51 @@ __global__ void k_restrict_fw(const double* fine, int pf, double* coarse, int pc
 
 // ------------------------------------------------------------- dispatch --
 
-template <typename E, int R, bool HELM>
-void launch_down(const DownArgs<E>& a, int nu, dim3 grid, hipStream_t s, const ProfScope& ps) {
+template <typename E, int R, bool HELM, int T>
+void launch_down_t(const DownArgs<E>& a, int nu, dim3 grid, hipStream_t s, const ProfScope& ps) {
+    constexpr int NT = tile_threads<T>();
     switch (nu) {
-        case 1: WQ_KLAUNCH(ps, (k_mg_down<E, R, HELM, 1, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
-        case 2: WQ_KLAUNCH(ps, (k_mg_down<E, R, HELM, 2, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
-        default: WQ_KLAUNCH(ps, (k_mg_down<E, R, HELM, 3, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
+        case 1: WQ_KLAUNCH(ps, (k_mg_down<E, R, HELM, 1, T>), grid, dim3(NT), 0, s, a); break;
+        case 2: WQ_KLAUNCH(ps, (k_mg_down<E, R, HELM, 2, T>), grid, dim3(NT), 0, s, a); break;
+        default: WQ_KLAUNCH(ps, (k_mg_down<E, R, HELM, 3, T>), grid, dim3(NT), 0, s, a); break;
+    }
+}
+
+template <typename E, int R, bool HELM, int T>
+void launch_up_t(const UpArgs<E>& a, int nu, dim3 grid, hipStream_t s, const ProfScope& ps) {
+    constexpr int NT = tile_threads<T>();
+    switch (nu) {
+        case 1: WQ_KLAUNCH(ps, (k_mg_up<E, R, HELM, 1, T>), grid, dim3(NT), 0, s, a); break;
+        case 2: WQ_KLAUNCH(ps, (k_mg_up<E, R, HELM, 2, T>), grid, dim3(NT), 0, s, a); break;
+        default: WQ_KLAUNCH(ps, (k_mg_up<E, R, HELM, 3, T>), grid, dim3(NT), 0, s, a); break;
     }
 }
 
 template <typename E, int R, bool HELM>
-void launch_up(const UpArgs<E>& a, int nu, dim3 grid, hipStream_t s, const ProfScope& ps) {
-    switch (nu) {
-        case 1: WQ_KLAUNCH(ps, (k_mg_up<E, R, HELM, 1, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
-        case 2: WQ_KLAUNCH(ps, (k_mg_up<E, R, HELM, 2, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
-        default: WQ_KLAUNCH(ps, (k_mg_up<E, R, HELM, 3, kTile>), grid, dim3(kTileThreads), 0, s, a); break;
-    }
+void launch_down(const DownArgs<E>& a, int nu, dim3 grid, hipStream_t s, const ProfScope& ps, int T) {
+    if (T == 16) launch_down_t<E, R, HELM, 16>(a, nu, grid, s, ps);
+    else launch_down_t<E, R, HELM, 32>(a, nu, grid, s, ps);
+}
+
+template <typename E, int R, bool HELM>
+void launch_up(const UpArgs<E>& a, int nu, dim3 grid, hipStream_t s, const ProfScope& ps, int T) {
+    if (T == 16) launch_up_t<E, R, HELM, 16>(a, nu, grid, s, ps);
+    else launch_up_t<E, R, HELM, 32>(a, nu, grid, s, ps);
 }
 
 template <typename E>
-void down(int R, bool helm, const DownArgs<E>& a, int nu, dim3 g, hipStream_t s, const ProfScope& ps) {
-    if (R == 1) helm ? launch_down<E, 1, true>(a, nu, g, s, ps) : launch_down<E, 1, false>(a, nu, g, s, ps);
-    else helm ? launch_down<E, 2, true>(a, nu, g, s, ps) : launch_down<E, 2, false>(a, nu, g, s, ps);
+void down(int R, bool helm, const DownArgs<E>& a, int nu, dim3 g, hipStream_t s, const ProfScope& ps, int T) {
+    if (R == 1) helm ? launch_down<E, 1, true>(a, nu, g, s, ps, T) : launch_down<E, 1, false>(a, nu, g, s, ps, T);
+    else helm ? launch_down<E, 2, true>(a, nu, g, s, ps, T) : launch_down<E, 2, false>(a, nu, g, s, ps, T);
 }
 
 template <typename E>
-void up(int R, bool helm, const UpArgs<E>& a, int nu, dim3 g, hipStream_t s, const ProfScope& ps) {
-    if (R == 1) helm ? launch_up<E, 1, true>(a, nu, g, s, ps) : launch_up<E, 1, false>(a, nu, g, s, ps);
-    else helm ? launch_up<E, 2, true>(a, nu, g, s, ps) : launch_up<E, 2, false>(a, nu, g, s, ps);
+void up(int R, bool helm, const UpArgs<E>& a, int nu, dim3 g, hipStream_t s, const ProfScope& ps, int T) {
+    if (R == 1) helm ? launch_up<E, 1, true>(a, nu, g, s, ps, T) : launch_up<E, 1, false>(a, nu, g, s, ps, T);
+    else helm ? launch_up<E, 2, true>(a, nu, g, s, ps, T) : launch_up<E, 2, false>(a, nu, g, s, ps, T);
 }
 
-dim3 tiles(int N) { return dim3((N + kTile - 1) / kTile, (N + kTile - 1) / kTile); }
+dim3 tiles(int N, int T = kTile) { return dim3((N + T - 1) / T, (N + T - 1) / T); }
 
 const char* type_name(double) { return "double"; }
 const char* type_name(float) { return "float"; }
@@ -774,7 +796,8 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
             a.f_c[r] = F(l + 1, r);
         }
         a.k2 = helm ? K(l) : nullptr;
-        const dim3 g = tiles(L.N);
+        const int T = tile_for(L.N);
+        const dim3 g = tiles(L.N, T);
         a.nblk = g.x * g.y;
         a.norm_part = (l == 0 && norm_slot >= 0)
                           ? c->norm_part + (size_t)norm_slot * 4 * c->max_tiles
@@ -782,11 +805,11 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
         // algorithmic bytes per owned node: u (when read), f, k2, smoothed u, coarse f
         const double nodes = (double)L.N * L.N;
         char nm[64];
-        std::snprintf(nm, sizeof nm, "k_mg_down<%s, %d, %s, %d, 32>@%d", type_name(E()), R,
-                      helm ? "true" : "false", c->cfg.nu_pre, L.N);
+        std::snprintf(nm, sizeof nm, "k_mg_down<%s, %d, %s, %d, %d>@%d", type_name(E()), R,
+                      helm ? "true" : "false", c->cfg.nu_pre, T, L.N);
         ProfScope ps(c, nm, nodes * ((a.u_in[0] ? eb * R : 0.0) + eb * R + (helm ? 8.0 : 0.0) +
                                      eb * R + eb * R / 4));
-        down<E>(R, helm, a, c->cfg.nu_pre, g, s, ps);
+        down<E>(R, helm, a, c->cfg.nu_pre, g, s, ps, T);
     }
     {
         wq::Level& L = c->lev[lc];
@@ -805,10 +828,18 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
         a.nu2 = c->cfg.nu_post;
         const double nodes = (double)(L.N + 1) * (L.N + 1);
         char nm[64];
-        std::snprintf(nm, sizeof nm, "k_mg_coarse<%s, %s>", type_name(E()), helm ? "true" : "false");
+        // float sweeps when the coarse levels only correct a finer level
+        const bool f32 = WQ_COARSE_F32 && lc > 0;
+        std::snprintf(nm, sizeof nm, "k_mg_coarse<%s, %s, %s>", type_name(E()),
+                      f32 ? "float" : type_name(E()), helm ? "true" : "false");
         ProfScope ps(c, nm, nodes * (eb * R + (a.u_init[0] ? eb * R : 0.0) + (helm ? 8.0 : 0.0) + eb * R));
-        if (helm) WQ_KLAUNCH(ps, (k_mg_coarse<E, true>), dim3(R), dim3(kCoarseThreads), 0, s, a);
-        else WQ_KLAUNCH(ps, (k_mg_coarse<E, false>), dim3(R), dim3(kCoarseThreads), 0, s, a);
+        if (f32) {
+            if (helm) WQ_KLAUNCH(ps, (k_mg_coarse<E, float, true>), dim3(R), dim3(kCoarseThreads), 0, s, a);
+            else WQ_KLAUNCH(ps, (k_mg_coarse<E, float, false>), dim3(R), dim3(kCoarseThreads), 0, s, a);
+        } else {
+            if (helm) WQ_KLAUNCH(ps, (k_mg_coarse<E, E, true>), dim3(R), dim3(kCoarseThreads), 0, s, a);
+            else WQ_KLAUNCH(ps, (k_mg_coarse<E, E, false>), dim3(R), dim3(kCoarseThreads), 0, s, a);
+        }
     }
     for (int l = lc - 1; l >= 0; --l) {
         wq::Level& L = c->lev[l];
@@ -827,10 +858,11 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
         // per owned node: smoothed u, coarse correction (1/4), f, k2, corrected u
         const double nodes = (double)L.N * L.N;
         char nm[64];
-        std::snprintf(nm, sizeof nm, "k_mg_up<%s, %d, %s, %d, 32>@%d", type_name(E()), R,
-                      helm ? "true" : "false", c->cfg.nu_post, L.N);
+        const int T = tile_for(L.N);
+        std::snprintf(nm, sizeof nm, "k_mg_up<%s, %d, %s, %d, %d>@%d", type_name(E()), R,
+                      helm ? "true" : "false", c->cfg.nu_post, T, L.N);
         ProfScope ps(c, nm, nodes * (eb * R + eb * R / 4 + eb * R + (helm ? 8.0 : 0.0) + eb * R));
-        up<E>(R, helm, a, c->cfg.nu_post, tiles(L.N), s, ps);
+        up<E>(R, helm, a, c->cfg.nu_post, tiles(L.N, T), s, ps, T);
     }
 }
 
@@ -839,7 +871,10 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
 void resnorm(wandqs_ctx* c, int R, bool helm, const Hier<double>& hz, int slot,
              float* const* r32) {
     const wq::Level& L = c->lev[0];
-    const dim3 g = tiles(L.N);
+    // the same tiles as the level-0 down pass: every norm slot of a solve has
+    // one partial-sum layout
+    const int T = tile_for(L.N);
+    const dim3 g = tiles(L.N, T);
     double* part = c->norm_part + (size_t)slot * 4 * c->max_tiles;
     const int nblk = g.x * g.y;
     const double* u1 = R > 1 ? hz.u0[1] : nullptr;
@@ -851,11 +886,11 @@ void resnorm(wandqs_ctx* c, int R, bool helm, const Hier<double>& hz, int slot,
                   r32 ? "+defect" : "");
     ProfScope ps(c, nm, (double)L.N * L.N * (16.0 * R + (helm ? 8.0 : 0.0) + (r32 ? 4.0 * R : 0.0)));
     if (R == 1) {
-        if (helm) WQ_KLAUNCH(ps, (k_resnorm<1, true>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch);
-        else WQ_KLAUNCH(ps, (k_resnorm<1, false>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch);
+        if (helm) WQ_KLAUNCH(ps, (k_resnorm<1, true>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch, T);
+        else WQ_KLAUNCH(ps, (k_resnorm<1, false>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch, T);
     } else {
-        if (helm) WQ_KLAUNCH(ps, (k_resnorm<2, true>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch);
-        else WQ_KLAUNCH(ps, (k_resnorm<2, false>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch);
+        if (helm) WQ_KLAUNCH(ps, (k_resnorm<2, true>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch, T);
+        else WQ_KLAUNCH(ps, (k_resnorm<2, false>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch, T);
     }
 }
 
@@ -926,7 +961,9 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
     }
     const int N = c->N;
     const double atol = c->cfg.mg_atol * std::sqrt((double)(N - 1) * (N - 1));
-    const dim3 g = tiles(N);
+    // partial sums per tile (the level-0 tiles, for both the down pass and the
+    // residual-norm kernel)
+    const dim3 g = tiles(N, tile_for(N));
     const int nblk = g.x * g.y;
     int done = 0;
     int pred = c->pred[kind] < 1 ? 1 : c->pred[kind];

@@ -200,7 +200,9 @@ __global__ __launch_bounds__(256) void k_deposit_n(int N, double L, double h, do
                                                    double* __restrict__ fpsi) {
     constexpr int TC = TN + 1;
     __shared__ double corner[TC * TC][4];
-    const int a0 = blockIdx.x * TN, b0 = blockIdx.y * TN;
+    int tbx, tby;
+    tile_of_block(tbx, tby);
+    const int a0 = tbx * TN, b0 = tby * TN;
     for (int c = threadIdx.x; c < TC * TC; c += blockDim.x) {
         const int cy = c / TC, cx = c - cy * TC;
         const int ga = a0 - 1 + cx, gb = b0 - 1 + cy;
@@ -258,7 +260,9 @@ __global__ __launch_bounds__(256) void k_deposit_jT(int N, double L, double h, d
     constexpr int TC = TN + 1;
     constexpr int M = 5;
     __shared__ double corner[TC * TC][4 * M];
-    const int a0 = blockIdx.x * TN, b0 = blockIdx.y * TN;
+    int tbx, tby;
+    tile_of_block(tbx, tby);
+    const int a0 = tbx * TN, b0 = tby * TN;
     bool bad = false;
     for (int c = threadIdx.x; c < TC * TC; c += blockDim.x) {
         const int cy = c / TC, cx = c - cy * TC;

@@ -50,6 +50,19 @@ struct Level {
     float* f32[2] = {nullptr, nullptr};
 };
 
+// Tile of this workgroup in a 2-D grid of tiles.  Workgroups are dealt to the
+// 8 XCDs round-robin in dispatch order; the mapping gives each XCD a contiguous
+// band of tiles (row-major), so the halo a tile shares with its neighbours is
+// mostly fetched once into that XCD's L2 instead of once per tile.
+__device__ __forceinline__ void tile_of_block(int& bx, int& by) {
+    const int gx = gridDim.x, n = gx * gridDim.y;
+    const int b = blockIdx.y * gx + blockIdx.x;
+    const int k = b & 7, q = n >> 3, r = n & 7;
+    const int t = k * q + (k < r ? k : r) + (b >> 3);
+    by = t / gx;
+    bx = t - by * gx;
+}
+
 enum SolveKind {
     kSolvePsi = 0,
     kSolveEB = 1,
