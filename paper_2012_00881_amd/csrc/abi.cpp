@@ -146,8 +146,10 @@ wandqs_status save_checkpoint(wandqs_ctx* c, wq::Checkpoint& k) {
         if ((s = copy_d2d(c, k.fields[q], c->fields[q], nb)) != WANDQS_OK) return s;
         if ((s = copy_d2d(c, k.fields_prev[q], c->fields_prev[q], nb)) != WANDQS_OK) return s;
         if ((s = copy_d2d(c, k.fields_prev2[q], c->fields_prev2[q], nb)) != WANDQS_OK) return s;
+        if (kGuessMax > 3 && (s = copy_d2d(c, k.fields_prev3[q], c->fields_prev3[q], nb)) != WANDQS_OK)
+            return s;
     }
-    if ((s = copy_d2d(c, k.st, c->st, 5 * sizeof(double))) != WANDQS_OK) return s;
+    if ((s = copy_d2d(c, k.st, c->st, 6 * sizeof(double))) != WANDQS_OK) return s;
     std::memcpy(k.pred, c->pred, sizeof(k.pred));
     k.n_guess = c->n_guess;
     return WANDQS_OK;
@@ -164,8 +166,10 @@ wandqs_status restore_checkpoint(wandqs_ctx* c, const wq::Checkpoint& k) {
         if ((s = copy_d2d(c, c->fields[q], k.fields[q], nb)) != WANDQS_OK) return s;
         if ((s = copy_d2d(c, c->fields_prev[q], k.fields_prev[q], nb)) != WANDQS_OK) return s;
         if ((s = copy_d2d(c, c->fields_prev2[q], k.fields_prev2[q], nb)) != WANDQS_OK) return s;
+        if (kGuessMax > 3 && (s = copy_d2d(c, c->fields_prev3[q], k.fields_prev3[q], nb)) != WANDQS_OK)
+            return s;
     }
-    if ((s = copy_d2d(c, c->st, k.st, 5 * sizeof(double))) != WANDQS_OK) return s;
+    if ((s = copy_d2d(c, c->st, k.st, 6 * sizeof(double))) != WANDQS_OK) return s;
     std::memcpy(c->pred, k.pred, sizeof(k.pred));
     c->n_guess = k.n_guess;
     return WANDQS_OK;
@@ -186,8 +190,8 @@ wandqs_status do_slice(wandqs_ctx* c, int rec_slot, int64_t probe_slice, bool ta
         else if ((s = save_checkpoint(c, c->ckpt[k])) != WANDQS_OK) return s;
     }
     // initial guesses: the previous slice's fields (Sec. VII.A), extrapolated in
-    // xi through the last two or three slices once they are known
-    if ((s = extrapolate_guess(c, c->n_guess < 3 ? c->n_guess - 1 : 2)) != WANDQS_OK) return s;
+    // xi through the last slices once they are known
+    if ((s = extrapolate_guess(c, c->n_guess - 1)) != WANDQS_OK) return s;
     if ((s = slice_sort(c)) != WANDQS_OK) return s;
     if (rec) {
         const size_t pb = sizeof(double) * (size_t)c->P;
@@ -222,7 +226,7 @@ wandqs_status do_slice(wandqs_ctx* c, int rec_slot, int64_t probe_slice, bool ta
     }
     if (!c->probes.empty() && (s = probes_accumulate(c, probe_slice)) != WANDQS_OK) return s;
     if ((s = push_and_step(c, rec_slot)) != WANDQS_OK) return s;  // Push_Trajectory + Step_Size_Refinement
-    if (c->n_guess < 3) ++c->n_guess;
+    if (c->n_guess < kGuessMax) ++c->n_guess;
     if (taping) ++c->tape_n;
     return WANDQS_OK;
 }
@@ -264,6 +268,8 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
     for (int k = 0; k < 5; ++k) c->fields[k] = arr(0);
     for (int k = 0; k < 5; ++k) c->fields_prev[k] = arr(0);
     for (int k = 0; k < 5; ++k) c->fields_prev2[k] = arr(0);
+    if (kGuessMax > 3)
+        for (int k = 0; k < 5; ++k) c->fields_prev3[k] = arr(0);
     for (int r = 0; r < 2; ++r) {
         L0.um[r] = arr(0);
         L0.f[r] = arr(0);
@@ -327,6 +333,7 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
                 k.fields[q] = arr(0);
                 k.fields_prev[q] = arr(0);
                 k.fields_prev2[q] = arr(0);
+                k.fields_prev3[q] = kGuessMax > 3 ? arr(0) : nullptr;
             }
             k.st = (double*)take(sizeof(double) * 8);
         }
@@ -543,7 +550,7 @@ wandqs_status wandqs_init(const wandqs_config* cfg, int32_t n_slices, void* d_wo
                     host[c->P + i] = -L + h * (((double)b + ((double)sy + 0.5) / s) + J * (2.0 * uy - 1.0));
                     ids[i] = (int32_t)i;
                 }
-    const double st0[5] = {0.0, cfg->dxi0, 0.0, 0.0, 0.0};
+    const double st0[6] = {0.0, cfg->dxi0, 0.0, 0.0, 0.0, 0.0};
     bool ok = hipMemcpyAsync(c->pa[0][0], host.data(), sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
               hipMemcpyAsync(c->pa[0][1], host.data() + c->P, sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
               hipMemcpyAsync(c->pid[0], ids.data(), sizeof(int32_t) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&

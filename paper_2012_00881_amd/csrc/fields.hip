@@ -170,14 +170,15 @@ __global__ void k_unpack(int N, int pitch, const double* __restrict__ src, doubl
 }
 
 // Initial guesses for the five solves of this slice: the fields u of the last
-// slice (at xi_u), extrapolated to xi through the slices before (p1 at xi_1,
-// p2 at xi_2) -- order 0: u; order 1: the line through u and p1; order 2: the
-// parabola through u, p1 and p2 (Lagrange form).  The guess goes to `out`
-// (p2's array, which the host then rotates into the field's place).
+// slice (at xi_0), extrapolated to xi through the slices before (p1 at xi_1,
+// p2 at xi_2, p3 at xi_3) -- order 0: u; order m: the Lagrange polynomial of
+// degree m through u, p1, ..., pm.  The guess goes to `out` (the oldest
+// array, which the host then rotates into the field's place).
 struct FieldPtrs {
     const double* u[5];
     const double* p1[5];
     const double* p2[5];
+    const double* p3[5];
     double* out[5];
 };
 
@@ -187,21 +188,31 @@ __global__ void k_extrapolate(int N, int pitch, const double* __restrict__ st, F
     const int b = blockIdx.y;
     if (a > N) return;
     const size_t g = (size_t)b * pitch + a;
-    const double xi = st[0], x0 = st[2], x1 = st[3], x2 = st[4];
-    if (order >= 2 && (x0 == x1 || x0 == x2 || x1 == x2)) order = 1;
-    if (order == 1 && x0 == x1) order = 0;
-    double t = 0.0, w1 = 0.0, w2 = 0.0;
-    if (order == 1) t = (xi - x0) / (x0 - x1);
-    if (order == 2) {
-        w1 = (xi - x0) * (xi - x2) / ((x1 - x0) * (x1 - x2));
-        w2 = (xi - x0) * (xi - x1) / ((x2 - x0) * (x2 - x1));
+    const double xi = st[0];
+    const double x[4] = {st[2], st[3], st[4], st[5]};
+    // drop to a lower order if two of the points coincide
+    for (bool ok = false; !ok && order > 0;) {
+        ok = true;
+        for (int i = 0; i <= order && ok; ++i)
+            for (int j = 0; j < i; ++j)
+                if (x[i] == x[j]) ok = false;
+        if (!ok) --order;
+    }
+    double w[4] = {1.0, 0.0, 0.0, 0.0};  // weights of p1..p3 relative to u (w[0] unused)
+    for (int i = 1; i <= order; ++i) {
+        double l = 1.0;
+        for (int j = 0; j <= order; ++j)
+            if (j != i) l *= (xi - x[j]) / (x[i] - x[j]);
+        w[i] = l;
     }
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
         const double u = f.u[k][g];
         double v = u;
-        if (order == 1) v = u + t * (u - f.p1[k][g]);
-        if (order == 2) v = u + (w1 * (f.p1[k][g] - u) + w2 * (f.p2[k][g] - u));
+        if (order == 1) v = u + w[1] * (f.p1[k][g] - u);
+        if (order == 2) v = u + (w[1] * (f.p1[k][g] - u) + w[2] * (f.p2[k][g] - u));
+        if (order == 3)
+            v = u + (w[1] * (f.p1[k][g] - u) + w[2] * (f.p2[k][g] - u) + w[3] * (f.p3[k][g] - u));
         f.out[k][g] = v;
     }
 }
@@ -297,21 +308,24 @@ wandqs_status unpack_fields(wandqs_ctx* c, const double* src, int n, double* con
 
 wandqs_status extrapolate_guess(wandqs_ctx* c, int order) {
     FieldPtrs f;
+    double* const* oldest = kGuessMax > 3 ? c->fields_prev3 : c->fields_prev2;
     for (int k = 0; k < 5; ++k) {
         f.u[k] = c->fields[k];
         f.p1[k] = c->fields_prev[k];
         f.p2[k] = c->fields_prev2[k];
-        f.out[k] = c->fields_prev2[k];
+        f.p3[k] = kGuessMax > 3 ? c->fields_prev3[k] : c->fields_prev2[k];
+        f.out[k] = oldest[k];
     }
-    order = order < 0 ? 0 : (order > 2 ? 2 : order);
+    order = order < 0 ? 0 : (order > kGuessMax - 1 ? kGuessMax - 1 : order);
     {
         ProfScope ps(c, "k_extrapolate", (double)(c->N + 1) * (c->N + 1) * 5 * 8.0 * (order + 2));
         WQ_KLAUNCH(ps, k_extrapolate, node_grid(c->N), dim3(128), 0, c->stream, c->N,
                    c->lev[0].pitch, c->st, f, order);
     }
     WQ_LAUNCH_CHECK();
-    for (int k = 0; k < 5; ++k) {  // prev2 <- prev, prev <- u, u <- guess
-        double* g = c->fields_prev2[k];
+    for (int k = 0; k < 5; ++k) {  // oldest <- ... <- prev <- u <- guess
+        double* g = oldest[k];
+        if (kGuessMax > 3) c->fields_prev3[k] = c->fields_prev2[k];
         c->fields_prev2[k] = c->fields_prev[k];
         c->fields_prev[k] = c->fields[k];
         c->fields[k] = g;

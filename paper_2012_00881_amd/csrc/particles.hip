@@ -427,7 +427,8 @@ __global__ __launch_bounds__(256) void k_dxi(int nparts, const double* __restric
         rec[2] = vmax;
         rec[3] = (double)flags[0];
     }
-    st[4] = st[3];  // the fields now stored belong to this slice
+    st[5] = st[4];  // the fields now stored belong to this slice
+    st[4] = st[3];
     st[3] = st[2];
     st[2] = st[0];
     st[0] = st[0] + st[1];

@@ -22,6 +22,10 @@ constexpr int kTile = 32;       // multigrid tile edge (fine nodes owned by one 
 constexpr int kDepTile = 16;    // deposit tile edge (nodes owned by one workgroup)
 constexpr int kPredKinds = 8;   // solve kinds with their own V-cycle batch prediction
 constexpr int kThetaSeg = 4096; // nodes per partial sum of the driver-parameter adjoint
+#ifndef WQ_EXTRAP_ORDER
+#define WQ_EXTRAP_ORDER 3
+#endif
+constexpr int kGuessMax = WQ_EXTRAP_ORDER + 1;  // solved slices the guesses use
 
 // Driver beams as a by-value kernel argument.
 struct BeamSet {
@@ -80,6 +84,7 @@ struct Checkpoint {
     double* fields[5] = {};
     double* fields_prev[5] = {};
     double* fields_prev2[5] = {};
+    double* fields_prev3[5] = {};
     double* st = nullptr;
     int pred[kPredKinds] = {};
     int n_guess = 0;
@@ -156,10 +161,11 @@ struct wandqs_ctx {
     // device memory carved from the caller's workspace
     wq::Level lev[wq::kMaxLevels];
     double* fields[5] = {};
-    // fields of the two slices before (initial-guess extrapolation); the three
-    // arrays of each field rotate by pointer
+    // fields of the slices before (initial-guess extrapolation); the arrays of
+    // each field rotate by pointer
     double* fields_prev[5] = {};
     double* fields_prev2[5] = {};
+    double* fields_prev3[5] = {};
     double* mom[6] = {};
     double* jz = nullptr;
     double* k2lev = nullptr;  // k2 of the coarse-kernel levels (dense, concatenated)
@@ -169,7 +175,7 @@ struct wandqs_ctx {
     int32_t *key = nullptr, *perm = nullptr, *cell_count = nullptr, *cell_start = nullptr,
             *scan_blk = nullptr;
     int n_scan_blocks = 0;
-    double* st = nullptr;  // [xi, dxi, xi of fields, of fields_prev, of fields_prev2]
+    double* st = nullptr;  // [xi, dxi, xi of fields, of fields_prev, of fields_prev2, of fields_prev3]
     double* vmax_part = nullptr;  // per push block
     int n_push_blocks = 0;
     int32_t* flags = nullptr;
@@ -201,7 +207,7 @@ struct wandqs_ctx {
     double* h_pin = nullptr;  // pinned readback buffer
     int pred[wq::kPredKinds] = {1, 1, 1, 1, 1, 1, 1, 1};  // V-cycles of the last solve per kind (batch size)
     bool failed = false;
-    int n_guess = 0;  // slices since init/set_state, up to 3 (extrapolation order + 1)
+    int n_guess = 0;  // slices since init/set_state, up to kGuessMax (extrapolation order + 1)
     std::string err;
     wq::SolveResult last[3];
     wq::Prof prof;
