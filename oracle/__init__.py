@@ -245,7 +245,37 @@ def _run_loss(self, state, n_slices, weights=None, grad=False):
     return st, loss.value, (tb[:nth] if grad else None)
 
 
+def _run_tangent(self, state, n_slices, dP=None, dtheta=None, weights=None):
+    """Tangent-linear run (forward mode, up to 8 directions): returns
+    (status, loss, dloss[K], dout[K][4][P], dF[K][5][N+1][N+1]).  dP: [K][4][P]
+    seeds of the particles, dtheta: [K][n_theta] seeds of the driver
+    parameters.  Advances `state` like run()."""
+    x, y, px, py = (_f64(state[k]).copy() for k in ("x", "y", "px", "py"))
+    P = x.size
+    nth = lib().oracle_theta_count(C.byref(self.c))
+    K = max(1, (0 if dP is None else np.asarray(dP).shape[0]),
+            (0 if dtheta is None else np.asarray(dtheta).shape[0]))
+    dPa = None if dP is None else _f64(dP).reshape(K, 4, P)
+    dTa = None if dtheta is None else _f64(dtheta).reshape(K, nth)
+    pr = _probe_array(self.cfg)
+    w = np.ones(len(pr)) if weights is None else _f64(weights)
+    fields = _f64(state["fields"]).reshape(5, self.N + 1, self.N + 1).copy()
+    xi = C.c_double(state["xi"])
+    dxi = C.c_double(state["dxi"])
+    loss = C.c_double(0.0)
+    dloss = np.zeros(K)
+    dout = np.zeros((K, 4, P))
+    dF = np.zeros((K, 5, self.N + 1, self.N + 1))
+    st = lib().oracle_run_tangent(C.byref(self.c), P, _p(x), _p(y), _p(px), _p(py), _p(fields),
+                                  C.byref(xi), C.byref(dxi), int(n_slices), int(K), _p(dPa),
+                                  _p(dTa), len(pr), _p(pr), _p(w), C.byref(loss), _p(dloss),
+                                  _p(dout), _p(dF))
+    state.update(x=x, y=y, px=px, py=py, fields=fields, xi=xi.value, dxi=dxi.value)
+    return st, loss.value, dloss, dout, dF
+
+
 Oracle.slice_adjoint = _slice_adjoint
+Oracle.run_tangent = _run_tangent
 Oracle.run_loss = _run_loss
 
 

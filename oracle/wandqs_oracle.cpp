@@ -26,6 +26,11 @@
  * Array layout: node (a, b) of an (N+1)x(N+1) array is element b*(N+1)+a
  * (x index fastest).  Field order: psi, Ez, Bz, Bx, By.
  *
+ * The forward slice is written once for a scalar type: double is the oracle;
+ * a dual number (value plus directional derivatives) gives its tangent-linear
+ * model (oracle_run_tangent).  The reverse sweep (oracle_slice_adjoint,
+ * oracle_run_loss) is written by hand from the same formulas.
+ *
  * Parity status of each function is recorded in the design notes; every
  * function here is pinned by a test in tests/test_oracle_*.py.
  */
@@ -73,6 +78,76 @@ enum { ORC_OK = 0, ORC_INVALID = -1, ORC_NOCONV = -4, ORC_NONPHYS = -5 };
 
 namespace {
 
+/* ------------------------------------------------------------- scalars -- */
+/* The forward code below is written once for a scalar type T: double (the
+ * oracle) or Dual<K>, a value with K directional derivatives (forward-mode,
+ * the tangent-linear model of the same discrete map).  Every value part of a
+ * Dual follows exactly the double arithmetic; the discrete decisions (the CIC
+ * cell, wall reflections, the multigrid stop) are taken on values. */
+template <int K>
+struct Dual {
+    double v;
+    double d[K];
+    Dual(double x = 0.0) : v(x) {
+        for (int k = 0; k < K; ++k) d[k] = 0.0;
+    }
+};
+template <int K> Dual<K> operator+(const Dual<K>& a, const Dual<K>& b) {
+    Dual<K> r(a.v + b.v);
+    for (int k = 0; k < K; ++k) r.d[k] = a.d[k] + b.d[k];
+    return r;
+}
+template <int K> Dual<K> operator-(const Dual<K>& a, const Dual<K>& b) {
+    Dual<K> r(a.v - b.v);
+    for (int k = 0; k < K; ++k) r.d[k] = a.d[k] - b.d[k];
+    return r;
+}
+template <int K> Dual<K> operator-(const Dual<K>& a) {
+    Dual<K> r(-a.v);
+    for (int k = 0; k < K; ++k) r.d[k] = -a.d[k];
+    return r;
+}
+template <int K> Dual<K> operator*(const Dual<K>& a, const Dual<K>& b) {
+    Dual<K> r(a.v * b.v);
+    for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+    return r;
+}
+template <int K> Dual<K> operator/(const Dual<K>& a, const Dual<K>& b) {
+    Dual<K> r(a.v / b.v);
+    for (int k = 0; k < K; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) / b.v;
+    return r;
+}
+template <int K> Dual<K> operator+(const Dual<K>& a, double b) { return a + Dual<K>(b); }
+template <int K> Dual<K> operator+(double a, const Dual<K>& b) { return Dual<K>(a) + b; }
+template <int K> Dual<K> operator-(const Dual<K>& a, double b) { return a - Dual<K>(b); }
+template <int K> Dual<K> operator-(double a, const Dual<K>& b) { return Dual<K>(a) - b; }
+template <int K> Dual<K> operator*(const Dual<K>& a, double b) { return a * Dual<K>(b); }
+template <int K> Dual<K> operator*(double a, const Dual<K>& b) { return Dual<K>(a) * b; }
+template <int K> Dual<K> operator/(const Dual<K>& a, double b) { return a / Dual<K>(b); }
+template <int K> Dual<K> operator/(double a, const Dual<K>& b) { return Dual<K>(a) / b; }
+template <int K> Dual<K>& operator+=(Dual<K>& a, const Dual<K>& b) { return a = a + b; }
+template <int K> Dual<K>& operator-=(Dual<K>& a, const Dual<K>& b) { return a = a - b; }
+template <int K> Dual<K> sqrt(const Dual<K>& a) {
+    Dual<K> r(std::sqrt(a.v));
+    for (int k = 0; k < K; ++k) r.d[k] = a.d[k] / (2.0 * r.v);
+    return r;
+}
+template <int K> Dual<K> exp(const Dual<K>& a) {
+    Dual<K> r(std::exp(a.v));
+    for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * r.v;
+    return r;
+}
+using std::exp;
+using std::sqrt;
+
+inline double val(double x) { return x; }
+template <int K> double val(const Dual<K>& x) { return x.v; }
+/* components for the multigrid stop rule: the value and every derivative */
+inline int ncomp(double) { return 1; }
+template <int K> int ncomp(const Dual<K>&) { return K + 1; }
+inline double comp(double x, int) { return x; }
+template <int K> double comp(const Dual<K>& x, int c) { return c == 0 ? x.v : x.d[c - 1]; }
+
 /* ------------------------------------------------------------------ grid -- */
 
 struct Grid {
@@ -86,27 +161,29 @@ struct Grid {
 
 /* Cloud-in-cell shape: cell index c in [0, N-1] and offset d in [0, 1] so that
  * the particle weights node c by (1 - d) and node c+1 by d. */
-void cic(const Grid& g, double x, int& c, double& d) {
-    double t = (x + g.L) / g.h;
-    int k = (int)std::floor(t);
+template <class T>
+void cic(const Grid& g, const T& x, int& c, T& d) {
+    T t = (x + g.L) / g.h;
+    int k = (int)std::floor(val(t));
     if (k < 0) k = 0;
     if (k > g.N - 1) k = g.N - 1;
     c = k;
-    d = t - k;
+    d = t - (double)k;
 }
 
 /* deposit(q)[a,b] = sum_i w q_i W_a(x_i) W_b(y_i) / h^2 with w = n0 h^2 / ppc.
  * With q = 1 this is the surface density n* of Sec. III.B (n* = int f* dP). */
-void deposit(const Grid& g, const oracle_cfg& c, int P, const double* x, const double* y,
-             const double* q, double* out) {
+template <class T>
+void deposit(const Grid& g, const oracle_cfg& c, int P, const T* x, const T* y, const T* q,
+             T* out) {
     const double w = c.n0 * g.h * g.h / c.ppc;
-    std::fill(out, out + g.nn(), 0.0);
+    std::fill(out, out + g.nn(), T(0.0));
     for (int i = 0; i < P; ++i) {
         int a, b;
-        double dx, dy;
+        T dx, dy;
         cic(g, x[i], a, dx);
         cic(g, y[i], b, dy);
-        double s = w * (q ? q[i] : 1.0) / (g.h * g.h);
+        T s = w * (q ? q[i] : T(1.0)) / (g.h * g.h);
         out[g.id(a, b)] += s * (1.0 - dx) * (1.0 - dy);
         out[g.id(a + 1, b)] += s * dx * (1.0 - dy);
         out[g.id(a, b + 1)] += s * (1.0 - dx) * dy;
@@ -115,9 +192,10 @@ void deposit(const Grid& g, const oracle_cfg& c, int P, const double* x, const d
 }
 
 /* gather(F)_i = sum over the four cell corners of F W_a W_b. */
-double gather1(const Grid& g, const double* F, double x, double y) {
+template <class T>
+T gather1(const Grid& g, const T* F, const T& x, const T& y) {
     int a, b;
-    double dx, dy;
+    T dx, dy;
     cic(g, x, a, dx);
     cic(g, y, b, dy);
     return F[g.id(a, b)] * (1.0 - dx) * (1.0 - dy) + F[g.id(a + 1, b)] * dx * (1.0 - dy) +
@@ -125,10 +203,12 @@ double gather1(const Grid& g, const double* F, double x, double y) {
 }
 
 /* Central differences D_x u, D_y u at interior nodes. */
-double Dx(const Grid& g, const double* u, int a, int b) {
+template <class T>
+T Dx(const Grid& g, const T* u, int a, int b) {
     return (u[g.id(a + 1, b)] - u[g.id(a - 1, b)]) / (2.0 * g.h);
 }
-double Dy(const Grid& g, const double* u, int a, int b) {
+template <class T>
+T Dy(const Grid& g, const T* u, int a, int b) {
     return (u[g.id(a, b + 1)] - u[g.id(a, b - 1)]) / (2.0 * g.h);
 }
 
@@ -136,36 +216,40 @@ double Dy(const Grid& g, const double* u, int a, int b) {
 
 /* One level of the hierarchy for  L_h u - k2 u = f  on the interior nodes,
  * u = 0 on the boundary.  k2 == empty means the Poisson operator. */
+template <class T>
 struct Level {
     int N;
     double h;
-    std::vector<double> u, f, k2;
+    std::vector<T> u, f, k2;
     int id(int a, int b) const { return b * (N + 1) + a; }
 };
 
 /* (L_h u - k2 u) at interior node (a, b); 5-point Laplacian, Sec. VII.B eq. (33). */
-double apply_at(const Level& lv, const double* u, int a, int b) {
-    double lap = (u[lv.id(a - 1, b)] + u[lv.id(a + 1, b)] + u[lv.id(a, b - 1)] +
-                  u[lv.id(a, b + 1)] - 4.0 * u[lv.id(a, b)]) / (lv.h * lv.h);
-    double k2 = lv.k2.empty() ? 0.0 : lv.k2[lv.id(a, b)];
+template <class T>
+T apply_at(const Level<T>& lv, const T* u, int a, int b) {
+    T lap = (u[lv.id(a - 1, b)] + u[lv.id(a + 1, b)] + u[lv.id(a, b - 1)] +
+             u[lv.id(a, b + 1)] - 4.0 * u[lv.id(a, b)]) / (lv.h * lv.h);
+    T k2 = lv.k2.empty() ? T(0.0) : lv.k2[lv.id(a, b)];
     return lap - k2 * u[lv.id(a, b)];
 }
 
 /* Red-black Gauss-Seidel half sweep: the nodes with (a+b) % 2 == color are set
  * to the value that zeroes their own equation given their four neighbours. */
-void relax_color(Level& lv, int color) {
+template <class T>
+void relax_color(Level<T>& lv, int color) {
     const double h2 = lv.h * lv.h;
     for (int b = 1; b < lv.N; ++b)
         for (int a = 1; a < lv.N; ++a) {
             if (((a + b) & 1) != color) continue;
-            double nb = lv.u[lv.id(a - 1, b)] + lv.u[lv.id(a + 1, b)] + lv.u[lv.id(a, b - 1)] +
-                        lv.u[lv.id(a, b + 1)];
-            double k2 = lv.k2.empty() ? 0.0 : lv.k2[lv.id(a, b)];
+            T nb = lv.u[lv.id(a - 1, b)] + lv.u[lv.id(a + 1, b)] + lv.u[lv.id(a, b - 1)] +
+                   lv.u[lv.id(a, b + 1)];
+            T k2 = lv.k2.empty() ? T(0.0) : lv.k2[lv.id(a, b)];
             lv.u[lv.id(a, b)] = (nb - h2 * lv.f[lv.id(a, b)]) / (4.0 + h2 * k2);
         }
 }
 
-void smooth(Level& lv, int nu) {
+template <class T>
+void smooth(Level<T>& lv, int nu) {
     for (int s = 0; s < nu; ++s) {
         relax_color(lv, 0);
         relax_color(lv, 1);
@@ -173,44 +257,49 @@ void smooth(Level& lv, int nu) {
 }
 
 /* Residual r = f - A u at the interior nodes (zero on the boundary). */
-void residual(const Level& lv, std::vector<double>& r) {
-    r.assign((lv.N + 1) * (lv.N + 1), 0.0);
+template <class T>
+void residual(const Level<T>& lv, std::vector<T>& r) {
+    r.assign((lv.N + 1) * (lv.N + 1), T(0.0));
     for (int b = 1; b < lv.N; ++b)
         for (int a = 1; a < lv.N; ++a)
             r[lv.id(a, b)] = lv.f[lv.id(a, b)] - apply_at(lv, lv.u.data(), a, b);
 }
 
-double norm2_interior(const Level& lv, const std::vector<double>& v) {
+/* 2-norm over the interior nodes of component c (0: the value). */
+template <class T>
+double norm2_interior(const Level<T>& lv, const std::vector<T>& v, int c = 0) {
     double s = 0.0;
     for (int b = 1; b < lv.N; ++b)
-        for (int a = 1; a < lv.N; ++a) s += v[lv.id(a, b)] * v[lv.id(a, b)];
+        for (int a = 1; a < lv.N; ++a) s += comp(v[lv.id(a, b)], c) * comp(v[lv.id(a, b)], c);
     return std::sqrt(s);
 }
 
 /* Full weighting of a fine-grid node array onto the interior coarse nodes. */
-void full_weighting(const Level& fine, const std::vector<double>& r, Level& coarse,
-                    std::vector<double>& out) {
-    out.assign((coarse.N + 1) * (coarse.N + 1), 0.0);
+template <class T>
+void full_weighting(const Level<T>& fine, const std::vector<T>& r, Level<T>& coarse,
+                    std::vector<T>& out) {
+    out.assign((coarse.N + 1) * (coarse.N + 1), T(0.0));
     for (int J = 1; J < coarse.N; ++J)
         for (int I = 1; I < coarse.N; ++I) {
             int a = 2 * I, b = 2 * J;
-            double s = 4.0 * r[fine.id(a, b)] +
-                       2.0 * (r[fine.id(a - 1, b)] + r[fine.id(a + 1, b)] + r[fine.id(a, b - 1)] +
-                              r[fine.id(a, b + 1)]) +
-                       (r[fine.id(a - 1, b - 1)] + r[fine.id(a + 1, b - 1)] +
-                        r[fine.id(a - 1, b + 1)] + r[fine.id(a + 1, b + 1)]);
+            T s = 4.0 * r[fine.id(a, b)] +
+                  2.0 * (r[fine.id(a - 1, b)] + r[fine.id(a + 1, b)] + r[fine.id(a, b - 1)] +
+                         r[fine.id(a, b + 1)]) +
+                  (r[fine.id(a - 1, b - 1)] + r[fine.id(a + 1, b - 1)] +
+                   r[fine.id(a - 1, b + 1)] + r[fine.id(a + 1, b + 1)]);
             out[coarse.id(I, J)] = s / 16.0;
         }
 }
 
 /* u_fine += bilinear interpolation of u_coarse. */
-void prolong_add(const Level& coarse, Level& fine) {
+template <class T>
+void prolong_add(const Level<T>& coarse, Level<T>& fine) {
     for (int b = 1; b < fine.N; ++b)
         for (int a = 1; a < fine.N; ++a) {
             int I = a / 2, J = b / 2;
             bool ox = a & 1, oy = b & 1;
-            const std::vector<double>& e = coarse.u;
-            double v;
+            const std::vector<T>& e = coarse.u;
+            T v;
             if (!ox && !oy) v = e[coarse.id(I, J)];
             else if (ox && !oy) v = 0.5 * (e[coarse.id(I, J)] + e[coarse.id(I + 1, J)]);
             else if (!ox && oy) v = 0.5 * (e[coarse.id(I, J)] + e[coarse.id(I, J + 1)]);
@@ -221,19 +310,20 @@ void prolong_add(const Level& coarse, Level& fine) {
         }
 }
 
-void vcycle(std::vector<Level>& lv, size_t l, int nu1, int nu2) {
-    Level& L = lv[l];
+template <class T>
+void vcycle(std::vector<Level<T>>& lv, size_t l, int nu1, int nu2) {
+    Level<T>& L = lv[l];
     if (L.N == 2) { /* one interior node, four zero boundary neighbours: exact */
-        double k2 = L.k2.empty() ? 0.0 : L.k2[L.id(1, 1)];
+        T k2 = L.k2.empty() ? T(0.0) : L.k2[L.id(1, 1)];
         L.u[L.id(1, 1)] = -L.f[L.id(1, 1)] / (4.0 / (L.h * L.h) + k2);
         return;
     }
     smooth(L, nu1);
-    std::vector<double> r;
+    std::vector<T> r;
     residual(L, r);
-    Level& C = lv[l + 1];
+    Level<T>& C = lv[l + 1];
     full_weighting(L, r, C, C.f);
-    std::fill(C.u.begin(), C.u.end(), 0.0);
+    std::fill(C.u.begin(), C.u.end(), T(0.0));
     vcycle(lv, l + 1, nu1, nu2);
     prolong_add(C, L);
     smooth(L, nu2);
@@ -241,89 +331,119 @@ void vcycle(std::vector<Level>& lv, size_t l, int nu1, int nu2) {
 
 /* Solve (L_h - k2) u = f for the interior nodes with u = 0 on the boundary,
  * starting from the guess held in u.  Stops when ||r|| <= rtol ||f|| + atol sqrt(n)
- * (n interior nodes), or at the rounding floor: a cycle after the second that
- * reduces ||r|| by less than 2x while ||r|| <= 1e-9 max(||f||, ||r_0||) (the guard
- * keeps a slowly converging solve from being taken for a converged one; r_0 is
- * the initial residual, which sets the scale when f vanishes).  Otherwise
- * returns ORC_NOCONV after max_cycles. */
-int mg_solve(int N, double h, const double* k2, const double* f, double* u, double rtol,
-             double atol, int max_cycles, int nu1, int nu2, int* cycles_out, double* rel_out) {
-    std::vector<Level> lv;
+ * (n interior nodes; ||r_0|| in place of ||f|| when f = 0), or at the rounding
+ * floor: a cycle after the second that reduces ||r|| by less than 2x while
+ * ||r|| <= 1e-9 max(||f||, ||r_0||) (the guard keeps a slowly converging solve
+ * from being taken for a converged one).  Otherwise returns ORC_NOCONV after
+ * max_cycles.  For a Dual scalar every component (value and each derivative)
+ * must meet the rule: the derivative solves converge along with the value. */
+template <class T>
+int mg_solve(int N, double h, const T* k2, const T* f, T* u, double rtol, double atol,
+             int max_cycles, int nu1, int nu2, int* cycles_out, double* rel_out) {
+    std::vector<Level<T>> lv;
     for (int n = N; n >= 2; n /= 2) {
-        Level l;
+        Level<T> l;
         l.N = n;
         l.h = h * (N / n);
-        l.u.assign((n + 1) * (n + 1), 0.0);
-        l.f.assign((n + 1) * (n + 1), 0.0);
+        l.u.assign((n + 1) * (n + 1), T(0.0));
+        l.f.assign((n + 1) * (n + 1), T(0.0));
         lv.push_back(l);
     }
-    Level& top = lv[0];
+    Level<T>& top = lv[0];
     std::copy(f, f + top.u.size(), top.f.begin());
     std::copy(u, u + top.u.size(), top.u.begin());
     for (int b = 0; b <= N; ++b)  /* Dirichlet: boundary values are zero */
         for (int a = 0; a <= N; ++a)
             if (a == 0 || b == 0 || a == N || b == N) {
-                top.u[top.id(a, b)] = 0.0;
-                top.f[top.id(a, b)] = 0.0;
+                top.u[top.id(a, b)] = T(0.0);
+                top.f[top.id(a, b)] = T(0.0);
             }
     if (k2) {  /* coarse k2 by full weighting of the finer level */
         top.k2.assign(k2, k2 + top.u.size());
         for (size_t l = 1; l < lv.size(); ++l) full_weighting(lv[l - 1], lv[l - 1].k2, lv[l], lv[l].k2);
     }
-    std::vector<double> r;
-    const double fnorm = norm2_interior(top, top.f);
+    const int nc = ncomp(T(0.0));
+    std::vector<T> r;
     residual(top, r);
-    double rn = norm2_interior(top, r), rprev = rn;
-    /* relative to ||f||; for f = 0 (solution 0) relative to the initial residual */
-    const double tol = rtol * (fnorm > 0 ? fnorm : rn) + atol * std::sqrt((double)(N - 1) * (N - 1));
-    const double scale = std::max(fnorm, rn);
-    int c = 0, status = ORC_NOCONV;
-    if (rn <= tol) status = ORC_OK;
-    while (status != ORC_OK && c < max_cycles) {
+    std::vector<double> fnorm(nc), rn(nc), rprev(nc), tol(nc), scale(nc);
+    for (int c = 0; c < nc; ++c) {
+        fnorm[c] = norm2_interior(top, top.f, c);
+        rn[c] = rprev[c] = norm2_interior(top, r, c);
+        /* relative to ||f||; for f = 0 (solution 0) relative to the initial residual */
+        tol[c] = rtol * (fnorm[c] > 0 ? fnorm[c] : rn[c]) + atol * std::sqrt((double)(N - 1) * (N - 1));
+        scale[c] = std::max(fnorm[c], rn[c]);
+    }
+    std::vector<bool> done(nc);
+    for (int c = 0; c < nc; ++c) done[c] = rn[c] <= tol[c];
+    auto all_done = [&]() {
+        for (int c = 0; c < nc; ++c)
+            if (!done[c]) return false;
+        return true;
+    };
+    int cyc = 0;
+    while (!all_done() && cyc < max_cycles) {
         vcycle(lv, 0, nu1, nu2);
-        ++c;
+        ++cyc;
         residual(top, r);
-        rprev = rn;
-        rn = norm2_interior(top, r);
-        if (rn <= tol) status = ORC_OK;
-        else if (c >= 2 && rn > 0.5 * rprev && rn <= 1e-9 * scale) status = ORC_OK; /* floor */
+        for (int c = 0; c < nc; ++c) {
+            rprev[c] = rn[c];
+            rn[c] = norm2_interior(top, r, c);
+            if (rn[c] <= tol[c]) done[c] = true;
+            else if (cyc >= 2 && rn[c] > 0.5 * rprev[c] && rn[c] <= 1e-9 * scale[c])
+                done[c] = true; /* floor */
+            else done[c] = false;
+        }
     }
     std::copy(top.u.begin(), top.u.end(), u);
-    if (cycles_out) *cycles_out = c;
-    if (rel_out) *rel_out = fnorm > 0 ? rn / fnorm : rn;
-    return (std::isfinite(rn) ? status : ORC_NOCONV);
+    if (cycles_out) *cycles_out = cyc;
+    if (rel_out) *rel_out = fnorm[0] > 0 ? rn[0] / fnorm[0] : rn[0];
+    bool finite = true;
+    for (int c = 0; c < nc; ++c) finite = finite && std::isfinite(rn[c]);
+    return (finite && all_done()) ? ORC_OK : ORC_NOCONV;
 }
 
 /* --------------------------------------------------------------- drivers -- */
 
 /* Frozen luminal driver density n_b(x, y, xi); zero for xi < 0 (the xi axis
  * starts at 0, Table 1 footnote).  Gaussian: amp exp(-r^2/sr^2 - (xi-xc)^2/sz^2)
- * as in Sec. V.A; radial bins: bin_amp[floor(r/dr)] exp(-(xi-xc)^2/sz^2). */
-double beam_density(const oracle_cfg& c, double x, double y, double xi) {
-    if (xi < 0.0) return 0.0;
-    double s = 0.0;
+ * as in Sec. V.A; radial bins: bin_amp[floor(r/dr)] exp(-(xi-xc)^2/sz^2).
+ * theta (or NULL: the configuration's values) lists the amplitudes beam by
+ * beam: amp (Gaussian) or the bin amplitudes (radial bins). */
+template <class T>
+T beam_density(const oracle_cfg& c, const T* theta, double x, double y, double xi) {
+    if (xi < 0.0) return T(0.0);
+    T s(0.0);
+    int t = 0;
     for (int k = 0; k < c.n_beams; ++k) {
         const oracle_beam& B = c.beams[k];
         double rx = x - B.x0, ry = y - B.y0;
         double r2 = rx * rx + ry * ry;
         double lz = (xi - B.xi_c) * (xi - B.xi_c) / (B.sigma_z * B.sigma_z);
         if (B.kind == 0) {
-            s += B.amp * std::exp(-r2 / (B.sigma_r * B.sigma_r) - lz);
+            const T amp = theta ? theta[t] : T(B.amp);
+            s += amp * std::exp(-r2 / (B.sigma_r * B.sigma_r) - lz);
+            t += 1;
         } else {
             double r = std::sqrt(r2);
             double dr = B.r_max / B.n_bins;
             int k2 = (int)std::floor(r / dr);
-            if (r < B.r_max && k2 < B.n_bins) s += B.bin_amp[k2] * std::exp(-lz);
+            if (r < B.r_max && k2 < B.n_bins) s += (theta ? theta[t + k2] : T(B.bin_amp[k2])) * std::exp(-lz);
+            t += B.n_bins;
         }
     }
     return s;
 }
+double beam_density(const oracle_cfg& c, double x, double y, double xi) {
+    return beam_density<double>(c, nullptr, x, y, xi);
+}
 
 /* ----------------------------------------------------------- slice step -- */
 
-struct Moments { /* node arrays deposited from the particles of one slice */
-    std::vector<double> n, jx, jy, txx, txy, tyy;
+template <class T>
+struct MomentsT { /* node arrays deposited from the particles of one slice */
+    std::vector<T> n, jx, jy, txx, txy, tyy;
 };
+using Moments = MomentsT<double>;
 
 /* Assembly of the B-perp system (Sec. III.B eqs. (18)-(19) with A-hat = 0, i.e.
  * rows 4-5 of eq. (30)):  G = n*<gamma> (eq. (9) and the gamma of Sec. III.A),
@@ -332,41 +452,43 @@ struct Moments { /* node arrays deposited from the particles of one slice */
  *   f_Bx =  S_y,  f_By = -S_x   (from -e_z x S),
  *   S = grad j_z - div T + (e_z x j) Bz/g + G grad psi/g^2 - j Ez/g - T.grad psi/g.
  * Returns ORC_NONPHYS if g <= 0 at a node that holds plasma. */
-int assemble(const Grid& g, const oracle_cfg& c, double xi, const Moments& m,
-             const double* psi, const double* Ez, const double* Bz, std::vector<double>& k2,
-             std::vector<double>& fBx, std::vector<double>& fBy, std::vector<double>* jz_out) {
+template <class T>
+int assemble(const Grid& g, const oracle_cfg& c, double xi, const MomentsT<T>& m,
+             const T* psi, const T* Ez, const T* Bz, std::vector<T>& k2,
+             std::vector<T>& fBx, std::vector<T>& fBy, std::vector<T>* jz_out,
+             const T* theta = nullptr) {
     const int nn = g.nn();
-    std::vector<double> G(nn, 0.0), jz(nn, 0.0);
+    std::vector<T> G(nn, T(0.0)), jz(nn, T(0.0));
     int status = ORC_OK;
     for (int b = 0; b <= g.N; ++b)
         for (int a = 0; a <= g.N; ++a) {
             int i = g.id(a, b);
-            double gg = 1.0 + psi[i];
-            double plasma_jz = 0.0;
-            if (m.n[i] > 0.0) {
-                if (gg <= 0.0) status = ORC_NONPHYS;
+            T gg = 1.0 + psi[i];
+            T plasma_jz(0.0);
+            if (val(m.n[i]) > 0.0) {
+                if (val(gg) <= 0.0) status = ORC_NONPHYS;
                 /* <gamma> = (1 + <p_perp^2> + g^2)/(2g) with <p_perp^2> = g^2 <V^2> */
                 G[i] = (m.n[i] * (1.0 + gg * gg) + gg * gg * (m.txx[i] + m.tyy[i])) / (2.0 * gg);
                 plasma_jz = G[i] / gg - m.n[i];
             }
-            jz[i] = plasma_jz + beam_density(c, g.xa(a), g.xa(b), xi);
+            jz[i] = plasma_jz + beam_density(c, theta, g.xa(a), g.xa(b), xi);
         }
-    k2.assign(nn, 0.0);
-    fBx.assign(nn, 0.0);
-    fBy.assign(nn, 0.0);
+    k2.assign(nn, T(0.0));
+    fBx.assign(nn, T(0.0));
+    fBy.assign(nn, T(0.0));
     for (int b = 1; b < g.N; ++b)
         for (int a = 1; a < g.N; ++a) {
             int i = g.id(a, b);
-            double gg = 1.0 + psi[i];
-            double px = Dx(g, psi, a, b), py = Dy(g, psi, a, b);
+            T gg = 1.0 + psi[i];
+            T px = Dx(g, psi, a, b), py = Dy(g, psi, a, b);
             /* grad j_z - div T, written as the D-terms of rows 4-5 of eq. (30) */
-            double d_jz_tyy = (jz[g.id(a, b + 1)] - m.tyy[g.id(a, b + 1)] -
-                               (jz[g.id(a, b - 1)] - m.tyy[g.id(a, b - 1)])) / (2.0 * g.h);
-            double d_txx_jz = (m.txx[g.id(a + 1, b)] - jz[g.id(a + 1, b)] -
-                               (m.txx[g.id(a - 1, b)] - jz[g.id(a - 1, b)])) / (2.0 * g.h);
-            double fx = d_jz_tyy - Dx(g, m.txy.data(), a, b);
-            double fy = d_txx_jz + Dy(g, m.txy.data(), a, b);
-            if (m.n[i] > 0.0) {
+            T d_jz_tyy = (jz[g.id(a, b + 1)] - m.tyy[g.id(a, b + 1)] -
+                          (jz[g.id(a, b - 1)] - m.tyy[g.id(a, b - 1)])) / (2.0 * g.h);
+            T d_txx_jz = (m.txx[g.id(a + 1, b)] - jz[g.id(a + 1, b)] -
+                          (m.txx[g.id(a - 1, b)] - jz[g.id(a - 1, b)])) / (2.0 * g.h);
+            T fx = d_jz_tyy - Dx(g, m.txy.data(), a, b);
+            T fy = d_txx_jz + Dy(g, m.txy.data(), a, b);
+            if (val(m.n[i]) > 0.0) {
                 k2[i] = m.n[i] / gg;
                 fx += (m.jx[i] * Bz[i] - m.jy[i] * Ez[i]) / gg +
                       (G[i] / (gg * gg) - m.tyy[i] / gg) * py - (m.txy[i] / gg) * px;
@@ -382,9 +504,10 @@ int assemble(const Grid& g, const oracle_cfg& c, double xi, const Moments& m,
 
 /* Node gradient of psi for the particle gather: central at interior nodes,
  * one-sided on the boundary rows/columns. */
-void psi_gradient(const Grid& g, const double* psi, std::vector<double>& gx, std::vector<double>& gy) {
-    gx.assign(g.nn(), 0.0);
-    gy.assign(g.nn(), 0.0);
+template <class T>
+void psi_gradient(const Grid& g, const T* psi, std::vector<T>& gx, std::vector<T>& gy) {
+    gx.assign(g.nn(), T(0.0));
+    gy.assign(g.nn(), T(0.0));
     for (int b = 0; b <= g.N; ++b)
         for (int a = 0; a <= g.N; ++a) {
             int i = g.id(a, b);
@@ -404,27 +527,28 @@ void psi_gradient(const Grid& g, const double* psi, std::vector<double>& gx, std
  * Half kick with F = gamma grad psi/g + e_z x B_perp, rotation by the
  * (e_z x V) Bz term (angle 2 atan(Bz dxi / 2g)), half kick, drift with the
  * new momentum, specular reflection at the walls x, y = +-L. */
-void push_one(double L, double dxi, double g_i, double gx, double gy, double Bx, double By,
-              double Bz, double& x, double& y, double& px, double& py) {
-    double gamma = (1.0 + px * px + py * py + g_i * g_i) / (2.0 * g_i);
-    double Fx = gamma * gx / g_i - By;
-    double Fy = gamma * gy / g_i + Bx;
-    double mx = px + 0.5 * dxi * Fx;
-    double my = py + 0.5 * dxi * Fy;
-    double t = Bz * dxi / (2.0 * g_i);
-    double s = 2.0 * t / (1.0 + t * t);
-    double qx = mx - t * my;
-    double qy = my + t * mx;
-    double rx = mx - s * qy;
-    double ry = my + s * qx;
+template <class T>
+void push_one(double L, double dxi, const T& g_i, const T& gx, const T& gy, const T& Bx,
+              const T& By, const T& Bz, T& x, T& y, T& px, T& py) {
+    T gamma = (1.0 + px * px + py * py + g_i * g_i) / (2.0 * g_i);
+    T Fx = gamma * gx / g_i - By;
+    T Fy = gamma * gy / g_i + Bx;
+    T mx = px + 0.5 * dxi * Fx;
+    T my = py + 0.5 * dxi * Fy;
+    T t = Bz * dxi / (2.0 * g_i);
+    T s = 2.0 * t / (1.0 + t * t);
+    T qx = mx - t * my;
+    T qy = my + t * mx;
+    T rx = mx - s * qy;
+    T ry = my + s * qx;
     px = rx + 0.5 * dxi * Fx;
     py = ry + 0.5 * dxi * Fy;
     x = x + dxi * px / g_i;
     y = y + dxi * py / g_i;
-    if (x > L) { x = 2.0 * L - x; px = -px; }
-    if (x < -L) { x = -2.0 * L - x; px = -px; }
-    if (y > L) { y = 2.0 * L - y; py = -py; }
-    if (y < -L) { y = -2.0 * L - y; py = -py; }
+    if (val(x) > L) { x = 2.0 * L - x; px = -px; }
+    if (val(x) < -L) { x = -2.0 * L - x; px = -px; }
+    if (val(y) > L) { y = 2.0 * L - y; py = -py; }
+    if (val(y) < -L) { y = -2.0 * L - y; py = -py; }
 }
 
 /* Step_Size_Refinement of Algorithm 1: V0 = dx/dxi0; dxi = dxi0 V0/Vmax if
@@ -438,6 +562,136 @@ double next_dxi(const oracle_cfg& c, double h, double vmax) {
     if (c.refine_k > 0 && d < c.dxi0 / c.refine_k) d = c.dxi0 / c.refine_k;
     return d;
 }
+
+
+/* One xi-slice (Algorithm 1 inner loop: Collect_Source, Solve_Wakefield,
+ * Push_Trajectory, Step_Size_Refinement).
+ *   in:  particles (x, y, px, py) at xi, fields[5][nn] = previous slice's fields
+ *        (multigrid initial guesses), *xi, *dxi (the step to take now);
+ *   out: fields at xi, particles at xi + dxi, *xi += dxi, *dxi = next step.
+ * moments_out ([6][nn], may be NULL) receives n*, jx, jy, Txx, Txy, Tyy and
+ * extra_out ([4][nn], may be NULL) receives k2, f_Bx, f_By, j_z.
+ * pz (may be NULL) carries p_z for the dynamic check of gamma - p_z = 1 + psi. */
+template <class T>
+int slice_step_t(const oracle_cfg* c, int P, T* x, T* y, T* px, T* py, T* pz, T* fields,
+                 double* xi, double* dxi, oracle_info* info, T* moments_out, T* extra_out,
+                 const T* theta) {
+    Grid g(c->n_cells, c->half_width);
+    const int nn = g.nn();
+    T* psi = fields;
+    T* Ez = fields + nn;
+    T* Bz = fields + 2 * nn;
+    T* Bx = fields + 3 * nn;
+    T* By = fields + 4 * nn;
+    oracle_info inf;
+    std::memset(&inf, 0, sizeof(inf));
+    inf.xi = *xi;
+    inf.dxi = *dxi;
+    int status = ORC_OK;
+    auto solve = [&](int k, const std::vector<T>* k2, const std::vector<T>& f, T* u) {
+        int st = mg_solve<T>(g.N, g.h, k2 ? k2->data() : nullptr, f.data(), u, c->mg_rtol, c->mg_atol,
+                          c->mg_max_cycles, c->nu_pre, c->nu_post, &inf.cycles[k], &inf.rel_resid[k]);
+        if (st != ORC_OK && status == ORC_OK) status = st;
+    };
+
+    /* 1. surface density n* (Collect_Source). */
+    MomentsT<T> m;
+    m.n.assign(nn, T(0.0));
+    deposit<T>(g, *c, P, x, y, nullptr, m.n.data());
+
+    /* 2. psi: L_h psi = n* - n0 (Sec. III.B eq. (12)). */
+    std::vector<T> f(nn, T(0.0));
+    for (int i = 0; i < nn; ++i) f[i] = m.n[i] - c->n0;
+    solve(0, nullptr, f, psi);
+
+    /* 3. per-particle g_i = 1 + psi(r_i) and V_i = p_i/g_i (eq. (6)); currents
+     *    j = n*<V> (eq. (9)) and pressure tensor T = n*<V V> (below eq. (16)). */
+    std::vector<T> gi(P), vx(P), vy(P), vxx(P), vxy(P), vyy(P);
+    double inv_err = 0.0;
+    for (int i = 0; i < P; ++i) {
+        gi[i] = 1.0 + gather1(g, psi, x[i], y[i]);
+        if (!(val(gi[i]) > 0.0)) status = ORC_NONPHYS;
+        vx[i] = px[i] / gi[i];
+        vy[i] = py[i] / gi[i];
+        vxx[i] = vx[i] * vx[i];
+        vxy[i] = vx[i] * vy[i];
+        vyy[i] = vy[i] * vy[i];
+        if (pz) {
+            T gam = (1.0 + px[i] * px[i] + py[i] * py[i] + gi[i] * gi[i]) / (2.0 * gi[i]);
+            inv_err = std::max(inv_err, std::fabs(val(gam - pz[i] - gi[i])));
+        }
+    }
+    inf.invariant_err = inv_err;
+    m.jx.assign(nn, T(0.0));
+    m.jy.assign(nn, T(0.0));
+    m.txx.assign(nn, T(0.0));
+    m.txy.assign(nn, T(0.0));
+    m.tyy.assign(nn, T(0.0));
+    deposit<T>(g, *c, P, x, y, vx.data(), m.jx.data());
+    deposit<T>(g, *c, P, x, y, vy.data(), m.jy.data());
+    deposit<T>(g, *c, P, x, y, vxx.data(), m.txx.data());
+    deposit<T>(g, *c, P, x, y, vxy.data(), m.txy.data());
+    deposit<T>(g, *c, P, x, y, vyy.data(), m.tyy.data());
+
+    /* 4. Ez and Bz: L_h Ez = -div j (eq. (13)), L_h Bz = e_z.(curl j) (eq. (14)). */
+    std::vector<T> fE(nn, T(0.0)), fB(nn, T(0.0));
+    for (int b = 1; b < g.N; ++b)
+        for (int a = 1; a < g.N; ++a) {
+            int i = g.id(a, b);
+            fE[i] = -(Dx(g, m.jx.data(), a, b) + Dy(g, m.jy.data(), a, b));
+            fB[i] = Dx(g, m.jy.data(), a, b) - Dy(g, m.jx.data(), a, b);
+        }
+    solve(1, nullptr, fE, Ez);
+    solve(2, nullptr, fB, Bz);
+
+    /* 5-6. B_perp: (L_h - n* / g) B_perp = -e_z x S (eqs. (18)-(19)). */
+    std::vector<T> k2, fBx, fBy, jz;
+    int st = assemble<T>(g, *c, *xi, m, psi, Ez, Bz, k2, fBx, fBy, &jz, theta);
+    if (st != ORC_OK && status == ORC_OK) status = st;
+    solve(3, &k2, fBx, Bx);
+    solve(4, &k2, fBy, By);
+
+    if (moments_out) {
+        const std::vector<T>* arr[6] = {&m.n, &m.jx, &m.jy, &m.txx, &m.txy, &m.tyy};
+        for (int k = 0; k < 6; ++k) std::copy(arr[k]->begin(), arr[k]->end(), moments_out + k * nn);
+    }
+    if (extra_out) {
+        const std::vector<T>* arr[4] = {&k2, &fBx, &fBy, &jz};
+        for (int k = 0; k < 4; ++k) std::copy(arr[k]->begin(), arr[k]->end(), extra_out + k * nn);
+    }
+
+    /* 7-8. gather grad psi, B and push (Push_Trajectory), Vmax after the push. */
+    std::vector<T> gx, gy;
+    psi_gradient<T>(g, psi, gx, gy);
+    double vmax = 0.0;
+    for (int i = 0; i < P; ++i) {
+        T Gx = gather1(g, gx.data(), x[i], y[i]);
+        T Gy = gather1(g, gy.data(), x[i], y[i]);
+        T bx = gather1(g, Bx, x[i], y[i]);
+        T by = gather1(g, By, x[i], y[i]);
+        T bz = gather1(g, Bz, x[i], y[i]);
+        T ez = pz ? gather1(g, Ez, x[i], y[i]) : T(0.0);
+        T p0x = px[i], p0y = py[i];
+        push_one(g.L, *dxi, gi[i], Gx, Gy, bx, by, bz, x[i], y[i], px[i], py[i]);
+        if (pz) { /* dp_z/dxi = -gamma Ez/g - Vx By + Vy Bx at the mean momentum */
+            T mx = 0.5 * (p0x + px[i]), my = 0.5 * (p0y + py[i]);
+            T gam = (1.0 + mx * mx + my * my + gi[i] * gi[i]) / (2.0 * gi[i]);
+            pz[i] += *dxi * (-gam * ez / gi[i] - (mx / gi[i]) * by + (my / gi[i]) * bx);
+        }
+        double v = val(sqrt(px[i] * px[i] + py[i] * py[i]) / gi[i]);
+        if (v > vmax) vmax = v;
+    }
+
+    /* 9. Step_Size_Refinement for the next slice. */
+    inf.vmax = vmax;
+    inf.dxi_next = next_dxi(*c, g.h, vmax);
+    *xi = *xi + *dxi;
+    *dxi = inf.dxi_next;
+    inf.status = status;
+    if (info) *info = inf;
+    return status;
+}
+
 
 } /* namespace */
 
@@ -460,7 +714,7 @@ int oracle_gather(const oracle_cfg* c, int P, const double* x, const double* y,
 
 /* out = L_h u - k2 u at interior nodes, 0 on the boundary (k2 may be NULL). */
 int oracle_apply(int N, double h, const double* k2, const double* u, double* out) {
-    Level lv;
+    Level<double> lv;
     lv.N = N;
     lv.h = h;
     if (k2) lv.k2.assign(k2, k2 + (N + 1) * (N + 1));
@@ -517,130 +771,105 @@ int oracle_assemble(const oracle_cfg* c, double xi, const double* mom, const dou
     return st;
 }
 
-/* One xi-slice (Algorithm 1 inner loop: Collect_Source, Solve_Wakefield,
- * Push_Trajectory, Step_Size_Refinement).
- *   in:  particles (x, y, px, py) at xi, fields[5][nn] = previous slice's fields
- *        (multigrid initial guesses), *xi, *dxi (the step to take now);
- *   out: fields at xi, particles at xi + dxi, *xi += dxi, *dxi = next step.
- * moments_out ([6][nn], may be NULL) receives n*, jx, jy, Txx, Txy, Tyy and
- * extra_out ([4][nn], may be NULL) receives k2, f_Bx, f_By, j_z.
- * pz (may be NULL) carries p_z for the dynamic check of gamma - p_z = 1 + psi. */
 int oracle_slice_step(const oracle_cfg* c, int P, double* x, double* y, double* px, double* py,
                       double* pz, double* fields, double* xi, double* dxi, oracle_info* info,
                       double* moments_out, double* extra_out) {
+    return slice_step_t<double>(c, P, x, y, px, py, pz, fields, xi, dxi, info, moments_out,
+                                extra_out, nullptr);
+}
+
+/* Tangent-linear model (forward mode) of n_slices slices with up to 8
+ * directions at once: the slice step above instantiated with Dual numbers.
+ * Seeds (each may be NULL = 0): dP [K][4][P] tangents of the input particles
+ * (x, y, px, py), dtheta [K][n_theta] tangents of the driver parameters (beam
+ * by beam: amp, or the bin amplitudes).  The fields given are the multigrid
+ * initial guesses only and carry no tangent.  The dxi sequence is that of the
+ * forward run (held, not differentiated).  Outputs (each may be NULL):
+ * dout [K][4][P] tangents of the final particles, dF [K][5][nn] tangents of the
+ * last slice's fields, loss / dloss[K] the probe loss of oracle_run_loss and
+ * its tangents.  The values (particles, fields, xi, dxi) advance exactly as in
+ * oracle_run. */
+int oracle_run_tangent(const oracle_cfg* c, int P, double* x, double* y, double* px, double* py,
+                       double* fields, double* xi, double* dxi, int n_slices, int K,
+                       const double* dP, const double* dtheta, int n_probes, const double* probes,
+                       const double* weights, double* loss, double* dloss, double* dout,
+                       double* dF) {
+    constexpr int KD = 8;
+    using D = Dual<KD>;
+    if (K < 1 || K > KD || P < 0) return ORC_INVALID;
     Grid g(c->n_cells, c->half_width);
     const int nn = g.nn();
-    double* psi = fields;
-    double* Ez = fields + nn;
-    double* Bz = fields + 2 * nn;
-    double* Bx = fields + 3 * nn;
-    double* By = fields + 4 * nn;
-    oracle_info inf;
-    std::memset(&inf, 0, sizeof(inf));
-    inf.xi = *xi;
-    inf.dxi = *dxi;
+    int nth = 0;
+    for (int k = 0; k < c->n_beams; ++k) nth += c->beams[k].kind == 0 ? 1 : c->beams[k].n_bins;
+    std::vector<D> X(P), Y(P), PX(P), PY(P), F(5 * (size_t)nn), TH(nth);
+    for (int i = 0; i < P; ++i) {
+        X[i] = D(x[i]);
+        Y[i] = D(y[i]);
+        PX[i] = D(px[i]);
+        PY[i] = D(py[i]);
+        if (dP)
+            for (int k = 0; k < K; ++k) {
+                const double* s = dP + (size_t)k * 4 * P;
+                X[i].d[k] = s[i];
+                Y[i].d[k] = s[P + i];
+                PX[i].d[k] = s[2 * P + i];
+                PY[i].d[k] = s[3 * P + i];
+            }
+    }
+    for (size_t i = 0; i < F.size(); ++i) F[i] = D(fields[i]);
+    int t = 0;
+    for (int k = 0; k < c->n_beams; ++k) {
+        const oracle_beam& B = c->beams[k];
+        if (B.kind == 0) TH[t++] = D(B.amp);
+        else
+            for (int m = 0; m < B.n_bins; ++m) TH[t++] = D(B.bin_amp[m]);
+    }
+    if (dtheta)
+        for (int k = 0; k < K; ++k)
+            for (int q = 0; q < nth; ++q) TH[q].d[k] = dtheta[(size_t)k * nth + q];
+    D Ls(0.0);
     int status = ORC_OK;
-    auto solve = [&](int k, const std::vector<double>* k2, const std::vector<double>& f, double* u) {
-        int st = mg_solve(g.N, g.h, k2 ? k2->data() : nullptr, f.data(), u, c->mg_rtol, c->mg_atol,
-                          c->mg_max_cycles, c->nu_pre, c->nu_post, &inf.cycles[k], &inf.rel_resid[k]);
-        if (st != ORC_OK && status == ORC_OK) status = st;
-    };
-
-    /* 1. surface density n* (Collect_Source). */
-    Moments m;
-    m.n.assign(nn, 0.0);
-    deposit(g, *c, P, x, y, nullptr, m.n.data());
-
-    /* 2. psi: L_h psi = n* - n0 (Sec. III.B eq. (12)). */
-    std::vector<double> f(nn, 0.0);
-    for (int i = 0; i < nn; ++i) f[i] = m.n[i] - c->n0;
-    solve(0, nullptr, f, psi);
-
-    /* 3. per-particle g_i = 1 + psi(r_i) and V_i = p_i/g_i (eq. (6)); currents
-     *    j = n*<V> (eq. (9)) and pressure tensor T = n*<V V> (below eq. (16)). */
-    std::vector<double> gi(P), vx(P), vy(P), vxx(P), vxy(P), vyy(P);
-    double inv_err = 0.0;
+    std::vector<int> nodes;
+    for (int j = 0; j < n_slices; ++j) {
+        oracle_info inf;
+        int st = slice_step_t<D>(c, P, X.data(), Y.data(), PX.data(), PY.data(), nullptr,
+                                 F.data(), xi, dxi, &inf, nullptr, nullptr, TH.data());
+        if (st != ORC_OK) status = st;
+        for (int k = 0; k < n_probes; ++k) {
+            const double* p = probes + 6 * k;
+            if (j < (int)p[1] || j >= (int)p[2]) continue;
+            nodes.clear();
+            for (int b = 0; b <= g.N; ++b)
+                for (int a = 0; a <= g.N; ++a) {
+                    double rx = g.xa(a) - p[4], ry = g.xa(b) - p[5];
+                    if (rx * rx + ry * ry <= p[3] * p[3]) nodes.push_back(g.id(a, b));
+                }
+            D sum(0.0);
+            for (int i : nodes) sum += F[(int)p[0] * nn + i];
+            if (!nodes.empty()) Ls += weights[k] * sum / (double)nodes.size() / (p[2] - p[1]);
+        }
+    }
     for (int i = 0; i < P; ++i) {
-        gi[i] = 1.0 + gather1(g, psi, x[i], y[i]);
-        if (!(gi[i] > 0.0)) status = ORC_NONPHYS;
-        vx[i] = px[i] / gi[i];
-        vy[i] = py[i] / gi[i];
-        vxx[i] = vx[i] * vx[i];
-        vxy[i] = vx[i] * vy[i];
-        vyy[i] = vy[i] * vy[i];
-        if (pz) {
-            double gam = (1.0 + px[i] * px[i] + py[i] * py[i] + gi[i] * gi[i]) / (2.0 * gi[i]);
-            inv_err = std::max(inv_err, std::fabs(gam - pz[i] - gi[i]));
-        }
+        x[i] = X[i].v;
+        y[i] = Y[i].v;
+        px[i] = PX[i].v;
+        py[i] = PY[i].v;
     }
-    inf.invariant_err = inv_err;
-    m.jx.assign(nn, 0.0);
-    m.jy.assign(nn, 0.0);
-    m.txx.assign(nn, 0.0);
-    m.txy.assign(nn, 0.0);
-    m.tyy.assign(nn, 0.0);
-    deposit(g, *c, P, x, y, vx.data(), m.jx.data());
-    deposit(g, *c, P, x, y, vy.data(), m.jy.data());
-    deposit(g, *c, P, x, y, vxx.data(), m.txx.data());
-    deposit(g, *c, P, x, y, vxy.data(), m.txy.data());
-    deposit(g, *c, P, x, y, vyy.data(), m.tyy.data());
-
-    /* 4. Ez and Bz: L_h Ez = -div j (eq. (13)), L_h Bz = e_z.(curl j) (eq. (14)). */
-    std::vector<double> fE(nn, 0.0), fB(nn, 0.0);
-    for (int b = 1; b < g.N; ++b)
-        for (int a = 1; a < g.N; ++a) {
-            int i = g.id(a, b);
-            fE[i] = -(Dx(g, m.jx.data(), a, b) + Dy(g, m.jy.data(), a, b));
-            fB[i] = Dx(g, m.jy.data(), a, b) - Dy(g, m.jx.data(), a, b);
-        }
-    solve(1, nullptr, fE, Ez);
-    solve(2, nullptr, fB, Bz);
-
-    /* 5-6. B_perp: (L_h - n* / g) B_perp = -e_z x S (eqs. (18)-(19)). */
-    std::vector<double> k2, fBx, fBy, jz;
-    int st = assemble(g, *c, *xi, m, psi, Ez, Bz, k2, fBx, fBy, &jz);
-    if (st != ORC_OK && status == ORC_OK) status = st;
-    solve(3, &k2, fBx, Bx);
-    solve(4, &k2, fBy, By);
-
-    if (moments_out) {
-        const std::vector<double>* arr[6] = {&m.n, &m.jx, &m.jy, &m.txx, &m.txy, &m.tyy};
-        for (int k = 0; k < 6; ++k) std::copy(arr[k]->begin(), arr[k]->end(), moments_out + k * nn);
+    for (size_t i = 0; i < F.size(); ++i) fields[i] = F[i].v;
+    if (loss) *loss = Ls.v;
+    for (int k = 0; k < K; ++k) {
+        if (dloss) dloss[k] = Ls.d[k];
+        if (dout)
+            for (int i = 0; i < P; ++i) {
+                double* o = dout + (size_t)k * 4 * P;
+                o[i] = X[i].d[k];
+                o[P + i] = Y[i].d[k];
+                o[2 * P + i] = PX[i].d[k];
+                o[3 * P + i] = PY[i].d[k];
+            }
+        if (dF)
+            for (size_t i = 0; i < F.size(); ++i) dF[(size_t)k * F.size() + i] = F[i].d[k];
     }
-    if (extra_out) {
-        const std::vector<double>* arr[4] = {&k2, &fBx, &fBy, &jz};
-        for (int k = 0; k < 4; ++k) std::copy(arr[k]->begin(), arr[k]->end(), extra_out + k * nn);
-    }
-
-    /* 7-8. gather grad psi, B and push (Push_Trajectory), Vmax after the push. */
-    std::vector<double> gx, gy;
-    psi_gradient(g, psi, gx, gy);
-    double vmax = 0.0;
-    for (int i = 0; i < P; ++i) {
-        double Gx = gather1(g, gx.data(), x[i], y[i]);
-        double Gy = gather1(g, gy.data(), x[i], y[i]);
-        double bx = gather1(g, Bx, x[i], y[i]);
-        double by = gather1(g, By, x[i], y[i]);
-        double bz = gather1(g, Bz, x[i], y[i]);
-        double ez = pz ? gather1(g, Ez, x[i], y[i]) : 0.0;
-        double p0x = px[i], p0y = py[i];
-        push_one(g.L, *dxi, gi[i], Gx, Gy, bx, by, bz, x[i], y[i], px[i], py[i]);
-        if (pz) { /* dp_z/dxi = -gamma Ez/g - Vx By + Vy Bx at the mean momentum */
-            double mx = 0.5 * (p0x + px[i]), my = 0.5 * (p0y + py[i]);
-            double gam = (1.0 + mx * mx + my * my + gi[i] * gi[i]) / (2.0 * gi[i]);
-            pz[i] += *dxi * (-gam * ez / gi[i] - (mx / gi[i]) * by + (my / gi[i]) * bx);
-        }
-        double v = std::sqrt(px[i] * px[i] + py[i] * py[i]) / gi[i];
-        if (v > vmax) vmax = v;
-    }
-
-    /* 9. Step_Size_Refinement for the next slice. */
-    inf.vmax = vmax;
-    inf.dxi_next = next_dxi(*c, g.h, vmax);
-    *xi = *xi + *dxi;
-    *dxi = inf.dxi_next;
-    inf.status = status;
-    if (info) *info = inf;
     return status;
 }
 
@@ -797,7 +1026,7 @@ int oracle_slice_adjoint(const oracle_cfg* c, int P, const double* x, const doub
     std::vector<double> gi(P), vx(P), vy(P);
     Moments m;
     m.n.assign(nn, 0.0);
-    deposit(g, *c, P, x, y, nullptr, m.n.data());
+    deposit<double>(g, *c, P, x, y, nullptr, m.n.data());
     for (int i = 0; i < P; ++i) {
         W[i] = cicw(g, x[i], y[i]);
         gi[i] = 1.0 + gather1(g, psi, x[i], y[i]);

@@ -211,3 +211,18 @@ def test_c4_full_gradient_matches_finite_differences(torch_cuda):
         ad = float(g @ d)
         print(f"C4 directional derivative: adjoint {ad:.10e} FD {fd:.10e}")
         assert abs(ad - fd) <= 1e-5 * np.abs(g * d).sum()
+
+
+def test_run_gradient_matches_tangent_linear(torch_cuda, oracle_mod):
+    """The GPU reverse sweep's dL/dtheta against the oracle's forward-mode
+    (dual-number) tangent-linear run along the 8 unit directions."""
+    cfg = _c4_small(checkpoint_every=16)
+    st, _, g_tlm, _, _ = oracle_mod.Oracle(cfg).run_tangent(oracle_mod.initial_state(cfg), 40,
+                                                            dtheta=np.eye(8))
+    assert st == 0
+    sim = _sim(cfg, 40)
+    sim.run(40, probes=True)
+    th, _ = sim.backward(dL_dprobe=[1.0])
+    print("GPU adjoint vs tangent-linear:", _rel(th, g_tlm))
+    assert _rel(th, g_tlm) <= ADJ_TOL
+    sim.close()
