@@ -29,6 +29,9 @@ namespace {
 #ifndef WQ_COARSE_THREADS
 #define WQ_COARSE_THREADS 1024
 #endif
+#ifndef WQ_COARSE_CYCLES
+#define WQ_COARSE_CYCLES 1
+#endif
 #ifndef WQ_COARSE_F32
 #define WQ_COARSE_F32 1
 #endif
@@ -40,9 +43,14 @@ constexpr int kCoarseThreads = WQ_COARSE_THREADS;
 // Tile kernels: 32 x 32 owned nodes with 512 threads, or 16 x 16 with 256
 // threads on the levels N <= WQ_SMALL_TILE_MAX (more workgroups and a shorter
 // chain of dependent LDS phases per workgroup where the grid is small).
+// 64 x 64 with 1024 threads on the levels N >= WQ_BIG_TILE_MIN (the finest
+// level of the large grids: a quarter of the halo re-reads of 32 x 32 tiles).
+#ifndef WQ_BIG_TILE_MIN
+#define WQ_BIG_TILE_MIN 1024
+#endif
 template <int T>
-constexpr int tile_threads() { return T >= 32 ? 512 : 256; }
-int tile_for(int N) { return N <= WQ_SMALL_TILE_MAX ? 16 : 32; }
+constexpr int tile_threads() { return T >= 64 ? 1024 : (T >= 32 ? 512 : 256); }
+int tile_for(int N) { return N <= WQ_SMALL_TILE_MAX ? 16 : (N >= (WQ_BIG_TILE_MIN) ? 64 : 32); }
 
 // Deterministic block sum of NV values; the result is valid in thread 0.
 template <int NV, int NT>
@@ -728,12 +736,14 @@ void launch_up_t(const UpArgs<E>& a, int nu, dim3 grid, hipStream_t s, const Pro
 template <typename E, int R, bool HELM>
 void launch_down(const DownArgs<E>& a, int nu, dim3 grid, hipStream_t s, const ProfScope& ps, int T) {
     if (T == 16) launch_down_t<E, R, HELM, 16>(a, nu, grid, s, ps);
+    else if (T == 64) launch_down_t<E, R, HELM, 64>(a, nu, grid, s, ps);
     else launch_down_t<E, R, HELM, 32>(a, nu, grid, s, ps);
 }
 
 template <typename E, int R, bool HELM>
 void launch_up(const UpArgs<E>& a, int nu, dim3 grid, hipStream_t s, const ProfScope& ps, int T) {
     if (T == 16) launch_up_t<E, R, HELM, 16>(a, nu, grid, s, ps);
+    else if (T == 64) launch_up_t<E, R, HELM, 64>(a, nu, grid, s, ps);
     else launch_up_t<E, R, HELM, 32>(a, nu, grid, s, ps);
 }
 
@@ -823,7 +833,7 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
             a.u_out[r] = U(lc, r);
         }
         a.k2lev = helm ? c->k2lev : nullptr;
-        a.ncycles = 1;
+        a.ncycles = WQ_COARSE_CYCLES;
         a.nu1 = c->cfg.nu_pre;
         a.nu2 = c->cfg.nu_post;
         const double nodes = (double)(L.N + 1) * (L.N + 1);
