@@ -134,7 +134,10 @@ wandqs_status wandqs_workspace_bytes(const wandqs_config* cfg, int32_t n_slices,
  * at least wandqs_workspace_bytes), build the cold plasma at rest on the lattice
  * (Sec. III.A: H = 1, P = 0 before the driver), zero the fields, xi = 0,
  * dxi = dxi0.  hip_stream is a hipStream_t (NULL: the null stream).  Synchronises
- * the stream once.  *out is NULL on error. */
+ * the stream once.  *out is NULL on error.  Diagnostic: with the environment
+ * variable WANDQS_MG_TILES=lds at init, every multigrid level runs the LDS tile
+ * kernels instead of the register tiles of the large levels (same results,
+ * bit for bit). */
 wandqs_status wandqs_init(const wandqs_config* cfg, int32_t n_slices, void* d_workspace,
                           size_t bytes, void* hip_stream, wandqs_ctx** out);
 

@@ -3,7 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 #include <new>
@@ -97,6 +99,10 @@ void set_sizes(wandqs_ctx* c, const wandqs_config* cfg, int32_t n_slices) {
     // lc: first level with N <= kCoarseMax
     c->lc = 0;
     while (c->lev[c->lc].N > wq::kCoarseMax) ++c->lc;
+    {
+        const char* e = std::getenv("WANDQS_MG_TILES");
+        c->reg_tile_min = (e && std::strcmp(e, "lds") == 0) ? INT_MAX : wq::reg_tile_min_default();
+    }
     const int t = (c->N + 15) / 16;  // norm partials: one per tile of the smallest tile size
     c->max_tiles = t * t;
     c->n_push_blocks = (int)((c->P + 255) / 256);

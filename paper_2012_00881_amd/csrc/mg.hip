@@ -82,6 +82,11 @@ __device__ void block_sum(double (&v)[NV], double* red) {
 // Gauss-Seidel diagonal D = 4 + h^2 k2 (and 1/D) in registers.  In a pair the
 // two nodes have opposite colours, so every thread updates exactly one node of
 // each of its pairs in every half sweep.
+// Fused multiply-add, written out so that every tile kernel rounds the same
+// way whatever the compiler shares between sweeps.
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // Value select (not an address select, so register arrays stay in registers).
 template <typename T>
 __device__ __forceinline__ T pick(int j, T a, T b) { return j ? b : a; }
@@ -120,7 +125,7 @@ __device__ __forceinline__ void tile_load(E (*su)[EX * EY], E (&fr)[R][KP][2], E
                 if (p < NP) su[r][ly * EX + lx] = uv;
                 fr[r][k][j] = in ? f[r][g] : E(0);
             }
-            const double D = 4.0 + h2 * ((HELM && in) ? k2[g] : 0.0);
+            const double D = fmad(h2, (HELM && in) ? k2[g] : 0.0, 4.0);
             Dr[k][j] = (E)D;
             iDr[k][j] = HELM ? (E)(1.0 / D) : E(0.25);
         }
@@ -151,7 +156,7 @@ __device__ __forceinline__ void tile_sweep(E (*su)[EX * EY], const E (&fr)[R][KP
             for (int r = 0; r < R; ++r) {
                 const E fv = pick(j, fr[r][k][0], fr[r][k][1]);
                 const E nb = su[r][l - 1] + su[r][l + 1] + su[r][l - EX] + su[r][l + EX];
-                su[r][l] = (nb - h2 * fv) * id;
+                su[r][l] = fmad(-h2, fv, nb) * id;
             }
         }
     }
@@ -203,7 +208,7 @@ __global__ __launch_bounds__(tile_threads<T>()) void k_mg_down(DownArgs<E> a) {
         const E nb = su[r][l - 1] + su[r][l + 1] + su[r][l - EX] + su[r][l + EX];
         const E D = pick(j, Dr[k][0], Dr[k][1]);
         const E fv = pick(j, fr[r][k][0], fr[r][k][1]);
-        return fv - (nb - D * u0) * ih2;
+        return fmad(-fmad(-D, u0, nb), ih2, fv);
     };
 
     if (a.norm_part) {  // residual of the incoming iterate on the owned interior nodes
@@ -394,6 +399,395 @@ __global__ __launch_bounds__(tile_threads<T>()) void k_mg_up(UpArgs<E> a) {
                 for (int r = 0; r < R; ++r)
                     a.u_out[r][(size_t)gy * a.pitch + gx] = su[r][ly * EX + lx];
         }
+    }
+}
+
+// ------------------------------------------------------- register tiles --
+//
+// Tile kernels for the large levels with the iterate held in registers.  A
+// workgroup of NW wavefronts holds a 128-column x 4 NW-row block of nodes
+// whose node (0, 0) is global node (ex0, ey0), both even: lane l of wavefront
+// w holds the node pair (2l, 2l + 1) of the rows 4w .. 4w + 3.  The colour of
+// element j of row k is (j + k) % 2, so in a half sweep every lane updates one
+// node per row, with no divergence.  Horizontal neighbours come from the next
+// lane by DPP wave shifts, vertical ones from the lane's own rows; the rows at
+// wavefront boundaries go through LDS once per half sweep.  The arithmetic and
+// its order are those of the LDS tile kernels above: both give the same bits.
+constexpr int kRegRows = 4;  // rows per wavefront (even)
+#ifndef WQ_REG_WAVES
+#define WQ_REG_WAVES 8
+#endif
+#ifndef WQ_REG_TILE_MIN
+#define WQ_REG_TILE_MIN 1024
+#endif
+constexpr int kRegWaves = WQ_REG_WAVES;
+static_assert(kRegWaves * kRegRows >= 32, "register tiles need at least 32 rows");
+
+// DPP wave shifts by one lane: lane i reads lane i - 1 (wave_shr:1) or lane
+// i + 1 (wave_shl:1); the lane past the end of the wavefront reads 0.
+constexpr int kFromLeft = 0x138, kFromRight = 0x130;
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, true);
+    const unsigned hi =
+        (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+template <typename E> struct Pair2;
+template <> struct Pair2<double> { using T = double2; };
+template <> struct Pair2<float> { using T = float2; };
+
+// Geometry of a register tile with halo HL: owned TX x TY nodes.
+template <int HL, int NW>
+struct RegShape {
+    static constexpr int ROWS = kRegRows * NW;
+    static constexpr int TX = 128 - 2 * HL, TY = ROWS - 2 * HL;
+    static_assert(TY > 0 && HL % 2 == 0, "register tile shape");
+};
+
+// Loads the lane's pairs of u (nullptr: 0), f and the Gauss-Seidel diagonal:
+// D = 4 + h^2 k2 and 1/D formed in double, rounded to E.  Nodes outside
+// [0, N]^2 read 0 (D = 4).
+template <typename E, int R, bool HELM, int K>
+__device__ __forceinline__ void reg_load(E (&u)[R][K][2], E (&f)[R][K][2], E (&D)[K][2],
+                                         E (&iD)[K][2], const E* const* uin, const E* const* fin,
+                                         const double* k2, int pitch, int gx, int gy0, int N,
+                                         double h2) {
+    using V2 = typename Pair2<E>::T;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int gy = gy0 + k;
+        const bool in = gy >= 0 && gy <= N && gx >= 0 && gx <= N;
+        const bool in1 = in && gx + 1 <= N;  // gx + 1 <= pitch - 1: the load stays in the row
+        const size_t g = in ? (size_t)gy * pitch + gx : 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            V2 uv{E(0), E(0)}, fv{E(0), E(0)};
+            if (in) {
+                if (uin[r]) uv = *reinterpret_cast<const V2*>(uin[r] + g);
+                fv = *reinterpret_cast<const V2*>(fin[r] + g);
+            }
+            u[r][k][0] = uv.x;
+            u[r][k][1] = in1 ? uv.y : E(0);
+            f[r][k][0] = fv.x;
+            f[r][k][1] = in1 ? fv.y : E(0);
+        }
+        double q0 = 0.0, q1 = 0.0;
+        if (HELM && in) {
+            const double2 kv = *reinterpret_cast<const double2*>(k2 + g);
+            q0 = kv.x;
+            q1 = in1 ? kv.y : 0.0;
+        }
+        const double D0 = fmad(h2, q0, 4.0), D1 = fmad(h2, q1, 4.0);
+        D[k][0] = (E)D0;
+        D[k][1] = (E)D1;
+        iD[k][0] = HELM ? (E)(1.0 / D0) : E(0.25);
+        iD[k][1] = HELM ? (E)(1.0 / D1) : E(0.25);
+    }
+}
+
+// Rows 0 and K-1 of every wavefront into buffer b; after a barrier each
+// wavefront reads the row above its row 0 and the row below its row K-1
+// (0 past the tile).
+template <typename E, int R, int K, int NW>
+struct RegExchange {
+    using V2 = typename Pair2<E>::T;
+    V2 (*xb)[R][NW][2][64];
+    __device__ __forceinline__ void put(int b, const E (&v)[R][K][2], int w, int lane) const {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            xb[b][r][w][0][lane] = V2{v[r][0][0], v[r][0][1]};
+            xb[b][r][w][1][lane] = V2{v[r][K - 1][0], v[r][K - 1][1]};
+        }
+    }
+    __device__ __forceinline__ void get(int b, V2 (&up)[R], V2 (&dn)[R], int w, int lane) const {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            up[r] = w > 0 ? xb[b][r][w - 1][1][lane] : V2{E(0), E(0)};
+            dn[r] = w < NW - 1 ? xb[b][r][w + 1][0][lane] : V2{E(0), E(0)};
+        }
+    }
+};
+
+template <typename V2>
+__device__ __forceinline__ auto el(const V2& v, int j) { return j ? v.y : v.x; }
+
+// One red-black half sweep of colour c over the lane's rows; upd[k][j] marks
+// the nodes inside the tile's update region and the domain interior.
+template <typename E, int R, bool HELM, int K>
+__device__ __forceinline__ void reg_half_sweep(E (&u)[R][K][2], const E (&f)[R][K][2],
+                                               const E (&iD)[K][2], const bool (&upd)[K][2],
+                                               const typename Pair2<E>::T (&up)[R],
+                                               const typename Pair2<E>::T (&dn)[R], E h2, int c) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+            if (((c + k) & 1) != jj) continue;  // element jj of row k has colour c
+            const int j = jj;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                E left, right;
+                if (j == 0) {
+                    left = lane_shift<kFromLeft>(u[r][k][1]);
+                    right = u[r][k][1];
+                } else {
+                    left = u[r][k][0];
+                    right = lane_shift<kFromRight>(u[r][k][0]);
+                }
+                const E upv = k == 0 ? el(up[r], j) : u[r][k - 1][j];
+                const E dnv = k == K - 1 ? el(dn[r], j) : u[r][k + 1][j];
+                const E nb = left + right + upv + dnv;
+                const E nv = fmad(-h2, f[r][k][j], nb) * iD[k][j];
+                u[r][k][j] = upd[k][j] ? nv : u[r][k][j];
+            }
+        }
+    }
+}
+
+// Residual f - A u of every node of the lane's rows (0 outside the domain
+// interior); up/dn are the rows across the wavefront boundaries.
+template <typename E, int R, int K>
+__device__ __forceinline__ void reg_residual(E (&rr)[R][K][2], const E (&u)[R][K][2],
+                                             const E (&f)[R][K][2], const E (&D)[K][2],
+                                             const bool (&dom)[K][2],
+                                             const typename Pair2<E>::T (&up)[R],
+                                             const typename Pair2<E>::T (&dn)[R], E ih2) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const E l0 = lane_shift<kFromLeft>(u[r][k][1]);
+            const E r1 = lane_shift<kFromRight>(u[r][k][0]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const E left = j == 0 ? l0 : u[r][k][0];
+                const E right = j == 0 ? u[r][k][1] : r1;
+                const E upv = k == 0 ? el(up[r], j) : u[r][k - 1][j];
+                const E dnv = k == K - 1 ? el(dn[r], j) : u[r][k + 1][j];
+                const E nb = left + right + upv + dnv;
+                const E v = fmad(-fmad(-D[k][j], u[r][k][j], nb), ih2, f[r][k][j]);
+                rr[r][k][j] = dom[k][j] ? v : E(0);
+            }
+        }
+}
+
+// Down pass with register tiles: the same steps as k_mg_down.
+template <typename E, int R, bool HELM, int NU, int NW>
+__global__ __launch_bounds__(64 * NW) void k_mg_down_reg(DownArgs<E> a) {
+    constexpr int K = kRegRows;
+    constexpr int HL = 2 * NU + 2;
+    using S = RegShape<HL, NW>;
+    constexpr int TX = S::TX, TY = S::TY, ROWS = S::ROWS;
+    using V2 = typename Pair2<E>::T;
+    __shared__ V2 xb[2][R][NW][2][64];
+    __shared__ double red[NW * 2 * R];
+    const RegExchange<E, R, K, NW> xc{xb};
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int N = a.N;
+    int bx, by;
+    tile_of_block(bx, by);
+    const int x0 = bx * TX, y0 = by * TY;
+    const int ex0 = x0 - HL, ey0 = y0 - HL;
+    const int gx = ex0 + 2 * lane, gy0 = ey0 + w * K;
+    const E h2 = (E)(a.h * a.h), ih2 = (E)(1.0 / (a.h * a.h));
+
+    E u[R][K][2], f[R][K][2], D[K][2], iD[K][2];
+    reg_load<E, R, HELM, K>(u, f, D, iD, a.u_in, a.f, a.k2, a.pitch, gx, gy0, N, a.h * a.h);
+
+    bool upd[K][2], dom[K][2], own[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int Y = w * K + k, gy = gy0 + k;
+        own[k] = Y >= HL && Y < HL + TY;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int X = 2 * lane + j;
+            dom[k][j] = gx + j >= 1 && gx + j <= N - 1 && gy >= 1 && gy <= N - 1;
+            upd[k][j] = dom[k][j] && X >= 1 && X <= 126 && Y >= 1 && Y <= ROWS - 2;
+        }
+    }
+    const bool own_x = 2 * lane >= HL && 2 * lane < HL + TX;
+
+    V2 up[R], dn[R];
+    int buf = 0;
+    xc.put(buf, u, w, lane);
+    __syncthreads();
+    xc.get(buf, up, dn, w, lane);
+
+    if (a.norm_part) {  // residual of the incoming iterate on the owned interior nodes
+        E rr[R][K][2];
+        reg_residual<E, R, K>(rr, u, f, D, dom, up, dn, ih2);
+        double acc[2 * R];
+#pragma unroll
+        for (int q = 0; q < 2 * R; ++q) acc[q] = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                if (own[k] && own_x && dom[k][j])
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const double rv = rr[r][k][j];
+                        const double fv = f[r][k][j];
+                        acc[2 * r] += rv * rv;
+                        acc[2 * r + 1] += fv * fv;
+                    }
+        block_sum<2 * R, 64 * NW>(acc, red);
+        if (threadIdx.x == 0) {
+            const int b = by * gridDim.x + bx;
+#pragma unroll
+            for (int q = 0; q < 2 * R; ++q) a.norm_part[q * a.nblk + b] = acc[q];
+        }
+    }
+
+#pragma unroll
+    for (int q = 0; q < 2 * NU; ++q) {
+        if (q > 0) {
+            buf ^= 1;
+            xc.put(buf, u, w, lane);
+            __syncthreads();
+            xc.get(buf, up, dn, w, lane);
+        }
+        reg_half_sweep<E, R, HELM, K>(u, f, iD, upd, up, dn, h2, q & 1);
+    }
+
+    // the smoothed owned nodes
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int gy = gy0 + k;
+        if (own[k] && own_x && gx <= N - 1 && gy <= N - 1)
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                *reinterpret_cast<V2*>(a.u_out[r] + (size_t)gy * a.pitch + gx) =
+                    V2{u[r][k][0], u[r][k][1]};
+    }
+
+    // residual of the smoothed iterate, then full weighting onto the coarse
+    // nodes (x0/2 + i, y0/2 + m) owned by this tile
+    buf ^= 1;
+    xc.put(buf, u, w, lane);
+    __syncthreads();
+    xc.get(buf, up, dn, w, lane);
+    E rr[R][K][2];
+    reg_residual<E, R, K>(rr, u, f, D, dom, up, dn, ih2);
+    buf ^= 1;
+    xc.put(buf, rr, w, lane);
+    __syncthreads();
+    xc.get(buf, up, dn, w, lane);
+
+    const int Nc = N / 2;
+    const int I = ex0 / 2 + lane;
+#pragma unroll
+    for (int k = 0; k < K; k += 2) {
+        const int J = (gy0 + k) / 2;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const E am = k == 0 ? up[r].y : rr[r][k - 1][1];  // row k-1, odd column
+            const E a0 = k == 0 ? up[r].x : rr[r][k - 1][0];
+            const E sl = lane_shift<kFromLeft>(rr[r][k][1]);
+            const E sm = lane_shift<kFromLeft>(am);
+            const E sp = lane_shift<kFromLeft>(rr[r][k + 1][1]);
+            if (own[k] && own_x && I <= Nc - 1 && J <= Nc - 1) {
+                E v = E(0);
+                if (I >= 1 && J >= 1)
+                    v = (E(4) * rr[r][k][0] +
+                         E(2) * (sl + rr[r][k][1] + a0 + rr[r][k + 1][0]) +
+                         (sm + am + sp + rr[r][k + 1][1])) *
+                        E(1.0 / 16.0);
+                a.f_c[r][(size_t)J * a.pitch_c + I] = v;
+            }
+        }
+    }
+}
+
+// Up pass with register tiles: the same steps as k_mg_up.
+template <typename E, int R, bool HELM, int NU, int NW>
+__global__ __launch_bounds__(64 * NW) void k_mg_up_reg(UpArgs<E> a) {
+    constexpr int K = kRegRows;
+    constexpr int H = 2 * NU;
+    using S = RegShape<H, NW>;
+    constexpr int TX = S::TX, TY = S::TY, ROWS = S::ROWS;
+    using V2 = typename Pair2<E>::T;
+    __shared__ V2 xb[2][R][NW][2][64];
+    const RegExchange<E, R, K, NW> xc{xb};
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int N = a.N, Nc = N / 2;
+    int bx, by;
+    tile_of_block(bx, by);
+    const int x0 = bx * TX, y0 = by * TY;
+    const int ex0 = x0 - H, ey0 = y0 - H;
+    const int gx = ex0 + 2 * lane, gy0 = ey0 + w * K;
+    const E h2 = (E)(a.h * a.h);
+
+    E u[R][K][2], f[R][K][2], D[K][2], iD[K][2];
+    reg_load<E, R, HELM, K>(u, f, D, iD, a.u_mid, a.f, a.k2, a.pitch, gx, gy0, N, a.h * a.h);
+
+    // coarse correction at (I, J0 + m) and (I + 1, J0 + m), m = 0 .. K/2
+    constexpr int KC = K / 2 + 1;
+    const int I = ex0 / 2 + lane, J0 = gy0 / 2;
+    E eL[R][KC], eR[R][KC];
+#pragma unroll
+    for (int m = 0; m < KC; ++m) {
+        const int J = J0 + m;
+        const bool inJ = J >= 0 && J <= Nc;
+        const bool inL = inJ && I >= 0 && I <= Nc, inR = inJ && I + 1 >= 0 && I + 1 <= Nc;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            eL[r][m] = inL ? a.e_c[r][(size_t)J * a.pitch_c + I] : E(0);
+            eR[r][m] = inR ? a.e_c[r][(size_t)J * a.pitch_c + I + 1] : E(0);
+        }
+    }
+
+    bool upd[K][2], own[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int Y = w * K + k, gy = gy0 + k;
+        own[k] = Y >= H && Y < H + TY;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int X = 2 * lane + j;
+            const bool dom = gx + j >= 1 && gx + j <= N - 1 && gy >= 1 && gy <= N - 1;
+            upd[k][j] = dom && X >= 1 && X <= 126 && Y >= 1 && Y <= ROWS - 2;
+            // u += bilinear prolongation (gy even: row J0 + k/2; odd: between it and the next)
+            const int m = k / 2;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                E v;
+                if (!(k & 1)) v = j == 0 ? eL[r][m] : E(0.5) * (eL[r][m] + eR[r][m]);
+                else if (j == 0) v = E(0.5) * (eL[r][m] + eL[r][m + 1]);
+                else v = E(0.25) * (eL[r][m] + eR[r][m] + eL[r][m + 1] + eR[r][m + 1]);
+                if (dom) u[r][k][j] += v;
+            }
+        }
+    }
+    const bool own_x = 2 * lane >= H && 2 * lane < H + TX;
+
+    V2 up[R], dn[R];
+#pragma unroll
+    for (int q = 0; q < 2 * NU; ++q) {
+        xc.put(q & 1, u, w, lane);
+        __syncthreads();
+        xc.get(q & 1, up, dn, w, lane);
+        reg_half_sweep<E, R, HELM, K>(u, f, iD, upd, up, dn, h2, q & 1);
+    }
+
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int gy = gy0 + k;
+        if (own[k] && own_x && gx <= N - 1 && gy <= N - 1)
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                *reinterpret_cast<V2*>(a.u_out[r] + (size_t)gy * a.pitch + gx) =
+                    V2{u[r][k][0], u[r][k][1]};
     }
 }
 
@@ -634,18 +1028,19 @@ __global__ __launch_bounds__(kThreads) void k_resnorm(int N, double h, int pitch
                                                       const double* u0, const double* u1,
                                                       const double* f0, const double* f1,
                                                       const double* k2, double* part, int nblk,
-                                                      float* r0, float* r1, int pitch32, int T) {
+                                                      float* r0, float* r1, int pitch32, int TX,
+                                                      int TY) {
     __shared__ double red[(kThreads / 64) * 2 * R];
     const double ih2 = 1.0 / (h * h);
-    const int x0 = blockIdx.x * T, y0 = blockIdx.y * T;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
     const double* u[2] = {u0, u1};
     const double* f[2] = {f0, f1};
     float* ro[2] = {r0, r1};
     double acc[2 * R];
 #pragma unroll
     for (int k = 0; k < 2 * R; ++k) acc[k] = 0.0;
-    for (int i = threadIdx.x; i < T * T; i += kThreads) {
-        const int oy = i / T, ox = i - oy * T;
+    for (int i = threadIdx.x; i < TX * TY; i += kThreads) {
+        const int oy = i / TX, ox = i - oy * TX;
         const int gx = x0 + ox, gy = y0 + oy;
         if (gx > N - 1 || gy > N - 1) continue;
         const bool interior = gx >= 1 && gy >= 1;
@@ -761,6 +1156,64 @@ void up(int R, bool helm, const UpArgs<E>& a, int nu, dim3 g, hipStream_t s, con
 
 dim3 tiles(int N, int T = kTile) { return dim3((N + T - 1) / T, (N + T - 1) / T); }
 
+// Tiles of a level's down or up pass: register tiles on the levels
+// N >= c->reg_tile_min, LDS tiles of edge tile_for(N) below.  TX x TY owned
+// nodes per workgroup.
+struct PassGeom {
+    bool reg;
+    int TX, TY;
+    dim3 grid;
+};
+PassGeom pass_geom(const wandqs_ctx* c, int N, int nu, bool down) {
+    PassGeom g{};
+    g.reg = N >= c->reg_tile_min;
+    if (g.reg) {
+        const int halo = down ? 2 * nu + 2 : 2 * nu;
+        g.TX = 128 - 2 * halo;
+        g.TY = kRegRows * kRegWaves - 2 * halo;
+    } else {
+        g.TX = g.TY = tile_for(N);
+    }
+    g.grid = dim3((N + g.TX - 1) / g.TX, (N + g.TY - 1) / g.TY);
+    return g;
+}
+
+template <typename E, int R, bool HELM>
+void launch_down_reg(const DownArgs<E>& a, int nu, dim3 grid, hipStream_t s, const ProfScope& ps) {
+    constexpr int NW = kRegWaves;
+    switch (nu) {
+        case 1: WQ_KLAUNCH(ps, (k_mg_down_reg<E, R, HELM, 1, NW>), grid, dim3(64 * NW), 0, s, a); break;
+        case 2: WQ_KLAUNCH(ps, (k_mg_down_reg<E, R, HELM, 2, NW>), grid, dim3(64 * NW), 0, s, a); break;
+        default: WQ_KLAUNCH(ps, (k_mg_down_reg<E, R, HELM, 3, NW>), grid, dim3(64 * NW), 0, s, a); break;
+    }
+}
+
+template <typename E, int R, bool HELM>
+void launch_up_reg(const UpArgs<E>& a, int nu, dim3 grid, hipStream_t s, const ProfScope& ps) {
+    constexpr int NW = kRegWaves;
+    switch (nu) {
+        case 1: WQ_KLAUNCH(ps, (k_mg_up_reg<E, R, HELM, 1, NW>), grid, dim3(64 * NW), 0, s, a); break;
+        case 2: WQ_KLAUNCH(ps, (k_mg_up_reg<E, R, HELM, 2, NW>), grid, dim3(64 * NW), 0, s, a); break;
+        default: WQ_KLAUNCH(ps, (k_mg_up_reg<E, R, HELM, 3, NW>), grid, dim3(64 * NW), 0, s, a); break;
+    }
+}
+
+template <typename E>
+void down_pass(int R, bool helm, const DownArgs<E>& a, int nu, const PassGeom& g, hipStream_t s,
+               const ProfScope& ps) {
+    if (!g.reg) return down<E>(R, helm, a, nu, g.grid, s, ps, g.TX);
+    if (R == 1) helm ? launch_down_reg<E, 1, true>(a, nu, g.grid, s, ps) : launch_down_reg<E, 1, false>(a, nu, g.grid, s, ps);
+    else helm ? launch_down_reg<E, 2, true>(a, nu, g.grid, s, ps) : launch_down_reg<E, 2, false>(a, nu, g.grid, s, ps);
+}
+
+template <typename E>
+void up_pass(int R, bool helm, const UpArgs<E>& a, int nu, const PassGeom& g, hipStream_t s,
+             const ProfScope& ps) {
+    if (!g.reg) return up<E>(R, helm, a, nu, g.grid, s, ps, g.TX);
+    if (R == 1) helm ? launch_up_reg<E, 1, true>(a, nu, g.grid, s, ps) : launch_up_reg<E, 1, false>(a, nu, g.grid, s, ps);
+    else helm ? launch_up_reg<E, 2, true>(a, nu, g.grid, s, ps) : launch_up_reg<E, 2, false>(a, nu, g.grid, s, ps);
+}
+
 const char* type_name(double) { return "double"; }
 const char* type_name(float) { return "float"; }
 
@@ -806,20 +1259,23 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
             a.f_c[r] = F(l + 1, r);
         }
         a.k2 = helm ? K(l) : nullptr;
-        const int T = tile_for(L.N);
-        const dim3 g = tiles(L.N, T);
-        a.nblk = g.x * g.y;
+        const PassGeom g = pass_geom(c, L.N, c->cfg.nu_pre, true);
+        a.nblk = g.grid.x * g.grid.y;
         a.norm_part = (l == 0 && norm_slot >= 0)
                           ? c->norm_part + (size_t)norm_slot * 4 * c->max_tiles
                           : nullptr;
         // algorithmic bytes per owned node: u (when read), f, k2, smoothed u, coarse f
         const double nodes = (double)L.N * L.N;
         char nm[64];
-        std::snprintf(nm, sizeof nm, "k_mg_down<%s, %d, %s, %d, %d>@%d", type_name(E()), R,
-                      helm ? "true" : "false", c->cfg.nu_pre, T, L.N);
+        if (g.reg)
+            std::snprintf(nm, sizeof nm, "k_mg_down_reg<%s, %d, %s, %d, %d>@%d", type_name(E()), R,
+                          helm ? "true" : "false", c->cfg.nu_pre, kRegWaves, L.N);
+        else
+            std::snprintf(nm, sizeof nm, "k_mg_down<%s, %d, %s, %d, %d>@%d", type_name(E()), R,
+                          helm ? "true" : "false", c->cfg.nu_pre, g.TX, L.N);
         ProfScope ps(c, nm, nodes * ((a.u_in[0] ? eb * R : 0.0) + eb * R + (helm ? 8.0 : 0.0) +
                                      eb * R + eb * R / 4));
-        down<E>(R, helm, a, c->cfg.nu_pre, g, s, ps, T);
+        down_pass<E>(R, helm, a, c->cfg.nu_pre, g, s, ps);
     }
     {
         wq::Level& L = c->lev[lc];
@@ -868,11 +1324,15 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
         // per owned node: smoothed u, coarse correction (1/4), f, k2, corrected u
         const double nodes = (double)L.N * L.N;
         char nm[64];
-        const int T = tile_for(L.N);
-        std::snprintf(nm, sizeof nm, "k_mg_up<%s, %d, %s, %d, %d>@%d", type_name(E()), R,
-                      helm ? "true" : "false", c->cfg.nu_post, T, L.N);
+        const PassGeom g = pass_geom(c, L.N, c->cfg.nu_post, false);
+        if (g.reg)
+            std::snprintf(nm, sizeof nm, "k_mg_up_reg<%s, %d, %s, %d, %d>@%d", type_name(E()), R,
+                          helm ? "true" : "false", c->cfg.nu_post, kRegWaves, L.N);
+        else
+            std::snprintf(nm, sizeof nm, "k_mg_up<%s, %d, %s, %d, %d>@%d", type_name(E()), R,
+                          helm ? "true" : "false", c->cfg.nu_post, g.TX, L.N);
         ProfScope ps(c, nm, nodes * (eb * R + eb * R / 4 + eb * R + (helm ? 8.0 : 0.0) + eb * R));
-        up<E>(R, helm, a, c->cfg.nu_post, tiles(L.N, T), s, ps, T);
+        up_pass<E>(R, helm, a, c->cfg.nu_post, g, s, ps);
     }
 }
 
@@ -883,8 +1343,9 @@ void resnorm(wandqs_ctx* c, int R, bool helm, const Hier<double>& hz, int slot,
     const wq::Level& L = c->lev[0];
     // the same tiles as the level-0 down pass: every norm slot of a solve has
     // one partial-sum layout
-    const int T = tile_for(L.N);
-    const dim3 g = tiles(L.N, T);
+    const PassGeom pg = pass_geom(c, L.N, c->cfg.nu_pre, true);
+    const dim3 g = pg.grid;
+    const int TX = pg.TX, TY = pg.TY;
     double* part = c->norm_part + (size_t)slot * 4 * c->max_tiles;
     const int nblk = g.x * g.y;
     const double* u1 = R > 1 ? hz.u0[1] : nullptr;
@@ -896,11 +1357,11 @@ void resnorm(wandqs_ctx* c, int R, bool helm, const Hier<double>& hz, int slot,
                   r32 ? "+defect" : "");
     ProfScope ps(c, nm, (double)L.N * L.N * (16.0 * R + (helm ? 8.0 : 0.0) + (r32 ? 4.0 * R : 0.0)));
     if (R == 1) {
-        if (helm) WQ_KLAUNCH(ps, (k_resnorm<1, true>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch, T);
-        else WQ_KLAUNCH(ps, (k_resnorm<1, false>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch, T);
+        if (helm) WQ_KLAUNCH(ps, (k_resnorm<1, true>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch, TX, TY);
+        else WQ_KLAUNCH(ps, (k_resnorm<1, false>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch, TX, TY);
     } else {
-        if (helm) WQ_KLAUNCH(ps, (k_resnorm<2, true>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch, T);
-        else WQ_KLAUNCH(ps, (k_resnorm<2, false>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch, T);
+        if (helm) WQ_KLAUNCH(ps, (k_resnorm<2, true>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch, TX, TY);
+        else WQ_KLAUNCH(ps, (k_resnorm<2, false>), g, dim3(kThreads), 0, c->stream, L.N, L.h, L.pitch, hz.u0[0], u1, hz.f0[0], f1, hz.k2, part, nblk, o0, o1, L.pitch, TX, TY);
     }
 }
 
@@ -920,6 +1381,8 @@ void mixed_iteration(wandqs_ctx* c, int R, bool helm, const Hier<double>& hz, in
 }
 
 }  // namespace
+
+int reg_tile_min_default() { return WQ_REG_TILE_MIN; }
 
 // Solve with the context's stop rule.  Tolerance mode (mg_rtol > 0) runs a batch
 // of V-cycles sized by the previous slice's count for this solve, reads the
@@ -973,7 +1436,7 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
     const double atol = c->cfg.mg_atol * std::sqrt((double)(N - 1) * (N - 1));
     // partial sums per tile (the level-0 tiles, for both the down pass and the
     // residual-norm kernel)
-    const dim3 g = tiles(N, tile_for(N));
+    const dim3 g = pass_geom(c, N, c->cfg.nu_pre, true).grid;
     const int nblk = g.x * g.y;
     int done = 0;
     int pred = c->pred[kind] < 1 ? 1 : c->pred[kind];

@@ -150,6 +150,9 @@ struct wandqs_ctx {
     std::vector<wandqs_probe> probes;
 
     int N = 0, ppc = 0, nlev = 0, lc = 0;
+    // levels N >= reg_tile_min run the register-tile pass kernels (environment
+    // WANDQS_MG_TILES=lds at init: never; the LDS tiles give the same bits)
+    int reg_tile_min = 0;
     double L = 0, h = 0;
     int64_t P = 0;
     int rec_cap = 0;
@@ -217,6 +220,8 @@ namespace wq {
 
 // layout of the workspace (offsets from the base, computed for any base)
 size_t carve(wandqs_ctx* c, char* base);
+// smallest level that runs the register-tile pass kernels by default
+int reg_tile_min_default();
 
 // multigrid (mg.hip)
 wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const u[2],

@@ -58,7 +58,7 @@ def _rand_rhs(N, seed, nrhs=1):
     return f
 
 
-@pytest.mark.parametrize("N", [8, 16, 64, 128, 256, 512])
+@pytest.mark.parametrize("N", [8, 16, 64, 128, 256, 512, 1024])
 @pytest.mark.parametrize("helm", [False, True])
 @pytest.mark.parametrize("nrhs", [1, 2])
 def test_mg_solve_matches_oracle(torch_cuda, oracle_mod, N, helm, nrhs):
@@ -263,3 +263,42 @@ def test_mg_zero_rhs_nonzero_guess(torch_cuda, N, helm):
     assert st == 0 and cyc < 30, (st, cyc)
     assert float(u.abs().max()) <= 1e-12 * np.abs(u0).max()
     sim.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("helm", [False, True])
+def test_register_tiles_bitwise_equal_lds_tiles(torch_cuda, monkeypatch, precision, helm):
+    """The register-tile pass kernels of the large levels against the LDS tile
+    kernels (WANDQS_MG_TILES=lds): three fixed V-cycles on 1024^2 and 2048^2
+    give the same bits, and so does a full C5 slice."""
+    outs = []
+    for mode in (None, "lds"):
+        if mode:
+            monkeypatch.setenv("WANDQS_MG_TILES", mode)
+        else:
+            monkeypatch.delenv("WANDQS_MG_TILES", raising=False)
+        res = []
+        for N in (1024, 2048):
+            cfg = wi.scaled(wi.config("C1"), n_cells=N, half_width=6.0, mg_rtol=0.0,
+                            mg_max_cycles=3, precision=precision)
+            sim = _sim(cfg)
+            f = _rand_rhs(N, N, 2)
+            u0 = 0.1 * _rand_rhs(N, N + 1, 2)
+            k2 = np.random.default_rng(7).uniform(0.0, 30.0, (N + 1, N + 1)) if helm else None
+            st, u, _, _ = sim.mg_solve(f, u0=u0, k2=k2)
+            assert st == 0
+            res.append(u.cpu().numpy().copy())
+            sim.close()
+        if not helm:
+            cfg = wi.scaled(wi.config("C5"), mg_rtol=0.0, mg_max_cycles=6, precision=precision)
+            state = wi.synthetic_state(cfg, seed=15, p_max=0.5, xi=2.0, field_amp=0.01)
+            sim = _sim(cfg)
+            sim.set_state(particles=_particles(state), fields=state["fields"], xi=state["xi"],
+                          dxi=state["dxi"])
+            F, _ = sim.step(fields=True)
+            res.append(F.cpu().numpy().copy())
+            res.append(sim.get_state()["particles"].cpu().numpy().copy())
+            sim.close()
+        outs.append(res)
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b), float(np.abs(a - b).max())
