@@ -26,9 +26,6 @@
 namespace wq {
 namespace {
 
-#ifndef WQ_COARSE_THREADS
-#define WQ_COARSE_THREADS 1024
-#endif
 #ifndef WQ_COARSE_CYCLES
 #define WQ_COARSE_CYCLES 1
 #endif
@@ -39,7 +36,7 @@ namespace {
 #define WQ_SMALL_TILE_MAX 256
 #endif
 constexpr int kThreads = 256;  // norm and reduction kernels
-constexpr int kCoarseThreads = WQ_COARSE_THREADS;
+constexpr int kCoarseThreads = 1024;
 // Tile kernels: 32 x 32 owned nodes with 512 threads, or 16 x 16 with 256
 // threads on the levels N <= WQ_SMALL_TILE_MAX (more workgroups and a shorter
 // chain of dependent LDS phases per workgroup where the grid is small).
@@ -418,7 +415,7 @@ constexpr int kRegRows = 4;  // rows per wavefront (even)
 #define WQ_REG_WAVES 8
 #endif
 #ifndef WQ_REG_TILE_MIN
-#define WQ_REG_TILE_MIN 1024
+#define WQ_REG_TILE_MIN 512
 #endif
 constexpr int kRegWaves = WQ_REG_WAVES;
 static_assert(kRegWaves * kRegRows >= 32, "register tiles need at least 32 rows");
@@ -811,84 +808,117 @@ constexpr int coarse_nodes() {
     return t;
 }
 
-// Level operations with the level size as a compile-time constant.
-template <typename E, bool HELM, int n>
+// Level operations with the level size as a compile-time constant.  FAST
+// (float LDS copies, which leave room in LDS): the restriction computes each
+// fine residual once into a buffer, and the Helmholtz sweeps multiply by a
+// stored 1/D instead of dividing.
+template <typename E, bool HELM, int n, bool FAST>
 struct LdsLevel {
     static constexpr int W = n + 1;
-    static constexpr int HALF = n / 2;  // nodes of one colour per interior row (upper bound)
+    static constexpr int HALF = n / 2;                // node slots of one colour per interior row
+    static constexpr int ITEMS = (n - 1) * HALF;
+    static constexpr int NTH = kCoarseThreads;
+    static constexpr int PER = (ITEMS + NTH - 1) / NTH;
 
-    static __device__ void smooth(E* u, const E* f, const E* k2, E h2, int nu) {
+    static __device__ __forceinline__ void sync() { __syncthreads(); }
+
+    // nu red-black sweeps; iD (FAST and HELM) = 1 / (4 + h2 k2)
+    static __device__ void smooth(E* u, const E* f, const E* k2, const E* iD, E h2, int nu) {
+        // slot i: row b, first node a0 = 1 + 2 (i mod HALF); colour c updates a0 + ((1 + b + c) % 2)
+        int lb[PER], pb[PER];
+        bool ok[PER], last[PER];
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int i = threadIdx.x + m * NTH;
+            const int b = 1 + i / HALF;
+            const int a0 = 1 + 2 * (i - (b - 1) * HALF);
+            ok[m] = i < ITEMS;
+            last[m] = a0 == n - 1;  // a0 + 1 lies on the boundary
+            lb[m] = b * W + a0;
+            pb[m] = (1 + b) & 1;
+        }
         for (int s = 0; s < nu; ++s)
             for (int color = 0; color < 2; ++color) {
-                for (int i = threadIdx.x; i < (n - 1) * HALF; i += kCoarseThreads) {
-                    const int b = 1 + i / HALF;
-                    const int a = 1 + ((1 + b + color) & 1) + 2 * (i - (b - 1) * HALF);
-                    if (a > n - 1) continue;
-                    const int l = b * W + a;
+#pragma unroll
+                for (int m = 0; m < PER; ++m) {
+                    const int d = (pb[m] + color) & 1;
+                    if (!ok[m] || (d && last[m])) continue;
+                    const int l = lb[m] + d;
                     const E nb = u[l - 1] + u[l + 1] + u[l - W] + u[l + W];
-                    u[l] = HELM ? (nb - h2 * f[l]) / (E(4) + h2 * (E)k2[l])
-                                : (nb - h2 * f[l]) * E(0.25);
+                    const E t = nb - h2 * f[l];
+                    u[l] = HELM ? (FAST ? t * iD[l] : t / (E(4) + h2 * k2[l])) : t * E(0.25);
                 }
-                __syncthreads();
+                sync();
             }
     }
 
     static __device__ E resid(const E* u, const E* f, const E* k2, E ih2, int l) {
         E au = (u[l - 1] + u[l + 1] + u[l - W] + u[l + W] - E(4) * u[l]) * ih2;
-        if (HELM) au -= (E)k2[l] * u[l];
+        if (HELM) au -= k2[l] * u[l];
         return f[l] - au;
     }
 
-    // f_c = full weighting of the residual; u_c = 0
-    static __device__ void restrict_to(const E* u, const E* f, const E* k2, E ih2, E* uc,
-                                       E* fc) {
+    // f_c = full weighting of the residual; u_c = 0.  sr (FAST): residual
+    // buffer of the level's size.
+    static __device__ void restrict_to(const E* u, const E* f, const E* k2, E ih2, E* uc, E* fc,
+                                       E* sr) {
         constexpr int nc = n / 2, Wc = nc + 1;
-        for (int i = threadIdx.x; i < Wc * Wc; i += kCoarseThreads) {
+        if (FAST) {
+            for (int i = threadIdx.x; i < (n - 1) * (n - 1); i += NTH) {
+                const int y = 1 + i / (n - 1), x = 1 + i - (y - 1) * (n - 1);
+                sr[y * W + x] = resid(u, f, k2, ih2, y * W + x);
+            }
+            sync();
+        }
+        for (int i = threadIdx.x; i < Wc * Wc; i += NTH) {
             const int J = i / Wc, I = i - J * Wc;
             E v = E(0);
             if (I >= 1 && J >= 1 && I <= nc - 1 && J <= nc - 1) {
                 const int c = (2 * J) * W + 2 * I;
-                v = (E(4) * resid(u, f, k2, ih2, c) +
-                     E(2) * (resid(u, f, k2, ih2, c - 1) + resid(u, f, k2, ih2, c + 1) +
-                             resid(u, f, k2, ih2, c - W) + resid(u, f, k2, ih2, c + W)) +
-                     (resid(u, f, k2, ih2, c - W - 1) + resid(u, f, k2, ih2, c - W + 1) +
-                      resid(u, f, k2, ih2, c + W - 1) + resid(u, f, k2, ih2, c + W + 1))) *
-                    E(1.0 / 16.0);
+                if (FAST)
+                    v = (E(4) * sr[c] + E(2) * (sr[c - 1] + sr[c + 1] + sr[c - W] + sr[c + W]) +
+                         (sr[c - W - 1] + sr[c - W + 1] + sr[c + W - 1] + sr[c + W + 1])) *
+                        E(1.0 / 16.0);
+                else
+                    v = (E(4) * resid(u, f, k2, ih2, c) +
+                         E(2) * (resid(u, f, k2, ih2, c - 1) + resid(u, f, k2, ih2, c + 1) +
+                                 resid(u, f, k2, ih2, c - W) + resid(u, f, k2, ih2, c + W)) +
+                         (resid(u, f, k2, ih2, c - W - 1) + resid(u, f, k2, ih2, c - W + 1) +
+                          resid(u, f, k2, ih2, c + W - 1) + resid(u, f, k2, ih2, c + W + 1))) *
+                        E(1.0 / 16.0);
             }
             fc[i] = v;
             uc[i] = E(0);
         }
-        __syncthreads();
+        sync();
     }
 
-    // u += bilinear interpolation of the coarse correction uc
+    // u += bilinear interpolation of the coarse correction uc, one coarse cell
+    // (its four fine nodes 2I..2I+1 x 2J..2J+1, interior ones only) per item
     static __device__ void prolong_add(E* u, const E* uc) {
         constexpr int nc = n / 2, Wc = nc + 1;
-        for (int i = threadIdx.x; i < W * W; i += kCoarseThreads) {
-            const int y = i / W, x = i - y * W;
-            if (x < 1 || y < 1 || x > n - 1 || y > n - 1) continue;
-            const int c = (y >> 1) * Wc + (x >> 1);
-            const bool ox = x & 1, oy = y & 1;
-            E v;
-            if (!ox && !oy) v = uc[c];
-            else if (ox && !oy) v = E(0.5) * (uc[c] + uc[c + 1]);
-            else if (!ox && oy) v = E(0.5) * (uc[c] + uc[c + Wc]);
-            else v = E(0.25) * (uc[c] + uc[c + 1] + uc[c + Wc] + uc[c + Wc + 1]);
-            u[i] += v;
+        for (int i = threadIdx.x; i < nc * nc; i += NTH) {
+            const int J = i / nc, I = i - J * nc;
+            const int c = J * Wc + I, l = (2 * J) * W + 2 * I;
+            const E e00 = uc[c], e10 = uc[c + 1], e01 = uc[c + Wc], e11 = uc[c + Wc + 1];
+            if (I >= 1 && J >= 1) u[l] += e00;
+            if (J >= 1) u[l + 1] += E(0.5) * (e00 + e10);
+            if (I >= 1) u[l + W] += E(0.5) * (e00 + e01);
+            u[l + W + 1] += E(0.25) * (e00 + e10 + e01 + e11);
         }
-        __syncthreads();
+        sync();
     }
 };
 
 // Level dispatch: runtime level size -> compile-time specialisation.
-template <typename E, bool HELM, typename Fn>
+template <typename E, bool HELM, bool FAST, typename Fn>
 __device__ __forceinline__ void with_level(int n, Fn&& fn) {
     switch (n) {
-        case 64: fn(LdsLevel<E, HELM, 64>{}); break;
-        case 32: fn(LdsLevel<E, HELM, 32>{}); break;
-        case 16: fn(LdsLevel<E, HELM, 16>{}); break;
-        case 8: fn(LdsLevel<E, HELM, 8>{}); break;
-        default: fn(LdsLevel<E, HELM, 4>{}); break;
+        case 64: fn(LdsLevel<E, HELM, 64, FAST>{}); break;
+        case 32: fn(LdsLevel<E, HELM, 32, FAST>{}); break;
+        case 16: fn(LdsLevel<E, HELM, 16, FAST>{}); break;
+        case 8: fn(LdsLevel<E, HELM, 8, FAST>{}); break;
+        default: fn(LdsLevel<E, HELM, 4, FAST>{}); break;
     }
 }
 
@@ -901,9 +931,12 @@ __device__ __forceinline__ void with_level(int n, Fn&& fn) {
 template <typename E, typename C, bool HELM>
 __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
     constexpr int TOT = coarse_nodes();
+    constexpr bool FAST = sizeof(C) == 4;
     __shared__ C su[TOT];
     __shared__ C sf[TOT];
     __shared__ C sk[HELM ? TOT : 1];
+    __shared__ C siD[(HELM && FAST) ? TOT : 1];
+    __shared__ C sr[FAST ? (kCoarseMax + 1) * (kCoarseMax + 1) : 1];
     const int r = blockIdx.x;
     const int tid = threadIdx.x;
 
@@ -953,18 +986,39 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
             }
         }
     __syncthreads();
-
-    for (int cyc = 0; cyc < a.ncycles; ++cyc) {
-        for (int l = 0; l < nl - 1; ++l) {
+    if (HELM && FAST) {  // 1 / (4 + h^2 k2) of every level
+        for (int l = 0; l < nl; ++l) {
             const double hl = a.h * (double)(1 << l);
-            C* u = su + off[l];
-            C* f = sf + off[l];
-            const C* k2 = sk + (HELM ? off[l] : 0);
-            with_level<C, HELM>(Ns[l], [&](auto L) {
-                L.smooth(u, f, k2, (C)(hl * hl), a.nu1);
-                L.restrict_to(u, f, k2, (C)(1.0 / (hl * hl)), su + off[l + 1], sf + off[l + 1]);
-            });
+            const C h2 = (C)(hl * hl);
+            const int n1 = (Ns[l] + 1) * (Ns[l] + 1);
+            for (int i = tid; i < n1; i += kCoarseThreads)
+                siD[off[l] + i] = C(1) / (C(4) + h2 * sk[off[l] + i]);
         }
+        __syncthreads();
+    }
+
+    auto down = [&](int l) {
+        const double hl = a.h * (double)(1 << l);
+        C* u = su + off[l];
+        C* f = sf + off[l];
+        const C* k2 = sk + (HELM ? off[l] : 0);
+        const C* iD = siD + ((HELM && FAST) ? off[l] : 0);
+        with_level<C, HELM, FAST>(Ns[l], [&](auto L) {
+            L.smooth(u, f, k2, iD, (C)(hl * hl), a.nu1);
+            L.restrict_to(u, f, k2, (C)(1.0 / (hl * hl)), su + off[l + 1], sf + off[l + 1], sr);
+        });
+    };
+    auto up = [&](int l) {
+        const double hl = a.h * (double)(1 << l);
+        C* u = su + off[l];
+        with_level<C, HELM, FAST>(Ns[l], [&](auto L) {
+            L.prolong_add(u, su + off[l + 1]);
+            L.smooth(u, sf + off[l], sk + (HELM ? off[l] : 0), siD + ((HELM && FAST) ? off[l] : 0),
+                     (C)(hl * hl), a.nu2);
+        });
+    };
+    for (int cyc = 0; cyc < a.ncycles; ++cyc) {
+        for (int l = 0; l < nl - 1; ++l) down(l);
         if (tid == 0) {  // 2x2 cells: one unknown, four zero neighbours
             const int l = nl - 1;
             const double hl = a.h * (double)(1 << l);
@@ -973,14 +1027,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
             su[off[l] + c] = (C)(-(double)sf[off[l] + c] / (4.0 / (hl * hl) + k2c));
         }
         __syncthreads();
-        for (int l = nl - 2; l >= 0; --l) {
-            const double hl = a.h * (double)(1 << l);
-            C* u = su + off[l];
-            with_level<C, HELM>(Ns[l], [&](auto L) {
-                L.prolong_add(u, su + off[l + 1]);
-                L.smooth(u, sf + off[l], sk + (HELM ? off[l] : 0), (C)(hl * hl), a.nu2);
-            });
-        }
+        for (int l = nl - 2; l >= 0; --l) up(l);
     }
     for (int i = tid; i < (N + 1) * (N + 1); i += kCoarseThreads) {
         const int y = i / (N + 1), x = i - y * (N + 1);
@@ -1514,3 +1561,4 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
 }
 
 }  // namespace wq
+

@@ -16,7 +16,10 @@ namespace wq {
 constexpr int kMaxBeams = 8;
 constexpr int kMaxProbes = 16;
 constexpr int kMaxLevels = 13;
-constexpr int kCoarseMax = 64;  // levels with N <= 64 are solved inside one workgroup
+#ifndef WQ_COARSE_MAX
+#define WQ_COARSE_MAX 64
+#endif
+constexpr int kCoarseMax = WQ_COARSE_MAX;  // levels with N <= kCoarseMax are solved inside one workgroup
 constexpr int kMaxSlots = 208;  // residual-norm records per solve (mg_max_cycles + batches)
 constexpr int kTile = 32;       // multigrid tile edge (fine nodes owned by one workgroup)
 constexpr int kDepTile = 16;    // deposit tile edge (nodes owned by one workgroup)
