@@ -34,6 +34,7 @@
  * Parity status of each function is recorded in the design notes; every
  * function here is pinned by a test in tests/test_oracle_*.py.
  */
+#include <limits>
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -332,7 +333,9 @@ void vcycle(std::vector<Level<T>>& lv, size_t l, int nu1, int nu2) {
 /* Solve (L_h - k2) u = f for the interior nodes with u = 0 on the boundary,
  * starting from the guess held in u.  Stops when ||r|| <= rtol ||f|| + atol sqrt(n)
  * (n interior nodes; ||r_0|| in place of ||f|| when f = 0), or at the rounding
- * floor: a cycle after the second that reduces ||r|| by less than 2x while
+ * floor: ||r|| <= 0.35 eps (8/h^2 ||u|| + ||f||), the size of the rounding
+ * error in forming r (a backward-error test; 8/h^2 bounds ||L_h||), or a cycle
+ * after the second that reduces ||r|| by less than 2x while
  * ||r|| <= 1e-9 max(||f||, ||r_0||) (the guard keeps a slowly converging solve
  * from being taken for a converged one).  Otherwise returns ORC_NOCONV after
  * max_cycles.  For a Dual scalar every component (value and each derivative)
@@ -365,7 +368,9 @@ int mg_solve(int N, double h, const T* k2, const T* f, T* u, double rtol, double
     const int nc = ncomp(T(0.0));
     std::vector<T> r;
     residual(top, r);
-    std::vector<double> fnorm(nc), rn(nc), rprev(nc), tol(nc), scale(nc);
+    std::vector<double> fnorm(nc), rn(nc), rprev(nc), tol(nc), scale(nc), un(nc);
+    const double floor_be = 0.35 * std::numeric_limits<double>::epsilon();
+    const double a_norm = 8.0 / (h * h);
     for (int c = 0; c < nc; ++c) {
         fnorm[c] = norm2_interior(top, top.f, c);
         rn[c] = rprev[c] = norm2_interior(top, r, c);
@@ -388,7 +393,8 @@ int mg_solve(int N, double h, const T* k2, const T* f, T* u, double rtol, double
         for (int c = 0; c < nc; ++c) {
             rprev[c] = rn[c];
             rn[c] = norm2_interior(top, r, c);
-            if (rn[c] <= tol[c]) done[c] = true;
+            un[c] = norm2_interior(top, top.u, c);
+            if (rn[c] <= tol[c] || rn[c] <= floor_be * (a_norm * un[c] + fnorm[c])) done[c] = true;
             else if (cyc >= 2 && rn[c] > 0.5 * rprev[c] && rn[c] <= 1e-9 * scale[c])
                 done[c] = true; /* floor */
             else done[c] = false;

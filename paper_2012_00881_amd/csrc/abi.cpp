@@ -323,8 +323,8 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
     c->st = (double*)take(sizeof(double) * 8);
     c->vmax_part = (double*)take(sizeof(double) * c->n_push_blocks);
     c->flags = (int32_t*)take(sizeof(int32_t) * 4);
-    c->norm_part = (double*)take(sizeof(double) * kMaxSlots * 4 * (size_t)c->max_tiles);
-    c->norm_red = (double*)take(sizeof(double) * kMaxSlots * 4);
+    c->norm_part = (double*)take(sizeof(double) * kMaxSlots * kNormVec * (size_t)c->max_tiles);
+    c->norm_red = (double*)take(sizeof(double) * kMaxSlots * kNormVec);
     c->rec = (double*)take(sizeof(double) * 4 * (size_t)c->rec_cap);
     c->probe_acc = (double*)take(sizeof(double) * kMaxProbes);
     c->bins_dev = (double*)take(sizeof(double) * (size_t)(c->n_bins_total + 1));
@@ -440,7 +440,7 @@ wandqs_status wandqs_init(const wandqs_config* cfg, int32_t n_slices, void* d_wo
         delete c;
         return WANDQS_E_HIP;
     };
-    if (hipHostMalloc((void**)&c->h_pin, sizeof(double) * (wq::kMaxSlots * 4 + 8)) != hipSuccess)
+    if (hipHostMalloc((void**)&c->h_pin, sizeof(double) * (wq::kMaxSlots * wq::kNormVec + 8)) != hipSuccess)
         return bail("hipHostMalloc failed");
     if (hipMemsetAsync(d_workspace, 0, need, c->stream) != hipSuccess)
         return bail("hipMemsetAsync of the workspace failed");

@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 
 #include "wq_common.h"
 
@@ -169,7 +170,7 @@ struct DownArgs {
     const double* k2;
     E* u_out[2];
     E* f_c[2];
-    double* norm_part;  // (double only) nullptr or [R*2][nblk]: sum r^2, sum f^2 of the incoming u
+    double* norm_part;  // (double only) nullptr or [3R][nblk]: sums r^2, f^2, u^2 of the incoming u
     int nblk;
 };
 
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(tile_threads<T>()) void k_mg_down(DownArgs<E> a) {
     using S = TileShape<R, HELM, EX, EY, NT>;
     constexpr int PW = S::PW, NP = S::NP, KP = S::KP, EN = S::EN;
     __shared__ E su[R][EN];
-    __shared__ double red[(NT / 64) * 2 * R];
+    __shared__ double red[(NT / 64) * 3 * R];
 
     const int tid = threadIdx.x;
     const int N = a.N;
@@ -209,9 +210,9 @@ __global__ __launch_bounds__(tile_threads<T>()) void k_mg_down(DownArgs<E> a) {
     };
 
     if (a.norm_part) {  // residual of the incoming iterate on the owned interior nodes
-        double acc[2 * R];
+        double acc[3 * R];
 #pragma unroll
-        for (int q = 0; q < 2 * R; ++q) acc[q] = 0.0;
+        for (int q = 0; q < 3 * R; ++q) acc[q] = 0.0;
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
             const int p = tid + k * NT;
@@ -226,17 +227,19 @@ __global__ __launch_bounds__(tile_threads<T>()) void k_mg_down(DownArgs<E> a) {
                     for (int r = 0; r < R; ++r) {
                         const double rr = residual(r, k, j, ly * EX + lx);
                         const double fv = pick(j, fr[r][k][0], fr[r][k][1]);
-                        acc[2 * r] += rr * rr;
-                        acc[2 * r + 1] += fv * fv;
+                        const double uv = su[r][ly * EX + lx];
+                        acc[3 * r] += rr * rr;
+                        acc[3 * r + 1] += fv * fv;
+                        acc[3 * r + 2] += uv * uv;
                     }
                 }
             }
         }
-        block_sum<2 * R, NT>(acc, red);
+        block_sum<3 * R, NT>(acc, red);
         if (tid == 0) {
             const int b = by * gridDim.x + bx;
 #pragma unroll
-            for (int q = 0; q < 2 * R; ++q) a.norm_part[q * a.nblk + b] = acc[q];
+            for (int q = 0; q < 3 * R; ++q) a.norm_part[q * a.nblk + b] = acc[q];
         }
     }
 
@@ -584,7 +587,7 @@ __global__ __launch_bounds__(64 * NW) void k_mg_down_reg(DownArgs<E> a) {
     constexpr int TX = S::TX, TY = S::TY, ROWS = S::ROWS;
     using V2 = typename Pair2<E>::T;
     __shared__ V2 xb[2][R][NW][2][64];
-    __shared__ double red[NW * 2 * R];
+    __shared__ double red[NW * 3 * R];
     const RegExchange<E, R, K, NW> xc{xb};
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -622,9 +625,9 @@ __global__ __launch_bounds__(64 * NW) void k_mg_down_reg(DownArgs<E> a) {
     if (a.norm_part) {  // residual of the incoming iterate on the owned interior nodes
         E rr[R][K][2];
         reg_residual<E, R, K>(rr, u, f, D, dom, up, dn, ih2);
-        double acc[2 * R];
+        double acc[3 * R];
 #pragma unroll
-        for (int q = 0; q < 2 * R; ++q) acc[q] = 0.0;
+        for (int q = 0; q < 3 * R; ++q) acc[q] = 0.0;
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -634,14 +637,16 @@ __global__ __launch_bounds__(64 * NW) void k_mg_down_reg(DownArgs<E> a) {
                     for (int r = 0; r < R; ++r) {
                         const double rv = rr[r][k][j];
                         const double fv = f[r][k][j];
-                        acc[2 * r] += rv * rv;
-                        acc[2 * r + 1] += fv * fv;
+                        const double uv = u[r][k][j];
+                        acc[3 * r] += rv * rv;
+                        acc[3 * r + 1] += fv * fv;
+                        acc[3 * r + 2] += uv * uv;
                     }
-        block_sum<2 * R, 64 * NW>(acc, red);
+        block_sum<3 * R, 64 * NW>(acc, red);
         if (threadIdx.x == 0) {
             const int b = by * gridDim.x + bx;
 #pragma unroll
-            for (int q = 0; q < 2 * R; ++q) a.norm_part[q * a.nblk + b] = acc[q];
+            for (int q = 0; q < 3 * R; ++q) a.norm_part[q * a.nblk + b] = acc[q];
         }
     }
 
@@ -1077,15 +1082,15 @@ __global__ __launch_bounds__(kThreads) void k_resnorm(int N, double h, int pitch
                                                       const double* k2, double* part, int nblk,
                                                       float* r0, float* r1, int pitch32, int TX,
                                                       int TY) {
-    __shared__ double red[(kThreads / 64) * 2 * R];
+    __shared__ double red[(kThreads / 64) * 3 * R];
     const double ih2 = 1.0 / (h * h);
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
     const double* u[2] = {u0, u1};
     const double* f[2] = {f0, f1};
     float* ro[2] = {r0, r1};
-    double acc[2 * R];
+    double acc[3 * R];
 #pragma unroll
-    for (int k = 0; k < 2 * R; ++k) acc[k] = 0.0;
+    for (int k = 0; k < 3 * R; ++k) acc[k] = 0.0;
     for (int i = threadIdx.x; i < TX * TY; i += kThreads) {
         const int oy = i / TX, ox = i - oy * TX;
         const int gx = x0 + ox, gy = y0 + oy;
@@ -1100,17 +1105,18 @@ __global__ __launch_bounds__(kThreads) void k_resnorm(int N, double h, int pitch
                 double au = (q[g - 1] + q[g + 1] + q[g - pitch] + q[g + pitch] - 4.0 * q[g]) * ih2;
                 if (HELM) au -= k2[g] * q[g];
                 rr = f[r][g] - au;
-                acc[2 * r] += rr * rr;
-                acc[2 * r + 1] += f[r][g] * f[r][g];
+                acc[3 * r] += rr * rr;
+                acc[3 * r + 1] += f[r][g] * f[r][g];
+                acc[3 * r + 2] += q[g] * q[g];
             }
             if (ro[0]) ro[r][(size_t)gy * pitch32 + gx] = (float)rr;
         }
     }
-    block_sum<2 * R, kThreads>(acc, red);
+    block_sum<3 * R, kThreads>(acc, red);
     if (threadIdx.x == 0) {
         const int b = blockIdx.y * gridDim.x + blockIdx.x;
 #pragma unroll
-        for (int k = 0; k < 2 * R; ++k) part[k * nblk + b] = acc[k];
+        for (int k = 0; k < 3 * R; ++k) part[k * nblk + b] = acc[k];
     }
 }
 
@@ -1125,7 +1131,7 @@ __global__ void k_correct(int N, int pitch, int pitch32, double* __restrict__ u0
     if (u1) u1[(size_t)b * pitch + a] += (double)e1[(size_t)b * pitch32 + a];
 }
 
-// out[s*4 + k] = sum_b part[s][k][b]: one block per (slot, k), fixed order.
+// out[s*kNormVec + k] = sum_b part[s][k][b]: one block per (slot, k), fixed order.
 __global__ __launch_bounds__(kThreads) void k_reduce_slots(const double* part, int stride,
                                                            int nblk, int s0, int nvec,
                                                            double* out) {
@@ -1135,7 +1141,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce_slots(const double* part, i
     double acc[1] = {0.0};
     for (int b = threadIdx.x; b < nblk; b += kThreads) acc[0] += p[b];
     block_sum<1, kThreads>(acc, red);
-    if (threadIdx.x == 0) out[s * 4 + k] = acc[0];
+    if (threadIdx.x == 0) out[s * kNormVec + k] = acc[0];
 }
 
 // Full weighting of a fine node array onto the interior coarse nodes (boundary 0).
@@ -1309,7 +1315,7 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
         const PassGeom g = pass_geom(c, L.N, c->cfg.nu_pre, true);
         a.nblk = g.grid.x * g.grid.y;
         a.norm_part = (l == 0 && norm_slot >= 0)
-                          ? c->norm_part + (size_t)norm_slot * 4 * c->max_tiles
+                          ? c->norm_part + (size_t)norm_slot * kNormVec * c->max_tiles
                           : nullptr;
         // algorithmic bytes per owned node: u (when read), f, k2, smoothed u, coarse f
         const double nodes = (double)L.N * L.N;
@@ -1393,7 +1399,7 @@ void resnorm(wandqs_ctx* c, int R, bool helm, const Hier<double>& hz, int slot,
     const PassGeom pg = pass_geom(c, L.N, c->cfg.nu_pre, true);
     const dim3 g = pg.grid;
     const int TX = pg.TX, TY = pg.TY;
-    double* part = c->norm_part + (size_t)slot * 4 * c->max_tiles;
+    double* part = c->norm_part + (size_t)slot * kNormVec * c->max_tiles;
     const int nblk = g.x * g.y;
     const double* u1 = R > 1 ? hz.u0[1] : nullptr;
     const double* f1 = R > 1 ? hz.f0[1] : nullptr;
@@ -1435,8 +1441,10 @@ int reg_tile_min_default() { return WQ_REG_TILE_MIN; }
 // of V-cycles sized by the previous slice's count for this solve, reads the
 // residual norms back once per batch and adds single cycles until every
 // right-hand side meets ||r|| <= rtol ||f|| + atol sqrt(n) or reaches the
-// rounding floor (a cycle that no longer halves ||r|| once
-// ||r|| <= 1e-9 max(||f||, ||r_0||), r_0 the initial residual).
+// rounding floor: either ||r|| <= kFloorBE eps (8/h^2 ||u|| + ||f||) (the
+// residual is at the size that rounding in forming it leaves), or a cycle no
+// longer halves ||r|| once ||r|| <= 1e-9 max(||f||, ||r_0||), r_0 the initial
+// residual.
 // Fixed mode runs mg_max_cycles cycles without any host synchronisation.
 wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const u[2],
                        double* const f[2], const double* k2, SolveResult* res) {
@@ -1487,7 +1495,10 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
     const int nblk = g.x * g.y;
     int done = 0;
     int pred = c->pred[kind] < 1 ? 1 : c->pred[kind];
-    double* hr = c->h_pin;  // [kMaxSlots][4] + flags
+    double* hr = c->h_pin;  // [kMaxSlots][kNormVec] + flags
+    constexpr int V = kNormVec;
+    const double a_norm = 8.0 / (c->lev[0].h * c->lev[0].h);  // ||L_h||_2 bound
+    const double eps = std::numeric_limits<double>::epsilon();
     if (separate_norm) resnorm(c, R, helm, hz, 0, nullptr);
     while (true) {
         int b = done == 0 ? pred : 1;
@@ -1501,31 +1512,33 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
         const int s0 = done == 0 ? 0 : done + 1;
         const int ns = done + b + 1 - s0;
         {
-            ProfScope ps(c, "k_reduce_slots", 8.0 * ns * 2 * R * (nblk + 1));
-            WQ_KLAUNCH(ps, k_reduce_slots, dim3(ns * 2 * R), dim3(kThreads), 0, s,
-                               c->norm_part, 4 * c->max_tiles, nblk, s0, 2 * R, c->norm_red);
+            ProfScope ps(c, "k_reduce_slots", 8.0 * ns * 3 * R * (nblk + 1));
+            WQ_KLAUNCH(ps, k_reduce_slots, dim3(ns * 3 * R), dim3(kThreads), 0, s,
+                               c->norm_part, V * c->max_tiles, nblk, s0, 3 * R, c->norm_red);
         }
         WQ_LAUNCH_CHECK();
-        WQ_HIP(hipMemcpyAsync(hr + 4 * s0, c->norm_red + 4 * s0, sizeof(double) * 4 * ns,
+        WQ_HIP(hipMemcpyAsync(hr + V * s0, c->norm_red + V * s0, sizeof(double) * V * ns,
                               hipMemcpyDeviceToHost, s));
-        WQ_HIP(hipMemcpyAsync(hr + 4 * kMaxSlots, c->flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        WQ_HIP(hipMemcpyAsync(hr + V * kMaxSlots, c->flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         WQ_HIP(hipStreamSynchronize(s));
         done += b;
         int32_t fl;
-        std::memcpy(&fl, hr + 4 * kMaxSlots, sizeof(fl));
+        std::memcpy(&fl, hr + V * kMaxSlots, sizeof(fl));
         // first cycle count at which every rhs satisfies the stop rule
         int need = -1;
         for (int k = 0; k <= done && need < 0; ++k) {
             bool all = true;
             for (int r = 0; r < R; ++r) {
-                const double rr = std::sqrt(hr[4 * k + 2 * r]);
-                const double ff = std::sqrt(hr[4 * k + 2 * r + 1]);
+                const double rr = std::sqrt(hr[V * k + 3 * r]);
+                const double ff = std::sqrt(hr[V * k + 3 * r + 1]);
+                const double uu = std::sqrt(hr[V * k + 3 * r + 2]);
                 // relative to ||f||; for f = 0 (solution 0) relative to ||r_0||
-                const double ref = ff > 0 ? ff : std::sqrt(hr[2 * r]);
-                bool ok = std::isfinite(rr) && rr <= c->cfg.mg_rtol * ref + atol;
+                const double ref = ff > 0 ? ff : std::sqrt(hr[3 * r]);
+                bool ok = std::isfinite(rr) && (rr <= c->cfg.mg_rtol * ref + atol ||
+                                                rr <= kFloorBE * eps * (a_norm * uu + ff));
                 if (!ok && k >= 2) {
-                    const double rp = std::sqrt(hr[4 * (k - 1) + 2 * r]);
-                    const double scale = std::max(ff, std::sqrt(hr[2 * r]));
+                    const double rp = std::sqrt(hr[V * (k - 1) + 3 * r]);
+                    const double scale = std::max(ff, std::sqrt(hr[3 * r]));
                     ok = std::isfinite(rr) && rr > 0.5 * rp && rr <= 1e-9 * scale;
                 }
                 all = all && ok;
@@ -1536,8 +1549,8 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
             if (res) {
                 res->cycles = done;
                 for (int r = 0; r < R; ++r) {
-                    const double rr = std::sqrt(hr[4 * done + 2 * r]);
-                    const double ff = std::sqrt(hr[4 * done + 2 * r + 1]);
+                    const double rr = std::sqrt(hr[V * done + 3 * r]);
+                    const double ff = std::sqrt(hr[V * done + 3 * r + 1]);
                     res->rel[r] = ff > 0 ? rr / ff : rr;
                 }
             }

@@ -21,6 +21,11 @@ constexpr int kMaxLevels = 13;
 #endif
 constexpr int kCoarseMax = WQ_COARSE_MAX;  // levels with N <= kCoarseMax are solved inside one workgroup
 constexpr int kMaxSlots = 208;  // residual-norm records per solve (mg_max_cycles + batches)
+constexpr int kNormVec = 6;     // per record and right-hand side r: sums of r^2, f^2, u^2 at 3r .. 3r+2
+// Rounding-floor test of the stop rule: ||r|| <= kFloorBE eps (||L_h|| ||u|| + ||f||).
+// Residuals formed in FP64 from an iterate at the floor measure about 0.2-0.25
+// of eps (8/h^2 ||u|| + ||f||); one cycle before the floor, 0.5 or more.
+constexpr double kFloorBE = 0.35;
 constexpr int kTile = 32;       // multigrid tile edge (fine nodes owned by one workgroup)
 constexpr int kDepTile = 16;    // deposit tile edge (nodes owned by one workgroup)
 constexpr int kPredKinds = 8;   // solve kinds with their own V-cycle batch prediction
@@ -185,8 +190,8 @@ struct wandqs_ctx {
     double* vmax_part = nullptr;  // per push block
     int n_push_blocks = 0;
     int32_t* flags = nullptr;
-    double* norm_part = nullptr;  // [kMaxSlots][4][max_tiles]
-    double* norm_red = nullptr;   // [kMaxSlots][4]
+    double* norm_part = nullptr;  // [kMaxSlots][kNormVec][max_tiles]
+    double* norm_red = nullptr;   // [kMaxSlots][kNormVec]
     int max_tiles = 0;
     double* rec = nullptr;        // [rec_cap][4] : xi, dxi, vmax, flags
     double* probe_acc = nullptr;  // [kMaxProbes]
