@@ -160,3 +160,38 @@ def test_zero_rhs_with_nonzero_guess(oracle_mod, helm):
     st, u, cyc, rel = oracle_mod.mg_solve(N, h, np.zeros_like(u0), u0=u0, k2=k2)
     assert st == 0 and cyc < 30
     assert np.abs(u).max() <= 1e-12 * np.abs(u0).max()
+
+
+@pytest.mark.parametrize("helm", [False, True])
+@pytest.mark.parametrize("smooth", [False, True])
+def test_stop_at_rounding_floor(oracle_mod, helm, smooth):
+    """The stop rule (rtol 1e-14, backward-error floor test) ends the solve at
+    the rounding floor, not before: one more V-cycle from the returned iterate
+    reduces ||r|| by less than 2x, while the cycle before the stop still
+    reduced it by more than 2x."""
+    N, L = 128, 6.0
+    h = 2 * L / N
+    rng = np.random.default_rng(11)
+    if smooth:
+        x = np.linspace(-L, L, N + 1)
+        X, Y = np.meshgrid(x, x)
+        f = np.exp(-(X ** 2 + Y ** 2) / 0.7)
+    else:
+        f = rng.standard_normal((N + 1, N + 1))
+    f[[0, -1], :] = 0
+    f[:, [0, -1]] = 0
+    k2 = rng.uniform(0.0, 30.0, (N + 1, N + 1)) if helm else None
+    A = _scipy_operator(N, h, k2)
+
+    def rnorm(u):
+        return np.linalg.norm(f[1:-1, 1:-1].ravel() - A @ u[1:-1, 1:-1].ravel())
+
+    st, u, cyc, _ = oracle_mod.mg_solve(N, h, f, k2=k2)
+    assert st == 0 and cyc >= 3
+    _, u_prev, _, _ = oracle_mod.mg_solve(N, h, f, k2=k2, rtol=0.0, max_cycles=cyc - 1)
+    _, u_more, c1, _ = oracle_mod.mg_solve(N, h, f, u0=u, k2=k2, rtol=0.0, max_cycles=1)
+    assert c1 == 1
+    r_prev, r_stop, r_more = rnorm(u_prev), rnorm(u), rnorm(u_more)
+    print(f"cycles {cyc}: ||r|| {r_prev:.3e} -> {r_stop:.3e} -> {r_more:.3e}")
+    assert r_more > 0.5 * r_stop
+    assert r_stop < 0.5 * r_prev
