@@ -288,6 +288,8 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
         for (int n = c->lev[c->lc].N; n >= 2; n /= 2) tot += (n + 1) * (n + 1);
         c->k2lev = (double*)take(sizeof(double) * (size_t)tot);
     }
+    c->dst_S = (float*)take(sizeof(float) * 64 * 64);
+    c->dst_M = (float*)take(sizeof(float) * 64 * 64);
     for (int l = 1; l <= c->lc; ++l) {
         Level& L = c->lev[l];
         for (int r = 0; r < 2; ++r) {
@@ -557,7 +559,11 @@ wandqs_status wandqs_init(const wandqs_config* cfg, int32_t n_slices, void* d_wo
                     ids[i] = (int32_t)i;
                 }
     const double st0[6] = {0.0, cfg->dxi0, 0.0, 0.0, 0.0, 0.0};
-    bool ok = hipMemcpyAsync(c->pa[0][0], host.data(), sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+    std::vector<float> dstS(64 * 64), dstM(64 * 64);
+    wq::dst_tables(c->lev[c->lc].h, dstS.data(), dstM.data());
+    bool ok = hipMemcpyAsync(c->dst_S, dstS.data(), sizeof(float) * dstS.size(), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+              hipMemcpyAsync(c->dst_M, dstM.data(), sizeof(float) * dstM.size(), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+              hipMemcpyAsync(c->pa[0][0], host.data(), sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
               hipMemcpyAsync(c->pa[0][1], host.data() + c->P, sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
               hipMemcpyAsync(c->pid[0], ids.data(), sizeof(int32_t) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
               hipMemcpyAsync(c->st, st0, sizeof(st0), hipMemcpyHostToDevice, c->stream) == hipSuccess &&

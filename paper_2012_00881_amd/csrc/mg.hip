@@ -1040,6 +1040,88 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
     }
 }
 
+// Exact solve of the Poisson problem on the 64^2 coarse level (u = 0 on the
+// boundary).  The 2-D sine transform diagonalises the 5-point operator of
+// eq. (33): with S_jk = sin(pi (j+1)(k+1) / 64) (S S = 32 I) and the
+// eigenvalues lambda_kl = -(4/H^2) (sin^2(pi (k+1)/128) + sin^2(pi (l+1)/128)),
+// u = S (M o (S f S)) S with M = 1 / (32^2 lambda).  The four products run on
+// fp32 MFMA (v_mfma_f32_16x16x4_f32), 16 wavefronts with one 16 x 16 output
+// tile each; the 63 interior rows and columns are padded to 64 with zeros.
+// Like the V-cycle coarse kernel below a finer level, the coarse correction
+// is computed in float.
+constexpr int kDstN = 64;
+constexpr int kDstLd = 68;  // LDS row stride of the 64 x 64 matrices
+typedef float dst_v4f __attribute__((ext_vector_type(4)));
+
+template <typename E>
+struct DstArgs {
+    int pitch;
+    const E* f[2];
+    E* u_out[2];
+    const float* S;
+    const float* M;
+};
+
+// D = A B for 64 x 64 matrices in LDS: A row-major, B given transposed (Bt[j][k]
+// = B[k][j]).  Wavefront w computes the tile rows 16 (w / 4) .., columns
+// 16 (w % 4) ..; lane l feeds A[i0 + l % 16][4 s + l / 16] and
+// Bt[j0 + l % 16][4 s + l / 16] at step s and holds D[i0 + 4 (l / 16) + q][j0 + l % 16].
+__device__ __forceinline__ dst_v4f dst_tile(const float* A, const float* Bt) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i0 = 16 * (w >> 2), j0 = 16 * (w & 3);
+    const float* a = A + (i0 + (lane & 15)) * kDstLd + (lane >> 4);
+    const float* b = Bt + (j0 + (lane & 15)) * kDstLd + (lane >> 4);
+    dst_v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < kDstN / 4; ++s)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * s], b[4 * s], acc, 0, 0, 0);
+    return acc;
+}
+
+template <typename E>
+__global__ __launch_bounds__(1024) void k_coarse_dst(DstArgs<E> a) {
+    __shared__ float sS[kDstN * kDstLd];
+    __shared__ float sX[kDstN * kDstLd];
+    __shared__ float sY[kDstN * kDstLd];
+    const int r = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int i0 = 16 * (w >> 2), j0 = 16 * (w & 3);
+    const int ti = i0 + 4 * (lane >> 4), tj = j0 + (lane & 15);  // this lane's outputs: rows ti + q, column tj
+    float mv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) mv[q] = a.M[(ti + q) * kDstN + tj];
+    // S (symmetric, so also S^T) and f^T: sX[x][y] = f(node y + 1, x + 1)
+    for (int i = tid; i < kDstN * kDstN; i += 1024) {
+        const int y = i >> 6, x = i & 63;
+        sS[y * kDstLd + x] = a.S[i];
+        sX[x * kDstLd + y] =
+            (x < kDstN - 1 && y < kDstN - 1) ? (float)a.f[r][(size_t)(y + 1) * a.pitch + x + 1] : 0.f;
+    }
+    __syncthreads();
+    dst_v4f d = dst_tile(sS, sX);  // Y = S F
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sY[(ti + q) * kDstLd + tj] = d[q];
+    __syncthreads();
+    d = dst_tile(sY, sS);  // X = M o (Y S), stored transposed for the next product
+    __syncthreads();       // every read of the operands is done before sX is rewritten
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sX[tj * kDstLd + ti + q] = mv[q] * d[q];
+    __syncthreads();
+    d = dst_tile(sS, sX);  // Y = S X
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sY[(ti + q) * kDstLd + tj] = d[q];
+    __syncthreads();
+    d = dst_tile(sY, sS);  // U = Y S
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sX[(ti + q) * kDstLd + tj] = d[q];
+    __syncthreads();
+    for (int i = tid; i < (kDstN + 1) * (kDstN + 1); i += 1024) {
+        const int y = i / (kDstN + 1), x = i - y * (kDstN + 1);
+        const bool in = x >= 1 && x <= kDstN - 1 && y >= 1 && y <= kDstN - 1;
+        a.u_out[r][(size_t)y * a.pitch + x] = (E)(in ? sX[(y - 1) * kDstLd + x - 1] : 0.f);
+    }
+}
+
 // k2 of the coarse-kernel levels: the top level (N <= 64, pitched) copied
 // densely, then full weighting level by level.  One block.
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_k2(int N, int pitch,
@@ -1347,17 +1429,31 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
         a.nu2 = c->cfg.nu_post;
         const double nodes = (double)(L.N + 1) * (L.N + 1);
         char nm[64];
-        // float sweeps when the coarse levels only correct a finer level
-        const bool f32 = WQ_COARSE_F32 && lc > 0;
-        std::snprintf(nm, sizeof nm, "k_mg_coarse<%s, %s, %s>", type_name(E()),
-                      f32 ? "float" : type_name(E()), helm ? "true" : "false");
-        ProfScope ps(c, nm, nodes * (eb * R + (a.u_init[0] ? eb * R : 0.0) + (helm ? 8.0 : 0.0) + eb * R));
-        if (f32) {
-            if (helm) WQ_KLAUNCH(ps, (k_mg_coarse<E, float, true>), dim3(R), dim3(kCoarseThreads), 0, s, a);
-            else WQ_KLAUNCH(ps, (k_mg_coarse<E, float, false>), dim3(R), dim3(kCoarseThreads), 0, s, a);
+        if (!helm && lc > 0 && L.N == kDstN) {  // exact Poisson coarse solve
+            DstArgs<E> d{};
+            d.pitch = L.pitch;
+            for (int r = 0; r < R; ++r) {
+                d.f[r] = F(lc, r);
+                d.u_out[r] = U(lc, r);
+            }
+            d.S = c->dst_S;
+            d.M = c->dst_M;
+            std::snprintf(nm, sizeof nm, "k_coarse_dst<%s>", type_name(E()));
+            ProfScope ps(c, nm, nodes * 2.0 * eb * R + 2.0 * 4.0 * kDstN * kDstN);
+            WQ_KLAUNCH(ps, k_coarse_dst<E>, dim3(R), dim3(1024), 0, s, d);
         } else {
-            if (helm) WQ_KLAUNCH(ps, (k_mg_coarse<E, E, true>), dim3(R), dim3(kCoarseThreads), 0, s, a);
-            else WQ_KLAUNCH(ps, (k_mg_coarse<E, E, false>), dim3(R), dim3(kCoarseThreads), 0, s, a);
+            // float sweeps when the coarse levels only correct a finer level
+            const bool f32 = WQ_COARSE_F32 && lc > 0;
+            std::snprintf(nm, sizeof nm, "k_mg_coarse<%s, %s, %s>", type_name(E()),
+                          f32 ? "float" : type_name(E()), helm ? "true" : "false");
+            ProfScope ps(c, nm, nodes * (eb * R + (a.u_init[0] ? eb * R : 0.0) + (helm ? 8.0 : 0.0) + eb * R));
+            if (f32) {
+                if (helm) WQ_KLAUNCH(ps, (k_mg_coarse<E, float, true>), dim3(R), dim3(kCoarseThreads), 0, s, a);
+                else WQ_KLAUNCH(ps, (k_mg_coarse<E, float, false>), dim3(R), dim3(kCoarseThreads), 0, s, a);
+            } else {
+                if (helm) WQ_KLAUNCH(ps, (k_mg_coarse<E, E, true>), dim3(R), dim3(kCoarseThreads), 0, s, a);
+                else WQ_KLAUNCH(ps, (k_mg_coarse<E, E, false>), dim3(R), dim3(kCoarseThreads), 0, s, a);
+            }
         }
     }
     for (int l = lc - 1; l >= 0; --l) {
@@ -1436,6 +1532,23 @@ void mixed_iteration(wandqs_ctx* c, int R, bool helm, const Hier<double>& hz, in
 }  // namespace
 
 int reg_tile_min_default() { return WQ_REG_TILE_MIN; }
+
+void dst_tables(double H, float* S, float* M) {
+    const double pi = 3.14159265358979323846;
+    for (int j = 0; j < kDstN; ++j)
+        for (int k = 0; k < kDstN; ++k) {
+            const bool in = j < kDstN - 1 && k < kDstN - 1;
+            S[j * kDstN + k] = in ? (float)std::sin(pi * (j + 1) * (k + 1) / kDstN) : 0.f;
+            double m = 0.0;
+            if (in) {
+                const double sj = std::sin(pi * (j + 1) / (2.0 * kDstN));
+                const double sk = std::sin(pi * (k + 1) / (2.0 * kDstN));
+                const double lambda = -(4.0 / (H * H)) * (sj * sj + sk * sk);
+                m = 1.0 / ((kDstN / 2.0) * (kDstN / 2.0) * lambda);
+            }
+            M[j * kDstN + k] = (float)m;
+        }
+}
 
 // Solve with the context's stop rule.  Tolerance mode (mg_rtol > 0) runs a batch
 // of V-cycles sized by the previous slice's count for this solve, reads the

@@ -180,6 +180,10 @@ struct wandqs_ctx {
     double* mom[6] = {};
     double* jz = nullptr;
     double* k2lev = nullptr;  // k2 of the coarse-kernel levels (dense, concatenated)
+    // exact Poisson solve on the 64^2 coarse level: sine-transform matrix S and
+    // the scaled inverse eigenvalues M, [64][64] float each (zero row/column 63)
+    float* dst_S = nullptr;
+    float* dst_M = nullptr;
     double* pa[2][4] = {};
     int32_t* pid[2] = {};
     int cur = 0;
@@ -230,6 +234,8 @@ namespace wq {
 size_t carve(wandqs_ctx* c, char* base);
 // smallest level that runs the register-tile pass kernels by default
 int reg_tile_min_default();
+// host tables of the 64^2 coarse-level Poisson solve (S and M, [64][64] each)
+void dst_tables(double H, float* S, float* M);
 
 // multigrid (mg.hip)
 wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const u[2],
