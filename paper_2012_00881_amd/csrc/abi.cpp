@@ -321,6 +321,8 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
     c->perm = (int32_t*)take(sizeof(int32_t) * P);
     c->cell_count = (int32_t*)take(sizeof(int32_t) * ncell);
     c->cell_start = (int32_t*)take(sizeof(int32_t) * (ncell + 1));
+    c->big_cells = (int32_t*)take(sizeof(int32_t) * ncell);
+    c->big_count = (int32_t*)take(sizeof(int32_t));
     c->scan_blk = (int32_t*)take(sizeof(int32_t) * c->n_scan_blocks);
     c->st = (double*)take(sizeof(double) * 8);
     c->vmax_part = (double*)take(sizeof(double) * c->n_push_blocks);

@@ -11,6 +11,8 @@
 // tile (plus the one-cell rim shared with the neighbouring tiles) sums its
 // particles' corner weights in registers, and each node adds its four cells'
 // corners from LDS in a fixed order.
+#include <algorithm>
+
 #include "wq_common.h"
 
 namespace wq {
@@ -57,8 +59,9 @@ __device__ __forceinline__ void key_run(int key, bool valid, int& head, int& len
 
 __global__ void k_cell_key(int64_t P, const double* __restrict__ x, const double* __restrict__ y,
                            double L, double h, int N, int32_t* __restrict__ key,
-                           int32_t* __restrict__ count) {
+                           int32_t* __restrict__ count, int32_t* __restrict__ big_n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *big_n = 0;  // list of crowded cells for k_cell_sort_big
     const bool valid = i < P;
     int k = -1;
     if (valid) {
@@ -154,12 +157,21 @@ __global__ void k_scatter(int64_t P, const int32_t* __restrict__ key,
     if (valid) perm[start[k] + top - len + (lane - head)] = (int32_t)i;
 }
 
-// Order each cell's particles by permanent ID (insertion sort; cells hold a few).
+// Order each cell's particles by permanent ID: an insertion sort by one thread
+// for cells of up to kSmallCell particles; crowded cells (blowout) go on a list
+// for k_cell_sort_big.
+constexpr int kSmallCell = 16;
+constexpr int kBigCellLds = 4096;
 __global__ void k_cell_sort(int ncell, const int32_t* __restrict__ start,
-                            int32_t* __restrict__ perm, const int32_t* __restrict__ id) {
+                            int32_t* __restrict__ perm, const int32_t* __restrict__ id,
+                            int32_t* __restrict__ big, int32_t* __restrict__ big_n) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
     const int s = start[c], e = start[c + 1];
+    if (e - s > kSmallCell) {
+        big[atomicAdd(big_n, 1)] = c;
+        return;
+    }
     for (int i = s + 1; i < e; ++i) {
         const int32_t p = perm[i];
         const int32_t pid = id[p];
@@ -169,6 +181,39 @@ __global__ void k_cell_sort(int ncell, const int32_t* __restrict__ start,
             --j;
         }
         perm[j + 1] = p;
+    }
+}
+
+// Crowded cells, one workgroup each: a particle's place is the number of the
+// cell's particles with a smaller ID (IDs are unique).  The new order goes to
+// tmp first, so that every rank is counted on the old one.
+__global__ __launch_bounds__(256) void k_cell_sort_big(const int32_t* __restrict__ start,
+                                                       int32_t* __restrict__ perm,
+                                                       const int32_t* __restrict__ id,
+                                                       int32_t* __restrict__ tmp,
+                                                       const int32_t* __restrict__ big,
+                                                       const int32_t* __restrict__ big_n) {
+    __shared__ int32_t sid[kBigCellLds];
+    const int nbig = *big_n;
+    for (int b = blockIdx.x; b < nbig; b += gridDim.x) {
+        const int c = big[b];
+        const int s = start[c], n = start[c + 1] - s;
+        const bool lds = n <= kBigCellLds;
+        if (lds)
+            for (int i = threadIdx.x; i < n; i += blockDim.x) sid[i] = id[perm[s + i]];
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const int32_t v = lds ? sid[i] : id[perm[s + i]];
+            int r = 0;
+            if (lds)
+                for (int j = 0; j < n; ++j) r += sid[j] < v;
+            else
+                for (int j = 0; j < n; ++j) r += id[perm[s + j]] < v;
+            tmp[s + r] = perm[s + i];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) perm[s + i] = tmp[s + i];
+        __syncthreads();
     }
 }
 
@@ -471,7 +516,8 @@ wandqs_status slice_sort(wandqs_ctx* c) {
     {
         ProfScope ps(c, "k_cell_key", (double)c->P * 20.0 + (double)ncell * 8.0);
         WQ_KLAUNCH(ps, k_cell_key, dim3(blocks_for(c->P, 256)), dim3(256), 0, s, c->P,
-                           c->pa[a][0], c->pa[a][1], c->L, c->h, c->N, c->key, c->cell_count);
+                           c->pa[a][0], c->pa[a][1], c->L, c->h, c->N, c->key, c->cell_count,
+                           c->big_count);
     }
     const int nb = (ncell + kScanBlock - 1) / kScanBlock;
     {
@@ -497,7 +543,12 @@ wandqs_status slice_sort(wandqs_ctx* c) {
     {
         ProfScope ps(c, "k_cell_sort", (double)c->P * 12.0 + (double)ncell * 4.0);
         WQ_KLAUNCH(ps, k_cell_sort, dim3(blocks_for(ncell, 256)), dim3(256), 0, s, ncell,
-                           c->cell_start, c->perm, c->pid[a]);
+                           c->cell_start, c->perm, c->pid[a], c->big_cells, c->big_count);
+    }
+    {  // the key array is free after the scatter: scratch for the crowded cells
+        ProfScope ps(c, "k_cell_sort_big", 0.0);
+        WQ_KLAUNCH(ps, k_cell_sort_big, dim3(std::min(ncell, 512)), dim3(256), 0, s,
+                           c->cell_start, c->perm, c->pid[a], c->key, c->big_cells, c->big_count);
     }
     {
         ProfScope ps(c, "k_permute", (double)c->P * 76.0);

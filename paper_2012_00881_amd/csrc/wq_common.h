@@ -189,6 +189,8 @@ struct wandqs_ctx {
     int cur = 0;
     int32_t *key = nullptr, *perm = nullptr, *cell_count = nullptr, *cell_start = nullptr,
             *scan_blk = nullptr;
+    int32_t* big_cells = nullptr;  // [N*N] cells too crowded for one thread's sort
+    int32_t* big_count = nullptr;  // their number
     int n_scan_blocks = 0;
     double* st = nullptr;  // [xi, dxi, xi of fields, of fields_prev, of fields_prev2, of fields_prev3]
     double* vmax_part = nullptr;  // per push block
