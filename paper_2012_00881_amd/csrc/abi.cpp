@@ -324,7 +324,7 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
     c->big_cells = (int32_t*)take(sizeof(int32_t) * ncell);
     c->big_count = (int32_t*)take(sizeof(int32_t));
     c->scan_blk = (int32_t*)take(sizeof(int32_t) * c->n_scan_blocks);
-    c->st = (double*)take(sizeof(double) * 8);
+    c->st = (double*)take(sizeof(double) * 16);  // [xi, dxi, 4 slice positions, -, -, guess weights]
     c->vmax_part = (double*)take(sizeof(double) * c->n_push_blocks);
     c->flags = (int32_t*)take(sizeof(int32_t) * 4);
     c->norm_part = (double*)take(sizeof(double) * kMaxSlots * kNormVec * (size_t)c->max_tiles);

@@ -182,15 +182,12 @@ struct FieldPtrs {
     double* out[5];
 };
 
-__global__ void k_extrapolate(int N, int pitch, const double* __restrict__ st, FieldPtrs f,
-                              int order) {
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = blockIdx.y;
-    if (a > N) return;
-    const size_t g = (size_t)b * pitch + a;
+// Lagrange weights of the guess through the stored slices (one thread): the
+// order drops while two of the points coincide; wts = [order, w1, w2, w3].
+__global__ void k_guess_weights(const double* __restrict__ st, int order, double* __restrict__ wts) {
+    if (threadIdx.x != 0) return;
     const double xi = st[0];
     const double x[4] = {st[2], st[3], st[4], st[5]};
-    // drop to a lower order if two of the points coincide
     for (bool ok = false; !ok && order > 0;) {
         ok = true;
         for (int i = 0; i <= order && ok; ++i)
@@ -205,14 +202,27 @@ __global__ void k_extrapolate(int N, int pitch, const double* __restrict__ st, F
             if (j != i) l *= (xi - x[j]) / (x[i] - x[j]);
         w[i] = l;
     }
+    wts[0] = (double)order;
+    wts[1] = w[1];
+    wts[2] = w[2];
+    wts[3] = w[3];
+}
+
+__global__ void k_extrapolate(int N, int pitch, const double* __restrict__ wts, FieldPtrs f) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (a > N) return;
+    const size_t g = (size_t)b * pitch + a;
+    const int order = (int)wts[0];
+    const double w1 = wts[1], w2 = wts[2], w3 = wts[3];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
         const double u = f.u[k][g];
         double v = u;
-        if (order == 1) v = u + w[1] * (f.p1[k][g] - u);
-        if (order == 2) v = u + (w[1] * (f.p1[k][g] - u) + w[2] * (f.p2[k][g] - u));
+        if (order == 1) v = u + w1 * (f.p1[k][g] - u);
+        if (order == 2) v = u + (w1 * (f.p1[k][g] - u) + w2 * (f.p2[k][g] - u));
         if (order == 3)
-            v = u + (w[1] * (f.p1[k][g] - u) + w[2] * (f.p2[k][g] - u) + w[3] * (f.p3[k][g] - u));
+            v = u + (w1 * (f.p1[k][g] - u) + w2 * (f.p2[k][g] - u) + w3 * (f.p3[k][g] - u));
         f.out[k][g] = v;
     }
 }
@@ -317,10 +327,15 @@ wandqs_status extrapolate_guess(wandqs_ctx* c, int order) {
         f.out[k] = oldest[k];
     }
     order = order < 0 ? 0 : (order > kGuessMax - 1 ? kGuessMax - 1 : order);
+    double* wts = c->st + 8;
+    {
+        ProfScope ps(c, "k_guess_weights", 80.0);
+        WQ_KLAUNCH(ps, k_guess_weights, dim3(1), dim3(64), 0, c->stream, c->st, order, wts);
+    }
     {
         ProfScope ps(c, "k_extrapolate", (double)(c->N + 1) * (c->N + 1) * 5 * 8.0 * (order + 2));
         WQ_KLAUNCH(ps, k_extrapolate, node_grid(c->N), dim3(128), 0, c->stream, c->N,
-                   c->lev[0].pitch, c->st, f, order);
+                   c->lev[0].pitch, wts, f);
     }
     WQ_LAUNCH_CHECK();
     for (int k = 0; k < 5; ++k) {  // oldest <- ... <- prev <- u <- guess

@@ -413,7 +413,10 @@ __global__ __launch_bounds__(tile_threads<T>()) void k_mg_up(UpArgs<E> a) {
 // lane by DPP wave shifts, vertical ones from the lane's own rows; the rows at
 // wavefront boundaries go through LDS once per half sweep.  The arithmetic and
 // its order are those of the LDS tile kernels above: both give the same bits.
-constexpr int kRegRows = 4;  // rows per wavefront (even)
+#ifndef WQ_REG_ROWS
+#define WQ_REG_ROWS 4
+#endif
+constexpr int kRegRows = WQ_REG_ROWS;  // rows per wavefront (even)
 #ifndef WQ_REG_WAVES
 #define WQ_REG_WAVES 8
 #endif

@@ -327,7 +327,8 @@ __global__ __launch_bounds__(256) void k_deposit_jT(int N, double L, double h, d
                 const double dy = (y[k] + L) / h - gb;
                 const double gi = 1.0 + cic_gather(p00, p10, p01, p11, dx, dy);
                 bad |= !(gi > 0.0);
-                const double vx = px[k] / gi, vy = py[k] / gi;
+                const double ig = 1.0 / gi;
+                const double vx = px[k] * ig, vy = py[k] * ig;
                 const double q[M] = {vx, vy, vx * vx, vx * vy, vy * vy};
                 const double w[4] = {(1.0 - dx) * (1.0 - dy), dx * (1.0 - dy), (1.0 - dx) * dy,
                                      dx * dy};
@@ -361,20 +362,21 @@ __global__ __launch_bounds__(256) void k_deposit_jT(int N, double L, double h, d
     }
 }
 
-// d psi / dx at node (a, b): central inside, one-sided on the boundary columns.
-__device__ __forceinline__ double grad_x(const double* psi, int pitch, int N, double h, int a,
-                                         int b) {
+// d psi / dx at node (a, b): central inside, one-sided on the boundary columns
+// (ih = 1/h, ih2 = 1/(2h)).
+__device__ __forceinline__ double grad_x(const double* psi, int pitch, int N, double ih,
+                                         double ih2, int a, int b) {
     const size_t r = (size_t)b * pitch;
-    if (a == 0) return (psi[r + 1] - psi[r]) / h;
-    if (a == N) return (psi[r + N] - psi[r + N - 1]) / h;
-    return (psi[r + a + 1] - psi[r + a - 1]) / (2.0 * h);
+    if (a == 0) return (psi[r + 1] - psi[r]) * ih;
+    if (a == N) return (psi[r + N] - psi[r + N - 1]) * ih;
+    return (psi[r + a + 1] - psi[r + a - 1]) * ih2;
 }
 
-__device__ __forceinline__ double grad_y(const double* psi, int pitch, int N, double h, int a,
-                                         int b) {
-    if (b == 0) return (psi[(size_t)pitch + a] - psi[a]) / h;
-    if (b == N) return (psi[(size_t)N * pitch + a] - psi[(size_t)(N - 1) * pitch + a]) / h;
-    return (psi[(size_t)(b + 1) * pitch + a] - psi[(size_t)(b - 1) * pitch + a]) / (2.0 * h);
+__device__ __forceinline__ double grad_y(const double* psi, int pitch, int N, double ih,
+                                         double ih2, int a, int b) {
+    if (b == 0) return (psi[(size_t)pitch + a] - psi[a]) * ih;
+    if (b == N) return (psi[(size_t)N * pitch + a] - psi[(size_t)(N - 1) * pitch + a]) * ih;
+    return (psi[(size_t)(b + 1) * pitch + a] - psi[(size_t)(b - 1) * pitch + a]) * ih2;
 }
 
 // Boris-like push over dxi with the fields frozen at this slice (eqs. (6)-(7)):
@@ -398,24 +400,28 @@ __global__ __launch_bounds__(kPushThreads) void k_push(
         cic(xi_, L, h, N, a, dx);
         cic(yi, L, h, N, b, dy);
         const size_t g = (size_t)b * pitch + a;
+        const double ih = 1.0 / h, ih2 = 0.5 * ih;
         const double g_i =
             1.0 + cic_gather(psi[g], psi[g + 1], psi[g + pitch], psi[g + pitch + 1], dx, dy);
-        const double Gx = cic_gather(grad_x(psi, pitch, N, h, a, b), grad_x(psi, pitch, N, h, a + 1, b),
-                                     grad_x(psi, pitch, N, h, a, b + 1),
-                                     grad_x(psi, pitch, N, h, a + 1, b + 1), dx, dy);
-        const double Gy = cic_gather(grad_y(psi, pitch, N, h, a, b), grad_y(psi, pitch, N, h, a + 1, b),
-                                     grad_y(psi, pitch, N, h, a, b + 1),
-                                     grad_y(psi, pitch, N, h, a + 1, b + 1), dx, dy);
+        const double Gx = cic_gather(grad_x(psi, pitch, N, ih, ih2, a, b),
+                                     grad_x(psi, pitch, N, ih, ih2, a + 1, b),
+                                     grad_x(psi, pitch, N, ih, ih2, a, b + 1),
+                                     grad_x(psi, pitch, N, ih, ih2, a + 1, b + 1), dx, dy);
+        const double Gy = cic_gather(grad_y(psi, pitch, N, ih, ih2, a, b),
+                                     grad_y(psi, pitch, N, ih, ih2, a + 1, b),
+                                     grad_y(psi, pitch, N, ih, ih2, a, b + 1),
+                                     grad_y(psi, pitch, N, ih, ih2, a + 1, b + 1), dx, dy);
         const double bx = cic_gather(Bx[g], Bx[g + 1], Bx[g + pitch], Bx[g + pitch + 1], dx, dy);
         const double by = cic_gather(By[g], By[g + 1], By[g + pitch], By[g + pitch + 1], dx, dy);
         const double bz = cic_gather(Bz[g], Bz[g + 1], Bz[g + pitch], Bz[g + pitch + 1], dx, dy);
 
-        const double gamma = (1.0 + pxi * pxi + pyi * pyi + g_i * g_i) / (2.0 * g_i);
-        const double Fx = gamma * Gx / g_i - by;
-        const double Fy = gamma * Gy / g_i + bx;
+        const double ig = 1.0 / g_i;
+        const double gamma = (1.0 + pxi * pxi + pyi * pyi + g_i * g_i) * (0.5 * ig);
+        const double Fx = gamma * Gx * ig - by;
+        const double Fy = gamma * Gy * ig + bx;
         const double mx = pxi + 0.5 * dxi * Fx;
         const double my = pyi + 0.5 * dxi * Fy;
-        const double t = bz * dxi / (2.0 * g_i);
+        const double t = bz * dxi * (0.5 * ig);
         const double s = 2.0 * t / (1.0 + t * t);
         const double qx = mx - t * my;
         const double qy = my + t * mx;
@@ -423,8 +429,8 @@ __global__ __launch_bounds__(kPushThreads) void k_push(
         const double ry = my + s * qx;
         pxi = rx + 0.5 * dxi * Fx;
         pyi = ry + 0.5 * dxi * Fy;
-        xi_ = xi_ + dxi * pxi / g_i;
-        yi = yi + dxi * pyi / g_i;
+        xi_ = xi_ + dxi * pxi * ig;
+        yi = yi + dxi * pyi * ig;
         if (xi_ > L) { xi_ = 2.0 * L - xi_; pxi = -pxi; }
         if (xi_ < -L) { xi_ = -2.0 * L - xi_; pxi = -pxi; }
         if (yi > L) { yi = 2.0 * L - yi; pyi = -pyi; }
@@ -433,7 +439,7 @@ __global__ __launch_bounds__(kPushThreads) void k_push(
         y[i] = yi;
         px[i] = pxi;
         py[i] = pyi;
-        v = sqrt(pxi * pxi + pyi * pyi) / g_i;
+        v = sqrt(pxi * pxi + pyi * pyi) / g_i;  // decides the step: same arithmetic as Algorithm 1
     }
     for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
