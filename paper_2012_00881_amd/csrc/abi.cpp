@@ -287,9 +287,16 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
         int tot = 0;
         for (int n = c->lev[c->lc].N; n >= 2; n /= 2) tot += (n + 1) * (n + 1);
         c->k2lev = (double*)take(sizeof(double) * (size_t)tot);
+        c->k2levf = (float*)take(sizeof(float) * (size_t)tot);
+        c->idlevf = (float*)take(sizeof(float) * (size_t)tot);
     }
     c->dst_S = (float*)take(sizeof(float) * 64 * 64);
     c->dst_M = (float*)take(sizeof(float) * 64 * 64);
+    if (dst128_used(c)) {
+        c->dst2_S = (float*)take(sizeof(float) * 128 * 128);
+        c->dst2_M = (float*)take(sizeof(float) * 128 * 128);
+        c->dst2_X = (float*)take(sizeof(float) * 2 * 128 * 128);
+    }
     for (int l = 1; l <= c->lc; ++l) {
         Level& L = c->lev[l];
         for (int r = 0; r < 2; ++r) {
@@ -561,10 +568,17 @@ wandqs_status wandqs_init(const wandqs_config* cfg, int32_t n_slices, void* d_wo
                     ids[i] = (int32_t)i;
                 }
     const double st0[6] = {0.0, cfg->dxi0, 0.0, 0.0, 0.0, 0.0};
-    std::vector<float> dstS(64 * 64), dstM(64 * 64);
-    wq::dst_tables(c->lev[c->lc].h, dstS.data(), dstM.data());
+    std::vector<float> dstS(64 * 64), dstM(64 * 64), dst2S, dst2M;
+    wq::dst_tables(64, c->lev[c->lc].h, dstS.data(), dstM.data());
+    if (wq::dst128_used(c)) {
+        dst2S.resize(128 * 128);
+        dst2M.resize(128 * 128);
+        wq::dst_tables(128, c->lev[c->lc - 1].h, dst2S.data(), dst2M.data());
+    }
     bool ok = hipMemcpyAsync(c->dst_S, dstS.data(), sizeof(float) * dstS.size(), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
               hipMemcpyAsync(c->dst_M, dstM.data(), sizeof(float) * dstM.size(), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+              (dst2S.empty() || hipMemcpyAsync(c->dst2_S, dst2S.data(), sizeof(float) * dst2S.size(), hipMemcpyHostToDevice, c->stream) == hipSuccess) &&
+              (dst2M.empty() || hipMemcpyAsync(c->dst2_M, dst2M.data(), sizeof(float) * dst2M.size(), hipMemcpyHostToDevice, c->stream) == hipSuccess) &&
               hipMemcpyAsync(c->pa[0][0], host.data(), sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
               hipMemcpyAsync(c->pa[0][1], host.data() + c->P, sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
               hipMemcpyAsync(c->pid[0], ids.data(), sizeof(int32_t) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&

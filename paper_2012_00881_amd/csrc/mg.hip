@@ -806,6 +806,8 @@ struct CoarseArgs {
     const E* f[2];
     const E* u_init[2];   // nullptr: zero initial guess
     const double* k2lev;  // Helmholtz: k2 of every level N..2, dense, concatenated
+    const float* k2levf;  // the same in float, and 1 / (4 + h_l^2 k2) in float
+    const float* idlevf;
     E* u_out[2];
     int ncycles, nu1, nu2;
 };
@@ -979,7 +981,25 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
             }
         }
     }
-    if (HELM)
+    if (HELM && FAST)  // k2 and 1/D of every level, made once per solve by k_coarse_k2
+        for (int base = 0; base < tot; base += kB * kCoarseThreads) {
+            float kv[kB], dv[kB];
+#pragma unroll
+            for (int b = 0; b < kB; ++b) {
+                const int i = base + b * kCoarseThreads + tid;
+                kv[b] = i < tot ? a.k2levf[i] : 0.f;
+                dv[b] = i < tot ? a.idlevf[i] : 0.f;
+            }
+#pragma unroll
+            for (int b = 0; b < kB; ++b) {
+                const int i = base + b * kCoarseThreads + tid;
+                if (i < tot) {
+                    sk[i] = (C)kv[b];
+                    siD[i] = (C)dv[b];
+                }
+            }
+        }
+    else if (HELM)
         for (int base = 0; base < tot; base += kB * kCoarseThreads) {
             double kv[kB];
 #pragma unroll
@@ -994,16 +1014,6 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
             }
         }
     __syncthreads();
-    if (HELM && FAST) {  // 1 / (4 + h^2 k2) of every level
-        for (int l = 0; l < nl; ++l) {
-            const double hl = a.h * (double)(1 << l);
-            const C h2 = (C)(hl * hl);
-            const int n1 = (Ns[l] + 1) * (Ns[l] + 1);
-            for (int i = tid; i < n1; i += kCoarseThreads)
-                siD[off[l] + i] = C(1) / (C(4) + h2 * sk[off[l] + i]);
-        }
-        __syncthreads();
-    }
 
     auto down = [&](int l) {
         const double hl = a.h * (double)(1 << l);
@@ -1092,12 +1102,24 @@ __global__ __launch_bounds__(1024) void k_coarse_dst(DstArgs<E> a) {
     float mv[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) mv[q] = a.M[(ti + q) * kDstN + tj];
-    // S (symmetric, so also S^T) and f^T: sX[x][y] = f(node y + 1, x + 1)
-    for (int i = tid; i < kDstN * kDstN; i += 1024) {
-        const int y = i >> 6, x = i & 63;
-        sS[y * kDstLd + x] = a.S[i];
-        sX[x * kDstLd + y] =
-            (x < kDstN - 1 && y < kDstN - 1) ? (float)a.f[r][(size_t)(y + 1) * a.pitch + x + 1] : 0.f;
+    // S (symmetric, so also S^T) and f^T: sX[x][y] = f(node y + 1, x + 1); every
+    // load is issued before the first store, so their latencies overlap
+    {
+        constexpr int kIt = kDstN * kDstN / 1024;
+        float sv[kIt], fv[kIt];
+#pragma unroll
+        for (int t = 0; t < kIt; ++t) {
+            const int i = tid + t * 1024, y = i >> 6, x = i & 63;
+            sv[t] = a.S[i];
+            fv[t] = (x < kDstN - 1 && y < kDstN - 1) ? (float)a.f[r][(size_t)(y + 1) * a.pitch + x + 1]
+                                                     : 0.f;
+        }
+#pragma unroll
+        for (int t = 0; t < kIt; ++t) {
+            const int i = tid + t * 1024, y = i >> 6, x = i & 63;
+            sS[y * kDstLd + x] = sv[t];
+            sX[x * kDstLd + y] = fv[t];
+        }
     }
     __syncthreads();
     dst_v4f d = dst_tile(sS, sX);  // Y = S F
@@ -1125,11 +1147,125 @@ __global__ __launch_bounds__(1024) void k_coarse_dst(DstArgs<E> a) {
     }
 }
 
+// The same exact solve on the 128^2 level when it lies below a finer level:
+// too much work for one workgroup, so it runs as two launches of 8 workgroups
+// (per right-hand side) holding 16 rows each.  The first forms the rows of
+// X = M o (S f S) (S_jk = sin(pi (j+1)(k+1)/128), S S = 64 I,
+// M = 1 / (64^2 lambda)), the second the rows of u = S X S.  8 wavefronts per
+// workgroup, one 16 x 16 output tile each, fp32 MFMA.
+#ifndef WQ_DST128
+#define WQ_DST128 1
+#endif
+constexpr int kD2 = 128;
+constexpr int kD2Ld = 132;  // LDS row stride
+constexpr int kD2Rows = 16;
+
+template <typename E>
+struct Dst2Args {
+    int pitch;
+    const E* f[2];
+    E* u_out[2];
+    const float* S;
+    const float* M;
+    float* X;  // [R][128][128]
+};
+
+// 16 x 16 tile (rows 0..15 of A, columns j0.. of B) of A B: A row-major with
+// stride kD2Ld, B given transposed (Bt[j][k] = B[k][j]), inner dimension 128.
+__device__ __forceinline__ dst_v4f d2_tile(const float* A, const float* Bt, int j0) {
+    const int lane = threadIdx.x & 63;
+    const float* a = A + (lane & 15) * kD2Ld + (lane >> 4);
+    const float* b = Bt + (j0 + (lane & 15)) * kD2Ld + (lane >> 4);
+    dst_v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
+    for (int s = 0; s < kD2 / 4; ++s)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * s], b[4 * s], acc, 0, 0, 0);
+    return acc;
+}
+
+template <typename E>
+__global__ __launch_bounds__(512) void k_dst2_fwd(Dst2Args<E> a) {
+    __shared__ float sS[kD2 * kD2Ld];
+    __shared__ float sFt[kD2 * kD2Ld];
+    __shared__ float sT[kD2Rows * kD2Ld];
+    const int i0 = kD2Rows * blockIdx.x, r = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int j0 = 16 * w, ti = 4 * (lane >> 4), tj = j0 + (lane & 15);
+    float mv[4];  // this lane's entries of M, loaded ahead
+#pragma unroll
+    for (int q = 0; q < 4; ++q) mv[q] = a.M[(i0 + ti + q) * kD2 + tj];
+    // every load is issued before the first store (one round trip): 32 per
+    // thread; a row of f is 127 interior nodes, read as doubles or floats
+    constexpr int kIt = kD2 * kD2 / 512;
+    float sv[kIt], fv[kIt];
+#pragma unroll
+    for (int t = 0; t < kIt; ++t) {
+        const int i = tid + t * 512, y = i >> 7, x = i & (kD2 - 1);
+        sv[t] = a.S[i];
+        const size_t g = (size_t)(y + 1) * a.pitch + x + 1;
+        fv[t] = (float)a.f[r][(x < kD2 - 1 && y < kD2 - 1) ? g : 0];
+    }
+#pragma unroll
+    for (int t = 0; t < kIt; ++t) {
+        const int i = tid + t * 512, y = i >> 7, x = i & (kD2 - 1);
+        sS[y * kD2Ld + x] = sv[t];
+        sFt[x * kD2Ld + y] = (x < kD2 - 1 && y < kD2 - 1) ? fv[t] : 0.f;
+    }
+    __syncthreads();
+    dst_v4f d = d2_tile(sS + i0 * kD2Ld, sFt, j0);  // T = S[i0 .. i0+15, :] f
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sT[(ti + q) * kD2Ld + tj] = d[q];
+    __syncthreads();
+    d = d2_tile(sT, sS, j0);  // T S
+    float* X = a.X + (size_t)r * kD2 * kD2;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) X[(i0 + ti + q) * kD2 + tj] = mv[q] * d[q];
+}
+
+template <typename E>
+__global__ __launch_bounds__(512) void k_dst2_inv(Dst2Args<E> a) {
+    __shared__ float sS[kD2 * kD2Ld];
+    __shared__ float sXt[kD2 * kD2Ld];
+    __shared__ float sY[kD2Rows * kD2Ld];
+    const int i0 = kD2Rows * blockIdx.x, r = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const float* X = a.X + (size_t)r * kD2 * kD2;
+    constexpr int kIt = kD2 * kD2 / 512;
+    float sv[kIt], xv[kIt];
+#pragma unroll
+    for (int t = 0; t < kIt; ++t) {
+        const int i = tid + t * 512;
+        sv[t] = a.S[i];
+        xv[t] = X[i];
+    }
+#pragma unroll
+    for (int t = 0; t < kIt; ++t) {
+        const int i = tid + t * 512, y = i >> 7, x = i & (kD2 - 1);
+        sS[y * kD2Ld + x] = sv[t];
+        sXt[x * kD2Ld + y] = xv[t];
+    }
+    __syncthreads();
+    const int j0 = 16 * w, ti = 4 * (lane >> 4), tj = j0 + (lane & 15);
+    dst_v4f d = d2_tile(sS + i0 * kD2Ld, sXt, j0);  // Y = S[i0 .., :] X
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sY[(ti + q) * kD2Ld + tj] = d[q];
+    __syncthreads();
+    d = d2_tile(sY, sS, j0);  // u = Y S; row and column 127 of S are 0, so node 128 gets 0
+    E* u = a.u_out[r];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) u[(size_t)(i0 + ti + q + 1) * a.pitch + tj + 1] = (E)d[q];
+    if (tid < kD2Rows) u[(size_t)(i0 + tid + 1) * a.pitch] = E(0);  // column 0
+    if (blockIdx.x == 0)
+        for (int x = tid; x <= kD2; x += 512) u[x] = E(0);  // row 0
+}
+
 // k2 of the coarse-kernel levels: the top level (N <= 64, pitched) copied
 // densely, then full weighting level by level.  One block.
-__global__ __launch_bounds__(kCoarseThreads) void k_coarse_k2(int N, int pitch,
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_k2(int N, int pitch, double h,
                                                               const double* __restrict__ k2top,
-                                                              double* __restrict__ out) {
+                                                              double* __restrict__ out,
+                                                              float* __restrict__ outf,
+                                                              float* __restrict__ idf) {
     for (int i = threadIdx.x; i < (N + 1) * (N + 1); i += kCoarseThreads) {
         const int y = i / (N + 1), x = i - y * (N + 1);
         const bool bnd = x == 0 || y == 0 || x == N || y == N;
@@ -1154,6 +1290,18 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_k2(int N, int pitch,
         }
         __syncthreads();
         off += (nf + 1) * (nf + 1);
+    }
+    // float copies and 1 / (4 + h_l^2 k2) for the coarse kernel's FP32 sweeps
+    off = 0;
+    for (int n = N, l = 0; n >= 2; n /= 2, ++l) {
+        const double hl = h * (double)(1 << l);
+        const float h2 = (float)(hl * hl);
+        for (int i = threadIdx.x; i < (n + 1) * (n + 1); i += kCoarseThreads) {
+            const float kf = (float)out[off + i];
+            outf[off + i] = kf;
+            idf[off + i] = 1.f / (4.f + h2 * kf);
+        }
+        off += (n + 1) * (n + 1);
     }
 }
 
@@ -1383,7 +1531,10 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
     auto U = [&](int l, int r) { return l == 0 ? hz.u0[r] : lev_u<E>(c->lev[l], r); };
     auto F = [&](int l, int r) { return l == 0 ? hz.f0[r] : lev_f<E>(c->lev[l], r); };
     auto K = [&](int l) { return l == 0 ? hz.k2 : (const double*)c->lev[l].k2; };
-    for (int l = 0; l < lc; ++l) {
+    // Poisson: the V-cycle ends with the exact solve on the 128^2 level when
+    // that lies below a finer level
+    const int lb = (!helm && dst128_used(c)) ? lc - 1 : lc;
+    for (int l = 0; l < lb; ++l) {
         wq::Level& L = c->lev[l];
         DownArgs<E> a{};
         a.N = L.N;
@@ -1415,7 +1566,31 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
                                      eb * R + eb * R / 4));
         down_pass<E>(R, helm, a, c->cfg.nu_pre, g, s, ps);
     }
-    {
+    if (lb < lc) {
+        wq::Level& L = c->lev[lb];
+        Dst2Args<E> d{};
+        d.pitch = L.pitch;
+        for (int r = 0; r < R; ++r) {
+            d.f[r] = F(lb, r);
+            d.u_out[r] = U(lb, r);
+        }
+        d.S = c->dst2_S;
+        d.M = c->dst2_M;
+        d.X = c->dst2_X;
+        const double nodes = (double)(L.N + 1) * (L.N + 1);
+        const dim3 g(kD2 / kD2Rows, R);
+        char nm[64];
+        std::snprintf(nm, sizeof nm, "k_dst2_fwd<%s>", type_name(E()));
+        {
+            ProfScope ps(c, nm, nodes * eb * R + 4.0 * kD2 * kD2 * (2.0 + R));
+            WQ_KLAUNCH(ps, k_dst2_fwd<E>, g, dim3(512), 0, s, d);
+        }
+        std::snprintf(nm, sizeof nm, "k_dst2_inv<%s>", type_name(E()));
+        {
+            ProfScope ps(c, nm, nodes * eb * R + 4.0 * kD2 * kD2 * (1.0 + R));
+            WQ_KLAUNCH(ps, k_dst2_inv<E>, g, dim3(512), 0, s, d);
+        }
+    } else {
         wq::Level& L = c->lev[lc];
         CoarseArgs<E> a{};
         a.N = L.N;
@@ -1427,6 +1602,8 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
             a.u_out[r] = U(lc, r);
         }
         a.k2lev = helm ? c->k2lev : nullptr;
+        a.k2levf = helm ? c->k2levf : nullptr;
+        a.idlevf = helm ? c->idlevf : nullptr;
         a.ncycles = WQ_COARSE_CYCLES;
         a.nu1 = c->cfg.nu_pre;
         a.nu2 = c->cfg.nu_post;
@@ -1459,7 +1636,7 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
             }
         }
     }
-    for (int l = lc - 1; l >= 0; --l) {
+    for (int l = lb - 1; l >= 0; --l) {
         wq::Level& L = c->lev[l];
         UpArgs<E> a{};
         a.N = L.N;
@@ -1536,21 +1713,25 @@ void mixed_iteration(wandqs_ctx* c, int R, bool helm, const Hier<double>& hz, in
 
 int reg_tile_min_default() { return WQ_REG_TILE_MIN; }
 
-void dst_tables(double H, float* S, float* M) {
+void dst_tables(int n, double H, float* S, float* M) {
     const double pi = 3.14159265358979323846;
-    for (int j = 0; j < kDstN; ++j)
-        for (int k = 0; k < kDstN; ++k) {
-            const bool in = j < kDstN - 1 && k < kDstN - 1;
-            S[j * kDstN + k] = in ? (float)std::sin(pi * (j + 1) * (k + 1) / kDstN) : 0.f;
+    for (int j = 0; j < n; ++j)
+        for (int k = 0; k < n; ++k) {
+            const bool in = j < n - 1 && k < n - 1;
+            S[j * n + k] = in ? (float)std::sin(pi * (j + 1) * (k + 1) / n) : 0.f;
             double m = 0.0;
             if (in) {
-                const double sj = std::sin(pi * (j + 1) / (2.0 * kDstN));
-                const double sk = std::sin(pi * (k + 1) / (2.0 * kDstN));
+                const double sj = std::sin(pi * (j + 1) / (2.0 * n));
+                const double sk = std::sin(pi * (k + 1) / (2.0 * n));
                 const double lambda = -(4.0 / (H * H)) * (sj * sj + sk * sk);
-                m = 1.0 / ((kDstN / 2.0) * (kDstN / 2.0) * lambda);
+                m = 1.0 / ((n / 2.0) * (n / 2.0) * lambda);
             }
-            M[j * kDstN + k] = (float)m;
+            M[j * n + k] = (float)m;
         }
+}
+
+bool dst128_used(const wandqs_ctx* c) {
+    return WQ_DST128 && c->lc >= 2 && c->lev[c->lc - 1].N == kD2;
 }
 
 // Solve with the context's stop rule.  Tolerance mode (mg_rtol > 0) runs a batch
@@ -1581,9 +1762,9 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
         const double* top = c->lc == 0 ? k2 : T.k2;
         int tot = 0;
         for (int n = T.N; n >= 2; n /= 2) tot += (n + 1) * (n + 1);
-        ProfScope ps(c, "k_coarse_k2", 16.0 * tot);
-        WQ_KLAUNCH(ps, k_coarse_k2, dim3(1), dim3(kCoarseThreads), 0, s, T.N, T.pitch, top,
-                           c->k2lev);
+        ProfScope ps(c, "k_coarse_k2", 24.0 * tot);
+        WQ_KLAUNCH(ps, k_coarse_k2, dim3(1), dim3(kCoarseThreads), 0, s, T.N, T.pitch, T.h, top,
+                           c->k2lev, c->k2levf, c->idlevf);
     }
     // one "cycle" is a V-cycle (FP64) or an outer defect-correction iteration (mixed)
     auto cycle = [&](int slot) {

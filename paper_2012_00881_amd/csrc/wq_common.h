@@ -180,10 +180,17 @@ struct wandqs_ctx {
     double* mom[6] = {};
     double* jz = nullptr;
     double* k2lev = nullptr;  // k2 of the coarse-kernel levels (dense, concatenated)
+    float* k2levf = nullptr;  // the same in float, and 1 / (4 + h_l^2 k2) in float
+    float* idlevf = nullptr;
     // exact Poisson solve on the 64^2 coarse level: sine-transform matrix S and
     // the scaled inverse eigenvalues M, [64][64] float each (zero row/column 63)
     float* dst_S = nullptr;
     float* dst_M = nullptr;
+    // the same on the 128^2 level (when it lies below a finer one), and the
+    // intermediate X = M o (S f S), [2][128][128] float
+    float* dst2_S = nullptr;
+    float* dst2_M = nullptr;
+    float* dst2_X = nullptr;
     double* pa[2][4] = {};
     int32_t* pid[2] = {};
     int cur = 0;
@@ -236,8 +243,11 @@ namespace wq {
 size_t carve(wandqs_ctx* c, char* base);
 // smallest level that runs the register-tile pass kernels by default
 int reg_tile_min_default();
-// host tables of the 64^2 coarse-level Poisson solve (S and M, [64][64] each)
-void dst_tables(double H, float* S, float* M);
+// host tables of the exact coarse-level Poisson solve on an n^2 level (S and
+// M, [n][n] each; n = 64 or 128)
+void dst_tables(int n, double H, float* S, float* M);
+// whether the Poisson V-cycles end with the exact solve on the 128^2 level
+bool dst128_used(const wandqs_ctx* c);
 
 // multigrid (mg.hip)
 wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const u[2],
