@@ -137,7 +137,9 @@ wandqs_status wandqs_workspace_bytes(const wandqs_config* cfg, int32_t n_slices,
  * the stream once.  *out is NULL on error.  Diagnostic: with the environment
  * variable WANDQS_MG_TILES=lds at init, every multigrid level runs the LDS tile
  * kernels instead of the register tiles of the large levels (same results,
- * bit for bit). */
+ * bit for bit); with WANDQS_GRAPHS=1 at init, each multigrid cycle is captured
+ * once as a HIP graph per set of launch arguments and replayed (same kernels,
+ * same results; the graphs are freed by wandqs_destroy). */
 wandqs_status wandqs_init(const wandqs_config* cfg, int32_t n_slices, void* d_workspace,
                           size_t bytes, void* hip_stream, wandqs_ctx** out);
 

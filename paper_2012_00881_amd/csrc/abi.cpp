@@ -102,6 +102,8 @@ void set_sizes(wandqs_ctx* c, const wandqs_config* cfg, int32_t n_slices) {
     {
         const char* e = std::getenv("WANDQS_MG_TILES");
         c->reg_tile_min = (e && std::strcmp(e, "lds") == 0) ? INT_MAX : wq::reg_tile_min_default();
+        const char* g = std::getenv("WANDQS_GRAPHS");
+        c->graphs_on = g && std::strcmp(g, "1") == 0;
     }
     const int t = (c->N + 15) / 16;  // norm partials: one per tile of the smallest tile size
     c->max_tiles = t * t;
@@ -826,6 +828,8 @@ wandqs_status wandqs_backward(wandqs_ctx* c, const double* h_dL_dprobe, const do
 void wandqs_destroy(wandqs_ctx* c) {
     if (!c) return;
     wq::prof_reset(c, false);
+    for (const wq::CycleGraph& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->h_pin) (void)hipHostFree(c->h_pin);
     delete c;
 }

@@ -27,6 +27,13 @@
 namespace wq {
 namespace {
 
+// Kernel names for the per-kernel timing; formatted only when it is on.
+template <class... A>
+void prof_name(const wandqs_ctx* c, char* nm, size_t n, const char* fmt, A... a) {
+    if (c->prof.on) std::snprintf(nm, n, fmt, a...);
+    else nm[0] = 0;
+}
+
 #ifndef WQ_COARSE_CYCLES
 #define WQ_COARSE_CYCLES 1
 #endif
@@ -1557,10 +1564,10 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
         const double nodes = (double)L.N * L.N;
         char nm[64];
         if (g.reg)
-            std::snprintf(nm, sizeof nm, "k_mg_down_reg<%s, %d, %s, %d, %d>@%d", type_name(E()), R,
+            prof_name(c, nm, sizeof nm, "k_mg_down_reg<%s, %d, %s, %d, %d>@%d", type_name(E()), R,
                           helm ? "true" : "false", c->cfg.nu_pre, kRegWaves, L.N);
         else
-            std::snprintf(nm, sizeof nm, "k_mg_down<%s, %d, %s, %d, %d>@%d", type_name(E()), R,
+            prof_name(c, nm, sizeof nm, "k_mg_down<%s, %d, %s, %d, %d>@%d", type_name(E()), R,
                           helm ? "true" : "false", c->cfg.nu_pre, g.TX, L.N);
         ProfScope ps(c, nm, nodes * ((a.u_in[0] ? eb * R : 0.0) + eb * R + (helm ? 8.0 : 0.0) +
                                      eb * R + eb * R / 4));
@@ -1580,12 +1587,12 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
         const double nodes = (double)(L.N + 1) * (L.N + 1);
         const dim3 g(kD2 / kD2Rows, R);
         char nm[64];
-        std::snprintf(nm, sizeof nm, "k_dst2_fwd<%s>", type_name(E()));
+        prof_name(c, nm, sizeof nm, "k_dst2_fwd<%s>", type_name(E()));
         {
             ProfScope ps(c, nm, nodes * eb * R + 4.0 * kD2 * kD2 * (2.0 + R));
             WQ_KLAUNCH(ps, k_dst2_fwd<E>, g, dim3(512), 0, s, d);
         }
-        std::snprintf(nm, sizeof nm, "k_dst2_inv<%s>", type_name(E()));
+        prof_name(c, nm, sizeof nm, "k_dst2_inv<%s>", type_name(E()));
         {
             ProfScope ps(c, nm, nodes * eb * R + 4.0 * kD2 * kD2 * (1.0 + R));
             WQ_KLAUNCH(ps, k_dst2_inv<E>, g, dim3(512), 0, s, d);
@@ -1618,13 +1625,13 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
             }
             d.S = c->dst_S;
             d.M = c->dst_M;
-            std::snprintf(nm, sizeof nm, "k_coarse_dst<%s>", type_name(E()));
+            prof_name(c, nm, sizeof nm, "k_coarse_dst<%s>", type_name(E()));
             ProfScope ps(c, nm, nodes * 2.0 * eb * R + 2.0 * 4.0 * kDstN * kDstN);
             WQ_KLAUNCH(ps, k_coarse_dst<E>, dim3(R), dim3(1024), 0, s, d);
         } else {
             // float sweeps when the coarse levels only correct a finer level
             const bool f32 = WQ_COARSE_F32 && lc > 0;
-            std::snprintf(nm, sizeof nm, "k_mg_coarse<%s, %s, %s>", type_name(E()),
+            prof_name(c, nm, sizeof nm, "k_mg_coarse<%s, %s, %s>", type_name(E()),
                           f32 ? "float" : type_name(E()), helm ? "true" : "false");
             ProfScope ps(c, nm, nodes * (eb * R + (a.u_init[0] ? eb * R : 0.0) + (helm ? 8.0 : 0.0) + eb * R));
             if (f32) {
@@ -1655,10 +1662,10 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
         char nm[64];
         const PassGeom g = pass_geom(c, L.N, c->cfg.nu_post, false);
         if (g.reg)
-            std::snprintf(nm, sizeof nm, "k_mg_up_reg<%s, %d, %s, %d, %d>@%d", type_name(E()), R,
+            prof_name(c, nm, sizeof nm, "k_mg_up_reg<%s, %d, %s, %d, %d>@%d", type_name(E()), R,
                           helm ? "true" : "false", c->cfg.nu_post, kRegWaves, L.N);
         else
-            std::snprintf(nm, sizeof nm, "k_mg_up<%s, %d, %s, %d, %d>@%d", type_name(E()), R,
+            prof_name(c, nm, sizeof nm, "k_mg_up<%s, %d, %s, %d, %d>@%d", type_name(E()), R,
                           helm ? "true" : "false", c->cfg.nu_post, g.TX, L.N);
         ProfScope ps(c, nm, nodes * (eb * R + eb * R / 4 + eb * R + (helm ? 8.0 : 0.0) + eb * R));
         up_pass<E>(R, helm, a, c->cfg.nu_post, g, s, ps);
@@ -1682,7 +1689,7 @@ void resnorm(wandqs_ctx* c, int R, bool helm, const Hier<double>& hz, int slot,
     float* o0 = r32 ? r32[0] : nullptr;
     float* o1 = (r32 && R > 1) ? r32[1] : nullptr;
     char nm[56];
-    std::snprintf(nm, sizeof nm, "k_resnorm<%d, %s>%s", R, helm ? "true" : "false",
+    prof_name(c, nm, sizeof nm, "k_resnorm<%d, %s>%s", R, helm ? "true" : "false",
                   r32 ? "+defect" : "");
     ProfScope ps(c, nm, (double)L.N * L.N * (16.0 * R + (helm ? 8.0 : 0.0) + (r32 ? 4.0 * R : 0.0)));
     if (R == 1) {
@@ -1734,6 +1741,46 @@ bool dst128_used(const wandqs_ctx* c) {
     return WQ_DST128 && c->lc >= 2 && c->lev[c->lc - 1].N == kD2;
 }
 
+// Launches one cycle, body() on c->stream, as a HIP graph: the graph of `key`
+// is captured on c->cap_stream and instantiated at its first use and replayed
+// after.  With graphs off, with the per-kernel timing on (its events belong to
+// direct launches), or when a capture fails (graphs then stay off for the
+// context), body() launches directly.
+template <class F>
+hipError_t run_cycle(wandqs_ctx* c, const CycleKey& key, F&& body) {
+    if (c->graphs_on && !c->prof.on && hipPeekAtLastError() == hipSuccess) {
+        for (const CycleGraph& g : c->graphs)
+            if (g.key == key) return hipGraphLaunch(g.exec, c->stream);
+        if ((int)c->graphs.size() < kMaxGraphs) {
+            hipGraphExec_t ex = nullptr;
+            bool ok = c->cap_stream ||
+                      hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
+            if (!ok) c->cap_stream = nullptr;
+            ok = ok && hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed) == hipSuccess;
+            if (ok) {
+                const hipStream_t s0 = c->stream;
+                c->stream = c->cap_stream;
+                body();
+                c->stream = s0;
+                const bool launched = hipGetLastError() == hipSuccess;
+                hipGraph_t g = nullptr;
+                ok = hipStreamEndCapture(c->cap_stream, &g) == hipSuccess && launched && g &&
+                     hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+                if (g) (void)hipGraphDestroy(g);
+            }
+            if (ok) {
+                c->graphs.push_back(CycleGraph{key, ex});
+                return hipGraphLaunch(ex, c->stream);
+            }
+            if (ex) (void)hipGraphExecDestroy(ex);
+            (void)hipGetLastError();
+            c->graphs_on = false;
+        }
+    }
+    body();
+    return hipSuccess;
+}
+
 // Solve with the context's stop rule.  Tolerance mode (mg_rtol > 0) runs a batch
 // of V-cycles sized by the previous slice's count for this solve, reads the
 // residual norms back once per batch and adds single cycles until every
@@ -1766,20 +1813,29 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
         WQ_KLAUNCH(ps, k_coarse_k2, dim3(1), dim3(kCoarseThreads), 0, s, T.N, T.pitch, T.h, top,
                            c->k2lev, c->k2levf, c->idlevf);
     }
-    // one "cycle" is a V-cycle (FP64) or an outer defect-correction iteration (mixed)
+    // one "cycle" is a V-cycle (FP64) or an outer defect-correction iteration
+    // (mixed) that records its residual norms in `slot` (FP64: -1, none)
+    hipError_t gerr = hipSuccess;
     auto cycle = [&](int slot) {
-        if (mixed) mixed_iteration(c, R, helm, hz, slot);
-        else vcycle<double>(c, R, helm, hz, false, c->lc == 0 ? -1 : slot);
+        const CycleKey key{{hz.u0[0], hz.u0[1], hz.f0[0], hz.f0[1], hz.k2}, R, helm, mixed, slot};
+        const hipError_t e = run_cycle(c, key, [&] {
+            if (mixed) mixed_iteration(c, R, helm, hz, slot);
+            else vcycle<double>(c, R, helm, hz, false, slot);
+        });
+        if (gerr == hipSuccess) gerr = e;
+    };
+    auto graph_check = [&]() -> wandqs_status {
+        if (gerr == hipSuccess) return WANDQS_OK;
+        c->err = std::string("hipGraphLaunch: ") + hipGetErrorString(gerr);
+        return WANDQS_E_HIP;
     };
     // the down pass records the incoming residual itself unless the top level is
     // the coarse kernel (FP64) ; the mixed defect kernel always records it
     const bool separate_norm = !mixed && c->lc == 0;
     const int maxc = c->cfg.mg_max_cycles;
     if (!(c->cfg.mg_rtol > 0.0)) {
-        for (int k = 0; k < maxc; ++k) {
-            if (mixed) mixed_iteration(c, R, helm, hz, 0);
-            else vcycle<double>(c, R, helm, hz, false, -1);
-        }
+        for (int k = 0; k < maxc; ++k) cycle(mixed ? 0 : -1);
+        if (graph_check() != WANDQS_OK) return WANDQS_E_HIP;
         WQ_LAUNCH_CHECK();
         if (res) *res = SolveResult{maxc, {-1.0, -1.0}};
         return WANDQS_OK;
@@ -1802,7 +1858,7 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
         if (done + b > maxc) b = maxc - done;
         for (int k = 0; k < b; ++k) {
             const int cyc = done + k;
-            cycle(cyc);
+            cycle(mixed || c->lc > 0 ? cyc : -1);
             if (separate_norm) resnorm(c, R, helm, hz, cyc + 1, nullptr);
         }
         if (!separate_norm) resnorm(c, R, helm, hz, done + b, nullptr);
@@ -1813,6 +1869,7 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
             WQ_KLAUNCH(ps, k_reduce_slots, dim3(ns * 3 * R), dim3(kThreads), 0, s,
                                c->norm_part, V * c->max_tiles, nblk, s0, 3 * R, c->norm_red);
         }
+        if (graph_check() != WANDQS_OK) return WANDQS_E_HIP;
         WQ_LAUNCH_CHECK();
         WQ_HIP(hipMemcpyAsync(hr + V * s0, c->norm_red + V * s0, sizeof(double) * V * ns,
                               hipMemcpyDeviceToHost, s));

@@ -132,6 +132,24 @@ struct SolveResult {
     double rel[2] = {-1.0, -1.0};
 };
 
+// One multigrid cycle of a solve as an instantiated HIP graph, keyed by every
+// launch argument that varies between cycles: the solve's arrays, the number
+// of right-hand sides, the operator, the precision form and the norm slot.
+struct CycleKey {
+    const void* p[5];
+    int R, helm, mixed, slot;
+    bool operator==(const CycleKey& o) const {
+        for (int i = 0; i < 5; ++i)
+            if (p[i] != o.p[i]) return false;
+        return R == o.R && helm == o.helm && mixed == o.mixed && slot == o.slot;
+    }
+};
+struct CycleGraph {
+    CycleKey key;
+    hipGraphExec_t exec;
+};
+constexpr int kMaxGraphs = 1024;
+
 // Optional per-kernel timing with HIP events (see wandqs_profile).
 struct ProfPending {
     int cls;
@@ -161,6 +179,13 @@ struct wandqs_ctx {
     // levels N >= reg_tile_min run the register-tile pass kernels (environment
     // WANDQS_MG_TILES=lds at init: never; the LDS tiles give the same bits)
     int reg_tile_min = 0;
+    // environment WANDQS_GRAPHS=1 at init: multigrid cycles replay as HIP
+    // graphs, captured on cap_stream at their first use (the kernels and their
+    // arguments are those of the direct launches; on the 1024^2 job the
+    // replays run 5-6% slower than direct launches, so they are off by default)
+    bool graphs_on = false;
+    hipStream_t cap_stream = nullptr;
+    std::vector<wq::CycleGraph> graphs;
     double L = 0, h = 0;
     int64_t P = 0;
     int rec_cap = 0;

@@ -302,3 +302,29 @@ def test_register_tiles_bitwise_equal_lds_tiles(torch_cuda, monkeypatch, precisi
         outs.append(res)
     for a, b in zip(*outs):
         assert np.array_equal(a, b), float(np.abs(a - b).max())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replay_bitwise_equal_direct_launches(torch_cuda, monkeypatch, precision):
+    """Multigrid cycles replayed as HIP graphs (WANDQS_GRAPHS=1) against
+    direct launches: the first 48 slices of the 512^2 case in tolerance mode
+    replay every captured cycle many times, with the particle kernels and the
+    host's norm reads between replays, and give the same bits, the same cycle
+    counts and the same steps."""
+    outs = []
+    for mode in ("1", None):
+        if mode:
+            monkeypatch.setenv("WANDQS_GRAPHS", mode)
+        else:
+            monkeypatch.delenv("WANDQS_GRAPHS", raising=False)
+        cfg = wi.scaled(wi.config("C3"), precision=precision)
+        sim = _sim(cfg, 48)
+        infos, _ = sim.run(48, infos=True)
+        got = sim.get_state()
+        outs.append((got["fields"].cpu().numpy().copy(), got["particles"].cpu().numpy().copy(),
+                     [(i["xi"], i["dxi"], tuple(i["vcycles"])) for i in infos]))
+        sim.close()
+    (fa, pa, ia), (fb, pb, ib) = outs
+    assert np.array_equal(fa, fb), float(np.abs(fa - fb).max())
+    assert np.array_equal(pa, pb), float(np.abs(pa - pb).max())
+    assert ia == ib
