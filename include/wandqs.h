@@ -97,7 +97,8 @@ typedef struct {
                             mg_max_cycles V-cycles, no host syncs */
     double mg_atol;      /* >= 0; 0 recommended (an absolute floor loosens small fields) */
     int32_t mg_max_cycles; /* 1 .. 200 */
-    int32_t nu_pre, nu_post; /* red-black Gauss-Seidel sweeps per V-cycle, each 1 .. 3 */
+    int32_t nu_pre, nu_post; /* over-relaxed red-black Gauss-Seidel sweeps per V-cycle,
+                                each 1 .. 3 */
     int32_t n_beams;       /* 0 .. 8 */
     const wandqs_beam* beams;
     int32_t n_probes;      /* 0 .. 16 */
@@ -112,6 +113,13 @@ typedef struct {
                                  FP64 and smooths/transfers the error equation in FP32;
                                  particles stay FP64.  Each "V-cycle" counted in
                                  wandqs_slice_info.vcycles is then one outer iteration. */
+    double mg_omega;          /* relaxation factor om of the smoothing sweeps of the
+                                 Poisson solves (psi, Ez, Bz): each node of a
+                                 half sweep moves to u + om (g - u), g the value that
+                                 solves its own equation; 0 < om < 2, 0 selects
+                                 1.175.  om = 1 is plain Gauss-Seidel. */
+    double mg_omega_helm;     /* the same for the Helmholtz solve (B_perp); 0
+                                 selects 1.125 */
 } wandqs_config;
 
 typedef struct {

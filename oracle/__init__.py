@@ -40,7 +40,8 @@ class Cfg(C.Structure):
                 ("n0", C.c_double), ("dxi0", C.c_double), ("adaptive", C.c_int),
                 ("refine_k", C.c_int), ("mg_rtol", C.c_double), ("mg_atol", C.c_double),
                 ("mg_max_cycles", C.c_int), ("nu_pre", C.c_int), ("nu_post", C.c_int),
-                ("n_beams", C.c_int), ("beams", C.POINTER(Beam))]
+                ("n_beams", C.c_int), ("beams", C.POINTER(Beam)), ("mg_omega", C.c_double),
+                ("mg_omega_helm", C.c_double)]
 
 
 class Info(C.Structure):
@@ -100,6 +101,8 @@ class Oracle:
         c.mg_rtol, c.mg_atol = cfg["mg_rtol"], cfg["mg_atol"]
         c.mg_max_cycles, c.nu_pre, c.nu_post = cfg["mg_max_cycles"], cfg["nu_pre"], cfg["nu_post"]
         c.n_beams, c.beams = len(cfg["beams"]), beams
+        c.mg_omega = cfg.get("mg_omega", 0.0)
+        c.mg_omega_helm = cfg.get("mg_omega_helm", 0.0)
         self.c = c
 
     # ---------------------------------------------------------------- pieces
@@ -298,15 +301,18 @@ def apply(N, h, u, k2=None):
     return out
 
 
-def mg_solve(N, h, f, u0=None, k2=None, rtol=1e-14, atol=0.0, max_cycles=50, nu1=2, nu2=2):
-    """Multigrid solve of (L_h - k2) u = f with zero Dirichlet boundary."""
+def mg_solve(N, h, f, u0=None, k2=None, rtol=1e-14, atol=0.0, max_cycles=50, nu1=2, nu2=2,
+             omega=0.0):
+    """Multigrid solve of (L_h - k2) u = f with zero Dirichlet boundary; omega is
+    the relaxation factor of the smoothing sweeps (0: the operator's default)."""
     f = _f64(f)
     u = np.zeros_like(f) if u0 is None else _f64(u0).copy()
     cyc = C.c_int(0)
     rel = C.c_double(0)
     st = lib().oracle_mg_solve(int(N), C.c_double(h), _p(None if k2 is None else _f64(k2)),
                                _p(f), _p(u), C.c_double(rtol), C.c_double(atol), int(max_cycles),
-                               int(nu1), int(nu2), C.byref(cyc), C.byref(rel))
+                               int(nu1), int(nu2), C.c_double(omega), C.byref(cyc),
+                               C.byref(rel))
     return st, u, cyc.value, rel.value
 
 

@@ -19,9 +19,12 @@
  *  - central differences at interior nodes, one-sided at boundary nodes only
  *    for the gradient of psi used by the particle gather;
  *  - 5-point Laplacian of Sec. VII.B, eq. (33);
- *  - geometric multigrid: V(nu1,nu2) cycles, red-black Gauss-Seidel, full
- *    weighting, bilinear prolongation, rediscretised coarse operators, exact
- *    solve on the 2x2-cell grid (Sec. II item 4 and Sec. VII.A).
+ *  - geometric multigrid: V(nu1,nu2) cycles, red-black Gauss-Seidel
+ *    over-relaxed by a factor om (the paper names only "iterative relaxation";
+ *    om = 1.175 for the Poisson operator and 1.125 for the Helmholtz one unless
+ *    the configuration gives others), full weighting, bilinear prolongation,
+ *    rediscretised coarse operators, exact solve on the 2x2-cell grid (Sec. II
+ *    item 4 and Sec. VII.A).
  *
  * Array layout: node (a, b) of an (N+1)x(N+1) array is element b*(N+1)+a
  * (x index fastest).  Field order: psi, Ez, Bz, Bx, By.
@@ -63,6 +66,7 @@ typedef struct {
     int mg_max_cycles, nu_pre, nu_post;
     int n_beams;
     const oracle_beam* beams;
+    double mg_omega, mg_omega_helm; /* relaxation factors (Poisson, Helmholtz); 0: the defaults */
 } oracle_cfg;
 
 typedef struct {
@@ -234,10 +238,11 @@ T apply_at(const Level<T>& lv, const T* u, int a, int b) {
     return lap - k2 * u[lv.id(a, b)];
 }
 
-/* Red-black Gauss-Seidel half sweep: the nodes with (a+b) % 2 == color are set
- * to the value that zeroes their own equation given their four neighbours. */
+/* Over-relaxed red-black Gauss-Seidel half sweep: each node with
+ * (a+b) % 2 == color moves from u to u + om (g - u), where g is the value that
+ * zeroes its own equation given its four neighbours (om = 1: Gauss-Seidel). */
 template <class T>
-void relax_color(Level<T>& lv, int color) {
+void relax_color(Level<T>& lv, int color, double om) {
     const double h2 = lv.h * lv.h;
     for (int b = 1; b < lv.N; ++b)
         for (int a = 1; a < lv.N; ++a) {
@@ -245,15 +250,16 @@ void relax_color(Level<T>& lv, int color) {
             T nb = lv.u[lv.id(a - 1, b)] + lv.u[lv.id(a + 1, b)] + lv.u[lv.id(a, b - 1)] +
                    lv.u[lv.id(a, b + 1)];
             T k2 = lv.k2.empty() ? T(0.0) : lv.k2[lv.id(a, b)];
-            lv.u[lv.id(a, b)] = (nb - h2 * lv.f[lv.id(a, b)]) / (4.0 + h2 * k2);
+            T g = (nb - h2 * lv.f[lv.id(a, b)]) / (4.0 + h2 * k2);
+            lv.u[lv.id(a, b)] = lv.u[lv.id(a, b)] + om * (g - lv.u[lv.id(a, b)]);
         }
 }
 
 template <class T>
-void smooth(Level<T>& lv, int nu) {
+void smooth(Level<T>& lv, int nu, double om) {
     for (int s = 0; s < nu; ++s) {
-        relax_color(lv, 0);
-        relax_color(lv, 1);
+        relax_color(lv, 0, om);
+        relax_color(lv, 1, om);
     }
 }
 
@@ -312,22 +318,22 @@ void prolong_add(const Level<T>& coarse, Level<T>& fine) {
 }
 
 template <class T>
-void vcycle(std::vector<Level<T>>& lv, size_t l, int nu1, int nu2) {
+void vcycle(std::vector<Level<T>>& lv, size_t l, int nu1, int nu2, double om) {
     Level<T>& L = lv[l];
     if (L.N == 2) { /* one interior node, four zero boundary neighbours: exact */
         T k2 = L.k2.empty() ? T(0.0) : L.k2[L.id(1, 1)];
         L.u[L.id(1, 1)] = -L.f[L.id(1, 1)] / (4.0 / (L.h * L.h) + k2);
         return;
     }
-    smooth(L, nu1);
+    smooth(L, nu1, om);
     std::vector<T> r;
     residual(L, r);
     Level<T>& C = lv[l + 1];
     full_weighting(L, r, C, C.f);
     std::fill(C.u.begin(), C.u.end(), T(0.0));
-    vcycle(lv, l + 1, nu1, nu2);
+    vcycle(lv, l + 1, nu1, nu2, om);
     prolong_add(C, L);
-    smooth(L, nu2);
+    smooth(L, nu2, om);
 }
 
 /* Solve (L_h - k2) u = f for the interior nodes with u = 0 on the boundary,
@@ -342,7 +348,8 @@ void vcycle(std::vector<Level<T>>& lv, size_t l, int nu1, int nu2) {
  * must meet the rule: the derivative solves converge along with the value. */
 template <class T>
 int mg_solve(int N, double h, const T* k2, const T* f, T* u, double rtol, double atol,
-             int max_cycles, int nu1, int nu2, int* cycles_out, double* rel_out) {
+             int max_cycles, int nu1, int nu2, double om, int* cycles_out, double* rel_out) {
+    if (om == 0.0) om = k2 ? 1.125 : 1.175;
     std::vector<Level<T>> lv;
     for (int n = N; n >= 2; n /= 2) {
         Level<T> l;
@@ -387,7 +394,7 @@ int mg_solve(int N, double h, const T* k2, const T* f, T* u, double rtol, double
     };
     int cyc = 0;
     while (!all_done() && cyc < max_cycles) {
-        vcycle(lv, 0, nu1, nu2);
+        vcycle(lv, 0, nu1, nu2, om);
         ++cyc;
         residual(top, r);
         for (int c = 0; c < nc; ++c) {
@@ -596,7 +603,8 @@ int slice_step_t(const oracle_cfg* c, int P, T* x, T* y, T* px, T* py, T* pz, T*
     int status = ORC_OK;
     auto solve = [&](int k, const std::vector<T>* k2, const std::vector<T>& f, T* u) {
         int st = mg_solve<T>(g.N, g.h, k2 ? k2->data() : nullptr, f.data(), u, c->mg_rtol, c->mg_atol,
-                          c->mg_max_cycles, c->nu_pre, c->nu_post, &inf.cycles[k], &inf.rel_resid[k]);
+                          c->mg_max_cycles, c->nu_pre, c->nu_post, k2 ? c->mg_omega_helm : c->mg_omega,
+                          &inf.cycles[k], &inf.rel_resid[k]);
         if (st != ORC_OK && status == ORC_OK) status = st;
     };
 
@@ -731,9 +739,10 @@ int oracle_apply(int N, double h, const double* k2, const double* u, double* out
 }
 
 int oracle_mg_solve(int N, double h, const double* k2, const double* f, double* u, double rtol,
-                    double atol, int max_cycles, int nu1, int nu2, int* cycles, double* rel) {
-    if (N < 2 || (N & (N - 1))) return ORC_INVALID;
-    return mg_solve(N, h, k2, f, u, rtol, atol, max_cycles, nu1, nu2, cycles, rel);
+                    double atol, int max_cycles, int nu1, int nu2, double om, int* cycles,
+                    double* rel) {
+    if (N < 2 || (N & (N - 1)) || !(om >= 0.0 && om < 2.0)) return ORC_INVALID;
+    return mg_solve(N, h, k2, f, u, rtol, atol, max_cycles, nu1, nu2, om, cycles, rel);
 }
 
 int oracle_beam_density(const oracle_cfg* c, double xi, double* out) {
@@ -1000,7 +1009,8 @@ int adjoint_solve(const Grid& g, const oracle_cfg& c, const std::vector<double>*
     int cyc;
     double rel;
     return mg_solve(g.N, g.h, k2 ? k2->data() : nullptr, rhs.data(), lam.data(), c.mg_rtol, c.mg_atol,
-                    c.mg_max_cycles, c.nu_pre, c.nu_post, &cyc, &rel);
+                    c.mg_max_cycles, c.nu_pre, c.nu_post, k2 ? c.mg_omega_helm : c.mg_omega, &cyc,
+                    &rel);
 }
 
 } /* namespace */

@@ -39,6 +39,8 @@ std::string check_config(const wandqs_config* c, int32_t n_slices) {
     if (c->mg_max_cycles < 1 || c->mg_max_cycles > 200) return "mg_max_cycles must be in [1, 200]";
     if (c->nu_pre < 1 || c->nu_pre > 3 || c->nu_post < 1 || c->nu_post > 3)
         return "nu_pre and nu_post must be in [1, 3]";
+    for (double om : {c->mg_omega, c->mg_omega_helm})
+        if (!(om == 0.0 || (om > 0.0 && om < 2.0))) return "mg_omega and mg_omega_helm must be in (0, 2) or 0";
     if (c->n_beams < 0 || c->n_beams > wq::kMaxBeams) return "n_beams must be in [0, 8]";
     if (c->n_beams > 0 && !c->beams) return "beams is NULL";
     for (int k = 0; k < c->n_beams; ++k) {
@@ -428,6 +430,10 @@ wandqs_status wandqs_init(const wandqs_config* cfg, int32_t n_slices, void* d_wo
         return WANDQS_E_NOMEM;
     }
     c->cfg = *cfg;
+    // relaxation factors measured to minimise the V-cycles per solve on the
+    // blowout workloads (Poisson and Helmholtz operators separately)
+    if (c->cfg.mg_omega == 0.0) c->cfg.mg_omega = 1.175;
+    if (c->cfg.mg_omega_helm == 0.0) c->cfg.mg_omega_helm = 1.125;
     c->beams.assign(cfg->beams, cfg->beams + cfg->n_beams);
     c->probes.assign(cfg->probes, cfg->probes + cfg->n_probes);
     c->cfg.beams = nullptr;

@@ -137,13 +137,22 @@ __device__ __forceinline__ void tile_load(E (*su)[EX * EY], E (&fr)[R][KP][2], E
     }
 }
 
-// One red-black half sweep: u <- (sum of 4 neighbours - h^2 f) / D on the nodes
-// of colour `color` ((gx + gy) % 2) that have all four neighbours in the tile
-// and lie inside the domain.
+// Over-relaxed red-black update of one node: with g = (sum of the 4
+// neighbours - h^2 f) / D, the node's own equation solved for it,
+// u <- u + om (g - u).  Every smoothing kernel forms it with these three
+// fused operations, so they all give the same bits.
+template <typename E>
+__device__ __forceinline__ E sor_update(E u, E nb, E fv, E iD, E h2, E om) {
+    return fmad(om, fmad(fmad(-h2, fv, nb), iD, -u), u);
+}
+
+// One red-black half sweep (sor_update) on the nodes of colour `color`
+// ((gx + gy) % 2) that have all four neighbours in the tile and lie inside the
+// domain.
 template <typename E, int R, bool HELM, int EX, int EY, int KP, int NT>
 __device__ __forceinline__ void tile_sweep(E (*su)[EX * EY], const E (&fr)[R][KP][2],
                                            const E (&iDr)[KP][2], int ex0, int ey0, int N, E h2,
-                                           int color) {
+                                           E om, int color) {
     constexpr int PW = EX / 2, NP = PW * EY;
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
@@ -161,7 +170,7 @@ __device__ __forceinline__ void tile_sweep(E (*su)[EX * EY], const E (&fr)[R][KP
             for (int r = 0; r < R; ++r) {
                 const E fv = pick(j, fr[r][k][0], fr[r][k][1]);
                 const E nb = su[r][l - 1] + su[r][l + 1] + su[r][l - EX] + su[r][l + EX];
-                su[r][l] = fmad(-h2, fv, nb) * id;
+                su[r][l] = sor_update(su[r][l], nb, fv, id, h2, om);
             }
         }
     }
@@ -179,6 +188,7 @@ struct DownArgs {
     E* f_c[2];
     double* norm_part;  // (double only) nullptr or [3R][nblk]: sums r^2, f^2, u^2 of the incoming u
     int nblk;
+    double omega;  // relaxation factor of the smoothing sweeps
 };
 
 // Down pass of one level: nu1 sweeps on the tile, write the smoothed tile,
@@ -202,6 +212,7 @@ __global__ __launch_bounds__(tile_threads<T>()) void k_mg_down(DownArgs<E> a) {
     const int x0 = bx * T, y0 = by * T;
     const int ex0 = x0 - HL, ey0 = y0 - HL;
     const E h2 = (E)(a.h * a.h), ih2 = (E)(1.0 / (a.h * a.h));
+    const E om = (E)a.omega;
 
     E fr[R][KP][2], Dr[KP][2], iDr[KP][2];
     tile_load<E, R, HELM, EX, EY, KP, NT>(su, fr, Dr, iDr, a.u_in, a.f, a.k2, a.pitch, ex0, ey0, N,
@@ -252,7 +263,7 @@ __global__ __launch_bounds__(tile_threads<T>()) void k_mg_down(DownArgs<E> a) {
 
     for (int s = 0; s < NU; ++s)
         for (int color = 0; color < 2; ++color) {
-            tile_sweep<E, R, HELM, EX, EY, KP, NT>(su, fr, iDr, ex0, ey0, N, h2, color);
+            tile_sweep<E, R, HELM, EX, EY, KP, NT>(su, fr, iDr, ex0, ey0, N, h2, om, color);
             __syncthreads();
         }
 
@@ -325,6 +336,7 @@ struct UpArgs {
     const E* f[2];
     const double* k2;
     E* u_out[2];
+    double omega;
 };
 
 // Up pass of one level: u += bilinear prolongation of the coarse correction on
@@ -348,6 +360,7 @@ __global__ __launch_bounds__(tile_threads<T>()) void k_mg_up(UpArgs<E> a) {
     const int ex0 = x0 - H, ey0 = y0 - H;  // even
     const int cx0 = ex0 / 2, cy0 = ey0 / 2;
     const E h2 = (E)(a.h * a.h);
+    const E om = (E)a.omega;
 
     E fr[R][KP][2], Dr[KP][2], iDr[KP][2];
     tile_load<E, R, HELM, EX, EY, KP, NT>(su, fr, Dr, iDr, a.u_mid, a.f, a.k2, a.pitch, ex0, ey0, N,
@@ -388,7 +401,7 @@ __global__ __launch_bounds__(tile_threads<T>()) void k_mg_up(UpArgs<E> a) {
 
     for (int s = 0; s < NU; ++s)
         for (int color = 0; color < 2; ++color) {
-            tile_sweep<E, R, HELM, EX, EY, KP, NT>(su, fr, iDr, ex0, ey0, N, h2, color);
+            tile_sweep<E, R, HELM, EX, EY, KP, NT>(su, fr, iDr, ex0, ey0, N, h2, om, color);
             __syncthreads();
         }
 
@@ -534,7 +547,8 @@ template <typename E, int R, bool HELM, int K>
 __device__ __forceinline__ void reg_half_sweep(E (&u)[R][K][2], const E (&f)[R][K][2],
                                                const E (&iD)[K][2], const bool (&upd)[K][2],
                                                const typename Pair2<E>::T (&up)[R],
-                                               const typename Pair2<E>::T (&dn)[R], E h2, int c) {
+                                               const typename Pair2<E>::T (&dn)[R], E h2, E om,
+                                               int c) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
 #pragma unroll
@@ -554,7 +568,7 @@ __device__ __forceinline__ void reg_half_sweep(E (&u)[R][K][2], const E (&f)[R][
                 const E upv = k == 0 ? el(up[r], j) : u[r][k - 1][j];
                 const E dnv = k == K - 1 ? el(dn[r], j) : u[r][k + 1][j];
                 const E nb = left + right + upv + dnv;
-                const E nv = fmad(-h2, f[r][k][j], nb) * iD[k][j];
+                const E nv = sor_update(u[r][k][j], nb, f[r][k][j], iD[k][j], h2, om);
                 u[r][k][j] = upd[k][j] ? nv : u[r][k][j];
             }
         }
@@ -608,6 +622,7 @@ __global__ __launch_bounds__(64 * NW) void k_mg_down_reg(DownArgs<E> a) {
     const int ex0 = x0 - HL, ey0 = y0 - HL;
     const int gx = ex0 + 2 * lane, gy0 = ey0 + w * K;
     const E h2 = (E)(a.h * a.h), ih2 = (E)(1.0 / (a.h * a.h));
+    const E om = (E)a.omega;
 
     E u[R][K][2], f[R][K][2], D[K][2], iD[K][2];
     reg_load<E, R, HELM, K>(u, f, D, iD, a.u_in, a.f, a.k2, a.pitch, gx, gy0, N, a.h * a.h);
@@ -668,7 +683,7 @@ __global__ __launch_bounds__(64 * NW) void k_mg_down_reg(DownArgs<E> a) {
             __syncthreads();
             xc.get(buf, up, dn, w, lane);
         }
-        reg_half_sweep<E, R, HELM, K>(u, f, iD, upd, up, dn, h2, q & 1);
+        reg_half_sweep<E, R, HELM, K>(u, f, iD, upd, up, dn, h2, om, q & 1);
     }
 
     // the smoothed owned nodes
@@ -739,6 +754,7 @@ __global__ __launch_bounds__(64 * NW) void k_mg_up_reg(UpArgs<E> a) {
     const int ex0 = x0 - H, ey0 = y0 - H;
     const int gx = ex0 + 2 * lane, gy0 = ey0 + w * K;
     const E h2 = (E)(a.h * a.h);
+    const E om = (E)a.omega;
 
     E u[R][K][2], f[R][K][2], D[K][2], iD[K][2];
     reg_load<E, R, HELM, K>(u, f, D, iD, a.u_mid, a.f, a.k2, a.pitch, gx, gy0, N, a.h * a.h);
@@ -789,7 +805,7 @@ __global__ __launch_bounds__(64 * NW) void k_mg_up_reg(UpArgs<E> a) {
         xc.put(q & 1, u, w, lane);
         __syncthreads();
         xc.get(q & 1, up, dn, w, lane);
-        reg_half_sweep<E, R, HELM, K>(u, f, iD, upd, up, dn, h2, q & 1);
+        reg_half_sweep<E, R, HELM, K>(u, f, iD, upd, up, dn, h2, om, q & 1);
     }
 
 #pragma unroll
@@ -817,6 +833,7 @@ struct CoarseArgs {
     const float* idlevf;
     E* u_out[2];
     int ncycles, nu1, nu2;
+    double omega;
 };
 
 constexpr int coarse_nodes() {
@@ -839,8 +856,9 @@ struct LdsLevel {
 
     static __device__ __forceinline__ void sync() { __syncthreads(); }
 
-    // nu red-black sweeps; iD (FAST and HELM) = 1 / (4 + h2 k2)
-    static __device__ void smooth(E* u, const E* f, const E* k2, const E* iD, E h2, int nu) {
+    // nu over-relaxed red-black sweeps (sor_update); iD (FAST and HELM) =
+    // 1 / (4 + h2 k2)
+    static __device__ void smooth(E* u, const E* f, const E* k2, const E* iD, E h2, E om, int nu) {
         // slot i: row b, first node a0 = 1 + 2 (i mod HALF); colour c updates a0 + ((1 + b + c) % 2)
         int lb[PER], pb[PER];
         bool ok[PER], last[PER];
@@ -862,8 +880,12 @@ struct LdsLevel {
                     if (!ok[m] || (d && last[m])) continue;
                     const int l = lb[m] + d;
                     const E nb = u[l - 1] + u[l + 1] + u[l - W] + u[l + W];
-                    const E t = nb - h2 * f[l];
-                    u[l] = HELM ? (FAST ? t * iD[l] : t / (E(4) + h2 * k2[l])) : t * E(0.25);
+                    if (HELM && !FAST) {
+                        const E g = fmad(-h2, f[l], nb) / fmad(h2, k2[l], E(4));
+                        u[l] = fmad(om, g - u[l], u[l]);
+                    } else {
+                        u[l] = sor_update(u[l], nb, f[l], HELM ? iD[l] : E(0.25), h2, om);
+                    }
                 }
                 sync();
             }
@@ -1029,7 +1051,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
         const C* k2 = sk + (HELM ? off[l] : 0);
         const C* iD = siD + ((HELM && FAST) ? off[l] : 0);
         with_level<C, HELM, FAST>(Ns[l], [&](auto L) {
-            L.smooth(u, f, k2, iD, (C)(hl * hl), a.nu1);
+            L.smooth(u, f, k2, iD, (C)(hl * hl), (C)a.omega, a.nu1);
             L.restrict_to(u, f, k2, (C)(1.0 / (hl * hl)), su + off[l + 1], sf + off[l + 1], sr);
         });
     };
@@ -1039,7 +1061,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
         with_level<C, HELM, FAST>(Ns[l], [&](auto L) {
             L.prolong_add(u, su + off[l + 1]);
             L.smooth(u, sf + off[l], sk + (HELM ? off[l] : 0), siD + ((HELM && FAST) ? off[l] : 0),
-                     (C)(hl * hl), a.nu2);
+                     (C)(hl * hl), (C)a.omega, a.nu2);
         });
     };
     for (int cyc = 0; cyc < a.ncycles; ++cyc) {
@@ -1541,9 +1563,11 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
     // Poisson: the V-cycle ends with the exact solve on the 128^2 level when
     // that lies below a finer level
     const int lb = (!helm && dst128_used(c)) ? lc - 1 : lc;
+    const double om = helm ? c->cfg.mg_omega_helm : c->cfg.mg_omega;  // smoothing sweeps
     for (int l = 0; l < lb; ++l) {
         wq::Level& L = c->lev[l];
         DownArgs<E> a{};
+        a.omega = om;
         a.N = L.N;
         a.h = L.h;
         a.pitch = L.pitch;
@@ -1600,6 +1624,7 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
     } else {
         wq::Level& L = c->lev[lc];
         CoarseArgs<E> a{};
+        a.omega = om;
         a.N = L.N;
         a.h = L.h;
         a.pitch = L.pitch;
@@ -1646,6 +1671,7 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
     for (int l = lb - 1; l >= 0; --l) {
         wq::Level& L = c->lev[l];
         UpArgs<E> a{};
+        a.omega = om;
         a.N = L.N;
         a.h = L.h;
         a.pitch = L.pitch;

@@ -50,7 +50,8 @@ class Config(C.Structure):
                 ("mg_max_cycles", C.c_int32), ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
                 ("n_beams", C.c_int32), ("beams", C.POINTER(Beam)), ("n_probes", C.c_int32),
                 ("probes", C.POINTER(Probe)), ("checkpoint_every", C.c_int32),
-                ("mg_inner_cycles", C.c_int32)]
+                ("mg_inner_cycles", C.c_int32), ("mg_omega", C.c_double),
+                ("mg_omega_helm", C.c_double)]
 
 
 class KernelStat(C.Structure):
@@ -149,6 +150,8 @@ def make_config(cfg: dict):
     c.n_probes, c.probes = len(cfg["probes"]), probes
     c.checkpoint_every = cfg.get("checkpoint_every", 0)
     c.mg_inner_cycles = cfg.get("mg_inner_cycles", 0)
+    c.mg_omega = cfg.get("mg_omega", 0.0)
+    c.mg_omega_helm = cfg.get("mg_omega_helm", 0.0)
     return c, keep
 
 

@@ -165,10 +165,10 @@ def test_zero_rhs_with_nonzero_guess(oracle_mod, helm):
 @pytest.mark.parametrize("helm", [False, True])
 @pytest.mark.parametrize("smooth", [False, True])
 def test_stop_at_rounding_floor(oracle_mod, helm, smooth):
-    """The stop rule (rtol 1e-14, backward-error floor test) ends the solve at
-    the rounding floor, not before: one more V-cycle from the returned iterate
-    reduces ||r|| by less than 2x, while the cycle before the stop still
-    reduced it by more than 2x."""
+    """With a tolerance below reach (rtol 1e-16) the floor tests of the stop
+    rule end the solve at the rounding floor, not before: one more V-cycle from
+    the returned iterate reduces ||r|| by less than 2x, while the cycle before
+    the stop still reduced it by more than 2x."""
     N, L = 128, 6.0
     h = 2 * L / N
     rng = np.random.default_rng(11)
@@ -186,7 +186,7 @@ def test_stop_at_rounding_floor(oracle_mod, helm, smooth):
     def rnorm(u):
         return np.linalg.norm(f[1:-1, 1:-1].ravel() - A @ u[1:-1, 1:-1].ravel())
 
-    st, u, cyc, _ = oracle_mod.mg_solve(N, h, f, k2=k2)
+    st, u, cyc, _ = oracle_mod.mg_solve(N, h, f, k2=k2, rtol=1e-16)
     assert st == 0 and cyc >= 3
     _, u_prev, _, _ = oracle_mod.mg_solve(N, h, f, k2=k2, rtol=0.0, max_cycles=cyc - 1)
     _, u_more, c1, _ = oracle_mod.mg_solve(N, h, f, u0=u, k2=k2, rtol=0.0, max_cycles=1)
@@ -195,3 +195,47 @@ def test_stop_at_rounding_floor(oracle_mod, helm, smooth):
     print(f"cycles {cyc}: ||r|| {r_prev:.3e} -> {r_stop:.3e} -> {r_more:.3e}")
     assert r_more > 0.5 * r_stop
     assert r_stop < 0.5 * r_prev
+
+
+@pytest.mark.parametrize("helm", [False, True])
+@pytest.mark.parametrize("omega", [0.8, 1.0, 1.5])
+def test_relaxation_factor_keeps_the_solution(oracle_mod, helm, omega):
+    """The relaxation factor of the red-black sweeps changes the path, not the
+    fixed point: for om in (0, 2) the solve reaches the sparse direct solution."""
+    N, L = 64, 5.0
+    h = 2 * L / N
+    rng = np.random.default_rng(21)
+    f = np.zeros((N + 1, N + 1))
+    f[1:-1, 1:-1] = rng.standard_normal((N - 1, N - 1))
+    k2 = rng.uniform(0.0, 10.0, (N + 1, N + 1)) if helm else None
+    ref = spla.spsolve(_scipy_operator(N, h, k2), f[1:-1, 1:-1].ravel()).reshape(N - 1, N - 1)
+    st, u, cyc, _ = oracle_mod.mg_solve(N, h, f, k2=k2, omega=omega)
+    assert st == 0
+    assert np.abs(u[1:-1, 1:-1] - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_over_relaxation_speeds_the_v_cycle(oracle_mod):
+    """Over-relaxed red-black smoothing (om = 1.175) on the Poisson model
+    problem: the residual falls by a factor below 0.025 per V(2,2) cycle, where
+    plain Gauss-Seidel (om = 1) gives 0.05-0.06, the textbook rate of V-cycles
+    with red-black Gauss-Seidel, full weighting and bilinear prolongation; and
+    an over-relaxation past the optimum (om = 1.3) is slower again."""
+    N, L = 128, 8.0
+    h = 2 * L / N
+    rng = np.random.default_rng(1)
+    f = np.zeros((N + 1, N + 1))
+    f[1:-1, 1:-1] = rng.standard_normal((N - 1, N - 1))
+    A = _scipy_operator(N, h)
+
+    def rate(om):
+        r = []
+        for m in (4, 5, 6):
+            _, u, _, _ = oracle_mod.mg_solve(N, h, f, rtol=0.0, max_cycles=m, omega=om)
+            r.append(np.linalg.norm(f[1:-1, 1:-1].ravel() - A @ u[1:-1, 1:-1].ravel()))
+        return max(r[1] / r[0], r[2] / r[1])
+
+    r1, r_opt, r_over = rate(1.0), rate(1.175), rate(1.3)
+    print(f"rate per cycle: om=1 {r1:.4f}, om=1.175 {r_opt:.4f}, om=1.3 {r_over:.4f}")
+    assert 0.04 <= r1 <= 0.07
+    assert r_opt <= 0.025
+    assert r_over > r_opt
