@@ -1295,18 +1295,34 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_k2(int N, int pitch, 
                                                               double* __restrict__ out,
                                                               float* __restrict__ outf,
                                                               float* __restrict__ idf) {
-    for (int i = threadIdx.x; i < (N + 1) * (N + 1); i += kCoarseThreads) {
-        const int y = i / (N + 1), x = i - y * (N + 1);
-        const bool bnd = x == 0 || y == 0 || x == N || y == N;
-        out[i] = bnd ? 0.0 : k2top[(size_t)y * pitch + x];
+    // every level in LDS: the top level's loads in batches of kB per thread,
+    // the restrictions from LDS, the three outputs written once
+    __shared__ double sk[coarse_nodes()];
+    constexpr int kB = 8;
+    const int tid = threadIdx.x;
+    const int nt = (N + 1) * (N + 1);
+    for (int base = 0; base < nt; base += kB * kCoarseThreads) {
+        double v[kB];
+#pragma unroll
+        for (int b = 0; b < kB; ++b) {
+            const int i = base + b * kCoarseThreads + tid;
+            const int y = i / (N + 1), x = i - y * (N + 1);
+            const bool ok = i < nt && x != 0 && y != 0 && x != N && y != N;
+            v[b] = ok ? k2top[(size_t)y * pitch + x] : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < kB; ++b) {
+            const int i = base + b * kCoarseThreads + tid;
+            if (i < nt) sk[i] = v[b];
+        }
     }
     __syncthreads();
     int off = 0;
     for (int nf = N; nf > 2; nf /= 2) {
         const int nc = nf / 2, w = nf + 1;
-        const double* kf = out + off;
-        double* kc = out + off + (nf + 1) * (nf + 1);
-        for (int i = threadIdx.x; i < (nc + 1) * (nc + 1); i += kCoarseThreads) {
+        const double* kf = sk + off;
+        double* kc = sk + off + (nf + 1) * (nf + 1);
+        for (int i = tid; i < (nc + 1) * (nc + 1); i += kCoarseThreads) {
             const int J = i / (nc + 1), I = i - J * (nc + 1);
             double v = 0.0;
             if (I >= 1 && J >= 1 && I <= nc - 1 && J <= nc - 1) {
@@ -1320,13 +1336,16 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_k2(int N, int pitch, 
         __syncthreads();
         off += (nf + 1) * (nf + 1);
     }
-    // float copies and 1 / (4 + h_l^2 k2) for the coarse kernel's FP32 sweeps
+    // double and float copies and 1 / (4 + h_l^2 k2) for the coarse kernel's
+    // FP32 sweeps
     off = 0;
     for (int n = N, l = 0; n >= 2; n /= 2, ++l) {
         const double hl = h * (double)(1 << l);
         const float h2 = (float)(hl * hl);
-        for (int i = threadIdx.x; i < (n + 1) * (n + 1); i += kCoarseThreads) {
-            const float kf = (float)out[off + i];
+        for (int i = tid; i < (n + 1) * (n + 1); i += kCoarseThreads) {
+            const double kd = sk[off + i];
+            const float kf = (float)kd;
+            out[off + i] = kd;
             outf[off + i] = kf;
             idf[off + i] = 1.f / (4.f + h2 * kf);
         }

@@ -452,20 +452,34 @@ __global__ __launch_bounds__(kPushThreads) void k_push(
 }
 
 // Step_Size_Refinement (Algorithm 1) with the floor dxi0/k (Sec. V.A); writes
-// the slice record (xi, dxi, vmax, flags) and advances xi.  One block.
-__global__ __launch_bounds__(256) void k_dxi(int nparts, const double* __restrict__ vmax_part,
-                                             double* __restrict__ st, double dxi0, double h,
-                                             int adaptive, int refine_k,
-                                             const int32_t* __restrict__ flags,
-                                             double* __restrict__ rec) {
-    __shared__ double red[4];
+// the slice record (xi, dxi, vmax, flags) and advances xi.  One block; each
+// thread issues its loads of the push-block maxima in batches of kDxiBatch so
+// that their latencies overlap (max is exact in any order).
+constexpr int kDxiThreads = 1024, kDxiBatch = 8;
+__global__ __launch_bounds__(kDxiThreads) void k_dxi(int nparts,
+                                                     const double* __restrict__ vmax_part,
+                                                     double* __restrict__ st, double dxi0,
+                                                     double h, int adaptive, int refine_k,
+                                                     const int32_t* __restrict__ flags,
+                                                     double* __restrict__ rec) {
+    __shared__ double red[kDxiThreads / 64];
     double v = 0.0;
-    for (int b = threadIdx.x; b < nparts; b += 256) v = fmax(v, vmax_part[b]);
+    for (int b0 = threadIdx.x; b0 < nparts; b0 += kDxiBatch * kDxiThreads) {
+        double w[kDxiBatch];
+#pragma unroll
+        for (int q = 0; q < kDxiBatch; ++q) {
+            const int b = b0 + q * kDxiThreads;
+            w[q] = b < nparts ? vmax_part[b] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kDxiBatch; ++q) v = fmax(v, w[q]);
+    }
     for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
     if (threadIdx.x != 0) return;
-    const double vmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    double vmax = red[0];
+    for (int q = 1; q < kDxiThreads / 64; ++q) vmax = fmax(vmax, red[q]);
     double d = dxi0;
     if (adaptive) {
         const double V0 = h / dxi0;
@@ -607,7 +621,7 @@ wandqs_status push_and_step(wandqs_ctx* c, int rec_slot) {
     double* rec = rec_slot >= 0 ? c->rec + 4 * (size_t)rec_slot : nullptr;
     {
         ProfScope ps(c, "k_dxi", 8.0 * c->n_push_blocks);
-        WQ_KLAUNCH(ps, k_dxi, dim3(1), dim3(256), 0, c->stream, c->n_push_blocks, c->vmax_part,
+        WQ_KLAUNCH(ps, k_dxi, dim3(1), dim3(kDxiThreads), 0, c->stream, c->n_push_blocks, c->vmax_part,
                            c->st, c->cfg.dxi0, c->h, c->cfg.adaptive, c->cfg.refine_k, c->flags, rec);
     }
     WQ_LAUNCH_CHECK();
