@@ -615,6 +615,7 @@ __global__ __launch_bounds__(64 * NW) void k_mg_down_reg(DownArgs<E> a) {
     const RegExchange<E, R, K, NW> xc{xb};
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int z = blockIdx.z;  // right-hand side of a split launch (R = 1, one per z)
     const int N = a.N;
     int bx, by;
     tile_of_block(bx, by);
@@ -625,7 +626,7 @@ __global__ __launch_bounds__(64 * NW) void k_mg_down_reg(DownArgs<E> a) {
     const E om = (E)a.omega;
 
     E u[R][K][2], f[R][K][2], D[K][2], iD[K][2];
-    reg_load<E, R, HELM, K>(u, f, D, iD, a.u_in, a.f, a.k2, a.pitch, gx, gy0, N, a.h * a.h);
+    reg_load<E, R, HELM, K>(u, f, D, iD, a.u_in + z, a.f + z, a.k2, a.pitch, gx, gy0, N, a.h * a.h);
 
     bool upd[K][2], dom[K][2], own[K];
 #pragma unroll
@@ -671,7 +672,7 @@ __global__ __launch_bounds__(64 * NW) void k_mg_down_reg(DownArgs<E> a) {
         if (threadIdx.x == 0) {
             const int b = by * gridDim.x + bx;
 #pragma unroll
-            for (int q = 0; q < 3 * R; ++q) a.norm_part[q * a.nblk + b] = acc[q];
+            for (int q = 0; q < 3 * R; ++q) a.norm_part[(3 * z + q) * a.nblk + b] = acc[q];
         }
     }
 
@@ -693,7 +694,7 @@ __global__ __launch_bounds__(64 * NW) void k_mg_down_reg(DownArgs<E> a) {
         if (own[k] && own_x && gx <= N - 1 && gy <= N - 1)
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                *reinterpret_cast<V2*>(a.u_out[r] + (size_t)gy * a.pitch + gx) =
+                *reinterpret_cast<V2*>(a.u_out[r + z] + (size_t)gy * a.pitch + gx) =
                     V2{u[r][k][0], u[r][k][1]};
     }
 
@@ -729,7 +730,7 @@ __global__ __launch_bounds__(64 * NW) void k_mg_down_reg(DownArgs<E> a) {
                          E(2) * (sl + rr[r][k][1] + a0 + rr[r][k + 1][0]) +
                          (sm + am + sp + rr[r][k + 1][1])) *
                         E(1.0 / 16.0);
-                a.f_c[r][(size_t)J * a.pitch_c + I] = v;
+                a.f_c[r + z][(size_t)J * a.pitch_c + I] = v;
             }
         }
     }
@@ -747,6 +748,7 @@ __global__ __launch_bounds__(64 * NW) void k_mg_up_reg(UpArgs<E> a) {
     const RegExchange<E, R, K, NW> xc{xb};
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int z = blockIdx.z;  // right-hand side of a split launch (R = 1, one per z)
     const int N = a.N, Nc = N / 2;
     int bx, by;
     tile_of_block(bx, by);
@@ -757,7 +759,7 @@ __global__ __launch_bounds__(64 * NW) void k_mg_up_reg(UpArgs<E> a) {
     const E om = (E)a.omega;
 
     E u[R][K][2], f[R][K][2], D[K][2], iD[K][2];
-    reg_load<E, R, HELM, K>(u, f, D, iD, a.u_mid, a.f, a.k2, a.pitch, gx, gy0, N, a.h * a.h);
+    reg_load<E, R, HELM, K>(u, f, D, iD, a.u_mid + z, a.f + z, a.k2, a.pitch, gx, gy0, N, a.h * a.h);
 
     // coarse correction at (I, J0 + m) and (I + 1, J0 + m), m = 0 .. K/2
     constexpr int KC = K / 2 + 1;
@@ -770,8 +772,8 @@ __global__ __launch_bounds__(64 * NW) void k_mg_up_reg(UpArgs<E> a) {
         const bool inL = inJ && I >= 0 && I <= Nc, inR = inJ && I + 1 >= 0 && I + 1 <= Nc;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            eL[r][m] = inL ? a.e_c[r][(size_t)J * a.pitch_c + I] : E(0);
-            eR[r][m] = inR ? a.e_c[r][(size_t)J * a.pitch_c + I + 1] : E(0);
+            eL[r][m] = inL ? a.e_c[r + z][(size_t)J * a.pitch_c + I] : E(0);
+            eR[r][m] = inR ? a.e_c[r + z][(size_t)J * a.pitch_c + I + 1] : E(0);
         }
     }
 
@@ -814,7 +816,7 @@ __global__ __launch_bounds__(64 * NW) void k_mg_up_reg(UpArgs<E> a) {
         if (own[k] && own_x && gx <= N - 1 && gy <= N - 1)
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                *reinterpret_cast<V2*>(a.u_out[r] + (size_t)gy * a.pitch + gx) =
+                *reinterpret_cast<V2*>(a.u_out[r + z] + (size_t)gy * a.pitch + gx) =
                     V2{u[r][k][0], u[r][k][1]};
     }
 }
@@ -1492,15 +1494,17 @@ dim3 tiles(int N, int T = kTile) { return dim3((N + T - 1) / T, (N + T - 1) / T)
 
 // Tiles of a level's down or up pass: register tiles on the levels
 // N >= c->reg_tile_min, LDS tiles of edge tile_for(N) below.  TX x TY owned
-// nodes per workgroup.
+// nodes per workgroup.  split: register tiles run two right-hand sides as
+// separate workgroups of one launch (grid z), not both in each workgroup.
 struct PassGeom {
-    bool reg;
+    bool reg, split;
     int TX, TY;
     dim3 grid;
 };
 PassGeom pass_geom(const wandqs_ctx* c, int N, int nu, bool down) {
     PassGeom g{};
     g.reg = N >= c->reg_tile_min;
+    g.split = c->reg_split;
     if (g.reg) {
         const int halo = down ? 2 * nu + 2 : 2 * nu;
         g.TX = 128 - 2 * halo;
@@ -1536,16 +1540,24 @@ template <typename E>
 void down_pass(int R, bool helm, const DownArgs<E>& a, int nu, const PassGeom& g, hipStream_t s,
                const ProfScope& ps) {
     if (!g.reg) return down<E>(R, helm, a, nu, g.grid, s, ps, g.TX);
-    if (R == 1) helm ? launch_down_reg<E, 1, true>(a, nu, g.grid, s, ps) : launch_down_reg<E, 1, false>(a, nu, g.grid, s, ps);
-    else helm ? launch_down_reg<E, 2, true>(a, nu, g.grid, s, ps) : launch_down_reg<E, 2, false>(a, nu, g.grid, s, ps);
+    if (R == 1 || g.split) {
+        const dim3 gz(g.grid.x, g.grid.y, R);
+        helm ? launch_down_reg<E, 1, true>(a, nu, gz, s, ps) : launch_down_reg<E, 1, false>(a, nu, gz, s, ps);
+    } else {
+        helm ? launch_down_reg<E, 2, true>(a, nu, g.grid, s, ps) : launch_down_reg<E, 2, false>(a, nu, g.grid, s, ps);
+    }
 }
 
 template <typename E>
 void up_pass(int R, bool helm, const UpArgs<E>& a, int nu, const PassGeom& g, hipStream_t s,
              const ProfScope& ps) {
     if (!g.reg) return up<E>(R, helm, a, nu, g.grid, s, ps, g.TX);
-    if (R == 1) helm ? launch_up_reg<E, 1, true>(a, nu, g.grid, s, ps) : launch_up_reg<E, 1, false>(a, nu, g.grid, s, ps);
-    else helm ? launch_up_reg<E, 2, true>(a, nu, g.grid, s, ps) : launch_up_reg<E, 2, false>(a, nu, g.grid, s, ps);
+    if (R == 1 || g.split) {
+        const dim3 gz(g.grid.x, g.grid.y, R);
+        helm ? launch_up_reg<E, 1, true>(a, nu, gz, s, ps) : launch_up_reg<E, 1, false>(a, nu, gz, s, ps);
+    } else {
+        helm ? launch_up_reg<E, 2, true>(a, nu, g.grid, s, ps) : launch_up_reg<E, 2, false>(a, nu, g.grid, s, ps);
+    }
 }
 
 const char* type_name(double) { return "double"; }
@@ -1607,7 +1619,7 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
         const double nodes = (double)L.N * L.N;
         char nm[64];
         if (g.reg)
-            prof_name(c, nm, sizeof nm, "k_mg_down_reg<%s, %d, %s, %d, %d>@%d", type_name(E()), R,
+            prof_name(c, nm, sizeof nm, "k_mg_down_reg<%s, %d, %s, %d, %d>@%d", type_name(E()), g.split ? 1 : R,
                           helm ? "true" : "false", c->cfg.nu_pre, kRegWaves, L.N);
         else
             prof_name(c, nm, sizeof nm, "k_mg_down<%s, %d, %s, %d, %d>@%d", type_name(E()), R,
@@ -1707,7 +1719,7 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
         char nm[64];
         const PassGeom g = pass_geom(c, L.N, c->cfg.nu_post, false);
         if (g.reg)
-            prof_name(c, nm, sizeof nm, "k_mg_up_reg<%s, %d, %s, %d, %d>@%d", type_name(E()), R,
+            prof_name(c, nm, sizeof nm, "k_mg_up_reg<%s, %d, %s, %d, %d>@%d", type_name(E()), g.split ? 1 : R,
                           helm ? "true" : "false", c->cfg.nu_post, kRegWaves, L.N);
         else
             prof_name(c, nm, sizeof nm, "k_mg_up<%s, %d, %s, %d, %d>@%d", type_name(E()), R,

@@ -269,14 +269,18 @@ def test_mg_zero_rhs_nonzero_guess(torch_cuda, N, helm):
 @pytest.mark.parametrize("helm", [False, True])
 def test_register_tiles_bitwise_equal_lds_tiles(torch_cuda, monkeypatch, precision, helm):
     """The register-tile pass kernels of the large levels against the LDS tile
-    kernels (WANDQS_MG_TILES=lds): three fixed V-cycles on 1024^2 and 2048^2
-    give the same bits, and so does a full C5 slice."""
+    kernels (WANDQS_MG_TILES=lds), and with both right-hand sides in every
+    workgroup (WANDQS_MG_SPLIT=0) against one per workgroup: three fixed
+    V-cycles on 1024^2 and 2048^2 give the same bits, and so does a full C5
+    slice."""
     outs = []
-    for mode in (None, "lds"):
-        if mode:
+    for mode in (None, "lds", "fused"):
+        monkeypatch.delenv("WANDQS_MG_TILES", raising=False)
+        monkeypatch.delenv("WANDQS_MG_SPLIT", raising=False)
+        if mode == "lds":
             monkeypatch.setenv("WANDQS_MG_TILES", mode)
-        else:
-            monkeypatch.delenv("WANDQS_MG_TILES", raising=False)
+        elif mode == "fused":
+            monkeypatch.setenv("WANDQS_MG_SPLIT", "0")
         res = []
         for N in (1024, 2048):
             cfg = wi.scaled(wi.config("C1"), n_cells=N, half_width=6.0, mg_rtol=0.0,
@@ -300,8 +304,9 @@ def test_register_tiles_bitwise_equal_lds_tiles(torch_cuda, monkeypatch, precisi
             res.append(sim.get_state()["particles"].cpu().numpy().copy())
             sim.close()
         outs.append(res)
-    for a, b in zip(*outs):
-        assert np.array_equal(a, b), float(np.abs(a - b).max())
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            assert np.array_equal(a, b), float(np.abs(a - b).max())
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
