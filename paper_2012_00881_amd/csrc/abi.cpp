@@ -105,7 +105,9 @@ void set_sizes(wandqs_ctx* c, const wandqs_config* cfg, int32_t n_slices) {
         const char* e = std::getenv("WANDQS_MG_TILES");
         c->reg_tile_min = (e && std::strcmp(e, "lds") == 0) ? INT_MAX : wq::reg_tile_min_default();
         const char* sp = std::getenv("WANDQS_MG_SPLIT");
-        c->reg_split = !(sp && std::strcmp(sp, "0") == 0);
+        const std::string spm = sp ? sp : "";
+        c->reg_split = !(spm == "0" || spm == "lds");
+        c->lds_split = !(spm == "0" || spm == "reg");
         const char* g = std::getenv("WANDQS_GRAPHS");
         c->graphs_on = g && std::strcmp(g, "1") == 0;
     }

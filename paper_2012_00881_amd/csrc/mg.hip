@@ -206,6 +206,7 @@ __global__ __launch_bounds__(tile_threads<T>()) void k_mg_down(DownArgs<E> a) {
     __shared__ double red[(NT / 64) * 3 * R];
 
     const int tid = threadIdx.x;
+    const int z = blockIdx.z;  // right-hand side of a split launch (R = 1, one per z)
     const int N = a.N;
     int bx, by;
     tile_of_block(bx, by);
@@ -215,7 +216,7 @@ __global__ __launch_bounds__(tile_threads<T>()) void k_mg_down(DownArgs<E> a) {
     const E om = (E)a.omega;
 
     E fr[R][KP][2], Dr[KP][2], iDr[KP][2];
-    tile_load<E, R, HELM, EX, EY, KP, NT>(su, fr, Dr, iDr, a.u_in, a.f, a.k2, a.pitch, ex0, ey0, N,
+    tile_load<E, R, HELM, EX, EY, KP, NT>(su, fr, Dr, iDr, a.u_in + z, a.f + z, a.k2, a.pitch, ex0, ey0, N,
                                       a.h * a.h);
     __syncthreads();
 
@@ -257,7 +258,7 @@ __global__ __launch_bounds__(tile_threads<T>()) void k_mg_down(DownArgs<E> a) {
         if (tid == 0) {
             const int b = by * gridDim.x + bx;
 #pragma unroll
-            for (int q = 0; q < 3 * R; ++q) a.norm_part[q * a.nblk + b] = acc[q];
+            for (int q = 0; q < 3 * R; ++q) a.norm_part[(3 * z + q) * a.nblk + b] = acc[q];
         }
     }
 
@@ -281,7 +282,7 @@ __global__ __launch_bounds__(tile_threads<T>()) void k_mg_down(DownArgs<E> a) {
             if (p < NP && lx >= HL && lx < HL + T && ly >= HL && ly < HL + T && gx <= N - 1 &&
                 gy <= N - 1)
 #pragma unroll
-                for (int r = 0; r < R; ++r) a.u_out[r][(size_t)gy * a.pitch + gx] = su[r][l];
+                for (int r = 0; r < R; ++r) a.u_out[r + z][(size_t)gy * a.pitch + gx] = su[r][l];
             const bool interior = p < NP && lx >= HL - 1 && lx <= HL + T - 1 && ly >= HL - 1 &&
                                   ly <= HL + T - 1 && gx >= 1 && gx <= N - 1 && gy >= 1 &&
                                   gy <= N - 1;
@@ -321,7 +322,7 @@ __global__ __launch_bounds__(tile_threads<T>()) void k_mg_down(DownArgs<E> a) {
                      (q[l - EX - 1] + q[l - EX + 1] + q[l + EX - 1] + q[l + EX + 1])) *
                     E(1.0 / 16.0);
             }
-            a.f_c[r][(size_t)J * a.pitch_c + I] = v;
+            a.f_c[r + z][(size_t)J * a.pitch_c + I] = v;
         }
     }
 }
@@ -353,6 +354,7 @@ __global__ __launch_bounds__(tile_threads<T>()) void k_mg_up(UpArgs<E> a) {
     __shared__ E se[R][CX * CY];
 
     const int tid = threadIdx.x;
+    const int z = blockIdx.z;  // right-hand side of a split launch (R = 1, one per z)
     const int N = a.N, Nc = N / 2;
     int bx, by;
     tile_of_block(bx, by);
@@ -363,14 +365,14 @@ __global__ __launch_bounds__(tile_threads<T>()) void k_mg_up(UpArgs<E> a) {
     const E om = (E)a.omega;
 
     E fr[R][KP][2], Dr[KP][2], iDr[KP][2];
-    tile_load<E, R, HELM, EX, EY, KP, NT>(su, fr, Dr, iDr, a.u_mid, a.f, a.k2, a.pitch, ex0, ey0, N,
+    tile_load<E, R, HELM, EX, EY, KP, NT>(su, fr, Dr, iDr, a.u_mid + z, a.f + z, a.k2, a.pitch, ex0, ey0, N,
                                       a.h * a.h);
     for (int i = tid; i < CX * CY; i += NT) {
         const int cy = i / CX, cx = i - cy * CX;
         const int I = cx0 + cx, J = cy0 + cy;
         const bool in = I >= 0 && I <= Nc && J >= 0 && J <= Nc;
 #pragma unroll
-        for (int r = 0; r < R; ++r) se[r][i] = in ? a.e_c[r][(size_t)J * a.pitch_c + I] : E(0);
+        for (int r = 0; r < R; ++r) se[r][i] = in ? a.e_c[r + z][(size_t)J * a.pitch_c + I] : E(0);
     }
     __syncthreads();
 
@@ -417,7 +419,7 @@ __global__ __launch_bounds__(tile_threads<T>()) void k_mg_up(UpArgs<E> a) {
                 gy <= N - 1)
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    a.u_out[r][(size_t)gy * a.pitch + gx] = su[r][ly * EX + lx];
+                    a.u_out[r + z][(size_t)gy * a.pitch + gx] = su[r][ly * EX + lx];
         }
     }
 }
@@ -1494,10 +1496,11 @@ dim3 tiles(int N, int T = kTile) { return dim3((N + T - 1) / T, (N + T - 1) / T)
 
 // Tiles of a level's down or up pass: register tiles on the levels
 // N >= c->reg_tile_min, LDS tiles of edge tile_for(N) below.  TX x TY owned
-// nodes per workgroup.  split: register tiles run two right-hand sides as
-// separate workgroups of one launch (grid z), not both in each workgroup.
+// nodes per workgroup.  split (register tiles) and split_lds (LDS tiles): two
+// right-hand sides run as separate workgroups of one launch (grid z), not both
+// in each workgroup.
 struct PassGeom {
-    bool reg, split;
+    bool reg, split, split_lds;
     int TX, TY;
     dim3 grid;
 };
@@ -1505,6 +1508,7 @@ PassGeom pass_geom(const wandqs_ctx* c, int N, int nu, bool down) {
     PassGeom g{};
     g.reg = N >= c->reg_tile_min;
     g.split = c->reg_split;
+    g.split_lds = c->lds_split;
     if (g.reg) {
         const int halo = down ? 2 * nu + 2 : 2 * nu;
         g.TX = 128 - 2 * halo;
@@ -1539,7 +1543,10 @@ void launch_up_reg(const UpArgs<E>& a, int nu, dim3 grid, hipStream_t s, const P
 template <typename E>
 void down_pass(int R, bool helm, const DownArgs<E>& a, int nu, const PassGeom& g, hipStream_t s,
                const ProfScope& ps) {
-    if (!g.reg) return down<E>(R, helm, a, nu, g.grid, s, ps, g.TX);
+    if (!g.reg) {
+        if (g.split_lds) return down<E>(1, helm, a, nu, dim3(g.grid.x, g.grid.y, R), s, ps, g.TX);
+        return down<E>(R, helm, a, nu, g.grid, s, ps, g.TX);
+    }
     if (R == 1 || g.split) {
         const dim3 gz(g.grid.x, g.grid.y, R);
         helm ? launch_down_reg<E, 1, true>(a, nu, gz, s, ps) : launch_down_reg<E, 1, false>(a, nu, gz, s, ps);
@@ -1551,7 +1558,10 @@ void down_pass(int R, bool helm, const DownArgs<E>& a, int nu, const PassGeom& g
 template <typename E>
 void up_pass(int R, bool helm, const UpArgs<E>& a, int nu, const PassGeom& g, hipStream_t s,
              const ProfScope& ps) {
-    if (!g.reg) return up<E>(R, helm, a, nu, g.grid, s, ps, g.TX);
+    if (!g.reg) {
+        if (g.split_lds) return up<E>(1, helm, a, nu, dim3(g.grid.x, g.grid.y, R), s, ps, g.TX);
+        return up<E>(R, helm, a, nu, g.grid, s, ps, g.TX);
+    }
     if (R == 1 || g.split) {
         const dim3 gz(g.grid.x, g.grid.y, R);
         helm ? launch_up_reg<E, 1, true>(a, nu, gz, s, ps) : launch_up_reg<E, 1, false>(a, nu, gz, s, ps);
@@ -1622,7 +1632,7 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
             prof_name(c, nm, sizeof nm, "k_mg_down_reg<%s, %d, %s, %d, %d>@%d", type_name(E()), g.split ? 1 : R,
                           helm ? "true" : "false", c->cfg.nu_pre, kRegWaves, L.N);
         else
-            prof_name(c, nm, sizeof nm, "k_mg_down<%s, %d, %s, %d, %d>@%d", type_name(E()), R,
+            prof_name(c, nm, sizeof nm, "k_mg_down<%s, %d, %s, %d, %d>@%d", type_name(E()), g.split_lds ? 1 : R,
                           helm ? "true" : "false", c->cfg.nu_pre, g.TX, L.N);
         ProfScope ps(c, nm, nodes * ((a.u_in[0] ? eb * R : 0.0) + eb * R + (helm ? 8.0 : 0.0) +
                                      eb * R + eb * R / 4));
@@ -1722,7 +1732,7 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
             prof_name(c, nm, sizeof nm, "k_mg_up_reg<%s, %d, %s, %d, %d>@%d", type_name(E()), g.split ? 1 : R,
                           helm ? "true" : "false", c->cfg.nu_post, kRegWaves, L.N);
         else
-            prof_name(c, nm, sizeof nm, "k_mg_up<%s, %d, %s, %d, %d>@%d", type_name(E()), R,
+            prof_name(c, nm, sizeof nm, "k_mg_up<%s, %d, %s, %d, %d>@%d", type_name(E()), g.split_lds ? 1 : R,
                           helm ? "true" : "false", c->cfg.nu_post, g.TX, L.N);
         ProfScope ps(c, nm, nodes * (eb * R + eb * R / 4 + eb * R + (helm ? 8.0 : 0.0) + eb * R));
         up_pass<E>(R, helm, a, c->cfg.nu_post, g, s, ps);

@@ -179,10 +179,11 @@ struct wandqs_ctx {
     // levels N >= reg_tile_min run the register-tile pass kernels (environment
     // WANDQS_MG_TILES=lds at init: never; the LDS tiles give the same bits)
     int reg_tile_min = 0;
-    // register tiles run the two right-hand sides of a solve as separate
-    // workgroups of one launch (environment WANDQS_MG_SPLIT=0 at init: both in
-    // every workgroup; the same bits either way)
-    bool reg_split = true;
+    // the tile kernels run the two right-hand sides of a solve as separate
+    // workgroups of one launch (environment WANDQS_MG_SPLIT at init: 0, both in
+    // every workgroup; reg, split on the register-tile levels only; lds, on the
+    // LDS-tile levels only; the same bits in every case)
+    bool reg_split = true, lds_split = true;
     // environment WANDQS_GRAPHS=1 at init: multigrid cycles replay as HIP
     // graphs, captured on cap_stream at their first use (the kernels and their
     // arguments are those of the direct launches; on the 1024^2 job the
