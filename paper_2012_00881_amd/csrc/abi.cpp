@@ -104,6 +104,9 @@ void set_sizes(wandqs_ctx* c, const wandqs_config* cfg, int32_t n_slices) {
     {
         const char* e = std::getenv("WANDQS_MG_TILES");
         c->reg_tile_min = (e && std::strcmp(e, "lds") == 0) ? INT_MAX : wq::reg_tile_min_default();
+        if (e && std::atoi(e) >= 8) c->reg_tile_min = std::atoi(e);  // smallest register-tile level
+        const char* st = std::getenv("WANDQS_MG_SMALL");
+        c->small_tile_max = st && std::atoi(st) >= 8 ? std::atoi(st) : wq::small_tile_max_default();
         const char* sp = std::getenv("WANDQS_MG_SPLIT");
         const std::string spm = sp ? sp : "";
         c->reg_split = !(spm == "0" || spm == "lds");

@@ -55,7 +55,9 @@ constexpr int kCoarseThreads = 1024;
 #endif
 template <int T>
 constexpr int tile_threads() { return T >= 64 ? 1024 : (T >= 32 ? 512 : 256); }
-int tile_for(int N) { return N <= WQ_SMALL_TILE_MAX ? 16 : (N >= (WQ_BIG_TILE_MIN) ? 64 : 32); }
+int tile_for(const wandqs_ctx* c, int N) {
+    return N <= c->small_tile_max ? 16 : (N >= (WQ_BIG_TILE_MIN) ? 64 : 32);
+}
 
 // Deterministic block sum of NV values; the result is valid in thread 0.
 template <int NV, int NT>
@@ -1514,7 +1516,7 @@ PassGeom pass_geom(const wandqs_ctx* c, int N, int nu, bool down) {
         g.TX = 128 - 2 * halo;
         g.TY = kRegRows * kRegWaves - 2 * halo;
     } else {
-        g.TX = g.TY = tile_for(N);
+        g.TX = g.TY = tile_for(c, N);
     }
     g.grid = dim3((N + g.TX - 1) / g.TX, (N + g.TY - 1) / g.TY);
     return g;
@@ -1786,6 +1788,7 @@ void mixed_iteration(wandqs_ctx* c, int R, bool helm, const Hier<double>& hz, in
 }  // namespace
 
 int reg_tile_min_default() { return WQ_REG_TILE_MIN; }
+int small_tile_max_default() { return WQ_SMALL_TILE_MAX; }
 
 void dst_tables(int n, double H, float* S, float* M) {
     const double pi = 3.14159265358979323846;

@@ -184,6 +184,9 @@ struct wandqs_ctx {
     // every workgroup; reg, split on the register-tile levels only; lds, on the
     // LDS-tile levels only; the same bits in every case)
     bool reg_split = true, lds_split = true;
+    // LDS tiles of 16 x 16 owned nodes on the levels N <= small_tile_max
+    // (environment WANDQS_MG_SMALL at init), 32 x 32 or 64 x 64 above
+    int small_tile_max = 0;
     // environment WANDQS_GRAPHS=1 at init: multigrid cycles replay as HIP
     // graphs, captured on cap_stream at their first use (the kernels and their
     // arguments are those of the direct launches; on the 1024^2 job the
@@ -273,6 +276,8 @@ namespace wq {
 size_t carve(wandqs_ctx* c, char* base);
 // smallest level that runs the register-tile pass kernels by default
 int reg_tile_min_default();
+// largest level with 16 x 16 LDS tiles by default
+int small_tile_max_default();
 // host tables of the exact coarse-level Poisson solve on an n^2 level (S and
 // M, [n][n] each; n = 64 or 128)
 void dst_tables(int n, double H, float* S, float* M);
