@@ -157,40 +157,45 @@ __global__ void k_scatter(int64_t P, const int32_t* __restrict__ key,
     if (valid) perm[start[k] + top - len + (lane - head)] = (int32_t)i;
 }
 
-// Order each cell's particles by permanent ID: an insertion sort by one thread
-// for cells of up to kSmallCell particles; crowded cells (blowout) go on a list
-// for k_cell_sort_big.
+// Order each cell's particles by permanent ID into perm_out: the particle in
+// slot i of the scatter's order (perm) goes to slot s + r of its cell, r the
+// number of the cell's particles with a smaller ID (IDs are unique).  One
+// thread per slot; its cell's IDs are loaded in batches of kRankBatch so that
+// their latencies overlap.  Cells of more than kSmallCell particles
+// (blowout) go on a list for k_cell_sort_big.
 constexpr int kSmallCell = 16;
+constexpr int kRankBatch = 8;
 constexpr int kBigCellLds = 4096;
-__global__ void k_cell_sort(int ncell, const int32_t* __restrict__ start,
-                            int32_t* __restrict__ perm, const int32_t* __restrict__ id,
+__global__ void k_cell_rank(int64_t P, const int32_t* __restrict__ start,
+                            const int32_t* __restrict__ perm, const int32_t* __restrict__ id,
+                            const int32_t* __restrict__ key, int32_t* __restrict__ perm_out,
                             int32_t* __restrict__ big, int32_t* __restrict__ big_n) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const int32_t p = perm[i];
+    const int c = key[p];
     const int s = start[c], e = start[c + 1];
     if (e - s > kSmallCell) {
-        big[atomicAdd(big_n, 1)] = c;
+        if (i == s) big[atomicAdd(big_n, 1)] = c;
         return;
     }
-    for (int i = s + 1; i < e; ++i) {
-        const int32_t p = perm[i];
-        const int32_t pid = id[p];
-        int j = i - 1;
-        while (j >= s && id[perm[j]] > pid) {
-            perm[j + 1] = perm[j];
-            --j;
-        }
-        perm[j + 1] = p;
+    const int32_t mine = id[p];
+    int r = 0;
+    for (int j0 = s; j0 < e; j0 += kRankBatch) {
+        int32_t q[kRankBatch];
+#pragma unroll
+        for (int t = 0; t < kRankBatch; ++t) q[t] = j0 + t < e ? perm[j0 + t] : p;
+#pragma unroll
+        for (int t = 0; t < kRankBatch; ++t) r += id[q[t]] < mine;
     }
+    perm_out[s + r] = p;
 }
 
-// Crowded cells, one workgroup each: a particle's place is the number of the
-// cell's particles with a smaller ID (IDs are unique).  The new order goes to
-// tmp first, so that every rank is counted on the old one.
+// Crowded cells, one workgroup each, the same ranks into perm_out.
 __global__ __launch_bounds__(256) void k_cell_sort_big(const int32_t* __restrict__ start,
-                                                       int32_t* __restrict__ perm,
+                                                       const int32_t* __restrict__ perm,
                                                        const int32_t* __restrict__ id,
-                                                       int32_t* __restrict__ tmp,
+                                                       int32_t* __restrict__ perm_out,
                                                        const int32_t* __restrict__ big,
                                                        const int32_t* __restrict__ big_n) {
     __shared__ int32_t sid[kBigCellLds];
@@ -209,10 +214,8 @@ __global__ __launch_bounds__(256) void k_cell_sort_big(const int32_t* __restrict
                 for (int j = 0; j < n; ++j) r += sid[j] < v;
             else
                 for (int j = 0; j < n; ++j) r += id[perm[s + j]] < v;
-            tmp[s + r] = perm[s + i];
+            perm_out[s + r] = perm[s + i];
         }
-        __syncthreads();
-        for (int i = threadIdx.x; i < n; i += blockDim.x) perm[s + i] = tmp[s + i];
         __syncthreads();
     }
 }
@@ -233,10 +236,18 @@ __global__ void k_permute(int64_t P, const int32_t* __restrict__ perm,
     id2[j] = id[s];
 }
 
+// particles per batch of loads in the deposits (latencies overlap; the sums
+// keep the cell's particle order).  The density deposit has one thread per
+// cell of a tile's (kDepTile + 1)^2 cells, in five wavefronts; the current
+// and stress deposit, whose LDS sets the occupancy, keeps four (measured).
+constexpr int kDepBatch = 8, kDepBatchJ = 4;
+constexpr int kDepThreads = 320, kDepThreadsJ = 256;
+static_assert((kDepTile + 1) * (kDepTile + 1) <= kDepThreads, "one cell per deposit thread");
+
 // n* = deposit(1) (Sec. III.B: surface density) and the psi right-hand side
 // n* - n0 (eq. (12)) on the interior nodes.
 template <int TN>
-__global__ __launch_bounds__(256) void k_deposit_n(int N, double L, double h, double wdep,
+__global__ __launch_bounds__(kDepThreads) void k_deposit_n(int N, double L, double h, double wdep,
                                                    double n0, int pitch,
                                                    const double* __restrict__ x,
                                                    const double* __restrict__ y,
@@ -254,13 +265,25 @@ __global__ __launch_bounds__(256) void k_deposit_n(int N, double L, double h, do
         double s00 = 0.0, s10 = 0.0, s01 = 0.0, s11 = 0.0;
         if (ga >= 0 && ga < N && gb >= 0 && gb < N) {
             const int cell = gb * N + ga;
-            for (int k = start[cell]; k < start[cell + 1]; ++k) {
-                const double dx = (x[k] + L) / h - ga;
-                const double dy = (y[k] + L) / h - gb;
-                s00 += (1.0 - dx) * (1.0 - dy);
-                s10 += dx * (1.0 - dy);
-                s01 += (1.0 - dx) * dy;
-                s11 += dx * dy;
+            const int k1 = start[cell + 1];
+            // the cell's particles in order, loaded kDepBatch at a time
+            for (int k0 = start[cell]; k0 < k1; k0 += kDepBatch) {
+                double xv[kDepBatch], yv[kDepBatch];
+#pragma unroll
+                for (int t = 0; t < kDepBatch; ++t) {
+                    xv[t] = k0 + t < k1 ? x[k0 + t] : 0.0;
+                    yv[t] = k0 + t < k1 ? y[k0 + t] : 0.0;
+                }
+#pragma unroll
+                for (int t = 0; t < kDepBatch; ++t) {
+                    if (k0 + t >= k1) break;
+                    const double dx = (xv[t] + L) / h - ga;
+                    const double dy = (yv[t] + L) / h - gb;
+                    s00 += (1.0 - dx) * (1.0 - dy);
+                    s10 += dx * (1.0 - dy);
+                    s01 += (1.0 - dx) * dy;
+                    s11 += dx * dy;
+                }
             }
         }
         corner[c][0] = s00;
@@ -289,7 +312,7 @@ __global__ __launch_bounds__(256) void k_deposit_n(int N, double L, double h, do
 // V_i = p_i / g_i (eq. (6)); deposit j = n*<V> (eq. (9)) and T = n*<V V>
 // (below eq. (16)).  Output order: jx, jy, Txx, Txy, Tyy.
 template <int TN>
-__global__ __launch_bounds__(256) void k_deposit_jT(int N, double L, double h, double wdep,
+__global__ __launch_bounds__(kDepThreadsJ) void k_deposit_jT(int N, double L, double h, double wdep,
                                                     int pitch, const double* __restrict__ x,
                                                     const double* __restrict__ y,
                                                     const double* __restrict__ px,
@@ -322,20 +345,35 @@ __global__ __launch_bounds__(256) void k_deposit_jT(int N, double L, double h, d
             const size_t g = (size_t)gb * pitch + ga;
             const double p00 = psi[g], p10 = psi[g + 1], p01 = psi[g + pitch],
                          p11 = psi[g + pitch + 1];
-            for (int k = start[cell]; k < start[cell + 1]; ++k) {
-                const double dx = (x[k] + L) / h - ga;
-                const double dy = (y[k] + L) / h - gb;
-                const double gi = 1.0 + cic_gather(p00, p10, p01, p11, dx, dy);
-                bad |= !(gi > 0.0);
-                const double ig = 1.0 / gi;
-                const double vx = px[k] * ig, vy = py[k] * ig;
-                const double q[M] = {vx, vy, vx * vx, vx * vy, vy * vy};
-                const double w[4] = {(1.0 - dx) * (1.0 - dy), dx * (1.0 - dy), (1.0 - dx) * dy,
-                                     dx * dy};
+            const int k1 = start[cell + 1];
+            // the cell's particles in order, loaded kDepBatchJ at a time
+            for (int k0 = start[cell]; k0 < k1; k0 += kDepBatchJ) {
+                double xv[kDepBatchJ], yv[kDepBatchJ], pxv[kDepBatchJ], pyv[kDepBatchJ];
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
+                for (int t = 0; t < kDepBatchJ; ++t) {
+                    const bool in = k0 + t < k1;
+                    xv[t] = in ? x[k0 + t] : 0.0;
+                    yv[t] = in ? y[k0 + t] : 0.0;
+                    pxv[t] = in ? px[k0 + t] : 0.0;
+                    pyv[t] = in ? py[k0 + t] : 0.0;
+                }
 #pragma unroll
-                    for (int m = 0; m < M; ++m) s[r][m] += w[r] * q[m];
+                for (int t = 0; t < kDepBatchJ; ++t) {
+                    if (k0 + t >= k1) break;
+                    const double dx = (xv[t] + L) / h - ga;
+                    const double dy = (yv[t] + L) / h - gb;
+                    const double gi = 1.0 + cic_gather(p00, p10, p01, p11, dx, dy);
+                    bad |= !(gi > 0.0);
+                    const double ig = 1.0 / gi;
+                    const double vx = pxv[t] * ig, vy = pyv[t] * ig;
+                    const double q[M] = {vx, vy, vx * vx, vx * vy, vy * vy};
+                    const double w[4] = {(1.0 - dx) * (1.0 - dy), dx * (1.0 - dy),
+                                         (1.0 - dx) * dy, dx * dy};
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int m = 0; m < M; ++m) s[r][m] += w[r] * q[m];
+                }
             }
         }
 #pragma unroll
@@ -561,18 +599,19 @@ wandqs_status slice_sort(wandqs_ctx* c) {
                            c->cell_start, c->cell_count, c->perm);
     }
     {
-        ProfScope ps(c, "k_cell_sort", (double)c->P * 12.0 + (double)ncell * 4.0);
-        WQ_KLAUNCH(ps, k_cell_sort, dim3(blocks_for(ncell, 256)), dim3(256), 0, s, ncell,
-                           c->cell_start, c->perm, c->pid[a], c->big_cells, c->big_count);
+        ProfScope ps(c, "k_cell_rank", (double)c->P * 20.0 + (double)ncell * 4.0);
+        WQ_KLAUNCH(ps, k_cell_rank, dim3(blocks_for(c->P, 256)), dim3(256), 0, s, c->P,
+                           c->cell_start, c->perm, c->pid[a], c->key, c->perm2, c->big_cells,
+                           c->big_count);
     }
-    {  // the key array is free after the scatter: scratch for the crowded cells
+    {
         ProfScope ps(c, "k_cell_sort_big", 0.0);
         WQ_KLAUNCH(ps, k_cell_sort_big, dim3(std::min(ncell, 512)), dim3(256), 0, s,
-                           c->cell_start, c->perm, c->pid[a], c->key, c->big_cells, c->big_count);
+                           c->cell_start, c->perm, c->pid[a], c->perm2, c->big_cells, c->big_count);
     }
     {
         ProfScope ps(c, "k_permute", (double)c->P * 76.0);
-        WQ_KLAUNCH(ps, k_permute, dim3(blocks_for(c->P, 256)), dim3(256), 0, s, c->P, c->perm,
+        WQ_KLAUNCH(ps, k_permute, dim3(blocks_for(c->P, 256)), dim3(256), 0, s, c->P, c->perm2,
                            c->pa[a][0], c->pa[a][1], c->pa[a][2], c->pa[a][3], c->pid[a], c->pa[b][0],
                            c->pa[b][1], c->pa[b][2], c->pa[b][3], c->pid[b]);
     }
@@ -586,7 +625,7 @@ wandqs_status deposit_n(wandqs_ctx* c) {
     const double wdep = c->cfg.n0 / c->ppc;
     {
         ProfScope ps(c, "k_deposit_n<16>", (double)c->P * 16.0 + (double)c->N * c->N * 4.0 + (double)(c->N + 1) * (c->N + 1) * 16.0);
-        WQ_KLAUNCH(ps, (k_deposit_n<kDepTile>), dim3(nt, nt), dim3(256), 0, c->stream, c->N, c->L,
+        WQ_KLAUNCH(ps, (k_deposit_n<kDepTile>), dim3(nt, nt), dim3(kDepThreads), 0, c->stream, c->N, c->L,
                            c->h, wdep, c->cfg.n0, c->lev[0].pitch, c->pa[c->cur][0], c->pa[c->cur][1],
                            c->cell_start, c->mom[0], c->lev[0].f[0]);
     }
@@ -600,7 +639,7 @@ wandqs_status deposit_jT(wandqs_ctx* c) {
     const int k = c->cur;
     {
         ProfScope ps(c, "k_deposit_jT<16>", (double)c->P * 32.0 + (double)c->N * c->N * 4.0 + (double)(c->N + 1) * (c->N + 1) * 48.0);
-        WQ_KLAUNCH(ps, (k_deposit_jT<kDepTile>), dim3(nt, nt), dim3(256), 0, c->stream, c->N, c->L,
+        WQ_KLAUNCH(ps, (k_deposit_jT<kDepTile>), dim3(nt, nt), dim3(kDepThreadsJ), 0, c->stream, c->N, c->L,
                            c->h, wdep, c->lev[0].pitch, c->pa[k][0], c->pa[k][1], c->pa[k][2],
                            c->pa[k][3], c->cell_start, c->fields[0], c->mom[1], c->mom[2], c->mom[3],
                            c->mom[4], c->mom[5], c->flags);
