@@ -417,6 +417,25 @@ __device__ __forceinline__ double grad_y(const double* psi, int pitch, int N, do
     return (psi[(size_t)(b + 1) * pitch + a] - psi[(size_t)(b - 1) * pitch + a]) * ih2;
 }
 
+// grad psi at every node (grad_x, grad_y above) into two node arrays, once per
+// slice, so that the push gathers it like the other fields.
+__global__ void k_grad_psi(int N, double h, int pitch, const double* __restrict__ psi,
+                           double* __restrict__ gx, double* __restrict__ gy) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y;
+    if (a > N) return;
+    const double ih = 1.0 / h, ih2 = 0.5 * ih;
+    const size_t g = (size_t)b * pitch + a;
+    gx[g] = grad_x(psi, pitch, N, ih, ih2, a, b);
+    gy[g] = grad_y(psi, pitch, N, ih, ih2, a, b);
+}
+
+// Nodes a and a + 1 of a row in one 16-byte load (8-byte aligned).
+__device__ __forceinline__ double2 ld_pair(const double* p) {
+    double2 v;
+    __builtin_memcpy(&v, p, sizeof(v));
+    return v;
+}
+
 // Boris-like push over dxi with the fields frozen at this slice (eqs. (6)-(7)):
 // half kick by F = gamma grad psi / g + e_z x B_perp with gamma from the old
 // momentum, rotation by the (e_z x V) Bz term through angle 2 atan(Bz dxi / 2g),
@@ -424,7 +443,8 @@ __device__ __forceinline__ double grad_y(const double* psi, int pitch, int N, do
 // maximum of |p_new| / g_i for Algorithm 1.
 __global__ __launch_bounds__(kPushThreads) void k_push(
     int64_t P, int N, double L, double h, int pitch, const double* __restrict__ st,
-    const double* __restrict__ psi, const double* __restrict__ Bx, const double* __restrict__ By,
+    const double* __restrict__ psi, const double* __restrict__ gpx, const double* __restrict__ gpy,
+    const double* __restrict__ Bx, const double* __restrict__ By,
     const double* __restrict__ Bz, double* __restrict__ x, double* __restrict__ y,
     double* __restrict__ px, double* __restrict__ py, double* __restrict__ vmax_part) {
     __shared__ double red[kPushThreads / 64];
@@ -437,21 +457,20 @@ __global__ __launch_bounds__(kPushThreads) void k_push(
         double dx, dy;
         cic(xi_, L, h, N, a, dx);
         cic(yi, L, h, N, b, dy);
+        // the cell's four nodes: (a, a + 1) of rows b and b + 1 (a + 1 <= N < pitch)
         const size_t g = (size_t)b * pitch + a;
-        const double ih = 1.0 / h, ih2 = 0.5 * ih;
-        const double g_i =
-            1.0 + cic_gather(psi[g], psi[g + 1], psi[g + pitch], psi[g + pitch + 1], dx, dy);
-        const double Gx = cic_gather(grad_x(psi, pitch, N, ih, ih2, a, b),
-                                     grad_x(psi, pitch, N, ih, ih2, a + 1, b),
-                                     grad_x(psi, pitch, N, ih, ih2, a, b + 1),
-                                     grad_x(psi, pitch, N, ih, ih2, a + 1, b + 1), dx, dy);
-        const double Gy = cic_gather(grad_y(psi, pitch, N, ih, ih2, a, b),
-                                     grad_y(psi, pitch, N, ih, ih2, a + 1, b),
-                                     grad_y(psi, pitch, N, ih, ih2, a, b + 1),
-                                     grad_y(psi, pitch, N, ih, ih2, a + 1, b + 1), dx, dy);
-        const double bx = cic_gather(Bx[g], Bx[g + 1], Bx[g + pitch], Bx[g + pitch + 1], dx, dy);
-        const double by = cic_gather(By[g], By[g + 1], By[g + pitch], By[g + pitch + 1], dx, dy);
-        const double bz = cic_gather(Bz[g], Bz[g + 1], Bz[g + pitch], Bz[g + pitch + 1], dx, dy);
+        const double2 p0 = ld_pair(psi + g), p1 = ld_pair(psi + g + pitch);
+        const double2 x0 = ld_pair(gpx + g), x1 = ld_pair(gpx + g + pitch);
+        const double2 y0 = ld_pair(gpy + g), y1 = ld_pair(gpy + g + pitch);
+        const double2 bx0 = ld_pair(Bx + g), bx1 = ld_pair(Bx + g + pitch);
+        const double2 by0 = ld_pair(By + g), by1 = ld_pair(By + g + pitch);
+        const double2 bz0 = ld_pair(Bz + g), bz1 = ld_pair(Bz + g + pitch);
+        const double g_i = 1.0 + cic_gather(p0.x, p0.y, p1.x, p1.y, dx, dy);
+        const double Gx = cic_gather(x0.x, x0.y, x1.x, x1.y, dx, dy);
+        const double Gy = cic_gather(y0.x, y0.y, y1.x, y1.y, dx, dy);
+        const double bx = cic_gather(bx0.x, bx0.y, bx1.x, bx1.y, dx, dy);
+        const double by = cic_gather(by0.x, by0.y, by1.x, by1.y, dx, dy);
+        const double bz = cic_gather(bz0.x, bz0.y, bz1.x, bz1.y, dx, dy);
 
         const double ig = 1.0 / g_i;
         const double gamma = (1.0 + pxi * pxi + pyi * pyi + g_i * g_i) * (0.5 * ig);
@@ -651,11 +670,16 @@ wandqs_status deposit_jT(wandqs_ctx* c) {
 wandqs_status push_and_step(wandqs_ctx* c, int rec_slot) {
     const int k = c->cur;
     {
-        ProfScope ps(c, "k_push", (double)c->P * 64.0 + (double)(c->N + 1) * (c->N + 1) * 32.0);
+        ProfScope pg(c, "k_grad_psi", (double)(c->N + 1) * (c->N + 1) * 24.0);
+        WQ_KLAUNCH(pg, k_grad_psi, dim3((c->N + 1 + 127) / 128, c->N + 1), dim3(128), 0, c->stream,
+                           c->N, c->h, c->lev[0].pitch, c->fields[0], c->gpsi[0], c->gpsi[1]);
+    }
+    {
+        ProfScope ps(c, "k_push", (double)c->P * 64.0 + (double)(c->N + 1) * (c->N + 1) * 48.0);
         WQ_KLAUNCH(ps, k_push, dim3(c->n_push_blocks), dim3(kPushThreads), 0, c->stream, c->P,
-                           c->N, c->L, c->h, c->lev[0].pitch, c->st, c->fields[0], c->fields[3],
-                           c->fields[4], c->fields[2], c->pa[k][0], c->pa[k][1], c->pa[k][2],
-                           c->pa[k][3], c->vmax_part);
+                           c->N, c->L, c->h, c->lev[0].pitch, c->st, c->fields[0], c->gpsi[0],
+                           c->gpsi[1], c->fields[3], c->fields[4], c->fields[2], c->pa[k][0],
+                           c->pa[k][1], c->pa[k][2], c->pa[k][3], c->vmax_part);
     }
     double* rec = rec_slot >= 0 ? c->rec + 4 * (size_t)rec_slot : nullptr;
     {

@@ -212,6 +212,7 @@ struct wandqs_ctx {
     double* fields_prev3[5] = {};
     double* mom[6] = {};
     double* jz = nullptr;
+    double* gpsi[2] = {};  // grad psi at the nodes (x, y), for the push
     double* k2lev = nullptr;  // k2 of the coarse-kernel levels (dense, concatenated)
     float* k2levf = nullptr;  // the same in float, and 1 / (4 + h_l^2 k2) in float
     float* idlevf = nullptr;
