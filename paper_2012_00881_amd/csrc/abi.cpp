@@ -337,7 +337,6 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
     }
     c->key = (int32_t*)take(sizeof(int32_t) * P);
     c->perm = (int32_t*)take(sizeof(int32_t) * P);
-    c->perm2 = (int32_t*)take(sizeof(int32_t) * P);
     for (int q = 0; q < 2; ++q) c->gpsi[q] = arr(0);
     c->cell_count = (int32_t*)take(sizeof(int32_t) * ncell);
     c->cell_start = (int32_t*)take(sizeof(int32_t) * (ncell + 1));

@@ -157,19 +157,35 @@ __global__ void k_scatter(int64_t P, const int32_t* __restrict__ key,
     if (valid) perm[start[k] + top - len + (lane - head)] = (int32_t)i;
 }
 
-// Order each cell's particles by permanent ID into perm_out: the particle in
-// slot i of the scatter's order (perm) goes to slot s + r of its cell, r the
-// number of the cell's particles with a smaller ID (IDs are unique).  One
+// Place each particle in the new order, by cell and within a cell by
+// permanent ID: the particle in slot i of the scatter's order (perm) moves to
+// slot s + r of its cell, r the number of the cell's particles with a smaller
+// ID (IDs are unique), and its x, y, px, py and ID are copied there.  One
 // thread per slot; its cell's IDs are loaded in batches of kRankBatch so that
-// their latencies overlap.  Cells of more than kSmallCell particles
-// (blowout) go on a list for k_cell_sort_big.
+// their latencies overlap.  Cells of more than kSmallCell particles (blowout)
+// go on a list for k_cell_sort_big.
 constexpr int kSmallCell = 16;
 constexpr int kRankBatch = 8;
 constexpr int kBigCellLds = 4096;
+
+struct PartArrays {
+    const double *x, *y, *px, *py;
+    const int32_t* id;
+    double *x2, *y2, *px2, *py2;
+    int32_t* id2;
+    __device__ __forceinline__ void move(int32_t from, int to) const {
+        x2[to] = x[from];
+        y2[to] = y[from];
+        px2[to] = px[from];
+        py2[to] = py[from];
+        id2[to] = id[from];
+    }
+};
+
 __global__ void k_cell_rank(int64_t P, const int32_t* __restrict__ start,
-                            const int32_t* __restrict__ perm, const int32_t* __restrict__ id,
-                            const int32_t* __restrict__ key, int32_t* __restrict__ perm_out,
-                            int32_t* __restrict__ big, int32_t* __restrict__ big_n) {
+                            const int32_t* __restrict__ perm, const int32_t* __restrict__ key,
+                            PartArrays pa, int32_t* __restrict__ big,
+                            int32_t* __restrict__ big_n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P) return;
     const int32_t p = perm[i];
@@ -179,6 +195,7 @@ __global__ void k_cell_rank(int64_t P, const int32_t* __restrict__ start,
         if (i == s) big[atomicAdd(big_n, 1)] = c;
         return;
     }
+    const int32_t* __restrict__ id = pa.id;
     const int32_t mine = id[p];
     int r = 0;
     for (int j0 = s; j0 < e; j0 += kRankBatch) {
@@ -188,17 +205,17 @@ __global__ void k_cell_rank(int64_t P, const int32_t* __restrict__ start,
 #pragma unroll
         for (int t = 0; t < kRankBatch; ++t) r += id[q[t]] < mine;
     }
-    perm_out[s + r] = p;
+    pa.move(p, s + r);
 }
 
-// Crowded cells, one workgroup each, the same ranks into perm_out.
+// Crowded cells, one workgroup each: the same ranks and moves.
 __global__ __launch_bounds__(256) void k_cell_sort_big(const int32_t* __restrict__ start,
                                                        const int32_t* __restrict__ perm,
-                                                       const int32_t* __restrict__ id,
-                                                       int32_t* __restrict__ perm_out,
+                                                       PartArrays pa,
                                                        const int32_t* __restrict__ big,
                                                        const int32_t* __restrict__ big_n) {
     __shared__ int32_t sid[kBigCellLds];
+    const int32_t* __restrict__ id = pa.id;
     const int nbig = *big_n;
     for (int b = blockIdx.x; b < nbig; b += gridDim.x) {
         const int c = big[b];
@@ -214,34 +231,26 @@ __global__ __launch_bounds__(256) void k_cell_sort_big(const int32_t* __restrict
                 for (int j = 0; j < n; ++j) r += sid[j] < v;
             else
                 for (int j = 0; j < n; ++j) r += id[perm[s + j]] < v;
-            perm_out[s + r] = perm[s + i];
+            pa.move(perm[s + i], s + r);
         }
         __syncthreads();
     }
 }
 
-__global__ void k_permute(int64_t P, const int32_t* __restrict__ perm,
-                          const double* __restrict__ x, const double* __restrict__ y,
-                          const double* __restrict__ px, const double* __restrict__ py,
-                          const int32_t* __restrict__ id, double* __restrict__ x2,
-                          double* __restrict__ y2, double* __restrict__ px2,
-                          double* __restrict__ py2, int32_t* __restrict__ id2) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= P) return;
-    const int s = perm[j];
-    x2[j] = x[s];
-    y2[j] = y[s];
-    px2[j] = px[s];
-    py2[j] = py[s];
-    id2[j] = id[s];
-}
-
 // particles per batch of loads in the deposits (latencies overlap; the sums
-// keep the cell's particle order).  The density deposit has one thread per
-// cell of a tile's (kDepTile + 1)^2 cells, in five wavefronts; the current
-// and stress deposit, whose LDS sets the occupancy, keeps four (measured).
+// keep the cell's particle order), one thread per cell of a tile's
+// (tile + 1)^2 cells.  The density deposit uses kDepTile = 16 (five
+// wavefronts); the current and stress deposit, whose LDS sets the occupancy,
+// 15 x 15 node tiles (16 x 16 cells, four wavefronts: the fastest measured of
+// 8..16).
 constexpr int kDepBatch = 8, kDepBatchJ = 4;
-constexpr int kDepThreads = 320, kDepThreadsJ = 256;
+#ifndef WQ_DEP_TILE_J
+#define WQ_DEP_TILE_J 15
+#endif
+#ifndef WQ_DEP_THREADS_J
+#define WQ_DEP_THREADS_J 256
+#endif
+constexpr int kDepThreads = 320, kDepTileJ = WQ_DEP_TILE_J, kDepThreadsJ = WQ_DEP_THREADS_J;
 static_assert((kDepTile + 1) * (kDepTile + 1) <= kDepThreads, "one cell per deposit thread");
 
 // n* = deposit(1) (Sec. III.B: surface density) and the psi right-hand side
@@ -617,22 +626,17 @@ wandqs_status slice_sort(wandqs_ctx* c) {
         WQ_KLAUNCH(ps, k_scatter, dim3(blocks_for(c->P, 256)), dim3(256), 0, s, c->P, c->key,
                            c->cell_start, c->cell_count, c->perm);
     }
+    const PartArrays pa{c->pa[a][0], c->pa[a][1], c->pa[a][2], c->pa[a][3], c->pid[a],
+                        c->pa[b][0], c->pa[b][1], c->pa[b][2], c->pa[b][3], c->pid[b]};
     {
-        ProfScope ps(c, "k_cell_rank", (double)c->P * 20.0 + (double)ncell * 4.0);
+        ProfScope ps(c, "k_cell_rank", (double)c->P * 88.0 + (double)ncell * 4.0);
         WQ_KLAUNCH(ps, k_cell_rank, dim3(blocks_for(c->P, 256)), dim3(256), 0, s, c->P,
-                           c->cell_start, c->perm, c->pid[a], c->key, c->perm2, c->big_cells,
-                           c->big_count);
+                           c->cell_start, c->perm, c->key, pa, c->big_cells, c->big_count);
     }
     {
         ProfScope ps(c, "k_cell_sort_big", 0.0);
         WQ_KLAUNCH(ps, k_cell_sort_big, dim3(std::min(ncell, 512)), dim3(256), 0, s,
-                           c->cell_start, c->perm, c->pid[a], c->perm2, c->big_cells, c->big_count);
-    }
-    {
-        ProfScope ps(c, "k_permute", (double)c->P * 76.0);
-        WQ_KLAUNCH(ps, k_permute, dim3(blocks_for(c->P, 256)), dim3(256), 0, s, c->P, c->perm2,
-                           c->pa[a][0], c->pa[a][1], c->pa[a][2], c->pa[a][3], c->pid[a], c->pa[b][0],
-                           c->pa[b][1], c->pa[b][2], c->pa[b][3], c->pid[b]);
+                           c->cell_start, c->perm, pa, c->big_cells, c->big_count);
     }
     WQ_LAUNCH_CHECK();
     c->cur = b;
@@ -653,12 +657,12 @@ wandqs_status deposit_n(wandqs_ctx* c) {
 }
 
 wandqs_status deposit_jT(wandqs_ctx* c) {
-    const int nt = (c->N + 1 + kDepTile - 1) / kDepTile;
+    const int nt = (c->N + 1 + kDepTileJ - 1) / kDepTileJ;
     const double wdep = c->cfg.n0 / c->ppc;
     const int k = c->cur;
     {
-        ProfScope ps(c, "k_deposit_jT<16>", (double)c->P * 32.0 + (double)c->N * c->N * 4.0 + (double)(c->N + 1) * (c->N + 1) * 48.0);
-        WQ_KLAUNCH(ps, (k_deposit_jT<kDepTile>), dim3(nt, nt), dim3(kDepThreadsJ), 0, c->stream, c->N, c->L,
+        ProfScope ps(c, "k_deposit_jT<15>", (double)c->P * 32.0 + (double)c->N * c->N * 4.0 + (double)(c->N + 1) * (c->N + 1) * 48.0);
+        WQ_KLAUNCH(ps, (k_deposit_jT<kDepTileJ>), dim3(nt, nt), dim3(kDepThreadsJ), 0, c->stream, c->N, c->L,
                            c->h, wdep, c->lev[0].pitch, c->pa[k][0], c->pa[k][1], c->pa[k][2],
                            c->pa[k][3], c->cell_start, c->fields[0], c->mom[1], c->mom[2], c->mom[3],
                            c->mom[4], c->mom[5], c->flags);

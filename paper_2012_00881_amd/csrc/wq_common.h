@@ -230,7 +230,6 @@ struct wandqs_ctx {
     int cur = 0;
     int32_t *key = nullptr, *perm = nullptr, *cell_count = nullptr, *cell_start = nullptr,
             *scan_blk = nullptr;
-    int32_t* perm2 = nullptr;  // the scatter's order (perm) sorted by ID within each cell
     int32_t* big_cells = nullptr;  // [N*N] cells too crowded for one thread's sort
     int32_t* big_count = nullptr;  // their number
     int n_scan_blocks = 0;
