@@ -467,8 +467,11 @@ wandqs_status wandqs_init(const wandqs_config* cfg, int32_t n_slices, void* d_wo
         delete c;
         return WANDQS_E_HIP;
     };
-    if (hipHostMalloc((void**)&c->h_pin, sizeof(double) * (wq::kMaxSlots * wq::kNormVec + 8)) != hipSuccess)
+    // coherent: the kernels publish residual norms into it (mg_solve)
+    if (hipHostMalloc((void**)&c->h_pin, sizeof(double) * (wq::kMaxSlots * wq::kNormVec + 8),
+                      hipHostMallocCoherent) != hipSuccess)
         return bail("hipHostMalloc failed");
+    std::memset(c->h_pin, 0, sizeof(double) * (wq::kMaxSlots * wq::kNormVec + 8));
     if (hipMemsetAsync(d_workspace, 0, need, c->stream) != hipSuccess)
         return bail("hipMemsetAsync of the workspace failed");
 

@@ -17,6 +17,7 @@
 // All reductions (residual norms) have a fixed order: results are bitwise
 // reproducible.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1431,6 +1432,22 @@ __global__ __launch_bounds__(kThreads) void k_reduce_slots(const double* part, i
     if (threadIdx.x == 0) out[s * kNormVec + k] = acc[0];
 }
 
+// Publishes n reduced norms and the flags word into the host's coherent pinned
+// buffer, then, after a system-scope release, the sequence number seq: the
+// host waits for seq instead of synchronising the stream.
+__global__ __launch_bounds__(64) void k_publish(const double* __restrict__ src, int n,
+                                                const int32_t* __restrict__ flags,
+                                                double* dst, int32_t* dst_flags, uint32_t* dst_seq,
+                                                uint32_t seq) {
+    for (int i = threadIdx.x; i < n; i += 64) dst[i] = src[i];
+    if (threadIdx.x == 0) *dst_flags = *flags;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence_system();
+        __hip_atomic_store(dst_seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
 // Full weighting of a fine node array onto the interior coarse nodes (boundary 0).
 __global__ void k_restrict_fw(const double* fine, int pf, double* coarse, int pc, int Nc) {
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1851,6 +1868,24 @@ hipError_t run_cycle(wandqs_ctx* c, const CycleKey& key, F&& body) {
     return hipSuccess;
 }
 
+// Waits until the device has published sequence number seq (k_publish): a
+// bounded spin on the coherent host word, then a stream synchronisation,
+// which also reports a failed kernel.
+wandqs_status wait_published(wandqs_ctx* c, const uint32_t* h_seq, uint32_t seq) {
+    const auto t0 = std::chrono::steady_clock::now();
+    for (long it = 0;; ++it) {
+        if (__atomic_load_n(h_seq, __ATOMIC_ACQUIRE) == seq) return WANDQS_OK;
+        if ((it & 1023) == 1023 &&
+            std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(200))
+            break;
+        __builtin_ia32_pause();
+    }
+    WQ_HIP(hipStreamSynchronize(c->stream));
+    if (__atomic_load_n(h_seq, __ATOMIC_ACQUIRE) == seq) return WANDQS_OK;
+    c->err = "residual norms were not published by the device";
+    return WANDQS_E_HIP;
+}
+
 // Solve with the context's stop rule.  Tolerance mode (mg_rtol > 0) runs a batch
 // of V-cycles sized by the previous slice's count for this solve, reads the
 // residual norms back once per batch and adds single cycles until every
@@ -1941,13 +1976,18 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
         }
         if (graph_check() != WANDQS_OK) return WANDQS_E_HIP;
         WQ_LAUNCH_CHECK();
-        WQ_HIP(hipMemcpyAsync(hr + V * s0, c->norm_red + V * s0, sizeof(double) * V * ns,
-                              hipMemcpyDeviceToHost, s));
-        WQ_HIP(hipMemcpyAsync(hr + V * kMaxSlots, c->flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        WQ_HIP(hipStreamSynchronize(s));
+        int32_t* h_flags = reinterpret_cast<int32_t*>(hr + V * kMaxSlots);
+        uint32_t* h_seq = reinterpret_cast<uint32_t*>(hr + V * kMaxSlots + 1);
+        const uint32_t seq = ++c->pub_seq;
+        {
+            ProfScope ps(c, "k_publish", 8.0 * V * ns);
+            WQ_KLAUNCH(ps, k_publish, dim3(1), dim3(64), 0, s, c->norm_red + V * s0, V * ns,
+                               c->flags, hr + V * s0, h_flags, h_seq, seq);
+        }
+        WQ_LAUNCH_CHECK();
+        if (wait_published(c, h_seq, seq) != WANDQS_OK) return WANDQS_E_HIP;
         done += b;
-        int32_t fl;
-        std::memcpy(&fl, hr + V * kMaxSlots, sizeof(fl));
+        const int32_t fl = __atomic_load_n(h_flags, __ATOMIC_ACQUIRE);
         // first cycle count at which every rhs satisfies the stop rule
         int need = -1;
         for (int k = 0; k <= done && need < 0; ++k) {

@@ -262,7 +262,8 @@ struct wandqs_ctx {
     std::vector<double> probe_count;  // nodes in each probe disc
 
     // host side
-    double* h_pin = nullptr;  // pinned readback buffer
+    double* h_pin = nullptr;  // pinned coherent readback buffer
+    uint32_t pub_seq = 0;     // last sequence number published into h_pin
     int pred[wq::kPredKinds] = {1, 1, 1, 1, 1, 1, 1, 1};  // V-cycles of the last solve per kind (batch size)
     bool failed = false;
     int n_guess = 0;  // slices since init/set_state, up to kGuessMax (extrapolation order + 1)
