@@ -45,7 +45,10 @@ void prof_name(const wandqs_ctx* c, char* nm, size_t n, const char* fmt, A... a)
 #define WQ_SMALL_TILE_MAX 256
 #endif
 constexpr int kThreads = 256;  // norm and reduction kernels
-constexpr int kCoarseThreads = 1024;
+#ifndef WQ_COARSE_THREADS
+#define WQ_COARSE_THREADS 1024
+#endif
+constexpr int kCoarseThreads = WQ_COARSE_THREADS;
 // Tile kernels: 32 x 32 owned nodes with 512 threads, or 16 x 16 with 256
 // threads on the levels N <= WQ_SMALL_TILE_MAX (more workgroups and a shorter
 // chain of dependent LDS phases per workgroup where the grid is small).
