@@ -1000,58 +1000,87 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
     // loads in batches of kB per thread so that their latencies overlap
     constexpr int kB = 8;
     const int nt = (N + 1) * (N + 1);
-    for (int base = 0; base < nt; base += kB * kCoarseThreads) {
+    if (HELM && FAST && tot <= kB * kCoarseThreads) {
+        // one batch: u, f, k2 and 1/D all issued before the first LDS store
         E uv[kB], fv[kB];
+        float kv[kB], dv[kB];
 #pragma unroll
         for (int b = 0; b < kB; ++b) {
-            const int i = base + b * kCoarseThreads + tid;
+            const int i = b * kCoarseThreads + tid;
             const int y = i / (N + 1), x = i - y * (N + 1);
             const bool ok = i < nt && x != 0 && y != 0 && x != N && y != N;
             const size_t g = ok ? (size_t)y * a.pitch + x : 0;
             uv[b] = (ok && a.u_init[r]) ? a.u_init[r][g] : E(0);
             fv[b] = ok ? a.f[r][g] : E(0);
+            kv[b] = i < tot ? a.k2levf[i] : 0.f;
+            dv[b] = i < tot ? a.idlevf[i] : 0.f;
         }
 #pragma unroll
         for (int b = 0; b < kB; ++b) {
-            const int i = base + b * kCoarseThreads + tid;
+            const int i = b * kCoarseThreads + tid;
             if (i < nt) {
                 su[i] = (C)uv[b];
                 sf[i] = (C)fv[b];
             }
+            if (i < tot) {
+                sk[i] = (C)kv[b];
+                siD[i] = (C)dv[b];
+            }
         }
-    }
-    if (HELM && FAST)  // k2 and 1/D of every level, made once per solve by k_coarse_k2
-        for (int base = 0; base < tot; base += kB * kCoarseThreads) {
-            float kv[kB], dv[kB];
+    } else {
+        for (int base = 0; base < nt; base += kB * kCoarseThreads) {
+            E uv[kB], fv[kB];
 #pragma unroll
             for (int b = 0; b < kB; ++b) {
                 const int i = base + b * kCoarseThreads + tid;
-                kv[b] = i < tot ? a.k2levf[i] : 0.f;
-                dv[b] = i < tot ? a.idlevf[i] : 0.f;
+                const int y = i / (N + 1), x = i - y * (N + 1);
+                const bool ok = i < nt && x != 0 && y != 0 && x != N && y != N;
+                const size_t g = ok ? (size_t)y * a.pitch + x : 0;
+                uv[b] = (ok && a.u_init[r]) ? a.u_init[r][g] : E(0);
+                fv[b] = ok ? a.f[r][g] : E(0);
             }
 #pragma unroll
             for (int b = 0; b < kB; ++b) {
                 const int i = base + b * kCoarseThreads + tid;
-                if (i < tot) {
-                    sk[i] = (C)kv[b];
-                    siD[i] = (C)dv[b];
+                if (i < nt) {
+                    su[i] = (C)uv[b];
+                    sf[i] = (C)fv[b];
                 }
             }
         }
-    else if (HELM)
-        for (int base = 0; base < tot; base += kB * kCoarseThreads) {
-            double kv[kB];
+        if (HELM && FAST)  // k2 and 1/D of every level, made once per solve by k_coarse_k2
+            for (int base = 0; base < tot; base += kB * kCoarseThreads) {
+                float kv[kB], dv[kB];
 #pragma unroll
-            for (int b = 0; b < kB; ++b) {
-                const int i = base + b * kCoarseThreads + tid;
-                kv[b] = i < tot ? a.k2lev[i] : 0.0;
-            }
+                for (int b = 0; b < kB; ++b) {
+                    const int i = base + b * kCoarseThreads + tid;
+                    kv[b] = i < tot ? a.k2levf[i] : 0.f;
+                    dv[b] = i < tot ? a.idlevf[i] : 0.f;
+                }
 #pragma unroll
-            for (int b = 0; b < kB; ++b) {
-                const int i = base + b * kCoarseThreads + tid;
-                if (i < tot) sk[i] = (C)kv[b];
+                for (int b = 0; b < kB; ++b) {
+                    const int i = base + b * kCoarseThreads + tid;
+                    if (i < tot) {
+                        sk[i] = (C)kv[b];
+                        siD[i] = (C)dv[b];
+                    }
+                }
             }
-        }
+        else if (HELM)
+            for (int base = 0; base < tot; base += kB * kCoarseThreads) {
+                double kv[kB];
+#pragma unroll
+                for (int b = 0; b < kB; ++b) {
+                    const int i = base + b * kCoarseThreads + tid;
+                    kv[b] = i < tot ? a.k2lev[i] : 0.0;
+                }
+#pragma unroll
+                for (int b = 0; b < kB; ++b) {
+                    const int i = base + b * kCoarseThreads + tid;
+                    if (i < tot) sk[i] = (C)kv[b];
+                }
+            }
+    }
     __syncthreads();
 
     auto down = [&](int l) {

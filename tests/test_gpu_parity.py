@@ -137,6 +137,25 @@ def test_slice_matches_oracle_synthetic(torch_cuda, oracle_mod, name, N, seed, p
     _compare_slice(torch_cuda, oracle_mod, cfg, state)
 
 
+def test_slice_crowded_cells_matches_oracle(torch_cuda, oracle_mod):
+    """Cells of more than 16 particles take the crowded-cell path of the sort
+    (one workgroup per cell).  Three cells of 40, 24 and 17 particles, spread
+    over the particle index range so that the scatter interleaves them, then
+    one slice against the oracle; the state after it holds every particle
+    exactly once (ID order)."""
+    cfg = wi.scaled(wi.config("C2"), n_cells=128, precision="fp64")
+    state = wi.synthetic_state(cfg, seed=21, p_max=0.3, xi=2.0, field_amp=0.01)
+    N, L = cfg["n_cells"], cfg["half_width"]
+    h = 2 * L / N
+    rng = np.random.default_rng(5)
+    P = state["x"].size
+    for (ca, cb), n in (((40, 61), 40), ((41, 61), 24), ((90, 30), 17)):
+        idx = rng.choice(P, n, replace=False)
+        state["x"][idx] = -L + (ca + rng.uniform(0.05, 0.95, n)) * h
+        state["y"][idx] = -L + (cb + rng.uniform(0.05, 0.95, n)) * h
+    _compare_slice(torch_cuda, oracle_mod, cfg, state)
+
+
 def test_slice_matches_oracle_vortex(torch_cuda, oracle_mod):
     cfg = wi.scaled(wi.config("C2"), n_cells=256)
     state = wi.vortex_state(cfg, 0.8, 1.0, xi=2.2)
