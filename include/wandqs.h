@@ -118,8 +118,10 @@ typedef struct {
                                  half sweep moves to u + om (g - u), g the value that
                                  solves its own equation; 0 < om < 2, 0 selects
                                  1.175.  om = 1 is plain Gauss-Seidel. */
-    double mg_omega_helm;     /* the same for the Helmholtz solve (B_perp); 0
-                                 selects 1.125 */
+    double mg_omega_helm;     /* the same for the Helmholtz solve (B_perp) on its
+                                 levels with h^2 n0 <= 1/8; the coarser ones,
+                                 whose diagonal shift h^2 k2 is no longer small,
+                                 relax with om = 1; 0 selects 1.175 */
 } wandqs_config;
 
 typedef struct {

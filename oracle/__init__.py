@@ -302,17 +302,18 @@ def apply(N, h, u, k2=None):
 
 
 def mg_solve(N, h, f, u0=None, k2=None, rtol=1e-14, atol=0.0, max_cycles=50, nu1=2, nu2=2,
-             omega=0.0):
+             omega=0.0, k2_scale=1.0):
     """Multigrid solve of (L_h - k2) u = f with zero Dirichlet boundary; omega is
-    the relaxation factor of the smoothing sweeps (0: the operator's default)."""
+    the relaxation factor of the smoothing sweeps (0: the default), applied on
+    the Helmholtz levels with h^2 k2_scale <= 1/8 (k2_scale <= 0: on all)."""
     f = _f64(f)
     u = np.zeros_like(f) if u0 is None else _f64(u0).copy()
     cyc = C.c_int(0)
     rel = C.c_double(0)
     st = lib().oracle_mg_solve(int(N), C.c_double(h), _p(None if k2 is None else _f64(k2)),
                                _p(f), _p(u), C.c_double(rtol), C.c_double(atol), int(max_cycles),
-                               int(nu1), int(nu2), C.c_double(omega), C.byref(cyc),
-                               C.byref(rel))
+                               int(nu1), int(nu2), C.c_double(omega), C.c_double(k2_scale),
+                               C.byref(cyc), C.byref(rel))
     return st, u, cyc.value, rel.value
 
 

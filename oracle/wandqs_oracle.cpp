@@ -21,8 +21,9 @@
  *  - 5-point Laplacian of Sec. VII.B, eq. (33);
  *  - geometric multigrid: V(nu1,nu2) cycles, red-black Gauss-Seidel
  *    over-relaxed by a factor om (the paper names only "iterative relaxation";
- *    om = 1.175 for the Poisson operator and 1.125 for the Helmholtz one unless
- *    the configuration gives others), full weighting, bilinear prolongation,
+ *    om = 1.175 unless the configuration gives another), except on the
+ *    Helmholtz levels whose diagonal shift is no longer small, h^2 n0 > 1/8,
+ *    which relax with om = 1; full weighting, bilinear prolongation,
  *    rediscretised coarse operators, exact solve on the 2x2-cell grid (Sec. II
  *    item 4 and Sec. VII.A).
  *
@@ -318,22 +319,24 @@ void prolong_add(const Level<T>& coarse, Level<T>& fine) {
 }
 
 template <class T>
-void vcycle(std::vector<Level<T>>& lv, size_t l, int nu1, int nu2, double om) {
+void vcycle(std::vector<Level<T>>& lv, size_t l, int nu1, int nu2, double om, double h2max) {
     Level<T>& L = lv[l];
     if (L.N == 2) { /* one interior node, four zero boundary neighbours: exact */
         T k2 = L.k2.empty() ? T(0.0) : L.k2[L.id(1, 1)];
         L.u[L.id(1, 1)] = -L.f[L.id(1, 1)] / (4.0 / (L.h * L.h) + k2);
         return;
     }
-    smooth(L, nu1, om);
+    /* Helmholtz levels with h^2 > h2max relax without over-relaxation */
+    const double oml = (!L.k2.empty() && L.h * L.h > h2max) ? 1.0 : om;
+    smooth(L, nu1, oml);
     std::vector<T> r;
     residual(L, r);
     Level<T>& C = lv[l + 1];
     full_weighting(L, r, C, C.f);
     std::fill(C.u.begin(), C.u.end(), T(0.0));
-    vcycle(lv, l + 1, nu1, nu2, om);
+    vcycle(lv, l + 1, nu1, nu2, om, h2max);
     prolong_add(C, L);
-    smooth(L, nu2, om);
+    smooth(L, nu2, oml);
 }
 
 /* Solve (L_h - k2) u = f for the interior nodes with u = 0 on the boundary,
@@ -348,8 +351,11 @@ void vcycle(std::vector<Level<T>>& lv, size_t l, int nu1, int nu2, double om) {
  * must meet the rule: the derivative solves converge along with the value. */
 template <class T>
 int mg_solve(int N, double h, const T* k2, const T* f, T* u, double rtol, double atol,
-             int max_cycles, int nu1, int nu2, double om, int* cycles_out, double* rel_out) {
-    if (om == 0.0) om = k2 ? 1.125 : 1.175;
+             int max_cycles, int nu1, int nu2, double om, double k2_scale, int* cycles_out,
+             double* rel_out) {
+    if (om == 0.0) om = 1.175;
+    /* over-relaxation only where h^2 k2_scale <= 1/8 (k2_scale <= 0: everywhere) */
+    const double h2max = k2_scale > 0.0 ? 0.125 / k2_scale : std::numeric_limits<double>::infinity();
     std::vector<Level<T>> lv;
     for (int n = N; n >= 2; n /= 2) {
         Level<T> l;
@@ -394,7 +400,7 @@ int mg_solve(int N, double h, const T* k2, const T* f, T* u, double rtol, double
     };
     int cyc = 0;
     while (!all_done() && cyc < max_cycles) {
-        vcycle(lv, 0, nu1, nu2, om);
+        vcycle(lv, 0, nu1, nu2, om, h2max);
         ++cyc;
         residual(top, r);
         for (int c = 0; c < nc; ++c) {
@@ -603,7 +609,7 @@ int slice_step_t(const oracle_cfg* c, int P, T* x, T* y, T* px, T* py, T* pz, T*
     int status = ORC_OK;
     auto solve = [&](int k, const std::vector<T>* k2, const std::vector<T>& f, T* u) {
         int st = mg_solve<T>(g.N, g.h, k2 ? k2->data() : nullptr, f.data(), u, c->mg_rtol, c->mg_atol,
-                          c->mg_max_cycles, c->nu_pre, c->nu_post, k2 ? c->mg_omega_helm : c->mg_omega,
+                          c->mg_max_cycles, c->nu_pre, c->nu_post, k2 ? c->mg_omega_helm : c->mg_omega, c->n0,
                           &inf.cycles[k], &inf.rel_resid[k]);
         if (st != ORC_OK && status == ORC_OK) status = st;
     };
@@ -739,10 +745,10 @@ int oracle_apply(int N, double h, const double* k2, const double* u, double* out
 }
 
 int oracle_mg_solve(int N, double h, const double* k2, const double* f, double* u, double rtol,
-                    double atol, int max_cycles, int nu1, int nu2, double om, int* cycles,
-                    double* rel) {
+                    double atol, int max_cycles, int nu1, int nu2, double om, double k2_scale,
+                    int* cycles, double* rel) {
     if (N < 2 || (N & (N - 1)) || !(om >= 0.0 && om < 2.0)) return ORC_INVALID;
-    return mg_solve(N, h, k2, f, u, rtol, atol, max_cycles, nu1, nu2, om, cycles, rel);
+    return mg_solve(N, h, k2, f, u, rtol, atol, max_cycles, nu1, nu2, om, k2_scale, cycles, rel);
 }
 
 int oracle_beam_density(const oracle_cfg* c, double xi, double* out) {
@@ -1009,8 +1015,8 @@ int adjoint_solve(const Grid& g, const oracle_cfg& c, const std::vector<double>*
     int cyc;
     double rel;
     return mg_solve(g.N, g.h, k2 ? k2->data() : nullptr, rhs.data(), lam.data(), c.mg_rtol, c.mg_atol,
-                    c.mg_max_cycles, c.nu_pre, c.nu_post, k2 ? c.mg_omega_helm : c.mg_omega, &cyc,
-                    &rel);
+                    c.mg_max_cycles, c.nu_pre, c.nu_post, k2 ? c.mg_omega_helm : c.mg_omega, c.n0,
+                    &cyc, &rel);
 }
 
 } /* namespace */

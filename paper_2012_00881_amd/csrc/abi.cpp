@@ -439,9 +439,9 @@ wandqs_status wandqs_init(const wandqs_config* cfg, int32_t n_slices, void* d_wo
     }
     c->cfg = *cfg;
     // relaxation factors measured to minimise the V-cycles per solve on the
-    // blowout workloads (Poisson and Helmholtz operators separately)
+    // blowout workloads (the Helmholtz one on its levels with h^2 n0 <= 1/8)
     if (c->cfg.mg_omega == 0.0) c->cfg.mg_omega = 1.175;
-    if (c->cfg.mg_omega_helm == 0.0) c->cfg.mg_omega_helm = 1.125;
+    if (c->cfg.mg_omega_helm == 0.0) c->cfg.mg_omega_helm = 1.175;
     c->beams.assign(cfg->beams, cfg->beams + cfg->n_beams);
     c->probes.assign(cfg->probes, cfg->probes + cfg->n_probes);
     c->cfg.beams = nullptr;

@@ -45,6 +45,10 @@ void prof_name(const wandqs_ctx* c, char* nm, size_t n, const char* fmt, A... a)
 #define WQ_SMALL_TILE_MAX 256
 #endif
 constexpr int kThreads = 256;  // norm and reduction kernels
+// Helmholtz levels with h^2 n0 > kOmegaH2N0 smooth with plain Gauss-Seidel:
+// where the diagonal shift h^2 k2 (k2 ~ n0 in the plasma) is no longer small,
+// over-relaxation slows the cycle (measured).
+constexpr double kOmegaH2N0 = 0.125;
 #ifndef WQ_COARSE_THREADS
 #define WQ_COARSE_THREADS 1024
 #endif
@@ -843,7 +847,8 @@ struct CoarseArgs {
     const float* idlevf;
     E* u_out[2];
     int ncycles, nu1, nu2;
-    double omega;
+    double omega;   // relaxation factor of the levels with h^2 <= h2max (Helmholtz)
+    double h2max;   // coarser Helmholtz levels relax with factor 1
 };
 
 constexpr int coarse_nodes() {
@@ -1090,7 +1095,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
         const C* k2 = sk + (HELM ? off[l] : 0);
         const C* iD = siD + ((HELM && FAST) ? off[l] : 0);
         with_level<C, HELM, FAST>(Ns[l], [&](auto L) {
-            L.smooth(u, f, k2, iD, (C)(hl * hl), (C)a.omega, a.nu1);
+            L.smooth(u, f, k2, iD, (C)(hl * hl), (C)(HELM && hl * hl > a.h2max ? 1.0 : a.omega), a.nu1);
             L.restrict_to(u, f, k2, (C)(1.0 / (hl * hl)), su + off[l + 1], sf + off[l + 1], sr);
         });
     };
@@ -1100,7 +1105,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
         with_level<C, HELM, FAST>(Ns[l], [&](auto L) {
             L.prolong_add(u, su + off[l + 1]);
             L.smooth(u, sf + off[l], sk + (HELM ? off[l] : 0), siD + ((HELM && FAST) ? off[l] : 0),
-                     (C)(hl * hl), (C)a.omega, a.nu2);
+                     (C)(hl * hl), (C)(HELM && hl * hl > a.h2max ? 1.0 : a.omega), a.nu2);
         });
     };
     for (int cyc = 0; cyc < a.ncycles; ++cyc) {
@@ -1655,11 +1660,15 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
     // Poisson: the V-cycle ends with the exact solve on the 128^2 level when
     // that lies below a finer level
     const int lb = (!helm && dst128_used(c)) ? lc - 1 : lc;
-    const double om = helm ? c->cfg.mg_omega_helm : c->cfg.mg_omega;  // smoothing sweeps
+    // relaxation factor of the smoothing sweeps: the Helmholtz levels whose
+    // diagonal shift is no longer small (h^2 n0 > 1/8) relax with factor 1
+    const double om = helm ? c->cfg.mg_omega_helm : c->cfg.mg_omega;
+    const double h2max = helm ? kOmegaH2N0 / c->cfg.n0 : std::numeric_limits<double>::infinity();
+    auto omega_of = [&](double h) { return h * h > h2max ? 1.0 : om; };
     for (int l = 0; l < lb; ++l) {
         wq::Level& L = c->lev[l];
         DownArgs<E> a{};
-        a.omega = om;
+        a.omega = omega_of(L.h);
         a.N = L.N;
         a.h = L.h;
         a.pitch = L.pitch;
@@ -1717,6 +1726,7 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
         wq::Level& L = c->lev[lc];
         CoarseArgs<E> a{};
         a.omega = om;
+        a.h2max = h2max;
         a.N = L.N;
         a.h = L.h;
         a.pitch = L.pitch;
@@ -1763,7 +1773,7 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
     for (int l = lb - 1; l >= 0; --l) {
         wq::Level& L = c->lev[l];
         UpArgs<E> a{};
-        a.omega = om;
+        a.omega = omega_of(L.h);
         a.N = L.N;
         a.h = L.h;
         a.pitch = L.pitch;

@@ -239,3 +239,31 @@ def test_over_relaxation_speeds_the_v_cycle(oracle_mod):
     assert 0.04 <= r1 <= 0.07
     assert r_opt <= 0.025
     assert r_over > r_opt
+
+
+def test_helmholtz_coarse_levels_relax_without_over_relaxation(oracle_mod):
+    """Helmholtz model problem (k2 uniform in [0.5, 1.5], h = 1/8): over-relaxing
+    only the levels with h^2 k2_scale <= 1/8 (the default) gives a faster V-cycle
+    than over-relaxing every level, which is slower than plain Gauss-Seidel:
+    where the diagonal shift h^2 k2 is no longer small, over-relaxation hurts."""
+    N, L = 128, 8.0
+    h = 2 * L / N
+    rng = np.random.default_rng(3)
+    f = np.zeros((N + 1, N + 1))
+    f[1:-1, 1:-1] = rng.standard_normal((N - 1, N - 1))
+    k2 = rng.uniform(0.5, 1.5, (N + 1, N + 1))
+    A = _scipy_operator(N, h, k2)
+
+    def rate(**kw):
+        r = []
+        for m in (4, 5, 6):
+            _, u, _, _ = oracle_mod.mg_solve(N, h, f, k2=k2, rtol=0.0, max_cycles=m, **kw)
+            r.append(np.linalg.norm(f[1:-1, 1:-1].ravel() - A @ u[1:-1, 1:-1].ravel()))
+        return max(r[1] / r[0], r[2] / r[1])
+
+    r_rule = rate(omega=1.175)
+    r_all = rate(omega=1.175, k2_scale=0.0)
+    r_gs = rate(omega=1.0, k2_scale=0.0)
+    print(f"rate per cycle: level rule {r_rule:.4f}, all levels {r_all:.4f}, GS {r_gs:.4f}")
+    assert r_rule < 0.85 * r_gs
+    assert r_all > r_gs
