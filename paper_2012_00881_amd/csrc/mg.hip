@@ -348,6 +348,10 @@ struct UpArgs {
     const double* k2;
     E* u_out[2];
     double omega;
+    // (register tiles, double only) nullptr or [3R][nblk]: sums r^2, f^2, u^2
+    // of the corrected, smoothed u on the owned nodes (halo 2 nu + 2)
+    double* norm_part;
+    int nblk;
 };
 
 // Up pass of one level: u += bilinear prolongation of the coarse correction on
@@ -748,11 +752,13 @@ __global__ __launch_bounds__(64 * NW) void k_mg_down_reg(DownArgs<E> a) {
     }
 }
 
-// Up pass with register tiles: the same steps as k_mg_up.
-template <typename E, int R, bool HELM, int NU, int NW>
+// Up pass with register tiles: the same steps as k_mg_up.  NORM: the tiles
+// carry a halo of 2 nu + 2, so that the residual of the result is exact on the
+// owned nodes, and its norms go to a.norm_part (the last cycle of a batch).
+template <typename E, int R, bool HELM, int NU, int NW, bool NORM>
 __global__ __launch_bounds__(64 * NW) void k_mg_up_reg(UpArgs<E> a) {
     constexpr int K = kRegRows;
-    constexpr int H = 2 * NU;
+    constexpr int H = NORM ? 2 * NU + 2 : 2 * NU;
     using S = RegShape<H, NW>;
     constexpr int TX = S::TX, TY = S::TY, ROWS = S::ROWS;
     using V2 = typename Pair2<E>::T;
@@ -830,6 +836,45 @@ __global__ __launch_bounds__(64 * NW) void k_mg_up_reg(UpArgs<E> a) {
             for (int r = 0; r < R; ++r)
                 *reinterpret_cast<V2*>(a.u_out[r + z] + (size_t)gy * a.pitch + gx) =
                     V2{u[r][k][0], u[r][k][1]};
+    }
+
+    if (NORM) {  // residual norms of the result on the owned interior nodes
+        __shared__ double red[NW * 3 * R];
+        bool dom[K][2];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                dom[k][j] = gx + j >= 1 && gx + j <= N - 1 && gy0 + k >= 1 && gy0 + k <= N - 1;
+        const int qb = 2 * NU;  // exchange buffer not used by the last sweep
+        xc.put(qb & 1, u, w, lane);
+        __syncthreads();
+        xc.get(qb & 1, up, dn, w, lane);
+        E rr[R][K][2];
+        reg_residual<E, R, K>(rr, u, f, D, dom, up, dn, (E)(1.0 / (a.h * a.h)));
+        double acc[3 * R];
+#pragma unroll
+        for (int q = 0; q < 3 * R; ++q) acc[q] = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                if (own[k] && own_x && dom[k][j])
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const double rv = rr[r][k][j];
+                        const double fv = f[r][k][j];
+                        const double uv = u[r][k][j];
+                        acc[3 * r] += rv * rv;
+                        acc[3 * r + 1] += fv * fv;
+                        acc[3 * r + 2] += uv * uv;
+                    }
+        block_sum<3 * R, 64 * NW>(acc, red);
+        if (threadIdx.x == 0) {
+            const int b = by * gridDim.x + bx;
+#pragma unroll
+            for (int q = 0; q < 3 * R; ++q) a.norm_part[(3 * z + q) * a.nblk + b] = acc[q];
+        }
     }
 }
 
@@ -1457,11 +1502,13 @@ __global__ void k_correct(int N, int pitch, int pitch32, double* __restrict__ u0
 }
 
 // out[s*kNormVec + k] = sum_b part[s][k][b]: one block per (slot, k), fixed order.
+// Slot up_slot holds nblk_up partials (written by an up pass), the others nblk.
 __global__ __launch_bounds__(kThreads) void k_reduce_slots(const double* part, int stride,
                                                            int nblk, int s0, int nvec,
-                                                           double* out) {
+                                                           double* out, int up_slot, int nblk_up) {
     __shared__ double red[kThreads / 64];
     const int s = s0 + blockIdx.x / nvec, k = blockIdx.x % nvec;
+    if (s == up_slot) nblk = nblk_up;
     const double* p = part + (size_t)s * stride + (size_t)k * nblk;
     double acc[1] = {0.0};
     for (int b = threadIdx.x; b < nblk; b += kThreads) acc[0] += p[b];
@@ -1560,13 +1607,13 @@ struct PassGeom {
     int TX, TY;
     dim3 grid;
 };
-PassGeom pass_geom(const wandqs_ctx* c, int N, int nu, bool down) {
+PassGeom pass_geom(const wandqs_ctx* c, int N, int nu, bool down, bool norm = false) {
     PassGeom g{};
     g.reg = N >= c->reg_tile_min;
     g.split = c->reg_split;
     g.split_lds = c->lds_split;
     if (g.reg) {
-        const int halo = down ? 2 * nu + 2 : 2 * nu;
+        const int halo = down || norm ? 2 * nu + 2 : 2 * nu;
         g.TX = 128 - 2 * halo;
         g.TY = kRegRows * kRegWaves - 2 * halo;
     } else {
@@ -1589,10 +1636,18 @@ void launch_down_reg(const DownArgs<E>& a, int nu, dim3 grid, hipStream_t s, con
 template <typename E, int R, bool HELM>
 void launch_up_reg(const UpArgs<E>& a, int nu, dim3 grid, hipStream_t s, const ProfScope& ps) {
     constexpr int NW = kRegWaves;
+    if (a.norm_part) {
+        switch (nu) {
+            case 1: WQ_KLAUNCH(ps, (k_mg_up_reg<E, R, HELM, 1, NW, true>), grid, dim3(64 * NW), 0, s, a); break;
+            case 2: WQ_KLAUNCH(ps, (k_mg_up_reg<E, R, HELM, 2, NW, true>), grid, dim3(64 * NW), 0, s, a); break;
+            default: WQ_KLAUNCH(ps, (k_mg_up_reg<E, R, HELM, 3, NW, true>), grid, dim3(64 * NW), 0, s, a); break;
+        }
+        return;
+    }
     switch (nu) {
-        case 1: WQ_KLAUNCH(ps, (k_mg_up_reg<E, R, HELM, 1, NW>), grid, dim3(64 * NW), 0, s, a); break;
-        case 2: WQ_KLAUNCH(ps, (k_mg_up_reg<E, R, HELM, 2, NW>), grid, dim3(64 * NW), 0, s, a); break;
-        default: WQ_KLAUNCH(ps, (k_mg_up_reg<E, R, HELM, 3, NW>), grid, dim3(64 * NW), 0, s, a); break;
+        case 1: WQ_KLAUNCH(ps, (k_mg_up_reg<E, R, HELM, 1, NW, false>), grid, dim3(64 * NW), 0, s, a); break;
+        case 2: WQ_KLAUNCH(ps, (k_mg_up_reg<E, R, HELM, 2, NW, false>), grid, dim3(64 * NW), 0, s, a); break;
+        default: WQ_KLAUNCH(ps, (k_mg_up_reg<E, R, HELM, 3, NW, false>), grid, dim3(64 * NW), 0, s, a); break;
     }
 }
 
@@ -1650,7 +1705,8 @@ template <> float* lev_f<float>(wq::Level& L, int r) { return L.f32[r]; }
 // One V-cycle on levels 0..L.  zero_guess: the level-0 iterate starts from 0.
 // norm_slot >= 0 (double only) records the residual of the incoming iterate.
 template <typename E>
-void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess, int norm_slot) {
+void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess, int norm_slot,
+            int up_norm_slot = -1) {
     hipStream_t s = c->stream;
     const int lc = c->lc;
     const double eb = sizeof(E);
@@ -1788,10 +1844,17 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
         // per owned node: smoothed u, coarse correction (1/4), f, k2, corrected u
         const double nodes = (double)L.N * L.N;
         char nm[64];
-        const PassGeom g = pass_geom(c, L.N, c->cfg.nu_post, false);
+        // the finest up pass of a batch's last cycle records the result's norms
+        const bool unorm = l == 0 && up_norm_slot >= 0;
+        const PassGeom g = pass_geom(c, L.N, c->cfg.nu_post, false, unorm);
+        if (unorm) {
+            a.norm_part = c->norm_part + (size_t)up_norm_slot * kNormVec * c->max_tiles;
+            a.nblk = g.grid.x * g.grid.y;
+        }
         if (g.reg)
-            prof_name(c, nm, sizeof nm, "k_mg_up_reg<%s, %d, %s, %d, %d>@%d", type_name(E()), g.split ? 1 : R,
-                          helm ? "true" : "false", c->cfg.nu_post, kRegWaves, L.N);
+            prof_name(c, nm, sizeof nm, "k_mg_up_reg<%s, %d, %s, %d, %d, %s>@%d", type_name(E()),
+                      g.split ? 1 : R, helm ? "true" : "false", c->cfg.nu_post, kRegWaves,
+                      unorm ? "true" : "false", L.N);
         else
             prof_name(c, nm, sizeof nm, "k_mg_up<%s, %d, %s, %d, %d>@%d", type_name(E()), g.split_lds ? 1 : R,
                           helm ? "true" : "false", c->cfg.nu_post, g.TX, L.N);
@@ -1963,11 +2026,14 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
     // one "cycle" is a V-cycle (FP64) or an outer defect-correction iteration
     // (mixed) that records its residual norms in `slot` (FP64: -1, none)
     hipError_t gerr = hipSuccess;
-    auto cycle = [&](int slot) {
-        const CycleKey key{{hz.u0[0], hz.u0[1], hz.f0[0], hz.f0[1], hz.k2}, R, helm, mixed, slot};
+    // upslot >= 0 (FP64, register tiles on level 0): the cycle's finest up pass
+    // records the norms of its result in slot upslot
+    auto cycle = [&](int slot, int upslot) {
+        const CycleKey key{{hz.u0[0], hz.u0[1], hz.f0[0], hz.f0[1], hz.k2}, R, helm, mixed, slot,
+                           upslot};
         const hipError_t e = run_cycle(c, key, [&] {
             if (mixed) mixed_iteration(c, R, helm, hz, slot);
-            else vcycle<double>(c, R, helm, hz, false, slot);
+            else vcycle<double>(c, R, helm, hz, false, slot, upslot);
         });
         if (gerr == hipSuccess) gerr = e;
     };
@@ -1981,7 +2047,7 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
     const bool separate_norm = !mixed && c->lc == 0;
     const int maxc = c->cfg.mg_max_cycles;
     if (!(c->cfg.mg_rtol > 0.0)) {
-        for (int k = 0; k < maxc; ++k) cycle(mixed ? 0 : -1);
+        for (int k = 0; k < maxc; ++k) cycle(mixed ? 0 : -1, -1);
         if (graph_check() != WANDQS_OK) return WANDQS_E_HIP;
         WQ_LAUNCH_CHECK();
         if (res) *res = SolveResult{maxc, {-1.0, -1.0}};
@@ -1993,6 +2059,11 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
     // residual-norm kernel)
     const dim3 g = pass_geom(c, N, c->cfg.nu_pre, true).grid;
     const int nblk = g.x * g.y;
+    // the batch's last cycle records the final norms in its finest up pass
+    // (register tiles, FP64) instead of a separate residual pass
+    const PassGeom gu = pass_geom(c, N, c->cfg.nu_post, false, true);
+    const bool up_norms = !mixed && !separate_norm && gu.reg;
+    const int nblk_up = gu.grid.x * gu.grid.y;
     int done = 0;
     int pred = c->pred[kind] < 1 ? 1 : c->pred[kind];
     double* hr = c->h_pin;  // [kMaxSlots][kNormVec] + flags
@@ -2005,16 +2076,17 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
         if (done + b > maxc) b = maxc - done;
         for (int k = 0; k < b; ++k) {
             const int cyc = done + k;
-            cycle(mixed || c->lc > 0 ? cyc : -1);
+            cycle(mixed || c->lc > 0 ? cyc : -1, up_norms && k == b - 1 ? cyc + 1 : -1);
             if (separate_norm) resnorm(c, R, helm, hz, cyc + 1, nullptr);
         }
-        if (!separate_norm) resnorm(c, R, helm, hz, done + b, nullptr);
+        if (!separate_norm && !up_norms) resnorm(c, R, helm, hz, done + b, nullptr);
         const int s0 = done == 0 ? 0 : done + 1;
         const int ns = done + b + 1 - s0;
         {
             ProfScope ps(c, "k_reduce_slots", 8.0 * ns * 3 * R * (nblk + 1));
             WQ_KLAUNCH(ps, k_reduce_slots, dim3(ns * 3 * R), dim3(kThreads), 0, s,
-                               c->norm_part, V * c->max_tiles, nblk, s0, 3 * R, c->norm_red);
+                               c->norm_part, V * c->max_tiles, nblk, s0, 3 * R, c->norm_red,
+                               up_norms ? done + b : -1, nblk_up);
         }
         if (graph_check() != WANDQS_OK) return WANDQS_E_HIP;
         WQ_LAUNCH_CHECK();

@@ -137,11 +137,12 @@ struct SolveResult {
 // of right-hand sides, the operator, the precision form and the norm slot.
 struct CycleKey {
     const void* p[5];
-    int R, helm, mixed, slot;
+    int R, helm, mixed, slot, upslot;
     bool operator==(const CycleKey& o) const {
         for (int i = 0; i < 5; ++i)
             if (p[i] != o.p[i]) return false;
-        return R == o.R && helm == o.helm && mixed == o.mixed && slot == o.slot;
+        return R == o.R && helm == o.helm && mixed == o.mixed && slot == o.slot &&
+               upslot == o.upslot;
     }
 };
 struct CycleGraph {
