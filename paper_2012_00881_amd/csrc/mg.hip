@@ -352,6 +352,9 @@ struct UpArgs {
     // of the corrected, smoothed u on the owned nodes (halo 2 nu + 2)
     double* norm_part;
     int nblk;
+    // (float, finest level of the mixed form) nullptr, or the FP64 iterates
+    // that the result corrects in place (u += e) instead of being stored
+    double* corr[2];
 };
 
 // Up pass of one level: u += bilinear prolongation of the coarse correction on
@@ -432,8 +435,11 @@ __global__ __launch_bounds__(tile_threads<T>()) void k_mg_up(UpArgs<E> a) {
             if (p < NP && lx >= H && lx < H + T && ly >= H && ly < H + T && gx <= N - 1 &&
                 gy <= N - 1)
 #pragma unroll
-                for (int r = 0; r < R; ++r)
-                    a.u_out[r + z][(size_t)gy * a.pitch + gx] = su[r][ly * EX + lx];
+                for (int r = 0; r < R; ++r) {
+                    const size_t g = (size_t)gy * a.pitch + gx;
+                    if (a.corr[0]) a.corr[r + z][g] += (double)su[r][ly * EX + lx];
+                    else a.u_out[r + z][g] = su[r][ly * EX + lx];
+                }
         }
     }
 }
@@ -833,9 +839,18 @@ __global__ __launch_bounds__(64 * NW) void k_mg_up_reg(UpArgs<E> a) {
         const int gy = gy0 + k;
         if (own[k] && own_x && gx <= N - 1 && gy <= N - 1)
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-                *reinterpret_cast<V2*>(a.u_out[r + z] + (size_t)gy * a.pitch + gx) =
-                    V2{u[r][k][0], u[r][k][1]};
+            for (int r = 0; r < R; ++r) {
+                const size_t g = (size_t)gy * a.pitch + gx;
+                if (a.corr[0]) {
+                    double2* p = reinterpret_cast<double2*>(a.corr[r + z] + g);
+                    double2 o = *p;
+                    o.x += (double)u[r][k][0];
+                    o.y += (double)u[r][k][1];
+                    *p = o;
+                } else {
+                    *reinterpret_cast<V2*>(a.u_out[r + z] + g) = V2{u[r][k][0], u[r][k][1]};
+                }
+            }
     }
 
     if (NORM) {  // residual norms of the result on the owned interior nodes
@@ -1706,7 +1721,7 @@ template <> float* lev_f<float>(wq::Level& L, int r) { return L.f32[r]; }
 // norm_slot >= 0 (double only) records the residual of the incoming iterate.
 template <typename E>
 void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess, int norm_slot,
-            int up_norm_slot = -1) {
+            int up_norm_slot = -1, double* const* corr = nullptr) {
     hipStream_t s = c->stream;
     const int lc = c->lc;
     const double eb = sizeof(E);
@@ -1846,6 +1861,8 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
         char nm[64];
         // the finest up pass of a batch's last cycle records the result's norms
         const bool unorm = l == 0 && up_norm_slot >= 0;
+        if (l == 0 && corr)
+            for (int r = 0; r < R; ++r) a.corr[r] = corr[r];
         const PassGeom g = pass_geom(c, L.N, c->cfg.nu_post, false, unorm);
         if (unorm) {
             a.norm_part = c->norm_part + (size_t)up_norm_slot * kNormVec * c->max_tiles;
@@ -1900,7 +1917,13 @@ void mixed_iteration(wandqs_ctx* c, int R, bool helm, const Hier<double>& hz, in
     Hier<float> hf{{L0.u32[0], L0.u32[1]}, {L0.f32[0], L0.f32[1]}, hz.k2};
     resnorm(c, R, helm, hz, slot, hf.f0);
     const int inner = c->cfg.mg_inner_cycles > 0 ? c->cfg.mg_inner_cycles : 1;
-    for (int i = 0; i < inner; ++i) vcycle<float>(c, R, helm, hf, i == 0, -1);
+    // the last inner cycle's finest up pass adds its result to the FP64
+    // iterate (u += e) itself, unless level 0 is the coarse kernel's
+    double* const corr[2] = {hz.u0[0], R > 1 ? hz.u0[1] : nullptr};
+    const bool fused = c->lc > 0;
+    for (int i = 0; i < inner; ++i)
+        vcycle<float>(c, R, helm, hf, i == 0, -1, -1, fused && i == inner - 1 ? corr : nullptr);
+    if (fused) return;
     ProfScope ps(c, "k_correct", (double)L0.N * L0.N * 20.0 * R);
     WQ_KLAUNCH(ps, k_correct, dim3((L0.N + 1 + 127) / 128, L0.N + 1), dim3(128), 0, c->stream,
                        L0.N, L0.pitch, L0.pitch, hz.u0[0], R > 1 ? hz.u0[1] : nullptr, L0.u32[0],
