@@ -98,7 +98,8 @@ typedef struct {
     double mg_atol;      /* >= 0; 0 recommended (an absolute floor loosens small fields) */
     int32_t mg_max_cycles; /* 1 .. 200 */
     int32_t nu_pre, nu_post; /* over-relaxed red-black Gauss-Seidel sweeps per V-cycle,
-                                each 1 .. 3 */
+                                each 1 .. 3; the levels two or more below the
+                                finest pre-smooth with one sweep */
     int32_t n_beams;       /* 0 .. 8 */
     const wandqs_beam* beams;
     int32_t n_probes;      /* 0 .. 16 */

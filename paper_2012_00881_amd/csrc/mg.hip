@@ -49,6 +49,11 @@ constexpr int kThreads = 256;  // norm and reduction kernels
 // where the diagonal shift h^2 k2 (k2 ~ n0 in the plasma) is no longer small,
 // over-relaxation slows the cycle (measured).
 constexpr double kOmegaH2N0 = 0.125;
+// Pre-smoothing on the levels kFullPreLevels and more below the finest (the
+// coarse kernel's levels included when it lies that deep) is one sweep: a
+// second sweep there cost more time than the extra V-cycles it saved
+// (measured).  The finer levels and every post-smoothing keep nu_pre, nu_post.
+constexpr int kFullPreLevels = 2;
 #ifndef WQ_COARSE_THREADS
 #define WQ_COARSE_THREADS 1024
 #endif
@@ -1717,6 +1722,8 @@ template <typename E> E* lev_f(wq::Level& L, int r);
 template <> double* lev_f<double>(wq::Level& L, int r) { return L.f[r]; }
 template <> float* lev_f<float>(wq::Level& L, int r) { return L.f32[r]; }
 
+int nu_pre_at(const wandqs_ctx* c, int l) { return l >= kFullPreLevels ? 1 : c->cfg.nu_pre; }
+
 // One V-cycle on levels 0..L.  zero_guess: the level-0 iterate starts from 0.
 // norm_slot >= 0 (double only) records the residual of the incoming iterate.
 template <typename E>
@@ -1751,7 +1758,8 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
             a.f_c[r] = F(l + 1, r);
         }
         a.k2 = helm ? K(l) : nullptr;
-        const PassGeom g = pass_geom(c, L.N, c->cfg.nu_pre, true);
+        const int nu = nu_pre_at(c, l);
+        const PassGeom g = pass_geom(c, L.N, nu, true);
         a.nblk = g.grid.x * g.grid.y;
         a.norm_part = (l == 0 && norm_slot >= 0)
                           ? c->norm_part + (size_t)norm_slot * kNormVec * c->max_tiles
@@ -1761,13 +1769,13 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
         char nm[64];
         if (g.reg)
             prof_name(c, nm, sizeof nm, "k_mg_down_reg<%s, %d, %s, %d, %d>@%d", type_name(E()), g.split ? 1 : R,
-                          helm ? "true" : "false", c->cfg.nu_pre, kRegWaves, L.N);
+                          helm ? "true" : "false", nu, kRegWaves, L.N);
         else
             prof_name(c, nm, sizeof nm, "k_mg_down<%s, %d, %s, %d, %d>@%d", type_name(E()), g.split_lds ? 1 : R,
-                          helm ? "true" : "false", c->cfg.nu_pre, g.TX, L.N);
+                          helm ? "true" : "false", nu, g.TX, L.N);
         ProfScope ps(c, nm, nodes * ((a.u_in[0] ? eb * R : 0.0) + eb * R + (helm ? 8.0 : 0.0) +
                                      eb * R + eb * R / 4));
-        down_pass<E>(R, helm, a, c->cfg.nu_pre, g, s, ps);
+        down_pass<E>(R, helm, a, nu, g, s, ps);
     }
     if (lb < lc) {
         wq::Level& L = c->lev[lb];
@@ -1810,7 +1818,7 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
         a.k2levf = helm ? c->k2levf : nullptr;
         a.idlevf = helm ? c->idlevf : nullptr;
         a.ncycles = WQ_COARSE_CYCLES;
-        a.nu1 = c->cfg.nu_pre;
+        a.nu1 = nu_pre_at(c, lc);
         a.nu2 = c->cfg.nu_post;
         const double nodes = (double)(L.N + 1) * (L.N + 1);
         char nm[64];
