@@ -1895,7 +1895,7 @@ void resnorm(wandqs_ctx* c, int R, bool helm, const Hier<double>& hz, int slot,
     const wq::Level& L = c->lev[0];
     // the same tiles as the level-0 down pass: every norm slot of a solve has
     // one partial-sum layout
-    const PassGeom pg = pass_geom(c, L.N, c->cfg.nu_pre, true);
+    const PassGeom pg = pass_geom(c, L.N, nu_pre_at(c, 0), true);
     const dim3 g = pg.grid;
     const int TX = pg.TX, TY = pg.TY;
     double* part = c->norm_part + (size_t)slot * kNormVec * c->max_tiles;
@@ -2088,7 +2088,7 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
     const double atol = c->cfg.mg_atol * std::sqrt((double)(N - 1) * (N - 1));
     // partial sums per tile (the level-0 tiles, for both the down pass and the
     // residual-norm kernel)
-    const dim3 g = pass_geom(c, N, c->cfg.nu_pre, true).grid;
+    const dim3 g = pass_geom(c, N, nu_pre_at(c, 0), true).grid;
     const int nblk = g.x * g.y;
     // the batch's last cycle records the final norms in its finest up pass
     // (register tiles, FP64) instead of a separate residual pass
