@@ -170,6 +170,15 @@ def test_slice_matches_oracle_full_size_c5(torch_cuda, oracle_mod):
     _compare_slice(torch_cuda, oracle_mod, cfg, state)
 
 
+def test_slice_matches_oracle_largest_grid(torch_cuda, oracle_mod):
+    """The largest grid the library accepts, 4096^2 over the C5 box (twelve
+    multigrid levels, four on register tiles), with one particle per cell
+    (16.8M particles): one slice from a synthetic state in the driver region."""
+    cfg = wi.scaled(wi.config("C5"), n_cells=4096, ppc_side=1, precision="fp64")
+    state = wi.synthetic_state(cfg, seed=41, p_max=0.5, xi=2.0, field_amp=0.01)
+    _compare_slice(torch_cuda, oracle_mod, cfg, state)
+
+
 # ------------------------------------------------------------------ runs ----
 
 def test_run_c1_matches_oracle(torch_cuda, oracle_mod):
