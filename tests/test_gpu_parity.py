@@ -282,6 +282,29 @@ def test_bitwise_deterministic(torch_cuda):
     assert np.array_equal(outs[0][1], outs[1][1])
 
 
+def test_noconv_is_an_error(torch_cuda):
+    """A solve that cannot meet its tolerance within mg_max_cycles (here one
+    V-cycle, from a state with a nonzero source) returns WANDQS_E_NOCONV and
+    names the solve; the context then refuses to step until set_state, after
+    which the same slice fails the same way again.  Every kernel completes:
+    the host decides non-convergence from the published norms."""
+    from paper_2012_00881_amd import WandQSError
+    cfg = wi.scaled(wi.config("C2"), n_cells=64, mg_max_cycles=1)
+    state = wi.synthetic_state(cfg, seed=3, p_max=0.3, xi=2.0, field_amp=0.01)
+    sim = _sim(cfg)
+    for _ in range(2):
+        sim.set_state(particles=_particles(state), fields=state["fields"], xi=state["xi"],
+                      dxi=state["dxi"])
+        with pytest.raises(WandQSError) as e:
+            sim.step(info=True)
+        assert e.value.status == -4, e.value
+        assert "psi solve" in str(e.value), e.value
+        with pytest.raises(WandQSError) as e2:
+            sim.step()
+        assert e2.value.status == -6
+    sim.close()
+
+
 def test_nonphysical_is_an_error(torch_cuda):
     from paper_2012_00881_amd import WandQSError
     cfg = wi.scaled(wi.config("C1"), n_cells=32)
