@@ -98,6 +98,8 @@ def test_mg_sine_eigenmode_closed_form(torch_cuda):
 # ------------------------------------------------------------ one slice -----
 
 SLICE_CASES = [
+    ("C1", 8, 31, 0.3),     # smallest grid: particle tiles overhang it, one coarse kernel solves
+    ("C1", 16, 32, 0.3),
     ("C1", 64, 1, 0.3),
     ("C2", 128, 11, 0.5),
     ("C2", 256, 12, 0.8),
