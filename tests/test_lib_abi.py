@@ -83,3 +83,14 @@ def test_init_without_gpu_fails_cleanly(lib):
         assert L.wandqs_last_error(None)
         st = L.wandqs_init(C.byref(c), 8, C.c_void_p(1 << 20), n.value - 256, None, C.byref(ctx))
         assert st == lib.E_NOMEM
+
+
+def test_missing_library_fails_loudly(lib, monkeypatch, tmp_path):
+    """Without libwandqs.so the binding raises, both at load and when a
+    Simulation is built; nothing falls back to the CPU or to the oracle."""
+    monkeypatch.setattr(lib, "LIB_PATH", str(tmp_path / "libwandqs.so"))
+    monkeypatch.setattr(lib, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        lib.load()
+    with pytest.raises(RuntimeError, match="missing"):
+        lib.Simulation(wi.config("C1"), n_slices=1)
