@@ -137,9 +137,14 @@ def adjoint_timing(cfg: dict, S: int, K: int):
         torch.cuda.synchronize()
         res["backward_s"] = time.perf_counter() - t0
         res["dL_dtheta"] = [float(v) for v in th]
+        P = sim.P
         sim.close()
         del sim
     res["backward_over_forward"] = res["backward_s"] / res["forward_s"]
+    # the forward-plus-adjoint form's throughput: particle-slices over the taped
+    # forward and the reverse sweep together
+    res["fwd_adj_value"] = P * S / (res["forward_taped_s"] + res["backward_s"])
+    res["fwd_adj_unit"] = "particle-slice updates/s"
     res["ms_per_slice_backward"] = 1e3 * res["backward_s"] / S
     res["tape_overhead"] = res["forward_taped_s"] / res["forward_s"] - 1.0
     print(f"[bench] adjoint: forward {res['forward_s']:.3f} s, taped {res['forward_taped_s']:.3f} s, "
