@@ -92,6 +92,17 @@ def vcycle_bandwidth(stats, tot_ms):
     return out
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
 def cpu_baseline(cfg: dict, n_slices: int):
     import oracle
     orc = oracle.Oracle(cfg)
@@ -102,7 +113,8 @@ def cpu_baseline(cfg: dict, n_slices: int):
     P = st["x"].size
     return dict(value=P * n_slices / dt, unit="particle-slice updates/s", cores=1, kind="oracle",
                 sample=f"first {n_slices} slices of the same job from xi=0 "
-                       f"(single-threaded FP64 oracle, {dt:.1f} s, status {r['status']})")
+                       f"(single-threaded FP64 oracle on {_cpu_model()}, {dt:.1f} s, "
+                       f"status {r['status']})")
 
 
 def adjoint_timing(cfg: dict, S: int, K: int):
