@@ -2,8 +2,12 @@
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It wraps ``liboracle_wandqs.so`` (plain
-FP64 C++, single threaded, see ``wandqs_oracle.cpp``) with numpy arrays.  It
-shares no code with the GPU library in ``paper_2012_00881_amd``.
+FP64 C++ with OpenMP loops whose results do not depend on the thread count, see
+``wandqs_oracle.cpp``) with numpy arrays.  It shares no code with the GPU
+library in ``paper_2012_00881_amd``.
+
+The environment variable ``WANDQS_ORACLE_LIB`` names another build of the same
+source to load instead (the sanitizer build of the tests).
 
 Every function is pinned by ``tests/test_oracle_*.py`` against facts fixed by the
 paper or by mathematics (closed forms, dense direct solves, invariants).
@@ -16,7 +20,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle_wandqs.so")
+_LIB_PATH = os.environ.get("WANDQS_ORACLE_LIB") or os.path.join(_HERE, "liboracle_wandqs.so")
 _lib = None
 
 FIELDS = ("psi", "Ez", "Bz", "Bx", "By")
@@ -40,8 +44,7 @@ class Cfg(C.Structure):
                 ("n0", C.c_double), ("dxi0", C.c_double), ("adaptive", C.c_int),
                 ("refine_k", C.c_int), ("mg_rtol", C.c_double), ("mg_atol", C.c_double),
                 ("mg_max_cycles", C.c_int), ("nu_pre", C.c_int), ("nu_post", C.c_int),
-                ("n_beams", C.c_int), ("beams", C.POINTER(Beam)), ("mg_omega", C.c_double),
-                ("mg_omega_helm", C.c_double)]
+                ("n_beams", C.c_int), ("beams", C.POINTER(Beam))]
 
 
 class Info(C.Structure):
@@ -58,6 +61,7 @@ def lib():
             _b.build()
         L = C.CDLL(_LIB_PATH)
         L.oracle_next_dxi.restype = C.c_double
+        L.oracle_get_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -101,8 +105,6 @@ class Oracle:
         c.mg_rtol, c.mg_atol = cfg["mg_rtol"], cfg["mg_atol"]
         c.mg_max_cycles, c.nu_pre, c.nu_post = cfg["mg_max_cycles"], cfg["nu_pre"], cfg["nu_post"]
         c.n_beams, c.beams = len(cfg["beams"]), beams
-        c.mg_omega = cfg.get("mg_omega", 0.0)
-        c.mg_omega_helm = cfg.get("mg_omega_helm", 0.0)
         self.c = c
 
     # ---------------------------------------------------------------- pieces
@@ -301,20 +303,34 @@ def apply(N, h, u, k2=None):
     return out
 
 
-def mg_solve(N, h, f, u0=None, k2=None, rtol=1e-14, atol=0.0, max_cycles=50, nu1=2, nu2=2,
-             omega=0.0, k2_scale=1.0):
-    """Multigrid solve of (L_h - k2) u = f with zero Dirichlet boundary; omega is
-    the relaxation factor of the smoothing sweeps (0: the default), applied on
-    the Helmholtz levels with h^2 k2_scale <= 1/8 (k2_scale <= 0: on all)."""
+def mg_solve(N, h, f, u0=None, k2=None, rtol=1e-14, atol=0.0, max_cycles=50, nu1=2, nu2=2):
+    """Multigrid solve of (L_h - k2) u = f with zero Dirichlet boundary: V(nu1, nu2)
+    cycles of red-black Gauss-Seidel from the guess u0 (default 0)."""
     f = _f64(f)
     u = np.zeros_like(f) if u0 is None else _f64(u0).copy()
     cyc = C.c_int(0)
     rel = C.c_double(0)
     st = lib().oracle_mg_solve(int(N), C.c_double(h), _p(None if k2 is None else _f64(k2)),
                                _p(f), _p(u), C.c_double(rtol), C.c_double(atol), int(max_cycles),
-                               int(nu1), int(nu2), C.c_double(omega), C.c_double(k2_scale),
-                               C.byref(cyc), C.byref(rel))
+                               int(nu1), int(nu2), C.byref(cyc), C.byref(rel))
     return st, u, cyc.value, rel.value
+
+
+def psi_gradient(N, L, psi):
+    """Node gradient of psi used by the particle gather: [2][N+1][N+1] (d/dx, d/dy)."""
+    psi = _f64(psi)
+    out = np.zeros((2,) + psi.shape)
+    lib().oracle_psi_gradient(int(N), C.c_double(L), _p(psi), _p(out))
+    return out
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (the results do not depend on it)."""
+    lib().oracle_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().oracle_get_threads())
 
 
 def push(L, dxi, g_i, gx, gy, Bx, By, Bz, x, y, px, py):

@@ -1,7 +1,7 @@
 /*
  * wandqs oracle -- TEST INFRASTRUCTURE ONLY, NOT THE PRODUCT.
  *
- * A plain, slow, single-threaded FP64 CPU implementation of one quasi-static
+ * A plain, slow FP64 CPU implementation of one quasi-static
  * xi-slice step of plasma electrons driven by a frozen luminal beam, after
  * T. Wang, V. Khudik, J. Kim, G. Shvets, "WAND-PIC: an accelerated
  * three-dimensional quasi-static particle-in-cell code" (arXiv 2012.00881).
@@ -19,13 +19,10 @@
  *  - central differences at interior nodes, one-sided at boundary nodes only
  *    for the gradient of psi used by the particle gather;
  *  - 5-point Laplacian of Sec. VII.B, eq. (33);
- *  - geometric multigrid: V(nu1,nu2) cycles, red-black Gauss-Seidel
- *    over-relaxed by a factor om (the paper names only "iterative relaxation";
- *    om = 1.175 unless the configuration gives another), except on the
- *    Helmholtz levels whose diagonal shift is no longer small, h^2 n0 > 1/8,
- *    which relax with om = 1; full weighting, bilinear prolongation,
- *    rediscretised coarse operators, exact solve on the 2x2-cell grid (Sec. II
- *    item 4 and Sec. VII.A).
+ *  - geometric multigrid: V(nu1,nu2) cycles of plain red-black Gauss-Seidel
+ *    (the paper names only "iterative relaxation" on a hierarchy of grids),
+ *    full weighting, bilinear prolongation, rediscretised coarse operators,
+ *    exact solve on the 2x2-cell grid (Sec. II item 4 and Sec. VII.A).
  *
  * Array layout: node (a, b) of an (N+1)x(N+1) array is element b*(N+1)+a
  * (x index fastest).  Field order: psi, Ez, Bz, Bx, By.
@@ -34,6 +31,13 @@
  * a dual number (value plus directional derivatives) gives its tangent-linear
  * model (oracle_run_tangent).  The reverse sweep (oracle_slice_adjoint,
  * oracle_run_loss) is written by hand from the same formulas.
+ *
+ * Threads (OpenMP): loops whose iterations write disjoint elements run in
+ * parallel (colour sweeps, transfers, per-particle gathers and pushes, node
+ * formulas); the deposit splits the node rows among the threads, each of which
+ * adds the particles in index order; norms are summed serially.  Every result
+ * is therefore bitwise the same for any thread count, and equal to the serial
+ * program's.
  *
  * Parity status of each function is recorded in the design notes; every
  * function here is pinned by a test in tests/test_oracle_*.py.
@@ -44,6 +48,8 @@
 #include <cstdint>
 #include <cstring>
 #include <vector>
+
+#include <omp.h>
 
 extern "C" {
 
@@ -67,7 +73,6 @@ typedef struct {
     int mg_max_cycles, nu_pre, nu_post;
     int n_beams;
     const oracle_beam* beams;
-    double mg_omega, mg_omega_helm; /* relaxation factors (Poisson, Helmholtz); 0: the defaults */
 } oracle_cfg;
 
 typedef struct {
@@ -178,22 +183,36 @@ void cic(const Grid& g, const T& x, int& c, T& d) {
 }
 
 /* deposit(q)[a,b] = sum_i w q_i W_a(x_i) W_b(y_i) / h^2 with w = n0 h^2 / ppc.
- * With q = 1 this is the surface density n* of Sec. III.B (n* = int f* dP). */
+ * With q = 1 this is the surface density n* of Sec. III.B (n* = int f* dP).
+ * Each thread owns a band of node rows b and adds, in particle order, the
+ * contributions of the particles whose cell touches its rows, so every node
+ * sums its particles in index order whatever the number of threads. */
 template <class T>
 void deposit(const Grid& g, const oracle_cfg& c, int P, const T* x, const T* y, const T* q,
              T* out) {
     const double w = c.n0 * g.h * g.h / c.ppc;
     std::fill(out, out + g.nn(), T(0.0));
-    for (int i = 0; i < P; ++i) {
-        int a, b;
-        T dx, dy;
-        cic(g, x[i], a, dx);
-        cic(g, y[i], b, dy);
-        T s = w * (q ? q[i] : T(1.0)) / (g.h * g.h);
-        out[g.id(a, b)] += s * (1.0 - dx) * (1.0 - dy);
-        out[g.id(a + 1, b)] += s * dx * (1.0 - dy);
-        out[g.id(a, b + 1)] += s * (1.0 - dx) * dy;
-        out[g.id(a + 1, b + 1)] += s * dx * dy;
+#pragma omp parallel
+    {
+        const int nt = omp_get_num_threads(), t = omp_get_thread_num();
+        const int rows = g.N + 1;
+        const int r0 = (int)((long)rows * t / nt), r1 = (int)((long)rows * (t + 1) / nt);
+        for (int i = 0; i < P; ++i) {
+            int a, b;
+            T dx, dy;
+            cic(g, y[i], b, dy);
+            if (b + 1 < r0 || b >= r1) continue;
+            cic(g, x[i], a, dx);
+            T s = w * (q ? q[i] : T(1.0)) / (g.h * g.h);
+            if (b >= r0) {
+                out[g.id(a, b)] += s * (1.0 - dx) * (1.0 - dy);
+                out[g.id(a + 1, b)] += s * dx * (1.0 - dy);
+            }
+            if (b + 1 < r1) {
+                out[g.id(a, b + 1)] += s * (1.0 - dx) * dy;
+                out[g.id(a + 1, b + 1)] += s * dx * dy;
+            }
+        }
     }
 }
 
@@ -239,28 +258,29 @@ T apply_at(const Level<T>& lv, const T* u, int a, int b) {
     return lap - k2 * u[lv.id(a, b)];
 }
 
-/* Over-relaxed red-black Gauss-Seidel half sweep: each node with
- * (a+b) % 2 == color moves from u to u + om (g - u), where g is the value that
- * zeroes its own equation given its four neighbours (om = 1: Gauss-Seidel). */
+/* Red-black Gauss-Seidel half sweep: each node with (a+b) % 2 == color takes
+ * the value that zeroes its own equation given its four neighbours,
+ * u = (sum of the neighbours - h^2 f) / (4 + h^2 k2).  The nodes of one colour
+ * depend only on the other colour, so the rows can be swept in any order. */
 template <class T>
-void relax_color(Level<T>& lv, int color, double om) {
+void relax_color(Level<T>& lv, int color) {
     const double h2 = lv.h * lv.h;
+#pragma omp parallel for schedule(static)
     for (int b = 1; b < lv.N; ++b)
         for (int a = 1; a < lv.N; ++a) {
             if (((a + b) & 1) != color) continue;
             T nb = lv.u[lv.id(a - 1, b)] + lv.u[lv.id(a + 1, b)] + lv.u[lv.id(a, b - 1)] +
                    lv.u[lv.id(a, b + 1)];
             T k2 = lv.k2.empty() ? T(0.0) : lv.k2[lv.id(a, b)];
-            T g = (nb - h2 * lv.f[lv.id(a, b)]) / (4.0 + h2 * k2);
-            lv.u[lv.id(a, b)] = lv.u[lv.id(a, b)] + om * (g - lv.u[lv.id(a, b)]);
+            lv.u[lv.id(a, b)] = (nb - h2 * lv.f[lv.id(a, b)]) / (4.0 + h2 * k2);
         }
 }
 
 template <class T>
-void smooth(Level<T>& lv, int nu, double om) {
+void smooth(Level<T>& lv, int nu) {
     for (int s = 0; s < nu; ++s) {
-        relax_color(lv, 0, om);
-        relax_color(lv, 1, om);
+        relax_color(lv, 0);
+        relax_color(lv, 1);
     }
 }
 
@@ -268,6 +288,7 @@ void smooth(Level<T>& lv, int nu, double om) {
 template <class T>
 void residual(const Level<T>& lv, std::vector<T>& r) {
     r.assign((lv.N + 1) * (lv.N + 1), T(0.0));
+#pragma omp parallel for schedule(static)
     for (int b = 1; b < lv.N; ++b)
         for (int a = 1; a < lv.N; ++a)
             r[lv.id(a, b)] = lv.f[lv.id(a, b)] - apply_at(lv, lv.u.data(), a, b);
@@ -287,6 +308,7 @@ template <class T>
 void full_weighting(const Level<T>& fine, const std::vector<T>& r, Level<T>& coarse,
                     std::vector<T>& out) {
     out.assign((coarse.N + 1) * (coarse.N + 1), T(0.0));
+#pragma omp parallel for schedule(static)
     for (int J = 1; J < coarse.N; ++J)
         for (int I = 1; I < coarse.N; ++I) {
             int a = 2 * I, b = 2 * J;
@@ -302,6 +324,7 @@ void full_weighting(const Level<T>& fine, const std::vector<T>& r, Level<T>& coa
 /* u_fine += bilinear interpolation of u_coarse. */
 template <class T>
 void prolong_add(const Level<T>& coarse, Level<T>& fine) {
+#pragma omp parallel for schedule(static)
     for (int b = 1; b < fine.N; ++b)
         for (int a = 1; a < fine.N; ++a) {
             int I = a / 2, J = b / 2;
@@ -319,24 +342,22 @@ void prolong_add(const Level<T>& coarse, Level<T>& fine) {
 }
 
 template <class T>
-void vcycle(std::vector<Level<T>>& lv, size_t l, int nu1, int nu2, double om, double h2max) {
+void vcycle(std::vector<Level<T>>& lv, size_t l, int nu1, int nu2) {
     Level<T>& L = lv[l];
     if (L.N == 2) { /* one interior node, four zero boundary neighbours: exact */
         T k2 = L.k2.empty() ? T(0.0) : L.k2[L.id(1, 1)];
         L.u[L.id(1, 1)] = -L.f[L.id(1, 1)] / (4.0 / (L.h * L.h) + k2);
         return;
     }
-    /* Helmholtz levels with h^2 > h2max relax without over-relaxation */
-    const double oml = (!L.k2.empty() && L.h * L.h > h2max) ? 1.0 : om;
-    smooth(L, nu1, oml);
+    smooth(L, nu1);
     std::vector<T> r;
     residual(L, r);
     Level<T>& C = lv[l + 1];
     full_weighting(L, r, C, C.f);
     std::fill(C.u.begin(), C.u.end(), T(0.0));
-    vcycle(lv, l + 1, nu1, nu2, om, h2max);
+    vcycle(lv, l + 1, nu1, nu2);
     prolong_add(C, L);
-    smooth(L, nu2, oml);
+    smooth(L, nu2);
 }
 
 /* Solve (L_h - k2) u = f for the interior nodes with u = 0 on the boundary,
@@ -351,11 +372,7 @@ void vcycle(std::vector<Level<T>>& lv, size_t l, int nu1, int nu2, double om, do
  * must meet the rule: the derivative solves converge along with the value. */
 template <class T>
 int mg_solve(int N, double h, const T* k2, const T* f, T* u, double rtol, double atol,
-             int max_cycles, int nu1, int nu2, double om, double k2_scale, int* cycles_out,
-             double* rel_out) {
-    if (om == 0.0) om = 1.175;
-    /* over-relaxation only where h^2 k2_scale <= 1/8 (k2_scale <= 0: everywhere) */
-    const double h2max = k2_scale > 0.0 ? 0.125 / k2_scale : std::numeric_limits<double>::infinity();
+             int max_cycles, int nu1, int nu2, int* cycles_out, double* rel_out) {
     std::vector<Level<T>> lv;
     for (int n = N; n >= 2; n /= 2) {
         Level<T> l;
@@ -400,7 +417,7 @@ int mg_solve(int N, double h, const T* k2, const T* f, T* u, double rtol, double
     };
     int cyc = 0;
     while (!all_done() && cyc < max_cycles) {
-        vcycle(lv, 0, nu1, nu2, om, h2max);
+        vcycle(lv, 0, nu1, nu2);
         ++cyc;
         residual(top, r);
         for (int c = 0; c < nc; ++c) {
@@ -478,23 +495,26 @@ int assemble(const Grid& g, const oracle_cfg& c, double xi, const MomentsT<T>& m
              const T* theta = nullptr) {
     const int nn = g.nn();
     std::vector<T> G(nn, T(0.0)), jz(nn, T(0.0));
-    int status = ORC_OK;
+    int nonphys = 0;
+#pragma omp parallel for schedule(static) reduction(| : nonphys)
     for (int b = 0; b <= g.N; ++b)
         for (int a = 0; a <= g.N; ++a) {
             int i = g.id(a, b);
             T gg = 1.0 + psi[i];
             T plasma_jz(0.0);
             if (val(m.n[i]) > 0.0) {
-                if (val(gg) <= 0.0) status = ORC_NONPHYS;
+                if (val(gg) <= 0.0) nonphys = 1;
                 /* <gamma> = (1 + <p_perp^2> + g^2)/(2g) with <p_perp^2> = g^2 <V^2> */
                 G[i] = (m.n[i] * (1.0 + gg * gg) + gg * gg * (m.txx[i] + m.tyy[i])) / (2.0 * gg);
                 plasma_jz = G[i] / gg - m.n[i];
             }
             jz[i] = plasma_jz + beam_density(c, theta, g.xa(a), g.xa(b), xi);
         }
+    const int status = nonphys ? ORC_NONPHYS : ORC_OK;
     k2.assign(nn, T(0.0));
     fBx.assign(nn, T(0.0));
     fBy.assign(nn, T(0.0));
+#pragma omp parallel for schedule(static)
     for (int b = 1; b < g.N; ++b)
         for (int a = 1; a < g.N; ++a) {
             int i = g.id(a, b);
@@ -527,6 +547,7 @@ template <class T>
 void psi_gradient(const Grid& g, const T* psi, std::vector<T>& gx, std::vector<T>& gy) {
     gx.assign(g.nn(), T(0.0));
     gy.assign(g.nn(), T(0.0));
+#pragma omp parallel for schedule(static)
     for (int b = 0; b <= g.N; ++b)
         for (int a = 0; a <= g.N; ++a) {
             int i = g.id(a, b);
@@ -570,15 +591,16 @@ void push_one(double L, double dxi, const T& g_i, const T& gx, const T& gy, cons
     if (val(y) < -L) { y = -2.0 * L - y; py = -py; }
 }
 
-/* Step_Size_Refinement of Algorithm 1: V0 = dx/dxi0; dxi = dxi0 V0/Vmax if
- * Vmax > V0 else dxi0; with refinement level k the step never drops below
- * dxi0/k (Sec. V.A). */
+/* Step_Size_Refinement (Algorithm 1): the step is the largest that keeps the
+ * fastest particle within one cell, h / Vmax, but never above the initial
+ * step dxi0 (the paper's V0 = h / dxi0 marks where the refinement starts) and,
+ * with refinement level k, never below dxi0 / k (Sec. V.A). */
 double next_dxi(const oracle_cfg& c, double h, double vmax) {
-    if (!c.adaptive) return c.dxi0;
-    double V0 = h / c.dxi0;
     double d = c.dxi0;
-    if (vmax > V0) d = c.dxi0 * V0 / vmax;
-    if (c.refine_k > 0 && d < c.dxi0 / c.refine_k) d = c.dxi0 / c.refine_k;
+    if (c.adaptive && vmax > 0.0) {
+        d = std::min(c.dxi0, h / vmax);
+        if (c.refine_k > 0) d = std::max(d, c.dxi0 / c.refine_k);
+    }
     return d;
 }
 
@@ -609,8 +631,7 @@ int slice_step_t(const oracle_cfg* c, int P, T* x, T* y, T* px, T* py, T* pz, T*
     int status = ORC_OK;
     auto solve = [&](int k, const std::vector<T>* k2, const std::vector<T>& f, T* u) {
         int st = mg_solve<T>(g.N, g.h, k2 ? k2->data() : nullptr, f.data(), u, c->mg_rtol, c->mg_atol,
-                          c->mg_max_cycles, c->nu_pre, c->nu_post, k2 ? c->mg_omega_helm : c->mg_omega, c->n0,
-                          &inf.cycles[k], &inf.rel_resid[k]);
+                          c->mg_max_cycles, c->nu_pre, c->nu_post, &inf.cycles[k], &inf.rel_resid[k]);
         if (st != ORC_OK && status == ORC_OK) status = st;
     };
 
@@ -628,9 +649,11 @@ int slice_step_t(const oracle_cfg* c, int P, T* x, T* y, T* px, T* py, T* pz, T*
      *    j = n*<V> (eq. (9)) and pressure tensor T = n*<V V> (below eq. (16)). */
     std::vector<T> gi(P), vx(P), vy(P), vxx(P), vxy(P), vyy(P);
     double inv_err = 0.0;
+    int nonphys = 0;
+#pragma omp parallel for schedule(static) reduction(max : inv_err) reduction(| : nonphys)
     for (int i = 0; i < P; ++i) {
         gi[i] = 1.0 + gather1(g, psi, x[i], y[i]);
-        if (!(val(gi[i]) > 0.0)) status = ORC_NONPHYS;
+        if (!(val(gi[i]) > 0.0)) nonphys = 1;
         vx[i] = px[i] / gi[i];
         vy[i] = py[i] / gi[i];
         vxx[i] = vx[i] * vx[i];
@@ -641,6 +664,7 @@ int slice_step_t(const oracle_cfg* c, int P, T* x, T* y, T* px, T* py, T* pz, T*
             inv_err = std::max(inv_err, std::fabs(val(gam - pz[i] - gi[i])));
         }
     }
+    if (nonphys) status = ORC_NONPHYS;
     inf.invariant_err = inv_err;
     m.jx.assign(nn, T(0.0));
     m.jy.assign(nn, T(0.0));
@@ -655,6 +679,7 @@ int slice_step_t(const oracle_cfg* c, int P, T* x, T* y, T* px, T* py, T* pz, T*
 
     /* 4. Ez and Bz: L_h Ez = -div j (eq. (13)), L_h Bz = e_z.(curl j) (eq. (14)). */
     std::vector<T> fE(nn, T(0.0)), fB(nn, T(0.0));
+#pragma omp parallel for schedule(static)
     for (int b = 1; b < g.N; ++b)
         for (int a = 1; a < g.N; ++a) {
             int i = g.id(a, b);
@@ -684,6 +709,7 @@ int slice_step_t(const oracle_cfg* c, int P, T* x, T* y, T* px, T* py, T* pz, T*
     std::vector<T> gx, gy;
     psi_gradient<T>(g, psi, gx, gy);
     double vmax = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : vmax)
     for (int i = 0; i < P; ++i) {
         T Gx = gather1(g, gx.data(), x[i], y[i]);
         T Gy = gather1(g, gy.data(), x[i], y[i]);
@@ -728,6 +754,7 @@ int oracle_deposit(const oracle_cfg* c, int P, const double* x, const double* y,
 int oracle_gather(const oracle_cfg* c, int P, const double* x, const double* y,
                   const double* F, double* out) {
     Grid g(c->n_cells, c->half_width);
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < P; ++i) out[i] = gather1(g, F, x[i], y[i]);
     return ORC_OK;
 }
@@ -745,11 +772,27 @@ int oracle_apply(int N, double h, const double* k2, const double* u, double* out
 }
 
 int oracle_mg_solve(int N, double h, const double* k2, const double* f, double* u, double rtol,
-                    double atol, int max_cycles, int nu1, int nu2, double om, double k2_scale,
-                    int* cycles, double* rel) {
-    if (N < 2 || (N & (N - 1)) || !(om >= 0.0 && om < 2.0)) return ORC_INVALID;
-    return mg_solve(N, h, k2, f, u, rtol, atol, max_cycles, nu1, nu2, om, k2_scale, cycles, rel);
+                    double atol, int max_cycles, int nu1, int nu2, int* cycles, double* rel) {
+    if (N < 2 || (N & (N - 1))) return ORC_INVALID;
+    return mg_solve(N, h, k2, f, u, rtol, atol, max_cycles, nu1, nu2, cycles, rel);
 }
+
+/* Node gradient of psi as the particle gather uses it (see psi_gradient):
+ * out [2][nn] = d/dx, d/dy. */
+int oracle_psi_gradient(int N, double L, const double* psi, double* out) {
+    Grid g(N, L);
+    std::vector<double> gx, gy;
+    psi_gradient(g, psi, gx, gy);
+    std::copy(gx.begin(), gx.end(), out);
+    std::copy(gy.begin(), gy.end(), out + g.nn());
+    return ORC_OK;
+}
+
+/* Threads used by the parallel loops (n <= 0: the OpenMP default). */
+void oracle_set_threads(int n) {
+    if (n > 0) omp_set_num_threads(n);
+}
+int oracle_get_threads(void) { return omp_get_max_threads(); }
 
 int oracle_beam_density(const oracle_cfg* c, double xi, double* out) {
     Grid g(c->n_cells, c->half_width);
@@ -1015,8 +1058,7 @@ int adjoint_solve(const Grid& g, const oracle_cfg& c, const std::vector<double>*
     int cyc;
     double rel;
     return mg_solve(g.N, g.h, k2 ? k2->data() : nullptr, rhs.data(), lam.data(), c.mg_rtol, c.mg_atol,
-                    c.mg_max_cycles, c.nu_pre, c.nu_post, k2 ? c.mg_omega_helm : c.mg_omega, c.n0,
-                    &cyc, &rel);
+                    c.mg_max_cycles, c.nu_pre, c.nu_post, &cyc, &rel);
 }
 
 } /* namespace */

@@ -546,11 +546,12 @@ __global__ __launch_bounds__(kDxiThreads) void k_dxi(int nparts,
     if (threadIdx.x != 0) return;
     double vmax = red[0];
     for (int q = 1; q < kDxiThreads / 64; ++q) vmax = fmax(vmax, red[q]);
+    // Step_Size_Refinement: the step that keeps the fastest particle within one
+    // cell, capped at dxi0 and floored at dxi0 / k
     double d = dxi0;
-    if (adaptive) {
-        const double V0 = h / dxi0;
-        if (vmax > V0) d = dxi0 * V0 / vmax;
-        if (refine_k > 0 && d < dxi0 / refine_k) d = dxi0 / refine_k;
+    if (adaptive && vmax > 0.0) {
+        d = fmin(dxi0, h / vmax);
+        if (refine_k > 0) d = fmax(d, dxi0 / refine_k);
     }
     if (rec) {
         rec[0] = st[0];

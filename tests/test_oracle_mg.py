@@ -167,8 +167,10 @@ def test_zero_rhs_with_nonzero_guess(oracle_mod, helm):
 def test_stop_at_rounding_floor(oracle_mod, helm, smooth):
     """With a tolerance below reach (rtol 1e-16) the floor tests of the stop
     rule end the solve at the rounding floor, not before: one more V-cycle from
-    the returned iterate reduces ||r|| by less than 2x, while the cycle before
-    the stop still reduced it by more than 2x."""
+    the returned iterate reduces ||r|| by less than 2x.  And not much later:
+    the stop comes at most one cycle after the last cycle that still reduced
+    ||r|| by more than 2x (the stagnation test needs that one cycle when the
+    backward-error test does not fire at the first cycle on the floor)."""
     N, L = 128, 6.0
     h = 2 * L / N
     rng = np.random.default_rng(11)
@@ -188,38 +190,22 @@ def test_stop_at_rounding_floor(oracle_mod, helm, smooth):
 
     st, u, cyc, _ = oracle_mod.mg_solve(N, h, f, k2=k2, rtol=1e-16)
     assert st == 0 and cyc >= 3
+    _, u_prev2, _, _ = oracle_mod.mg_solve(N, h, f, k2=k2, rtol=0.0, max_cycles=cyc - 2)
     _, u_prev, _, _ = oracle_mod.mg_solve(N, h, f, k2=k2, rtol=0.0, max_cycles=cyc - 1)
     _, u_more, c1, _ = oracle_mod.mg_solve(N, h, f, u0=u, k2=k2, rtol=0.0, max_cycles=1)
     assert c1 == 1
-    r_prev, r_stop, r_more = rnorm(u_prev), rnorm(u), rnorm(u_more)
-    print(f"cycles {cyc}: ||r|| {r_prev:.3e} -> {r_stop:.3e} -> {r_more:.3e}")
+    r_prev2, r_prev, r_stop, r_more = rnorm(u_prev2), rnorm(u_prev), rnorm(u), rnorm(u_more)
+    print(f"cycles {cyc}: ||r|| {r_prev2:.3e} -> {r_prev:.3e} -> {r_stop:.3e} -> {r_more:.3e}")
     assert r_more > 0.5 * r_stop
-    assert r_stop < 0.5 * r_prev
+    assert r_stop < 0.5 * r_prev or r_prev < 0.5 * r_prev2
 
 
-@pytest.mark.parametrize("helm", [False, True])
-@pytest.mark.parametrize("omega", [0.8, 1.0, 1.5])
-def test_relaxation_factor_keeps_the_solution(oracle_mod, helm, omega):
-    """The relaxation factor of the red-black sweeps changes the path, not the
-    fixed point: for om in (0, 2) the solve reaches the sparse direct solution."""
-    N, L = 64, 5.0
-    h = 2 * L / N
-    rng = np.random.default_rng(21)
-    f = np.zeros((N + 1, N + 1))
-    f[1:-1, 1:-1] = rng.standard_normal((N - 1, N - 1))
-    k2 = rng.uniform(0.0, 10.0, (N + 1, N + 1)) if helm else None
-    ref = spla.spsolve(_scipy_operator(N, h, k2), f[1:-1, 1:-1].ravel()).reshape(N - 1, N - 1)
-    st, u, cyc, _ = oracle_mod.mg_solve(N, h, f, k2=k2, omega=omega)
-    assert st == 0
-    assert np.abs(u[1:-1, 1:-1] - ref).max() <= 1e-11 * np.abs(ref).max()
-
-
-def test_over_relaxation_speeds_the_v_cycle(oracle_mod):
-    """Over-relaxed red-black smoothing (om = 1.175) on the Poisson model
-    problem: the residual falls by a factor below 0.025 per V(2,2) cycle, where
-    plain Gauss-Seidel (om = 1) gives 0.05-0.06, the textbook rate of V-cycles
-    with red-black Gauss-Seidel, full weighting and bilinear prolongation; and
-    an over-relaxation past the optimum (om = 1.3) is slower again."""
+def test_vcycle_rate_is_textbook(oracle_mod):
+    """V(2,2) cycles of red-black Gauss-Seidel with full weighting and bilinear
+    prolongation reduce the residual of the Poisson model problem by a factor
+    of 0.04-0.07 per cycle (the textbook rate of this cycle, e.g. Trottenberg,
+    Oosterlee & Schueller, Multigrid, Sec. 4.6, about 0.05); a plainer cycle
+    (V(1,1)) is slower."""
     N, L = 128, 8.0
     h = 2 * L / N
     rng = np.random.default_rng(1)
@@ -227,43 +213,14 @@ def test_over_relaxation_speeds_the_v_cycle(oracle_mod):
     f[1:-1, 1:-1] = rng.standard_normal((N - 1, N - 1))
     A = _scipy_operator(N, h)
 
-    def rate(om):
+    def rate(nu):
         r = []
         for m in (4, 5, 6):
-            _, u, _, _ = oracle_mod.mg_solve(N, h, f, rtol=0.0, max_cycles=m, omega=om)
+            _, u, _, _ = oracle_mod.mg_solve(N, h, f, rtol=0.0, max_cycles=m, nu1=nu, nu2=nu)
             r.append(np.linalg.norm(f[1:-1, 1:-1].ravel() - A @ u[1:-1, 1:-1].ravel()))
         return max(r[1] / r[0], r[2] / r[1])
 
-    r1, r_opt, r_over = rate(1.0), rate(1.175), rate(1.3)
-    print(f"rate per cycle: om=1 {r1:.4f}, om=1.175 {r_opt:.4f}, om=1.3 {r_over:.4f}")
-    assert 0.04 <= r1 <= 0.07
-    assert r_opt <= 0.025
-    assert r_over > r_opt
-
-
-def test_helmholtz_coarse_levels_relax_without_over_relaxation(oracle_mod):
-    """Helmholtz model problem (k2 uniform in [0.5, 1.5], h = 1/8): over-relaxing
-    only the levels with h^2 k2_scale <= 1/8 (the default) gives a faster V-cycle
-    than over-relaxing every level, which is slower than plain Gauss-Seidel:
-    where the diagonal shift h^2 k2 is no longer small, over-relaxation hurts."""
-    N, L = 128, 8.0
-    h = 2 * L / N
-    rng = np.random.default_rng(3)
-    f = np.zeros((N + 1, N + 1))
-    f[1:-1, 1:-1] = rng.standard_normal((N - 1, N - 1))
-    k2 = rng.uniform(0.5, 1.5, (N + 1, N + 1))
-    A = _scipy_operator(N, h, k2)
-
-    def rate(**kw):
-        r = []
-        for m in (4, 5, 6):
-            _, u, _, _ = oracle_mod.mg_solve(N, h, f, k2=k2, rtol=0.0, max_cycles=m, **kw)
-            r.append(np.linalg.norm(f[1:-1, 1:-1].ravel() - A @ u[1:-1, 1:-1].ravel()))
-        return max(r[1] / r[0], r[2] / r[1])
-
-    r_rule = rate(omega=1.175)
-    r_all = rate(omega=1.175, k2_scale=0.0)
-    r_gs = rate(omega=1.0, k2_scale=0.0)
-    print(f"rate per cycle: level rule {r_rule:.4f}, all levels {r_all:.4f}, GS {r_gs:.4f}")
-    assert r_rule < 0.85 * r_gs
-    assert r_all > r_gs
+    r22, r11 = rate(2), rate(1)
+    print(f"rate per cycle: V(2,2) {r22:.4f}, V(1,1) {r11:.4f}")
+    assert 0.04 <= r22 <= 0.07
+    assert r11 > r22

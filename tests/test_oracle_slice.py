@@ -264,7 +264,14 @@ def test_linear_wake_closed_form(oracle_mod):
     and its convergence when h and dxi are halved (C1 and a refined C1)."""
     e64, r, cfg = _linear_error(oracle_mod, 64, 0.0625, 0.1)
     e128, _, _ = _linear_error(oracle_mod, 128, 0.03125, 0.01)
-    assert e64 < 0.2 and e128 < 0.06 and e64 / e128 > 2.5, (e64, e128)
+    e256, _, _ = _linear_error(oracle_mod, 256, 0.015625, 0.001)
+    print(f"on-axis Ez error vs the linear wake: {e64:.4f}, {e128:.4f}, {e256:.4f}")
+    # budget 20% / 6% / 2.5% (measured 16.3% / 5.0% / 1.65%): at C1 the driver
+    # spans sigma_r / h = 2.7 cells, so the discretisation error dominates; the
+    # pin's strength is that the error keeps falling ~3-4x per halving of h and
+    # dxi, which a wrong term would stop at an O(1) floor
+    assert e64 < 0.2 and e128 < 0.06 and e256 < 0.025, (e64, e128, e256)
+    assert 2.7 < e64 / e128 < 4.5 and 2.7 < e128 / e256 < 4.5, (e64, e128, e256)
     # B_perp of the linear wake at a few points, refined case
     N, dxi = 128, 0.03125
     cfg = wi.scaled(wi.config("C1"), n_cells=N, dxi0=dxi)
@@ -383,3 +390,82 @@ def test_nonphysical_reported(oracle_mod):
     st["y"] = st["y"] * 0.0 - 0.01
     r = o.slice_step(st)
     assert r["status"] == oracle_mod.NONPHYS
+
+
+def test_psi_gradient_boundary_rows(oracle_mod):
+    """The node gradient the particle gather uses: central differences inside,
+    one-sided differences on the boundary rows and columns.  A linear field's
+    gradient is exact on every node, the boundary included; for psi = x^2 the
+    interior gradient is exact (2x) and the one-sided boundary values carry
+    the first-order error +-h: (x_1^2 - x_0^2)/h = 2 x_0 + h and
+    (x_N^2 - x_{N-1}^2)/h = 2 x_N - h.  (A second-order one-sided formula would
+    be exact here, a zero or mirrored boundary value would not be 2x +- h.)"""
+    N, L = 32, 3.0
+    h = 2 * L / N
+    g = -L + h * np.arange(N + 1)
+    X, Y = np.meshgrid(g, g, indexing="xy")
+    G = oracle_mod.psi_gradient(N, L, 0.7 * X - 1.3 * Y + 0.25)
+    assert np.allclose(G[0], 0.7, rtol=0, atol=1e-13) and np.allclose(G[1], -1.3, rtol=0, atol=1e-13)
+    G = oracle_mod.psi_gradient(N, L, X * X + 0.5 * Y * Y * Y)
+    assert np.allclose(G[0][:, 1:-1], 2 * X[:, 1:-1], rtol=0, atol=1e-12)
+    assert np.allclose(G[0][:, 0], 2 * g[0] + h, rtol=0, atol=1e-12)
+    assert np.allclose(G[0][:, -1], 2 * g[-1] - h, rtol=0, atol=1e-12)
+    # y: central difference of y^3 is 3y^2 + h^2 (exact); one-sided at the edges
+    y = g
+    assert np.allclose(G[1][1:-1, :].T, 0.5 * (3 * y[1:-1] ** 2 + h * h), rtol=0, atol=1e-11)
+    assert np.allclose(G[1][0, :], 0.5 * (y[1] ** 3 - y[0] ** 3) / h, rtol=0, atol=1e-11)
+    assert np.allclose(G[1][-1, :], 0.5 * (y[-1] ** 3 - y[-2] ** 3) / h, rtol=0, atol=1e-11)
+
+
+def _lattice_bin_counts(n_half, p, q, n_bins):
+    """Nodes (i, j) of the integer lattice |i|, |j| <= n_half whose distance
+    from the origin, in units of the bin width p/q lattice steps, falls in bin
+    k: k <= q sqrt(i^2 + j^2) / p < k + 1, decided in exact integer arithmetic
+    ((k p)^2 <= q^2 (i^2 + j^2) < ((k+1) p)^2)."""
+    i = np.arange(-n_half, n_half + 1, dtype=np.int64)
+    d2 = (i[:, None] ** 2 + i[None, :] ** 2) * q * q
+    return np.array([np.count_nonzero((d2 >= (k * p) ** 2) & (d2 < ((k + 1) * p) ** 2))
+                     for k in range(n_bins)])
+
+
+@pytest.mark.parametrize("case", ["edges_on_nodes", "edges_between_nodes"])
+def test_radial_bin_driver_nodes(oracle_mod, case):
+    """Radial-bin driver: bin k holds the nodes with k dr <= r < (k+1) dr around
+    its centre (r_max = n_bins dr), its density there is bin_amp[k] times the
+    xi factor exp(-(xi-xc)^2/sz^2), and it vanishes for xi < 0.  The node set of
+    every bin is checked against an exact integer count of lattice points in
+    the annulus; the summed charge per bin, sum n_b h^2, against the annulus
+    area pi((k+1)^2 - k^2) dr^2 within the lattice-point bound
+    pi((r+h/sqrt2)^2 - (r-h/sqrt2)^2) on each edge.  Two cases: the C4 recipe
+    (dr = h, so edges fall on nodes, which belong to the outer bin) and
+    dr = 208/25 h off-centre (no node on an edge)."""
+    if case == "edges_on_nodes":
+        N, L, p, q, nb, cx, cy = 256, 8.0, 1, 1, 32, 0, 0
+    else:
+        N, L, p, q, nb, cx, cy = 256, 4.0, 208, 25, 9, 3, -5
+    h = 2 * L / N
+    dr = h * p / q
+    x0, y0 = cx * h, cy * h
+    n_half = N // 2 - max(abs(cx), abs(cy))
+    assert nb * dr < n_half * h  # every annulus lies inside the grid
+    exact = _lattice_bin_counts(n_half, p, q, nb)
+    xc, sz = 1.5, 0.8
+    for k in range(nb):
+        amp = np.zeros(nb)
+        amp[k] = 1.0 + k
+        cfg = wi.scaled(wi.config("C1"), n_cells=N, half_width=L,
+                        beams=[wi.radial_bins_beam(amp, nb * dr, sz, xc, x0=x0, y0=y0)])
+        o = oracle_mod.Oracle(cfg)
+        nbd = o.beam_density(xc)
+        on = nbd != 0.0
+        assert np.count_nonzero(on) == exact[k], (k, np.count_nonzero(on), exact[k])
+        assert np.all(nbd[on] == amp[k])
+        q_bin = nbd.sum() * h * h / amp[k]
+        area = np.pi * ((k + 1) ** 2 - k ** 2) * dr * dr
+        bound = sum(np.pi * ((r + h / np.sqrt(2)) ** 2 - max(r - h / np.sqrt(2), 0.0) ** 2)
+                    for r in (k * dr, (k + 1) * dr))
+        assert abs(q_bin - area) <= bound, (k, q_bin, area, bound)
+        if k == nb // 2:
+            np.testing.assert_allclose(o.beam_density(xc + sz)[on], amp[k] * np.exp(-1.0),
+                                       rtol=1e-15)
+            assert not o.beam_density(-1e-3).any()
