@@ -10,12 +10,16 @@ adaptive dxi (dxi0 = 0.005, refinement k = 8), FP64, multigrid solved to the
 rounding floor.  Inputs are synthetic (the cold plasma lattice of the input
 module) and resident on the GPU before the timed region.
 
-Timed region: K slices of one job started at xi = 0 (default K = 4096, the
-whole job), after W warm-up slices on a separate context.  Printed value:
-particle-slice updates per second (P * K / wall time).  A second pass over the
-same K slices records every kernel launch with HIP events for the roofline of
-the dominant kernel.  The CPU oracle is timed on a bounded sample of the same
-job (its first slices) for the cpu_baseline record.
+Timed region: the job runs untimed from xi = 0 to the driver centre (xi >= 2 by
+default: inside the blowout, where the solves are hardest and crowded cells
+appear), then W warm-up slices, then K timed slices.  Printed value:
+particle-slice updates per second (P * K / wall time).  The window's start
+state is kept; a second pass over the same K slices from it records every
+kernel launch with HIP events for the roofline of the dominant kernel, and the
+FP64-vs-mixed comparison and the forward-plus-adjoint timing start from it too.
+The CPU oracle is timed on a bounded sample of the same job from its own cold
+start (it cannot reach the window within the run's time), on all the threads
+it is given and on one.
 """
 from __future__ import annotations
 
@@ -103,35 +107,66 @@ def _cpu_model() -> str:
     return "unknown CPU"
 
 
-def cpu_baseline(cfg: dict, n_slices: int):
+def cpu_baseline(cfg: dict, slices_all: int, slices_one: int, reps: int = 3):
+    """The oracle on the first slices of the job from its cold start: `reps`
+    runs of `slices_all` slices on all the threads OpenMP is given (the
+    OMP_NUM_THREADS share of the host) and of `slices_one` slices on one
+    thread; the median of each.  Its results do not depend on the thread
+    count.  Returns the record for the all-threads figure."""
+    import statistics
     import oracle
     orc = oracle.Oracle(cfg)
-    st = oracle.initial_state(cfg)
-    t0 = time.perf_counter()
-    r = orc.run(st, n_slices)
-    dt = time.perf_counter() - t0
-    P = st["x"].size
-    return dict(value=P * n_slices / dt, unit="particle-slice updates/s", cores=1, kind="oracle",
-                sample=f"first {n_slices} slices of the same job from xi=0 "
-                       f"(single-threaded FP64 oracle on {_cpu_model()}, {dt:.1f} s, "
-                       f"status {r['status']})")
+    n_all = oracle.get_threads()
+    res = {}
+    for nt, ns in ((n_all, slices_all), (1, slices_one)):
+        oracle.set_threads(nt)
+        rates, cyc = [], None
+        for _ in range(reps):
+            st = oracle.initial_state(cfg)
+            t0 = time.perf_counter()
+            r = orc.run(st, ns)
+            dt = time.perf_counter() - t0
+            assert r["status"] == 0, r["status"]
+            rates.append(st["x"].size * ns / dt)
+            cyc = [sum(i.cycles[k] for i in r["infos"]) / ns for k in range(5)]
+        res[nt] = (statistics.median(rates), rates, cyc)
+        print(f"[bench] oracle on {nt} thread(s): {ns} slices x {reps}: "
+              f"{['%.3e' % v for v in rates]} particle-slice/s", file=sys.stderr, flush=True)
+    oracle.set_threads(n_all)
+    v_all, r_all, cyc = res[n_all]
+    v_one = res[1][0]
+    return dict(value=v_all, unit="particle-slice updates/s", cores=n_all, kind="oracle",
+                single_core_value=v_one, runs=reps,
+                sample=(f"median of {reps} runs of the first {slices_all} slices of the same job "
+                        f"from its cold start (xi = 0) on {n_all} OpenMP threads, and of "
+                        f"{reps} runs of {slices_one} slices on 1 thread ({v_one:.3e}/s); FP64 "
+                        f"oracle, plain V(2,2) Gauss-Seidel, mean V-cycles per solve "
+                        f"{[round(c, 2) for c in cyc]}, on {_cpu_model()}"))
 
 
-def adjoint_timing(cfg: dict, S: int, K: int):
+def _start(sim, win):
+    """Put the window's start state into a fresh context (its tape, if any,
+    starts there)."""
+    sim.set_state(particles=win["particles"], fields=win["fields"], xi=win["xi"], dxi=win["dxi"])
+
+
+def adjoint_timing(cfg: dict, win: dict, S: int, K: int):
     """Forward without tape, forward with the tape (checkpoint every K) and the
-    reverse sweep over the same S slices from the cold plasma.  Loss: the mean
-    Ez on a disc over the last S/4 slices plus a random linear function of the
-    final particles, so every slice carries nonzero adjoints."""
+    reverse sweep over the same S slices from the window's start state.  Loss:
+    the mean Ez on a disc over the last S/4 slices plus a random linear
+    function of the final particles, so every slice carries nonzero adjoints.
+    The adaptive steps are held at the forward's values in the reverse sweep."""
     import numpy as np
     import torch
     from paper_2012_00881_amd import Simulation
     probe = dict(field=1, slice_begin=S - S // 4, slice_end=S, r_max=0.5, x0=0.0, y0=0.0)
-    res = {"slices": S, "checkpoint_every": K}
+    res = {"slices": S, "checkpoint_every": K, "xi_start": win["xi"]}
     for taped in (False, True):
-        c = dict(cfg, probes=[probe], checkpoint_every=K if taped else 0)
+        c = dict(cfg, probes=[probe], checkpoint_every=K if taped else 0, adjoint_hold_dxi=1)
         print(f"[bench] adjoint: forward {S} slices, tape {'on' if taped else 'off'}",
               file=sys.stderr, flush=True)
         sim = Simulation(c, n_slices=S)
+        _start(sim, win)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sim.run(S, probes=True)
@@ -165,13 +200,70 @@ def adjoint_timing(cfg: dict, S: int, K: int):
     return res
 
 
+def forms_timing(cfg: dict, win: dict, S: int, rtol: float):
+    """The FP64 and the mixed form, both solved to `rtol`, over the same S
+    slices from the window's start state, against the FP64 path solved to the
+    rounding floor over those slices: time per slice and every field's error
+    after the last slice."""
+    import numpy as np
+    import torch
+    import wandqs_inputs as wi
+    from paper_2012_00881_amd import Simulation
+    print(f"[bench] forms reference (FP64, rtol {cfg['mg_rtol']:g}): {S} slices", file=sys.stderr,
+          flush=True)
+    sim = Simulation(wi.scaled(cfg, precision="fp64"), n_slices=S)
+    _start(sim, win)
+    sim.run(S)
+    ref = sim.get_state()["fields"].cpu().numpy()
+    sim.close()
+    del sim
+    out = {"rtol": rtol, "steps": S, "xi_start": win["xi"]}
+    for prec in ("fp64", "mixed"):
+        fc = wi.scaled(cfg, precision=prec, mg_rtol=rtol)
+        print(f"[bench] form {prec} @ rtol {rtol:g}: {S} slices", file=sys.stderr, flush=True)
+        sim = Simulation(fc, n_slices=S)
+        _start(sim, win)
+        torch.cuda.synchronize()
+        tf = time.perf_counter()
+        fi, _ = sim.run(S, infos=True)
+        torch.cuda.synchronize()
+        tf = time.perf_counter() - tf
+        got = sim.get_state()["fields"].cpu().numpy()
+        P = sim.P
+        sim.close()
+        del sim
+        # per-field error after the last slice: relative L2 over the interior
+        # (floored at 1e-3 of the largest field, for B_z = 0 runs) and node by node
+        I = (slice(1, -1), slice(1, -1))
+        big = max(float(np.linalg.norm(ref[j][I])) for j in range(5))
+        bigm = max(float(np.abs(ref[j][I]).max()) for j in range(5))
+        errs = [float(np.linalg.norm((got[k] - ref[k])[I]) /
+                      max(np.linalg.norm(ref[k][I]), 1e-3 * big)) for k in range(5)]
+        merrs = [float(np.abs((got[k] - ref[k])[I]).max() /
+                       max(np.abs(ref[k][I]).max(), 1e-3 * bigm)) for k in range(5)]
+        out[prec] = {
+            "value": P * S / tf, "ms_per_step": 1e3 * tf / S,
+            "mean_vcycles": [round(sum(i["vcycles"][k] for i in fi) / len(fi), 3) for k in range(5)],
+            "field_rel_err_vs_fp64_full": [float("%.3g" % e) for e in errs],
+            "field_maxabs_err_vs_fp64_full": [float("%.3g" % e) for e in merrs],
+            "within_1e-6": bool(max(errs + merrs) <= 1e-6)}
+    out["mixed_speedup"] = out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"]
+    print(f"[bench] mixed speedup at rtol {rtol:g}: {out['mixed_speedup']:.3f}", file=sys.stderr,
+          flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4096)
-    ap.add_argument("--warmup", type=int, default=64)
+    ap.add_argument("--steps", type=int, default=256)
+    ap.add_argument("--warmup", type=int, default=16)
+    ap.add_argument("--xi-start", type=float, default=2.0,
+                    help="run the job untimed up to this xi before the warm-up and timed slices "
+                         "(default: the driver centre, inside the blowout)")
     ap.add_argument("--workload", default="C5")
-    ap.add_argument("--cpu-slices", type=int, default=8)
+    ap.add_argument("--cpu-slices", type=int, default=4,
+                    help="oracle slices per timed run on all threads (1 thread: half as many)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile-pass", action="store_true")
     ap.add_argument("--breakdown", default=None, help="write per-kernel stats (JSON) here")
@@ -179,10 +271,11 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--rtol", type=float, default=None, help="multigrid rtol (default 1e-14)")
     ap.add_argument("--inner", type=int, default=0, help="mixed: FP32 cycles per correction")
-    ap.add_argument("--forms-steps", type=int, default=1024,
-                    help="slices for the FP64-vs-mixed comparison at 1e-6 (0: skip)")
-    ap.add_argument("--forms-rtol", type=float, default=1e-6,
-                    help="multigrid rtol of both forms in the FP64-vs-mixed comparison")
+    ap.add_argument("--forms-steps", type=int, default=512,
+                    help="slices of the FP64-vs-mixed comparison (0: skip)")
+    ap.add_argument("--forms-rtol", type=float, default=None,
+                    help="multigrid rtol of both forms in that comparison (default: the input "
+                         "module's FORMS_RTOL)")
     ap.add_argument("--adjoint-steps", type=int, default=512,
                     help="slices of the taped forward + reverse sweep (0: skip)")
     ap.add_argument("--checkpoint-every", type=int, default=32)
@@ -195,7 +288,6 @@ def main():
               "across GPUs); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     import wandqs_inputs as wi
     from paper_2012_00881_amd import Simulation
@@ -219,17 +311,22 @@ def main():
               flush=True)
         del src, dst
 
-    print(f"[bench] warm-up: {W} slices", file=sys.stderr, flush=True)
-    sim = Simulation(cfg, n_slices=max(W, 1))
+    sim = Simulation(cfg, n_slices=max(K, W, 64))
+    P = sim.P
+    lead = 0
+    xi = 0.0
+    while xi < args.xi_start:
+        sim.run(64)
+        lead += 64
+        xi = sim.get_state()["xi"]
+    print(f"[bench] lead-in: {lead} slices to xi={xi:.4f}; warm-up: {W} slices", file=sys.stderr,
+          flush=True)
     if W:
         sim.run(W)
-    torch.cuda.synchronize()
-    sim.close()
-    del sim
-
-    print(f"[bench] timed: {K} slices", file=sys.stderr, flush=True)
-    sim = Simulation(cfg, n_slices=max(K, 1))
-    P = sim.P
+    win = sim.get_state()
+    win = dict(particles=win["particles"].clone(), fields=win["fields"].clone(), xi=win["xi"],
+               dxi=win["dxi"])
+    print(f"[bench] timed: {K} slices from xi={win['xi']:.4f}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos, _ = sim.run(K, infos=True)
@@ -240,15 +337,18 @@ def main():
     del sim
     value = P * K / dt
     cyc = [sum(i["vcycles"][k] for i in infos) / max(1, len(infos)) for k in range(5)]
-    print(f"[bench] {K} slices in {dt:.3f} s: {value:.4e} particle-slice/s, xi_end={final['xi']:.4f}, "
-          f"mean V-cycles per solve {['%.2f' % c for c in cyc]}", file=sys.stderr, flush=True)
+    print(f"[bench] {K} slices in {dt:.3f} s: {value:.4e} particle-slice/s, xi {win['xi']:.4f} -> "
+          f"{final['xi']:.4f}, mean V-cycles per solve {['%.2f' % c for c in cyc]}",
+          file=sys.stderr, flush=True)
 
     roof = None
     vcycle = None
     stats = []
     if not args.no_profile_pass:
-        print("[bench] profiled pass (HIP events per launch)", file=sys.stderr, flush=True)
+        print("[bench] profiled pass (HIP events per launch) over the same slices", file=sys.stderr,
+              flush=True)
         sim = Simulation(cfg, n_slices=max(K, 1))
+        _start(sim, win)
         sim.profile(True)
         torch.cuda.synchronize()
         tp = time.perf_counter()
@@ -269,7 +369,7 @@ def main():
             g["alg_bytes"] += s["alg_bytes"]
         stats = sorted(groups.values(), key=lambda s: -s["total_ms"])
         tot = sum(s["total_ms"] for s in stats)
-        for s in stats[:12]:
+        for s in stats[:14]:
             avg = s["total_ms"] / s["launches"]
             print(f"[bench]   {s['name']:34s} {s['launches']:7d} launches {s['total_ms']:9.2f} ms "
                   f"({100 * s['total_ms'] / tot:5.1f}%) avg {1e3 * avg:8.2f} us "
@@ -290,67 +390,29 @@ def main():
                 "traffic": traffic, "alg_bytes_per_launch": round(bytes_per_launch),
                 "avg_launch_us": round(avg_s * 1e6, 2), "launches": dom["launches"],
                 "share_of_kernel_time": round(dom["total_ms"] / tot, 4),
+                "kernel_ms_per_slice": round(tot / K, 4),
                 "profiled_pass_s": round(tp, 3)}
         vcycle = vcycle_bandwidth(stats, tot)
         print(f"[bench] V-cycle kernels: {vcycle}", file=sys.stderr, flush=True)
         if args.breakdown:
             os.makedirs(os.path.dirname(os.path.abspath(args.breakdown)), exist_ok=True)
             with open(args.breakdown, "w") as fh:
-                json.dump(dict(workload=args.workload, slices=K, particles=P, stats=stats,
-                               per_level=per_level, source_hash=kernel_source_hash()), fh,
-                          indent=1)
+                json.dump(dict(workload=args.workload, slices=K, particles=P, xi_start=win["xi"],
+                               stats=stats, per_level=per_level,
+                               source_hash=kernel_source_hash()), fh, indent=1)
 
     forms = None
     if args.forms_steps > 0:
-        # FP64 and mixed solved to the same loose tolerance: rtol 1e-6 is the
-        # loosest that keeps every field within 1e-6 of the FP64 path at full
-        # tolerance over the job's first 1024 slices (measured: 6.3e-7 for B_z;
-        # at rtol 1e-5, 1.6e-5); each form's per-field error is reported
-        forms = {}
-        # reference: the FP64 path at full parity tolerance over the same slices
-        print(f"[bench] forms reference (FP64, rtol 1e-14): {args.forms_steps} slices",
-              file=sys.stderr, flush=True)
-        sim = Simulation(cfg, n_slices=args.forms_steps)
-        sim.run(args.forms_steps)
-        ref = sim.get_state()["fields"].cpu().numpy()
-        sim.close()
-        del sim
-        for prec in ("fp64", "mixed"):
-            fc = wi.scaled(cfg, precision=prec, mg_rtol=args.forms_rtol)
-            print(f"[bench] form {prec} @1e-6: {args.forms_steps} slices", file=sys.stderr, flush=True)
-            sim = Simulation(fc, n_slices=args.forms_steps)
-            torch.cuda.synchronize()
-            tf = time.perf_counter()
-            fi, _ = sim.run(args.forms_steps, infos=True)
-            torch.cuda.synchronize()
-            tf = time.perf_counter() - tf
-            got = sim.get_state()["fields"].cpu().numpy()
-            sim.close()
-            del sim
-            # per-field error after the last slice (the scale floor of the parity
-            # tests: 1e-3 of the largest field, for B_z = 0 runs)
-            big = max(float(np.linalg.norm(ref[j])) for j in range(5))
-            errs = [float(np.linalg.norm(got[k] - ref[k]) / max(np.linalg.norm(ref[k]), 1e-3 * big))
-                    for k in range(5)]
-            forms[prec + "@1e-6"] = {
-                "value": P * args.forms_steps / tf, "ms_per_step": 1e3 * tf / args.forms_steps,
-                "steps": args.forms_steps,
-                "mean_vcycles": [round(sum(i["vcycles"][k] for i in fi) / len(fi), 3)
-                                 for k in range(5)],
-                "field_rel_err_vs_fp64_full": [float("%.3g" % e) for e in errs]}
-        forms["mixed_speedup"] = (forms["fp64@1e-6"]["ms_per_step"] /
-                                  forms["mixed@1e-6"]["ms_per_step"])
-        print(f"[bench] mixed speedup at 1e-6: {forms['mixed_speedup']:.3f}", file=sys.stderr,
-              flush=True)
+        forms = forms_timing(cfg, win, args.forms_steps,
+                             args.forms_rtol if args.forms_rtol is not None else wi.FORMS_RTOL)
 
     adjoint = None
     if args.adjoint_steps > 0:
-        adjoint = adjoint_timing(cfg, args.adjoint_steps, args.checkpoint_every)
+        adjoint = adjoint_timing(cfg, win, args.adjoint_steps, args.checkpoint_every)
 
     cpu = None
     if not args.no_cpu_baseline:
-        print(f"[bench] CPU oracle on {args.cpu_slices} slices", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(cfg, args.cpu_slices)
+        cpu = cpu_baseline(cfg, args.cpu_slices, max(1, args.cpu_slices // 2))
 
     line = {"metric": "particle-slice updates/s", "value": value,
             "unit": "particle-slice updates/s", "n_gpus": 1, "steps": K, "warmup": W,
@@ -360,7 +422,11 @@ def main():
             "config": {"workload": WORKLOAD if args.workload == "C5" else args.workload,
                        "grid": cfg["n_cells"], "particles": P, "slices": K,
                        "precision": args.precision, "mg_rtol": cfg["mg_rtol"],
-                       "xi_end": final["xi"],
+                       "coarse_corrections": "the FP64 form's Helmholtz coarse levels (<= 64^2) "
+                                             "sweep in FP32 and its Poisson coarse level is solved "
+                                             "by an FP32 sine transform; the FP64 fine levels' "
+                                             "residuals carry the answer to the FP64 rounding floor",
+                       "lead_in_slices": lead, "xi_start": win["xi"], "xi_end": final["xi"],
                        "mean_vcycles": [round(c, 3) for c in cyc]},
             "roofline": roof, "vcycle_hbm": vcycle, "cpu_baseline": cpu, "forms": forms,
             "adjoint": adjoint}

@@ -123,6 +123,16 @@ typedef struct {
                                  levels with h^2 n0 <= 1/8; the coarser ones,
                                  whose diagonal shift h^2 k2 is no longer small,
                                  relax with om = 1; 0 selects 1.175 */
+    int32_t adjoint_hold_dxi; /* 1: with adaptive = 1 and a tape (checkpoint_every > 0),
+                                 wandqs_backward differentiates the slice map with
+                                 the step sequence dxi_j the forward took held
+                                 fixed (Step_Size_Refinement is not differentiated:
+                                 the gradient is exact only while each step is
+                                 dxi0 or its floor dxi0/k, where Vmax does not
+                                 enter); 0: such a configuration is rejected
+                                 (WANDQS_E_INVALID), since the step then depends on
+                                 the state through Vmax.  Ignored without adaptive
+                                 steps or without a tape. */
 } wandqs_config;
 
 typedef struct {

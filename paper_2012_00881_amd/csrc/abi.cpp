@@ -64,6 +64,10 @@ std::string check_config(const wandqs_config* c, int32_t n_slices) {
             return "bad probe";
     }
     if (c->checkpoint_every < 0) return "checkpoint_every must be >= 0";
+    if (c->adjoint_hold_dxi != 0 && c->adjoint_hold_dxi != 1) return "adjoint_hold_dxi must be 0 or 1";
+    if (c->checkpoint_every > 0 && c->adaptive && !c->adjoint_hold_dxi)
+        return "a tape with adaptive steps differentiates with the forward's steps held fixed "
+               "(they depend on the state through Vmax): set adjoint_hold_dxi = 1 to accept that";
     return "";
 }
 

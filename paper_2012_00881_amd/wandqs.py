@@ -51,7 +51,7 @@ class Config(C.Structure):
                 ("n_beams", C.c_int32), ("beams", C.POINTER(Beam)), ("n_probes", C.c_int32),
                 ("probes", C.POINTER(Probe)), ("checkpoint_every", C.c_int32),
                 ("mg_inner_cycles", C.c_int32), ("mg_omega", C.c_double),
-                ("mg_omega_helm", C.c_double)]
+                ("mg_omega_helm", C.c_double), ("adjoint_hold_dxi", C.c_int32)]
 
 
 class KernelStat(C.Structure):
@@ -152,6 +152,7 @@ def make_config(cfg: dict):
     c.mg_inner_cycles = cfg.get("mg_inner_cycles", 0)
     c.mg_omega = cfg.get("mg_omega", 0.0)
     c.mg_omega_helm = cfg.get("mg_omega_helm", 0.0)
+    c.adjoint_hold_dxi = int(cfg.get("adjoint_hold_dxi", 0))
     return c, keep
 
 

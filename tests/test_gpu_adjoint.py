@@ -90,6 +90,43 @@ def test_slice_adjoint_matches_oracle(torch_cuda, oracle_mod, seed):
     sim.close()
 
 
+@pytest.mark.parametrize("name,N", [("C2", 256), ("C5", 1024)])
+def test_slice_adjoint_matches_oracle_large(torch_cuda, oracle_mod, name, N):
+    """One taped slice on the C2 (256^2) and C5 (1024^2, 4.2M particles) grids,
+    where the adjoint solves run through the register and LDS tiles, the exact
+    sine-transform coarse solve and the Helmholtz coarse kernel, and the
+    particle adjoint kernels over hundreds of tiles: random adjoints on every
+    output, against the oracle's reverse of the same slice.  A radial-bin beam
+    next to the Gaussian driver gives bin adjoints too."""
+    cfg = wi.scaled(wi.config(name), n_cells=N, adaptive=0, checkpoint_every=1)
+    cfg["beams"].append(wi.radial_bins_beam([0.3, 0.7, 0.2, 0.5], 1.2, 0.6, 2.1, x0=0.3))
+    st0 = wi.synthetic_state(cfg, seed=31, p_max=0.4, xi=2.0, field_amp=0.01)
+    P = st0["x"].size
+    orc = oracle_mod.Oracle(cfg)
+    ost = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in st0.items()}
+    assert orc.slice_step(ost)["status"] == 0
+    rng = np.random.default_rng(N)
+    abar = rng.standard_normal((4, P))
+    Fbar = rng.standard_normal((5, N + 1, N + 1))
+    Fbar[:, [0, -1], :] = 0
+    Fbar[:, :, [0, -1]] = 0
+    so, ib, tb = orc.slice_adjoint(st0, ost["fields"].copy(), abar, Fbar)
+    assert so == 0
+    sim = _sim(cfg, 1)
+    sim.set_state(particles=np.stack([st0["x"], st0["y"], st0["px"], st0["py"]]),
+                  fields=st0["fields"], xi=st0["xi"], dxi=st0["dxi"])
+    sim.step()
+    th, p0 = sim.backward(dL_dfields=Fbar[None], dL_dparticles=abar, particles_grad=True)
+    p0 = p0.cpu().numpy()
+    errs = [_rel(p0[k], ib[k]) for k in range(4)]
+    emax = [float(np.abs(p0[k] - ib[k]).max() / np.abs(ib[k]).max()) for k in range(4)]
+    print(f"{name} slice adjoint rel errors x, y, px, py: {errs}; node-wise {emax}; "
+          f"theta {_rel(th, tb)}", flush=True)
+    assert max(errs) <= ADJ_TOL and max(emax) <= ADJ_TOL, (errs, emax)
+    assert _rel(th, tb) <= ADJ_TOL, (th, tb)
+    sim.close()
+
+
 @pytest.mark.parametrize("K", [1, 7, 16, 64])
 def test_run_gradient_matches_oracle(torch_cuda, oracle_mod, K):
     """dL/dtheta of the probe loss through 40 slices from the cold plasma, for
@@ -210,7 +247,7 @@ def test_c4_full_gradient_matches_finite_differences(torch_cuda):
         fd = (probe(th0 + eps * d) - probe(th0 - eps * d)) / (2 * eps)
         ad = float(g @ d)
         print(f"C4 directional derivative: adjoint {ad:.10e} FD {fd:.10e}")
-        assert abs(ad - fd) <= 1e-5 * np.abs(g * d).sum()
+        assert abs(ad - fd) <= 1e-5 * abs(ad)
 
 
 def test_run_gradient_matches_tangent_linear(torch_cuda, oracle_mod):

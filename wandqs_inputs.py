@@ -86,6 +86,11 @@ def radial_bins_beam(bin_amp, r_max, sigma_z, xi_c, x0=0.0, y0=0.0):
                 xi_c=float(xi_c), x0=float(x0), y0=float(y0), amp=1.0, sigma_r=1.0)
 
 
+#: multigrid tolerance at which the FP64 and mixed forms are compared for
+#: speed (every field must stay within 1e-6 of the oracle there)
+FORMS_RTOL = 1e-7
+
+
 def _base(**kw):
     cfg = dict(n_cells=64, half_width=6.0, ppc_side=1, jitter=0.0, seed=0, n0=1.0,
                dxi0=0.0625, adaptive=0, refine_k=0, precision="fp64",
