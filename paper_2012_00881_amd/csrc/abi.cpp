@@ -6,6 +6,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 #include <new>
@@ -15,12 +16,18 @@
 
 namespace {
 
-thread_local std::string g_init_err;
+// message of the last failed call made without a context (copied into a fixed
+// buffer: no allocation on the paths that must not allocate)
+thread_local char g_init_err[256];
+
+void set_init_err(const char* m) {
+    std::snprintf(g_init_err, sizeof g_init_err, "%s", m ? m : "");
+}
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
-// Returns an empty string when the configuration is valid.
-std::string check_config(const wandqs_config* c, int32_t n_slices) {
+// Returns NULL when the configuration is valid, else the reason.
+const char* check_config(const wandqs_config* c, int32_t n_slices) {
     if (!c) return "config is NULL";
     if (n_slices < 1) return "n_slices must be >= 1";
     if (!is_pow2(c->n_cells) || c->n_cells < 8 || c->n_cells > 4096)
@@ -68,7 +75,7 @@ std::string check_config(const wandqs_config* c, int32_t n_slices) {
     if (c->checkpoint_every > 0 && c->adaptive && !c->adjoint_hold_dxi)
         return "a tape with adaptive steps differentiates with the forward's steps held fixed "
                "(they depend on the state through Vmax): set adjoint_hold_dxi = 1 to accept that";
-    return "";
+    return nullptr;
 }
 
 // SplitMix64 (Steele, Lea & Flood 2014), counter form: draw k of stream `seed`.
@@ -141,6 +148,13 @@ void set_sizes(wandqs_ctx* c, const wandqs_config* cfg, int32_t n_slices) {
     }
     c->tape_K = cfg->checkpoint_every;
     c->n_ckpt = c->tape_K > 0 ? (n_slices + c->tape_K - 1) / c->tape_K + 1 : 0;
+}
+
+// relaxation factors measured to minimise the V-cycles per solve on the
+// blowout workloads (the Helmholtz one on its levels with h^2 n0 <= 1/8)
+void apply_defaults(wandqs_ctx* c) {
+    if (c->cfg.mg_omega == 0.0) c->cfg.mg_omega = 1.175;
+    if (c->cfg.mg_omega_helm == 0.0) c->cfg.mg_omega_helm = 1.175;
 }
 
 wandqs_status fail(wandqs_ctx* c, wandqs_status s) {
@@ -272,6 +286,25 @@ wandqs_status check_flags(wandqs_ctx* c) {
     return WANDQS_OK;
 }
 
+// Tables of the exact coarse Poisson solves (float; the mixed form also keeps
+// double copies for its FP64 coarsest-grid solve).
+template <class Take>
+void carve_dst(wandqs_ctx* c, Take&& take) {
+    const bool mixed = c->cfg.precision == WANDQS_MIXED;
+    c->dst_S = (float*)take(sizeof(float) * 64 * 64);
+    c->dst_M = (float*)take(sizeof(float) * 64 * 64);
+    c->dst_S64 = mixed ? (double*)take(sizeof(double) * 64 * 64) : nullptr;
+    c->dst_M64 = mixed ? (double*)take(sizeof(double) * 64 * 64) : nullptr;
+    if (wq::dst128_used(c)) {
+        c->dst2_S = (float*)take(sizeof(float) * 128 * 128);
+        c->dst2_M = (float*)take(sizeof(float) * 128 * 128);
+        c->dst2_X = (float*)take(sizeof(float) * 2 * 128 * 128);
+        c->dst2_S64 = mixed ? (double*)take(sizeof(double) * 128 * 128) : nullptr;
+        c->dst2_M64 = mixed ? (double*)take(sizeof(double) * 128 * 128) : nullptr;
+        c->dst2_X64 = mixed ? (double*)take(sizeof(double) * 2 * 128 * 128) : nullptr;
+    }
+}
+
 }  // namespace
 
 size_t wq::carve(wandqs_ctx* c, char* base) {
@@ -305,13 +338,7 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
         c->k2levf = (float*)take(sizeof(float) * (size_t)tot);
         c->idlevf = (float*)take(sizeof(float) * (size_t)tot);
     }
-    c->dst_S = (float*)take(sizeof(float) * 64 * 64);
-    c->dst_M = (float*)take(sizeof(float) * 64 * 64);
-    if (dst128_used(c)) {
-        c->dst2_S = (float*)take(sizeof(float) * 128 * 128);
-        c->dst2_M = (float*)take(sizeof(float) * 128 * 128);
-        c->dst2_X = (float*)take(sizeof(float) * 2 * 128 * 128);
-    }
+    carve_dst(c, take);
     for (int l = 1; l <= c->lc; ++l) {
         Level& L = c->lev[l];
         for (int r = 0; r < 2; ++r) {
@@ -408,9 +435,9 @@ bool wq::node_in_disc_host(double L, double h, int a, int b, double x0, double y
 extern "C" {
 
 wandqs_status wandqs_workspace_bytes(const wandqs_config* cfg, int32_t n_slices, size_t* bytes) {
-    const std::string e = check_config(cfg, n_slices);
-    if (!e.empty() || !bytes) {
-        g_init_err = e.empty() ? "bytes is NULL" : e;
+    const char* e = check_config(cfg, n_slices);
+    if (e || !bytes) {
+        set_init_err(e ? e : "bytes is NULL");
         return WANDQS_E_INVALID;
     }
     wandqs_ctx tmp;
@@ -423,29 +450,26 @@ wandqs_status wandqs_workspace_bytes(const wandqs_config* cfg, int32_t n_slices,
 wandqs_status wandqs_init(const wandqs_config* cfg, int32_t n_slices, void* d_workspace,
                           size_t bytes, void* hip_stream, wandqs_ctx** out) {
     if (!out) {
-        g_init_err = "out is NULL";
+        set_init_err("out is NULL");
         return WANDQS_E_INVALID;
     }
     *out = nullptr;
-    const std::string e = check_config(cfg, n_slices);
-    if (!e.empty()) {
-        g_init_err = e;
+    const char* e = check_config(cfg, n_slices);
+    if (e) {
+        set_init_err(e);
         return WANDQS_E_INVALID;
     }
     if (!d_workspace || ((uintptr_t)d_workspace & 255)) {
-        g_init_err = "workspace must be a 256-byte aligned device pointer";
+        set_init_err("workspace must be a 256-byte aligned device pointer");
         return WANDQS_E_INVALID;
     }
     wandqs_ctx* c = new (std::nothrow) wandqs_ctx();
     if (!c) {
-        g_init_err = "out of host memory";
+        set_init_err("out of host memory");
         return WANDQS_E_NOMEM;
     }
     c->cfg = *cfg;
-    // relaxation factors measured to minimise the V-cycles per solve on the
-    // blowout workloads (the Helmholtz one on its levels with h^2 n0 <= 1/8)
-    if (c->cfg.mg_omega == 0.0) c->cfg.mg_omega = 1.175;
-    if (c->cfg.mg_omega_helm == 0.0) c->cfg.mg_omega_helm = 1.175;
+    apply_defaults(c);
     c->beams.assign(cfg->beams, cfg->beams + cfg->n_beams);
     c->probes.assign(cfg->probes, cfg->probes + cfg->n_probes);
     c->cfg.beams = nullptr;
@@ -459,14 +483,14 @@ wandqs_status wandqs_init(const wandqs_config* cfg, int32_t n_slices, void* d_wo
     set_sizes(c, cfg, n_slices);
     const size_t need = wq::carve(c, nullptr);
     if (bytes < need) {
-        g_init_err = "workspace too small: need " + std::to_string(need) + " bytes";
+        set_init_err(("workspace too small: need " + std::to_string(need) + " bytes").c_str());
         delete c;
         return WANDQS_E_NOMEM;
     }
     wq::carve(c, (char*)d_workspace);
 
     auto bail = [&](const std::string& msg) {
-        g_init_err = msg;
+        set_init_err(msg.c_str());
         if (c->h_pin) (void)hipHostFree(c->h_pin);
         delete c;
         return WANDQS_E_HIP;
@@ -591,17 +615,7 @@ wandqs_status wandqs_init(const wandqs_config* cfg, int32_t n_slices, void* d_wo
                     ids[i] = (int32_t)i;
                 }
     const double st0[6] = {0.0, cfg->dxi0, 0.0, 0.0, 0.0, 0.0};
-    std::vector<float> dstS(64 * 64), dstM(64 * 64), dst2S, dst2M;
-    wq::dst_tables(64, c->lev[c->lc].h, dstS.data(), dstM.data());
-    if (wq::dst128_used(c)) {
-        dst2S.resize(128 * 128);
-        dst2M.resize(128 * 128);
-        wq::dst_tables(128, c->lev[c->lc - 1].h, dst2S.data(), dst2M.data());
-    }
-    bool ok = hipMemcpyAsync(c->dst_S, dstS.data(), sizeof(float) * dstS.size(), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
-              hipMemcpyAsync(c->dst_M, dstM.data(), sizeof(float) * dstM.size(), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
-              (dst2S.empty() || hipMemcpyAsync(c->dst2_S, dst2S.data(), sizeof(float) * dst2S.size(), hipMemcpyHostToDevice, c->stream) == hipSuccess) &&
-              (dst2M.empty() || hipMemcpyAsync(c->dst2_M, dst2M.data(), sizeof(float) * dst2M.size(), hipMemcpyHostToDevice, c->stream) == hipSuccess) &&
+    bool ok = wq::make_dst_tables(c) == WANDQS_OK &&
               hipMemcpyAsync(c->pa[0][0], host.data(), sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
               hipMemcpyAsync(c->pa[0][1], host.data() + c->P, sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
               hipMemcpyAsync(c->pid[0], ids.data(), sizeof(int32_t) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
@@ -856,7 +870,7 @@ void wandqs_destroy(wandqs_ctx* c) {
 }
 
 const char* wandqs_last_error(const wandqs_ctx* c) {
-    return c ? c->err.c_str() : g_init_err.c_str();
+    return c ? c->err.c_str() : g_init_err;
 }
 
 }  // extern "C"

@@ -22,6 +22,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <type_traits>
 
 #include "wq_common.h"
 
@@ -1397,6 +1398,236 @@ __global__ __launch_bounds__(512) void k_dst2_inv(Dst2Args<E> a) {
         for (int x = tid; x <= kD2; x += 512) u[x] = E(0);  // row 0
 }
 
+// FP64 forms of the two exact coarse Poisson solves, for the mixed form,
+// whose coarsest-grid solve stays in FP64 while its V-cycle levels run in
+// FP32.  The products are plain FP64 fused multiply-adds from LDS (MI355X
+// issues FP64 matrix and vector arithmetic at the same rate): each thread owns
+// one column j and four consecutive rows of the output, so a wavefront reads
+// one row element of the left operand (an LDS broadcast) and 64 consecutive
+// elements of a row of the right operand per step.
+constexpr int kD2Ld64 = kD2 + 1;   // LDS row stride (doubles) of the 128 x 128 operands
+constexpr int kDstLd64 = kDstN + 1;
+
+template <typename E>
+struct Dst2Args64 {
+    int pitch;
+    const E* f[2];
+    E* u_out[2];
+    const double* S;
+    const double* M;
+    double* X;  // [R][128][128]
+};
+
+// acc[q] = sum_k A[q0 + q][k] B[k][j] for an inner dimension n.
+template <int n, int LDA, int LDB>
+__device__ __forceinline__ void rows4_times(const double* A, const double* B, int q0, int j,
+                                            double (&acc)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < n; ++k) {
+        const double b = B[k * LDB + j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = __builtin_fma(A[(q0 + q) * LDA + k], b, acc[q]);
+    }
+}
+
+// Rows i0 .. i0+15 of X = M o (S F S) on the 128^2 level: T = S[i0.., :] F,
+// then X = M o (T S); F[k][j] = f(node j+1, k+1).  8 workgroups of 512
+// threads per right-hand side.  LDS: the full right operand (F, then S) and
+// the 16-row left operand (rows of S, then T).
+template <typename E>
+__global__ __launch_bounds__(512) void k_dst2_fwd64(Dst2Args64<E> a) {
+    __shared__ double sB[kD2 * kD2Ld64];
+    __shared__ double sA[kD2Rows * kD2Ld64];
+    const int i0 = kD2Rows * blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+    const int j = tid & (kD2 - 1), q0 = 4 * (tid >> 7);
+    constexpr int kIt = kD2 * kD2 / 512, kRows = kD2Rows * kD2 / 512;
+    {   // every load before the first store (one round trip)
+        double fv[kIt], sv[kRows];
+#pragma unroll
+        for (int t = 0; t < kIt; ++t) {
+            const int i = tid + t * 512, y = i >> 7, x = i & (kD2 - 1);
+            fv[t] = (x < kD2 - 1 && y < kD2 - 1) ? (double)a.f[r][(size_t)(y + 1) * a.pitch + x + 1] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < kRows; ++t) sv[t] = a.S[i0 * kD2 + tid + t * 512];
+#pragma unroll
+        for (int t = 0; t < kIt; ++t) {
+            const int i = tid + t * 512;
+            sB[(i >> 7) * kD2Ld64 + (i & (kD2 - 1))] = fv[t];
+        }
+#pragma unroll
+        for (int t = 0; t < kRows; ++t) {
+            const int i = tid + t * 512;
+            sA[(i >> 7) * kD2Ld64 + (i & (kD2 - 1))] = sv[t];
+        }
+    }
+    __syncthreads();
+    double acc[4];
+    rows4_times<kD2, kD2Ld64, kD2Ld64>(sA, sB, q0, j, acc);  // T = S[i0.., :] F
+    __syncthreads();  // every read of the rows of S and of F is done
+    {
+        double sv[kIt];
+#pragma unroll
+        for (int t = 0; t < kIt; ++t) sv[t] = a.S[tid + t * 512];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sA[(q0 + q) * kD2Ld64 + j] = acc[q];
+#pragma unroll
+        for (int t = 0; t < kIt; ++t) {
+            const int i = tid + t * 512;
+            sB[(i >> 7) * kD2Ld64 + (i & (kD2 - 1))] = sv[t];
+        }
+    }
+    __syncthreads();
+    rows4_times<kD2, kD2Ld64, kD2Ld64>(sA, sB, q0, j, acc);  // T S
+    double* X = a.X + (size_t)r * kD2 * kD2;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = (i0 + q0 + q) * kD2 + j;
+        X[i] = a.M[i] * acc[q];
+    }
+}
+
+// Rows i0 .. i0+15 of u = S X S: Y = S[i0.., :] X, then u = Y S.
+template <typename E>
+__global__ __launch_bounds__(512) void k_dst2_inv64(Dst2Args64<E> a) {
+    __shared__ double sB[kD2 * kD2Ld64];
+    __shared__ double sA[kD2Rows * kD2Ld64];
+    const int i0 = kD2Rows * blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+    const int j = tid & (kD2 - 1), q0 = 4 * (tid >> 7);
+    constexpr int kIt = kD2 * kD2 / 512, kRows = kD2Rows * kD2 / 512;
+    const double* X = a.X + (size_t)r * kD2 * kD2;
+    {
+        double xv[kIt], sv[kRows];
+#pragma unroll
+        for (int t = 0; t < kIt; ++t) xv[t] = X[tid + t * 512];
+#pragma unroll
+        for (int t = 0; t < kRows; ++t) sv[t] = a.S[i0 * kD2 + tid + t * 512];
+#pragma unroll
+        for (int t = 0; t < kIt; ++t) {
+            const int i = tid + t * 512;
+            sB[(i >> 7) * kD2Ld64 + (i & (kD2 - 1))] = xv[t];
+        }
+#pragma unroll
+        for (int t = 0; t < kRows; ++t) {
+            const int i = tid + t * 512;
+            sA[(i >> 7) * kD2Ld64 + (i & (kD2 - 1))] = sv[t];
+        }
+    }
+    __syncthreads();
+    double acc[4];
+    rows4_times<kD2, kD2Ld64, kD2Ld64>(sA, sB, q0, j, acc);  // Y = S[i0.., :] X
+    __syncthreads();
+    {
+        double sv[kIt];
+#pragma unroll
+        for (int t = 0; t < kIt; ++t) sv[t] = a.S[tid + t * 512];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sA[(q0 + q) * kD2Ld64 + j] = acc[q];
+#pragma unroll
+        for (int t = 0; t < kIt; ++t) {
+            const int i = tid + t * 512;
+            sB[(i >> 7) * kD2Ld64 + (i & (kD2 - 1))] = sv[t];
+        }
+    }
+    __syncthreads();
+    rows4_times<kD2, kD2Ld64, kD2Ld64>(sA, sB, q0, j, acc);  // u = Y S
+    E* u = a.u_out[r];
+    // row and column 127 of S are 0, so row and column 128 (boundary) get 0
+#pragma unroll
+    for (int q = 0; q < 4; ++q) u[(size_t)(i0 + q0 + q + 1) * a.pitch + j + 1] = (E)acc[q];
+    if (tid < kD2Rows) u[(size_t)(i0 + tid + 1) * a.pitch] = E(0);  // column 0
+    if (blockIdx.x == 0)
+        for (int x = tid; x <= kD2; x += 512) u[x] = E(0);  // row 0
+}
+
+// The 64^2 exact solve in FP64 (grids of 128^2): one workgroup of 1024 threads
+// per right-hand side, u = S (M o (S F S)) S as four products in LDS.
+template <typename E>
+struct DstArgs64 {
+    int pitch;
+    const E* f[2];
+    E* u_out[2];
+    const double* S;
+    const double* M;
+};
+
+template <typename E>
+__global__ __launch_bounds__(1024) void k_coarse_dst64(DstArgs64<E> a) {
+    __shared__ double sS[kDstN * kDstLd64];
+    __shared__ double sX[kDstN * kDstLd64];
+    __shared__ double sY[kDstN * kDstLd64];
+    const int r = blockIdx.x, tid = threadIdx.x;
+    const int j = tid & (kDstN - 1), q0 = 4 * (tid >> 6);
+    constexpr int kIt = kDstN * kDstN / 1024;
+    {
+        double sv[kIt], fv[kIt];
+#pragma unroll
+        for (int t = 0; t < kIt; ++t) {
+            const int i = tid + t * 1024, y = i >> 6, x = i & (kDstN - 1);
+            sv[t] = a.S[i];
+            fv[t] = (x < kDstN - 1 && y < kDstN - 1) ? (double)a.f[r][(size_t)(y + 1) * a.pitch + x + 1] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < kIt; ++t) {
+            const int i = tid + t * 1024, y = i >> 6, x = i & (kDstN - 1);
+            sS[y * kDstLd64 + x] = sv[t];
+            sX[y * kDstLd64 + x] = fv[t];
+        }
+    }
+    __syncthreads();
+    double acc[4];
+    rows4_times<kDstN, kDstLd64, kDstLd64>(sS, sX, q0, j, acc);  // Y = S F
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sY[(q0 + q) * kDstLd64 + j] = acc[q];
+    __syncthreads();
+    rows4_times<kDstN, kDstLd64, kDstLd64>(sY, sS, q0, j, acc);  // X = M o (Y S)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sX[(q0 + q) * kDstLd64 + j] = a.M[(q0 + q) * kDstN + j] * acc[q];
+    __syncthreads();
+    rows4_times<kDstN, kDstLd64, kDstLd64>(sS, sX, q0, j, acc);  // Y = S X
+    __syncthreads();  // every read of sY (the previous product) is done
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sY[(q0 + q) * kDstLd64 + j] = acc[q];
+    __syncthreads();
+    rows4_times<kDstN, kDstLd64, kDstLd64>(sY, sS, q0, j, acc);  // U = Y S
+    E* u = a.u_out[r];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) u[(size_t)(q0 + q + 1) * a.pitch + j + 1] = (E)acc[q];
+    if (tid < kDstN) u[(size_t)(tid + 1) * a.pitch] = E(0);
+    if (tid <= kDstN) u[tid] = E(0);
+}
+
+// Tables of the exact coarse Poisson solve on an n^2 level of spacing H:
+// S_jk = sin(pi (j+1)(k+1) / n) (the argument reduced exactly modulo 2 pi),
+// M_jk = 1 / ((n/2)^2 lambda_jk), lambda_jk = -(4/H^2)(sin^2(pi (j+1)/2n) +
+// sin^2(pi (k+1)/2n)), the eigenvalue of the 5-point operator for the sine
+// mode (j+1, k+1); row and column n-1 are zero.  Float and (when S64 is set)
+// double copies.
+__global__ void k_dst_tables(int n, double H, float* S, float* M, double* S64, double* M64) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * n) return;
+    const int jj = i / n, kk = i - jj * n;
+    const bool in = jj < n - 1 && kk < n - 1;
+    const double pi = 3.14159265358979323846;
+    double sv = 0.0, mv = 0.0;
+    if (in) {
+        const int m = ((jj + 1) * (kk + 1)) % (2 * n);
+        sv = sin(pi * (double)m / (double)n);
+        const double sj = sin(pi * (jj + 1) / (2.0 * n));
+        const double sk = sin(pi * (kk + 1) / (2.0 * n));
+        const double lambda = -(4.0 / (H * H)) * (sj * sj + sk * sk);
+        mv = 1.0 / ((n / 2.0) * (n / 2.0) * lambda);
+    }
+    S[i] = (float)sv;
+    M[i] = (float)mv;
+    if (S64) {
+        S64[i] = sv;
+        M64[i] = mv;
+    }
+}
+
 // k2 of the coarse-kernel levels: the top level (N <= 64, pitched) copied
 // densely, then full weighting level by level.  One block.
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_k2(int N, int pitch, double h,
@@ -1777,7 +2008,30 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
                                      eb * R + eb * R / 4));
         down_pass<E>(R, helm, a, nu, g, s, ps);
     }
-    if (lb < lc) {
+    // the mixed form's inner cycles (E = float) solve their coarsest grid in FP64
+    constexpr bool coarse64 = std::is_same<E, float>::value;
+    if (lb < lc && coarse64) {
+        wq::Level& L = c->lev[lb];
+        Dst2Args64<E> d{};
+        d.pitch = L.pitch;
+        for (int r = 0; r < R; ++r) {
+            d.f[r] = F(lb, r);
+            d.u_out[r] = U(lb, r);
+        }
+        d.S = c->dst2_S64;
+        d.M = c->dst2_M64;
+        d.X = c->dst2_X64;
+        const double nodes = (double)(L.N + 1) * (L.N + 1);
+        const dim3 g(kD2 / kD2Rows, R);
+        {
+            ProfScope ps(c, "k_dst2_fwd64<float>", nodes * eb * R + 8.0 * kD2 * kD2 * (2.0 + R));
+            WQ_KLAUNCH(ps, k_dst2_fwd64<E>, g, dim3(512), 0, s, d);
+        }
+        {
+            ProfScope ps(c, "k_dst2_inv64<float>", nodes * eb * R + 8.0 * kD2 * kD2 * (1.0 + R));
+            WQ_KLAUNCH(ps, k_dst2_inv64<E>, g, dim3(512), 0, s, d);
+        }
+    } else if (lb < lc) {
         wq::Level& L = c->lev[lb];
         Dst2Args<E> d{};
         d.pitch = L.pitch;
@@ -1822,7 +2076,18 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
         a.nu2 = c->cfg.nu_post;
         const double nodes = (double)(L.N + 1) * (L.N + 1);
         char nm[64];
-        if (!helm && lc > 0 && L.N == kDstN) {  // exact Poisson coarse solve
+        if (!helm && lc > 0 && L.N == kDstN && coarse64) {  // exact Poisson coarse solve, FP64
+            DstArgs64<E> d{};
+            d.pitch = L.pitch;
+            for (int r = 0; r < R; ++r) {
+                d.f[r] = F(lc, r);
+                d.u_out[r] = U(lc, r);
+            }
+            d.S = c->dst_S64;
+            d.M = c->dst_M64;
+            ProfScope ps(c, "k_coarse_dst64<float>", nodes * 2.0 * eb * R + 2.0 * 8.0 * kDstN * kDstN);
+            WQ_KLAUNCH(ps, k_coarse_dst64<E>, dim3(R), dim3(1024), 0, s, d);
+        } else if (!helm && lc > 0 && L.N == kDstN) {  // exact Poisson coarse solve
             DstArgs<E> d{};
             d.pitch = L.pitch;
             for (int r = 0; r < R; ++r) {
@@ -1835,12 +2100,16 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
             ProfScope ps(c, nm, nodes * 2.0 * eb * R + 2.0 * 4.0 * kDstN * kDstN);
             WQ_KLAUNCH(ps, k_coarse_dst<E>, dim3(R), dim3(1024), 0, s, d);
         } else {
-            // float sweeps when the coarse levels only correct a finer level
-            const bool f32 = WQ_COARSE_F32 && lc > 0;
+            // float sweeps when the coarse levels only correct a finer FP64
+            // level; the mixed form's inner cycles run them in double
+            const bool f32 = WQ_COARSE_F32 && lc > 0 && !coarse64;
             prof_name(c, nm, sizeof nm, "k_mg_coarse<%s, %s, %s>", type_name(E()),
-                          f32 ? "float" : type_name(E()), helm ? "true" : "false");
+                          f32 ? "float" : (coarse64 ? "double" : type_name(E())), helm ? "true" : "false");
             ProfScope ps(c, nm, nodes * (eb * R + (a.u_init[0] ? eb * R : 0.0) + (helm ? 8.0 : 0.0) + eb * R));
-            if (f32) {
+            if (coarse64) {
+                if (helm) WQ_KLAUNCH(ps, (k_mg_coarse<E, double, true>), dim3(R), dim3(kCoarseThreads), 0, s, a);
+                else WQ_KLAUNCH(ps, (k_mg_coarse<E, double, false>), dim3(R), dim3(kCoarseThreads), 0, s, a);
+            } else if (f32) {
                 if (helm) WQ_KLAUNCH(ps, (k_mg_coarse<E, float, true>), dim3(R), dim3(kCoarseThreads), 0, s, a);
                 else WQ_KLAUNCH(ps, (k_mg_coarse<E, float, false>), dim3(R), dim3(kCoarseThreads), 0, s, a);
             } else {
@@ -1943,21 +2212,15 @@ void mixed_iteration(wandqs_ctx* c, int R, bool helm, const Hier<double>& hz, in
 int reg_tile_min_default() { return WQ_REG_TILE_MIN; }
 int small_tile_max_default() { return WQ_SMALL_TILE_MAX; }
 
-void dst_tables(int n, double H, float* S, float* M) {
-    const double pi = 3.14159265358979323846;
-    for (int j = 0; j < n; ++j)
-        for (int k = 0; k < n; ++k) {
-            const bool in = j < n - 1 && k < n - 1;
-            S[j * n + k] = in ? (float)std::sin(pi * (j + 1) * (k + 1) / n) : 0.f;
-            double m = 0.0;
-            if (in) {
-                const double sj = std::sin(pi * (j + 1) / (2.0 * n));
-                const double sk = std::sin(pi * (k + 1) / (2.0 * n));
-                const double lambda = -(4.0 / (H * H)) * (sj * sj + sk * sk);
-                m = 1.0 / ((n / 2.0) * (n / 2.0) * lambda);
-            }
-            M[j * n + k] = (float)m;
-        }
+wandqs_status make_dst_tables(wandqs_ctx* c) {
+    const int n1 = kDstN;
+    hipLaunchKernelGGL(k_dst_tables, dim3((n1 * n1 + 255) / 256), dim3(256), 0, c->stream, n1,
+                       c->lev[c->lc].h, c->dst_S, c->dst_M, c->dst_S64, c->dst_M64);
+    if (dst128_used(c))
+        hipLaunchKernelGGL(k_dst_tables, dim3((kD2 * kD2 + 255) / 256), dim3(256), 0, c->stream, kD2,
+                           c->lev[c->lc - 1].h, c->dst2_S, c->dst2_M, c->dst2_S64, c->dst2_M64);
+    WQ_LAUNCH_CHECK();
+    return WANDQS_OK;
 }
 
 bool dst128_used(const wandqs_ctx* c) {

@@ -226,6 +226,13 @@ struct wandqs_ctx {
     float* dst2_S = nullptr;
     float* dst2_M = nullptr;
     float* dst2_X = nullptr;
+    // double copies of the tables and X for the mixed form, whose coarsest-grid
+    // solve runs in FP64 (null in the FP64 form)
+    double* dst_S64 = nullptr;
+    double* dst_M64 = nullptr;
+    double* dst2_S64 = nullptr;
+    double* dst2_M64 = nullptr;
+    double* dst2_X64 = nullptr;
     double* pa[2][4] = {};
     int32_t* pid[2] = {};
     int cur = 0;
@@ -281,9 +288,9 @@ size_t carve(wandqs_ctx* c, char* base);
 int reg_tile_min_default();
 // largest level with 16 x 16 LDS tiles by default
 int small_tile_max_default();
-// host tables of the exact coarse-level Poisson solve on an n^2 level (S and
-// M, [n][n] each; n = 64 or 128)
-void dst_tables(int n, double H, float* S, float* M);
+// tables of the exact coarse-level Poisson solves (the 64^2 level and, when
+// used, the 128^2 level), made on the device on the context's stream
+wandqs_status make_dst_tables(wandqs_ctx* c);
 // whether the Poisson V-cycles end with the exact solve on the 128^2 level
 bool dst128_used(const wandqs_ctx* c);
 
