@@ -57,6 +57,7 @@ typedef enum {
 typedef enum { WANDQS_FP64 = 0, WANDQS_MIXED = 1 } wandqs_precision;
 typedef enum { WANDQS_BEAM_GAUSS = 0, WANDQS_BEAM_RADIAL_BINS = 1 } wandqs_beam_kind;
 
+
 /* Frozen luminal driver (Sec. V.A).  It enters only through the longitudinal
  * current j_z of the B_perp source (a luminal beam has rho_b = J_bz, so it drops
  * out of the psi equation).  Density for xi >= 0, zero for xi < 0:
@@ -198,6 +199,31 @@ wandqs_status wandqs_set_state(wandqs_ctx* ctx, const double* d_particles,
  * the stored fields used as initial guesses. */
 wandqs_status wandqs_mg_solve(wandqs_ctx* ctx, int32_t nrhs, const double* d_k2,
                               const double* d_f, double* d_u, int32_t* h_cycles, double* h_rel);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * multigrid solve of wandqs_mg_solve without a context or workspace.  The level
+ * hierarchy and every other work array live in one static device array of the
+ * library (12 MiB, one copy per GPU, held until the process ends); on its
+ * success path the call allocates no device or host memory.
+ *   cfg       the grid (n_cells a power of two in [8, 256], half_width), n0,
+ *             precision, nu_pre / nu_post, mg_omega / mg_omega_helm, and
+ *             mg_max_cycles = the number of V-cycles (FP64) or outer
+ *             iterations (mixed) run; mg_rtol must be <= 0 (no tolerance mode:
+ *             it would need the host to read norms); beams, probes and the tape
+ *             are ignored
+ *   nrhs, d_k2, d_f, d_u  as in wandqs_mg_solve (device, dense [N+1][N+1]
+ *             per array; d_u holds the guess and receives the result)
+ *   hip_stream the hipStream_t the work is enqueued on (NULL: null stream),
+ *             on the current device; the call returns once it is enqueued
+ * The result equals wandqs_mg_solve's on a context made with the same cfg.
+ * Calls on one GPU share its static array: calls that overlap in time on one
+ * GPU (on different streams or from different threads) race and give wrong
+ * results; each call clears the array before use.  WANDQS_E_INVALID (no work
+ * enqueued) for a bad argument, a grid above 256 or mg_rtol > 0; WANDQS_E_HIP
+ * if a launch fails.  wandqs_last_error(NULL) gives the message. */
+wandqs_status wandqs_mg_solve_noalloc(const wandqs_config* cfg, int32_t nrhs, const double* d_k2,
+                                      const double* d_f, double* d_u, void* hip_stream);
 
 /* Diagnostic copy of the node arrays of the last slice (device [9][N+1][N+1]):
  * n*, jx, jy, Txx, Txy, Tyy, k2 = n* / (1+psi), f_Bx, f_By. */

@@ -424,7 +424,82 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
     return (off + 255) & ~(size_t)255;
 }
 
+// The arrays of a solve alone (wandqs_mg_solve_noalloc): the two level-0
+// iterates, the level hierarchy, the coarse-level k2 arrays, the sine-transform
+// tables and one residual-norm slot, in the layout carve() gives them inside a
+// context's workspace.
+size_t wq::carve_solver(wandqs_ctx* c, char* base) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        off = (off + 255) & ~(size_t)255;
+        char* p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    auto arr = [&](int l) {
+        return (double*)take(sizeof(double) * (size_t)(c->lev[l].N + 1) * c->lev[l].pitch);
+    };
+    Level& L0 = c->lev[0];
+    for (int k = 0; k < 2; ++k) c->fields[k] = arr(0);
+    for (int r = 0; r < 2; ++r) {
+        L0.um[r] = arr(0);
+        L0.f[r] = arr(0);
+    }
+    L0.k2 = arr(0);
+    {
+        int tot = 0;
+        for (int n = c->lev[c->lc].N; n >= 2; n /= 2) tot += (n + 1) * (n + 1);
+        c->k2lev = (double*)take(sizeof(double) * (size_t)tot);
+        c->k2levf = (float*)take(sizeof(float) * (size_t)tot);
+        c->idlevf = (float*)take(sizeof(float) * (size_t)tot);
+    }
+    carve_dst(c, take);
+    for (int l = 1; l <= c->lc; ++l) {
+        Level& L = c->lev[l];
+        for (int r = 0; r < 2; ++r) {
+            L.u[r] = arr(l);
+            L.um[r] = l < c->lc ? arr(l) : nullptr;
+            L.f[r] = arr(l);
+        }
+        L.k2 = arr(l);
+    }
+    if (c->cfg.precision == WANDQS_MIXED) {
+        auto arr32 = [&](int l) {
+            return (float*)take(sizeof(float) * (size_t)(c->lev[l].N + 1) * c->lev[l].pitch);
+        };
+        for (int l = 0; l <= c->lc; ++l)
+            for (int r = 0; r < 2; ++r) {
+                Level& L = c->lev[l];
+                L.u32[r] = arr32(l);
+                L.um32[r] = l < c->lc ? arr32(l) : nullptr;
+                L.f32[r] = arr32(l);
+            }
+    }
+    c->norm_part = (double*)take(sizeof(double) * kNormVec * (size_t)c->max_tiles);
+    c->norm_red = (double*)take(sizeof(double) * kNormVec);
+    return (off + 255) & ~(size_t)255;
+}
+
+// A context for solves on cfg's grid only: its sizes and settings, no beams,
+// probes, tape or HIP graphs.  Returns the reason when cfg is not valid.
+const char* wq::setup_solver_ctx(wandqs_ctx* c, const wandqs_config* cfg) {
+    if (!cfg) return "config is NULL";
+    c->cfg = *cfg;
+    c->cfg.n_beams = 0;
+    c->cfg.beams = nullptr;
+    c->cfg.n_probes = 0;
+    c->cfg.probes = nullptr;
+    c->cfg.checkpoint_every = 0;
+    if (const char* e = check_config(&c->cfg, 1)) return e;
+    apply_defaults(c);
+    set_sizes(c, &c->cfg, 1);
+    c->graphs_on = false;
+    return nullptr;
+}
+
 const char* wq::hip_err(hipError_t e) { return hipGetErrorString(e); }
+
+void wq::set_call_error(const char* m) { set_init_err(m); }
 
 // (this file is compiled without floating-point contraction)
 bool wq::node_in_disc_host(double L, double h, int a, int b, double x0, double y0, double r) {

@@ -284,6 +284,12 @@ namespace wq {
 
 // layout of the workspace (offsets from the base, computed for any base)
 size_t carve(wandqs_ctx* c, char* base);
+// layout of the arrays of a solve alone (the same rules; base may be NULL)
+size_t carve_solver(wandqs_ctx* c, char* base);
+// a context for solves only on cfg's grid; returns NULL or the reason cfg is invalid
+const char* setup_solver_ctx(wandqs_ctx* c, const wandqs_config* cfg);
+// message for wandqs_last_error(NULL) (copied into a fixed buffer)
+void set_call_error(const char* m);
 // smallest level that runs the register-tile pass kernels by default
 int reg_tile_min_default();
 // largest level with 16 x 16 LDS tiles by default

@@ -27,7 +27,8 @@ _dp = C.POINTER(C.c_double)
 EXPORTS = ("wandqs_workspace_bytes", "wandqs_init", "wandqs_slice_step", "wandqs_run",
            "wandqs_get_state", "wandqs_set_state", "wandqs_mg_solve", "wandqs_get_moments",
            "wandqs_num_particles", "wandqs_destroy", "wandqs_last_error", "wandqs_profile",
-           "wandqs_profile_stats", "wandqs_backward", "wandqs_num_theta", "wandqs_tape_slices")
+           "wandqs_profile_stats", "wandqs_backward", "wandqs_num_theta", "wandqs_tape_slices",
+           "wandqs_mg_solve_noalloc")
 
 
 class Beam(C.Structure):
@@ -89,6 +90,7 @@ def load():
     L.wandqs_set_state.argtypes = [vp, vp, vp, _dp]
     L.wandqs_mg_solve.argtypes = [vp, i32, vp, vp, vp, C.POINTER(i32), _dp]
     L.wandqs_get_moments.argtypes = [vp, vp]
+    L.wandqs_mg_solve_noalloc.argtypes = [C.POINTER(Config), i32, vp, vp, vp, vp]
     L.wandqs_num_particles.argtypes = [vp]
     L.wandqs_num_particles.restype = C.c_int64
     L.wandqs_profile.argtypes = [vp, i32]
@@ -105,7 +107,7 @@ def load():
     for name in ("wandqs_workspace_bytes", "wandqs_init", "wandqs_slice_step", "wandqs_run",
                  "wandqs_get_state", "wandqs_set_state", "wandqs_mg_solve",
                  "wandqs_get_moments", "wandqs_profile", "wandqs_profile_stats",
-                 "wandqs_backward"):
+                 "wandqs_backward", "wandqs_mg_solve_noalloc"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -195,6 +197,32 @@ def workspace_bytes(cfg: dict, n_slices: int = 1) -> int:
     if st != OK:
         raise WandQSError(st, L.wandqs_last_error(None).decode())
     return n.value
+
+
+def mg_solve_noalloc(cfg: dict, f, u0=None, k2=None, stream=None):
+    """wandqs_mg_solve_noalloc on cfg's grid: exactly cfg["mg_max_cycles"]
+    V-cycles (cfg["mg_rtol"] must be <= 0) on 1 or 2 right-hand sides, with the
+    library's static scratch array.  f, u0, k2: [nrhs][N+1][N+1] / [N+1][N+1]
+    float64 (device tensors are used in place).  Returns (status, u); the work
+    is enqueued on `stream` (default: torch's current stream)."""
+    import torch
+    L = load()
+    c, keep = make_config(cfg)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    f = torch.as_tensor(f, dtype=torch.float64).to(dev).contiguous()
+    if f.dim() == 2:
+        f = f.unsqueeze(0)
+    u = (torch.zeros_like(f) if u0 is None else
+         torch.as_tensor(u0, dtype=torch.float64).to(dev).reshape(f.shape).contiguous().clone())
+    kk = None if k2 is None else torch.as_tensor(k2, dtype=torch.float64).to(dev).contiguous()
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    st = L.wandqs_mg_solve_noalloc(C.byref(c), int(f.shape[0]),
+                                   C.c_void_p(kk.data_ptr()) if kk is not None else None,
+                                   C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()),
+                                   C.c_void_p(s.cuda_stream))
+    if st != OK:
+        raise WandQSError(st, L.wandqs_last_error(None).decode())
+    return st, u
 
 
 class Simulation:
