@@ -279,6 +279,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=512,
                     help="slices of the taped forward + reverse sweep (0: skip)")
     ap.add_argument("--checkpoint-every", type=int, default=32)
+    ap.add_argument("--pusher-steps", type=int, default=128,
+                    help="slices timed from the window with each Runge-Kutta pusher (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times (the "
                          "reference for scaling hardware byte counters)")
@@ -406,6 +408,27 @@ def main():
         forms = forms_timing(cfg, win, args.forms_steps,
                              args.forms_rtol if args.forms_rtol is not None else wi.FORMS_RTOL)
 
+    pushers = None
+    if args.pusher_steps > 0:
+        # the same window with each Runge-Kutta pusher (the Boris-like one is
+        # the headline's)
+        pushers = {}
+        for pu in ("rk1", "rk2", "rk4"):
+            print(f"[bench] pusher {pu}: {args.pusher_steps} slices", file=sys.stderr, flush=True)
+            sim = Simulation(wi.scaled(cfg, pusher=pu), n_slices=args.pusher_steps)
+            _start(sim, win)
+            torch.cuda.synchronize()
+            tq = time.perf_counter()
+            sim.run(args.pusher_steps)
+            torch.cuda.synchronize()
+            tq = time.perf_counter() - tq
+            sim.close()
+            del sim
+            pushers[pu] = {"value": P * args.pusher_steps / tq,
+                           "ms_per_step": 1e3 * tq / args.pusher_steps}
+        pushers["steps"] = args.pusher_steps
+        print(f"[bench] pushers: {pushers}", file=sys.stderr, flush=True)
+
     adjoint = None
     if args.adjoint_steps > 0:
         adjoint = adjoint_timing(cfg, win, args.adjoint_steps, args.checkpoint_every)
@@ -429,7 +452,7 @@ def main():
                        "lead_in_slices": lead, "xi_start": win["xi"], "xi_end": final["xi"],
                        "mean_vcycles": [round(c, 3) for c in cyc]},
             "roofline": roof, "vcycle_hbm": vcycle, "cpu_baseline": cpu, "forms": forms,
-            "adjoint": adjoint}
+            "adjoint": adjoint, "pushers": pushers}
     print(json.dumps(line), flush=True)
 
 

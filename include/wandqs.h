@@ -57,6 +57,22 @@ typedef enum {
 typedef enum { WANDQS_FP64 = 0, WANDQS_MIXED = 1 } wandqs_precision;
 typedef enum { WANDQS_BEAM_GAUSS = 0, WANDQS_BEAM_RADIAL_BINS = 1 } wandqs_beam_kind;
 
+/* Plasma pushers (Sec. VII.A: a Boris-like pusher, with first-, second- and
+ * fourth-order Runge-Kutta as alternatives).  All advance (r_perp, p_perp) over
+ * dxi with the fields frozen at the slice (eqs. (6)-(7)).  BORIS: half kick by
+ * gamma grad psi/g + e_z x B_perp with gamma from the old momentum, rotation for
+ * (e_z x V) B_z through angle 2 atan(B_z dxi / 2g), half kick, drift with the new
+ * momentum and g at the start.  RK1 / RK2 / RK4: forward Euler, the midpoint
+ * rule and the classical four-stage scheme on dr/dxi = p/g, dp/dxi = the force
+ * above, each stage gathering psi (hence g), grad psi and B at its own
+ * position.  Every pusher reflects the end position at the walls x, y = +-L.
+ * The adjoint (wandqs_backward) is that of BORIS only. */
+typedef enum {
+    WANDQS_PUSH_BORIS = 0,
+    WANDQS_PUSH_RK1 = 1,
+    WANDQS_PUSH_RK2 = 2,
+    WANDQS_PUSH_RK4 = 4
+} wandqs_pusher;
 
 /* Frozen luminal driver (Sec. V.A).  It enters only through the longitudinal
  * current j_z of the B_perp source (a luminal beam has rho_b = J_bz, so it drops
@@ -134,6 +150,7 @@ typedef struct {
                                  (WANDQS_E_INVALID), since the step then depends on
                                  the state through Vmax.  Ignored without adaptive
                                  steps or without a tape. */
+    int32_t pusher;           /* a wandqs_pusher value, 0 = Boris-like; a tape needs BORIS */
 } wandqs_config;
 
 typedef struct {

@@ -28,6 +28,8 @@ MOMENTS = ("n", "jx", "jy", "Txx", "Txy", "Tyy")
 EXTRA = ("k2", "fBx", "fBy", "jz")
 
 OK, INVALID, NOCONV, NONPHYS = 0, -1, -4, -5
+#: plasma pushers: the Boris-like scheme and Runge-Kutta of order 1, 2, 4
+PUSHERS = {"boris": 0, "rk1": 1, "rk2": 2, "rk4": 4}
 
 _dp = C.POINTER(C.c_double)
 
@@ -44,7 +46,7 @@ class Cfg(C.Structure):
                 ("n0", C.c_double), ("dxi0", C.c_double), ("adaptive", C.c_int),
                 ("refine_k", C.c_int), ("mg_rtol", C.c_double), ("mg_atol", C.c_double),
                 ("mg_max_cycles", C.c_int), ("nu_pre", C.c_int), ("nu_post", C.c_int),
-                ("n_beams", C.c_int), ("beams", C.POINTER(Beam))]
+                ("n_beams", C.c_int), ("beams", C.POINTER(Beam)), ("pusher", C.c_int)]
 
 
 class Info(C.Structure):
@@ -105,6 +107,7 @@ class Oracle:
         c.mg_rtol, c.mg_atol = cfg["mg_rtol"], cfg["mg_atol"]
         c.mg_max_cycles, c.nu_pre, c.nu_post = cfg["mg_max_cycles"], cfg["nu_pre"], cfg["nu_post"]
         c.n_beams, c.beams = len(cfg["beams"]), beams
+        c.pusher = PUSHERS[cfg.get("pusher", "boris")]
         self.c = c
 
     # ---------------------------------------------------------------- pieces
@@ -132,6 +135,16 @@ class Oracle:
         st = lib().oracle_assemble(C.byref(self.c), C.c_double(xi), _p(mom), _p(_f64(psi)),
                                    _p(_f64(Ez)), _p(_f64(Bz)), _p(out))
         return st, out.reshape(4, self.N + 1, self.N + 1)
+
+    def push_fields(self, dxi, x, y, px, py, fields):
+        """The particle advance of a slice from its solved fields (the
+        configuration's pusher); returns (status, x, y, px, py, vmax)."""
+        arrs = [_f64(a).copy() for a in (x, y, px, py)]
+        F = _f64(fields).reshape(5, -1)
+        vm = C.c_double(0.0)
+        st = lib().oracle_push_fields(C.byref(self.c), C.c_double(dxi), arrs[0].size, _p(F),
+                                      *[_p(a) for a in arrs], C.byref(vm))
+        return (st, *arrs, vm.value)
 
     def next_dxi(self, vmax):
         return lib().oracle_next_dxi(C.byref(self.c), C.c_double(vmax))

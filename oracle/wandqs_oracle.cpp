@@ -73,6 +73,7 @@ typedef struct {
     int mg_max_cycles, nu_pre, nu_post;
     int n_beams;
     const oracle_beam* beams;
+    int pusher;           /* 0: Boris-like; 1, 2, 4: Runge-Kutta of that order */
 } oracle_cfg;
 
 typedef struct {
@@ -84,6 +85,7 @@ typedef struct {
 } oracle_info;
 
 enum { ORC_OK = 0, ORC_INVALID = -1, ORC_NOCONV = -4, ORC_NONPHYS = -5 };
+enum { PUSH_BORIS = 0, PUSH_RK1 = 1, PUSH_RK2 = 2, PUSH_RK4 = 4 };
 
 } /* extern "C" */
 
@@ -591,6 +593,72 @@ void push_one(double L, double dxi, const T& g_i, const T& gx, const T& gy, cons
     if (val(y) < -L) { y = -2.0 * L - y; py = -py; }
 }
 
+/* Right-hand side of the plasma electron's equations of motion in xi with the
+ * fields frozen at the slice (Sec. III.A eqs. (6)-(7), A-hat = 0), at the
+ * position and momentum s = (x, y, p_x, p_y):
+ *   dr/dxi = V = p/g,
+ *   dp/dxi = gamma grad psi/g + (e_z x V) B_z + e_z x B_perp,
+ *   g = 1 + psi and gamma = (1 + p^2 + g^2)/(2g),
+ * every field gathered (CIC) at the position itself.  Returns false when
+ * g <= 0 there. */
+template <class T>
+bool eom_rhs(const Grid& g, const T* psi, const T* gx, const T* gy, const T* Bx, const T* By,
+             const T* Bz, const T (&s)[4], T (&d)[4]) {
+    const T gg = 1.0 + gather1(g, psi, s[0], s[1]);
+    if (!(val(gg) > 0.0)) return false;
+    const T Gx = gather1(g, gx, s[0], s[1]), Gy = gather1(g, gy, s[0], s[1]);
+    const T bx = gather1(g, Bx, s[0], s[1]), by = gather1(g, By, s[0], s[1]);
+    const T bz = gather1(g, Bz, s[0], s[1]);
+    const T gamma = (1.0 + s[2] * s[2] + s[3] * s[3] + gg * gg) / (2.0 * gg);
+    const T vx = s[2] / gg, vy = s[3] / gg;
+    d[0] = vx;
+    d[1] = vy;
+    d[2] = gamma * Gx / gg - vy * bz - by;
+    d[3] = gamma * Gy / gg + vx * bz + bx;
+    return true;
+}
+
+/* Runge-Kutta advance over dxi of the same equations (the alternative pushers
+ * the paper lists beside the Boris-like one, Sec. VII.A): order 1 (forward
+ * Euler), 2 (the midpoint rule) or 4 (the classical four-stage scheme).
+ * Every stage gathers the frozen fields at its own position (a stage position
+ * outside the box uses its edge cell's bilinear form); the walls reflect the
+ * end position as in push_one.  Returns false when a stage meets g <= 0. */
+template <class T>
+bool push_rk(const Grid& g, int order, double dxi, const T* psi, const T* gx, const T* gy,
+             const T* Bx, const T* By, const T* Bz, T& x, T& y, T& px, T& py) {
+    const T s0[4] = {x, y, px, py};
+    T k1[4], k2[4], k3[4], k4[4], s[4];
+    bool ok = eom_rhs(g, psi, gx, gy, Bx, By, Bz, s0, k1);
+    T out[4];
+    if (order == PUSH_RK1) {
+        for (int q = 0; q < 4; ++q) out[q] = s0[q] + dxi * k1[q];
+    } else if (order == PUSH_RK2) {
+        for (int q = 0; q < 4; ++q) s[q] = s0[q] + (0.5 * dxi) * k1[q];
+        ok = eom_rhs(g, psi, gx, gy, Bx, By, Bz, s, k2) && ok;
+        for (int q = 0; q < 4; ++q) out[q] = s0[q] + dxi * k2[q];
+    } else {
+        for (int q = 0; q < 4; ++q) s[q] = s0[q] + (0.5 * dxi) * k1[q];
+        ok = eom_rhs(g, psi, gx, gy, Bx, By, Bz, s, k2) && ok;
+        for (int q = 0; q < 4; ++q) s[q] = s0[q] + (0.5 * dxi) * k2[q];
+        ok = eom_rhs(g, psi, gx, gy, Bx, By, Bz, s, k3) && ok;
+        for (int q = 0; q < 4; ++q) s[q] = s0[q] + dxi * k3[q];
+        ok = eom_rhs(g, psi, gx, gy, Bx, By, Bz, s, k4) && ok;
+        for (int q = 0; q < 4; ++q)
+            out[q] = s0[q] + (dxi / 6.0) * (k1[q] + 2.0 * k2[q] + 2.0 * k3[q] + k4[q]);
+    }
+    x = out[0];
+    y = out[1];
+    px = out[2];
+    py = out[3];
+    const double L = g.L;
+    if (val(x) > L) { x = 2.0 * L - x; px = -px; }
+    if (val(x) < -L) { x = -2.0 * L - x; px = -px; }
+    if (val(y) > L) { y = 2.0 * L - y; py = -py; }
+    if (val(y) < -L) { y = -2.0 * L - y; py = -py; }
+    return ok;
+}
+
 /* Step_Size_Refinement (Algorithm 1): the step is the largest that keeps the
  * fastest particle within one cell, h / Vmax, but never above the initial
  * step dxi0 (the paper's V0 = h / dxi0 marks where the refinement starts) and,
@@ -709,23 +777,36 @@ int slice_step_t(const oracle_cfg* c, int P, T* x, T* y, T* px, T* py, T* pz, T*
     std::vector<T> gx, gy;
     psi_gradient<T>(g, psi, gx, gy);
     double vmax = 0.0;
-#pragma omp parallel for schedule(static) reduction(max : vmax)
-    for (int i = 0; i < P; ++i) {
-        T Gx = gather1(g, gx.data(), x[i], y[i]);
-        T Gy = gather1(g, gy.data(), x[i], y[i]);
-        T bx = gather1(g, Bx, x[i], y[i]);
-        T by = gather1(g, By, x[i], y[i]);
-        T bz = gather1(g, Bz, x[i], y[i]);
-        T ez = pz ? gather1(g, Ez, x[i], y[i]) : T(0.0);
-        T p0x = px[i], p0y = py[i];
-        push_one(g.L, *dxi, gi[i], Gx, Gy, bx, by, bz, x[i], y[i], px[i], py[i]);
-        if (pz) { /* dp_z/dxi = -gamma Ez/g - Vx By + Vy Bx at the mean momentum */
-            T mx = 0.5 * (p0x + px[i]), my = 0.5 * (p0y + py[i]);
-            T gam = (1.0 + mx * mx + my * my + gi[i] * gi[i]) / (2.0 * gi[i]);
-            pz[i] += *dxi * (-gam * ez / gi[i] - (mx / gi[i]) * by + (my / gi[i]) * bx);
+    if (c->pusher != PUSH_BORIS) {
+        int rk_nonphys = 0;
+#pragma omp parallel for schedule(static) reduction(max : vmax) reduction(| : rk_nonphys)
+        for (int i = 0; i < P; ++i) {
+            if (!push_rk(g, c->pusher, *dxi, psi, gx.data(), gy.data(), Bx, By, Bz, x[i], y[i],
+                         px[i], py[i]))
+                rk_nonphys = 1;
+            double v = val(sqrt(px[i] * px[i] + py[i] * py[i]) / gi[i]);
+            if (v > vmax) vmax = v;
         }
-        double v = val(sqrt(px[i] * px[i] + py[i] * py[i]) / gi[i]);
-        if (v > vmax) vmax = v;
+        if (rk_nonphys) status = ORC_NONPHYS;
+    } else {
+#pragma omp parallel for schedule(static) reduction(max : vmax)
+        for (int i = 0; i < P; ++i) {
+            T Gx = gather1(g, gx.data(), x[i], y[i]);
+            T Gy = gather1(g, gy.data(), x[i], y[i]);
+            T bx = gather1(g, Bx, x[i], y[i]);
+            T by = gather1(g, By, x[i], y[i]);
+            T bz = gather1(g, Bz, x[i], y[i]);
+            T ez = pz ? gather1(g, Ez, x[i], y[i]) : T(0.0);
+            T p0x = px[i], p0y = py[i];
+            push_one(g.L, *dxi, gi[i], Gx, Gy, bx, by, bz, x[i], y[i], px[i], py[i]);
+            if (pz) { /* dp_z/dxi = -gamma Ez/g - Vx By + Vy Bx at the mean momentum */
+                T mx = 0.5 * (p0x + px[i]), my = 0.5 * (p0y + py[i]);
+                T gam = (1.0 + mx * mx + my * my + gi[i] * gi[i]) / (2.0 * gi[i]);
+                pz[i] += *dxi * (-gam * ez / gi[i] - (mx / gi[i]) * by + (my / gi[i]) * bx);
+            }
+            double v = val(sqrt(px[i] * px[i] + py[i] * py[i]) / gi[i]);
+            if (v > vmax) vmax = v;
+        }
     }
 
     /* 9. Step_Size_Refinement for the next slice. */
@@ -809,6 +890,37 @@ int oracle_push(double L, double dxi, int P, const double* g_i, const double* gx
     return ORC_OK;
 }
 
+/* The particle advance of a slice given its solved fields [5][nn] (psi, Ez,
+ * Bz, Bx, By): node gradient of psi, g_i = 1 + psi(r_i), then the pusher of
+ * the configuration (Boris-like or Runge-Kutta), walls included.  vmax (may be
+ * NULL) receives max |p_new|/g_i. */
+int oracle_push_fields(const oracle_cfg* c, double dxi, int P, const double* fields, double* x,
+                       double* y, double* px, double* py, double* vmax) {
+    Grid g(c->n_cells, c->half_width);
+    const int nn = g.nn();
+    const double *psi = fields, *Bz = fields + 2 * nn, *Bx = fields + 3 * nn, *By = fields + 4 * nn;
+    std::vector<double> gx, gy;
+    psi_gradient(g, psi, gx, gy);
+    double vm = 0.0;
+    int nonphys = 0;
+#pragma omp parallel for schedule(static) reduction(max : vm) reduction(| : nonphys)
+    for (int i = 0; i < P; ++i) {
+        const double gi = 1.0 + gather1(g, psi, x[i], y[i]);
+        if (!(gi > 0.0)) nonphys = 1;
+        if (c->pusher == PUSH_BORIS) {
+            push_one(g.L, dxi, gi, gather1(g, gx.data(), x[i], y[i]), gather1(g, gy.data(), x[i], y[i]),
+                     gather1(g, Bx, x[i], y[i]), gather1(g, By, x[i], y[i]), gather1(g, Bz, x[i], y[i]),
+                     x[i], y[i], px[i], py[i]);
+        } else if (!push_rk(g, c->pusher, dxi, psi, gx.data(), gy.data(), Bx, By, Bz, x[i], y[i],
+                            px[i], py[i])) {
+            nonphys = 1;
+        }
+        vm = std::max(vm, std::sqrt(px[i] * px[i] + py[i] * py[i]) / gi);
+    }
+    if (vmax) *vmax = vm;
+    return nonphys ? ORC_NONPHYS : ORC_OK;
+}
+
 double oracle_next_dxi(const oracle_cfg* c, double vmax) {
     return next_dxi(*c, 2.0 * c->half_width / c->n_cells, vmax);
 }
@@ -838,6 +950,9 @@ int oracle_assemble(const oracle_cfg* c, double xi, const double* mom, const dou
 int oracle_slice_step(const oracle_cfg* c, int P, double* x, double* y, double* px, double* py,
                       double* pz, double* fields, double* xi, double* dxi, oracle_info* info,
                       double* moments_out, double* extra_out) {
+    if (!(c->pusher == PUSH_BORIS || c->pusher == PUSH_RK1 || c->pusher == PUSH_RK2 ||
+          c->pusher == PUSH_RK4) || (pz && c->pusher != PUSH_BORIS))
+        return ORC_INVALID;
     return slice_step_t<double>(c, P, x, y, px, py, pz, fields, xi, dxi, info, moments_out,
                                 extra_out, nullptr);
 }
@@ -861,6 +976,7 @@ int oracle_run_tangent(const oracle_cfg* c, int P, double* x, double* y, double*
     constexpr int KD = 8;
     using D = Dual<KD>;
     if (K < 1 || K > KD || P < 0) return ORC_INVALID;
+    if (c->pusher != PUSH_BORIS) return ORC_INVALID;
     Grid g(c->n_cells, c->half_width);
     const int nn = g.nn();
     int nth = 0;
@@ -1075,6 +1191,7 @@ int oracle_slice_adjoint(const oracle_cfg* c, int P, const double* x, const doub
                          const double* px, const double* py, const double* fields, double xi,
                          double dxi, double* xb, double* yb, double* pxb, double* pyb,
                          const double* Fbar, double* theta_bar) {
+    if (c->pusher != PUSH_BORIS) return ORC_INVALID;  /* the reverse sweep is the Boris-like push's */
     Grid g(c->n_cells, c->half_width);
     const int nn = g.nn();
     const double* psi = fields;

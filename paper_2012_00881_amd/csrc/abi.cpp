@@ -72,6 +72,11 @@ const char* check_config(const wandqs_config* c, int32_t n_slices) {
     }
     if (c->checkpoint_every < 0) return "checkpoint_every must be >= 0";
     if (c->adjoint_hold_dxi != 0 && c->adjoint_hold_dxi != 1) return "adjoint_hold_dxi must be 0 or 1";
+    if (c->pusher != WANDQS_PUSH_BORIS && c->pusher != WANDQS_PUSH_RK1 &&
+        c->pusher != WANDQS_PUSH_RK2 && c->pusher != WANDQS_PUSH_RK4)
+        return "pusher must be WANDQS_PUSH_BORIS, _RK1, _RK2 or _RK4";
+    if (c->checkpoint_every > 0 && c->pusher != WANDQS_PUSH_BORIS)
+        return "the adjoint tape needs the Boris-like pusher (the reverse sweep is its adjoint)";
     if (c->checkpoint_every > 0 && c->adaptive && !c->adjoint_hold_dxi)
         return "a tape with adaptive steps differentiates with the forward's steps held fixed "
                "(they depend on the state through Vmax): set adjoint_hold_dxi = 1 to accept that";

@@ -517,6 +517,112 @@ __global__ __launch_bounds__(kPushThreads) void k_push(
     }
 }
 
+// Frozen slice fields for the Runge-Kutta pushers: psi, its node gradient,
+// B_perp and B_z, gathered (CIC) at any position.
+struct PushFields {
+    int N, pitch;
+    double L, h;
+    const double *psi, *gx, *gy, *Bx, *By, *Bz;
+};
+
+// Right-hand side of the equations of motion at s = (x, y, p_x, p_y) (Sec.
+// III.A eqs. (6)-(7)): dr/dxi = p/g, dp/dxi = gamma grad psi/g + (e_z x V) B_z
+// + e_z x B_perp with g = 1 + psi and gamma = (1 + p^2 + g^2)/(2g), every field
+// gathered at s.  Returns g.
+__device__ __forceinline__ double eom_rhs(const PushFields& F, const double (&s)[4],
+                                          double (&d)[4]) {
+    int a, b;
+    double dx, dy;
+    cic(s[0], F.L, F.h, F.N, a, dx);
+    cic(s[1], F.L, F.h, F.N, b, dy);
+    const size_t g = (size_t)b * F.pitch + a;
+    const double2 p0 = ld_pair(F.psi + g), p1 = ld_pair(F.psi + g + F.pitch);
+    const double2 x0 = ld_pair(F.gx + g), x1 = ld_pair(F.gx + g + F.pitch);
+    const double2 y0 = ld_pair(F.gy + g), y1 = ld_pair(F.gy + g + F.pitch);
+    const double2 bx0 = ld_pair(F.Bx + g), bx1 = ld_pair(F.Bx + g + F.pitch);
+    const double2 by0 = ld_pair(F.By + g), by1 = ld_pair(F.By + g + F.pitch);
+    const double2 bz0 = ld_pair(F.Bz + g), bz1 = ld_pair(F.Bz + g + F.pitch);
+    const double gg = 1.0 + cic_gather(p0.x, p0.y, p1.x, p1.y, dx, dy);
+    const double Gx = cic_gather(x0.x, x0.y, x1.x, x1.y, dx, dy);
+    const double Gy = cic_gather(y0.x, y0.y, y1.x, y1.y, dx, dy);
+    const double bx = cic_gather(bx0.x, bx0.y, bx1.x, bx1.y, dx, dy);
+    const double by = cic_gather(by0.x, by0.y, by1.x, by1.y, dx, dy);
+    const double bz = cic_gather(bz0.x, bz0.y, bz1.x, bz1.y, dx, dy);
+    const double ig = 1.0 / gg;
+    const double gamma = (1.0 + s[2] * s[2] + s[3] * s[3] + gg * gg) * (0.5 * ig);
+    const double vx = s[2] * ig, vy = s[3] * ig;
+    d[0] = vx;
+    d[1] = vy;
+    d[2] = gamma * Gx * ig - vy * bz - by;
+    d[3] = gamma * Gy * ig + vx * bz + bx;
+    return gg;
+}
+
+// Runge-Kutta push over dxi with the fields frozen at this slice, the
+// alternative to the Boris-like push (Sec. VII.A): ORDER 1 (forward Euler), 2
+// (midpoint rule) or 4 (classical four stages); each stage gathers at its own
+// position.  Walls, V_max (with g at the start position) and the block maxima
+// as in k_push; a stage with g <= 0 raises flags bit 0.
+template <int ORDER>
+__global__ __launch_bounds__(kPushThreads) void k_push_rk(int64_t P, PushFields F,
+                                                          const double* __restrict__ st,
+                                                          double* __restrict__ x, double* __restrict__ y,
+                                                          double* __restrict__ px, double* __restrict__ py,
+                                                          double* __restrict__ vmax_part,
+                                                          int32_t* __restrict__ flags) {
+    __shared__ double red[kPushThreads / 64];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v = 0.0;
+    if (i < P) {
+        const double dxi = st[1], L = F.L;
+        const double s0[4] = {x[i], y[i], px[i], py[i]};
+        double k1[4], k2[4], k3[4], k4[4], s[4], o[4];
+        const double g_i = eom_rhs(F, s0, k1);
+        bool bad = !(g_i > 0.0);
+        if (ORDER == 1) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) o[q] = s0[q] + dxi * k1[q];
+        } else if (ORDER == 2) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s[q] = s0[q] + (0.5 * dxi) * k1[q];
+            bad = !(eom_rhs(F, s, k2) > 0.0) || bad;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) o[q] = s0[q] + dxi * k2[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s[q] = s0[q] + (0.5 * dxi) * k1[q];
+            bad = !(eom_rhs(F, s, k2) > 0.0) || bad;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s[q] = s0[q] + (0.5 * dxi) * k2[q];
+            bad = !(eom_rhs(F, s, k3) > 0.0) || bad;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s[q] = s0[q] + dxi * k3[q];
+            bad = !(eom_rhs(F, s, k4) > 0.0) || bad;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                o[q] = s0[q] + (dxi / 6.0) * (k1[q] + 2.0 * k2[q] + 2.0 * k3[q] + k4[q]);
+        }
+        if (o[0] > L) { o[0] = 2.0 * L - o[0]; o[2] = -o[2]; }
+        if (o[0] < -L) { o[0] = -2.0 * L - o[0]; o[2] = -o[2]; }
+        if (o[1] > L) { o[1] = 2.0 * L - o[1]; o[3] = -o[3]; }
+        if (o[1] < -L) { o[1] = -2.0 * L - o[1]; o[3] = -o[3]; }
+        x[i] = o[0];
+        y[i] = o[1];
+        px[i] = o[2];
+        py[i] = o[3];
+        v = sqrt(o[2] * o[2] + o[3] * o[3]) / g_i;
+        if (bad) atomicOr(flags, 1);
+    }
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < kPushThreads / 64; ++w) m = fmax(m, red[w]);
+        vmax_part[blockIdx.x] = m;
+    }
+}
+
 // Step_Size_Refinement (Algorithm 1) with the floor dxi0/k (Sec. V.A); writes
 // the slice record (xi, dxi, vmax, flags) and advances xi.  One block; each
 // thread issues its loads of the push-block maxima in batches of kDxiBatch so
@@ -679,12 +785,32 @@ wandqs_status push_and_step(wandqs_ctx* c, int rec_slot) {
         WQ_KLAUNCH(pg, k_grad_psi, dim3((c->N + 1 + 127) / 128, c->N + 1), dim3(128), 0, c->stream,
                            c->N, c->h, c->lev[0].pitch, c->fields[0], c->gpsi[0], c->gpsi[1]);
     }
-    {
+    const int pusher = c->cfg.pusher;
+    if (pusher == WANDQS_PUSH_BORIS) {
         ProfScope ps(c, "k_push", (double)c->P * 64.0 + (double)(c->N + 1) * (c->N + 1) * 48.0);
         WQ_KLAUNCH(ps, k_push, dim3(c->n_push_blocks), dim3(kPushThreads), 0, c->stream, c->P,
                            c->N, c->L, c->h, c->lev[0].pitch, c->st, c->fields[0], c->gpsi[0],
                            c->gpsi[1], c->fields[3], c->fields[4], c->fields[2], c->pa[k][0],
                            c->pa[k][1], c->pa[k][2], c->pa[k][3], c->vmax_part);
+    } else {
+        const PushFields F{c->N, c->lev[0].pitch, c->L, c->h, c->fields[0], c->gpsi[0], c->gpsi[1],
+                           c->fields[3], c->fields[4], c->fields[2]};
+        // per particle: its state read and written; per node (read once): six fields
+        const double bytes = (double)c->P * 64.0 + (double)(c->N + 1) * (c->N + 1) * 48.0;
+        const dim3 g(c->n_push_blocks), b(kPushThreads);
+        if (pusher == WANDQS_PUSH_RK1) {
+            ProfScope ps(c, "k_push_rk<1>", bytes);
+            WQ_KLAUNCH(ps, k_push_rk<1>, g, b, 0, c->stream, c->P, F, c->st, c->pa[k][0], c->pa[k][1],
+                       c->pa[k][2], c->pa[k][3], c->vmax_part, c->flags);
+        } else if (pusher == WANDQS_PUSH_RK2) {
+            ProfScope ps(c, "k_push_rk<2>", bytes);
+            WQ_KLAUNCH(ps, k_push_rk<2>, g, b, 0, c->stream, c->P, F, c->st, c->pa[k][0], c->pa[k][1],
+                       c->pa[k][2], c->pa[k][3], c->vmax_part, c->flags);
+        } else {
+            ProfScope ps(c, "k_push_rk<4>", bytes);
+            WQ_KLAUNCH(ps, k_push_rk<4>, g, b, 0, c->stream, c->P, F, c->st, c->pa[k][0], c->pa[k][1],
+                       c->pa[k][2], c->pa[k][3], c->vmax_part, c->flags);
+        }
     }
     double* rec = rec_slot >= 0 ? c->rec + 4 * (size_t)rec_slot : nullptr;
     {

@@ -19,6 +19,8 @@ OK, E_INVALID, E_NOMEM, E_HIP, E_NOCONV, E_NONPHYS, E_STATE = 0, -1, -2, -3, -4,
 STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_HIP", -4: "E_NOCONV",
                 -5: "E_NONPHYS", -6: "E_STATE"}
 FP64, MIXED = 0, 1
+#: plasma pushers of wandqs_config.pusher
+PUSHERS = {"boris": 0, "rk1": 1, "rk2": 2, "rk4": 4}
 BEAM_GAUSS, BEAM_RADIAL_BINS = 0, 1
 
 _dp = C.POINTER(C.c_double)
@@ -52,7 +54,8 @@ class Config(C.Structure):
                 ("n_beams", C.c_int32), ("beams", C.POINTER(Beam)), ("n_probes", C.c_int32),
                 ("probes", C.POINTER(Probe)), ("checkpoint_every", C.c_int32),
                 ("mg_inner_cycles", C.c_int32), ("mg_omega", C.c_double),
-                ("mg_omega_helm", C.c_double), ("adjoint_hold_dxi", C.c_int32)]
+                ("mg_omega_helm", C.c_double), ("adjoint_hold_dxi", C.c_int32),
+                ("pusher", C.c_int32)]
 
 
 class KernelStat(C.Structure):
@@ -155,6 +158,8 @@ def make_config(cfg: dict):
     c.mg_omega = cfg.get("mg_omega", 0.0)
     c.mg_omega_helm = cfg.get("mg_omega_helm", 0.0)
     c.adjoint_hold_dxi = int(cfg.get("adjoint_hold_dxi", 0))
+    pu = cfg.get("pusher", "boris")
+    c.pusher = PUSHERS[pu] if isinstance(pu, str) else int(pu)
     return c, keep
 
 

@@ -433,3 +433,33 @@ def test_graph_replay_bitwise_equal_direct_launches(torch_cuda, monkeypatch, pre
     assert np.array_equal(fa, fb), float(np.abs(fa - fb).max())
     assert np.array_equal(pa, pb), float(np.abs(pa - pb).max())
     assert ia == ib
+
+
+# ------------------------------------------------------------- pushers ------
+
+@pytest.mark.parametrize("pusher", ["rk1", "rk2", "rk4"])
+@pytest.mark.parametrize("name,N", [("C2", 256), ("C5", 1024)])
+def test_slice_rk_pushers_match_oracle(torch_cuda, oracle_mod, pusher, name, N):
+    """The Runge-Kutta pushers (every stage gathers at its own position) on the
+    C2 and C5 grids: one slice from a synthetic state against the oracle."""
+    cfg = wi.scaled(wi.config(name), n_cells=N, precision="fp64", pusher=pusher)
+    state = wi.synthetic_state(cfg, seed=17, p_max=0.5, xi=2.0, field_amp=0.01)
+    _compare_slice(torch_cuda, oracle_mod, cfg, state)
+
+
+@pytest.mark.parametrize("pusher", ["rk2", "rk4"])
+def test_run_c2_start_rk_matches_oracle(torch_cuda, oracle_mod, pusher):
+    """The first 80 slices of the blowout case (adaptive step) with a
+    Runge-Kutta pusher."""
+    cfg = wi.scaled(wi.config("C2"), pusher=pusher)
+    n = 80
+    orc = oracle_mod.Oracle(cfg)
+    st = oracle_mod.initial_state(cfg)
+    assert orc.run(st, n)["status"] == 0
+    sim = _sim(cfg, n)
+    sim.run(n)
+    got = sim.get_state()
+    check_fields(got["fields"].cpu().numpy(), st["fields"], FIELD_TOL, f"C2 run {pusher}")
+    assert np.abs(got["particles"].cpu().numpy() - _particles(st)).max() <= 1e-10
+    assert abs(got["xi"] - st["xi"]) <= 1e-10
+    sim.close()

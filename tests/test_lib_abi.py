@@ -38,7 +38,8 @@ def test_struct_sizes_match_header_layout(lib):
     dict(n_cells=100), dict(n_cells=4), dict(n_cells=8192), dict(half_width=0.0),
     dict(ppc_side=5), dict(ppc_side=2, jitter=0.3), dict(dxi0=0.0), dict(refine_k=-1),
     dict(mg_max_cycles=0), dict(nu_pre=4), dict(nu_post=0), dict(adaptive=2),
-    dict(adaptive=1, checkpoint_every=8), dict(adjoint_hold_dxi=2),
+    dict(adaptive=1, checkpoint_every=8), dict(adjoint_hold_dxi=2), dict(pusher=3),
+    dict(pusher="rk4", checkpoint_every=4, adaptive=0),
 ])
 def test_invalid_configs_rejected(lib, bad):
     cfg = wi.scaled(wi.config("C2"), **bad)
