@@ -938,8 +938,10 @@ struct LdsLevel {
     static __device__ __forceinline__ void sync() { __syncthreads(); }
 
     // nu over-relaxed red-black sweeps (sor_update); iD (FAST and HELM) =
-    // 1 / (4 + h2 k2)
-    static __device__ void smooth(E* u, const E* f, const E* k2, const E* iD, E h2, E om, int nu) {
+    // 1 / (4 + h2 k2); iDf (HELM, not FAST) = the same in float, refined by one
+    // Newton step to the precision of E instead of dividing
+    static __device__ void smooth(E* u, const E* f, const E* k2, const E* iD, const float* iDf, E h2,
+                                  E om, int nu) {
         // slot i: row b, first node a0 = 1 + 2 (i mod HALF); colour c updates a0 + ((1 + b + c) % 2)
         int lb[PER], pb[PER];
         bool ok[PER], last[PER];
@@ -962,7 +964,10 @@ struct LdsLevel {
                     const int l = lb[m] + d;
                     const E nb = u[l - 1] + u[l + 1] + u[l - W] + u[l + W];
                     if (HELM && !FAST) {
-                        const E g = fmad(-h2, f[l], nb) / fmad(h2, k2[l], E(4));
+                        const E D = fmad(h2, k2[l], E(4));
+                        E q = (E)iDf[l];
+                        q = q * fmad(-D, q, E(2));
+                        const E g = fmad(-h2, f[l], nb) * q;
                         u[l] = fmad(om, g - u[l], u[l]);
                     } else {
                         u[l] = sor_update(u[l], nb, f[l], HELM ? iD[l] : E(0.25), h2, om);
@@ -1056,6 +1061,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
     __shared__ C sf[TOT];
     __shared__ C sk[HELM ? TOT : 1];
     __shared__ C siD[(HELM && FAST) ? TOT : 1];
+    __shared__ float siDf[(HELM && !FAST) ? TOT : 1];  // float 1/D for the double sweeps
     __shared__ C sr[FAST ? (kCoarseMax + 1) * (kCoarseMax + 1) : 1];
     const int r = blockIdx.x;
     const int tid = threadIdx.x;
@@ -1071,10 +1077,12 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
     // loads in batches of kB per thread so that their latencies overlap
     constexpr int kB = 8;
     const int nt = (N + 1) * (N + 1);
-    if (HELM && FAST && tot <= kB * kCoarseThreads) {
+    if (HELM && tot <= kB * kCoarseThreads) {
         // one batch: u, f, k2 and 1/D all issued before the first LDS store
+        // (k2 in the type of the sweeps; 1/D always from the float table)
         E uv[kB], fv[kB];
-        float kv[kB], dv[kB];
+        C kv[kB];
+        float dv[kB];
 #pragma unroll
         for (int b = 0; b < kB; ++b) {
             const int i = b * kCoarseThreads + tid;
@@ -1083,7 +1091,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
             const size_t g = ok ? (size_t)y * a.pitch + x : 0;
             uv[b] = (ok && a.u_init[r]) ? a.u_init[r][g] : E(0);
             fv[b] = ok ? a.f[r][g] : E(0);
-            kv[b] = i < tot ? a.k2levf[i] : 0.f;
+            kv[b] = i < tot ? (FAST ? (C)a.k2levf[i] : (C)a.k2lev[i]) : C(0);
             dv[b] = i < tot ? a.idlevf[i] : 0.f;
         }
 #pragma unroll
@@ -1094,8 +1102,9 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
                 sf[i] = (C)fv[b];
             }
             if (i < tot) {
-                sk[i] = (C)kv[b];
-                siD[i] = (C)dv[b];
+                sk[i] = kv[b];
+                if (FAST) siD[i] = (C)dv[b];
+                else siDf[i] = dv[b];
             }
         }
     } else {
@@ -1140,15 +1149,20 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
         else if (HELM)
             for (int base = 0; base < tot; base += kB * kCoarseThreads) {
                 double kv[kB];
+                float dv[kB];
 #pragma unroll
                 for (int b = 0; b < kB; ++b) {
                     const int i = base + b * kCoarseThreads + tid;
                     kv[b] = i < tot ? a.k2lev[i] : 0.0;
+                    dv[b] = i < tot ? a.idlevf[i] : 0.f;
                 }
 #pragma unroll
                 for (int b = 0; b < kB; ++b) {
                     const int i = base + b * kCoarseThreads + tid;
-                    if (i < tot) sk[i] = (C)kv[b];
+                    if (i < tot) {
+                        sk[i] = (C)kv[b];
+                        siDf[i] = dv[b];
+                    }
                 }
             }
     }
@@ -1160,8 +1174,9 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
         C* f = sf + off[l];
         const C* k2 = sk + (HELM ? off[l] : 0);
         const C* iD = siD + ((HELM && FAST) ? off[l] : 0);
+        const float* iDf = siDf + ((HELM && !FAST) ? off[l] : 0);
         with_level<C, HELM, FAST>(Ns[l], [&](auto L) {
-            L.smooth(u, f, k2, iD, (C)(hl * hl), (C)(HELM && hl * hl > a.h2max ? 1.0 : a.omega), a.nu1);
+            L.smooth(u, f, k2, iD, iDf, (C)(hl * hl), (C)(HELM && hl * hl > a.h2max ? 1.0 : a.omega), a.nu1);
             L.restrict_to(u, f, k2, (C)(1.0 / (hl * hl)), su + off[l + 1], sf + off[l + 1], sr);
         });
     };
@@ -1171,7 +1186,8 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
         with_level<C, HELM, FAST>(Ns[l], [&](auto L) {
             L.prolong_add(u, su + off[l + 1]);
             L.smooth(u, sf + off[l], sk + (HELM ? off[l] : 0), siD + ((HELM && FAST) ? off[l] : 0),
-                     (C)(hl * hl), (C)(HELM && hl * hl > a.h2max ? 1.0 : a.omega), a.nu2);
+                     siDf + ((HELM && !FAST) ? off[l] : 0), (C)(hl * hl),
+                     (C)(HELM && hl * hl > a.h2max ? 1.0 : a.omega), a.nu2);
         });
     };
     for (int cyc = 0; cyc < a.ncycles; ++cyc) {
@@ -1400,13 +1416,15 @@ __global__ __launch_bounds__(512) void k_dst2_inv(Dst2Args<E> a) {
 
 // FP64 forms of the two exact coarse Poisson solves, for the mixed form,
 // whose coarsest-grid solve stays in FP64 while its V-cycle levels run in
-// FP32.  The products are plain FP64 fused multiply-adds from LDS (MI355X
-// issues FP64 matrix and vector arithmetic at the same rate): each thread owns
-// one column j and four consecutive rows of the output, so a wavefront reads
-// one row element of the left operand (an LDS broadcast) and 64 consecutive
-// elements of a row of the right operand per step.
-constexpr int kD2Ld64 = kD2 + 1;   // LDS row stride (doubles) of the 128 x 128 operands
-constexpr int kDstLd64 = kDstN + 1;
+// FP32.  The same blocking as the FP32 kernels above, with the products on
+// FP64 MFMA (v_mfma_f64_16x16x4_f64: one 16 x 16 output tile per wavefront,
+// lane l feeding A[i0 + l % 16][4 s + l / 16] and Bt[j0 + l % 16][4 s + l / 16]
+// and holding D[i0 + 4 (l / 16) + q][j0 + l % 16], the layout of the FP32
+// instruction).  Plain FP64 fused multiply-adds from LDS were LDS-bound here:
+// a wavefront's read of one shared row element costs a full LDS pass.
+typedef double dst_v4d __attribute__((ext_vector_type(4)));
+constexpr int kD2Ld64 = kD2 + 1;     // LDS row stride (doubles) of the 128-wide operands
+constexpr int kDstLd64 = kDstN + 4;  // and of the 64 x 64 ones
 
 template <typename E>
 struct Dst2Args64 {
@@ -1418,44 +1436,50 @@ struct Dst2Args64 {
     double* X;  // [R][128][128]
 };
 
-// acc[q] = sum_k A[q0 + q][k] B[k][j] for an inner dimension n.
+// 16 x 16 tile (rows 0..15 of A, columns j0.. of B) of A B for an inner
+// dimension n: A row-major with stride LDA, B given transposed (Bt[j][k] =
+// B[k][j]) with stride LDB.
 template <int n, int LDA, int LDB>
-__device__ __forceinline__ void rows4_times(const double* A, const double* B, int q0, int j,
-                                            double (&acc)[4]) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = 0.0;
+__device__ __forceinline__ dst_v4d tile64(const double* A, const double* Bt, int j0) {
+    const int lane = threadIdx.x & 63;
+    const double* pa = A + (lane & 15) * LDA + (lane >> 4);
+    const double* pb = Bt + (j0 + (lane & 15)) * LDB + (lane >> 4);
+    dst_v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 8
-    for (int k = 0; k < n; ++k) {
-        const double b = B[k * LDB + j];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = __builtin_fma(A[(q0 + q) * LDA + k], b, acc[q]);
-    }
+    for (int s = 0; s < n / 4; ++s)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[4 * s], pb[4 * s], acc, 0, 0, 0);
+    return acc;
 }
 
 // Rows i0 .. i0+15 of X = M o (S F S) on the 128^2 level: T = S[i0.., :] F,
-// then X = M o (T S); F[k][j] = f(node j+1, k+1).  8 workgroups of 512
-// threads per right-hand side.  LDS: the full right operand (F, then S) and
-// the 16-row left operand (rows of S, then T).
+// then X = M o (T S); F[k][j] = f(node j+1, k+1).  8 workgroups of 8
+// wavefronts per right-hand side, wavefront w owning the columns 16 w ...
+// LDS: the right operand transposed (F^T, then S, which is symmetric) and the
+// 16-row left operand (rows of S, then T).
 template <typename E>
 __global__ __launch_bounds__(512) void k_dst2_fwd64(Dst2Args64<E> a) {
-    __shared__ double sB[kD2 * kD2Ld64];
+    __shared__ double sBt[kD2 * kD2Ld64];
     __shared__ double sA[kD2Rows * kD2Ld64];
     const int i0 = kD2Rows * blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
-    const int j = tid & (kD2 - 1), q0 = 4 * (tid >> 7);
+    const int lane = tid & 63, j0 = 16 * (tid >> 6);
+    const int ti = 4 * (lane >> 4), tj = j0 + (lane & 15);  // this lane's outputs: rows ti + q, column tj
     constexpr int kIt = kD2 * kD2 / 512, kRows = kD2Rows * kD2 / 512;
-    {   // every load before the first store (one round trip)
+    {   // every load before the first store (one round trip): the loads are
+        // unconditional (a clamped index) so that none waits for another
         double fv[kIt], sv[kRows];
 #pragma unroll
         for (int t = 0; t < kIt; ++t) {
             const int i = tid + t * 512, y = i >> 7, x = i & (kD2 - 1);
-            fv[t] = (x < kD2 - 1 && y < kD2 - 1) ? (double)a.f[r][(size_t)(y + 1) * a.pitch + x + 1] : 0.0;
+            const bool in = x < kD2 - 1 && y < kD2 - 1;
+            const double v = (double)a.f[r][in ? (size_t)(y + 1) * a.pitch + x + 1 : 0];
+            fv[t] = in ? v : 0.0;
         }
 #pragma unroll
         for (int t = 0; t < kRows; ++t) sv[t] = a.S[i0 * kD2 + tid + t * 512];
 #pragma unroll
         for (int t = 0; t < kIt; ++t) {
-            const int i = tid + t * 512;
-            sB[(i >> 7) * kD2Ld64 + (i & (kD2 - 1))] = fv[t];
+            const int i = tid + t * 512, y = i >> 7, x = i & (kD2 - 1);
+            sBt[x * kD2Ld64 + y] = fv[t];
         }
 #pragma unroll
         for (int t = 0; t < kRows; ++t) {
@@ -1464,38 +1488,38 @@ __global__ __launch_bounds__(512) void k_dst2_fwd64(Dst2Args64<E> a) {
         }
     }
     __syncthreads();
-    double acc[4];
-    rows4_times<kD2, kD2Ld64, kD2Ld64>(sA, sB, q0, j, acc);  // T = S[i0.., :] F
+    dst_v4d d = tile64<kD2, kD2Ld64, kD2Ld64>(sA, sBt, j0);  // T = S[i0.., :] F
     __syncthreads();  // every read of the rows of S and of F is done
     {
         double sv[kIt];
 #pragma unroll
         for (int t = 0; t < kIt; ++t) sv[t] = a.S[tid + t * 512];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) sA[(q0 + q) * kD2Ld64 + j] = acc[q];
+        for (int q = 0; q < 4; ++q) sA[(ti + q) * kD2Ld64 + tj] = d[q];
 #pragma unroll
         for (int t = 0; t < kIt; ++t) {
             const int i = tid + t * 512;
-            sB[(i >> 7) * kD2Ld64 + (i & (kD2 - 1))] = sv[t];
+            sBt[(i >> 7) * kD2Ld64 + (i & (kD2 - 1))] = sv[t];
         }
     }
     __syncthreads();
-    rows4_times<kD2, kD2Ld64, kD2Ld64>(sA, sB, q0, j, acc);  // T S
+    d = tile64<kD2, kD2Ld64, kD2Ld64>(sA, sBt, j0);  // T S
     double* X = a.X + (size_t)r * kD2 * kD2;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int i = (i0 + q0 + q) * kD2 + j;
-        X[i] = a.M[i] * acc[q];
+        const int i = (i0 + ti + q) * kD2 + tj;
+        X[i] = a.M[i] * d[q];
     }
 }
 
 // Rows i0 .. i0+15 of u = S X S: Y = S[i0.., :] X, then u = Y S.
 template <typename E>
 __global__ __launch_bounds__(512) void k_dst2_inv64(Dst2Args64<E> a) {
-    __shared__ double sB[kD2 * kD2Ld64];
+    __shared__ double sBt[kD2 * kD2Ld64];
     __shared__ double sA[kD2Rows * kD2Ld64];
     const int i0 = kD2Rows * blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
-    const int j = tid & (kD2 - 1), q0 = 4 * (tid >> 7);
+    const int lane = tid & 63, j0 = 16 * (tid >> 6);
+    const int ti = 4 * (lane >> 4), tj = j0 + (lane & 15);
     constexpr int kIt = kD2 * kD2 / 512, kRows = kD2Rows * kD2 / 512;
     const double* X = a.X + (size_t)r * kD2 * kD2;
     {
@@ -1506,8 +1530,8 @@ __global__ __launch_bounds__(512) void k_dst2_inv64(Dst2Args64<E> a) {
         for (int t = 0; t < kRows; ++t) sv[t] = a.S[i0 * kD2 + tid + t * 512];
 #pragma unroll
         for (int t = 0; t < kIt; ++t) {
-            const int i = tid + t * 512;
-            sB[(i >> 7) * kD2Ld64 + (i & (kD2 - 1))] = xv[t];
+            const int i = tid + t * 512, y = i >> 7, x = i & (kD2 - 1);
+            sBt[x * kD2Ld64 + y] = xv[t];
         }
 #pragma unroll
         for (int t = 0; t < kRows; ++t) {
@@ -1516,34 +1540,34 @@ __global__ __launch_bounds__(512) void k_dst2_inv64(Dst2Args64<E> a) {
         }
     }
     __syncthreads();
-    double acc[4];
-    rows4_times<kD2, kD2Ld64, kD2Ld64>(sA, sB, q0, j, acc);  // Y = S[i0.., :] X
+    dst_v4d d = tile64<kD2, kD2Ld64, kD2Ld64>(sA, sBt, j0);  // Y = S[i0.., :] X
     __syncthreads();
     {
         double sv[kIt];
 #pragma unroll
         for (int t = 0; t < kIt; ++t) sv[t] = a.S[tid + t * 512];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) sA[(q0 + q) * kD2Ld64 + j] = acc[q];
+        for (int q = 0; q < 4; ++q) sA[(ti + q) * kD2Ld64 + tj] = d[q];
 #pragma unroll
         for (int t = 0; t < kIt; ++t) {
             const int i = tid + t * 512;
-            sB[(i >> 7) * kD2Ld64 + (i & (kD2 - 1))] = sv[t];
+            sBt[(i >> 7) * kD2Ld64 + (i & (kD2 - 1))] = sv[t];
         }
     }
     __syncthreads();
-    rows4_times<kD2, kD2Ld64, kD2Ld64>(sA, sB, q0, j, acc);  // u = Y S
+    d = tile64<kD2, kD2Ld64, kD2Ld64>(sA, sBt, j0);  // u = Y S
     E* u = a.u_out[r];
     // row and column 127 of S are 0, so row and column 128 (boundary) get 0
 #pragma unroll
-    for (int q = 0; q < 4; ++q) u[(size_t)(i0 + q0 + q + 1) * a.pitch + j + 1] = (E)acc[q];
+    for (int q = 0; q < 4; ++q) u[(size_t)(i0 + ti + q + 1) * a.pitch + tj + 1] = (E)d[q];
     if (tid < kD2Rows) u[(size_t)(i0 + tid + 1) * a.pitch] = E(0);  // column 0
     if (blockIdx.x == 0)
         for (int x = tid; x <= kD2; x += 512) u[x] = E(0);  // row 0
 }
 
-// The 64^2 exact solve in FP64 (grids of 128^2): one workgroup of 1024 threads
-// per right-hand side, u = S (M o (S F S)) S as four products in LDS.
+// The 64^2 exact solve in FP64 (grids of 128^2): one workgroup of 16
+// wavefronts per right-hand side, u = S (M o (S F S)) S as four products in
+// LDS, as in k_coarse_dst.
 template <typename E>
 struct DstArgs64 {
     int pitch;
@@ -1558,45 +1582,54 @@ __global__ __launch_bounds__(1024) void k_coarse_dst64(DstArgs64<E> a) {
     __shared__ double sS[kDstN * kDstLd64];
     __shared__ double sX[kDstN * kDstLd64];
     __shared__ double sY[kDstN * kDstLd64];
-    const int r = blockIdx.x, tid = threadIdx.x;
-    const int j = tid & (kDstN - 1), q0 = 4 * (tid >> 6);
+    const int r = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int i0 = 16 * (w >> 2), j0 = 16 * (w & 3);
+    const int ti = i0 + 4 * (lane >> 4), tj = j0 + (lane & 15);
+    double mv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) mv[q] = a.M[(ti + q) * kDstN + tj];
     constexpr int kIt = kDstN * kDstN / 1024;
-    {
+    {   // S and F^T: sX[x][y] = f(node y + 1, x + 1); unconditional loads first
         double sv[kIt], fv[kIt];
 #pragma unroll
         for (int t = 0; t < kIt; ++t) {
             const int i = tid + t * 1024, y = i >> 6, x = i & (kDstN - 1);
+            const bool in = x < kDstN - 1 && y < kDstN - 1;
             sv[t] = a.S[i];
-            fv[t] = (x < kDstN - 1 && y < kDstN - 1) ? (double)a.f[r][(size_t)(y + 1) * a.pitch + x + 1] : 0.0;
+            const double v = (double)a.f[r][in ? (size_t)(y + 1) * a.pitch + x + 1 : 0];
+            fv[t] = in ? v : 0.0;
         }
 #pragma unroll
         for (int t = 0; t < kIt; ++t) {
             const int i = tid + t * 1024, y = i >> 6, x = i & (kDstN - 1);
             sS[y * kDstLd64 + x] = sv[t];
-            sX[y * kDstLd64 + x] = fv[t];
+            sX[x * kDstLd64 + y] = fv[t];
         }
     }
     __syncthreads();
-    double acc[4];
-    rows4_times<kDstN, kDstLd64, kDstLd64>(sS, sX, q0, j, acc);  // Y = S F
+    dst_v4d d = tile64<kDstN, kDstLd64, kDstLd64>(sS + i0 * kDstLd64, sX, j0);  // Y = S F
 #pragma unroll
-    for (int q = 0; q < 4; ++q) sY[(q0 + q) * kDstLd64 + j] = acc[q];
+    for (int q = 0; q < 4; ++q) sY[(ti + q) * kDstLd64 + tj] = d[q];
     __syncthreads();
-    rows4_times<kDstN, kDstLd64, kDstLd64>(sY, sS, q0, j, acc);  // X = M o (Y S)
+    d = tile64<kDstN, kDstLd64, kDstLd64>(sY + i0 * kDstLd64, sS, j0);  // X = M o (Y S), stored transposed
+    __syncthreads();  // every read of the operands is done before sX is rewritten
 #pragma unroll
-    for (int q = 0; q < 4; ++q) sX[(q0 + q) * kDstLd64 + j] = a.M[(q0 + q) * kDstN + j] * acc[q];
+    for (int q = 0; q < 4; ++q) sX[tj * kDstLd64 + ti + q] = mv[q] * d[q];
     __syncthreads();
-    rows4_times<kDstN, kDstLd64, kDstLd64>(sS, sX, q0, j, acc);  // Y = S X
-    __syncthreads();  // every read of sY (the previous product) is done
-#pragma unroll
-    for (int q = 0; q < 4; ++q) sY[(q0 + q) * kDstLd64 + j] = acc[q];
+    d = tile64<kDstN, kDstLd64, kDstLd64>(sS + i0 * kDstLd64, sX, j0);  // Y = S X
     __syncthreads();
-    rows4_times<kDstN, kDstLd64, kDstLd64>(sY, sS, q0, j, acc);  // U = Y S
-    E* u = a.u_out[r];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) u[(size_t)(q0 + q + 1) * a.pitch + j + 1] = (E)acc[q];
-    if (tid < kDstN) u[(size_t)(tid + 1) * a.pitch] = E(0);
-    if (tid <= kDstN) u[tid] = E(0);
+    for (int q = 0; q < 4; ++q) sY[(ti + q) * kDstLd64 + tj] = d[q];
+    __syncthreads();
+    d = tile64<kDstN, kDstLd64, kDstLd64>(sY + i0 * kDstLd64, sS, j0);  // U = Y S
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sX[(ti + q) * kDstLd64 + tj] = d[q];
+    __syncthreads();
+    for (int i = tid; i < (kDstN + 1) * (kDstN + 1); i += 1024) {
+        const int y = i / (kDstN + 1), x = i - y * (kDstN + 1);
+        const bool in = x >= 1 && x <= kDstN - 1 && y >= 1 && y <= kDstN - 1;
+        a.u_out[r][(size_t)y * a.pitch + x] = (E)(in ? sX[(y - 1) * kDstLd64 + x - 1] : 0.0);
+    }
 }
 
 // Tables of the exact coarse Poisson solve on an n^2 level of spacing H:
