@@ -151,6 +151,11 @@ typedef struct {
                                  the state through Vmax.  Ignored without adaptive
                                  steps or without a tape. */
     int32_t pusher;           /* a wandqs_pusher value, 0 = Boris-like; a tape needs BORIS */
+    int32_t driver_max;       /* > 0: room for that many driver macroparticles and the
+                                 time loop (wandqs_driver_set, wandqs_time_step); 0: none.
+                                 Not with a tape. */
+    int32_t driver_nz;        /* driver current planes xi_m = driver_xi0 + m driver_dz,   */
+    double driver_xi0, driver_dz; /* m = 0 .. driver_nz - 1 (>= 2 planes, dz > 0)          */
 } wandqs_config;
 
 typedef struct {
@@ -204,6 +209,36 @@ wandqs_status wandqs_get_state(wandqs_ctx* ctx, double* d_particles, double* d_f
  * boundary nodes are set to zero.  Clears a failed context. */
 wandqs_status wandqs_set_state(wandqs_ctx* ctx, const double* d_particles,
                                const double* d_fields, const double* h_xi_dxi);
+
+/* The time loop of Algorithm 1 (outer loop over t, Push_Driver; Sec. VII.A,
+ * eqs. (25)-(26)), for contexts made with driver_max > 0.
+ *
+ * wandqs_driver_set copies n (<= driver_max) driver macroparticles, device
+ * [8][n] rows x, y, xi (= t - z), p_x, p_y, p_z (momenta in m_e c), q/m (in
+ * units of e/m_e: -1 for electrons) and w (the number of particles each
+ * stands for, in units of n0 k_p^-3); wandqs_driver_get copies the current
+ * ones back (device [8][n]).
+ *
+ * wandqs_time_step(dt, n_slices): the driver particles deposit their
+ * longitudinal current -q/m w v_z (CIC in x, y; linear in xi onto the planes
+ * xi_m = driver_xi0 + m driver_dz; particles outside the box or the planes add
+ * nothing; a fixed-point sum, so the deposit is deterministic); the plasma
+ * restarts as the cold plasma at rest at xi = 0 with zero fields and is swept
+ * through n_slices slices (as wandqs_run, the records in h_infos) with that
+ * current added to j_z, the planes interpolated linearly in xi at each slice
+ * (a near-luminal driver has rho_b = J_bz, so it enters only j_z); each
+ * driver particle takes the wake at its mid-step position x + (dt/2) v,
+ * xi + (dt/2)(1 - v_z) from the two slices that bracket it (CIC in each,
+ * linear in xi; zero ahead of the first slice, at or behind the last and
+ * outside the box), with E = (-d_x psi + B_y, -d_y psi - B_x, Ez) and B =
+ * (Bx, By, Bz); finally every driver particle advances by dt with a drift of
+ * dt/2, a kick dt/2, the rotation of a Boris push about (q/m) B / gamma, a kick
+ * dt/2 and a drift dt/2.  The fields and plasma state after the call are those
+ * of the last slice.  WANDQS_E_INVALID without driver_max. */
+wandqs_status wandqs_driver_set(wandqs_ctx* ctx, int64_t n, const double* d_state);
+wandqs_status wandqs_driver_get(wandqs_ctx* ctx, double* d_state);
+wandqs_status wandqs_time_step(wandqs_ctx* ctx, double dt, int32_t n_slices,
+                               wandqs_slice_info* h_infos);
 
 /* Multigrid solve on the context's grid, the solver of Solve_Wakefield
  * (Sec. II item 4, Sec. VII.A): (L_h - k2) u = f on the interior nodes with

@@ -46,7 +46,9 @@ class Cfg(C.Structure):
                 ("n0", C.c_double), ("dxi0", C.c_double), ("adaptive", C.c_int),
                 ("refine_k", C.c_int), ("mg_rtol", C.c_double), ("mg_atol", C.c_double),
                 ("mg_max_cycles", C.c_int), ("nu_pre", C.c_int), ("nu_post", C.c_int),
-                ("n_beams", C.c_int), ("beams", C.POINTER(Beam)), ("pusher", C.c_int)]
+                ("n_beams", C.c_int), ("beams", C.POINTER(Beam)), ("pusher", C.c_int),
+                ("drv_planes", _dp), ("drv_nz", C.c_int), ("drv_xi0", C.c_double),
+                ("drv_dz", C.c_double)]
 
 
 class Info(C.Structure):
@@ -145,6 +147,48 @@ class Oracle:
         st = lib().oracle_push_fields(C.byref(self.c), C.c_double(dxi), arrs[0].size, _p(F),
                                       *[_p(a) for a in arrs], C.byref(vm))
         return (st, *arrs, vm.value)
+
+    # ------------------------------------------------------------ driver
+    def driver_deposit(self, drv, nz, xi0, dz):
+        """Longitudinal current of driver particles drv [8][n] on nz planes."""
+        d = _f64(drv).reshape(8, -1)
+        out = np.zeros((nz, self.nn))
+        lib().oracle_driver_deposit(C.byref(self.c), d.shape[1], _p(d), int(nz), C.c_double(xi0),
+                                    C.c_double(dz), _p(out))
+        return out.reshape(nz, self.N + 1, self.N + 1)
+
+    def driver_push(self, drv, dt, xi_s, F_s):
+        """Advance driver particles drv [8][n] by dt through the slices
+        (xi_s [ns], F_s [ns][5][N+1][N+1]); returns the new state."""
+        d = _f64(drv).reshape(8, -1).copy()
+        xs = _f64(xi_s)
+        Fs = _f64(F_s).reshape(xs.size, 5, -1)
+        lib().oracle_driver_push(C.byref(self.c), C.c_double(dt), d.shape[1], _p(d), xs.size,
+                                 _p(xs), _p(Fs))
+        return d
+
+    def time_step(self, state, drv, n_slices, dt, nz, xi0, dz, keep_fields=False):
+        """One step of the time loop: the driver's current on nz planes, a sweep
+        of n_slices slices through `state` (advanced in place), the driver
+        (drv [8][n], advanced in place) pushed by dt.  Returns dict(status,
+        infos[, xi, fields])."""
+        state["fields"] = _f64(state["fields"]).reshape(5, self.N + 1, self.N + 1)
+        d = _f64(drv).reshape(8, -1)
+        xi = C.c_double(state["xi"])
+        dxi = C.c_double(state["dxi"])
+        hx = np.zeros(n_slices)
+        hF = np.zeros((n_slices, 5, self.nn)) if keep_fields else None
+        infos = (Info * n_slices)()
+        st = lib().oracle_time_step(C.byref(self.c), state["x"].size, _p(state["x"]),
+                                    _p(state["y"]), _p(state["px"]), _p(state["py"]),
+                                    _p(state["fields"]), C.byref(xi), C.byref(dxi), int(n_slices),
+                                    d.shape[1], _p(d), int(nz), C.c_double(xi0), C.c_double(dz),
+                                    C.c_double(dt), _p(hx), _p(hF), infos)
+        state["xi"], state["dxi"] = xi.value, dxi.value
+        out = dict(status=st, infos=list(infos), xi=hx)
+        if keep_fields:
+            out["fields"] = hF.reshape(n_slices, 5, self.N + 1, self.N + 1)
+        return out
 
     def next_dxi(self, vmax):
         return lib().oracle_next_dxi(C.byref(self.c), C.c_double(vmax))

@@ -74,6 +74,11 @@ typedef struct {
     int n_beams;
     const oracle_beam* beams;
     int pusher;           /* 0: Boris-like; 1, 2, 4: Runge-Kutta of that order */
+    /* longitudinal current of driver macroparticles (oracle_driver_deposit) on
+     * drv_nz planes xi = drv_xi0 + m drv_dz, [drv_nz][nn]; NULL: none */
+    const double* drv_planes;
+    int drv_nz;
+    double drv_xi0, drv_dz;
 } oracle_cfg;
 
 typedef struct {
@@ -475,6 +480,18 @@ double beam_density(const oracle_cfg& c, double x, double y, double xi) {
     return beam_density<double>(c, nullptr, x, y, xi);
 }
 
+/* Driver macroparticles' longitudinal current at node i and slice position
+ * xi: linear interpolation between the two deposit planes around xi, zero
+ * outside the planes. */
+double driver_current(const oracle_cfg& c, int i, int nn, double xi) {
+    if (!c.drv_planes || c.drv_nz < 2) return 0.0;
+    const double t = (xi - c.drv_xi0) / c.drv_dz;
+    const int m = (int)std::floor(t);
+    if (m < 0 || m > c.drv_nz - 2) return 0.0;
+    const double a = t - m;
+    return (1.0 - a) * c.drv_planes[(size_t)m * nn + i] + a * c.drv_planes[(size_t)(m + 1) * nn + i];
+}
+
 /* ----------------------------------------------------------- slice step -- */
 
 template <class T>
@@ -510,7 +527,8 @@ int assemble(const Grid& g, const oracle_cfg& c, double xi, const MomentsT<T>& m
                 G[i] = (m.n[i] * (1.0 + gg * gg) + gg * gg * (m.txx[i] + m.tyy[i])) / (2.0 * gg);
                 plasma_jz = G[i] / gg - m.n[i];
             }
-            jz[i] = plasma_jz + beam_density(c, theta, g.xa(a), g.xa(b), xi);
+            jz[i] = plasma_jz + beam_density(c, theta, g.xa(a), g.xa(b), xi) +
+                    driver_current(c, i, nn, xi);
         }
     const int status = nonphys ? ORC_NONPHYS : ORC_OK;
     k2.assign(nn, T(0.0));
@@ -1066,6 +1084,189 @@ int oracle_run(const oracle_cfg* c, int P, double* x, double* y, double* px, dou
         if (fields_hist) std::copy(fields, fields + 5 * nn, fields_hist + (size_t)j * 5 * nn);
         if (st != ORC_OK) return st;
     }
+    return ORC_OK;
+}
+
+} /* extern "C" */
+
+/* ============================================================ driver == */
+/*
+ * The time loop of Algorithm 1 around the xi-sweep: driver macroparticles
+ * (positions x, y, xi = t - z, momenta p_x, p_y, p_z, charge-to-mass ratio
+ * q/m in units of e/m_e, and weight w = their number in units of n0 k_p^-3)
+ * deposit their longitudinal current onto planes in xi, the plasma is swept
+ * through the slices with that current in j_z, the wakefields are gathered at
+ * the driver particles and the driver is advanced in t by eqs. (25)-(26).
+ * Driver state layout [8][n]: x, y, xi, px, py, pz, qm, w.
+ */
+namespace {
+
+enum { DX = 0, DY, DXI, DPX, DPY, DPZ, DQM, DW, DNV };
+
+/* The wakefields at one point from a stack of solved slices: psi's node
+ * gradient, Ez, Bz, B_perp gathered (CIC) in the two slices that bracket xi
+ * (xi_j <= xi < xi_{j+1}) and interpolated linearly in xi; zero ahead of the
+ * first slice, at or behind the last and outside the transverse box.  E_perp = -grad psi - e_z x B_perp (the
+ * field whose force on a luminal particle is -grad psi, as in the plasma
+ * electrons' equations of motion), so E = (-d_x psi + B_y, -d_y psi - B_x, Ez). */
+struct SliceStack {
+    const Grid* g;
+    int ns;
+    const double* xi;                  /* [ns] */
+    const double* F;                   /* [ns][5][nn] */
+    const std::vector<double>* gx;     /* [ns] node gradients of psi */
+    const std::vector<double>* gy;
+};
+
+void wake_at(const SliceStack& S, double x, double y, double xi, double (&E)[3], double (&B)[3]) {
+    for (int q = 0; q < 3; ++q) E[q] = B[q] = 0.0;
+    const Grid& g = *S.g;
+    if (S.ns < 2 || xi < S.xi[0] || xi >= S.xi[S.ns - 1] || std::fabs(x) > g.L || std::fabs(y) > g.L)
+        return;
+    int j = 0;  /* xi_j <= xi < xi_{j+1} */
+    while (S.xi[j + 1] <= xi) ++j;
+    const int j1 = j + 1;
+    const double a = (xi - S.xi[j]) / (S.xi[j1] - S.xi[j]);
+    const int nn = g.nn();
+    const int js[2] = {j, j1};
+    const double ws[2] = {1.0 - a, a};
+    for (int k = 0; k < 2; ++k) {
+        const double* F = S.F + (size_t)js[k] * 5 * nn;
+        const double Gx = gather1(g, S.gx[js[k]].data(), x, y), Gy = gather1(g, S.gy[js[k]].data(), x, y);
+        const double ez = gather1(g, F + nn, x, y), bz = gather1(g, F + 2 * nn, x, y);
+        const double bx = gather1(g, F + 3 * nn, x, y), by = gather1(g, F + 4 * nn, x, y);
+        E[0] += ws[k] * (-Gx + by);
+        E[1] += ws[k] * (-Gy - bx);
+        E[2] += ws[k] * ez;
+        B[0] += ws[k] * bx;
+        B[1] += ws[k] * by;
+        B[2] += ws[k] * bz;
+    }
+}
+
+/* One step dt of eqs. (25)-(26) for one driver particle: a drift of dt/2,
+ * a kick of dt/2 by qm E, the rotation of a Boris push about qm B/gamma, a
+ * kick of dt/2 and a drift of dt/2 with the new momentum, the fields taken at
+ * the mid-step position (a volume-preserving splitting of the relativistic
+ * Lorentz-force flow).  In (x, y, xi): dx/dt = p_x/gamma, dy/dt = p_y/gamma,
+ * dxi/dt = 1 - p_z/gamma. */
+void drive_one(const SliceStack& S, double dt, double* st) {
+    double g0 = std::sqrt(1.0 + st[DPX] * st[DPX] + st[DPY] * st[DPY] + st[DPZ] * st[DPZ]);
+    const double xh = st[DX] + 0.5 * dt * st[DPX] / g0;
+    const double yh = st[DY] + 0.5 * dt * st[DPY] / g0;
+    const double xih = st[DXI] + 0.5 * dt * (1.0 - st[DPZ] / g0);
+    double E[3], B[3];
+    wake_at(S, xh, yh, xih, E, B);
+    const double k = 0.5 * dt * st[DQM];
+    double m[3] = {st[DPX] + k * E[0], st[DPY] + k * E[1], st[DPZ] + k * E[2]};
+    const double gm = std::sqrt(1.0 + m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+    const double t[3] = {k * B[0] / gm, k * B[1] / gm, k * B[2] / gm};
+    const double tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+    const double sv[3] = {2.0 * t[0] / (1.0 + tt), 2.0 * t[1] / (1.0 + tt), 2.0 * t[2] / (1.0 + tt)};
+    const double pr[3] = {m[0] + (m[1] * t[2] - m[2] * t[1]), m[1] + (m[2] * t[0] - m[0] * t[2]),
+                          m[2] + (m[0] * t[1] - m[1] * t[0])};
+    const double pp[3] = {m[0] + (pr[1] * sv[2] - pr[2] * sv[1]), m[1] + (pr[2] * sv[0] - pr[0] * sv[2]),
+                          m[2] + (pr[0] * sv[1] - pr[1] * sv[0])};
+    st[DPX] = pp[0] + k * E[0];
+    st[DPY] = pp[1] + k * E[1];
+    st[DPZ] = pp[2] + k * E[2];
+    const double g1 = std::sqrt(1.0 + st[DPX] * st[DPX] + st[DPY] * st[DPY] + st[DPZ] * st[DPZ]);
+    st[DX] = xh + 0.5 * dt * st[DPX] / g1;
+    st[DY] = yh + 0.5 * dt * st[DPY] / g1;
+    st[DXI] = xih + 0.5 * dt * (1.0 - st[DPZ] / g1);
+}
+
+}  // namespace
+
+extern "C" {
+
+/* Longitudinal current of the driver particles on nz planes xi_m = xi0 +
+ * m dz (out [nz][nn]): each particle adds -qm w v_z (its charge -qm in units
+ * of -e times its number, times v_z = p_z/gamma) with CIC weights in x and y
+ * and linear (hat) weights in xi, divided by h^2 dz.  Particles outside the
+ * transverse box or the plane range add nothing.  (A luminal driver,
+ * v_z -> 1, has rho_b = J_bz: it enters the slice only through j_z.) */
+int oracle_driver_deposit(const oracle_cfg* c, int n, const double* st, int nz, double xi0,
+                          double dz, double* out) {
+    Grid g(c->n_cells, c->half_width);
+    const int nn = g.nn();
+    std::fill(out, out + (size_t)nz * nn, 0.0);
+    for (int p = 0; p < n; ++p) {
+        const double x = st[DX * n + p], y = st[DY * n + p], xi = st[DXI * n + p];
+        if (std::fabs(x) > g.L || std::fabs(y) > g.L) continue;
+        const double t = (xi - xi0) / dz;
+        const int m = (int)std::floor(t);
+        if (m < 0 || m > nz - 2) continue;
+        const double az = t - m;
+        const double px = st[DPX * n + p], py = st[DPY * n + p], pz = st[DPZ * n + p];
+        const double vz = pz / std::sqrt(1.0 + px * px + py * py + pz * pz);
+        const double q = -st[DQM * n + p] * st[DW * n + p] * vz / (g.h * g.h * dz);
+        int a, b;
+        double dx, dy;
+        cic(g, x, a, dx);
+        cic(g, y, b, dy);
+        for (int k = 0; k < 2; ++k) {
+            double* P = out + (size_t)(m + k) * nn;
+            const double wz = k ? az : 1.0 - az;
+            P[g.id(a, b)] += q * wz * (1.0 - dx) * (1.0 - dy);
+            P[g.id(a + 1, b)] += q * wz * dx * (1.0 - dy);
+            P[g.id(a, b + 1)] += q * wz * (1.0 - dx) * dy;
+            P[g.id(a + 1, b + 1)] += q * wz * dx * dy;
+        }
+    }
+    return ORC_OK;
+}
+
+/* Advance n driver particles (state [8][n], updated) by dt through the wake
+ * of ns solved slices at positions xi_s[ns] with fields F_s [ns][5][nn]. */
+int oracle_driver_push(const oracle_cfg* c, double dt, int n, double* st, int ns,
+                       const double* xi_s, const double* F_s) {
+    Grid g(c->n_cells, c->half_width);
+    const int nn = g.nn();
+    std::vector<std::vector<double>> gx(ns), gy(ns);
+    for (int j = 0; j < ns; ++j) psi_gradient(g, F_s + (size_t)j * 5 * nn, gx[j], gy[j]);
+    const SliceStack S{&g, ns, xi_s, F_s, gx.data(), gy.data()};
+#pragma omp parallel for schedule(static)
+    for (int p = 0; p < n; ++p) {
+        double v[DNV];
+        for (int q = 0; q < DNV; ++q) v[q] = st[(size_t)q * n + p];
+        drive_one(S, dt, v);
+        for (int q = 0; q < DNV; ++q) st[(size_t)q * n + p] = v[q];
+    }
+    return ORC_OK;
+}
+
+/* One step of the time loop (Algorithm 1, outer loop): the driver's current
+ * on nz planes (xi0, dz), a sweep of n_slices slices through the plasma given
+ * (normally the cold plasma at xi = 0 with zero fields, advanced in place)
+ * with that current in j_z, then the driver advanced by dt through the wake
+ * of those slices.  xi_hist [n_slices] and fields_hist [n_slices][5][nn] (may
+ * be NULL) receive the slices. */
+int oracle_time_step(const oracle_cfg* c, int P, double* x, double* y, double* px, double* py,
+                     double* fields, double* xi, double* dxi, int n_slices, int n_drv,
+                     double* drv, int nz, double xi0, double dz, double dt, double* xi_hist,
+                     double* fields_hist, oracle_info* infos) {
+    Grid g(c->n_cells, c->half_width);
+    const int nn = g.nn();
+    std::vector<double> planes((size_t)nz * nn), hx(n_slices), hF((size_t)n_slices * 5 * nn);
+    oracle_driver_deposit(c, n_drv, drv, nz, xi0, dz, planes.data());
+    oracle_cfg cc = *c;
+    cc.drv_planes = planes.data();
+    cc.drv_nz = nz;
+    cc.drv_xi0 = xi0;
+    cc.drv_dz = dz;
+    int status = ORC_OK;
+    for (int j = 0; j < n_slices && status == ORC_OK; ++j) {
+        hx[j] = *xi;
+        oracle_info inf;
+        status = oracle_slice_step(&cc, P, x, y, px, py, nullptr, fields, xi, dxi, &inf, nullptr, nullptr);
+        if (infos) infos[j] = inf;
+        std::copy(fields, fields + 5 * nn, hF.begin() + (size_t)j * 5 * nn);
+    }
+    if (status != ORC_OK) return status;
+    oracle_driver_push(c, dt, n_drv, drv, n_slices, hx.data(), hF.data());
+    if (xi_hist) std::copy(hx.begin(), hx.end(), xi_hist);
+    if (fields_hist) std::copy(hF.begin(), hF.end(), fields_hist);
     return ORC_OK;
 }
 

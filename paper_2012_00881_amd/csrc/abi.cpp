@@ -77,6 +77,13 @@ const char* check_config(const wandqs_config* c, int32_t n_slices) {
         return "pusher must be WANDQS_PUSH_BORIS, _RK1, _RK2 or _RK4";
     if (c->checkpoint_every > 0 && c->pusher != WANDQS_PUSH_BORIS)
         return "the adjoint tape needs the Boris-like pusher (the reverse sweep is its adjoint)";
+    if (c->driver_max < 0) return "driver_max must be >= 0";
+    if (c->driver_max > 0) {
+        if (c->driver_nz < 2 || c->driver_nz > 65536 || !(c->driver_dz > 0.0) ||
+            !std::isfinite(c->driver_xi0))
+            return "a time loop needs driver_nz in [2, 65536], driver_dz > 0 and a finite driver_xi0";
+        if (c->checkpoint_every > 0) return "the time loop (driver_max > 0) has no adjoint tape";
+    }
     if (c->checkpoint_every > 0 && c->adaptive && !c->adjoint_hold_dxi)
         return "a tape with adaptive steps differentiates with the forward's steps held fixed "
                "(they depend on the state through Vmax): set adjoint_hold_dxi = 1 to accept that";
@@ -151,6 +158,7 @@ void set_sizes(wandqs_ctx* c, const wandqs_config* cfg, int32_t n_slices) {
             c->n_seg_cap += segs_all;
         }
     }
+    c->drv_nz = cfg->driver_max > 0 ? cfg->driver_nz : 0;
     c->tape_K = cfg->checkpoint_every;
     c->n_ckpt = c->tape_K > 0 ? (n_slices + c->tape_K - 1) / c->tape_K + 1 : 0;
 }
@@ -266,6 +274,14 @@ wandqs_status do_slice(wandqs_ctx* c, int rec_slot, int64_t probe_slice, bool ta
     }
     if (!c->probes.empty() && (s = probes_accumulate(c, probe_slice)) != WANDQS_OK) return s;
     if ((s = push_and_step(c, rec_slot)) != WANDQS_OK) return s;  // Push_Trajectory + Step_Size_Refinement
+    if (c->drv_active) {
+        // the driver particles whose mid-step xi lies between the previous
+        // slice and this one take their wake from the two; this slice's
+        // grad psi becomes the previous one
+        if (c->n_guess >= 1 && (s = driver_gather(c, c->drv_dt)) != WANDQS_OK) return s;
+        std::swap(c->gpsi[0], c->gpsi_prev[0]);
+        std::swap(c->gpsi[1], c->gpsi_prev[1]);
+    }
     if (c->n_guess < kGuessMax) ++c->n_guess;
     if (taping) ++c->tape_n;
     return WANDQS_OK;
@@ -374,6 +390,16 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
     c->key = (int32_t*)take(sizeof(int32_t) * P);
     c->perm = (int32_t*)take(sizeof(int32_t) * P);
     for (int q = 0; q < 2; ++q) c->gpsi[q] = arr(0);
+    if (c->cfg.driver_max > 0) {
+        const size_t D = (size_t)c->cfg.driver_max;
+        c->drv = (double*)take(sizeof(double) * 8 * D);
+        c->drv_eb = (double*)take(sizeof(double) * 6 * D);
+        c->drv_planes = (unsigned long long*)take(sizeof(unsigned long long) * (size_t)c->drv_nz *
+                                                  (c->N + 1) * L0.pitch);
+        for (int q = 0; q < 2; ++q) c->gpsi_prev[q] = arr(0);
+        for (int q = 0; q < 2; ++q) c->lat[q] = (double*)take(sizeof(double) * P);
+        c->lat_id = (int32_t*)take(sizeof(int32_t) * P);
+    }
     c->cell_count = (int32_t*)take(sizeof(int32_t) * ncell);
     c->cell_start = (int32_t*)take(sizeof(int32_t) * (ncell + 1));
     c->big_cells = (int32_t*)take(sizeof(int32_t) * ncell);
@@ -699,6 +725,9 @@ wandqs_status wandqs_init(const wandqs_config* cfg, int32_t n_slices, void* d_wo
               hipMemcpyAsync(c->pa[0][0], host.data(), sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
               hipMemcpyAsync(c->pa[0][1], host.data() + c->P, sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
               hipMemcpyAsync(c->pid[0], ids.data(), sizeof(int32_t) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+              (!c->lat[0] || (hipMemcpyAsync(c->lat[0], host.data(), sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+                              hipMemcpyAsync(c->lat[1], host.data() + c->P, sizeof(double) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+                              hipMemcpyAsync(c->lat_id, ids.data(), sizeof(int32_t) * c->P, hipMemcpyHostToDevice, c->stream) == hipSuccess)) &&
               hipMemcpyAsync(c->st, st0, sizeof(st0), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
               (bins_host.empty() || hipMemcpyAsync(c->bins_dev, bins_host.data(), sizeof(double) * bins_host.size(), hipMemcpyHostToDevice, c->stream) == hipSuccess) &&
               (bmap.empty() || hipMemcpyAsync(c->bin_map, bmap.data(), sizeof(int32_t) * bmap.size(), hipMemcpyHostToDevice, c->stream) == hipSuccess) &&
@@ -823,6 +852,78 @@ wandqs_status wandqs_set_state(wandqs_ctx* c, const double* d_particles, const d
     c->tape_n = 0;  // the tape restarts from this state
     c->tape_ok = true;
     c->run_len = -1;
+    return WANDQS_OK;
+}
+
+wandqs_status wandqs_driver_set(wandqs_ctx* c, int64_t n, const double* d_state) {
+    if (!c) return WANDQS_E_INVALID;
+    if (c->cfg.driver_max <= 0) {
+        c->err = "no room for driver particles: initialise with driver_max > 0";
+        return WANDQS_E_INVALID;
+    }
+    if (n < 0 || n > c->cfg.driver_max || (n > 0 && !d_state)) {
+        c->err = "driver particle count must be in [0, driver_max] with a state array";
+        return WANDQS_E_INVALID;
+    }
+    const size_t D = (size_t)c->cfg.driver_max;
+    wandqs_status s;
+    for (int q = 0; q < 8 && n > 0; ++q)
+        if ((s = wq::copy_d2d(c, c->drv + q * D, d_state + (size_t)q * n, sizeof(double) * n)) != WANDQS_OK)
+            return fail(c, s);
+    c->drv_n = n;
+    return WANDQS_OK;
+}
+
+wandqs_status wandqs_driver_get(wandqs_ctx* c, double* d_state) {
+    if (!c || (c->drv_n > 0 && !d_state)) return WANDQS_E_INVALID;
+    const size_t D = (size_t)c->cfg.driver_max, n = (size_t)c->drv_n;
+    wandqs_status s;
+    for (int q = 0; q < 8 && n > 0; ++q)
+        if ((s = wq::copy_d2d(c, d_state + q * n, c->drv + q * D, sizeof(double) * n)) != WANDQS_OK)
+            return fail(c, s);
+    return WANDQS_OK;
+}
+
+wandqs_status wandqs_time_step(wandqs_ctx* c, double dt, int32_t n_slices, wandqs_slice_info* h_infos) {
+    using namespace wq;
+    if (!c || n_slices < 1 || !std::isfinite(dt)) return WANDQS_E_INVALID;
+    if (c->cfg.driver_max <= 0) {
+        c->err = "no time loop: initialise with driver_max > 0";
+        return WANDQS_E_INVALID;
+    }
+    if (c->failed) {
+        c->err = "context failed earlier; call wandqs_set_state";
+        return WANDQS_E_STATE;
+    }
+    // the plasma ahead of the drivers is the cold plasma at rest: every time
+    // step sweeps it from xi = 0 with zero fields
+    wandqs_status s;
+    const size_t P = (size_t)c->P, nb = (size_t)(c->N + 1) * c->lev[0].pitch;
+    const int k = c->cur;
+    if ((s = copy_d2d(c, c->pa[k][0], c->lat[0], sizeof(double) * P)) != WANDQS_OK ||
+        (s = copy_d2d(c, c->pa[k][1], c->lat[1], sizeof(double) * P)) != WANDQS_OK ||
+        (s = copy_d2d(c, c->pid[k], c->lat_id, sizeof(int32_t) * P)) != WANDQS_OK ||
+        (s = fill_f64(c, c->pa[k][2], P, 0.0)) != WANDQS_OK ||
+        (s = fill_f64(c, c->pa[k][3], P, 0.0)) != WANDQS_OK)
+        return fail(c, s);
+    for (int q = 0; q < 5; ++q) {
+        double* arrs[4] = {c->fields[q], c->fields_prev[q], c->fields_prev2[q], c->fields_prev3[q]};
+        for (double* a : arrs)
+            if (a && (s = fill_f64(c, a, nb, 0.0)) != WANDQS_OK) return fail(c, s);
+    }
+    if ((s = fill_f64(c, c->st, 16, 0.0)) != WANDQS_OK || (s = fill_f64(c, c->st + 1, 1, c->cfg.dxi0)) != WANDQS_OK ||
+        (s = driver_deposit(c)) != WANDQS_OK ||
+        (s = fill_f64(c, c->drv_eb, 6 * (size_t)c->cfg.driver_max, 0.0)) != WANDQS_OK)
+        return fail(c, s);
+    WQ_HIP(hipMemsetAsync(c->flags, 0, sizeof(int32_t), c->stream));
+    c->n_guess = 0;
+    c->tape_n = 0;
+    c->drv_active = true;
+    c->drv_dt = dt;
+    s = wandqs_run(c, n_slices, nullptr, h_infos);
+    c->drv_active = false;
+    if (s != WANDQS_OK) return s;
+    if ((s = driver_push(c, dt)) != WANDQS_OK) return fail(c, s);
     return WANDQS_OK;
 }
 

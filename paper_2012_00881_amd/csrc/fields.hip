@@ -57,13 +57,36 @@ __device__ bool in_disc(double L, double h, int a, int b, double x0, double y0, 
     return rx * rx + ry * ry <= r * r;
 }
 
+// Current of the driver macroparticles (time loop) at a node and slice
+// position xi: the fixed-point deposit planes interpolated linearly in xi
+// (zero outside them).
+struct DriverPlanes {
+    const unsigned long long* p;  // nullptr: no driver particles in this sweep
+    int nz;
+    double xi0, dz;
+    size_t plane;  // words per plane
+};
+
+__device__ __forceinline__ double driver_current(const DriverPlanes& D, size_t i, double xi) {
+    if (!D.p) return 0.0;
+    const double t = (xi - D.xi0) / D.dz;
+    const int m = (int)floor(t);
+    if (m < 0 || m > D.nz - 2) return 0.0;
+    const double a = t - m;
+    constexpr double kUnfix = 1.0 / 1099511627776.0;  // one unit of the planes: 2^-40
+    const double v0 = (double)(long long)D.p[(size_t)m * D.plane + i] * kUnfix;
+    const double v1 = (double)(long long)D.p[(size_t)(m + 1) * D.plane + i] * kUnfix;
+    return (1.0 - a) * v0 + a * v1;
+}
+
 // Total j_z on every node: plasma n*<p_z>/g = G/g - n* with G = n*<gamma> =
 // [n*(1 + g^2) + g^2 (Txx + Tyy)]/(2g) (eq. (9) and the gamma of Sec. III.A,
-// <p_perp^2> = g^2 <V^2>), plus the driver density at xi (luminal beam current).
+// <p_perp^2> = g^2 <V^2>), plus the frozen drivers' density at xi (luminal beam
+// current) and the driver macroparticles' current (time loop).
 __global__ void k_jz(int N, double L, double h, int pitch, const double* __restrict__ n,
                      const double* __restrict__ txx, const double* __restrict__ tyy,
                      const double* __restrict__ psi, const double* __restrict__ st, BeamSet beams,
-                     double* __restrict__ jz, int32_t* __restrict__ flags) {
+                     DriverPlanes drv, double* __restrict__ jz, int32_t* __restrict__ flags) {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
     if (a > N) return;
@@ -75,7 +98,8 @@ __global__ void k_jz(int N, double L, double h, int pitch, const double* __restr
         const double G = (n[i] * (1.0 + g * g) + g * g * (txx[i] + tyy[i])) / (2.0 * g);
         v = G / g - n[i];
     }
-    jz[i] = v + beam_density(beams, -L + a * h, -L + b * h, (size_t)b * (N + 1) + a, st[0]);
+    jz[i] = v + beam_density(beams, -L + a * h, -L + b * h, (size_t)b * (N + 1) + a, st[0]) +
+            driver_current(drv, i, st[0]);
 }
 
 // k2 = n* / g and the B_perp right-hand sides on the interior nodes:
@@ -250,10 +274,12 @@ wandqs_status rhs_EB(wandqs_ctx* c) {
 wandqs_status assemble(wandqs_ctx* c) {
     const Level& L0 = c->lev[0];
     {
+        const DriverPlanes drv{c->drv_active ? c->drv_planes : nullptr, c->drv_nz, c->cfg.driver_xi0,
+                               c->cfg.driver_dz, (size_t)(c->N + 1) * L0.pitch};
         ProfScope ps(c, "k_jz", (double)(c->N + 1) * (c->N + 1) * 40.0);
         WQ_KLAUNCH(ps, k_jz, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->L, c->h, L0.pitch,
-                           c->mom[0], c->mom[3], c->mom[5], c->fields[0], c->st, c->beamset, c->jz,
-                           c->flags);
+                           c->mom[0], c->mom[3], c->mom[5], c->fields[0], c->st, c->beamset, drv,
+                           c->jz, c->flags);
     }
     {
         ProfScope ps(c, "k_assemble", (double)(c->N + 1) * (c->N + 1) * 104.0);

@@ -214,6 +214,20 @@ struct wandqs_ctx {
     double* mom[6] = {};
     double* jz = nullptr;
     double* gpsi[2] = {};  // grad psi at the nodes (x, y), for the push
+    // time loop (driver_max > 0): driver state [8][driver_max], the wake at its
+    // mid-step positions [6][driver_max], the current planes (fixed point,
+    // [driver_nz][N+1][pitch]), the previous slice's grad psi, and the cold
+    // lattice the plasma restarts from at every time step
+    double* drv = nullptr;
+    double* drv_eb = nullptr;
+    unsigned long long* drv_planes = nullptr;
+    int64_t drv_n = 0;
+    int drv_nz = 0;
+    bool drv_active = false;  // inside wandqs_time_step's sweep
+    double drv_dt = 0.0;
+    double* gpsi_prev[2] = {};
+    double* lat[2] = {};
+    int32_t* lat_id = nullptr;
     double* k2lev = nullptr;  // k2 of the coarse-kernel levels (dense, concatenated)
     float* k2levf = nullptr;  // the same in float, and 1 / (4 + h_l^2 k2) in float
     float* idlevf = nullptr;
@@ -320,6 +334,11 @@ wandqs_status fill_f64(wandqs_ctx* c, double* p, size_t n, double v);
 wandqs_status extrapolate_guess(wandqs_ctx* c, int order);
 wandqs_status copy_d2d(wandqs_ctx* c, void* dst, const void* src, size_t bytes);
 wandqs_status probe_seed(wandqs_ctx* c, int k, double w, double* const* Fb);
+
+// time loop (driver.hip)
+wandqs_status driver_deposit(wandqs_ctx* c);
+wandqs_status driver_gather(wandqs_ctx* c, double dt);
+wandqs_status driver_push(wandqs_ctx* c, double dt);
 
 // adjoint (adjoint.hip); tape slot t holds the slice, tape index j its place
 // in the slice sequence (for probe seeds)

@@ -30,7 +30,8 @@ EXPORTS = ("wandqs_workspace_bytes", "wandqs_init", "wandqs_slice_step", "wandqs
            "wandqs_get_state", "wandqs_set_state", "wandqs_mg_solve", "wandqs_get_moments",
            "wandqs_num_particles", "wandqs_destroy", "wandqs_last_error", "wandqs_profile",
            "wandqs_profile_stats", "wandqs_backward", "wandqs_num_theta", "wandqs_tape_slices",
-           "wandqs_mg_solve_noalloc")
+           "wandqs_mg_solve_noalloc", "wandqs_driver_set", "wandqs_driver_get",
+           "wandqs_time_step")
 
 
 class Beam(C.Structure):
@@ -55,7 +56,8 @@ class Config(C.Structure):
                 ("probes", C.POINTER(Probe)), ("checkpoint_every", C.c_int32),
                 ("mg_inner_cycles", C.c_int32), ("mg_omega", C.c_double),
                 ("mg_omega_helm", C.c_double), ("adjoint_hold_dxi", C.c_int32),
-                ("pusher", C.c_int32)]
+                ("pusher", C.c_int32), ("driver_max", C.c_int32), ("driver_nz", C.c_int32),
+                ("driver_xi0", C.c_double), ("driver_dz", C.c_double)]
 
 
 class KernelStat(C.Structure):
@@ -94,6 +96,9 @@ def load():
     L.wandqs_mg_solve.argtypes = [vp, i32, vp, vp, vp, C.POINTER(i32), _dp]
     L.wandqs_get_moments.argtypes = [vp, vp]
     L.wandqs_mg_solve_noalloc.argtypes = [C.POINTER(Config), i32, vp, vp, vp, vp]
+    L.wandqs_driver_set.argtypes = [vp, C.c_int64, vp]
+    L.wandqs_driver_get.argtypes = [vp, vp]
+    L.wandqs_time_step.argtypes = [vp, C.c_double, i32, C.POINTER(SliceInfo)]
     L.wandqs_num_particles.argtypes = [vp]
     L.wandqs_num_particles.restype = C.c_int64
     L.wandqs_profile.argtypes = [vp, i32]
@@ -110,7 +115,8 @@ def load():
     for name in ("wandqs_workspace_bytes", "wandqs_init", "wandqs_slice_step", "wandqs_run",
                  "wandqs_get_state", "wandqs_set_state", "wandqs_mg_solve",
                  "wandqs_get_moments", "wandqs_profile", "wandqs_profile_stats",
-                 "wandqs_backward", "wandqs_mg_solve_noalloc"):
+                 "wandqs_backward", "wandqs_mg_solve_noalloc", "wandqs_driver_set",
+                 "wandqs_driver_get", "wandqs_time_step"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -160,6 +166,10 @@ def make_config(cfg: dict):
     c.adjoint_hold_dxi = int(cfg.get("adjoint_hold_dxi", 0))
     pu = cfg.get("pusher", "boris")
     c.pusher = PUSHERS[pu] if isinstance(pu, str) else int(pu)
+    c.driver_max = int(cfg.get("driver_max", 0))
+    c.driver_nz = int(cfg.get("driver_nz", 0))
+    c.driver_xi0 = float(cfg.get("driver_xi0", 0.0))
+    c.driver_dz = float(cfg.get("driver_dz", 0.0))
     return c, keep
 
 
@@ -324,6 +334,30 @@ class Simulation:
         if st not in (OK, E_NOCONV):
             self._check(st)
         return st, u, cyc.value, list(rel)[:nrhs]
+
+    # ------------------------------------------------------------ time loop
+    def driver_set(self, state):
+        """Driver macroparticles [8][n] (x, y, xi, px, py, pz, q/m, w)."""
+        t = self.torch
+        d = t.as_tensor(state, dtype=t.float64).to(self.device).contiguous()
+        assert d.dim() == 2 and d.shape[0] == 8
+        self._ndrv = int(d.shape[1])
+        self.stream.synchronize()
+        self._check(self.L.wandqs_driver_set(self.ctx, self._ndrv, C.c_void_p(d.data_ptr())))
+        self.stream.synchronize()
+
+    def driver_get(self):
+        out = self.torch.empty((8, getattr(self, "_ndrv", 0)), dtype=self.torch.float64,
+                               device=self.device)
+        self._check(self.L.wandqs_driver_get(self.ctx, C.c_void_p(out.data_ptr())))
+        return out
+
+    def time_step(self, dt: float, n_slices: int, infos: bool = False):
+        """One step of the time loop: a sweep of n_slices slices through the
+        cold plasma with the driver's current, then the driver pushed by dt."""
+        arr = (SliceInfo * max(1, n_slices))() if infos else None
+        self._check(self.L.wandqs_time_step(self.ctx, C.c_double(dt), int(n_slices), arr))
+        return [a.as_dict() for a in arr[:n_slices]] if infos else None
 
     def moments(self):
         out = self._nodes(9)

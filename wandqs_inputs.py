@@ -74,6 +74,60 @@ def plasma_lattice(n_cells: int, half_width: float, ppc_side: int, jitter: float
     return x, y, z.copy(), z.copy()
 
 
+def normal01(seed: int, count: int, start: int = 0) -> np.ndarray:
+    """Standard normal draws by the Box-Muller transform (G. E. P. Box and
+    M. E. Muller, Ann. Math. Statist. 29, 610 (1958)) of SplitMix64 pairs:
+    z = sqrt(-2 ln(1 - u1)) cos(2 pi u2)."""
+    u = uniform01(seed, 2 * count, start)
+    return np.sqrt(-2.0 * np.log1p(-u[0::2])) * np.cos(2.0 * np.pi * u[1::2])
+
+
+#: driver state rows: positions, momenta, charge-to-mass ratio (e/m_e units)
+#: and weight (number of particles in units of n0 k_p^-3)
+DRIVER_ROWS = ("x", "y", "xi", "px", "py", "pz", "qm", "w")
+
+
+def driver_gaussian(beam: dict, n: int, seed: int, gamma0: float = 2000.0, qm: float = -1.0):
+    """n driver macroparticles of equal weight sampled from the density
+    amp exp(-r^2/sr^2 - (xi - xc)^2/sz^2) of a Gaussian beam (x, y and xi each
+    normal with standard deviation sigma/sqrt 2), all moving along z with
+    p_z = sqrt(gamma0^2 - 1) (electrons: qm = -1).  Returns [8][n]."""
+    z = normal01(seed, 3 * n)
+    sr, sz = beam["sigma_r"] / np.sqrt(2.0), beam["sigma_z"] / np.sqrt(2.0)
+    total = beam["amp"] * np.pi * beam["sigma_r"] ** 2 * np.sqrt(np.pi) * beam["sigma_z"]
+    out = np.zeros((8, n))
+    out[0] = beam.get("x0", 0.0) + sr * z[0::3]
+    out[1] = beam.get("y0", 0.0) + sr * z[1::3]
+    out[2] = beam["xi_c"] + sz * z[2::3]
+    out[5] = np.sqrt(gamma0 * gamma0 - 1.0)
+    out[6] = qm
+    out[7] = total / n
+    return out
+
+
+def driver_lattice(beam: dict, n_cells: int, half_width: float, xi0: float, dz: float, nz: int,
+                   gamma0: float = 2000.0, qm: float = -1.0, cut: float = 1e-12):
+    """A quiet driver: one macroparticle on every transverse node x_a, y_b and
+    deposit plane xi_m = xi0 + m dz (m = 1 .. nz-2) where the Gaussian density
+    exceeds cut times its peak, weighted by that density times h^2 dz, so that
+    its deposit is the density itself on the nodes and planes.  Returns [8][n]."""
+    N, L = int(n_cells), float(half_width)
+    h = 2.0 * L / N
+    g = -L + h * np.arange(N + 1)
+    xis = xi0 + dz * np.arange(1, nz - 1)
+    XI, Y, X = np.meshgrid(xis, g, g, indexing="ij")
+    r2 = (X - beam.get("x0", 0.0)) ** 2 + (Y - beam.get("y0", 0.0)) ** 2
+    dens = beam["amp"] * np.exp(-r2 / beam["sigma_r"] ** 2 - (XI - beam["xi_c"]) ** 2 / beam["sigma_z"] ** 2)
+    keep = (dens > cut * beam["amp"]) & (np.abs(X) < L) & (np.abs(Y) < L)
+    n = int(keep.sum())
+    out = np.zeros((8, n))
+    out[0], out[1], out[2] = X[keep], Y[keep], XI[keep]
+    out[5] = np.sqrt(gamma0 * gamma0 - 1.0)
+    out[6] = qm
+    out[7] = dens[keep] * h * h * dz
+    return out
+
+
 def gauss_beam(amp, sigma_r, sigma_z, xi_c, x0=0.0, y0=0.0):
     return dict(kind="gauss", amp=float(amp), sigma_r=float(sigma_r), sigma_z=float(sigma_z),
                 xi_c=float(xi_c), x0=float(x0), y0=float(y0))
