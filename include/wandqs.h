@@ -127,9 +127,11 @@ typedef struct {
                                  K recompute slots); 0 = no tape */
     int32_t mg_inner_cycles;  /* WANDQS_MIXED: FP32 V-cycles per FP64 defect correction
                                  (0: 1, the fastest measured at C5).  The mixed form keeps the residual, the
-                                 correction sum u += e and the coarsest (2x2) solve in
-                                 FP64 and smooths/transfers the error equation in FP32;
-                                 particles stay FP64.  Each "V-cycle" counted in
+                                 correction sum u += e and the coarsest-grid solve (the
+                                 exact sine-transform solve of the Poisson V-cycle's last
+                                 level; the Helmholtz levels <= 64^2) in FP64 and
+                                 smooths/transfers the error equation on the levels
+                                 above in FP32; particles stay FP64.  Each "V-cycle" counted in
                                  wandqs_slice_info.vcycles is then one outer iteration. */
     double mg_omega;          /* relaxation factor om of the smoothing sweeps of the
                                  Poisson solves (psi, Ez, Bz): each node of a
