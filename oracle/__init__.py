@@ -48,7 +48,8 @@ class Cfg(C.Structure):
                 ("mg_max_cycles", C.c_int), ("nu_pre", C.c_int), ("nu_post", C.c_int),
                 ("n_beams", C.c_int), ("beams", C.POINTER(Beam)), ("pusher", C.c_int),
                 ("drv_planes", _dp), ("drv_nz", C.c_int), ("drv_xi0", C.c_double),
-                ("drv_dz", C.c_double)]
+                ("drv_dz", C.c_double), ("las_env", _dp), ("las_nz", C.c_int),
+                ("las_k0", C.c_double)]
 
 
 class Info(C.Structure):
@@ -111,6 +112,37 @@ class Oracle:
         c.n_beams, c.beams = len(cfg["beams"]), beams
         c.pusher = PUSHERS[cfg.get("pusher", "boris")]
         self.c = c
+        self.laser_env = None
+
+    # ----------------------------------------------------------------- laser
+    def set_laser(self, env, k0):
+        """Laser envelope A-hat on planes xi_m = m dxi0: complex [nz][N+1][N+1]
+        (None: no laser); k0 = omega0/omega_p."""
+        if env is None:
+            self.laser_env = None
+            self.c.las_env, self.c.las_nz = None, 0
+            return
+        e = np.ascontiguousarray(env, dtype=np.complex128).reshape(-1, self.N + 1, self.N + 1)
+        self.laser_env = e
+        self.c.las_env = e.ctypes.data_as(_dp)
+        self.c.las_nz, self.c.las_k0 = e.shape[0], float(k0)
+
+    def laser_advance(self, dt, env, chi=None, k0=None):
+        """Advance envelope planes env (complex [nz][N+1][N+1]) by dt with the
+        susceptibility chi [nz][N+1][N+1] (None: vacuum); returns (status,
+        new planes, multigrid cycles per plane)."""
+        e = np.ascontiguousarray(env, dtype=np.complex128).reshape(-1, self.N + 1, self.N + 1)
+        nz = e.shape[0]
+        out = np.zeros_like(e)
+        ch = None if chi is None else _f64(chi).reshape(nz, -1)
+        cyc = np.zeros(nz, dtype=np.int32)
+        c = Cfg.from_buffer_copy(self.c)
+        if k0 is not None:
+            c.las_k0 = float(k0)
+        st = lib().oracle_laser_advance(C.byref(c), C.c_double(dt), nz, e.ctypes.data_as(_dp),
+                                        _p(ch), out.ctypes.data_as(_dp),
+                                        cyc.ctypes.data_as(C.POINTER(C.c_int)))
+        return st, out, cyc
 
     # ---------------------------------------------------------------- pieces
     def deposit(self, x, y, q=None):
@@ -138,14 +170,15 @@ class Oracle:
                                    _p(_f64(Ez)), _p(_f64(Bz)), _p(out))
         return st, out.reshape(4, self.N + 1, self.N + 1)
 
-    def push_fields(self, dxi, x, y, px, py, fields):
-        """The particle advance of a slice from its solved fields (the
-        configuration's pusher); returns (status, x, y, px, py, vmax)."""
+    def push_fields(self, dxi, x, y, px, py, fields, xi=0.0):
+        """The particle advance of a slice at xi from its solved fields (the
+        configuration's pusher, a laser's ponderomotive terms at xi); returns
+        (status, x, y, px, py, vmax)."""
         arrs = [_f64(a).copy() for a in (x, y, px, py)]
         F = _f64(fields).reshape(5, -1)
         vm = C.c_double(0.0)
-        st = lib().oracle_push_fields(C.byref(self.c), C.c_double(dxi), arrs[0].size, _p(F),
-                                      *[_p(a) for a in arrs], C.byref(vm))
+        st = lib().oracle_push_fields(C.byref(self.c), C.c_double(xi), C.c_double(dxi),
+                                      arrs[0].size, _p(F), *[_p(a) for a in arrs], C.byref(vm))
         return (st, *arrs, vm.value)
 
     # ------------------------------------------------------------ driver
@@ -170,8 +203,9 @@ class Oracle:
     def time_step(self, state, drv, n_slices, dt, nz, xi0, dz, keep_fields=False):
         """One step of the time loop: the driver's current on nz planes, a sweep
         of n_slices slices through `state` (advanced in place), the driver
-        (drv [8][n], advanced in place) pushed by dt.  Returns dict(status,
-        infos[, xi, fields])."""
+        (drv [8][n], advanced in place) pushed by dt.  With a laser set
+        (set_laser) its envelope is advanced by dt in the same sweep and
+        replaces the one set.  Returns dict(status, infos[, xi, fields])."""
         state["fields"] = _f64(state["fields"]).reshape(5, self.N + 1, self.N + 1)
         d = _f64(drv).reshape(8, -1)
         xi = C.c_double(state["xi"])
@@ -179,12 +213,16 @@ class Oracle:
         hx = np.zeros(n_slices)
         hF = np.zeros((n_slices, 5, self.nn)) if keep_fields else None
         infos = (Info * n_slices)()
+        nxt = None if self.laser_env is None else np.zeros_like(self.laser_env)
         st = lib().oracle_time_step(C.byref(self.c), state["x"].size, _p(state["x"]),
                                     _p(state["y"]), _p(state["px"]), _p(state["py"]),
                                     _p(state["fields"]), C.byref(xi), C.byref(dxi), int(n_slices),
                                     d.shape[1], _p(d), int(nz), C.c_double(xi0), C.c_double(dz),
-                                    C.c_double(dt), _p(hx), _p(hF), infos)
+                                    C.c_double(dt), _p(hx), _p(hF), infos,
+                                    None if nxt is None else nxt.ctypes.data_as(_dp))
         state["xi"], state["dxi"] = xi.value, dxi.value
+        if nxt is not None and st == OK:
+            self.set_laser(nxt, self.c.las_k0)
         out = dict(status=st, infos=list(infos), xi=hx)
         if keep_fields:
             out["fields"] = hF.reshape(n_slices, 5, self.N + 1, self.N + 1)

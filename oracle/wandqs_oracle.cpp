@@ -45,6 +45,7 @@
 #include <limits>
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdint>
 #include <cstring>
 #include <vector>
@@ -79,6 +80,12 @@ typedef struct {
     const double* drv_planes;
     int drv_nz;
     double drv_xi0, drv_dz;
+    /* laser envelope A-hat of eq. (20) on las_nz planes xi_m = m dxi0, complex
+     * [las_nz][nn] stored as (re, im) pairs; NULL: no laser.  las_k0 is the
+     * carrier wavenumber k0 = omega0/omega_p. */
+    const double* las_env;
+    int las_nz;
+    double las_k0;
 } oracle_cfg;
 
 typedef struct {
@@ -165,6 +172,11 @@ inline int ncomp(double) { return 1; }
 template <int K> int ncomp(const Dual<K>&) { return K + 1; }
 inline double comp(double x, int) { return x; }
 template <int K> double comp(const Dual<K>& x, int c) { return c == 0 ? x.v : x.d[c - 1]; }
+/* complex values (the laser envelope): the real and imaginary parts are the
+ * two components the multigrid's stop rule checks */
+using cplx = std::complex<double>;
+inline int ncomp(const cplx&) { return 2; }
+inline double comp(const cplx& x, int c) { return c == 0 ? x.real() : x.imag(); }
 
 /* ------------------------------------------------------------------ grid -- */
 
@@ -492,6 +504,64 @@ double driver_current(const oracle_cfg& c, int i, int nn, double xi) {
     return (1.0 - a) * c.drv_planes[(size_t)m * nn + i] + a * c.drv_planes[(size_t)(m + 1) * nn + i];
 }
 
+/* |A-hat|^2 of the laser envelope on the nodes at slice position xi: the
+ * planes xi_m = m dxi0 around xi interpolated linearly in xi, planes outside
+ * [0, las_nz) taken as zero.  Empty without a laser. */
+std::vector<double> laser_a2(const Grid& g, const oracle_cfg& c, double xi) {
+    if (!c.las_env || c.las_nz < 1) return {};
+    const int nn = g.nn();
+    std::vector<double> out(nn, 0.0);
+    const double t = xi / c.dxi0;
+    const double mf = std::floor(t);
+    const double a = t - mf;
+    const double w[2] = {1.0 - a, a};
+    for (int k = 0; k < 2; ++k) {
+        const double q = mf + k;
+        if (q < 0.0 || q >= c.las_nz) continue;
+        const double* e = c.las_env + 2 * (size_t)q * nn;
+        for (int i = 0; i < nn; ++i) out[i] += w[k] * (e[2 * i] * e[2 * i] + e[2 * i + 1] * e[2 * i + 1]);
+    }
+    return out;
+}
+
+/* ------------------------------------------------------ laser envelope -- */
+
+/* One time step dt of the envelope equation (eq. (20)) at one xi-plane.
+ * With a0 = A-hat(t, xi_j), a1 = A-hat(t + dt, xi_j) and p0, p1 the same on
+ * the plane ahead, xi_{j-1} = xi_j - dxi (zero ahead of the first plane),
+ * eq. (20) is taken centred in t,
+ *   2 i k0 (a1 - a0)/dt - 2 [(a1 - a0) - (p1 - p0)]/(dt dxi)
+ *       + L_h (a1 + a0)/2 = chi (a1 + a0)/2,
+ * the xi-derivative backward (the plane ahead is already at t + dt when the
+ * sweep reaches plane j).  For a1 it is the complex Helmholtz problem
+ *   L_h a1 - (chi + beta - i gam) a1 = (chi - beta + i gam) a0 - L_h a0 - beta (p1 - p0),
+ * beta = 4/(dt dxi), gam = 4 k0/dt, with a1 = 0 on the boundary, solved by the
+ * multigrid above from the guess a0.  chi (the plasma susceptibility n* / (1+psi)
+ * at the nodes) may be NULL (vacuum). */
+int laser_plane_advance(const Grid& g, const oracle_cfg& c, double dt, const double* chi,
+                        const cplx* a0, const cplx* p0, const cplx* p1, cplx* a1, int* cycles,
+                        double* rel) {
+    const int nn = g.nn();
+    const double beta = 4.0 / (dt * c.dxi0), gam = 4.0 * c.las_k0 / dt;
+    const cplx ig(0.0, gam);
+    std::vector<cplx> k2(nn, cplx(0.0)), f(nn, cplx(0.0));
+    const double h2 = g.h * g.h;
+    for (int b = 0; b <= g.N; ++b)
+        for (int a = 0; a <= g.N; ++a) {
+            const int i = g.id(a, b);
+            const double x = chi ? chi[i] : 0.0;
+            k2[i] = x + beta - ig;
+            if (a == 0 || b == 0 || a == g.N || b == g.N) continue;
+            const cplx lap = (a0[g.id(a - 1, b)] + a0[g.id(a + 1, b)] + a0[g.id(a, b - 1)] +
+                              a0[g.id(a, b + 1)] - 4.0 * a0[i]) / h2;
+            const cplx dp = (p1 ? p1[i] : cplx(0.0)) - (p0 ? p0[i] : cplx(0.0));
+            f[i] = (x - beta + ig) * a0[i] - lap - beta * dp;
+        }
+    std::copy(a0, a0 + nn, a1);
+    return mg_solve<cplx>(g.N, g.h, k2.data(), f.data(), a1, c.mg_rtol, c.mg_atol, c.mg_max_cycles,
+                          c.nu_pre, c.nu_post, cycles, rel);
+}
+
 /* ----------------------------------------------------------- slice step -- */
 
 template <class T>
@@ -500,12 +570,14 @@ struct MomentsT { /* node arrays deposited from the particles of one slice */
 };
 using Moments = MomentsT<double>;
 
-/* Assembly of the B-perp system (Sec. III.B eqs. (18)-(19) with A-hat = 0, i.e.
- * rows 4-5 of eq. (30)):  G = n*<gamma> (eq. (9) and the gamma of Sec. III.A),
- * plasma j_z = n*<p_z>/(1+psi) = G/g - n*, total j_z adds the beam, k2 = n* / g,
- * and the right-hand sides
+/* Assembly of the B-perp system (Sec. III.B eqs. (18)-(19), i.e. rows 4-5 of
+ * eq. (30)):  G = n*<gamma> (eq. (9) and the gamma of Sec. III.A, with
+ * a2 = |A-hat|^2 of a laser envelope, zero without one), plasma
+ * j_z = n*<p_z>/(1+psi) = G/g - n*, total j_z adds the beam and the driver
+ * particles, k2 = n* / g, and the right-hand sides
  *   f_Bx =  S_y,  f_By = -S_x   (from -e_z x S),
- *   S = grad j_z - div T + (e_z x j) Bz/g + G grad psi/g^2 - j Ez/g - T.grad psi/g.
+ *   S = grad j_z - div T + (e_z x j) Bz/g + (G grad psi - n* grad(a2/4))/g^2
+ *       - j Ez/g - T.grad psi/g.
  * Returns ORC_NONPHYS if g <= 0 at a node that holds plasma. */
 template <class T>
 int assemble(const Grid& g, const oracle_cfg& c, double xi, const MomentsT<T>& m,
@@ -514,6 +586,8 @@ int assemble(const Grid& g, const oracle_cfg& c, double xi, const MomentsT<T>& m
              const T* theta = nullptr) {
     const int nn = g.nn();
     std::vector<T> G(nn, T(0.0)), jz(nn, T(0.0));
+    const std::vector<double> A2 = laser_a2(g, c, xi);
+    const bool las = !A2.empty();
     int nonphys = 0;
 #pragma omp parallel for schedule(static) reduction(| : nonphys)
     for (int b = 0; b <= g.N; ++b)
@@ -523,8 +597,10 @@ int assemble(const Grid& g, const oracle_cfg& c, double xi, const MomentsT<T>& m
             T plasma_jz(0.0);
             if (val(m.n[i]) > 0.0) {
                 if (val(gg) <= 0.0) nonphys = 1;
-                /* <gamma> = (1 + <p_perp^2> + g^2)/(2g) with <p_perp^2> = g^2 <V^2> */
-                G[i] = (m.n[i] * (1.0 + gg * gg) + gg * gg * (m.txx[i] + m.tyy[i])) / (2.0 * gg);
+                /* <gamma> = (1 + <p_perp^2> + g^2 + a2/2)/(2g) with <p_perp^2> = g^2 <V^2> */
+                const double a2 = las ? A2[i] : 0.0;
+                G[i] = (m.n[i] * (1.0 + gg * gg + 0.5 * a2) + gg * gg * (m.txx[i] + m.tyy[i])) /
+                       (2.0 * gg);
                 plasma_jz = G[i] / gg - m.n[i];
             }
             jz[i] = plasma_jz + beam_density(c, theta, g.xa(a), g.xa(b), xi) +
@@ -553,6 +629,10 @@ int assemble(const Grid& g, const oracle_cfg& c, double xi, const MomentsT<T>& m
                       (G[i] / (gg * gg) - m.tyy[i] / gg) * py - (m.txy[i] / gg) * px;
                 fy += (m.jy[i] * Bz[i] + m.jx[i] * Ez[i]) / gg -
                       (G[i] / (gg * gg) - m.txx[i] / gg) * px + (m.txy[i] / gg) * py;
+                if (las) { /* the ponderomotive term -n* grad(a2/4)/g^2 of S */
+                    fx -= m.n[i] * (0.25 * Dy(g, A2.data(), a, b)) / (gg * gg);
+                    fy += m.n[i] * (0.25 * Dx(g, A2.data(), a, b)) / (gg * gg);
+                }
             }
             fBx[i] = fx;
             fBy[i] = fy;
@@ -581,18 +661,22 @@ void psi_gradient(const Grid& g, const T* psi, std::vector<T>& gx, std::vector<T
 }
 
 /* Boris-like advance of one plasma electron over dxi with the fields frozen at
- * the current slice (Sec. III.A eqs. (6)-(7), A-hat = 0):
- *   dr/dxi = V = p/g,   dp/dxi = gamma grad psi/g + (e_z x V) Bz + e_z x B_perp,
- *   gamma = (1 + p^2 + g^2)/(2g)  taken at the old momentum.
- * Half kick with F = gamma grad psi/g + e_z x B_perp, rotation by the
- * (e_z x V) Bz term (angle 2 atan(Bz dxi / 2g)), half kick, drift with the
- * new momentum, specular reflection at the walls x, y = +-L. */
+ * the current slice (Sec. III.A eqs. (6)-(7)):
+ *   dr/dxi = V = p/g,
+ *   dp/dxi = (gamma grad psi - grad(a2/4))/g + (e_z x V) Bz + e_z x B_perp,
+ *   gamma = (1 + p^2 + g^2 + a2/2)/(2g)  taken at the old momentum,
+ * a2 = |A-hat|^2 of a laser envelope and (ax, ay) its gradient, gathered at the
+ * particle (zero without a laser).
+ * Half kick with F = (gamma grad psi - grad(a2/4))/g + e_z x B_perp, rotation
+ * by the (e_z x V) Bz term (angle 2 atan(Bz dxi / 2g)), half kick, drift with
+ * the new momentum, specular reflection at the walls x, y = +-L. */
 template <class T>
 void push_one(double L, double dxi, const T& g_i, const T& gx, const T& gy, const T& Bx,
-              const T& By, const T& Bz, T& x, T& y, T& px, T& py) {
-    T gamma = (1.0 + px * px + py * py + g_i * g_i) / (2.0 * g_i);
-    T Fx = gamma * gx / g_i - By;
-    T Fy = gamma * gy / g_i + Bx;
+              const T& By, const T& Bz, T& x, T& y, T& px, T& py, double a2 = 0.0,
+              double ax = 0.0, double ay = 0.0) {
+    T gamma = (1.0 + px * px + py * py + g_i * g_i + 0.5 * a2) / (2.0 * g_i);
+    T Fx = (gamma * gx - 0.25 * ax) / g_i - By;
+    T Fy = (gamma * gy - 0.25 * ay) / g_i + Bx;
     T mx = px + 0.5 * dxi * Fx;
     T my = py + 0.5 * dxi * Fy;
     T t = Bz * dxi / (2.0 * g_i);
@@ -611,28 +695,41 @@ void push_one(double L, double dxi, const T& g_i, const T& gx, const T& gy, cons
     if (val(y) < -L) { y = -2.0 * L - y; py = -py; }
 }
 
+/* A laser envelope's |A-hat|^2 on the nodes of a slice and its node gradient
+ * (the same differences as psi's); all empty without a laser. */
+struct LaserNodes {
+    std::vector<double> a2, ax, ay;
+    bool on() const { return !a2.empty(); }
+};
+
 /* Right-hand side of the plasma electron's equations of motion in xi with the
- * fields frozen at the slice (Sec. III.A eqs. (6)-(7), A-hat = 0), at the
- * position and momentum s = (x, y, p_x, p_y):
+ * fields frozen at the slice (Sec. III.A eqs. (6)-(7)), at the position and
+ * momentum s = (x, y, p_x, p_y):
  *   dr/dxi = V = p/g,
- *   dp/dxi = gamma grad psi/g + (e_z x V) B_z + e_z x B_perp,
- *   g = 1 + psi and gamma = (1 + p^2 + g^2)/(2g),
+ *   dp/dxi = (gamma grad psi - grad(a2/4))/g + (e_z x V) B_z + e_z x B_perp,
+ *   g = 1 + psi and gamma = (1 + p^2 + g^2 + a2/2)/(2g),
  * every field gathered (CIC) at the position itself.  Returns false when
  * g <= 0 there. */
 template <class T>
 bool eom_rhs(const Grid& g, const T* psi, const T* gx, const T* gy, const T* Bx, const T* By,
-             const T* Bz, const T (&s)[4], T (&d)[4]) {
+             const T* Bz, const LaserNodes& las, const T (&s)[4], T (&d)[4]) {
     const T gg = 1.0 + gather1(g, psi, s[0], s[1]);
     if (!(val(gg) > 0.0)) return false;
     const T Gx = gather1(g, gx, s[0], s[1]), Gy = gather1(g, gy, s[0], s[1]);
     const T bx = gather1(g, Bx, s[0], s[1]), by = gather1(g, By, s[0], s[1]);
     const T bz = gather1(g, Bz, s[0], s[1]);
-    const T gamma = (1.0 + s[2] * s[2] + s[3] * s[3] + gg * gg) / (2.0 * gg);
+    T a2(0.0), ax(0.0), ay(0.0);
+    if (las.on()) {
+        a2 = gather1(g, las.a2.data(), val(s[0]), val(s[1]));
+        ax = gather1(g, las.ax.data(), val(s[0]), val(s[1]));
+        ay = gather1(g, las.ay.data(), val(s[0]), val(s[1]));
+    }
+    const T gamma = (1.0 + s[2] * s[2] + s[3] * s[3] + gg * gg + 0.5 * a2) / (2.0 * gg);
     const T vx = s[2] / gg, vy = s[3] / gg;
     d[0] = vx;
     d[1] = vy;
-    d[2] = gamma * Gx / gg - vy * bz - by;
-    d[3] = gamma * Gy / gg + vx * bz + bx;
+    d[2] = (gamma * Gx - 0.25 * ax) / gg - vy * bz - by;
+    d[3] = (gamma * Gy - 0.25 * ay) / gg + vx * bz + bx;
     return true;
 }
 
@@ -644,24 +741,25 @@ bool eom_rhs(const Grid& g, const T* psi, const T* gx, const T* gy, const T* Bx,
  * end position as in push_one.  Returns false when a stage meets g <= 0. */
 template <class T>
 bool push_rk(const Grid& g, int order, double dxi, const T* psi, const T* gx, const T* gy,
-             const T* Bx, const T* By, const T* Bz, T& x, T& y, T& px, T& py) {
+             const T* Bx, const T* By, const T* Bz, const LaserNodes& las, T& x, T& y, T& px,
+             T& py) {
     const T s0[4] = {x, y, px, py};
     T k1[4], k2[4], k3[4], k4[4], s[4];
-    bool ok = eom_rhs(g, psi, gx, gy, Bx, By, Bz, s0, k1);
+    bool ok = eom_rhs(g, psi, gx, gy, Bx, By, Bz, las, s0, k1);
     T out[4];
     if (order == PUSH_RK1) {
         for (int q = 0; q < 4; ++q) out[q] = s0[q] + dxi * k1[q];
     } else if (order == PUSH_RK2) {
         for (int q = 0; q < 4; ++q) s[q] = s0[q] + (0.5 * dxi) * k1[q];
-        ok = eom_rhs(g, psi, gx, gy, Bx, By, Bz, s, k2) && ok;
+        ok = eom_rhs(g, psi, gx, gy, Bx, By, Bz, las, s, k2) && ok;
         for (int q = 0; q < 4; ++q) out[q] = s0[q] + dxi * k2[q];
     } else {
         for (int q = 0; q < 4; ++q) s[q] = s0[q] + (0.5 * dxi) * k1[q];
-        ok = eom_rhs(g, psi, gx, gy, Bx, By, Bz, s, k2) && ok;
+        ok = eom_rhs(g, psi, gx, gy, Bx, By, Bz, las, s, k2) && ok;
         for (int q = 0; q < 4; ++q) s[q] = s0[q] + (0.5 * dxi) * k2[q];
-        ok = eom_rhs(g, psi, gx, gy, Bx, By, Bz, s, k3) && ok;
+        ok = eom_rhs(g, psi, gx, gy, Bx, By, Bz, las, s, k3) && ok;
         for (int q = 0; q < 4; ++q) s[q] = s0[q] + dxi * k3[q];
-        ok = eom_rhs(g, psi, gx, gy, Bx, By, Bz, s, k4) && ok;
+        ok = eom_rhs(g, psi, gx, gy, Bx, By, Bz, las, s, k4) && ok;
         for (int q = 0; q < 4; ++q)
             out[q] = s0[q] + (dxi / 6.0) * (k1[q] + 2.0 * k2[q] + 2.0 * k3[q] + k4[q]);
     }
@@ -791,15 +889,19 @@ int slice_step_t(const oracle_cfg* c, int P, T* x, T* y, T* px, T* py, T* pz, T*
         for (int k = 0; k < 4; ++k) std::copy(arr[k]->begin(), arr[k]->end(), extra_out + k * nn);
     }
 
-    /* 7-8. gather grad psi, B and push (Push_Trajectory), Vmax after the push. */
+    /* 7-8. gather grad psi, B (and a laser's a2 = |A-hat|^2 with its gradient)
+     *      and push (Push_Trajectory), Vmax after the push. */
     std::vector<T> gx, gy;
     psi_gradient<T>(g, psi, gx, gy);
+    LaserNodes las;
+    las.a2 = laser_a2(g, *c, *xi);
+    if (las.on()) psi_gradient<double>(g, las.a2.data(), las.ax, las.ay);
     double vmax = 0.0;
     if (c->pusher != PUSH_BORIS) {
         int rk_nonphys = 0;
 #pragma omp parallel for schedule(static) reduction(max : vmax) reduction(| : rk_nonphys)
         for (int i = 0; i < P; ++i) {
-            if (!push_rk(g, c->pusher, *dxi, psi, gx.data(), gy.data(), Bx, By, Bz, x[i], y[i],
+            if (!push_rk(g, c->pusher, *dxi, psi, gx.data(), gy.data(), Bx, By, Bz, las, x[i], y[i],
                          px[i], py[i]))
                 rk_nonphys = 1;
             double v = val(sqrt(px[i] * px[i] + py[i] * py[i]) / gi[i]);
@@ -816,7 +918,14 @@ int slice_step_t(const oracle_cfg* c, int P, T* x, T* y, T* px, T* py, T* pz, T*
             T bz = gather1(g, Bz, x[i], y[i]);
             T ez = pz ? gather1(g, Ez, x[i], y[i]) : T(0.0);
             T p0x = px[i], p0y = py[i];
-            push_one(g.L, *dxi, gi[i], Gx, Gy, bx, by, bz, x[i], y[i], px[i], py[i]);
+            double a2 = 0.0, ax = 0.0, ay = 0.0;
+            if (las.on()) {
+                const double xv = val(x[i]), yv = val(y[i]);
+                a2 = gather1(g, las.a2.data(), xv, yv);
+                ax = gather1(g, las.ax.data(), xv, yv);
+                ay = gather1(g, las.ay.data(), xv, yv);
+            }
+            push_one(g.L, *dxi, gi[i], Gx, Gy, bx, by, bz, x[i], y[i], px[i], py[i], a2, ax, ay);
             if (pz) { /* dp_z/dxi = -gamma Ez/g - Vx By + Vy Bx at the mean momentum */
                 T mx = 0.5 * (p0x + px[i]), my = 0.5 * (p0y + py[i]);
                 T gam = (1.0 + mx * mx + my * my + gi[i] * gi[i]) / (2.0 * gi[i]);
@@ -908,17 +1017,21 @@ int oracle_push(double L, double dxi, int P, const double* g_i, const double* gx
     return ORC_OK;
 }
 
-/* The particle advance of a slice given its solved fields [5][nn] (psi, Ez,
- * Bz, Bx, By): node gradient of psi, g_i = 1 + psi(r_i), then the pusher of
- * the configuration (Boris-like or Runge-Kutta), walls included.  vmax (may be
- * NULL) receives max |p_new|/g_i. */
-int oracle_push_fields(const oracle_cfg* c, double dxi, int P, const double* fields, double* x,
-                       double* y, double* px, double* py, double* vmax) {
+/* The particle advance of a slice at xi given its solved fields [5][nn] (psi,
+ * Ez, Bz, Bx, By): node gradient of psi, g_i = 1 + psi(r_i), then the pusher
+ * of the configuration (Boris-like or Runge-Kutta), walls included, with the
+ * laser envelope's ponderomotive terms at xi when the configuration has one.
+ * vmax (may be NULL) receives max |p_new|/g_i. */
+int oracle_push_fields(const oracle_cfg* c, double xi, double dxi, int P, const double* fields,
+                       double* x, double* y, double* px, double* py, double* vmax) {
     Grid g(c->n_cells, c->half_width);
     const int nn = g.nn();
     const double *psi = fields, *Bz = fields + 2 * nn, *Bx = fields + 3 * nn, *By = fields + 4 * nn;
     std::vector<double> gx, gy;
     psi_gradient(g, psi, gx, gy);
+    LaserNodes las;
+    las.a2 = laser_a2(g, *c, xi);
+    if (las.on()) psi_gradient<double>(g, las.a2.data(), las.ax, las.ay);
     double vm = 0.0;
     int nonphys = 0;
 #pragma omp parallel for schedule(static) reduction(max : vm) reduction(| : nonphys)
@@ -926,10 +1039,16 @@ int oracle_push_fields(const oracle_cfg* c, double dxi, int P, const double* fie
         const double gi = 1.0 + gather1(g, psi, x[i], y[i]);
         if (!(gi > 0.0)) nonphys = 1;
         if (c->pusher == PUSH_BORIS) {
+            double a2 = 0.0, ax = 0.0, ay = 0.0;
+            if (las.on()) {
+                a2 = gather1(g, las.a2.data(), x[i], y[i]);
+                ax = gather1(g, las.ax.data(), x[i], y[i]);
+                ay = gather1(g, las.ay.data(), x[i], y[i]);
+            }
             push_one(g.L, dxi, gi, gather1(g, gx.data(), x[i], y[i]), gather1(g, gy.data(), x[i], y[i]),
                      gather1(g, Bx, x[i], y[i]), gather1(g, By, x[i], y[i]), gather1(g, Bz, x[i], y[i]),
-                     x[i], y[i], px[i], py[i]);
-        } else if (!push_rk(g, c->pusher, dxi, psi, gx.data(), gy.data(), Bx, By, Bz, x[i], y[i],
+                     x[i], y[i], px[i], py[i], a2, ax, ay);
+        } else if (!push_rk(g, c->pusher, dxi, psi, gx.data(), gy.data(), Bx, By, Bz, las, x[i], y[i],
                             px[i], py[i])) {
             nonphys = 1;
         }
@@ -994,7 +1113,7 @@ int oracle_run_tangent(const oracle_cfg* c, int P, double* x, double* y, double*
     constexpr int KD = 8;
     using D = Dual<KD>;
     if (K < 1 || K > KD || P < 0) return ORC_INVALID;
-    if (c->pusher != PUSH_BORIS) return ORC_INVALID;
+    if (c->pusher != PUSH_BORIS || c->las_env) return ORC_INVALID;
     Grid g(c->n_cells, c->half_width);
     const int nn = g.nn();
     int nth = 0;
@@ -1236,19 +1355,54 @@ int oracle_driver_push(const oracle_cfg* c, double dt, int n, double* st, int ns
     return ORC_OK;
 }
 
+/* Envelope planes env_in [nz][nn] (complex, (re, im) pairs) at time t
+ * advanced by dt into env_out (same layout), plane after plane from the front
+ * (laser_plane_advance), with the susceptibility chi [nz][nn] (NULL: vacuum).
+ * The configuration gives k0, the plane spacing dxi0 and the multigrid's stop
+ * rule; cycles [nz] (may be NULL) receives each plane's cycle count. */
+int oracle_laser_advance(const oracle_cfg* c, double dt, int nz, const double* env_in,
+                         const double* chi, double* env_out, int* cycles) {
+    Grid g(c->n_cells, c->half_width);
+    const int nn = g.nn();
+    const cplx* A0 = reinterpret_cast<const cplx*>(env_in);
+    cplx* A1 = reinterpret_cast<cplx*>(env_out);
+    for (int j = 0; j < nz; ++j) {
+        int cyc = 0;
+        double rel = 0.0;
+        const int st = laser_plane_advance(
+            g, *c, dt, chi ? chi + (size_t)j * nn : nullptr, A0 + (size_t)j * nn,
+            j ? A0 + (size_t)(j - 1) * nn : nullptr, j ? A1 + (size_t)(j - 1) * nn : nullptr,
+            A1 + (size_t)j * nn, &cyc, &rel);
+        if (cycles) cycles[j] = cyc;
+        if (st != ORC_OK) return st;
+    }
+    return ORC_OK;
+}
+
 /* One step of the time loop (Algorithm 1, outer loop): the driver's current
  * on nz planes (xi0, dz), a sweep of n_slices slices through the plasma given
  * (normally the cold plasma at xi = 0 with zero fields, advanced in place)
  * with that current in j_z, then the driver advanced by dt through the wake
  * of those slices.  xi_hist [n_slices] and fields_hist [n_slices][5][nn] (may
- * be NULL) receive the slices. */
+ * be NULL) receive the slices.
+ * With a laser envelope in the configuration (c->las_env, the planes at t)
+ * the plasma sees it, and env_next (non-NULL, [las_nz][nn] complex) receives
+ * the planes at t + dt: each plane j is advanced (laser_plane_advance) right
+ * after slice j, with that slice's susceptibility chi = n* / (1+psi) (the k2 of
+ * its B-perp system).  This needs fixed steps (adaptive = 0, so that slice j
+ * lies on plane j) and n_slices >= las_nz. */
 int oracle_time_step(const oracle_cfg* c, int P, double* x, double* y, double* px, double* py,
                      double* fields, double* xi, double* dxi, int n_slices, int n_drv,
                      double* drv, int nz, double xi0, double dz, double dt, double* xi_hist,
-                     double* fields_hist, oracle_info* infos) {
+                     double* fields_hist, oracle_info* infos, double* env_next) {
     Grid g(c->n_cells, c->half_width);
     const int nn = g.nn();
+    const bool las = c->las_env && env_next;
+    if (las && (c->adaptive || n_slices < c->las_nz)) return ORC_INVALID;
     std::vector<double> planes((size_t)nz * nn), hx(n_slices), hF((size_t)n_slices * 5 * nn);
+    std::vector<double> extra(las ? 4 * (size_t)nn : 0);
+    const cplx* A0 = reinterpret_cast<const cplx*>(c->las_env);
+    cplx* A1 = reinterpret_cast<cplx*>(env_next);
     oracle_driver_deposit(c, n_drv, drv, nz, xi0, dz, planes.data());
     oracle_cfg cc = *c;
     cc.drv_planes = planes.data();
@@ -1259,9 +1413,15 @@ int oracle_time_step(const oracle_cfg* c, int P, double* x, double* y, double* p
     for (int j = 0; j < n_slices && status == ORC_OK; ++j) {
         hx[j] = *xi;
         oracle_info inf;
-        status = oracle_slice_step(&cc, P, x, y, px, py, nullptr, fields, xi, dxi, &inf, nullptr, nullptr);
+        status = oracle_slice_step(&cc, P, x, y, px, py, nullptr, fields, xi, dxi, &inf, nullptr,
+                                   las ? extra.data() : nullptr);
         if (infos) infos[j] = inf;
         std::copy(fields, fields + 5 * nn, hF.begin() + (size_t)j * 5 * nn);
+        if (las && status == ORC_OK && j < c->las_nz)
+            status = laser_plane_advance(g, *c, dt, extra.data(), A0 + (size_t)j * nn,
+                                         j ? A0 + (size_t)(j - 1) * nn : nullptr,
+                                         j ? A1 + (size_t)(j - 1) * nn : nullptr,
+                                         A1 + (size_t)j * nn, nullptr, nullptr);
     }
     if (status != ORC_OK) return status;
     oracle_driver_push(c, dt, n_drv, drv, n_slices, hx.data(), hF.data());
@@ -1392,7 +1552,8 @@ int oracle_slice_adjoint(const oracle_cfg* c, int P, const double* x, const doub
                          const double* px, const double* py, const double* fields, double xi,
                          double dxi, double* xb, double* yb, double* pxb, double* pyb,
                          const double* Fbar, double* theta_bar) {
-    if (c->pusher != PUSH_BORIS) return ORC_INVALID;  /* the reverse sweep is the Boris-like push's */
+    /* the reverse sweep is the Boris-like push's, without a laser */
+    if (c->pusher != PUSH_BORIS || c->las_env) return ORC_INVALID;
     Grid g(c->n_cells, c->half_width);
     const int nn = g.nn();
     const double* psi = fields;

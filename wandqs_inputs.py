@@ -128,6 +128,22 @@ def driver_lattice(beam: dict, n_cells: int, half_width: float, xi0: float, dz: 
     return out
 
 
+def laser_gaussian(n_cells: int, half_width: float, nz: int, dxi: float, a0: float, w0: float,
+                   xi_c: float, sigma_z: float, x0: float = 0.0, y0: float = 0.0):
+    """Envelope planes of a Gaussian laser pulse on the nodes, planes xi_m =
+    m dxi (m = 0 .. nz-1): a0 exp(-r^2/w0^2 - (xi - xi_c)^2/sigma_z^2), real
+    (zero phase), zero on the boundary nodes.  Returns complex [nz][N+1][N+1]."""
+    N, L = int(n_cells), float(half_width)
+    h = 2.0 * L / N
+    g = -L + h * np.arange(N + 1)
+    xis = dxi * np.arange(nz)
+    XI, Y, X = np.meshgrid(xis, g, g, indexing="ij")
+    r2 = (X - x0) ** 2 + (Y - y0) ** 2
+    env = a0 * np.exp(-r2 / w0 ** 2 - (XI - xi_c) ** 2 / sigma_z ** 2)
+    env[:, 0, :] = env[:, -1, :] = env[:, :, 0] = env[:, :, -1] = 0.0
+    return env.astype(np.complex128)
+
+
 def gauss_beam(amp, sigma_r, sigma_z, xi_c, x0=0.0, y0=0.0):
     return dict(kind="gauss", amp=float(amp), sigma_r=float(sigma_r), sigma_z=float(sigma_z),
                 xi_c=float(xi_c), x0=float(x0), y0=float(y0))
