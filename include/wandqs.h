@@ -158,6 +158,10 @@ typedef struct {
                                  Not with a tape. */
     int32_t driver_nz;        /* driver current planes xi_m = driver_xi0 + m driver_dz,   */
     double driver_xi0, driver_dz; /* m = 0 .. driver_nz - 1 (>= 2 planes, dz > 0)          */
+    int32_t laser_nz;         /* > 0: room for a laser envelope on laser_nz planes
+                                 xi_m = m dxi0 (wandqs_laser_set) and the time loop
+                                 that advances it; 0: none.  Not with a tape. */
+    double laser_k0;          /* carrier wavenumber k0 = omega0/omega_p (> 0 with a laser) */
 } wandqs_config;
 
 typedef struct {
@@ -167,6 +171,8 @@ typedef struct {
     int32_t vcycles[5];   /* V-cycles per field solve (psi, Ez, Bz, Bx, By); -1 if not tracked */
     double rel_resid[5];  /* final ||r||/||f|| per field; -1 if not tracked */
     int32_t flags;        /* bit 0: 1+psi <= 0 met */
+    int32_t laser_vcycles; /* multigrid cycles of the envelope plane this slice advanced
+                              (time loop with a laser), else 0 */
 } wandqs_slice_info;
 
 /* Bytes of device workspace needed for cfg and runs of up to n_slices slices
@@ -238,6 +244,44 @@ wandqs_status wandqs_set_state(wandqs_ctx* ctx, const double* d_particles,
  * dt/2 and a drift dt/2.  The fields and plasma state after the call are those
  * of the last slice.  WANDQS_E_INVALID without driver_max. */
 wandqs_status wandqs_driver_set(wandqs_ctx* ctx, int64_t n, const double* d_state);
+
+/* Laser driver (Sec. IV, eq. (20); contexts made with laser_nz > 0).  The
+ * complex envelope A-hat of the laser's vector potential (A = A-hat
+ * exp(-i k0 xi), normalised to m c / e) lives on the planes xi_m = m dxi0,
+ * m = 0 .. laser_nz - 1.
+ *
+ * wandqs_laser_set copies the planes from device memory, [laser_nz][N+1][N+1]
+ * complex numbers as (re, im) pairs of doubles (NULL: the context forgets its
+ * laser); wandqs_laser_get copies the current planes back (same layout).
+ *
+ * With a laser set, every slice takes a2 = |A-hat|^2 at its position (the two
+ * planes around xi interpolated linearly; zero outside the planes) and the
+ * plasma feels it through the ponderomotive terms of eqs. (6)-(7) (the push:
+ * gamma = (1 + p^2 + g^2 + a2/2)/(2g), force -grad(a2/4)/g), eq. (9) (<gamma>
+ * and j_z) and eq. (19) (the term -n* grad(a2/4)/g^2 of S).
+ *
+ * The envelope advances in t by eq. (20) taken centred in t with a backward
+ * xi-difference between neighbouring planes, plane after plane from the
+ * front: with a0, a1 a plane at t and t + dt and p0, p1 the plane ahead
+ * (zero ahead of plane 0), a1 solves the complex Helmholtz problem
+ *   L_h a1 - (chi + beta - i gam) a1 = (chi - beta + i gam) a0 - L_h a0 - beta (p1 - p0),
+ * beta = 4/(dt dxi0), gam = 4 k0/dt, a1 = 0 on the boundary, by multigrid
+ * with the context's mg_* stop rule, from the guess a0; chi = n* / (1 + psi)
+ * is the plasma's susceptibility.
+ *
+ * wandqs_laser_advance(dt, d_chi, h_cycles) advances every plane by dt > 0
+ * with chi given on the device as [laser_nz][N+1][N+1] doubles (NULL:
+ * vacuum); h_cycles (host [laser_nz] or NULL) receives each plane's V-cycles.
+ * In wandqs_time_step (which a laser alone also enables) the plasma sees the
+ * planes at t, and each slice j (< laser_nz) advances plane j right after it
+ * with its own chi (the k2 of its B_perp system); this needs adaptive = 0 (so
+ * that slice j lies on plane j), n_slices >= laser_nz and dt > 0, else
+ * WANDQS_E_INVALID.  WANDQS_E_NOCONV if a plane's solve does not converge in
+ * mg_max_cycles; WANDQS_E_STATE if no envelope is set. */
+wandqs_status wandqs_laser_set(wandqs_ctx* ctx, const double* d_env);
+wandqs_status wandqs_laser_get(wandqs_ctx* ctx, double* d_env);
+wandqs_status wandqs_laser_advance(wandqs_ctx* ctx, double dt, const double* d_chi,
+                                   int32_t* h_cycles);
 wandqs_status wandqs_driver_get(wandqs_ctx* ctx, double* d_state);
 wandqs_status wandqs_time_step(wandqs_ctx* ctx, double dt, int32_t n_slices,
                                wandqs_slice_info* h_infos);

@@ -84,6 +84,11 @@ const char* check_config(const wandqs_config* c, int32_t n_slices) {
             return "a time loop needs driver_nz in [2, 65536], driver_dz > 0 and a finite driver_xi0";
         if (c->checkpoint_every > 0) return "the time loop (driver_max > 0) has no adjoint tape";
     }
+    if (c->laser_nz < 0 || c->laser_nz > 65536) return "laser_nz must be in [0, 65536]";
+    if (c->laser_nz > 0) {
+        if (!(c->laser_k0 > 0.0) || !std::isfinite(c->laser_k0)) return "a laser needs laser_k0 > 0";
+        if (c->checkpoint_every > 0) return "a laser envelope (laser_nz > 0) has no adjoint tape";
+    }
     if (c->checkpoint_every > 0 && c->adaptive && !c->adjoint_hold_dxi)
         return "a tape with adaptive steps differentiates with the forward's steps held fixed "
                "(they depend on the state through Vmax): set adjoint_hold_dxi = 1 to accept that";
@@ -159,6 +164,8 @@ void set_sizes(wandqs_ctx* c, const wandqs_config* cfg, int32_t n_slices) {
         }
     }
     c->drv_nz = cfg->driver_max > 0 ? cfg->driver_nz : 0;
+    c->las_ll = 0;  // the laser's workgroup levels: N <= 32
+    while (c->lev[c->las_ll].N > 32) ++c->las_ll;
     c->tape_K = cfg->checkpoint_every;
     c->n_ckpt = c->tape_K > 0 ? (n_slices + c->tape_K - 1) / c->tape_K + 1 : 0;
 }
@@ -240,6 +247,9 @@ wandqs_status do_slice(wandqs_ctx* c, int rec_slot, int64_t probe_slice, bool ta
     // initial guesses: the previous slice's fields (Sec. VII.A), extrapolated in
     // xi through the last slices once they are known
     if ((s = extrapolate_guess(c, c->n_guess - 1)) != WANDQS_OK) return s;
+    // a laser envelope's |A-hat|^2 at this slice and its gradient (ponderomotive terms)
+    c->las_cycles = 0;
+    if (c->las_on && (s = laser_nodes(c)) != WANDQS_OK) return s;
     if ((s = slice_sort(c)) != WANDQS_OK) return s;
     if (rec) {
         const size_t pb = sizeof(double) * (size_t)c->P;
@@ -282,6 +292,14 @@ wandqs_status do_slice(wandqs_ctx* c, int rec_slot, int64_t probe_slice, bool ta
         std::swap(c->gpsi[0], c->gpsi_prev[0]);
         std::swap(c->gpsi[1], c->gpsi_prev[1]);
     }
+    if (c->las_adv) {
+        // time loop: this slice's plane of the envelope advances by dt with the
+        // slice's susceptibility chi = n* / (1+psi), the k2 of its B_perp system
+        if (c->las_j < c->cfg.laser_nz &&
+            (s = laser_plane_advance(c, c->las_dt, L0.k2, c->las_j, &c->las_cycles)) != WANDQS_OK)
+            return s;
+        ++c->las_j;
+    }
     if (c->n_guess < kGuessMax) ++c->n_guess;
     if (taping) ++c->tape_n;
     return WANDQS_OK;
@@ -294,6 +312,7 @@ void fill_info_host(const wandqs_ctx* c, wandqs_slice_info* info) {
         info->vcycles[k] = r[idx[k][0]].cycles;
         info->rel_resid[k] = r[idx[k][0]].rel[idx[k][1]];
     }
+    info->laser_vcycles = c->las_cycles;
 }
 
 wandqs_status check_flags(wandqs_ctx* c) {
@@ -397,8 +416,27 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
         c->drv_planes = (unsigned long long*)take(sizeof(unsigned long long) * (size_t)c->drv_nz *
                                                   (c->N + 1) * L0.pitch);
         for (int q = 0; q < 2; ++q) c->gpsi_prev[q] = arr(0);
+    }
+    if (c->cfg.driver_max > 0 || c->cfg.laser_nz > 0) {  // the time loop's cold lattice
         for (int q = 0; q < 2; ++q) c->lat[q] = (double*)take(sizeof(double) * P);
         c->lat_id = (int32_t*)take(sizeof(int32_t) * P);
+    }
+    if (c->cfg.laser_nz > 0) {
+        auto carr = [&](int l) {
+            return (double2*)take(sizeof(double2) * (size_t)(c->lev[l].N + 1) * c->lev[l].pitch);
+        };
+        const size_t plane = (size_t)(c->N + 1) * L0.pitch;
+        for (int q = 0; q < 2; ++q)
+            c->las_env[q] = (double2*)take(sizeof(double2) * plane * (size_t)c->cfg.laser_nz);
+        c->las_a2 = arr(0);
+        for (int q = 0; q < 2; ++q) c->las_g[q] = arr(0);
+        for (int l = 0; l <= c->las_ll; ++l) {
+            c->las_u[l] = l ? carr(l) : nullptr;
+            c->las_f[l] = carr(l);
+            c->las_k[l] = carr(l);
+        }
+        c->las_part = (double*)take(sizeof(double) * 4 * (size_t)(c->N + 1));
+        c->las_red = (double*)take(sizeof(double) * 4);
     }
     c->cell_count = (int32_t*)take(sizeof(int32_t) * ncell);
     c->cell_start = (int32_t*)take(sizeof(int32_t) * (ncell + 1));
@@ -602,10 +640,11 @@ wandqs_status wandqs_init(const wandqs_config* cfg, int32_t n_slices, void* d_wo
         return WANDQS_E_HIP;
     };
     // coherent: the kernels publish residual norms into it (mg_solve)
-    if (hipHostMalloc((void**)&c->h_pin, sizeof(double) * (wq::kMaxSlots * wq::kNormVec + 8),
+    // (+ 8: flags and sequence word; + 8 more: the laser solve's norms)
+    if (hipHostMalloc((void**)&c->h_pin, sizeof(double) * (wq::kMaxSlots * wq::kNormVec + 16),
                       hipHostMallocCoherent) != hipSuccess)
         return bail("hipHostMalloc failed");
-    std::memset(c->h_pin, 0, sizeof(double) * (wq::kMaxSlots * wq::kNormVec + 8));
+    std::memset(c->h_pin, 0, sizeof(double) * (wq::kMaxSlots * wq::kNormVec + 16));
     if (hipMemsetAsync(d_workspace, 0, need, c->stream) != hipSuccess)
         return bail("hipMemsetAsync of the workspace failed");
 
@@ -887,8 +926,13 @@ wandqs_status wandqs_driver_get(wandqs_ctx* c, double* d_state) {
 wandqs_status wandqs_time_step(wandqs_ctx* c, double dt, int32_t n_slices, wandqs_slice_info* h_infos) {
     using namespace wq;
     if (!c || n_slices < 1 || !std::isfinite(dt)) return WANDQS_E_INVALID;
-    if (c->cfg.driver_max <= 0) {
-        c->err = "no time loop: initialise with driver_max > 0";
+    if (c->cfg.driver_max <= 0 && c->cfg.laser_nz <= 0) {
+        c->err = "no time loop: initialise with driver_max > 0 or laser_nz > 0";
+        return WANDQS_E_INVALID;
+    }
+    if (c->las_on && (c->cfg.adaptive || n_slices < c->cfg.laser_nz || !(dt > 0.0))) {
+        c->err = "a time step with a laser envelope needs fixed steps (adaptive = 0, so that "
+                 "slice j lies on plane j), n_slices >= laser_nz and dt > 0";
         return WANDQS_E_INVALID;
     }
     if (c->failed) {
@@ -911,19 +955,72 @@ wandqs_status wandqs_time_step(wandqs_ctx* c, double dt, int32_t n_slices, wandq
         for (double* a : arrs)
             if (a && (s = fill_f64(c, a, nb, 0.0)) != WANDQS_OK) return fail(c, s);
     }
+    const bool drv = c->cfg.driver_max > 0;
     if ((s = fill_f64(c, c->st, 16, 0.0)) != WANDQS_OK || (s = fill_f64(c, c->st + 1, 1, c->cfg.dxi0)) != WANDQS_OK ||
-        (s = driver_deposit(c)) != WANDQS_OK ||
-        (s = fill_f64(c, c->drv_eb, 6 * (size_t)c->cfg.driver_max, 0.0)) != WANDQS_OK)
+        (drv && (s = driver_deposit(c)) != WANDQS_OK) ||
+        (drv && (s = fill_f64(c, c->drv_eb, 6 * (size_t)c->cfg.driver_max, 0.0)) != WANDQS_OK))
         return fail(c, s);
     WQ_HIP(hipMemsetAsync(c->flags, 0, sizeof(int32_t), c->stream));
     c->n_guess = 0;
     c->tape_n = 0;
-    c->drv_active = true;
+    c->drv_active = drv;
     c->drv_dt = dt;
+    c->las_adv = c->las_on;
+    c->las_dt = dt;
+    c->las_j = 0;
     s = wandqs_run(c, n_slices, nullptr, h_infos);
     c->drv_active = false;
+    c->las_adv = false;
     if (s != WANDQS_OK) return s;
-    if ((s = driver_push(c, dt)) != WANDQS_OK) return fail(c, s);
+    if (c->las_on) c->las_cur = 1 - c->las_cur;  // the planes at t + dt
+    if (drv && (s = driver_push(c, dt)) != WANDQS_OK) return fail(c, s);
+    return WANDQS_OK;
+}
+
+wandqs_status wandqs_laser_set(wandqs_ctx* c, const double* d_env) {
+    if (!c) return WANDQS_E_INVALID;
+    if (c->cfg.laser_nz <= 0) {
+        c->err = "no room for a laser envelope: initialise with laser_nz > 0";
+        return WANDQS_E_INVALID;
+    }
+    if (!d_env) {
+        c->las_on = false;
+        return WANDQS_OK;
+    }
+    wandqs_status s;
+    if ((s = wq::laser_unpack(c, d_env, c->las_cur)) != WANDQS_OK) return fail(c, s);
+    c->las_on = true;
+    return WANDQS_OK;
+}
+
+wandqs_status wandqs_laser_get(wandqs_ctx* c, double* d_env) {
+    if (!c || !d_env) return WANDQS_E_INVALID;
+    if (!c->las_on) {
+        c->err = "no laser envelope set";
+        return WANDQS_E_STATE;
+    }
+    wandqs_status s;
+    if ((s = wq::laser_pack(c, d_env)) != WANDQS_OK) return fail(c, s);
+    return WANDQS_OK;
+}
+
+wandqs_status wandqs_laser_advance(wandqs_ctx* c, double dt, const double* d_chi, int32_t* h_cycles) {
+    if (!c || !(dt > 0.0) || !std::isfinite(dt)) return WANDQS_E_INVALID;
+    if (!c->las_on) {
+        c->err = "no laser envelope set";
+        return WANDQS_E_STATE;
+    }
+    const size_t dense = (size_t)(c->N + 1) * (c->N + 1);
+    wandqs_status s;
+    for (int j = 0; j < c->cfg.laser_nz; ++j) {
+        double* k2 = c->lev[0].k2;
+        if (d_chi && (s = wq::unpack_fields(c, d_chi + j * dense, 1, &k2)) != WANDQS_OK) return fail(c, s);
+        int cyc = 0;
+        s = wq::laser_plane_advance(c, dt, d_chi ? k2 : nullptr, j, &cyc);
+        if (h_cycles) h_cycles[j] = cyc;
+        if (s != WANDQS_OK) return s;
+    }
+    c->las_cur = 1 - c->las_cur;
     return WANDQS_OK;
 }
 

@@ -80,13 +80,15 @@ __device__ __forceinline__ double driver_current(const DriverPlanes& D, size_t i
 }
 
 // Total j_z on every node: plasma n*<p_z>/g = G/g - n* with G = n*<gamma> =
-// [n*(1 + g^2) + g^2 (Txx + Tyy)]/(2g) (eq. (9) and the gamma of Sec. III.A,
-// <p_perp^2> = g^2 <V^2>), plus the frozen drivers' density at xi (luminal beam
-// current) and the driver macroparticles' current (time loop).
+// [n*(1 + g^2 + a2/2) + g^2 (Txx + Tyy)]/(2g) (eq. (9) and the gamma of Sec.
+// III.A, <p_perp^2> = g^2 <V^2>, a2 = |A-hat|^2 of a laser envelope or 0 when
+// a2 is null), plus the frozen drivers' density at xi (luminal beam current)
+// and the driver macroparticles' current (time loop).
 __global__ void k_jz(int N, double L, double h, int pitch, const double* __restrict__ n,
                      const double* __restrict__ txx, const double* __restrict__ tyy,
-                     const double* __restrict__ psi, const double* __restrict__ st, BeamSet beams,
-                     DriverPlanes drv, double* __restrict__ jz, int32_t* __restrict__ flags) {
+                     const double* __restrict__ psi, const double* __restrict__ a2,
+                     const double* __restrict__ st, BeamSet beams, DriverPlanes drv,
+                     double* __restrict__ jz, int32_t* __restrict__ flags) {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
     if (a > N) return;
@@ -95,7 +97,8 @@ __global__ void k_jz(int N, double L, double h, int pitch, const double* __restr
     if (n[i] > 0.0) {
         const double g = 1.0 + psi[i];
         if (!(g > 0.0)) atomicOr(flags, 1);
-        const double G = (n[i] * (1.0 + g * g) + g * g * (txx[i] + tyy[i])) / (2.0 * g);
+        const double q = a2 ? 0.5 * a2[i] : 0.0;
+        const double G = (n[i] * (1.0 + g * g + q) + g * g * (txx[i] + tyy[i])) / (2.0 * g);
         v = G / g - n[i];
     }
     jz[i] = v + beam_density(beams, -L + a * h, -L + b * h, (size_t)b * (N + 1) + a, st[0]) +
@@ -104,14 +107,19 @@ __global__ void k_jz(int N, double L, double h, int pitch, const double* __restr
 
 // k2 = n* / g and the B_perp right-hand sides on the interior nodes:
 //   f_Bx = D_y(j_z - Tyy) - D_x Txy + (jx Bz - jy Ez)/g + (G/g^2 - Tyy/g) psi_y - (Txy/g) psi_x
+//          - n* D_y(a2/4)/g^2
 //   f_By = D_x(Txx - j_z) + D_y Txy + (jy Bz + jx Ez)/g - (G/g^2 - Txx/g) psi_x + (Txy/g) psi_y
+//          + n* D_x(a2/4)/g^2
+// (G as in k_jz; the a2 terms are the ponderomotive part of S, present when a2
+// is not null).
 __global__ void k_assemble(int N, double h, int pitch, const double* __restrict__ n,
                            const double* __restrict__ jx, const double* __restrict__ jy,
                            const double* __restrict__ txx, const double* __restrict__ txy,
                            const double* __restrict__ tyy, const double* __restrict__ psi,
                            const double* __restrict__ Ez, const double* __restrict__ Bz,
-                           const double* __restrict__ jz, double* __restrict__ k2,
-                           double* __restrict__ fBx, double* __restrict__ fBy) {
+                           const double* __restrict__ jz, const double* __restrict__ a2,
+                           double* __restrict__ k2, double* __restrict__ fBx,
+                           double* __restrict__ fBy) {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
     if (a > N) return;
@@ -125,12 +133,17 @@ __global__ void k_assemble(int N, double h, int pitch, const double* __restrict_
         fx = ((jz[nn] - tyy[nn]) - (jz[s] - tyy[s])) * i2h - (txy[e] - txy[w]) * i2h;
         fy = ((txx[e] - jz[e]) - (txx[w] - jz[w])) * i2h + (txy[nn] - txy[s]) * i2h;
         if (n[i] > 0.0) {
-            const double G = (n[i] * (1.0 + g * g) + g * g * (txx[i] + tyy[i])) / (2.0 * g);
+            const double q = a2 ? 0.5 * a2[i] : 0.0;
+            const double G = (n[i] * (1.0 + g * g + q) + g * g * (txx[i] + tyy[i])) / (2.0 * g);
             k = n[i] / g;
             fx += (jx[i] * Bz[i] - jy[i] * Ez[i]) / g + (G / (g * g) - tyy[i] / g) * psy -
                   (txy[i] / g) * psx;
             fy += (jy[i] * Bz[i] + jx[i] * Ez[i]) / g - (G / (g * g) - txx[i] / g) * psx +
                   (txy[i] / g) * psy;
+            if (a2) {
+                fx -= n[i] * (0.25 * ((a2[nn] - a2[s]) * i2h)) / (g * g);
+                fy += n[i] * (0.25 * ((a2[e] - a2[w]) * i2h)) / (g * g);
+            }
         }
     }
     k2[i] = k;
@@ -278,14 +291,15 @@ wandqs_status assemble(wandqs_ctx* c) {
                                c->cfg.driver_dz, (size_t)(c->N + 1) * L0.pitch};
         ProfScope ps(c, "k_jz", (double)(c->N + 1) * (c->N + 1) * 40.0);
         WQ_KLAUNCH(ps, k_jz, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->L, c->h, L0.pitch,
-                           c->mom[0], c->mom[3], c->mom[5], c->fields[0], c->st, c->beamset, drv,
-                           c->jz, c->flags);
+                           c->mom[0], c->mom[3], c->mom[5], c->fields[0],
+                           c->las_on ? c->las_a2 : nullptr, c->st, c->beamset, drv, c->jz, c->flags);
     }
     {
         ProfScope ps(c, "k_assemble", (double)(c->N + 1) * (c->N + 1) * 104.0);
         WQ_KLAUNCH(ps, k_assemble, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->h, L0.pitch,
                            c->mom[0], c->mom[1], c->mom[2], c->mom[3], c->mom[4], c->mom[5],
-                           c->fields[0], c->fields[1], c->fields[2], c->jz, L0.k2, L0.f[0], L0.f[1]);
+                           c->fields[0], c->fields[1], c->fields[2], c->jz,
+                           c->las_on ? c->las_a2 : nullptr, L0.k2, L0.f[0], L0.f[1]);
     }
     WQ_LAUNCH_CHECK();
     return WANDQS_OK;

@@ -446,15 +446,19 @@ __device__ __forceinline__ double2 ld_pair(const double* p) {
 }
 
 // Boris-like push over dxi with the fields frozen at this slice (eqs. (6)-(7)):
-// half kick by F = gamma grad psi / g + e_z x B_perp with gamma from the old
-// momentum, rotation by the (e_z x V) Bz term through angle 2 atan(Bz dxi / 2g),
-// half kick, drift with the new momentum, specular walls.  Emits the block
-// maximum of |p_new| / g_i for Algorithm 1.
+// half kick by F = (gamma grad psi - grad(a2/4)) / g + e_z x B_perp with
+// gamma = (1 + p^2 + g^2 + a2/2)/(2g) from the old momentum, rotation by the
+// (e_z x V) Bz term through angle 2 atan(Bz dxi / 2g), half kick, drift with
+// the new momentum, specular walls.  LAS: a laser envelope's a2 = |A-hat|^2
+// and its node gradient (ax, ay) are gathered too (else a2 = 0).  Emits the
+// block maximum of |p_new| / g_i for Algorithm 1.
+template <bool LAS>
 __global__ __launch_bounds__(kPushThreads) void k_push(
     int64_t P, int N, double L, double h, int pitch, const double* __restrict__ st,
     const double* __restrict__ psi, const double* __restrict__ gpx, const double* __restrict__ gpy,
     const double* __restrict__ Bx, const double* __restrict__ By,
-    const double* __restrict__ Bz, double* __restrict__ x, double* __restrict__ y,
+    const double* __restrict__ Bz, const double* __restrict__ la2, const double* __restrict__ lax,
+    const double* __restrict__ lay, double* __restrict__ x, double* __restrict__ y,
     double* __restrict__ px, double* __restrict__ py, double* __restrict__ vmax_part) {
     __shared__ double red[kPushThreads / 64];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -480,11 +484,20 @@ __global__ __launch_bounds__(kPushThreads) void k_push(
         const double bx = cic_gather(bx0.x, bx0.y, bx1.x, bx1.y, dx, dy);
         const double by = cic_gather(by0.x, by0.y, by1.x, by1.y, dx, dy);
         const double bz = cic_gather(bz0.x, bz0.y, bz1.x, bz1.y, dx, dy);
+        double a2 = 0.0, ax = 0.0, ay = 0.0;
+        if (LAS) {
+            const double2 q0 = ld_pair(la2 + g), q1 = ld_pair(la2 + g + pitch);
+            const double2 u0 = ld_pair(lax + g), u1 = ld_pair(lax + g + pitch);
+            const double2 v0 = ld_pair(lay + g), v1 = ld_pair(lay + g + pitch);
+            a2 = cic_gather(q0.x, q0.y, q1.x, q1.y, dx, dy);
+            ax = cic_gather(u0.x, u0.y, u1.x, u1.y, dx, dy);
+            ay = cic_gather(v0.x, v0.y, v1.x, v1.y, dx, dy);
+        }
 
         const double ig = 1.0 / g_i;
-        const double gamma = (1.0 + pxi * pxi + pyi * pyi + g_i * g_i) * (0.5 * ig);
-        const double Fx = gamma * Gx * ig - by;
-        const double Fy = gamma * Gy * ig + bx;
+        const double gamma = (1.0 + pxi * pxi + pyi * pyi + g_i * g_i + 0.5 * a2) * (0.5 * ig);
+        const double Fx = (gamma * Gx - 0.25 * ax) * ig - by;
+        const double Fy = (gamma * Gy - 0.25 * ay) * ig + bx;
         const double mx = pxi + 0.5 * dxi * Fx;
         const double my = pyi + 0.5 * dxi * Fy;
         const double t = bz * dxi * (0.5 * ig);
@@ -518,17 +531,19 @@ __global__ __launch_bounds__(kPushThreads) void k_push(
 }
 
 // Frozen slice fields for the Runge-Kutta pushers: psi, its node gradient,
-// B_perp and B_z, gathered (CIC) at any position.
+// B_perp and B_z, and a laser envelope's |A-hat|^2 with its node gradient
+// (null without a laser), gathered (CIC) at any position.
 struct PushFields {
     int N, pitch;
     double L, h;
     const double *psi, *gx, *gy, *Bx, *By, *Bz;
+    const double *a2, *ax, *ay;
 };
 
 // Right-hand side of the equations of motion at s = (x, y, p_x, p_y) (Sec.
-// III.A eqs. (6)-(7)): dr/dxi = p/g, dp/dxi = gamma grad psi/g + (e_z x V) B_z
-// + e_z x B_perp with g = 1 + psi and gamma = (1 + p^2 + g^2)/(2g), every field
-// gathered at s.  Returns g.
+// III.A eqs. (6)-(7)): dr/dxi = p/g, dp/dxi = (gamma grad psi - grad(a2/4))/g
+// + (e_z x V) B_z + e_z x B_perp with g = 1 + psi and gamma = (1 + p^2 + g^2 +
+// a2/2)/(2g), every field gathered at s.  Returns g.
 __device__ __forceinline__ double eom_rhs(const PushFields& F, const double (&s)[4],
                                           double (&d)[4]) {
     int a, b;
@@ -548,13 +563,22 @@ __device__ __forceinline__ double eom_rhs(const PushFields& F, const double (&s)
     const double bx = cic_gather(bx0.x, bx0.y, bx1.x, bx1.y, dx, dy);
     const double by = cic_gather(by0.x, by0.y, by1.x, by1.y, dx, dy);
     const double bz = cic_gather(bz0.x, bz0.y, bz1.x, bz1.y, dx, dy);
+    double a2 = 0.0, ax = 0.0, ay = 0.0;
+    if (F.a2) {
+        const double2 q0 = ld_pair(F.a2 + g), q1 = ld_pair(F.a2 + g + F.pitch);
+        const double2 u0 = ld_pair(F.ax + g), u1 = ld_pair(F.ax + g + F.pitch);
+        const double2 v0 = ld_pair(F.ay + g), v1 = ld_pair(F.ay + g + F.pitch);
+        a2 = cic_gather(q0.x, q0.y, q1.x, q1.y, dx, dy);
+        ax = cic_gather(u0.x, u0.y, u1.x, u1.y, dx, dy);
+        ay = cic_gather(v0.x, v0.y, v1.x, v1.y, dx, dy);
+    }
     const double ig = 1.0 / gg;
-    const double gamma = (1.0 + s[2] * s[2] + s[3] * s[3] + gg * gg) * (0.5 * ig);
+    const double gamma = (1.0 + s[2] * s[2] + s[3] * s[3] + gg * gg + 0.5 * a2) * (0.5 * ig);
     const double vx = s[2] * ig, vy = s[3] * ig;
     d[0] = vx;
     d[1] = vy;
-    d[2] = gamma * Gx * ig - vy * bz - by;
-    d[3] = gamma * Gy * ig + vx * bz + bx;
+    d[2] = (gamma * Gx - 0.25 * ax) * ig - vy * bz - by;
+    d[3] = (gamma * Gy - 0.25 * ay) * ig + vx * bz + bx;
     return gg;
 }
 
@@ -786,15 +810,24 @@ wandqs_status push_and_step(wandqs_ctx* c, int rec_slot) {
                            c->N, c->h, c->lev[0].pitch, c->fields[0], c->gpsi[0], c->gpsi[1]);
     }
     const int pusher = c->cfg.pusher;
-    if (pusher == WANDQS_PUSH_BORIS) {
+    const bool las = c->las_on;
+    if (pusher == WANDQS_PUSH_BORIS && !las) {
         ProfScope ps(c, "k_push", (double)c->P * 64.0 + (double)(c->N + 1) * (c->N + 1) * 48.0);
-        WQ_KLAUNCH(ps, k_push, dim3(c->n_push_blocks), dim3(kPushThreads), 0, c->stream, c->P,
+        WQ_KLAUNCH(ps, k_push<false>, dim3(c->n_push_blocks), dim3(kPushThreads), 0, c->stream, c->P,
                            c->N, c->L, c->h, c->lev[0].pitch, c->st, c->fields[0], c->gpsi[0],
-                           c->gpsi[1], c->fields[3], c->fields[4], c->fields[2], c->pa[k][0],
-                           c->pa[k][1], c->pa[k][2], c->pa[k][3], c->vmax_part);
+                           c->gpsi[1], c->fields[3], c->fields[4], c->fields[2], nullptr, nullptr,
+                           nullptr, c->pa[k][0], c->pa[k][1], c->pa[k][2], c->pa[k][3], c->vmax_part);
+    } else if (pusher == WANDQS_PUSH_BORIS) {
+        ProfScope ps(c, "k_push<laser>", (double)c->P * 64.0 + (double)(c->N + 1) * (c->N + 1) * 72.0);
+        WQ_KLAUNCH(ps, k_push<true>, dim3(c->n_push_blocks), dim3(kPushThreads), 0, c->stream, c->P,
+                           c->N, c->L, c->h, c->lev[0].pitch, c->st, c->fields[0], c->gpsi[0],
+                           c->gpsi[1], c->fields[3], c->fields[4], c->fields[2], c->las_a2,
+                           c->las_g[0], c->las_g[1], c->pa[k][0], c->pa[k][1], c->pa[k][2],
+                           c->pa[k][3], c->vmax_part);
     } else {
         const PushFields F{c->N, c->lev[0].pitch, c->L, c->h, c->fields[0], c->gpsi[0], c->gpsi[1],
-                           c->fields[3], c->fields[4], c->fields[2]};
+                           c->fields[3], c->fields[4], c->fields[2], las ? c->las_a2 : nullptr,
+                           las ? c->las_g[0] : nullptr, las ? c->las_g[1] : nullptr};
         // per particle: its state read and written; per node (read once): six fields
         const double bytes = (double)c->P * 64.0 + (double)(c->N + 1) * (c->N + 1) * 48.0;
         const dim3 g(c->n_push_blocks), b(kPushThreads);
@@ -817,6 +850,16 @@ wandqs_status push_and_step(wandqs_ctx* c, int rec_slot) {
         ProfScope ps(c, "k_dxi", 8.0 * c->n_push_blocks);
         WQ_KLAUNCH(ps, k_dxi, dim3(1), dim3(kDxiThreads), 0, c->stream, c->n_push_blocks, c->vmax_part,
                            c->st, c->cfg.dxi0, c->h, c->cfg.adaptive, c->cfg.refine_k, c->flags, rec);
+    }
+    WQ_LAUNCH_CHECK();
+    return WANDQS_OK;
+}
+
+wandqs_status node_gradient(wandqs_ctx* c, const double* u, double* gx, double* gy) {
+    {
+        ProfScope pg(c, "k_grad_psi", (double)(c->N + 1) * (c->N + 1) * 24.0);
+        WQ_KLAUNCH(pg, k_grad_psi, dim3((c->N + 1 + 127) / 128, c->N + 1), dim3(128), 0, c->stream,
+                           c->N, c->h, c->lev[0].pitch, u, gx, gy);
     }
     WQ_LAUNCH_CHECK();
     return WANDQS_OK;

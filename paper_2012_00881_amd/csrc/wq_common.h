@@ -228,6 +228,25 @@ struct wandqs_ctx {
     double* gpsi_prev[2] = {};
     double* lat[2] = {};
     int32_t* lat_id = nullptr;
+    // laser envelope (laser_nz > 0): two sets of planes [laser_nz][N+1][pitch]
+    // (complex), las_env[las_cur] at the current time; |A-hat|^2 of the slice
+    // and its node gradient; the complex multigrid's levels 1 .. las_ll (level
+    // 0's iterate is the plane being advanced) and its norm partials
+    double2* las_env[2] = {};
+    int las_cur = 0;
+    bool las_on = false;      // an envelope has been set: the plasma feels it
+    bool las_adv = false;     // inside wandqs_time_step: each slice advances its plane
+    double las_dt = 0.0;
+    int las_j = 0;            // plane of the next slice in the time step's sweep
+    int las_cycles = 0;       // multigrid cycles of the last plane advanced
+    double* las_a2 = nullptr;
+    double* las_g[2] = {};
+    double2* las_u[wq::kMaxLevels] = {};
+    double2* las_f[wq::kMaxLevels] = {};
+    double2* las_k[wq::kMaxLevels] = {};
+    int las_ll = 0;           // level solved (with those below) by one workgroup
+    double* las_part = nullptr;
+    double* las_red = nullptr;
     double* k2lev = nullptr;  // k2 of the coarse-kernel levels (dense, concatenated)
     float* k2levf = nullptr;  // the same in float, and 1 / (4 + h_l^2 k2) in float
     float* idlevf = nullptr;
@@ -334,6 +353,17 @@ wandqs_status fill_f64(wandqs_ctx* c, double* p, size_t n, double v);
 wandqs_status extrapolate_guess(wandqs_ctx* c, int order);
 wandqs_status copy_d2d(wandqs_ctx* c, void* dst, const void* src, size_t bytes);
 wandqs_status probe_seed(wandqs_ctx* c, int k, double w, double* const* Fb);
+
+// laser envelope (laser.hip): |A-hat|^2 of the slice at st[0] and its node
+// gradient; one plane's time step (chi: n* / (1+psi) at the nodes, may be
+// null); dense <-> padded copies of the planes
+wandqs_status laser_nodes(wandqs_ctx* c);
+wandqs_status laser_plane_advance(wandqs_ctx* c, double dt, const double* chi, int j, int* cycles);
+wandqs_status laser_unpack(wandqs_ctx* c, const double* src, int set);
+wandqs_status laser_pack(wandqs_ctx* c, double* dst);
+// node gradient (central inside, one-sided on the boundary lines), as the
+// push's grad psi (particles.hip)
+wandqs_status node_gradient(wandqs_ctx* c, const double* u, double* gx, double* gy);
 
 // time loop (driver.hip)
 wandqs_status driver_deposit(wandqs_ctx* c);

@@ -31,7 +31,7 @@ EXPORTS = ("wandqs_workspace_bytes", "wandqs_init", "wandqs_slice_step", "wandqs
            "wandqs_num_particles", "wandqs_destroy", "wandqs_last_error", "wandqs_profile",
            "wandqs_profile_stats", "wandqs_backward", "wandqs_num_theta", "wandqs_tape_slices",
            "wandqs_mg_solve_noalloc", "wandqs_driver_set", "wandqs_driver_get",
-           "wandqs_time_step")
+           "wandqs_time_step", "wandqs_laser_set", "wandqs_laser_get", "wandqs_laser_advance")
 
 
 class Beam(C.Structure):
@@ -57,7 +57,8 @@ class Config(C.Structure):
                 ("mg_inner_cycles", C.c_int32), ("mg_omega", C.c_double),
                 ("mg_omega_helm", C.c_double), ("adjoint_hold_dxi", C.c_int32),
                 ("pusher", C.c_int32), ("driver_max", C.c_int32), ("driver_nz", C.c_int32),
-                ("driver_xi0", C.c_double), ("driver_dz", C.c_double)]
+                ("driver_xi0", C.c_double), ("driver_dz", C.c_double), ("laser_nz", C.c_int32),
+                ("laser_k0", C.c_double)]
 
 
 class KernelStat(C.Structure):
@@ -67,11 +68,13 @@ class KernelStat(C.Structure):
 
 class SliceInfo(C.Structure):
     _fields_ = [("xi", C.c_double), ("dxi", C.c_double), ("vmax", C.c_double),
-                ("vcycles", C.c_int32 * 5), ("rel_resid", C.c_double * 5), ("flags", C.c_int32)]
+                ("vcycles", C.c_int32 * 5), ("rel_resid", C.c_double * 5), ("flags", C.c_int32),
+                ("laser_vcycles", C.c_int32)]
 
     def as_dict(self):
         return dict(xi=self.xi, dxi=self.dxi, vmax=self.vmax, vcycles=list(self.vcycles),
-                    rel_resid=list(self.rel_resid), flags=self.flags)
+                    rel_resid=list(self.rel_resid), flags=self.flags,
+                    laser_vcycles=self.laser_vcycles)
 
 
 _lib = None
@@ -99,6 +102,9 @@ def load():
     L.wandqs_driver_set.argtypes = [vp, C.c_int64, vp]
     L.wandqs_driver_get.argtypes = [vp, vp]
     L.wandqs_time_step.argtypes = [vp, C.c_double, i32, C.POINTER(SliceInfo)]
+    L.wandqs_laser_set.argtypes = [vp, vp]
+    L.wandqs_laser_get.argtypes = [vp, vp]
+    L.wandqs_laser_advance.argtypes = [vp, C.c_double, vp, C.POINTER(i32)]
     L.wandqs_num_particles.argtypes = [vp]
     L.wandqs_num_particles.restype = C.c_int64
     L.wandqs_profile.argtypes = [vp, i32]
@@ -116,7 +122,8 @@ def load():
                  "wandqs_get_state", "wandqs_set_state", "wandqs_mg_solve",
                  "wandqs_get_moments", "wandqs_profile", "wandqs_profile_stats",
                  "wandqs_backward", "wandqs_mg_solve_noalloc", "wandqs_driver_set",
-                 "wandqs_driver_get", "wandqs_time_step"):
+                 "wandqs_driver_get", "wandqs_time_step", "wandqs_laser_set", "wandqs_laser_get",
+                 "wandqs_laser_advance"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -170,6 +177,8 @@ def make_config(cfg: dict):
     c.driver_nz = int(cfg.get("driver_nz", 0))
     c.driver_xi0 = float(cfg.get("driver_xi0", 0.0))
     c.driver_dz = float(cfg.get("driver_dz", 0.0))
+    c.laser_nz = int(cfg.get("laser_nz", 0))
+    c.laser_k0 = float(cfg.get("laser_k0", 0.0))
     return c, keep
 
 
@@ -358,6 +367,41 @@ class Simulation:
         arr = (SliceInfo * max(1, n_slices))() if infos else None
         self._check(self.L.wandqs_time_step(self.ctx, C.c_double(dt), int(n_slices), arr))
         return [a.as_dict() for a in arr[:n_slices]] if infos else None
+
+    # ---------------------------------------------------------------- laser
+    def laser_set(self, env):
+        """Laser envelope planes A-hat, complex [laser_nz][N+1][N+1] (None: no laser)."""
+        t = self.torch
+        if env is None:
+            self._check(self.L.wandqs_laser_set(self.ctx, None))
+            return
+        e = t.as_tensor(env, dtype=t.complex128).to(self.device).contiguous()
+        assert tuple(e.shape) == (int(self.cfg["laser_nz"]), self.N + 1, self.N + 1)
+        self.stream.synchronize()
+        self._check(self.L.wandqs_laser_set(self.ctx, C.c_void_p(e.data_ptr())))
+        self.stream.synchronize()
+
+    def laser_get(self):
+        out = self.torch.empty((int(self.cfg["laser_nz"]), self.N + 1, self.N + 1),
+                               dtype=self.torch.complex128, device=self.device)
+        self._check(self.L.wandqs_laser_get(self.ctx, C.c_void_p(out.data_ptr())))
+        return out
+
+    def laser_advance(self, dt: float, chi=None):
+        """Advance the envelope by dt with the susceptibility chi
+        [laser_nz][N+1][N+1] (None: vacuum); returns the V-cycles per plane."""
+        t = self.torch
+        nz = int(self.cfg["laser_nz"])
+        ch = None
+        if chi is not None:
+            ch = t.as_tensor(chi, dtype=t.float64).to(self.device).contiguous()
+            assert tuple(ch.shape) == (nz, self.N + 1, self.N + 1)
+        cyc = (C.c_int32 * max(1, nz))()
+        self.stream.synchronize()
+        self._check(self.L.wandqs_laser_advance(self.ctx, C.c_double(dt),
+                                                C.c_void_p(ch.data_ptr()) if ch is not None else None,
+                                                cyc))
+        return list(cyc[:nz])
 
     def moments(self):
         out = self._nodes(9)

@@ -31,7 +31,7 @@ def test_exports_every_declared_symbol(lib):
 def test_struct_sizes_match_header_layout(lib):
     # natural alignment on x86-64: the binding's ctypes structs must match
     assert C.sizeof(lib.Beam) == 4 + 4 + 6 * 8 + 8 + 8 + 8
-    assert C.sizeof(lib.SliceInfo) == 3 * 8 + 5 * 4 + 4 + 5 * 8 + 8
+    assert C.sizeof(lib.SliceInfo) == 3 * 8 + 5 * 4 + 4 + 5 * 8 + 4 + 4
 
 
 @pytest.mark.parametrize("bad", [
@@ -39,7 +39,8 @@ def test_struct_sizes_match_header_layout(lib):
     dict(ppc_side=5), dict(ppc_side=2, jitter=0.3), dict(dxi0=0.0), dict(refine_k=-1),
     dict(mg_max_cycles=0), dict(nu_pre=4), dict(nu_post=0), dict(adaptive=2),
     dict(adaptive=1, checkpoint_every=8), dict(adjoint_hold_dxi=2), dict(pusher=3),
-    dict(pusher="rk4", checkpoint_every=4, adaptive=0),
+    dict(pusher="rk4", checkpoint_every=4, adaptive=0), dict(laser_nz=-1),
+    dict(laser_nz=4, laser_k0=0.0), dict(laser_nz=4, laser_k0=5.0, checkpoint_every=4, adaptive=0),
 ])
 def test_invalid_configs_rejected(lib, bad):
     cfg = wi.scaled(wi.config("C2"), **bad)
@@ -65,6 +66,9 @@ def test_workspace_sizes_scale(lib):
     b5 = lib.workspace_bytes(wi.config("C5"), 4096)
     assert 0 < b1 < b2 < b5 < 2 * 1024**3
     assert b5 % 256 == 0
+    # a laser adds two sets of complex planes
+    bl = lib.workspace_bytes(wi.scaled(wi.config("C1"), laser_nz=10, laser_k0=5.0), 1)
+    assert bl >= b1 + 2 * 10 * 16 * 65 * 65
 
 
 def test_init_without_gpu_fails_cleanly(lib):
