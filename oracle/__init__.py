@@ -49,7 +49,7 @@ class Cfg(C.Structure):
                 ("n_beams", C.c_int), ("beams", C.POINTER(Beam)), ("pusher", C.c_int),
                 ("drv_planes", _dp), ("drv_nz", C.c_int), ("drv_xi0", C.c_double),
                 ("drv_dz", C.c_double), ("las_env", _dp), ("las_nz", C.c_int),
-                ("las_k0", C.c_double)]
+                ("las_k0", C.c_double), ("drv_nsub", C.c_int)]
 
 
 class Info(C.Structure):
@@ -111,6 +111,7 @@ class Oracle:
         c.mg_max_cycles, c.nu_pre, c.nu_post = cfg["mg_max_cycles"], cfg["nu_pre"], cfg["nu_post"]
         c.n_beams, c.beams = len(cfg["beams"]), beams
         c.pusher = PUSHERS[cfg.get("pusher", "boris")]
+        c.drv_nsub = int(cfg.get("driver_nsub", 1))
         self.c = c
         self.laser_env = None
 
@@ -190,15 +191,38 @@ class Oracle:
                                     C.c_double(dz), _p(out))
         return out.reshape(nz, self.N + 1, self.N + 1)
 
-    def driver_push(self, drv, dt, xi_s, F_s):
+    def driver_push(self, drv, dt, xi_s, F_s, env0=None, env1=None):
         """Advance driver particles drv [8][n] by dt through the slices
-        (xi_s [ns], F_s [ns][5][N+1][N+1]); returns the new state."""
+        (xi_s [ns], F_s [ns][5][N+1][N+1]) and, with env0 and env1 (the laser's
+        planes at t and t + dt, complex [nz][N+1][N+1]; k0 from set_laser), the
+        laser's fields, in driver_nsub sub-steps; returns the new state."""
         d = _f64(drv).reshape(8, -1).copy()
         xs = _f64(xi_s)
-        Fs = _f64(F_s).reshape(xs.size, 5, -1)
-        lib().oracle_driver_push(C.byref(self.c), C.c_double(dt), d.shape[1], _p(d), xs.size,
-                                 _p(xs), _p(Fs))
+        Fs = _f64(F_s).reshape(max(xs.size, 1), 5, -1)
+        e0 = None if env0 is None else np.ascontiguousarray(env0, dtype=np.complex128)
+        e1 = None if env1 is None else np.ascontiguousarray(env1, dtype=np.complex128)
+        c = Cfg.from_buffer_copy(self.c)
+        if e0 is not None:
+            c.las_nz = e0.shape[0]
+        st = lib().oracle_driver_push(C.byref(c), C.c_double(dt), d.shape[1], _p(d), xs.size,
+                                      _p(xs), _p(Fs), None if e0 is None else e0.ctypes.data_as(_dp),
+                                      None if e1 is None else e1.ctypes.data_as(_dp))
+        assert st == OK
         return d
+
+    def laser_fields(self, dt, tau, pts, env0, env1):
+        """The laser's fields at points pts [3][n] (x, y, xi) and time t + tau dt
+        from the planes env0 (t) and env1 (t + dt): [6][n] = E_x, E_y, E_z, B_x,
+        B_y, B_z (k0 from set_laser)."""
+        p = _f64(pts).reshape(3, -1)
+        e0 = np.ascontiguousarray(env0, dtype=np.complex128)
+        e1 = np.ascontiguousarray(env1, dtype=np.complex128)
+        c = Cfg.from_buffer_copy(self.c)
+        c.las_nz = e0.shape[0]
+        out = np.zeros((6, p.shape[1]))
+        lib().oracle_laser_fields(C.byref(c), C.c_double(dt), C.c_double(tau), p.shape[1], _p(p),
+                                  e0.ctypes.data_as(_dp), e1.ctypes.data_as(_dp), _p(out))
+        return out
 
     def time_step(self, state, drv, n_slices, dt, nz, xi0, dz, keep_fields=False):
         """One step of the time loop: the driver's current on nz planes, a sweep

@@ -86,6 +86,8 @@ typedef struct {
     const double* las_env;
     int las_nz;
     double las_k0;
+    /* sub-steps of the driver push per time step (0 or 1: one) */
+    int drv_nsub;
 } oracle_cfg;
 
 typedef struct {
@@ -1263,20 +1265,92 @@ void wake_at(const SliceStack& S, double x, double y, double xi, double (&E)[3],
     }
 }
 
-/* One step dt of eqs. (25)-(26) for one driver particle: a drift of dt/2,
- * a kick of dt/2 by qm E, the rotation of a Boris push about qm B/gamma, a
- * kick of dt/2 and a drift of dt/2 with the new momentum, the fields taken at
- * the mid-step position (a volume-preserving splitting of the relativistic
- * Lorentz-force flow).  In (x, y, xi): dx/dt = p_x/gamma, dy/dt = p_y/gamma,
+/* The high-frequency fields of the laser (Sec. IV, eqs. (21)-(24)) at (x, y,
+ * xi) and time t + tau dt, from the envelope planes at t (A0) and t + dt (A1)
+ * (x-polarised: A-hat is A-hat_x).  The envelope there is the interpolant
+ * linear in t between A0 and A1, linear in xi between the planes xi_m = m
+ * dxi0 around xi (planes outside [0, las_nz) are zero) and bilinear (CIC) in
+ * x, y; its derivatives are those of the interpolant.  With the phase
+ * e = exp(-i k0 xi):
+ *   E_x = Re[-(d_t A + d_xi A - i k0 A) e],  B_y = Re[(-d_xi A + i k0 A) e],
+ *   E_z = Re[-d_x A e],                      B_z = Re[-d_y A e],
+ * E_y = B_x = 0; zero outside the transverse box. */
+void laser_fields_at(const Grid& g, const oracle_cfg& c, const cplx* A0, const cplx* A1, double dt,
+                     double tau, double x, double y, double xi, double (&E)[3], double (&B)[3]) {
+    for (int q = 0; q < 3; ++q) E[q] = B[q] = 0.0;
+    if (std::fabs(x) > g.L || std::fabs(y) > g.L) return;
+    const int nn = g.nn();
+    int a, b;
+    double dx, dy;
+    cic(g, x, a, dx);
+    cic(g, y, b, dy);
+    const double t = xi / c.dxi0;
+    const double mf = std::floor(t);
+    const double wz = t - mf;
+    /* value, d/dx, d/dy of the bilinear interpolant of one plane */
+    auto plane = [&](const cplx* A, double q, cplx& v, cplx& vx, cplx& vy) {
+        v = vx = vy = cplx(0.0);
+        if (q < 0.0 || q >= c.las_nz) return;
+        const cplx* P = A + (size_t)q * nn;
+        const cplx f00 = P[g.id(a, b)], f10 = P[g.id(a + 1, b)];
+        const cplx f01 = P[g.id(a, b + 1)], f11 = P[g.id(a + 1, b + 1)];
+        v = f00 * ((1.0 - dx) * (1.0 - dy)) + f10 * (dx * (1.0 - dy)) + f01 * ((1.0 - dx) * dy) +
+            f11 * (dx * dy);
+        vx = ((f10 - f00) * (1.0 - dy) + (f11 - f01) * dy) / g.h;
+        vy = ((f01 - f00) * (1.0 - dx) + (f11 - f10) * dx) / g.h;
+    };
+    cplx v[2][2], vx[2][2], vy[2][2];  /* [time level][plane m, m + 1] */
+    const cplx* As[2] = {A0, A1};
+    for (int l = 0; l < 2; ++l)
+        for (int k = 0; k < 2; ++k) plane(As[l], mf + k, v[l][k], vx[l][k], vy[l][k]);
+    const double wt[2] = {1.0 - tau, tau}, wq[2] = {1.0 - wz, wz};
+    cplx A(0.0), At(0.0), Axi(0.0), Ax(0.0), Ay(0.0);
+    for (int l = 0; l < 2; ++l)
+        for (int k = 0; k < 2; ++k) {
+            A += (wt[l] * wq[k]) * v[l][k];
+            Ax += (wt[l] * wq[k]) * vx[l][k];
+            Ay += (wt[l] * wq[k]) * vy[l][k];
+        }
+    for (int k = 0; k < 2; ++k) At += wq[k] * (v[1][k] - v[0][k]) / dt;
+    for (int l = 0; l < 2; ++l) Axi += wt[l] * (v[l][1] - v[l][0]) / c.dxi0;
+    const cplx e(std::cos(c.las_k0 * xi), -std::sin(c.las_k0 * xi));
+    const cplx ik0A = cplx(0.0, c.las_k0) * A;
+    E[0] = std::real(-(At + Axi - ik0A) * e);
+    E[2] = std::real(-Ax * e);
+    B[1] = std::real((ik0A - Axi) * e);
+    B[2] = std::real(-Ay * e);
+}
+
+/* The laser's planes at t and t + dt seen by the driver push (both NULL: no
+ * laser fields). */
+struct LaserPair {
+    const cplx* A0;
+    const cplx* A1;
+};
+
+/* One sub-step of length d of the driver push below, at the fraction tau of
+ * the time step dt: a drift of d/2, a kick of d/2 by qm E, the rotation of a
+ * Boris push about qm B/gamma, a kick of d/2 and a drift of d/2 with the new
+ * momentum (a volume-preserving splitting of the relativistic Lorentz-force
+ * flow), with E, B = the wake (Ew, Bw) plus the laser's fields at the mid
+ * position.  In (x, y, xi): dx/dt = p_x/gamma, dy/dt = p_y/gamma,
  * dxi/dt = 1 - p_z/gamma. */
-void drive_one(const SliceStack& S, double dt, double* st) {
-    double g0 = std::sqrt(1.0 + st[DPX] * st[DPX] + st[DPY] * st[DPY] + st[DPZ] * st[DPZ]);
-    const double xh = st[DX] + 0.5 * dt * st[DPX] / g0;
-    const double yh = st[DY] + 0.5 * dt * st[DPY] / g0;
-    const double xih = st[DXI] + 0.5 * dt * (1.0 - st[DPZ] / g0);
-    double E[3], B[3];
-    wake_at(S, xh, yh, xih, E, B);
-    const double k = 0.5 * dt * st[DQM];
+void sub_step(const SliceStack& S, const LaserPair& las, const oracle_cfg& c, double d, double tau,
+              double dt, const double (&Ew)[3], const double (&Bw)[3], double* st) {
+    const double g0 = std::sqrt(1.0 + st[DPX] * st[DPX] + st[DPY] * st[DPY] + st[DPZ] * st[DPZ]);
+    const double xh = st[DX] + 0.5 * d * st[DPX] / g0;
+    const double yh = st[DY] + 0.5 * d * st[DPY] / g0;
+    const double xih = st[DXI] + 0.5 * d * (1.0 - st[DPZ] / g0);
+    double E[3] = {Ew[0], Ew[1], Ew[2]}, B[3] = {Bw[0], Bw[1], Bw[2]};
+    if (las.A0) {
+        double El[3], Bl[3];
+        laser_fields_at(*S.g, c, las.A0, las.A1, dt, tau, xh, yh, xih, El, Bl);
+        for (int q = 0; q < 3; ++q) {
+            E[q] += El[q];
+            B[q] += Bl[q];
+        }
+    }
+    const double k = 0.5 * d * st[DQM];
     double m[3] = {st[DPX] + k * E[0], st[DPY] + k * E[1], st[DPZ] + k * E[2]};
     const double gm = std::sqrt(1.0 + m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
     const double t[3] = {k * B[0] / gm, k * B[1] / gm, k * B[2] / gm};
@@ -1290,9 +1364,26 @@ void drive_one(const SliceStack& S, double dt, double* st) {
     st[DPY] = pp[1] + k * E[1];
     st[DPZ] = pp[2] + k * E[2];
     const double g1 = std::sqrt(1.0 + st[DPX] * st[DPX] + st[DPY] * st[DPY] + st[DPZ] * st[DPZ]);
-    st[DX] = xh + 0.5 * dt * st[DPX] / g1;
-    st[DY] = yh + 0.5 * dt * st[DPY] / g1;
-    st[DXI] = xih + 0.5 * dt * (1.0 - st[DPZ] / g1);
+    st[DX] = xh + 0.5 * d * st[DPX] / g1;
+    st[DY] = yh + 0.5 * d * st[DPY] / g1;
+    st[DXI] = xih + 0.5 * d * (1.0 - st[DPZ] / g1);
+}
+
+/* One step dt of eqs. (25)-(26) for one driver particle in c.drv_nsub
+ * sub-steps (the sub-cycling of Sec. IV that resolves the laser's
+ * oscillation).  The wake is gathered once, at the mid-step position of the
+ * whole step (it changes over the step only as the particle moves through
+ * it), the laser's fields (laser_fields_at) at every sub-step's mid position
+ * and time. */
+void drive_one(const SliceStack& S, const LaserPair& las, const oracle_cfg& c, double dt,
+               double* st) {
+    const int nsub = c.drv_nsub > 1 ? c.drv_nsub : 1;
+    const double g0 = std::sqrt(1.0 + st[DPX] * st[DPX] + st[DPY] * st[DPY] + st[DPZ] * st[DPZ]);
+    double Ew[3], Bw[3];
+    wake_at(S, st[DX] + 0.5 * dt * st[DPX] / g0, st[DY] + 0.5 * dt * st[DPY] / g0,
+            st[DXI] + 0.5 * dt * (1.0 - st[DPZ] / g0), Ew, Bw);
+    const double d = dt / nsub;
+    for (int sub = 0; sub < nsub; ++sub) sub_step(S, las, c, d, (sub + 0.5) / nsub, dt, Ew, Bw, st);
 }
 
 }  // namespace
@@ -1337,19 +1428,24 @@ int oracle_driver_deposit(const oracle_cfg* c, int n, const double* st, int nz, 
 }
 
 /* Advance n driver particles (state [8][n], updated) by dt through the wake
- * of ns solved slices at positions xi_s[ns] with fields F_s [ns][5][nn]. */
+ * of ns solved slices at positions xi_s[ns] with fields F_s [ns][5][nn] and,
+ * when env0 and env1 are given (the laser's planes at t and t + dt, complex
+ * [las_nz][nn]), the laser's fields, in c->drv_nsub sub-steps. */
 int oracle_driver_push(const oracle_cfg* c, double dt, int n, double* st, int ns,
-                       const double* xi_s, const double* F_s) {
+                       const double* xi_s, const double* F_s, const double* env0,
+                       const double* env1) {
     Grid g(c->n_cells, c->half_width);
     const int nn = g.nn();
+    if ((env0 == nullptr) != (env1 == nullptr)) return ORC_INVALID;
     std::vector<std::vector<double>> gx(ns), gy(ns);
     for (int j = 0; j < ns; ++j) psi_gradient(g, F_s + (size_t)j * 5 * nn, gx[j], gy[j]);
     const SliceStack S{&g, ns, xi_s, F_s, gx.data(), gy.data()};
+    const LaserPair las{reinterpret_cast<const cplx*>(env0), reinterpret_cast<const cplx*>(env1)};
 #pragma omp parallel for schedule(static)
     for (int p = 0; p < n; ++p) {
         double v[DNV];
         for (int q = 0; q < DNV; ++q) v[q] = st[(size_t)q * n + p];
-        drive_one(S, dt, v);
+        drive_one(S, las, *c, dt, v);
         for (int q = 0; q < DNV; ++q) st[(size_t)q * n + p] = v[q];
     }
     return ORC_OK;
@@ -1379,6 +1475,25 @@ int oracle_laser_advance(const oracle_cfg* c, double dt, int nz, const double* e
     return ORC_OK;
 }
 
+/* The laser's fields (laser_fields_at) at n points pts [3][n] (x, y, xi) and
+ * time t + tau dt from the planes env0 (t) and env1 (t + dt): out [6][n] =
+ * E_x, E_y, E_z, B_x, B_y, B_z. */
+int oracle_laser_fields(const oracle_cfg* c, double dt, double tau, int n, const double* pts,
+                        const double* env0, const double* env1, double* out) {
+    Grid g(c->n_cells, c->half_width);
+    const cplx* A0 = reinterpret_cast<const cplx*>(env0);
+    const cplx* A1 = reinterpret_cast<const cplx*>(env1);
+    for (int p = 0; p < n; ++p) {
+        double E[3], B[3];
+        laser_fields_at(g, *c, A0, A1, dt, tau, pts[p], pts[n + p], pts[2 * n + p], E, B);
+        for (int q = 0; q < 3; ++q) {
+            out[(size_t)q * n + p] = E[q];
+            out[(size_t)(3 + q) * n + p] = B[q];
+        }
+    }
+    return ORC_OK;
+}
+
 /* One step of the time loop (Algorithm 1, outer loop): the driver's current
  * on nz planes (xi0, dz), a sweep of n_slices slices through the plasma given
  * (normally the cold plasma at xi = 0 with zero fields, advanced in place)
@@ -1389,8 +1504,9 @@ int oracle_laser_advance(const oracle_cfg* c, double dt, int nz, const double* e
  * the plasma sees it, and env_next (non-NULL, [las_nz][nn] complex) receives
  * the planes at t + dt: each plane j is advanced (laser_plane_advance) right
  * after slice j, with that slice's susceptibility chi = n* / (1+psi) (the k2 of
- * its B-perp system).  This needs fixed steps (adaptive = 0, so that slice j
- * lies on plane j) and n_slices >= las_nz. */
+ * its B-perp system); the driver push then adds the laser's fields from both
+ * sets of planes.  This needs fixed steps (adaptive = 0, so that slice j lies
+ * on plane j) and n_slices >= las_nz. */
 int oracle_time_step(const oracle_cfg* c, int P, double* x, double* y, double* px, double* py,
                      double* fields, double* xi, double* dxi, int n_slices, int n_drv,
                      double* drv, int nz, double xi0, double dz, double dt, double* xi_hist,
@@ -1424,7 +1540,8 @@ int oracle_time_step(const oracle_cfg* c, int P, double* x, double* y, double* p
                                          A1 + (size_t)j * nn, nullptr, nullptr);
     }
     if (status != ORC_OK) return status;
-    oracle_driver_push(c, dt, n_drv, drv, n_slices, hx.data(), hF.data());
+    oracle_driver_push(c, dt, n_drv, drv, n_slices, hx.data(), hF.data(), las ? c->las_env : nullptr,
+                       las ? env_next : nullptr);
     if (xi_hist) std::copy(hx.begin(), hx.end(), xi_hist);
     if (fields_hist) std::copy(hF.begin(), hF.end(), fields_hist);
     return ORC_OK;
