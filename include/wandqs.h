@@ -162,6 +162,8 @@ typedef struct {
                                  xi_m = m dxi0 (wandqs_laser_set) and the time loop
                                  that advances it; 0: none.  Not with a tape. */
     double laser_k0;          /* carrier wavenumber k0 = omega0/omega_p (> 0 with a laser) */
+    int32_t driver_nsub;      /* sub-steps of the driver push per time step, 0 .. 4096
+                                 (0 or 1: one); see wandqs_time_step */
 } wandqs_config;
 
 typedef struct {
@@ -239,10 +241,19 @@ wandqs_status wandqs_set_state(wandqs_ctx* ctx, const double* d_particles,
  * xi + (dt/2)(1 - v_z) from the two slices that bracket it (CIC in each,
  * linear in xi; zero ahead of the first slice, at or behind the last and
  * outside the box), with E = (-d_x psi + B_y, -d_y psi - B_x, Ez) and B =
- * (Bx, By, Bz); finally every driver particle advances by dt with a drift of
- * dt/2, a kick dt/2, the rotation of a Boris push about (q/m) B / gamma, a kick
- * dt/2 and a drift dt/2.  The fields and plasma state after the call are those
- * of the last slice.  WANDQS_E_INVALID without driver_max. */
+ * (Bx, By, Bz); finally every driver particle advances by dt in driver_nsub
+ * sub-steps d = dt / driver_nsub (the sub-cycling of Sec. IV), each a drift of
+ * d/2, a kick d/2, the rotation of a Boris push about (q/m) B / gamma, a kick
+ * d/2 and a drift d/2, with E, B = that wake plus, with a laser set (see
+ * wandqs_laser_set), the laser's fields of eqs. (21)-(24) at the sub-step's mid
+ * position and time: x-polarised, from the envelope interpolated linearly in t
+ * between the planes at t and t + dt, linearly in xi between planes and
+ * bilinearly in x, y, with e = exp(-i k0 xi),
+ *   E_x = Re[-(d_t A + d_xi A - i k0 A) e],  B_y = Re[(-d_xi A + i k0 A) e],
+ *   E_z = Re[-d_x A e],  B_z = Re[-d_y A e],  E_y = B_x = 0
+ * (derivatives of that interpolant; zero outside the box).  The fields and
+ * plasma state after the call are those of the last slice.  WANDQS_E_INVALID
+ * without driver_max or laser_nz. */
 wandqs_status wandqs_driver_set(wandqs_ctx* ctx, int64_t n, const double* d_state);
 
 /* Laser driver (Sec. IV, eq. (20); contexts made with laser_nz > 0).  The

@@ -85,6 +85,7 @@ const char* check_config(const wandqs_config* c, int32_t n_slices) {
         if (c->checkpoint_every > 0) return "the time loop (driver_max > 0) has no adjoint tape";
     }
     if (c->laser_nz < 0 || c->laser_nz > 65536) return "laser_nz must be in [0, 65536]";
+    if (c->driver_nsub < 0 || c->driver_nsub > 4096) return "driver_nsub must be in [0, 4096]";
     if (c->laser_nz > 0) {
         if (!(c->laser_k0 > 0.0) || !std::isfinite(c->laser_k0)) return "a laser needs laser_k0 > 0";
         if (c->checkpoint_every > 0) return "a laser envelope (laser_nz > 0) has no adjoint tape";
@@ -972,8 +973,9 @@ wandqs_status wandqs_time_step(wandqs_ctx* c, double dt, int32_t n_slices, wandq
     c->drv_active = false;
     c->las_adv = false;
     if (s != WANDQS_OK) return s;
-    if (c->las_on) c->las_cur = 1 - c->las_cur;  // the planes at t + dt
+    // the driver push takes the laser's fields from the planes at t and t + dt
     if (drv && (s = driver_push(c, dt)) != WANDQS_OK) return fail(c, s);
+    if (c->las_on) c->las_cur = 1 - c->las_cur;  // the planes at t + dt
     return WANDQS_OK;
 }
 

@@ -58,7 +58,7 @@ class Config(C.Structure):
                 ("mg_omega_helm", C.c_double), ("adjoint_hold_dxi", C.c_int32),
                 ("pusher", C.c_int32), ("driver_max", C.c_int32), ("driver_nz", C.c_int32),
                 ("driver_xi0", C.c_double), ("driver_dz", C.c_double), ("laser_nz", C.c_int32),
-                ("laser_k0", C.c_double)]
+                ("laser_k0", C.c_double), ("driver_nsub", C.c_int32)]
 
 
 class KernelStat(C.Structure):
@@ -179,6 +179,7 @@ def make_config(cfg: dict):
     c.driver_dz = float(cfg.get("driver_dz", 0.0))
     c.laser_nz = int(cfg.get("laser_nz", 0))
     c.laser_k0 = float(cfg.get("laser_k0", 0.0))
+    c.driver_nsub = int(cfg.get("driver_nsub", 0))
     return c, keep
 
 

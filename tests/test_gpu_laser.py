@@ -10,7 +10,9 @@
   and in S), Boris-like and RK4 pushers: fields to 1e-10 (both field
   measures), particles to 1e-10;
 * the time loop with a laser: each plane advanced right after its slice with
-  that slice's chi, two steps: envelope, fields and particles as above.
+  that slice's chi, two steps: envelope, fields and particles as above; with
+  driver particles pushed through the laser's fields in 16 sub-steps: their
+  positions to 1e-10, momenta to 1e-9 of their largest change.
 """
 import numpy as np
 import pytest
@@ -140,4 +142,45 @@ def test_laser_time_step_needs_fixed_steps(torch_cuda):
     sim.laser_set(wi.laser_gaussian(N, 6.0, nz, 0.1, 0.5, 1.5, 0.3, 0.3))
     with pytest.raises(WandQSError):  # fewer slices than planes
         sim.time_step(1.0, nz - 1)
+    sim.close()
+
+
+def test_time_step_laser_and_subcycled_driver_match_oracle(torch_cuda, oracle_mod):
+    """Driver particles inside the laser (gamma 30): the push adds the laser's
+    fields from the planes at t and t + dt in 16 sub-steps (Sec. IV)."""
+    from paper_2012_00881_amd import Simulation
+    N, L, dxi, nz, k0, dt = 64, 6.0, 0.1, 40, 8.0, 4.0
+    print("[case] time loop, laser and sub-cycled driver N=64", flush=True)
+    beam = wi.gauss_beam(0.05, 0.8, 0.4, 1.8)
+    drv = wi.driver_gaussian(beam, 20_000, 41, gamma0=30.0)
+    cfg = _cfg(N, L, nz, k0, dxi0=dxi, ppc_side=2, driver_max=drv.shape[1], driver_nz=45,
+               driver_xi0=-0.1, driver_dz=0.1, driver_nsub=16)
+    env = wi.laser_gaussian(N, L, nz, dxi, 0.7, 1.5, 1.8, 0.6)
+    o = oracle_mod.Oracle(cfg)
+    o.set_laser(env, k0)
+    sim = Simulation(cfg, n_slices=nz)
+    sim.laser_set(env)
+    sim.driver_set(drv)
+    d_orc = drv.copy()
+    for step in range(2):
+        st = oracle_mod.initial_state(cfg)
+        r = o.time_step(st, d_orc, nz, dt, cfg["driver_nz"], cfg["driver_xi0"], cfg["driver_dz"])
+        assert r["status"] == 0
+        sim.time_step(dt, nz)
+        got = sim.get_state()
+        check_fields(got["fields"].cpu().numpy(), st["fields"], FIELD_TOL, f"laser+driver step {step}")
+        e = _env_err(sim.laser_get().cpu().numpy(), o.laser_env)
+        d_gpu = sim.driver_get().cpu().numpy()
+        dpos = np.abs(d_gpu[:3] - d_orc[:3]).max()
+        scale = np.abs(d_orc[3:6] - drv[3:6]).max()
+        dmom = np.abs(d_gpu[3:6] - d_orc[3:6]).max()
+        print(f"step {step}: envelope {e:.2e}, driver positions {dpos:.2e}, momenta {dmom:.2e} "
+              f"(largest change {scale:.3e})", flush=True)
+        assert e <= ENV_TOL
+        assert dpos <= 1e-10
+        assert dmom <= 1e-9 * scale
+    # the laser's oscillating field moves the particles: p_x (the polarisation)
+    # quivers by about a0, more than the wake moves p_y
+    dpx, dpy = np.abs(d_orc[3] - drv[3]).max(), np.abs(d_orc[4] - drv[4]).max()
+    assert dpx > 0.5 and dpx > 1.3 * dpy
     sim.close()
