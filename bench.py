@@ -253,6 +253,49 @@ def forms_timing(cfg: dict, win: dict, S: int, rtol: float):
     return out
 
 
+def laser_timing(cfg: dict, S: int):
+    """The laser-driven time loop on the workload's grid and plasma: a Gaussian
+    laser (a0 = 2, w0 = 3, sigma_z = 1, k0 = 20) on S envelope planes with fixed
+    steps dxi = 0.02, one time step dt = 10 (the plasma swept through the S
+    slices, each advancing its envelope plane): ms per slice, the envelope's
+    multigrid cycles per plane, and a profiled step's split between the
+    envelope kernels and the rest."""
+    import torch
+    import wandqs_inputs as wi
+    from paper_2012_00881_amd import Simulation
+    dxi, k0, dt = 0.02, 20.0, 10.0
+    c = wi.scaled(cfg, beams=[], adaptive=0, dxi0=dxi, laser_nz=S, laser_k0=k0)
+    env = wi.laser_gaussian(c["n_cells"], c["half_width"], S, dxi, 2.0, 3.0, 0.5 * S * dxi, 1.0)
+    env_t = torch.as_tensor(env, device="cuda")
+    res = {"slices": S, "dxi": dxi, "dt": dt, "k0": k0, "a0": 2.0, "w0": 3.0, "sigma_z": 1.0}
+    sim = Simulation(c, n_slices=S)
+    sim.laser_set(env_t)
+    print(f"[bench] laser: warm-up time step of {S} slices", file=sys.stderr, flush=True)
+    sim.time_step(dt, S)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = sim.time_step(dt, S, infos=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter() - t0
+    res["ms_per_slice"] = 1e3 * t1 / S
+    res["value"] = sim.P * S / t1
+    res["unit"] = "particle-slice updates/s (with the envelope advance)"
+    res["mean_laser_vcycles"] = sum(i["laser_vcycles"] for i in infos) / S
+    res["mean_vcycles"] = [round(sum(i["vcycles"][k] for i in infos) / S, 3) for k in range(5)]
+    sim.profile(True)
+    sim.time_step(dt, S)
+    st = sim.kernel_stats()
+    sim.close()
+    tot = sum(x["total_ms"] for x in st)
+    las = [x for x in st if x["name"].startswith("k_las")]
+    lms = sum(x["total_ms"] for x in las)
+    res["laser_kernel_share"] = round(lms / tot, 4)
+    res["laser_kernel_ms_per_slice"] = round(lms / S, 4)
+    res["laser_alg_GBps"] = round(sum(x["alg_bytes"] for x in las) / (lms * 1e-3) / 1e9, 1)
+    print(f"[bench] laser: {res}", file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,6 +324,8 @@ def main():
     ap.add_argument("--checkpoint-every", type=int, default=32)
     ap.add_argument("--pusher-steps", type=int, default=128,
                     help="slices timed from the window with each Runge-Kutta pusher (0: skip)")
+    ap.add_argument("--laser-steps", type=int, default=256,
+                    help="envelope planes (slices) of the laser-driven time step (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times (the "
                          "reference for scaling hardware byte counters)")
@@ -429,6 +474,10 @@ def main():
         pushers["steps"] = args.pusher_steps
         print(f"[bench] pushers: {pushers}", file=sys.stderr, flush=True)
 
+    laser = None
+    if args.laser_steps > 0:
+        laser = laser_timing(cfg, args.laser_steps)
+
     adjoint = None
     if args.adjoint_steps > 0:
         adjoint = adjoint_timing(cfg, win, args.adjoint_steps, args.checkpoint_every)
@@ -452,7 +501,7 @@ def main():
                        "lead_in_slices": lead, "xi_start": win["xi"], "xi_end": final["xi"],
                        "mean_vcycles": [round(c, 3) for c in cyc]},
             "roofline": roof, "vcycle_hbm": vcycle, "cpu_baseline": cpu, "forms": forms,
-            "adjoint": adjoint, "pushers": pushers}
+            "adjoint": adjoint, "pushers": pushers, "laser": laser}
     print(json.dumps(line), flush=True)
 
 
