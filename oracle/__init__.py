@@ -458,3 +458,59 @@ def push(L, dxi, g_i, gx, gy, Bx, By, Bz, x, y, px, py):
     lib().oracle_push(C.c_double(L), C.c_double(dxi), arrs[0].size, *[_p(a) for a in ins],
                       *[_p(a) for a in arrs])
     return arrs
+
+
+# ------------------------------------------------- non-uniform grids (Sec. VII.B)
+def _axes(X, Y):
+    X, Y = _f64(X), _f64(Y)
+    assert X.size == Y.size
+    return X.size - 1, X, Y
+
+
+def nu_apply(X, Y, u, M=None):
+    """L u (the non-uniform grid's nine-point operator with the third-order
+    correction, plus the M terms) at the interior nodes; u, M: [N+1][N+1]
+    indexed [j][i] (y, x)."""
+    N, X, Y = _axes(X, Y)
+    u = _f64(u)
+    out = np.zeros_like(u)
+    st = lib().oracle_nu_apply(N, _p(X), _p(Y), _p(None if M is None else _f64(M)), _p(u), _p(out))
+    assert st == OK
+    return out
+
+
+def nu_rhs(X, Y, J):
+    """R J, the right-hand side of the discrete equation L u = R J."""
+    N, X, Y = _axes(X, Y)
+    J = _f64(J)
+    out = np.zeros_like(J)
+    assert lib().oracle_nu_rhs(N, _p(X), _p(Y), _p(J), _p(out)) == OK
+    return out
+
+
+def nu_restrict(X, Y, v):
+    N, X, Y = _axes(X, Y)
+    out = np.zeros((N // 2 + 1, N // 2 + 1))
+    assert lib().oracle_nu_transfer(N, _p(X), _p(Y), 0, _p(_f64(v)), _p(out)) == OK
+    return out
+
+
+def nu_prolong(X, Y, e):
+    N, X, Y = _axes(X, Y)
+    out = np.zeros((N + 1, N + 1))
+    assert lib().oracle_nu_transfer(N, _p(X), _p(Y), 1, _p(_f64(e)), _p(out)) == OK
+    return out
+
+
+def nu_mg_solve(X, Y, J, u0=None, M=None, rtol=1e-14, atol=0.0, max_cycles=60, nu1=2, nu2=2):
+    """Multigrid solve of L u = R J on the non-uniform grid (X, Y), u = 0 on the
+    boundary, from the guess u0 (default 0).  Returns (status, u, cycles, rel)."""
+    N, X, Y = _axes(X, Y)
+    J = _f64(J)
+    u = np.zeros_like(J) if u0 is None else _f64(u0).copy()
+    cyc = C.c_int(0)
+    rel = C.c_double(0)
+    st = lib().oracle_nu_mg_solve(N, _p(X), _p(Y), _p(None if M is None else _f64(M)), _p(J),
+                                  _p(u), C.c_double(rtol), C.c_double(atol), int(max_cycles),
+                                  int(nu1), int(nu2), C.byref(cyc), C.byref(rel))
+    return st, u, cyc.value, rel.value

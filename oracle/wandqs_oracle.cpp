@@ -1990,3 +1990,350 @@ int oracle_run_loss(const oracle_cfg* c, int P, double* x, double* y, double* px
 }
 
 } /* extern "C" */
+
+/* ============================================== non-uniform grids == */
+/*
+ * Sec. VII.B: the transverse operator on a non-uniform tensor grid x_0 < x_1
+ * < ... < x_N (and y_0 < ... < y_N), the general wakefield equation
+ * lap u + M u = J with u = 0 on the boundary nodes.
+ *
+ * Along x at an interior node i, with h- = x_i - x_{i-1}, h+ = x_{i+1} - x_i,
+ * ha = h+ + h-, hb = h+ - h-:
+ *   Dxx u = 2 (h+ u_{i-1} - ha u_i + h- u_{i+1}) / (h- h+ ha),
+ *   dx u  = h-/(ha h+) (u_{i+1} - u_i) + h+/(ha h-) (u_i - u_{i-1})
+ * (the second-order three-point derivative of Sec. VII.B).  A Taylor expansion
+ * gives Dxx u = u_xx + (hb/3) u_xxx + O(h^2), so u_xx = Dxx u - (hb/3) u_xxx
+ * (the printed eq. (34) has the opposite sign; the expansion decides).  The
+ * third derivatives follow eq. (36): hb_x u_xxx + hb_y u_yyy =
+ * (hb_x dx + hb_y dy)(lap u) - hb_x dx(u_yy) - hb_y dy(u_xx) with lap u =
+ * J - M u, u_yy ~ Dyy u and u_xx ~ Dxx u, so the discrete equation is
+ *   L u = R J,
+ *   L u = Dxx u + Dyy u + (1/3)[hb_x dx(Dyy u) + hb_y dy(Dxx u)]
+ *         + (1/3)(hb_x dx + hb_y dy)(M u) + M u,
+ *   R J = J + (1/3)(hb_x dx + hb_y dy) J,
+ * a nine-point operator (dx(Dyy u) reaches the diagonal neighbours), not
+ * symmetric.  On a uniform grid hb = 0 and L is the 5-point Laplacian plus M.
+ *
+ * Multigrid: the coarse grid keeps every other node, L is rediscretised on it;
+ * prolongation is linear interpolation in the coordinates, restriction its
+ * transpose weighted by the control volumes V_i = (x_{i+1} - x_{i-1})/2 (the
+ * transfers weighted by the neighbouring cells' sizes, Sec. VII.B), in each
+ * direction; M is restricted the same way.  Smoothing: Gauss-Seidel in four
+ * colours (i mod 2, j mod 2), each node of a colour taking u += (F - L u)/d
+ * with d the coefficient of u_ij in its own equation (the nine-point stencil
+ * couples no two nodes of one colour); exact on the single interior node of
+ * the 2-cell grid.
+ */
+namespace {
+
+/* The 1-D coefficients of one interior index: Dxx weights (i-1, i, i+1),
+ * first-derivative weights (i-1, i, i+1) and hb. */
+struct AxisCoef {
+    double d2[3], d1[3], hb;
+};
+
+AxisCoef axis_coef(const std::vector<double>& X, int i) {
+    AxisCoef c;
+    const double hm = X[i] - X[i - 1], hp = X[i + 1] - X[i], ha = hm + hp;
+    c.d2[0] = 2.0 * hp / (hm * hp * ha);
+    c.d2[1] = -2.0 * ha / (hm * hp * ha);
+    c.d2[2] = 2.0 * hm / (hm * hp * ha);
+    c.d1[0] = -hp / (ha * hm);
+    c.d1[1] = -hm / (ha * hp) + hp / (ha * hm);
+    c.d1[2] = hm / (ha * hp);
+    c.hb = hp - hm;
+    return c;
+}
+
+struct NuLevel {
+    int N;
+    std::vector<double> X, Y;
+    std::vector<AxisCoef> cx, cy;  /* [N+1], interior entries used */
+    std::vector<double> u, F, M;   /* (N+1)^2, node (i, j) at j (N+1) + i */
+    int id(int i, int j) const { return j * (N + 1) + i; }
+    void build(int n, std::vector<double> x, std::vector<double> y) {
+        N = n;
+        X = std::move(x);
+        Y = std::move(y);
+        cx.assign(N + 1, AxisCoef{});
+        cy.assign(N + 1, AxisCoef{});
+        for (int i = 1; i < N; ++i) {
+            cx[i] = axis_coef(X, i);
+            cy[i] = axis_coef(Y, i);
+        }
+        u.assign((size_t)(N + 1) * (N + 1), 0.0);
+        F = u;
+        M = u;
+    }
+};
+
+/* Dxx u at (i, j) and Dyy u at (i, j) for i, j interior in that direction;
+ * zero on a boundary line (u = 0 there). */
+double nu_dxx(const NuLevel& l, const std::vector<double>& u, int i, int j) {
+    if (i <= 0 || i >= l.N) return 0.0;
+    const AxisCoef& c = l.cx[i];
+    return c.d2[0] * u[l.id(i - 1, j)] + c.d2[1] * u[l.id(i, j)] + c.d2[2] * u[l.id(i + 1, j)];
+}
+double nu_dyy(const NuLevel& l, const std::vector<double>& u, int i, int j) {
+    if (j <= 0 || j >= l.N) return 0.0;
+    const AxisCoef& c = l.cy[j];
+    return c.d2[0] * u[l.id(i, j - 1)] + c.d2[1] * u[l.id(i, j)] + c.d2[2] * u[l.id(i, j + 1)];
+}
+
+/* (L u) at the interior node (i, j). */
+double nu_apply_at(const NuLevel& l, const std::vector<double>& u, int i, int j) {
+    const AxisCoef &a = l.cx[i], &b = l.cy[j];
+    auto Mu = [&](int p, int q) { return l.M[l.id(p, q)] * u[l.id(p, q)]; };
+    double s = nu_dxx(l, u, i, j) + nu_dyy(l, u, i, j);
+    s += (a.hb * (a.d1[0] * nu_dyy(l, u, i - 1, j) + a.d1[1] * nu_dyy(l, u, i, j) +
+                  a.d1[2] * nu_dyy(l, u, i + 1, j)) +
+          b.hb * (b.d1[0] * nu_dxx(l, u, i, j - 1) + b.d1[1] * nu_dxx(l, u, i, j) +
+                  b.d1[2] * nu_dxx(l, u, i, j + 1))) / 3.0;
+    s += (a.hb * (a.d1[0] * Mu(i - 1, j) + a.d1[1] * Mu(i, j) + a.d1[2] * Mu(i + 1, j)) +
+          b.hb * (b.d1[0] * Mu(i, j - 1) + b.d1[1] * Mu(i, j) + b.d1[2] * Mu(i, j + 1))) / 3.0;
+    return s + Mu(i, j);
+}
+
+/* The coefficient of u_ij in its own equation. */
+double nu_diag(const NuLevel& l, int i, int j) {
+    const AxisCoef &a = l.cx[i], &b = l.cy[j];
+    const double m = l.M[l.id(i, j)];
+    return a.d2[1] + b.d2[1] + (a.hb * a.d1[1] * b.d2[1] + b.hb * b.d1[1] * a.d2[1]) / 3.0 +
+           (a.hb * a.d1[1] + b.hb * b.d1[1]) * m / 3.0 + m;
+}
+
+void nu_relax(NuLevel& l, int nu) {
+    for (int s = 0; s < nu; ++s)
+        for (int color = 0; color < 4; ++color) {
+            const int pi = color & 1, pj = color >> 1;
+#pragma omp parallel for schedule(static)
+            for (int j = 1; j < l.N; ++j) {
+                if ((j & 1) != pj) continue;
+                for (int i = 1; i < l.N; ++i) {
+                    if ((i & 1) != pi) continue;
+                    const double r = l.F[l.id(i, j)] - nu_apply_at(l, l.u, i, j);
+                    l.u[l.id(i, j)] += r / nu_diag(l, i, j);
+                }
+            }
+        }
+}
+
+void nu_residual(const NuLevel& l, std::vector<double>& r) {
+    r.assign(l.u.size(), 0.0);
+#pragma omp parallel for schedule(static)
+    for (int j = 1; j < l.N; ++j)
+        for (int i = 1; i < l.N; ++i) r[l.id(i, j)] = l.F[l.id(i, j)] - nu_apply_at(l, l.u, i, j);
+}
+
+/* 1-D transfer weights between fine node 2I + s (s = -1, 0, 1) and coarse
+ * node I: prolongation P (linear interpolation in the coordinate) and the
+ * volume-weighted restriction V_f P / V_c. */
+double prol_w(const std::vector<double>& X, int I, int s) {
+    if (s == 0) return 1.0;
+    const int f = 2 * I + s;  /* odd fine node between coarse I and I + s */
+    const double lo = X[f - 1], hi = X[f + 1];
+    return s > 0 ? (hi - X[f]) / (hi - lo) : (X[f] - lo) / (hi - lo);
+}
+double rest_w(const std::vector<double>& X, int I, int s) {
+    const int f = 2 * I + s;
+    const double Vf = 0.5 * (X[f + 1] - X[f - 1]);
+    const double Vc = 0.5 * (X[2 * I + 2] - X[2 * I - 2]);
+    return prol_w(X, I, s) * Vf / Vc;
+}
+
+/* out (coarse, interior nodes) = restriction of the fine node array in. */
+void nu_restrict(const NuLevel& f, const std::vector<double>& in, const NuLevel& c,
+                 std::vector<double>& out) {
+    out.assign((size_t)(c.N + 1) * (c.N + 1), 0.0);
+#pragma omp parallel for schedule(static)
+    for (int J = 1; J < c.N; ++J)
+        for (int I = 1; I < c.N; ++I) {
+            double s = 0.0;
+            for (int sy = -1; sy <= 1; ++sy)
+                for (int sx = -1; sx <= 1; ++sx)
+                    s += rest_w(f.X, I, sx) * rest_w(f.Y, J, sy) * in[f.id(2 * I + sx, 2 * J + sy)];
+            out[c.id(I, J)] = s;
+        }
+}
+
+/* fine u += prolongation of the coarse array e (interior fine nodes). */
+void nu_prolong_add(const NuLevel& c, const std::vector<double>& e, NuLevel& f) {
+#pragma omp parallel for schedule(static)
+    for (int j = 1; j < f.N; ++j)
+        for (int i = 1; i < f.N; ++i) {
+            /* the coarse nodes around fine node i: I = i/2 (and I+1 when i is odd) */
+            const int I = i / 2, J = j / 2;
+            const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1;
+            double v = 0.0;
+            for (int q = 0; q < nj; ++q)
+                for (int p = 0; p < ni; ++p) {
+                    /* weight of coarse node I + p seen from fine node i = 2(I+p) + s */
+                    const double wx = (i & 1) ? prol_w(f.X, I + p, p ? -1 : 1) : 1.0;
+                    const double wy = (j & 1) ? prol_w(f.Y, J + q, q ? -1 : 1) : 1.0;
+                    v += wx * wy * e[c.id(I + p, J + q)];
+                }
+            f.u[f.id(i, j)] += v;
+        }
+}
+
+double nu_norm(const NuLevel& l, const std::vector<double>& v) {
+    double s = 0.0;
+    for (int j = 1; j < l.N; ++j)
+        for (int i = 1; i < l.N; ++i) s += v[l.id(i, j)] * v[l.id(i, j)];
+    return std::sqrt(s);
+}
+
+void nu_vcycle(std::vector<NuLevel>& lv, size_t k, int nu1, int nu2) {
+    NuLevel& L = lv[k];
+    if (L.N == 2) {
+        L.u[L.id(1, 1)] = L.F[L.id(1, 1)] / nu_diag(L, 1, 1);
+        return;
+    }
+    nu_relax(L, nu1);
+    std::vector<double> r;
+    nu_residual(L, r);
+    NuLevel& C = lv[k + 1];
+    nu_restrict(L, r, C, C.F);
+    std::fill(C.u.begin(), C.u.end(), 0.0);
+    nu_vcycle(lv, k + 1, nu1, nu2);
+    nu_prolong_add(C, C.u, L);
+    nu_relax(L, nu2);
+}
+
+std::vector<NuLevel> nu_levels(int N, const double* X, const double* Y, const double* M) {
+    std::vector<NuLevel> lv;
+    std::vector<double> x(X, X + N + 1), y(Y, Y + N + 1);
+    for (int n = N; n >= 2; n /= 2) {
+        NuLevel l;
+        l.build(n, x, y);
+        lv.push_back(std::move(l));
+        std::vector<double> xc, yc;
+        for (int i = 0; i <= n; i += 2) {
+            xc.push_back(x[i]);
+            yc.push_back(y[i]);
+        }
+        x.swap(xc);
+        y.swap(yc);
+    }
+    if (M) {
+        for (int j = 1; j < N; ++j)
+            for (int i = 1; i < N; ++i) lv[0].M[lv[0].id(i, j)] = M[(size_t)j * (N + 1) + i];
+        for (size_t k = 1; k < lv.size(); ++k) nu_restrict(lv[k - 1], lv[k - 1].M, lv[k], lv[k].M);
+    }
+    return lv;
+}
+
+/* R J at the interior nodes (zero on the boundary). */
+void nu_rhs(const NuLevel& l, const double* J, std::vector<double>& F) {
+    F.assign(l.u.size(), 0.0);
+    for (int j = 1; j < l.N; ++j)
+        for (int i = 1; i < l.N; ++i) {
+            const AxisCoef &a = l.cx[i], &b = l.cy[j];
+            auto Jv = [&](int p, int q) { return J[(size_t)q * (l.N + 1) + p]; };
+            F[l.id(i, j)] = Jv(i, j) + (a.hb * (a.d1[0] * Jv(i - 1, j) + a.d1[1] * Jv(i, j) +
+                                               a.d1[2] * Jv(i + 1, j)) +
+                                        b.hb * (b.d1[0] * Jv(i, j - 1) + b.d1[1] * Jv(i, j) +
+                                               b.d1[2] * Jv(i, j + 1))) / 3.0;
+        }
+}
+
+bool increasing(const double* X, int N) {
+    for (int i = 0; i < N; ++i)
+        if (!(X[i + 1] > X[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+/* out [nn] = L u at the interior nodes (zero on the boundary) for the grid
+ * X, Y ([N+1] each, increasing) and M ([nn] or NULL: 0). */
+int oracle_nu_apply(int N, const double* X, const double* Y, const double* M, const double* u,
+                    double* out) {
+    if (N < 2 || (N & (N - 1)) || !increasing(X, N) || !increasing(Y, N)) return ORC_INVALID;
+    std::vector<NuLevel> lv = nu_levels(N, X, Y, M);
+    NuLevel& l = lv[0];
+    std::vector<double> uu(u, u + l.u.size());
+    for (int j = 0; j <= N; ++j)
+        for (int i = 0; i <= N; ++i)
+            if (i == 0 || j == 0 || i == N || j == N) uu[l.id(i, j)] = 0.0;
+    std::fill(out, out + l.u.size(), 0.0);
+    for (int j = 1; j < N; ++j)
+        for (int i = 1; i < N; ++i) out[l.id(i, j)] = nu_apply_at(l, uu, i, j);
+    return ORC_OK;
+}
+
+/* out [nn] = R J (interior nodes). */
+int oracle_nu_rhs(int N, const double* X, const double* Y, const double* J, double* out) {
+    if (N < 2 || (N & (N - 1)) || !increasing(X, N) || !increasing(Y, N)) return ORC_INVALID;
+    std::vector<NuLevel> lv = nu_levels(N, X, Y, nullptr);
+    std::vector<double> F;
+    nu_rhs(lv[0], J, F);
+    std::copy(F.begin(), F.end(), out);
+    return ORC_OK;
+}
+
+/* The transfers between the grid (X, Y) and its coarse grid: mode 0 restricts
+ * a fine array in [(N+1)^2] to out [(N/2+1)^2]; mode 1 prolongs a coarse array
+ * in to out (fine, interior nodes; boundary 0). */
+int oracle_nu_transfer(int N, const double* X, const double* Y, int mode, const double* in,
+                       double* out) {
+    if (N < 4 || (N & (N - 1)) || !increasing(X, N) || !increasing(Y, N)) return ORC_INVALID;
+    std::vector<NuLevel> lv = nu_levels(N, X, Y, nullptr);
+    if (mode == 0) {
+        std::vector<double> v(in, in + lv[0].u.size()), o;
+        nu_restrict(lv[0], v, lv[1], o);
+        std::copy(o.begin(), o.end(), out);
+    } else {
+        std::vector<double> e(in, in + lv[1].u.size());
+        nu_prolong_add(lv[1], e, lv[0]);
+        std::copy(lv[0].u.begin(), lv[0].u.end(), out);
+    }
+    return ORC_OK;
+}
+
+/* Solve L u = R J (u = 0 on the boundary) from the guess in u, with the stop
+ * rule of oracle_mg_solve: ||r|| <= rtol ||F|| + atol sqrt(n), or the
+ * rounding floor ||r|| <= 0.35 eps (a ||u|| + ||F||) with a = 2 max |d| (a
+ * bound on the operator's size), or a cycle after the second that no longer
+ * halves ||r|| once ||r|| <= 1e-9 max(||F||, ||r_0||). */
+int oracle_nu_mg_solve(int N, const double* X, const double* Y, const double* M, const double* J,
+                       double* u, double rtol, double atol, int max_cycles, int nu1, int nu2,
+                       int* cycles, double* rel) {
+    if (N < 2 || (N & (N - 1)) || !increasing(X, N) || !increasing(Y, N)) return ORC_INVALID;
+    std::vector<NuLevel> lv = nu_levels(N, X, Y, M);
+    NuLevel& top = lv[0];
+    nu_rhs(top, J, top.F);
+    for (int j = 1; j < N; ++j)
+        for (int i = 1; i < N; ++i) top.u[top.id(i, j)] = u[(size_t)j * (N + 1) + i];
+    double amax = 0.0;
+    for (int j = 1; j < N; ++j)
+        for (int i = 1; i < N; ++i) amax = std::max(amax, std::fabs(nu_diag(top, i, j)));
+    std::vector<double> r;
+    nu_residual(top, r);
+    const double fn = nu_norm(top, top.F);
+    double rn = nu_norm(top, r), rprev = rn;
+    const double tol = rtol * (fn > 0 ? fn : rn) + atol * std::sqrt((double)(N - 1) * (N - 1));
+    const double scale = std::max(fn, rn);
+    const double floor_be = 0.35 * std::numeric_limits<double>::epsilon();
+    bool done = rn <= tol;
+    int cyc = 0;
+    while (!done && cyc < max_cycles) {
+        nu_vcycle(lv, 0, nu1, nu2);
+        ++cyc;
+        nu_residual(top, r);
+        rprev = rn;
+        rn = nu_norm(top, r);
+        const double un = nu_norm(top, top.u);
+        done = rn <= tol || rn <= floor_be * (2.0 * amax * un + fn) ||
+               (cyc >= 2 && rn > 0.5 * rprev && rn <= 1e-9 * scale);
+    }
+    for (int j = 0; j <= N; ++j)
+        for (int i = 0; i <= N; ++i) u[(size_t)j * (N + 1) + i] = top.u[top.id(i, j)];
+    if (cycles) *cycles = cyc;
+    if (rel) *rel = fn > 0 ? rn / fn : rn;
+    return (done && std::isfinite(rn)) ? ORC_OK : ORC_NOCONV;
+}
+
+}  /* extern "C" */

@@ -144,6 +144,25 @@ def laser_gaussian(n_cells: int, half_width: float, nz: int, dxi: float, a0: flo
     return env.astype(np.complex128)
 
 
+def nonuniform_axis(n_cells: int, half_width: float, kind: str = "regions") -> np.ndarray:
+    """Node coordinates x_0 = -L < ... < x_N = L of a non-uniform axis.
+
+    "regions": three regions as in the paper's bubble example, spacing ratio
+    1 : 2 : 3 from the axis out (|s| < 1/4, 1/4 <= |s| < 1/2, beyond), with
+    abrupt changes; s = -1 + 2a/N is the uniform index coordinate, so the
+    region edges fall on nodes for N >= 8 and a refined grid keeps them.
+    "smooth": smooth stretching x = L sinh(2 s)/sinh(2), finest at the axis
+    (the spacing grows by cosh(2) ~ 3.8 towards the edges)."""
+    N, L = int(n_cells), float(half_width)
+    s = -1.0 + 2.0 * np.arange(N + 1) / N
+    if kind == "smooth":
+        return L * np.sinh(2.0 * s) / np.sinh(2.0)
+    a = np.abs(s)
+    # slope 1, 2, 3 on [0, 1/4), [1/4, 1/2), [1/2, 1]; scaled so x(1) = L
+    x = np.where(a < 0.25, a, np.where(a < 0.5, 0.25 + 2 * (a - 0.25), 0.75 + 3 * (a - 0.5)))
+    return np.sign(s) * x * (L / 2.25)
+
+
 def gauss_beam(amp, sigma_r, sigma_z, xi_c, x0=0.0, y0=0.0):
     return dict(kind="gauss", amp=float(amp), sigma_r=float(sigma_r), sigma_z=float(sigma_z),
                 xi_c=float(xi_c), x0=float(x0), y0=float(y0))
