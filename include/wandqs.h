@@ -309,6 +309,38 @@ wandqs_status wandqs_time_step(wandqs_ctx* ctx, double dt, int32_t n_slices,
 wandqs_status wandqs_mg_solve(wandqs_ctx* ctx, int32_t nrhs, const double* d_k2,
                               const double* d_f, double* d_u, int32_t* h_cycles, double* h_rel);
 
+/* Multigrid solve on a non-uniform transverse grid (Sec. VII.B): lap u + M u =
+ * J on the tensor grid of nodes (x_i, y_j), i, j = 0 .. N (N = the context's
+ * n_cells), u = 0 on the boundary.  Along x at an interior node, with h- =
+ * x_i - x_{i-1}, h+ = x_{i+1} - x_i, ha = h+ + h-, hb = h+ - h-:
+ *   Dxx u = 2 (h+ u_{i-1} - ha u_i + h- u_{i+1}) / (h- h+ ha),
+ *   dx u  = h-/(ha h+) (u_{i+1} - u_i) + h+/(ha h-) (u_i - u_{i-1}),
+ * and the same along y; the discrete equation is L u = R J with the
+ * third-order correction of eqs. (34)-(36) (sign from the Taylor expansion,
+ * Dxx u = u_xx + (hb/3) u_xxx + O(h^2)):
+ *   L u = Dxx u + Dyy u + (1/3)[hb_x dx(Dyy u) + hb_y dy(Dxx u)]
+ *         + (1/3)(hb_x dx + hb_y dy)(M u) + M u,
+ *   R J = J + (1/3)(hb_x dx + hb_y dy) J,
+ * nine-point and not symmetric; on a uniform grid the 5-point Laplacian + M.
+ * V(nu_pre, nu_post) cycles of four-colour Gauss-Seidel, coarse grids with
+ * every other node, linear interpolation in the coordinates as prolongation
+ * and its control-volume weighted transpose as restriction (for M too);
+ * the context's stop rule (mg_rtol, mg_atol, the rounding floor with
+ * 2 max |diagonal| as the operator's size; a cycle stagnates only when it
+ * gains less than 10% once ||r|| <= 1e-9 ||R J||).
+ *   h_x, h_y  host [N+1] each, strictly increasing
+ *   d_M       device [N+1][N+1] (row j, column i) or NULL (M = 0)
+ *   d_J       device [N+1][N+1]
+ *   d_u       device [N+1][N+1]: the initial guess in, the solution out
+ *             (its boundary values are taken as zero)
+ *   h_cycles, h_rel  host or NULL: V-cycles, final ||r|| / ||R J||
+ * Clobbers the context's multigrid scratch arrays and the stored fields used
+ * as initial guesses.  WANDQS_E_INVALID for coordinates that do not
+ * increase, WANDQS_E_NOCONV after mg_max_cycles. */
+wandqs_status wandqs_nu_mg_solve(wandqs_ctx* ctx, const double* h_x, const double* h_y,
+                                 const double* d_M, const double* d_J, double* d_u,
+                                 int32_t* h_cycles, double* h_rel);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the
  * multigrid solve of wandqs_mg_solve without a context or workspace.  The level

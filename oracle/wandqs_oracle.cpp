@@ -2296,8 +2296,10 @@ int oracle_nu_transfer(int N, const double* X, const double* Y, int mode, const 
 /* Solve L u = R J (u = 0 on the boundary) from the guess in u, with the stop
  * rule of oracle_mg_solve: ||r|| <= rtol ||F|| + atol sqrt(n), or the
  * rounding floor ||r|| <= 0.35 eps (a ||u|| + ||F||) with a = 2 max |d| (a
- * bound on the operator's size), or a cycle after the second that no longer
- * halves ||r|| once ||r|| <= 1e-9 max(||F||, ||r_0||). */
+ * bound on the operator's size), or stagnation -- a cycle after the second
+ * that reduces ||r|| by less than 10% once ||r|| <= 1e-9 ||F|| (||r_0|| when
+ * F = 0): the point smoother converges at 0.3 to 0.75 per cycle on cells of
+ * aspect ratio up to 3, so slow progress alone is not the floor. */
 int oracle_nu_mg_solve(int N, const double* X, const double* Y, const double* M, const double* J,
                        double* u, double rtol, double atol, int max_cycles, int nu1, int nu2,
                        int* cycles, double* rel) {
@@ -2315,7 +2317,7 @@ int oracle_nu_mg_solve(int N, const double* X, const double* Y, const double* M,
     const double fn = nu_norm(top, top.F);
     double rn = nu_norm(top, r), rprev = rn;
     const double tol = rtol * (fn > 0 ? fn : rn) + atol * std::sqrt((double)(N - 1) * (N - 1));
-    const double scale = std::max(fn, rn);
+    const double scale = fn > 0 ? fn : rn;
     const double floor_be = 0.35 * std::numeric_limits<double>::epsilon();
     bool done = rn <= tol;
     int cyc = 0;
@@ -2327,7 +2329,7 @@ int oracle_nu_mg_solve(int N, const double* X, const double* Y, const double* M,
         rn = nu_norm(top, r);
         const double un = nu_norm(top, top.u);
         done = rn <= tol || rn <= floor_be * (2.0 * amax * un + fn) ||
-               (cyc >= 2 && rn > 0.5 * rprev && rn <= 1e-9 * scale);
+               (cyc >= 2 && rn > 0.9 * rprev && rn <= 1e-9 * scale);
     }
     for (int j = 0; j <= N; ++j)
         for (int i = 0; i <= N; ++i) u[(size_t)j * (N + 1) + i] = top.u[top.id(i, j)];

@@ -439,6 +439,9 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
         c->las_part = (double*)take(sizeof(double) * 4 * (size_t)(c->N + 1));
         c->las_red = (double*)take(sizeof(double) * 4);
     }
+    c->nu_tab = (double*)take(sizeof(double) * nu_table_doubles(c->N));
+    c->nu_part = (double*)take(sizeof(double) * 3 * (size_t)(c->N + 1));
+    c->nu_red = (double*)take(sizeof(double) * 4);
     c->cell_count = (int32_t*)take(sizeof(int32_t) * ncell);
     c->cell_start = (int32_t*)take(sizeof(int32_t) * (ncell + 1));
     c->big_cells = (int32_t*)take(sizeof(int32_t) * ncell);
@@ -641,11 +644,12 @@ wandqs_status wandqs_init(const wandqs_config* cfg, int32_t n_slices, void* d_wo
         return WANDQS_E_HIP;
     };
     // coherent: the kernels publish residual norms into it (mg_solve)
-    // (+ 8: flags and sequence word; + 8 more: the laser solve's norms)
-    if (hipHostMalloc((void**)&c->h_pin, sizeof(double) * (wq::kMaxSlots * wq::kNormVec + 16),
+    // (+ 8: flags and sequence word; + 8: the laser solve's norms; + 8: the
+    // non-uniform solve's)
+    if (hipHostMalloc((void**)&c->h_pin, sizeof(double) * (wq::kMaxSlots * wq::kNormVec + 24),
                       hipHostMallocCoherent) != hipSuccess)
         return bail("hipHostMalloc failed");
-    std::memset(c->h_pin, 0, sizeof(double) * (wq::kMaxSlots * wq::kNormVec + 16));
+    std::memset(c->h_pin, 0, sizeof(double) * (wq::kMaxSlots * wq::kNormVec + 24));
     if (hipMemsetAsync(d_workspace, 0, need, c->stream) != hipSuccess)
         return bail("hipMemsetAsync of the workspace failed");
 

@@ -247,6 +247,11 @@ struct wandqs_ctx {
     int las_ll = 0;           // level solved (with those below) by one workgroup
     double* las_part = nullptr;
     double* las_red = nullptr;
+    // non-uniform grid solver (wandqs_nu_mg_solve): the per-level 1-D tables,
+    // the norm partials [3][N-1] and their sums [3]
+    double* nu_tab = nullptr;
+    double* nu_part = nullptr;
+    double* nu_red = nullptr;
     double* k2lev = nullptr;  // k2 of the coarse-kernel levels (dense, concatenated)
     float* k2levf = nullptr;  // the same in float, and 1 / (4 + h_l^2 k2) in float
     float* idlevf = nullptr;
@@ -361,6 +366,8 @@ wandqs_status laser_nodes(wandqs_ctx* c);
 wandqs_status laser_plane_advance(wandqs_ctx* c, double dt, const double* chi, int j, int* cycles);
 wandqs_status laser_unpack(wandqs_ctx* c, const double* src, int set);
 wandqs_status laser_pack(wandqs_ctx* c, double* dst);
+// doubles of the non-uniform solver's 1-D tables for an N-cell grid (nonuniform.hip)
+size_t nu_table_doubles(int N);
 // node gradient (central inside, one-sided on the boundary lines), as the
 // push's grad psi (particles.hip)
 wandqs_status node_gradient(wandqs_ctx* c, const double* u, double* gx, double* gy);

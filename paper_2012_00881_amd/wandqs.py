@@ -31,7 +31,8 @@ EXPORTS = ("wandqs_workspace_bytes", "wandqs_init", "wandqs_slice_step", "wandqs
            "wandqs_num_particles", "wandqs_destroy", "wandqs_last_error", "wandqs_profile",
            "wandqs_profile_stats", "wandqs_backward", "wandqs_num_theta", "wandqs_tape_slices",
            "wandqs_mg_solve_noalloc", "wandqs_driver_set", "wandqs_driver_get",
-           "wandqs_time_step", "wandqs_laser_set", "wandqs_laser_get", "wandqs_laser_advance")
+           "wandqs_time_step", "wandqs_laser_set", "wandqs_laser_get", "wandqs_laser_advance",
+           "wandqs_nu_mg_solve")
 
 
 class Beam(C.Structure):
@@ -105,6 +106,7 @@ def load():
     L.wandqs_laser_set.argtypes = [vp, vp]
     L.wandqs_laser_get.argtypes = [vp, vp]
     L.wandqs_laser_advance.argtypes = [vp, C.c_double, vp, C.POINTER(i32)]
+    L.wandqs_nu_mg_solve.argtypes = [vp, _dp, _dp, vp, vp, vp, C.POINTER(i32), _dp]
     L.wandqs_num_particles.argtypes = [vp]
     L.wandqs_num_particles.restype = C.c_int64
     L.wandqs_profile.argtypes = [vp, i32]
@@ -123,7 +125,7 @@ def load():
                  "wandqs_get_moments", "wandqs_profile", "wandqs_profile_stats",
                  "wandqs_backward", "wandqs_mg_solve_noalloc", "wandqs_driver_set",
                  "wandqs_driver_get", "wandqs_time_step", "wandqs_laser_set", "wandqs_laser_get",
-                 "wandqs_laser_advance"):
+                 "wandqs_laser_advance", "wandqs_nu_mg_solve"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -344,6 +346,29 @@ class Simulation:
         if st not in (OK, E_NOCONV):
             self._check(st)
         return st, u, cyc.value, list(rel)[:nrhs]
+
+    def nu_mg_solve(self, X, Y, J, u0=None, M=None):
+        """Solve lap u + M u = J on the non-uniform grid of node coordinates X,
+        Y ([N+1] each; arrays [N+1][N+1] indexed [j][i]).  Returns (status, u,
+        cycles, rel)."""
+        t = self.torch
+        Xh = np.ascontiguousarray(X, dtype=np.float64)
+        Yh = np.ascontiguousarray(Y, dtype=np.float64)
+        assert Xh.size == self.N + 1 and Yh.size == self.N + 1
+        Jd = t.as_tensor(J, dtype=t.float64).to(self.device).contiguous()
+        u = (t.zeros_like(Jd) if u0 is None else
+             t.as_tensor(u0, dtype=t.float64).to(self.device).contiguous().clone())
+        Md = None if M is None else t.as_tensor(M, dtype=t.float64).to(self.device).contiguous()
+        cyc = C.c_int32(0)
+        rel = C.c_double(0.0)
+        self.stream.synchronize()
+        st = self.L.wandqs_nu_mg_solve(self.ctx, Xh.ctypes.data_as(_dp), Yh.ctypes.data_as(_dp),
+                                       C.c_void_p(Md.data_ptr()) if Md is not None else None,
+                                       C.c_void_p(Jd.data_ptr()), C.c_void_p(u.data_ptr()),
+                                       C.byref(cyc), C.byref(rel))
+        if st not in (OK, E_NOCONV):
+            self._check(st)
+        return st, u, cyc.value, rel.value
 
     # ------------------------------------------------------------ time loop
     def driver_set(self, state):
