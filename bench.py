@@ -296,6 +296,48 @@ def laser_timing(cfg: dict, S: int):
     return res
 
 
+def nonuniform_timing(cfg: dict, reps: int = 3):
+    """The non-uniform grid solver (Sec. VII.B) on the workload's grid size: the
+    three-region axis (spacing 1 : 2 : 3 from the axis out) in x and y, a
+    Gaussian source of the bubble's size (the shape of n* - 1), the Poisson
+    and the Helmholtz (M = -1) forms from a zero guess to the rounding floor:
+    ms per solve, cycles, and the solver kernels' algorithmic HBM rate."""
+    import numpy as np
+    import torch
+    import wandqs_inputs as wi
+    from paper_2012_00881_amd import Simulation
+    N, L = cfg["n_cells"], cfg["half_width"]
+    X = wi.nonuniform_axis(N, L, "regions")
+    XX, YY = np.meshgrid(X, X, indexing="xy")
+    J = -np.exp(-(XX ** 2 + YY ** 2) / 4.0)
+    c = wi.scaled(cfg, mg_max_cycles=200)
+    sim = Simulation(c)
+    res = {"grid": N, "axis": "three regions, spacing 1:2:3", "source": "Gaussian, width 2"}
+    for name, M in (("poisson", None), ("helmholtz", -np.ones_like(J))):
+        sim.nu_mg_solve(X, X, J, M=M)  # warm-up
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, u, cyc, rel = sim.nu_mg_solve(X, X, J, M=M)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            assert st == 0, st
+        res[name] = {"ms_per_solve": round(1e3 * min(times), 3), "cycles": cyc,
+                     "ms_per_cycle": round(1e3 * min(times) / cyc, 4), "rel_resid": rel}
+    sim.profile(True)
+    sim.nu_mg_solve(X, X, J)
+    st = sim.kernel_stats()
+    sim.close()
+    nu = [x for x in st if x["name"].startswith("k_nu")]
+    ms = sum(x["total_ms"] for x in nu)
+    res["kernel_alg_GBps"] = round(sum(x["alg_bytes"] for x in nu) / (ms * 1e-3) / 1e9, 1)
+    res["kernels"] = {x["name"]: {"launches": x["launches"], "ms": round(x["total_ms"], 3)}
+                      for x in sorted(nu, key=lambda x: -x["total_ms"])[:6]}
+    print(f"[bench] non-uniform solver: {res}", file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -326,6 +368,8 @@ def main():
                     help="slices timed from the window with each Runge-Kutta pusher (0: skip)")
     ap.add_argument("--laser-steps", type=int, default=256,
                     help="envelope planes (slices) of the laser-driven time step (0: skip)")
+    ap.add_argument("--no-nonuniform", action="store_true",
+                    help="skip the non-uniform grid solver timing")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times (the "
                          "reference for scaling hardware byte counters)")
@@ -478,6 +522,10 @@ def main():
     if args.laser_steps > 0:
         laser = laser_timing(cfg, args.laser_steps)
 
+    nonuniform = None
+    if not args.no_nonuniform:
+        nonuniform = nonuniform_timing(cfg)
+
     adjoint = None
     if args.adjoint_steps > 0:
         adjoint = adjoint_timing(cfg, win, args.adjoint_steps, args.checkpoint_every)
@@ -501,7 +549,7 @@ def main():
                        "lead_in_slices": lead, "xi_start": win["xi"], "xi_end": final["xi"],
                        "mean_vcycles": [round(c, 3) for c in cyc]},
             "roofline": roof, "vcycle_hbm": vcycle, "cpu_baseline": cpu, "forms": forms,
-            "adjoint": adjoint, "pushers": pushers, "laser": laser}
+            "adjoint": adjoint, "pushers": pushers, "laser": laser, "nonuniform": nonuniform}
     print(json.dumps(line), flush=True)
 
 
