@@ -433,6 +433,7 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
         for (int q = 0; q < 2; ++q) c->las_g[q] = arr(0);
         for (int l = 0; l <= c->las_ll; ++l) {
             c->las_u[l] = l ? carr(l) : nullptr;
+            c->las_um[l] = l < c->las_ll ? carr(l) : nullptr;
             c->las_f[l] = carr(l);
             c->las_k[l] = carr(l);
         }

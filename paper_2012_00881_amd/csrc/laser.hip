@@ -16,8 +16,9 @@
 //   beta = 4/(dt dxi0), gam = 4 k0/dt,  a1 = 0 on the boundary,
 // chi = n* / (1 + psi) at the nodes.  It is solved by a complex multigrid:
 // V(nu_pre, nu_post) cycles of red-black Gauss-Seidel on the levels above
-// kLasCoarse (one launch per half sweep, a fused residual and full-weighting
-// restriction, bilinear prolongation) and one workgroup that runs the rest of
+// kLasCoarse (per level one fused down pass -- the pre-sweeps, the residual
+// and its full weighting, on LDS tiles with halos -- and one fused up pass --
+// bilinear prolongation and the post-sweeps) and one workgroup that runs the rest of
 // the V-cycle (levels kLasCoarse^2 .. 2^2, exact on the single interior node of
 // 2^2) in LDS; the context's stop rule (mg_rtol, mg_atol, the rounding floor)
 // on the real and imaginary parts, from the guess a0.
@@ -70,8 +71,10 @@ __global__ void k_las_a2(int N, int pitch, size_t plane, int nz, double dxi0,
 }
 
 // Level-0 problem of one plane: the shift k = chi + beta - i gam, the
-// right-hand side f (interior nodes) and the initial iterate u = a0 (zero on
-// the boundary).  chi, p0 and p1 may be null (vacuum, first plane).
+// right-hand side f (interior nodes) and the initial iterate (zero on the
+// boundary): a0 plus the plane ahead's change over the step, p1 - p0 (the
+// envelope changes smoothly from plane to plane), or a0 on the first plane.
+// chi, p0 and p1 may be null (vacuum, first plane).
 __global__ void k_las_rhs(int N, double h, int pitch, double beta, double gam,
                           const double* __restrict__ chi, const double2* __restrict__ a0,
                           const double2* __restrict__ p0, const double2* __restrict__ p1,
@@ -94,21 +97,7 @@ __global__ void k_las_rhs(int N, double h, int pitch, double beta, double gam,
     if (p1) d = p1[i];
     if (p0) d = csub(d, p0[i]);
     f[i] = csub(csub(cmul(make_double2(x - beta, gam), c), lap), cscl(beta, d));
-    u[i] = c;
-}
-
-// One colour of a red-black Gauss-Seidel sweep of (L_h - k) u = f:
-// u = (sum of the four neighbours - h^2 f) / (4 + h^2 k) on the interior nodes
-// with (a + b) % 2 == color.
-__global__ void k_las_smooth(int n, double h2, int pitch, int color, double2* __restrict__ u,
-                             const double2* __restrict__ f, const double2* __restrict__ k) {
-    const int a = 2 * (blockIdx.x * blockDim.x + threadIdx.x) + ((blockIdx.y + color) & 1);
-    const int b = blockIdx.y;
-    if (a < 1 || a > n - 1 || b < 1 || b > n - 1) return;
-    const size_t i = (size_t)b * pitch + a;
-    const double2 nb = cadd(cadd(u[i - 1], u[i + 1]), cadd(u[i - pitch], u[i + pitch]));
-    const double2 kk = k[i];
-    u[i] = cdiv(csub(nb, cscl(h2, f[i])), make_double2(4.0 + h2 * kk.x, h2 * kk.y));
+    u[i] = cadd(c, d);
 }
 
 __device__ __forceinline__ double2 resid_at(const double2* u, const double2* f, const double2* k,
@@ -119,28 +108,137 @@ __device__ __forceinline__ double2 resid_at(const double2* u, const double2* f, 
     return csub(f[i], csub(lap, cmul(k[i], c)));
 }
 
-// Coarse right-hand side = full weighting of the fine residual f - (L_h u - k u);
-// the coarse correction starts at zero.
-__global__ void k_las_restrict(int nc, int pf, double ihf2, const double2* __restrict__ uf,
-                               const double2* __restrict__ ff, const double2* __restrict__ kf,
-                               int pc, double2* __restrict__ fc, double2* __restrict__ uc) {
-    const int I = blockIdx.x * blockDim.x + threadIdx.x, J = blockIdx.y;
-    if (I > nc) return;
-    const size_t ic = (size_t)J * pc + I;
-    uc[ic] = make_double2(0.0, 0.0);
-    double2 s = make_double2(0.0, 0.0);
-    if (I >= 1 && J >= 1 && I <= nc - 1 && J <= nc - 1) {
-        const size_t c = (size_t)(2 * J) * pf + 2 * I;
-        const double w[3] = {1.0, 2.0, 1.0};
-#pragma unroll
-        for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-            for (int dx = -1; dx <= 1; ++dx)
-                s = cadd(s, cscl(w[dx + 1] * w[dy + 1],
-                                 resid_at(uf, ff, kf, c + (ptrdiff_t)dy * pf + dx, pf, ihf2)));
-        s = cscl(1.0 / 16.0, s);
+// Tiles of the fused passes: kLTX x kLTY owned nodes, loaded with a halo of
+// up to kLH nodes into LDS (u, f and the shift k: 16 B each per node).
+constexpr int kLTX = 32, kLTY = 16, kLH = 8;
+constexpr int kLRX = kLTX + 2 * kLH, kLRY = kLTY + 2 * kLH;
+constexpr int kLTThreads = 512;
+
+// Red-black Gauss-Seidel sweeps on the tile's region in LDS: a node with its
+// four neighbours in the region and inside the domain takes (sum of the
+// neighbours - h^2 f) / (4 + h^2 k); the region's edge keeps its loaded values,
+// so each half sweep leaves one more layer inside it exact.
+__device__ void tile_sweeps(double2 (*U)[kLRX], const double2 (*F)[kLRX], const double2 (*K)[kLRX],
+                            int RW, int RH, int ax0, int by0, int n, double h2, int nu) {
+    for (int s = 0; s < nu; ++s)
+        for (int color = 0; color < 2; ++color) {
+            for (int t = threadIdx.x; t < RW * RH; t += kLTThreads) {
+                const int lx = t % RW, ly = t / RW;
+                const int a = ax0 + lx, b = by0 + ly;
+                if (lx < 1 || ly < 1 || lx > RW - 2 || ly > RH - 2) continue;
+                if (a < 1 || b < 1 || a > n - 1 || b > n - 1 || ((a + b) & 1) != color) continue;
+                const double2 nb = cadd(cadd(U[ly][lx - 1], U[ly][lx + 1]), cadd(U[ly - 1][lx], U[ly + 1][lx]));
+                const double2 kk = K[ly][lx];
+                U[ly][lx] = cdiv(csub(nb, cscl(h2, F[ly][lx])), make_double2(4.0 + h2 * kk.x, h2 * kk.y));
+            }
+            __syncthreads();
+        }
+}
+
+// Down pass of one level: nu red-black sweeps of (L_h - k) u = f on the tile
+// (halo 2 nu + 2), the smoothed owned nodes into um, and, for the coarse nodes
+// the tile owns, the full weighting of the residual into the coarse f and a
+// zero coarse correction.  u_in is read only (tiles never see each other's
+// writes within a pass).
+__global__ __launch_bounds__(kLTThreads) void k_las_down(int n, double h, int pitch, int nu,
+                                                         const double2* __restrict__ u_in,
+                                                         const double2* __restrict__ f,
+                                                         const double2* __restrict__ k,
+                                                         double2* __restrict__ um, int pc,
+                                                         double2* __restrict__ fc,
+                                                         double2* __restrict__ uc) {
+    __shared__ double2 U[kLRY][kLRX], F[kLRY][kLRX], K[kLRY][kLRX];
+    const int H = 2 * nu + 2;
+    const int x0 = blockIdx.x * kLTX, y0 = blockIdx.y * kLTY;
+    const int ax0 = x0 - H, by0 = y0 - H, RW = kLTX + 2 * H, RH = kLTY + 2 * H;
+    const double2 z = make_double2(0.0, 0.0);
+    for (int t = threadIdx.x; t < RW * RH; t += kLTThreads) {
+        const int lx = t % RW, ly = t / RW, a = ax0 + lx, b = by0 + ly;
+        double2 uu = z, ff = z, kk = z;
+        if (a >= 0 && b >= 0 && a <= n && b <= n) {
+            const size_t g = (size_t)b * pitch + a;
+            ff = f[g];
+            kk = k[g];
+            if (a > 0 && b > 0 && a < n && b < n) uu = u_in[g];
+        }
+        U[ly][lx] = uu;
+        F[ly][lx] = ff;
+        K[ly][lx] = kk;
     }
-    fc[ic] = s;
+    __syncthreads();
+    const double h2 = h * h;
+    tile_sweeps(U, F, K, RW, RH, ax0, by0, n, h2, nu);
+    for (int t = threadIdx.x; t < kLTX * kLTY; t += kLTThreads) {
+        const int a = x0 + t % kLTX, b = y0 + t / kLTX;
+        if (a <= n && b <= n) um[(size_t)b * pitch + a] = U[b - by0][a - ax0];
+    }
+    const int nc = n / 2;
+    const double ih2 = 1.0 / h2;
+    for (int t = threadIdx.x; t < (kLTX / 2) * (kLTY / 2); t += kLTThreads) {
+        const int I = x0 / 2 + t % (kLTX / 2), J = y0 / 2 + t / (kLTX / 2);
+        if (I > nc || J > nc) continue;
+        double2 acc = z;
+        if (I >= 1 && J >= 1 && I <= nc - 1 && J <= nc - 1) {
+            const double w[3] = {1.0, 2.0, 1.0};
+            for (int sy = -1; sy <= 1; ++sy)
+                for (int sx = -1; sx <= 1; ++sx) {
+                    const int lx = 2 * I + sx - ax0, ly = 2 * J + sy - by0;
+                    const double2 c = U[ly][lx];
+                    const double2 lap = cscl(ih2, csub(cadd(cadd(U[ly][lx - 1], U[ly][lx + 1]),
+                                                            cadd(U[ly - 1][lx], U[ly + 1][lx])),
+                                                       cscl(4.0, c)));
+                    const double2 r = csub(F[ly][lx], csub(lap, cmul(K[ly][lx], c)));
+                    acc = cadd(acc, cscl(w[sx + 1] * w[sy + 1], r));
+                }
+            acc = cscl(1.0 / 16.0, acc);
+        }
+        fc[(size_t)J * pc + I] = acc;
+        uc[(size_t)J * pc + I] = z;
+    }
+}
+
+// Up pass of one level: um plus the bilinear interpolation of the coarse
+// correction on the tile (halo 2 nu), nu red-black sweeps, the owned nodes
+// into u_out.
+__global__ __launch_bounds__(kLTThreads) void k_las_up(int n, double h, int pitch, int nu,
+                                                       const double2* __restrict__ um,
+                                                       const double2* __restrict__ f,
+                                                       const double2* __restrict__ k, int pc,
+                                                       const double2* __restrict__ uc,
+                                                       double2* __restrict__ u_out) {
+    __shared__ double2 U[kLRY][kLRX], F[kLRY][kLRX], K[kLRY][kLRX];
+    const int H = 2 * nu;
+    const int x0 = blockIdx.x * kLTX, y0 = blockIdx.y * kLTY;
+    const int ax0 = x0 - H, by0 = y0 - H, RW = kLTX + 2 * H, RH = kLTY + 2 * H;
+    const double2 z = make_double2(0.0, 0.0);
+    for (int t = threadIdx.x; t < RW * RH; t += kLTThreads) {
+        const int lx = t % RW, ly = t / RW, a = ax0 + lx, b = by0 + ly;
+        double2 uu = z, ff = z, kk = z;
+        if (a >= 0 && b >= 0 && a <= n && b <= n) {
+            const size_t g = (size_t)b * pitch + a;
+            ff = f[g];
+            kk = k[g];
+            if (a > 0 && b > 0 && a < n && b < n) {
+                const int I = a >> 1, J = b >> 1;
+                const size_t cc = (size_t)J * pc + I;
+                double2 e;
+                if (!(a & 1) && !(b & 1)) e = uc[cc];
+                else if (a & 1 && !(b & 1)) e = cscl(0.5, cadd(uc[cc], uc[cc + 1]));
+                else if (!(a & 1)) e = cscl(0.5, cadd(uc[cc], uc[cc + pc]));
+                else e = cscl(0.25, cadd(cadd(uc[cc], uc[cc + 1]), cadd(uc[cc + pc], uc[cc + pc + 1])));
+                uu = cadd(um[g], e);
+            }
+        }
+        U[ly][lx] = uu;
+        F[ly][lx] = ff;
+        K[ly][lx] = kk;
+    }
+    __syncthreads();
+    tile_sweeps(U, F, K, RW, RH, ax0, by0, n, h * h, nu);
+    for (int t = threadIdx.x; t < kLTX * kLTY; t += kLTThreads) {
+        const int a = x0 + t % kLTX, b = y0 + t / kLTX;
+        if (a <= n && b <= n) u_out[(size_t)b * pitch + a] = U[b - by0][a - ax0];
+    }
 }
 
 // Full weighting of the shift k onto the interior coarse nodes.
@@ -156,22 +254,6 @@ __global__ void k_las_krestrict(int nc, int pf, const double2* __restrict__ kf, 
         s = cscl(1.0 / 16.0, s);
     }
     kc[(size_t)J * pc + I] = s;
-}
-
-// u_fine += bilinear interpolation of the coarse correction (interior nodes).
-__global__ void k_las_prolong(int nf, int pf, double2* __restrict__ uf, int pc,
-                              const double2* __restrict__ uc) {
-    const int a = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y;
-    if (a < 1 || a > nf - 1 || b < 1 || b > nf - 1) return;
-    const int I = a >> 1, J = b >> 1;
-    const size_t c = (size_t)J * pc + I;
-    double2 v;
-    if (!(a & 1) && !(b & 1)) v = uc[c];
-    else if (a & 1 && !(b & 1)) v = cscl(0.5, cadd(uc[c], uc[c + 1]));
-    else if (!(a & 1)) v = cscl(0.5, cadd(uc[c], uc[c + pc]));
-    else v = cscl(0.25, cadd(cadd(uc[c], uc[c + 1]), cadd(uc[c + pc], uc[c + pc + 1])));
-    const size_t i = (size_t)b * pf + a;
-    uf[i] = cadd(uf[i], v);
 }
 
 // The V-cycle from level n0 (<= kLasCoarse) down to 2^2 in one workgroup, in
@@ -392,22 +474,13 @@ wandqs_status las_vcycle(wandqs_ctx* c, double2* u0) {
     const int ll = c->las_ll, nu1 = c->cfg.nu_pre, nu2 = c->cfg.nu_post;
     hipStream_t s = c->stream;
     auto U = [&](int l) { return l == 0 ? u0 : c->las_u[l]; };
+    auto tiles = [](int n) { return dim3((n + 1 + kLTX - 1) / kLTX, (n + 1 + kLTY - 1) / kLTY); };
     for (int l = 0; l < ll; ++l) {
         const Level& F = c->lev[l];
         const Level& C = c->lev[l + 1];
-        const double h2 = F.h * F.h;
-        const dim3 g((F.N / 2 + 1 + 127) / 128, F.N + 1);
-        for (int q = 0; q < nu1; ++q)
-            for (int color = 0; color < 2; ++color) {
-                ProfScope ps(c, "k_las_smooth", (double)(F.N + 1) * (F.N + 1) * 40.0);
-                WQ_KLAUNCH(ps, k_las_smooth, g, dim3(128), 0, s, F.N, h2, F.pitch, color, U(l),
-                           c->las_f[l], c->las_k[l]);
-            }
-        {
-            ProfScope ps(c, "k_las_restrict", (double)(F.N + 1) * (F.N + 1) * 48.0 + (double)(C.N + 1) * (C.N + 1) * 32.0);
-            WQ_KLAUNCH(ps, k_las_restrict, rows_grid(C.N, 128), dim3(128), 0, s, C.N, F.pitch,
-                       1.0 / h2, U(l), c->las_f[l], c->las_k[l], C.pitch, c->las_f[l + 1], U(l + 1));
-        }
+        ProfScope ps(c, "k_las_down", (double)(F.N + 1) * (F.N + 1) * 64.0 + (double)(C.N + 1) * (C.N + 1) * 32.0);
+        WQ_KLAUNCH(ps, k_las_down, tiles(F.N), dim3(kLTThreads), 0, s, F.N, F.h, F.pitch, nu1, U(l),
+                   c->las_f[l], c->las_k[l], c->las_um[l], C.pitch, c->las_f[l + 1], U(l + 1));
     }
     {
         const Level& Cl = c->lev[ll];
@@ -418,19 +491,9 @@ wandqs_status las_vcycle(wandqs_ctx* c, double2* u0) {
     for (int l = ll - 1; l >= 0; --l) {
         const Level& F = c->lev[l];
         const Level& C = c->lev[l + 1];
-        {
-            ProfScope ps(c, "k_las_prolong", (double)(F.N + 1) * (F.N + 1) * 32.0 + (double)(C.N + 1) * (C.N + 1) * 16.0);
-            WQ_KLAUNCH(ps, k_las_prolong, rows_grid(F.N, 128), dim3(128), 0, s, F.N, F.pitch, U(l),
-                       C.pitch, U(l + 1));
-        }
-        const double h2 = F.h * F.h;
-        const dim3 g((F.N / 2 + 1 + 127) / 128, F.N + 1);
-        for (int q = 0; q < nu2; ++q)
-            for (int color = 0; color < 2; ++color) {
-                ProfScope ps(c, "k_las_smooth", (double)(F.N + 1) * (F.N + 1) * 40.0);
-                WQ_KLAUNCH(ps, k_las_smooth, g, dim3(128), 0, s, F.N, h2, F.pitch, color, U(l),
-                           c->las_f[l], c->las_k[l]);
-            }
+        ProfScope ps(c, "k_las_up", (double)(F.N + 1) * (F.N + 1) * 64.0 + (double)(C.N + 1) * (C.N + 1) * 16.0);
+        WQ_KLAUNCH(ps, k_las_up, tiles(F.N), dim3(kLTThreads), 0, s, F.N, F.h, F.pitch, nu2,
+                   c->las_um[l], c->las_f[l], c->las_k[l], C.pitch, U(l + 1), U(l));
     }
     WQ_LAUNCH_CHECK();
     return WANDQS_OK;
@@ -492,9 +555,15 @@ wandqs_status laser_plane_advance(wandqs_ctx* c, double dt, const double* chi, i
         done[q] = rn[q] <= tol[q];
     }
     int cyc = 0;
+    // the first batch runs one cycle fewer than the last plane needed (planes
+    // next to each other converge alike), then one cycle per norm check
+    int batch = std::max(1, c->las_pred - 1);
     while (!(done[0] && done[1]) && cyc < c->cfg.mg_max_cycles) {
-        if ((s = las_vcycle(c, u)) != WANDQS_OK) return s;
-        ++cyc;
+        const int b = std::min(batch, c->cfg.mg_max_cycles - cyc);
+        for (int q = 0; q < b; ++q)
+            if ((s = las_vcycle(c, u)) != WANDQS_OK) return s;
+        cyc += b;
+        batch = 1;
         if ((s = las_norms(c, 1, u, c->las_f[0], c->las_k[0], hn + 4)) != WANDQS_OK) return s;
         WQ_HIP(hipStreamSynchronize(c->stream));
         for (int q = 0; q < 2; ++q) {
@@ -507,6 +576,7 @@ wandqs_status laser_plane_advance(wandqs_ctx* c, double dt, const double* chi, i
         }
     }
     if (cycles) *cycles = cyc;
+    c->las_pred = cyc;
     if (!(std::isfinite(rn[0]) && std::isfinite(rn[1]) && done[0] && done[1])) {
         c->err = "laser envelope: multigrid did not converge";
         return WANDQS_E_NOCONV;

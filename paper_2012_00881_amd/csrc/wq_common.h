@@ -239,9 +239,11 @@ struct wandqs_ctx {
     double las_dt = 0.0;
     int las_j = 0;            // plane of the next slice in the time step's sweep
     int las_cycles = 0;       // multigrid cycles of the last plane advanced
+    int las_pred = 1;         // cycles the last solved plane needed (first batch size)
     double* las_a2 = nullptr;
     double* las_g[2] = {};
     double2* las_u[wq::kMaxLevels] = {};
+    double2* las_um[wq::kMaxLevels] = {};  // smoothed iterate of each down pass
     double2* las_f[wq::kMaxLevels] = {};
     double2* las_k[wq::kMaxLevels] = {};
     int las_ll = 0;           // level solved (with those below) by one workgroup
