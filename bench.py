@@ -338,6 +338,54 @@ def nonuniform_timing(cfg: dict, reps: int = 3):
     return res
 
 
+def workload_timing(name: str, xi_start: float, steps: int):
+    """Another workload's window, timed like the headline: the job run untimed
+    to xi_start, `steps` slices timed, then replayed with per-kernel timing
+    for the V-cycle kernels' aggregate HBM rate."""
+    import torch
+    import wandqs_inputs as wi
+    from paper_2012_00881_amd import Simulation
+    cfg = wi.config(name)
+    sim = Simulation(cfg, n_slices=max(steps, 64))
+    xi = 0.0
+    while xi < xi_start:
+        sim.run(64)
+        xi = sim.get_state()["xi"]
+    win = sim.get_state()
+    win = dict(particles=win["particles"].clone(), fields=win["fields"].clone(), xi=win["xi"],
+               dxi=win["dxi"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos, _ = sim.run(steps, infos=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    P = sim.P
+    xi_end = sim.get_state()["xi"]
+    sim.close()
+    sim = Simulation(cfg, n_slices=steps)
+    _start(sim, win)
+    sim.profile(True)
+    sim.run(steps)
+    stats = sim.kernel_stats()
+    sim.close()
+    groups = {}
+    for st in stats:
+        g = groups.setdefault(st["name"].split("@")[0], dict(name=st["name"].split("@")[0],
+                                                             launches=0, total_ms=0.0, alg_bytes=0.0))
+        g["launches"] += st["launches"]
+        g["total_ms"] += st["total_ms"]
+        g["alg_bytes"] += st["alg_bytes"]
+    gl = list(groups.values())
+    tot = sum(x["total_ms"] for x in gl)
+    res = {"workload": name, "grid": cfg["n_cells"], "particles": P, "slices": steps,
+           "value": P * steps / dt, "ms_per_slice": 1e3 * dt / steps, "xi_start": win["xi"],
+           "xi_end": xi_end,
+           "mean_vcycles": [round(sum(i["vcycles"][k] for i in infos) / steps, 3) for k in range(5)],
+           "vcycle_hbm": vcycle_bandwidth(gl, tot)}
+    print(f"[bench] {name}: {res}", file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -368,6 +416,8 @@ def main():
                     help="slices timed from the window with each Runge-Kutta pusher (0: skip)")
     ap.add_argument("--laser-steps", type=int, default=256,
                     help="envelope planes (slices) of the laser-driven time step (0: skip)")
+    ap.add_argument("--c3-steps", type=int, default=128,
+                    help="slices of the C3 (512^2, driver + witness) window, from xi = 2 (0: skip)")
     ap.add_argument("--no-nonuniform", action="store_true",
                     help="skip the non-uniform grid solver timing")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -522,6 +572,10 @@ def main():
     if args.laser_steps > 0:
         laser = laser_timing(cfg, args.laser_steps)
 
+    c3 = None
+    if args.c3_steps > 0:
+        c3 = workload_timing("C3", 2.0, args.c3_steps)
+
     nonuniform = None
     if not args.no_nonuniform:
         nonuniform = nonuniform_timing(cfg)
@@ -549,7 +603,8 @@ def main():
                        "lead_in_slices": lead, "xi_start": win["xi"], "xi_end": final["xi"],
                        "mean_vcycles": [round(c, 3) for c in cyc]},
             "roofline": roof, "vcycle_hbm": vcycle, "cpu_baseline": cpu, "forms": forms,
-            "adjoint": adjoint, "pushers": pushers, "laser": laser, "nonuniform": nonuniform}
+            "adjoint": adjoint, "pushers": pushers, "laser": laser, "nonuniform": nonuniform,
+            "c3": c3}
     print(json.dumps(line), flush=True)
 
 
