@@ -322,7 +322,9 @@ wandqs_status wandqs_mg_solve(wandqs_ctx* ctx, int32_t nrhs, const double* d_k2,
  *         + (1/3)(hb_x dx + hb_y dy)(M u) + M u,
  *   R J = J + (1/3)(hb_x dx + hb_y dy) J,
  * nine-point and not symmetric; on a uniform grid the 5-point Laplacian + M.
- * V(nu_pre, nu_post) cycles of four-colour Gauss-Seidel, coarse grids with
+ * V-cycles with alternating zebra line relaxation on the levels above 64^2
+ * (one step before and one after the coarse correction) and nu_pre / nu_post
+ * sweeps of four-colour Gauss-Seidel below, coarse grids with
  * every other node, linear interpolation in the coordinates as prolongation
  * and its control-volume weighted transpose as restriction (for M too);
  * the context's stop rule (mg_rtol, mg_atol, the rounding floor with

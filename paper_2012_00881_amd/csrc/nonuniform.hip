@@ -13,10 +13,14 @@
 // a nine-point, non-symmetric operator (the 5-point Laplacian plus M on a
 // uniform grid).
 //
-// The solver: V(nu_pre, nu_post) cycles with Gauss-Seidel in four colours
+// The solver: V-cycles smoothing by alternating zebra line relaxation on the
+// levels above 64^2 (x-lines of odd then even rows, y-lines of odd then even
+// columns, once before and once after the coarse correction: cells of aspect
+// ratio up to 3 defeat point smoothers) and by Gauss-Seidel in four colours
 // (i mod 2, j mod 2; the nine-point stencil couples no two nodes of one
-// colour), u += (R J - L u) / d with d the coefficient of u_ij in its own
-// equation; coarse grids keep every other node and rediscretise L; the
+// colour; nu_pre / nu_post sweeps) on the levels <= 64^2, u += (R J - L u) / d
+// with d the coefficient of u_ij in its own equation; coarse grids keep every
+// other node and rediscretise L; the
 // prolongation interpolates linearly in the coordinates and the restriction
 // is its transpose weighted by the control volumes (x_{i+1} - x_{i-1})/2 per
 // direction, for the residual and for M.  Levels of N <= 64 run in one
@@ -117,6 +121,97 @@ __global__ void k_nu_smooth(int N, int pitch, int pi, int pj, double* u, const d
     const size_t g = (size_t)j * pitch + i;
     const double r = F[g] - nu_Lu(U, Mm, i, j, cx, cy);
     u[g] += r / nu_diag(M[g], i, j, cx, cy);
+}
+
+// Line relaxation: the unknowns of one grid line solved together with the
+// neighbouring lines held fixed.  DIR 0: the x-line of row `line` (unknowns
+// u(1..n-1, line)); DIR 1: the y-line of column `line`.  Holding the other
+// lines, L restricted to the line is tridiagonal: for an x-line the
+// coefficients of u(i-1, j), u(i, j), u(i+1, j) are
+//   Dxx weights x (1 + hb_y dy_0/3) + (hb_x dx_k/3)(Dyy_0 + M(i+k-1, j)) and,
+//   on the diagonal, the coefficient d of the point smoother
+// (dy_0, Dyy_0: the y-stencils' central weights), mirrored for a y-line.  The
+// line takes u += T^-1 (R J - L u), T solved by parallel cyclic reduction in
+// LDS.  Lines of one parity do not couple (the stencil reaches one line
+// over), so each launch relaxes every other line.
+constexpr int kLineThreads = 512;
+constexpr int kLineMax = 4095;
+constexpr int kLinePer = (kLineMax + kLineThreads - 1) / kLineThreads;
+
+template <int DIR>
+__global__ __launch_bounds__(kLineThreads) void k_nu_line(int n, int pitch, int par, double* u,
+                                                          const double* __restrict__ F, double* M,
+                                                          const double* cx, const double* cy) {
+    extern __shared__ double sh[];
+    const int m = n - 1;
+    double* A = sh;
+    double* B = sh + m;
+    double* C = sh + 2 * m;
+    double* D = sh + 3 * m;
+    const int line = 2 * blockIdx.x + par;
+    if (line < 1 || line > n - 1) return;  // the whole workgroup
+    const Arr U{u, pitch}, Mm{M, pitch};
+    for (int t = threadIdx.x; t < m; t += kLineThreads) {
+        const int i = DIR == 0 ? t + 1 : line, j = DIR == 0 ? line : t + 1;
+        const double* a = cx + 7 * i;
+        const double* b = cy + 7 * j;
+        const double r = F[(size_t)j * pitch + i] - nu_Lu(U, Mm, i, j, cx, cy);
+        double sub, sup;
+        if (DIR == 0) {
+            const double fy = 1.0 + b[6] * b[4] / 3.0, gx = a[6] / 3.0;
+            sub = a[0] * fy + gx * a[3] * (b[1] + Mm(i - 1, j));
+            sup = a[2] * fy + gx * a[5] * (b[1] + Mm(i + 1, j));
+        } else {
+            const double fx = 1.0 + a[6] * a[4] / 3.0, gy = b[6] / 3.0;
+            sub = b[0] * fx + gy * b[3] * (a[1] + Mm(i, j - 1));
+            sup = b[2] * fx + gy * b[5] * (a[1] + Mm(i, j + 1));
+        }
+        A[t] = t == 0 ? 0.0 : sub;
+        C[t] = t == m - 1 ? 0.0 : sup;
+        B[t] = nu_diag(Mm(i, j), i, j, cx, cy);
+        D[t] = r;
+    }
+    __syncthreads();
+    for (int s = 1; s < m; s <<= 1) {
+        double na[kLinePer], nb[kLinePer], nc[kLinePer], nd[kLinePer];
+#pragma unroll
+        for (int q = 0; q < kLinePer; ++q) {
+            const int t = threadIdx.x + q * kLineThreads;
+            if (t >= m) break;
+            double xa = 0.0, xc = 0.0, xb = B[t], xd = D[t];
+            if (t - s >= 0) {
+                const double al = -A[t] / B[t - s];
+                xa = al * A[t - s];
+                xb += al * C[t - s];
+                xd += al * D[t - s];
+            }
+            if (t + s < m) {
+                const double ga = -C[t] / B[t + s];
+                xc = ga * C[t + s];
+                xb += ga * A[t + s];
+                xd += ga * D[t + s];
+            }
+            na[q] = xa;
+            nb[q] = xb;
+            nc[q] = xc;
+            nd[q] = xd;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kLinePer; ++q) {
+            const int t = threadIdx.x + q * kLineThreads;
+            if (t >= m) break;
+            A[t] = na[q];
+            B[t] = nb[q];
+            C[t] = nc[q];
+            D[t] = nd[q];
+        }
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < m; t += kLineThreads) {
+        const int i = DIR == 0 ? t + 1 : line, j = DIR == 0 ? line : t + 1;
+        u[(size_t)j * pitch + i] += D[t] / B[t];
+    }
 }
 
 // Coarse right-hand side = weighted restriction of the fine residual; the
@@ -499,16 +594,26 @@ extern "C" wandqs_status wandqs_nu_mg_solve(wandqs_ctx* c, const double* h_x, co
         WQ_HIP(hipMemcpyAsync(out, c->nu_red, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
         return WANDQS_OK;
     };
+    // one smoothing step on a tile level: x-lines of odd and even rows, then
+    // y-lines of odd and even columns (alternating zebra line relaxation)
+    auto line_step = [&](int l) {
+        const Level& Fl = c->lev[l];
+        const size_t lds = 4 * sizeof(double) * (size_t)(Fl.N - 1);
+        for (int dir = 0; dir < 2; ++dir)
+            for (int par = 1; par >= 0; --par) {
+                ProfScope ps(c, dir ? "k_nu_line<1>" : "k_nu_line<0>", (double)(Fl.N + 1) * (Fl.N + 1) * 24.0);
+                if (dir == 0)
+                    WQ_KLAUNCH(ps, k_nu_line<0>, dim3(Fl.N / 2), dim3(kLineThreads), lds, s, Fl.N, Fl.pitch,
+                               par, U(l), Fa(l), Ma(l), tabs[l].cx, tabs[l].cy);
+                else
+                    WQ_KLAUNCH(ps, k_nu_line<1>, dim3(Fl.N / 2), dim3(kLineThreads), lds, s, Fl.N, Fl.pitch,
+                               par, U(l), Fa(l), Ma(l), tabs[l].cx, tabs[l].cy);
+            }
+    };
     auto vcycle = [&]() -> wandqs_status {
         for (int l = 0; l < lc; ++l) {
             const Level &Fl = c->lev[l], &Cl = c->lev[l + 1];
-            const dim3 g((Fl.N / 2 + 127) / 128, Fl.N / 2 + 1);
-            for (int q = 0; q < nu1; ++q)
-                for (int color = 0; color < 4; ++color) {
-                    ProfScope ps(c, "k_nu_smooth", (double)(Fl.N + 1) * (Fl.N + 1) * 20.0);
-                    WQ_KLAUNCH(ps, k_nu_smooth, g, dim3(128), 0, s, Fl.N, Fl.pitch, color & 1, color >> 1,
-                               U(l), Fa(l), Ma(l), tabs[l].cx, tabs[l].cy);
-                }
+            line_step(l);  // one alternating line step smooths like several point sweeps
             ProfScope ps(c, "k_nu_restrict", (double)(Fl.N + 1) * (Fl.N + 1) * 24.0 + (double)(Cl.N + 1) * (Cl.N + 1) * 16.0);
             WQ_KLAUNCH(ps, k_nu_restrict, rows(Cl.N, 128), dim3(128), 0, s, Cl.N, Fl.pitch, U(l), Fa(l),
                        Ma(l), tabs[l].cx, tabs[l].cy, tabs[l].rx, tabs[l].ry, Cl.pitch, Fa(l + 1), U(l + 1));
@@ -526,17 +631,17 @@ extern "C" wandqs_status wandqs_nu_mg_solve(wandqs_ctx* c, const double* h_x, co
                 WQ_KLAUNCH(ps, k_nu_prolong, rows(Fl.N, 128), dim3(128), 0, s, Fl.N, Fl.pitch, U(l), Cl.pitch,
                            U(l + 1), tabs[l].px, tabs[l].py);
             }
-            const dim3 g((Fl.N / 2 + 127) / 128, Fl.N / 2 + 1);
-            for (int q = 0; q < nu2; ++q)
-                for (int color = 0; color < 4; ++color) {
-                    ProfScope ps(c, "k_nu_smooth", (double)(Fl.N + 1) * (Fl.N + 1) * 20.0);
-                    WQ_KLAUNCH(ps, k_nu_smooth, g, dim3(128), 0, s, Fl.N, Fl.pitch, color & 1, color >> 1,
-                               U(l), Fa(l), Ma(l), tabs[l].cx, tabs[l].cy);
-                }
+            line_step(l);
         }
         WQ_LAUNCH_CHECK();
         return WANDQS_OK;
     };
+    {
+        // line solves of up to 4095 unknowns keep four arrays of them in LDS
+        const int bytes = (int)(4 * sizeof(double) * (size_t)(N - 1));
+        WQ_HIP(hipFuncSetAttribute((const void*)k_nu_line<0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+        WQ_HIP(hipFuncSetAttribute((const void*)k_nu_line<1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    }
     if ((st = norms(0, hn)) != WANDQS_OK || (st = norms(1, hn + 4)) != WANDQS_OK) return st;
     WQ_HIP(hipStreamSynchronize(s));
     const double fn = std::sqrt(hn[0]), amax = hn[2];
