@@ -327,8 +327,9 @@ wandqs_status check_flags(wandqs_ctx* c) {
     return WANDQS_OK;
 }
 
-// Tables of the exact coarse Poisson solves (float; the mixed form also keeps
-// double copies for its FP64 coarsest-grid solve).
+// Tables of the exact coarse Poisson solves (the 64^2 sine matrices in float,
+// with double copies for the mixed form's FP64 coarsest-grid solve) and the
+// arrays of the fast sine transform solve on level 1.
 template <class Take>
 void carve_dst(wandqs_ctx* c, Take&& take) {
     const bool mixed = c->cfg.precision == WANDQS_MIXED;
@@ -336,13 +337,14 @@ void carve_dst(wandqs_ctx* c, Take&& take) {
     c->dst_M = (float*)take(sizeof(float) * 64 * 64);
     c->dst_S64 = mixed ? (double*)take(sizeof(double) * 64 * 64) : nullptr;
     c->dst_M64 = mixed ? (double*)take(sizeof(double) * 64 * 64) : nullptr;
-    if (wq::dst128_used(c)) {
-        c->dst2_S = (float*)take(sizeof(float) * 128 * 128);
-        c->dst2_M = (float*)take(sizeof(float) * 128 * 128);
-        c->dst2_X = (float*)take(sizeof(float) * 2 * 128 * 128);
-        c->dst2_S64 = mixed ? (double*)take(sizeof(double) * 128 * 128) : nullptr;
-        c->dst2_M64 = mixed ? (double*)take(sizeof(double) * 128 * 128) : nullptr;
-        c->dst2_X64 = mixed ? (double*)take(sizeof(double) * 2 * 128 * 128) : nullptr;
+    if (wq::fst_used(c)) {
+        const size_t n1 = c->lev[1].N;
+        for (int r = 0; r < 2; ++r) {
+            c->fst_t1[r] = (double*)take(sizeof(double) * (n1 - 1) * wq::fst_ld(c));
+            c->fst_t2[r] = (double*)take(sizeof(double) * (n1 - 1) * wq::fst_ld(c));
+        }
+        c->fst_tw = (double2*)take(sizeof(double2) * 2 * n1);
+        c->fst_s2 = (double*)take(sizeof(double) * (n1 + 1));
     }
 }
 

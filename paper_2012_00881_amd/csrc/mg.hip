@@ -1302,139 +1302,16 @@ __global__ __launch_bounds__(1024) void k_coarse_dst(DstArgs<E> a) {
     }
 }
 
-// The same exact solve on the 128^2 level when it lies below a finer level:
-// too much work for one workgroup, so it runs as two launches of 8 workgroups
-// (per right-hand side) holding 16 rows each.  The first forms the rows of
-// X = M o (S f S) (S_jk = sin(pi (j+1)(k+1)/128), S S = 64 I,
-// M = 1 / (64^2 lambda)), the second the rows of u = S X S.  8 wavefronts per
-// workgroup, one 16 x 16 output tile each, fp32 MFMA.
-#ifndef WQ_DST128
-#define WQ_DST128 1
-#endif
-constexpr int kD2 = 128;
-constexpr int kD2Ld = 132;  // LDS row stride
-constexpr int kD2Rows = 16;
-
-template <typename E>
-struct Dst2Args {
-    int pitch;
-    const E* f[2];
-    E* u_out[2];
-    const float* S;
-    const float* M;
-    float* X;  // [R][128][128]
-};
-
-// 16 x 16 tile (rows 0..15 of A, columns j0.. of B) of A B: A row-major with
-// stride kD2Ld, B given transposed (Bt[j][k] = B[k][j]), inner dimension 128.
-__device__ __forceinline__ dst_v4f d2_tile(const float* A, const float* Bt, int j0) {
-    const int lane = threadIdx.x & 63;
-    const float* a = A + (lane & 15) * kD2Ld + (lane >> 4);
-    const float* b = Bt + (j0 + (lane & 15)) * kD2Ld + (lane >> 4);
-    dst_v4f acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 8
-    for (int s = 0; s < kD2 / 4; ++s)
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * s], b[4 * s], acc, 0, 0, 0);
-    return acc;
-}
-
-template <typename E>
-__global__ __launch_bounds__(512) void k_dst2_fwd(Dst2Args<E> a) {
-    __shared__ float sS[kD2 * kD2Ld];
-    __shared__ float sFt[kD2 * kD2Ld];
-    __shared__ float sT[kD2Rows * kD2Ld];
-    const int i0 = kD2Rows * blockIdx.x, r = blockIdx.y;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int j0 = 16 * w, ti = 4 * (lane >> 4), tj = j0 + (lane & 15);
-    float mv[4];  // this lane's entries of M, loaded ahead
-#pragma unroll
-    for (int q = 0; q < 4; ++q) mv[q] = a.M[(i0 + ti + q) * kD2 + tj];
-    // every load is issued before the first store (one round trip): 32 per
-    // thread; a row of f is 127 interior nodes, read as doubles or floats
-    constexpr int kIt = kD2 * kD2 / 512;
-    float sv[kIt], fv[kIt];
-#pragma unroll
-    for (int t = 0; t < kIt; ++t) {
-        const int i = tid + t * 512, y = i >> 7, x = i & (kD2 - 1);
-        sv[t] = a.S[i];
-        const size_t g = (size_t)(y + 1) * a.pitch + x + 1;
-        fv[t] = (float)a.f[r][(x < kD2 - 1 && y < kD2 - 1) ? g : 0];
-    }
-#pragma unroll
-    for (int t = 0; t < kIt; ++t) {
-        const int i = tid + t * 512, y = i >> 7, x = i & (kD2 - 1);
-        sS[y * kD2Ld + x] = sv[t];
-        sFt[x * kD2Ld + y] = (x < kD2 - 1 && y < kD2 - 1) ? fv[t] : 0.f;
-    }
-    __syncthreads();
-    dst_v4f d = d2_tile(sS + i0 * kD2Ld, sFt, j0);  // T = S[i0 .. i0+15, :] f
-#pragma unroll
-    for (int q = 0; q < 4; ++q) sT[(ti + q) * kD2Ld + tj] = d[q];
-    __syncthreads();
-    d = d2_tile(sT, sS, j0);  // T S
-    float* X = a.X + (size_t)r * kD2 * kD2;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) X[(i0 + ti + q) * kD2 + tj] = mv[q] * d[q];
-}
-
-template <typename E>
-__global__ __launch_bounds__(512) void k_dst2_inv(Dst2Args<E> a) {
-    __shared__ float sS[kD2 * kD2Ld];
-    __shared__ float sXt[kD2 * kD2Ld];
-    __shared__ float sY[kD2Rows * kD2Ld];
-    const int i0 = kD2Rows * blockIdx.x, r = blockIdx.y;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const float* X = a.X + (size_t)r * kD2 * kD2;
-    constexpr int kIt = kD2 * kD2 / 512;
-    float sv[kIt], xv[kIt];
-#pragma unroll
-    for (int t = 0; t < kIt; ++t) {
-        const int i = tid + t * 512;
-        sv[t] = a.S[i];
-        xv[t] = X[i];
-    }
-#pragma unroll
-    for (int t = 0; t < kIt; ++t) {
-        const int i = tid + t * 512, y = i >> 7, x = i & (kD2 - 1);
-        sS[y * kD2Ld + x] = sv[t];
-        sXt[x * kD2Ld + y] = xv[t];
-    }
-    __syncthreads();
-    const int j0 = 16 * w, ti = 4 * (lane >> 4), tj = j0 + (lane & 15);
-    dst_v4f d = d2_tile(sS + i0 * kD2Ld, sXt, j0);  // Y = S[i0 .., :] X
-#pragma unroll
-    for (int q = 0; q < 4; ++q) sY[(ti + q) * kD2Ld + tj] = d[q];
-    __syncthreads();
-    d = d2_tile(sY, sS, j0);  // u = Y S; row and column 127 of S are 0, so node 128 gets 0
-    E* u = a.u_out[r];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) u[(size_t)(i0 + ti + q + 1) * a.pitch + tj + 1] = (E)d[q];
-    if (tid < kD2Rows) u[(size_t)(i0 + tid + 1) * a.pitch] = E(0);  // column 0
-    if (blockIdx.x == 0)
-        for (int x = tid; x <= kD2; x += 512) u[x] = E(0);  // row 0
-}
-
-// FP64 forms of the two exact coarse Poisson solves, for the mixed form,
-// whose coarsest-grid solve stays in FP64 while its V-cycle levels run in
-// FP32.  The same blocking as the FP32 kernels above, with the products on
-// FP64 MFMA (v_mfma_f64_16x16x4_f64: one 16 x 16 output tile per wavefront,
-// lane l feeding A[i0 + l % 16][4 s + l / 16] and Bt[j0 + l % 16][4 s + l / 16]
-// and holding D[i0 + 4 (l / 16) + q][j0 + l % 16], the layout of the FP32
-// instruction).  Plain FP64 fused multiply-adds from LDS were LDS-bound here:
-// a wavefront's read of one shared row element costs a full LDS pass.
+// FP64 form of the exact 64^2 coarse Poisson solve, for the mixed form, whose
+// coarsest-grid solve stays in FP64 while its V-cycle levels run in FP32.
+// The products run on FP64 MFMA (v_mfma_f64_16x16x4_f64: one 16 x 16 output
+// tile per wavefront, lane l feeding A[i0 + l % 16][4 s + l / 16] and
+// Bt[j0 + l % 16][4 s + l / 16] and holding D[i0 + 4 (l / 16) + q][j0 + l % 16],
+// the layout of the FP32 instruction).  Plain FP64 fused multiply-adds from LDS
+// were LDS-bound here: a wavefront's read of one shared row element costs a
+// full LDS pass.
 typedef double dst_v4d __attribute__((ext_vector_type(4)));
-constexpr int kD2Ld64 = kD2 + 1;     // LDS row stride (doubles) of the 128-wide operands
-constexpr int kDstLd64 = kDstN + 4;  // and of the 64 x 64 ones
-
-template <typename E>
-struct Dst2Args64 {
-    int pitch;
-    const E* f[2];
-    E* u_out[2];
-    const double* S;
-    const double* M;
-    double* X;  // [R][128][128]
-};
+constexpr int kDstLd64 = kDstN + 4;  // LDS row stride (doubles) of the 64 x 64 operands
 
 // 16 x 16 tile (rows 0..15 of A, columns j0.. of B) of A B for an inner
 // dimension n: A row-major with stride LDA, B given transposed (Bt[j][k] =
@@ -1449,120 +1326,6 @@ __device__ __forceinline__ dst_v4d tile64(const double* A, const double* Bt, int
     for (int s = 0; s < n / 4; ++s)
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[4 * s], pb[4 * s], acc, 0, 0, 0);
     return acc;
-}
-
-// Rows i0 .. i0+15 of X = M o (S F S) on the 128^2 level: T = S[i0.., :] F,
-// then X = M o (T S); F[k][j] = f(node j+1, k+1).  8 workgroups of 8
-// wavefronts per right-hand side, wavefront w owning the columns 16 w ...
-// LDS: the right operand transposed (F^T, then S, which is symmetric) and the
-// 16-row left operand (rows of S, then T).
-template <typename E>
-__global__ __launch_bounds__(512) void k_dst2_fwd64(Dst2Args64<E> a) {
-    __shared__ double sBt[kD2 * kD2Ld64];
-    __shared__ double sA[kD2Rows * kD2Ld64];
-    const int i0 = kD2Rows * blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
-    const int lane = tid & 63, j0 = 16 * (tid >> 6);
-    const int ti = 4 * (lane >> 4), tj = j0 + (lane & 15);  // this lane's outputs: rows ti + q, column tj
-    constexpr int kIt = kD2 * kD2 / 512, kRows = kD2Rows * kD2 / 512;
-    {   // every load before the first store (one round trip): the loads are
-        // unconditional (a clamped index) so that none waits for another
-        double fv[kIt], sv[kRows];
-#pragma unroll
-        for (int t = 0; t < kIt; ++t) {
-            const int i = tid + t * 512, y = i >> 7, x = i & (kD2 - 1);
-            const bool in = x < kD2 - 1 && y < kD2 - 1;
-            const double v = (double)a.f[r][in ? (size_t)(y + 1) * a.pitch + x + 1 : 0];
-            fv[t] = in ? v : 0.0;
-        }
-#pragma unroll
-        for (int t = 0; t < kRows; ++t) sv[t] = a.S[i0 * kD2 + tid + t * 512];
-#pragma unroll
-        for (int t = 0; t < kIt; ++t) {
-            const int i = tid + t * 512, y = i >> 7, x = i & (kD2 - 1);
-            sBt[x * kD2Ld64 + y] = fv[t];
-        }
-#pragma unroll
-        for (int t = 0; t < kRows; ++t) {
-            const int i = tid + t * 512;
-            sA[(i >> 7) * kD2Ld64 + (i & (kD2 - 1))] = sv[t];
-        }
-    }
-    __syncthreads();
-    dst_v4d d = tile64<kD2, kD2Ld64, kD2Ld64>(sA, sBt, j0);  // T = S[i0.., :] F
-    __syncthreads();  // every read of the rows of S and of F is done
-    {
-        double sv[kIt];
-#pragma unroll
-        for (int t = 0; t < kIt; ++t) sv[t] = a.S[tid + t * 512];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) sA[(ti + q) * kD2Ld64 + tj] = d[q];
-#pragma unroll
-        for (int t = 0; t < kIt; ++t) {
-            const int i = tid + t * 512;
-            sBt[(i >> 7) * kD2Ld64 + (i & (kD2 - 1))] = sv[t];
-        }
-    }
-    __syncthreads();
-    d = tile64<kD2, kD2Ld64, kD2Ld64>(sA, sBt, j0);  // T S
-    double* X = a.X + (size_t)r * kD2 * kD2;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int i = (i0 + ti + q) * kD2 + tj;
-        X[i] = a.M[i] * d[q];
-    }
-}
-
-// Rows i0 .. i0+15 of u = S X S: Y = S[i0.., :] X, then u = Y S.
-template <typename E>
-__global__ __launch_bounds__(512) void k_dst2_inv64(Dst2Args64<E> a) {
-    __shared__ double sBt[kD2 * kD2Ld64];
-    __shared__ double sA[kD2Rows * kD2Ld64];
-    const int i0 = kD2Rows * blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
-    const int lane = tid & 63, j0 = 16 * (tid >> 6);
-    const int ti = 4 * (lane >> 4), tj = j0 + (lane & 15);
-    constexpr int kIt = kD2 * kD2 / 512, kRows = kD2Rows * kD2 / 512;
-    const double* X = a.X + (size_t)r * kD2 * kD2;
-    {
-        double xv[kIt], sv[kRows];
-#pragma unroll
-        for (int t = 0; t < kIt; ++t) xv[t] = X[tid + t * 512];
-#pragma unroll
-        for (int t = 0; t < kRows; ++t) sv[t] = a.S[i0 * kD2 + tid + t * 512];
-#pragma unroll
-        for (int t = 0; t < kIt; ++t) {
-            const int i = tid + t * 512, y = i >> 7, x = i & (kD2 - 1);
-            sBt[x * kD2Ld64 + y] = xv[t];
-        }
-#pragma unroll
-        for (int t = 0; t < kRows; ++t) {
-            const int i = tid + t * 512;
-            sA[(i >> 7) * kD2Ld64 + (i & (kD2 - 1))] = sv[t];
-        }
-    }
-    __syncthreads();
-    dst_v4d d = tile64<kD2, kD2Ld64, kD2Ld64>(sA, sBt, j0);  // Y = S[i0.., :] X
-    __syncthreads();
-    {
-        double sv[kIt];
-#pragma unroll
-        for (int t = 0; t < kIt; ++t) sv[t] = a.S[tid + t * 512];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) sA[(ti + q) * kD2Ld64 + tj] = d[q];
-#pragma unroll
-        for (int t = 0; t < kIt; ++t) {
-            const int i = tid + t * 512;
-            sBt[(i >> 7) * kD2Ld64 + (i & (kD2 - 1))] = sv[t];
-        }
-    }
-    __syncthreads();
-    d = tile64<kD2, kD2Ld64, kD2Ld64>(sA, sBt, j0);  // u = Y S
-    E* u = a.u_out[r];
-    // row and column 127 of S are 0, so row and column 128 (boundary) get 0
-#pragma unroll
-    for (int q = 0; q < 4; ++q) u[(size_t)(i0 + ti + q + 1) * a.pitch + tj + 1] = (E)d[q];
-    if (tid < kD2Rows) u[(size_t)(i0 + tid + 1) * a.pitch] = E(0);  // column 0
-    if (blockIdx.x == 0)
-        for (int x = tid; x <= kD2; x += 512) u[x] = E(0);  // row 0
 }
 
 // The 64^2 exact solve in FP64 (grids of 128^2): one workgroup of 16
@@ -1999,9 +1762,10 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
     auto U = [&](int l, int r) { return l == 0 ? hz.u0[r] : lev_u<E>(c->lev[l], r); };
     auto F = [&](int l, int r) { return l == 0 ? hz.f0[r] : lev_f<E>(c->lev[l], r); };
     auto K = [&](int l) { return l == 0 ? hz.k2 : (const double*)c->lev[l].k2; };
-    // Poisson: the V-cycle ends with the exact solve on the 128^2 level when
-    // that lies below a finer level
-    const int lb = (!helm && dst128_used(c)) ? lc - 1 : lc;
+    // Poisson: the V-cycle ends with the exact fast-sine-transform solve on
+    // level 1 when that is 128^2 .. 2048^2
+    const bool fst = !helm && fst_used(c);
+    const int lb = fst ? 1 : lc;
     // relaxation factor of the smoothing sweeps: the Helmholtz levels whose
     // diagonal shift is no longer small (h^2 n0 > 1/8) relax with factor 1
     const double om = helm ? c->cfg.mg_omega_helm : c->cfg.mg_omega;
@@ -2043,51 +1807,10 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
     }
     // the mixed form's inner cycles (E = float) solve their coarsest grid in FP64
     constexpr bool coarse64 = std::is_same<E, float>::value;
-    if (lb < lc && coarse64) {
-        wq::Level& L = c->lev[lb];
-        Dst2Args64<E> d{};
-        d.pitch = L.pitch;
-        for (int r = 0; r < R; ++r) {
-            d.f[r] = F(lb, r);
-            d.u_out[r] = U(lb, r);
-        }
-        d.S = c->dst2_S64;
-        d.M = c->dst2_M64;
-        d.X = c->dst2_X64;
-        const double nodes = (double)(L.N + 1) * (L.N + 1);
-        const dim3 g(kD2 / kD2Rows, R);
-        {
-            ProfScope ps(c, "k_dst2_fwd64<float>", nodes * eb * R + 8.0 * kD2 * kD2 * (2.0 + R));
-            WQ_KLAUNCH(ps, k_dst2_fwd64<E>, g, dim3(512), 0, s, d);
-        }
-        {
-            ProfScope ps(c, "k_dst2_inv64<float>", nodes * eb * R + 8.0 * kD2 * kD2 * (1.0 + R));
-            WQ_KLAUNCH(ps, k_dst2_inv64<E>, g, dim3(512), 0, s, d);
-        }
-    } else if (lb < lc) {
-        wq::Level& L = c->lev[lb];
-        Dst2Args<E> d{};
-        d.pitch = L.pitch;
-        for (int r = 0; r < R; ++r) {
-            d.f[r] = F(lb, r);
-            d.u_out[r] = U(lb, r);
-        }
-        d.S = c->dst2_S;
-        d.M = c->dst2_M;
-        d.X = c->dst2_X;
-        const double nodes = (double)(L.N + 1) * (L.N + 1);
-        const dim3 g(kD2 / kD2Rows, R);
-        char nm[64];
-        prof_name(c, nm, sizeof nm, "k_dst2_fwd<%s>", type_name(E()));
-        {
-            ProfScope ps(c, nm, nodes * eb * R + 4.0 * kD2 * kD2 * (2.0 + R));
-            WQ_KLAUNCH(ps, k_dst2_fwd<E>, g, dim3(512), 0, s, d);
-        }
-        prof_name(c, nm, sizeof nm, "k_dst2_inv<%s>", type_name(E()));
-        {
-            ProfScope ps(c, nm, nodes * eb * R + 4.0 * kD2 * kD2 * (1.0 + R));
-            WQ_KLAUNCH(ps, k_dst2_inv<E>, g, dim3(512), 0, s, d);
-        }
+    if (fst) {
+        const E* fo[2] = {F(1, 0), R > 1 ? F(1, 1) : nullptr};
+        E* uo[2] = {U(1, 0), R > 1 ? U(1, 1) : nullptr};
+        fst_solve<E>(c, R, fo, uo);
     } else {
         wq::Level& L = c->lev[lc];
         CoarseArgs<E> a{};
@@ -2249,16 +1972,10 @@ wandqs_status make_dst_tables(wandqs_ctx* c) {
     const int n1 = kDstN;
     hipLaunchKernelGGL(k_dst_tables, dim3((n1 * n1 + 255) / 256), dim3(256), 0, c->stream, n1,
                        c->lev[c->lc].h, c->dst_S, c->dst_M, c->dst_S64, c->dst_M64);
-    if (dst128_used(c))
-        hipLaunchKernelGGL(k_dst_tables, dim3((kD2 * kD2 + 255) / 256), dim3(256), 0, c->stream, kD2,
-                           c->lev[c->lc - 1].h, c->dst2_S, c->dst2_M, c->dst2_S64, c->dst2_M64);
     WQ_LAUNCH_CHECK();
-    return WANDQS_OK;
+    return make_fst_tables(c);
 }
 
-bool dst128_used(const wandqs_ctx* c) {
-    return WQ_DST128 && c->lc >= 2 && c->lev[c->lc - 1].N == kD2;
-}
 
 // Launches one cycle, body() on c->stream, as a HIP graph: the graph of `key`
 // is captured on c->cap_stream and instantiated at its first use and replayed

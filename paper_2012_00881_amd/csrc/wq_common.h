@@ -261,18 +261,18 @@ struct wandqs_ctx {
     // the scaled inverse eigenvalues M, [64][64] float each (zero row/column 63)
     float* dst_S = nullptr;
     float* dst_M = nullptr;
-    // the same on the 128^2 level (when it lies below a finer one), and the
-    // intermediate X = M o (S f S), [2][128][128] float
-    float* dst2_S = nullptr;
-    float* dst2_M = nullptr;
-    float* dst2_X = nullptr;
-    // double copies of the tables and X for the mixed form, whose coarsest-grid
+    // double copies of the tables for the mixed form, whose coarsest-grid
     // solve runs in FP64 (null in the FP64 form)
     double* dst_S64 = nullptr;
     double* dst_M64 = nullptr;
-    double* dst2_S64 = nullptr;
-    double* dst2_M64 = nullptr;
-    double* dst2_X64 = nullptr;
+    // exact Poisson solve on level 1 by fast sine transforms (levels of 128^2
+    // to 2048^2 below a finer one): the FP64 intermediates T1, T2 of each
+    // right-hand side, [N1 - 1][N1 + 8]; the FFT twiddles exp(-2 pi i m / 2 N1),
+    // m < 2 N1; and sin^2(pi k / 2 N1), k <= N1
+    double* fst_t1[2] = {};
+    double* fst_t2[2] = {};
+    double2* fst_tw = nullptr;
+    double* fst_s2 = nullptr;
     double* pa[2][4] = {};
     int32_t* pid[2] = {};
     int cur = 0;
@@ -335,10 +335,19 @@ int reg_tile_min_default();
 // largest level with 16 x 16 LDS tiles by default
 int small_tile_max_default();
 // tables of the exact coarse-level Poisson solves (the 64^2 level and, when
-// used, the 128^2 level), made on the device on the context's stream
+// used, the fast sine transform solve on level 1), made on the device on the
+// context's stream
 wandqs_status make_dst_tables(wandqs_ctx* c);
-// whether the Poisson V-cycles end with the exact solve on the 128^2 level
-bool dst128_used(const wandqs_ctx* c);
+// fast sine transform solve (fst.hip): whether the Poisson V-cycles end with
+// it on level 1, the row stride of its intermediates, its tables, and the
+// solve itself (R right-hand sides f of level 1 into u of level 1)
+constexpr int kFstMinN = 128;
+constexpr int kFstMaxN = 2048;
+bool fst_used(const wandqs_ctx* c);
+size_t fst_ld(const wandqs_ctx* c);
+wandqs_status make_fst_tables(wandqs_ctx* c);
+template <typename E>
+void fst_solve(wandqs_ctx* c, int R, const E* const* f, E* const* u);
 
 // multigrid (mg.hip)
 wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const u[2],
