@@ -130,23 +130,30 @@ __device__ __forceinline__ void tile_load(E (*su)[EX * EY], E (&fr)[R][KP][2], E
                                           const double* k2, int pitch, int ex0, int ey0, int N,
                                           double h2) {
     constexpr int PW = EX / 2, NP = PW * EY;
+    // Every load and LDS store is unconditional, so that the loads are all in
+    // flight at once (the compiler waits for a load moved behind a
+    // lane-dependent branch before the branch ends): the threads past the
+    // tile redo the last pair (the same values to the same slots), the
+    // indices are clamped into the grid and the values outside it masked by a
+    // product with 0 (every value loaded is finite).
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-        const int p = threadIdx.x + k * NT;
+        const int p = min((int)threadIdx.x + k * NT, NP - 1);
         const int ly = p / PW, px = p - ly * PW;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int lx = 2 * px + j;
             const int gx = ex0 + lx, gy = ey0 + ly;
-            const bool in = p < NP && gx >= 0 && gx <= N && gy >= 0 && gy <= N;
-            const size_t g = in ? (size_t)gy * pitch + gx : 0;
+            const bool in = gx >= 0 && gx <= N && gy >= 0 && gy <= N;
+            const size_t g = (size_t)min(max(gy, 0), N) * pitch + min(max(gx, 0), N);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const E uv = (in && u[r]) ? u[r][g] : E(0);
-                if (p < NP) su[r][ly * EX + lx] = uv;
-                fr[r][k][j] = in ? f[r][g] : E(0);
+                const E* ur = u[r] ? u[r] : f[r];
+                const E uv = ur[g] * E(in && u[r] ? 1 : 0);
+                su[r][ly * EX + lx] = uv;
+                fr[r][k][j] = f[r][g] * E(in ? 1 : 0);
             }
-            const double D = fmad(h2, (HELM && in) ? k2[g] : 0.0, 4.0);
+            const double D = fmad(h2, HELM ? k2[g] * (in ? 1.0 : 0.0) : 0.0, 4.0);
             Dr[k][j] = (E)D;
             iDr[k][j] = HELM ? (E)(1.0 / D) : E(0.25);
         }
@@ -390,12 +397,17 @@ __global__ __launch_bounds__(tile_threads<T>()) void k_mg_up(UpArgs<E> a) {
     E fr[R][KP][2], Dr[KP][2], iDr[KP][2];
     tile_load<E, R, HELM, EX, EY, KP, NT>(su, fr, Dr, iDr, a.u_mid + z, a.f + z, a.k2, a.pitch, ex0, ey0, N,
                                       a.h * a.h);
-    for (int i = tid; i < CX * CY; i += NT) {
+    // the coarse correction, loaded as the tile (threads past the end redo
+    // the last node)
+#pragma unroll
+    for (int q = 0; q < (CX * CY + NT - 1) / NT; ++q) {
+        const int i = min(tid + q * NT, CX * CY - 1);
         const int cy = i / CX, cx = i - cy * CX;
         const int I = cx0 + cx, J = cy0 + cy;
         const bool in = I >= 0 && I <= Nc && J >= 0 && J <= Nc;
+        const size_t g = (size_t)min(max(J, 0), Nc) * a.pitch_c + min(max(I, 0), Nc);
 #pragma unroll
-        for (int r = 0; r < R; ++r) se[r][i] = in ? a.e_c[r + z][(size_t)J * a.pitch_c + I] : E(0);
+        for (int r = 0; r < R; ++r) se[r][i] = a.e_c[r + z][g] * E(in ? 1 : 0);
     }
     __syncthreads();
 
@@ -1057,11 +1069,13 @@ template <typename E, typename C, bool HELM>
 __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
     constexpr int TOT = coarse_nodes();
     constexpr bool FAST = sizeof(C) == 4;
-    __shared__ C su[TOT];
-    __shared__ C sf[TOT];
-    __shared__ C sk[HELM ? TOT : 1];
-    __shared__ C siD[(HELM && FAST) ? TOT : 1];
-    __shared__ float siDf[(HELM && !FAST) ? TOT : 1];  // float 1/D for the double sweeps
+    // (slot TOT of each array takes the stores of the threads past the end,
+    // so that no branch guards a store of loaded data)
+    __shared__ C su[TOT + 1];
+    __shared__ C sf[TOT + 1];
+    __shared__ C sk[HELM ? TOT + 1 : 1];
+    __shared__ C siD[(HELM && FAST) ? TOT + 1 : 1];
+    __shared__ float siDf[(HELM && !FAST) ? TOT + 1 : 1];  // float 1/D for the double sweeps
     __shared__ C sr[FAST ? (kCoarseMax + 1) * (kCoarseMax + 1) : 1];
     const int r = blockIdx.x;
     const int tid = threadIdx.x;
@@ -1074,9 +1088,29 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
         ++nl;
     }
     const int N = a.N;
-    // loads in batches of kB per thread so that their latencies overlap
+    // loads in batches of kB per thread so that their latencies overlap; every
+    // load and every LDS store of its value is unconditional (an index clamped
+    // into its array, the value selected after it, the store of a thread past
+    // the end going to slot TOT): a load that the compiler can move behind a
+    // lane-dependent branch is waited for before the branch ends, which would
+    // serialize the batch
     constexpr int kB = 8;
     const int nt = (N + 1) * (N + 1);
+    const bool has_u = a.u_init[r] != nullptr;
+    const E* ui = has_u ? a.u_init[r] : a.f[r];
+    const E* fi = a.f[r];
+    // (the values are masked by a product with 0 or 1, not a select: the
+    // compiler turns a select between a loaded value and a constant into a
+    // branch around the load; every value loaded here is finite)
+    const auto load_uf = [&](int i, E& uo, E& fo) {
+        const int ic = min(i, nt - 1);
+        const int y = ic / (N + 1), x = ic - y * (N + 1);
+        const size_t g = (size_t)y * a.pitch + x;
+        const E ut = ui[g], ft = fi[g];
+        const bool ok = i < nt && x != 0 && y != 0 && x != N && y != N;
+        uo = ut * E(ok && has_u ? 1 : 0);
+        fo = ft * E(ok ? 1 : 0);
+    };
     if (HELM && tot <= kB * kCoarseThreads) {
         // one batch: u, f, k2 and 1/D all issued before the first LDS store
         // (k2 in the type of the sweeps; 1/D always from the float table)
@@ -1085,84 +1119,49 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
         float dv[kB];
 #pragma unroll
         for (int b = 0; b < kB; ++b) {
-            const int i = b * kCoarseThreads + tid;
-            const int y = i / (N + 1), x = i - y * (N + 1);
-            const bool ok = i < nt && x != 0 && y != 0 && x != N && y != N;
-            const size_t g = ok ? (size_t)y * a.pitch + x : 0;
-            uv[b] = (ok && a.u_init[r]) ? a.u_init[r][g] : E(0);
-            fv[b] = ok ? a.f[r][g] : E(0);
-            kv[b] = i < tot ? (FAST ? (C)a.k2levf[i] : (C)a.k2lev[i]) : C(0);
-            dv[b] = i < tot ? a.idlevf[i] : 0.f;
+            const int i = b * kCoarseThreads + tid, ic = min(i, tot - 1);
+            load_uf(i, uv[b], fv[b]);
+            kv[b] = FAST ? (C)a.k2levf[ic] : (C)a.k2lev[ic];
+            dv[b] = a.idlevf[ic];
         }
 #pragma unroll
         for (int b = 0; b < kB; ++b) {
             const int i = b * kCoarseThreads + tid;
-            if (i < nt) {
-                su[i] = (C)uv[b];
-                sf[i] = (C)fv[b];
-            }
-            if (i < tot) {
-                sk[i] = kv[b];
-                if (FAST) siD[i] = (C)dv[b];
-                else siDf[i] = dv[b];
-            }
+            const int iu = i < nt ? i : TOT, ik = i < tot ? i : TOT;
+            su[iu] = (C)uv[b];
+            sf[iu] = (C)fv[b];
+            sk[ik] = kv[b];
+            if (FAST) siD[ik] = (C)dv[b];
+            else siDf[ik] = dv[b];
         }
     } else {
         for (int base = 0; base < nt; base += kB * kCoarseThreads) {
             E uv[kB], fv[kB];
 #pragma unroll
-            for (int b = 0; b < kB; ++b) {
-                const int i = base + b * kCoarseThreads + tid;
-                const int y = i / (N + 1), x = i - y * (N + 1);
-                const bool ok = i < nt && x != 0 && y != 0 && x != N && y != N;
-                const size_t g = ok ? (size_t)y * a.pitch + x : 0;
-                uv[b] = (ok && a.u_init[r]) ? a.u_init[r][g] : E(0);
-                fv[b] = ok ? a.f[r][g] : E(0);
-            }
+            for (int b = 0; b < kB; ++b) load_uf(base + b * kCoarseThreads + tid, uv[b], fv[b]);
 #pragma unroll
             for (int b = 0; b < kB; ++b) {
-                const int i = base + b * kCoarseThreads + tid;
-                if (i < nt) {
-                    su[i] = (C)uv[b];
-                    sf[i] = (C)fv[b];
-                }
+                const int i = base + b * kCoarseThreads + tid, iu = i < nt ? i : TOT;
+                su[iu] = (C)uv[b];
+                sf[iu] = (C)fv[b];
             }
         }
-        if (HELM && FAST)  // k2 and 1/D of every level, made once per solve by k_coarse_k2
+        if (HELM)  // k2 and 1/D of every level, made once per solve by k_coarse_k2
             for (int base = 0; base < tot; base += kB * kCoarseThreads) {
-                float kv[kB], dv[kB];
-#pragma unroll
-                for (int b = 0; b < kB; ++b) {
-                    const int i = base + b * kCoarseThreads + tid;
-                    kv[b] = i < tot ? a.k2levf[i] : 0.f;
-                    dv[b] = i < tot ? a.idlevf[i] : 0.f;
-                }
-#pragma unroll
-                for (int b = 0; b < kB; ++b) {
-                    const int i = base + b * kCoarseThreads + tid;
-                    if (i < tot) {
-                        sk[i] = (C)kv[b];
-                        siD[i] = (C)dv[b];
-                    }
-                }
-            }
-        else if (HELM)
-            for (int base = 0; base < tot; base += kB * kCoarseThreads) {
-                double kv[kB];
+                C kv[kB];
                 float dv[kB];
 #pragma unroll
                 for (int b = 0; b < kB; ++b) {
-                    const int i = base + b * kCoarseThreads + tid;
-                    kv[b] = i < tot ? a.k2lev[i] : 0.0;
-                    dv[b] = i < tot ? a.idlevf[i] : 0.f;
+                    const int i = base + b * kCoarseThreads + tid, ic = min(i, tot - 1);
+                    kv[b] = FAST ? (C)a.k2levf[ic] : (C)a.k2lev[ic];
+                    dv[b] = a.idlevf[ic];
                 }
 #pragma unroll
                 for (int b = 0; b < kB; ++b) {
-                    const int i = base + b * kCoarseThreads + tid;
-                    if (i < tot) {
-                        sk[i] = (C)kv[b];
-                        siDf[i] = dv[b];
-                    }
+                    const int i = base + b * kCoarseThreads + tid, ik = i < tot ? i : TOT;
+                    sk[ik] = kv[b];
+                    if (FAST) siD[ik] = (C)dv[b];
+                    else siDf[ik] = dv[b];
                 }
             }
     }
