@@ -229,10 +229,9 @@ __global__ __launch_bounds__(tile_threads<T>()) void k_mg_down(DownArgs<E> a) {
     __shared__ double red[(NT / 64) * 3 * R];
 
     const int tid = threadIdx.x;
-    const int z = blockIdx.z;  // right-hand side of a split launch (R = 1, one per z)
     const int N = a.N;
-    int bx, by;
-    tile_of_block(bx, by);
+    int bx, by, z;  // z: right-hand side of a split launch (R = 1, one per z)
+    tile_rhs_of_block(bx, by, z);
     const int x0 = bx * T, y0 = by * T;
     const int ex0 = x0 - HL, ey0 = y0 - HL;
     const E h2 = (E)(a.h * a.h), ih2 = (E)(1.0 / (a.h * a.h));
@@ -384,10 +383,9 @@ __global__ __launch_bounds__(tile_threads<T>()) void k_mg_up(UpArgs<E> a) {
     __shared__ E se[R][CX * CY];
 
     const int tid = threadIdx.x;
-    const int z = blockIdx.z;  // right-hand side of a split launch (R = 1, one per z)
     const int N = a.N, Nc = N / 2;
-    int bx, by;
-    tile_of_block(bx, by);
+    int bx, by, z;  // z: right-hand side of a split launch (R = 1, one per z)
+    tile_rhs_of_block(bx, by, z);
     const int x0 = bx * T, y0 = by * T;
     const int ex0 = x0 - H, ey0 = y0 - H;  // even
     const int cx0 = ex0 / 2, cy0 = ey0 / 2;
@@ -655,10 +653,9 @@ __global__ __launch_bounds__(64 * NW) void k_mg_down_reg(DownArgs<E> a) {
     const RegExchange<E, R, K, NW> xc{xb};
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int z = blockIdx.z;  // right-hand side of a split launch (R = 1, one per z)
     const int N = a.N;
-    int bx, by;
-    tile_of_block(bx, by);
+    int bx, by, z;  // z: right-hand side of a split launch (R = 1, one per z)
+    tile_rhs_of_block(bx, by, z);
     const int x0 = bx * TX, y0 = by * TY;
     const int ex0 = x0 - HL, ey0 = y0 - HL;
     const int gx = ex0 + 2 * lane, gy0 = ey0 + w * K;
@@ -790,10 +787,9 @@ __global__ __launch_bounds__(64 * NW) void k_mg_up_reg(UpArgs<E> a) {
     const RegExchange<E, R, K, NW> xc{xb};
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int z = blockIdx.z;  // right-hand side of a split launch (R = 1, one per z)
     const int N = a.N, Nc = N / 2;
-    int bx, by;
-    tile_of_block(bx, by);
+    int bx, by, z;  // z: right-hand side of a split launch (R = 1, one per z)
+    tile_rhs_of_block(bx, by, z);
     const int x0 = bx * TX, y0 = by * TY;
     const int ex0 = x0 - H, ey0 = y0 - H;
     const int gx = ex0 + 2 * lane, gy0 = ey0 + w * K;

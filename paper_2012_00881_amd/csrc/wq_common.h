@@ -75,6 +75,20 @@ __device__ __forceinline__ void tile_of_block(int& bx, int& by) {
     bx = t - by * gx;
 }
 
+// The same over a 3-D grid whose z indexes the right-hand sides of a split
+// launch: a tile's right-hand sides follow each other in its XCD's range, so
+// the operator's array that both read (k2) is fetched into that XCD's L2 once.
+__device__ __forceinline__ void tile_rhs_of_block(int& bx, int& by, int& z) {
+    const int gx = gridDim.x, gz = gridDim.z, n = gx * gridDim.y * gz;
+    const int b = (blockIdx.z * gridDim.y + blockIdx.y) * gx + blockIdx.x;
+    const int k = b & 7, q = n >> 3, r = n & 7;
+    const int t = k * q + (k < r ? k : r) + (b >> 3);
+    z = t % gz;
+    const int tile = t / gz;
+    by = tile / gx;
+    bx = tile - by * gx;
+}
+
 enum SolveKind {
     kSolvePsi = 0,
     kSolveEB = 1,

@@ -61,9 +61,9 @@ def _rand_rhs(N, seed, nrhs=1):
     return f
 
 
-@pytest.mark.parametrize("N", [8, 16, 64, 128, 256, 512, 1024])
-@pytest.mark.parametrize("helm", [False, True])
-@pytest.mark.parametrize("nrhs", [1, 2])
+@pytest.mark.parametrize("N,helm,nrhs", [(N, helm, nrhs) for N in (8, 16, 64, 128, 256, 512, 1024)
+                                          for helm in (False, True) for nrhs in (1, 2)]
+                         + [(2048, False, 2)])
 def test_mg_solve_matches_oracle(torch_cuda, oracle_mod, N, helm, nrhs):
     L = 6.0
     h = 2 * L / N
@@ -84,18 +84,27 @@ def test_mg_solve_matches_oracle(torch_cuda, oracle_mod, N, helm, nrhs):
     sim.close()
 
 
-def test_mg_sine_eigenmode_closed_form(torch_cuda):
-    """GPU solve of L_h u = lambda s recovers the exact eigenvector s."""
-    N, L = 256, 8.0
+@pytest.mark.parametrize("N", [256, 1024, 2048, 4096])
+def test_mg_sine_eigenmode_closed_form(torch_cuda, N):
+    """GPU solve of L_h u = lambda s recovers the exact eigenvector s, for two
+    right-hand sides at once (a smooth and an oscillating mode): the Poisson
+    V-cycles end with the fast sine transform solve on level 1 (FFT lengths
+    256 .. 4096)."""
+    L = 8.0
     h = 2 * L / N
     a = np.arange(N + 1)
-    k, l = 5, 3
-    s = np.outer(np.sin(l * np.pi * a / N), np.sin(k * np.pi * a / N))
-    lam = -(4 / h**2) * (np.sin(k * np.pi / (2 * N)) ** 2 + np.sin(l * np.pi / (2 * N)) ** 2)
-    sim = _sim(wi.scaled(wi.config("C2"), n_cells=N))
-    st, u, cyc, _ = sim.mg_solve(lam * s)
+    modes = [(5, 3), (N // 2 + 7, N - 9)]
+    s = np.stack([np.outer(np.sin(l * np.pi * a / N), np.sin(k * np.pi * a / N)) for k, l in modes])
+    lam = np.array([-(4 / h**2) * (np.sin(k * np.pi / (2 * N)) ** 2 + np.sin(l * np.pi / (2 * N)) ** 2)
+                    for k, l in modes])
+    cfg = wi.scaled(wi.config("C2"), n_cells=N, half_width=L, ppc_side=1)
+    sim = _sim(cfg)
+    st, u, cyc, _ = sim.mg_solve(lam[:, None, None] * s)
     assert st == 0
-    assert np.abs(u.cpu().numpy()[0] - s).max() <= 1e-12
+    err = np.abs(u.cpu().numpy() - s).max()
+    print(f"N={N}: cycles {cyc}, max error {err:.2e}")
+    assert err <= 1e-12
+    sim.close()
 
 
 # ------------------------------------------------------------ one slice -----
