@@ -140,6 +140,8 @@ void set_sizes(wandqs_ctx* c, const wandqs_config* cfg, int32_t n_slices) {
         const std::string spm = sp ? sp : "";
         c->reg_split = !(spm == "0" || spm == "lds");
         c->lds_split = !(spm == "0" || spm == "reg");
+        const char* fu = std::getenv("WANDQS_MG_FUSE");
+        c->mg_fuse = !(fu && std::strcmp(fu, "0") == 0);
         const char* g = std::getenv("WANDQS_GRAPHS");
         c->graphs_on = g && std::strcmp(g, "1") == 0;
     }
@@ -369,6 +371,7 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
         for (int k = 0; k < 5; ++k) c->fields_prev3[k] = arr(0);
     for (int r = 0; r < 2; ++r) {
         L0.um[r] = arr(0);
+        L0.um2[r] = c->N >= c->reg_tile_min ? arr(0) : nullptr;
         L0.f[r] = arr(0);
     }
     L0.k2 = arr(0);
@@ -519,6 +522,7 @@ size_t wq::carve_solver(wandqs_ctx* c, char* base) {
     for (int k = 0; k < 2; ++k) c->fields[k] = arr(0);
     for (int r = 0; r < 2; ++r) {
         L0.um[r] = arr(0);
+        L0.um2[r] = c->N >= c->reg_tile_min ? arr(0) : nullptr;
         L0.f[r] = arr(0);
     }
     L0.k2 = arr(0);

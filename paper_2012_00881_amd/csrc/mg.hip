@@ -504,10 +504,11 @@ template <typename E> struct Pair2;
 template <> struct Pair2<double> { using T = double2; };
 template <> struct Pair2<float> { using T = float2; };
 
-// Geometry of a register tile with halo HL: owned TX x TY nodes.
-template <int HL, int NW>
+// Geometry of a register tile with halo HL: owned TX x TY nodes (K rows per
+// wavefront).
+template <int HL, int NW, int K = kRegRows>
 struct RegShape {
-    static constexpr int ROWS = kRegRows * NW;
+    static constexpr int ROWS = K * NW;
     static constexpr int TX = 128 - 2 * HL, TY = ROWS - 2 * HL;
     static_assert(TY > 0 && HL % 2 == 0, "register tile shape");
 };
@@ -906,6 +907,190 @@ __global__ __launch_bounds__(64 * NW) void k_mg_up_reg(UpArgs<E> a) {
         }
     }
 }
+
+// Up pass of one V-cycle fused with the down pass of the next, on the finest
+// level (register tiles, FP64, one right-hand side per workgroup): the tile of
+// the smoothed iterate of the last down pass is corrected by the prolonged
+// coarse correction and post-smoothed (the up pass), the residual norms of that
+// iterate are recorded (those the next down pass would record), then it is
+// pre-smoothed, written, and its residual restricted (the down pass).  The
+// arithmetic and its order are those of the two passes, so the result has the
+// same bits; the iterate between them never goes to memory.  Halo: 2 NU2 + 2
+// NU1 + 2 nodes.
+template <typename E>
+struct FuseArgs {
+    int N;
+    double h;
+    int pitch, pitch_c;
+    const E* u_mid[2];  // smoothed iterate of the previous down pass
+    const E* e_c[2];    // coarse correction
+    const E* f[2];
+    const double* k2;
+    E* u_out[2];        // smoothed iterate of this pass's down part
+    E* f_c[2];          // restricted residual
+    double omega;
+    double* norm_part;  // [3R][nblk]: sums r^2, f^2, u^2 of the up part's result
+    int nblk;
+};
+
+template <typename E, int R, bool HELM, int NU1, int NU2, int NW, int K>
+__global__ __launch_bounds__(64 * NW) void k_mg_updown_reg(FuseArgs<E> a) {
+    constexpr int HL = 2 * NU2 + 2 * NU1 + 2;
+    using S = RegShape<HL, NW, K>;
+    constexpr int TX = S::TX, TY = S::TY, ROWS = S::ROWS;
+    using V2 = typename Pair2<E>::T;
+    __shared__ V2 xb[2][R][NW][2][64];
+    __shared__ double red[NW * 3 * R];
+    const RegExchange<E, R, K, NW> xc{xb};
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int N = a.N, Nc = N / 2;
+    int bx, by, z;  // z: right-hand side of a split launch (R = 1, one per z)
+    tile_rhs_of_block(bx, by, z);
+    const int x0 = bx * TX, y0 = by * TY;
+    const int ex0 = x0 - HL, ey0 = y0 - HL;
+    const int gx = ex0 + 2 * lane, gy0 = ey0 + w * K;
+    const E h2 = (E)(a.h * a.h), ih2 = (E)(1.0 / (a.h * a.h));
+    const E om = (E)a.omega;
+
+    E u[R][K][2], f[R][K][2], D[K][2], iD[K][2];
+    reg_load<E, R, HELM, K>(u, f, D, iD, a.u_mid + z, a.f + z, a.k2, a.pitch, gx, gy0, N, a.h * a.h);
+
+    // up part: coarse correction at (I, J0 + m) and (I + 1, J0 + m)
+    constexpr int KC = K / 2 + 1;
+    const int I = ex0 / 2 + lane, J0 = gy0 / 2;
+    E eL[R][KC], eR[R][KC];
+#pragma unroll
+    for (int m = 0; m < KC; ++m) {
+        const int J = J0 + m;
+        const bool inJ = J >= 0 && J <= Nc;
+        const bool inL = inJ && I >= 0 && I <= Nc, inR = inJ && I + 1 >= 0 && I + 1 <= Nc;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            eL[r][m] = inL ? a.e_c[r + z][(size_t)J * a.pitch_c + I] : E(0);
+            eR[r][m] = inR ? a.e_c[r + z][(size_t)J * a.pitch_c + I + 1] : E(0);
+        }
+    }
+    bool upd[K][2], dom[K][2], own[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int Y = w * K + k, gy = gy0 + k;
+        own[k] = Y >= HL && Y < HL + TY;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int X = 2 * lane + j;
+            dom[k][j] = gx + j >= 1 && gx + j <= N - 1 && gy >= 1 && gy <= N - 1;
+            upd[k][j] = dom[k][j] && X >= 1 && X <= 126 && Y >= 1 && Y <= ROWS - 2;
+            const int m = k / 2;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                E v;
+                if (!(k & 1)) v = j == 0 ? eL[r][m] : E(0.5) * (eL[r][m] + eR[r][m]);
+                else if (j == 0) v = E(0.5) * (eL[r][m] + eL[r][m + 1]);
+                else v = E(0.25) * (eL[r][m] + eR[r][m] + eL[r][m + 1] + eR[r][m + 1]);
+                if (dom[k][j]) u[r][k][j] += v;
+            }
+        }
+    }
+    const bool own_x = 2 * lane >= HL && 2 * lane < HL + TX;
+
+    V2 up[R], dn[R];
+    int buf = 0;
+#pragma unroll
+    for (int q = 0; q < 2 * NU2; ++q) {
+        xc.put(buf, u, w, lane);
+        __syncthreads();
+        xc.get(buf, up, dn, w, lane);
+        buf ^= 1;
+        reg_half_sweep<E, R, HELM, K>(u, f, iD, upd, up, dn, h2, om, q & 1);
+    }
+
+    // the norms of the up part's result (the next cycle's incoming iterate)
+    xc.put(buf, u, w, lane);
+    __syncthreads();
+    xc.get(buf, up, dn, w, lane);
+    buf ^= 1;
+    {
+        E rr[R][K][2];
+        reg_residual<E, R, K>(rr, u, f, D, dom, up, dn, ih2);
+        double acc[3 * R];
+#pragma unroll
+        for (int q = 0; q < 3 * R; ++q) acc[q] = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                if (own[k] && own_x && dom[k][j])
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const double rv = rr[r][k][j];
+                        const double fv = f[r][k][j];
+                        const double uv = u[r][k][j];
+                        acc[3 * r] += rv * rv;
+                        acc[3 * r + 1] += fv * fv;
+                        acc[3 * r + 2] += uv * uv;
+                    }
+        block_sum<3 * R, 64 * NW>(acc, red);
+        if (threadIdx.x == 0) {
+            const int b = by * gridDim.x + bx;
+#pragma unroll
+            for (int q = 0; q < 3 * R; ++q) a.norm_part[(3 * z + q) * a.nblk + b] = acc[q];
+        }
+    }
+
+    // down part: pre-smoothing (the first half sweep uses the exchange above)
+#pragma unroll
+    for (int q = 0; q < 2 * NU1; ++q) {
+        if (q > 0) {
+            xc.put(buf, u, w, lane);
+            __syncthreads();
+            xc.get(buf, up, dn, w, lane);
+            buf ^= 1;
+        }
+        reg_half_sweep<E, R, HELM, K>(u, f, iD, upd, up, dn, h2, om, q & 1);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int gy = gy0 + k;
+        if (own[k] && own_x && gx <= N - 1 && gy <= N - 1)
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                *reinterpret_cast<V2*>(a.u_out[r + z] + (size_t)gy * a.pitch + gx) =
+                    V2{u[r][k][0], u[r][k][1]};
+    }
+    xc.put(buf, u, w, lane);
+    __syncthreads();
+    xc.get(buf, up, dn, w, lane);
+    buf ^= 1;
+    E rr[R][K][2];
+    reg_residual<E, R, K>(rr, u, f, D, dom, up, dn, ih2);
+    xc.put(buf, rr, w, lane);
+    __syncthreads();
+    xc.get(buf, up, dn, w, lane);
+    const int Ic = ex0 / 2 + lane;
+#pragma unroll
+    for (int k = 0; k < K; k += 2) {
+        const int J = (gy0 + k) / 2;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const E am = k == 0 ? up[r].y : rr[r][k - 1][1];  // row k-1, odd column
+            const E a0 = k == 0 ? up[r].x : rr[r][k - 1][0];
+            const E sl = lane_shift<kFromLeft>(rr[r][k][1]);
+            const E sm = lane_shift<kFromLeft>(am);
+            const E sp = lane_shift<kFromLeft>(rr[r][k + 1][1]);
+            if (own[k] && own_x && Ic <= Nc - 1 && J <= Nc - 1) {
+                E v = E(0);
+                if (Ic >= 1 && J >= 1)
+                    v = (E(4) * rr[r][k][0] +
+                         E(2) * (sl + rr[r][k][1] + a0 + rr[r][k + 1][0]) +
+                         (sm + am + sp + rr[r][k + 1][1])) *
+                        E(1.0 / 16.0);
+                a.f_c[r + z][(size_t)J * a.pitch_c + Ic] = v;
+            }
+        }
+    }
+}
+
 
 // ---------------------------------------------------------------- coarse --
 
@@ -1547,10 +1732,13 @@ __global__ void k_correct(int N, int pitch, int pitch32, double* __restrict__ u0
 // Slot up_slot holds nblk_up partials (written by an up pass), the others nblk.
 __global__ __launch_bounds__(kThreads) void k_reduce_slots(const double* part, int stride,
                                                            int nblk, int s0, int nvec,
-                                                           double* out, int up_slot, int nblk_up) {
+                                                           double* out, int up_slot, int nblk_up,
+                                                           int fuse_lo, int fuse_hi,
+                                                           int nblk_fuse) {
     __shared__ double red[kThreads / 64];
     const int s = s0 + blockIdx.x / nvec, k = blockIdx.x % nvec;
     if (s == up_slot) nblk = nblk_up;
+    if (s >= fuse_lo && s < fuse_hi) nblk = nblk_fuse;  // written by fused up-and-down passes
     const double* p = part + (size_t)s * stride + (size_t)k * nblk;
     double acc[1] = {0.0};
     for (int b = threadIdx.x; b < nblk; b += kThreads) acc[0] += p[b];
@@ -1727,6 +1915,44 @@ const char* type_name(double) { return "double"; }
 const char* type_name(float) { return "float"; }
 
 // Arrays of one solve: level 0 (u, f, k2) and the per-level buffers of type E.
+// Geometry of the fused level-0 up-and-down launch (halo 2 nu_post + 2 nu_pre
+// + 2), and whether a solve can use it: FP64 register tiles with one
+// right-hand side per workgroup, equal pre- and post-sweep counts of 1 or 2.
+bool fuse_possible(const wandqs_ctx* c) {
+    const int nu = c->cfg.nu_pre;
+    return c->mg_fuse && c->lc > 0 && c->N >= c->reg_tile_min && c->reg_split &&
+           nu == c->cfg.nu_post && nu >= 1 && nu <= 2 && c->lev[0].um2[0] != nullptr;
+}
+#ifndef WQ_FUSE_ROWS
+#define WQ_FUSE_ROWS 8
+#endif
+constexpr int kFuseRows = WQ_FUSE_ROWS;  // rows per wavefront of the fused tiles
+dim3 fuse_grid(const wandqs_ctx* c, int R) {
+    const int hl = 4 * c->cfg.nu_pre + 2;
+    const int TX = 128 - 2 * hl, TY = kFuseRows * kRegWaves - 2 * hl, N = c->N;
+    return dim3((N + TX - 1) / TX, (N + TY - 1) / TY, R);
+}
+void launch_updown_reg(const FuseArgs<double>& a, bool helm, int nu, dim3 grid, hipStream_t s,
+                       const ProfScope& ps) {
+    constexpr int NW = kRegWaves;
+    const dim3 blk(64 * NW);
+    if (helm) {
+        if (nu == 1) WQ_KLAUNCH(ps, (k_mg_updown_reg<double, 1, true, 1, 1, NW, kFuseRows>), grid, blk, 0, s, a);
+        else WQ_KLAUNCH(ps, (k_mg_updown_reg<double, 1, true, 2, 2, NW, kFuseRows>), grid, blk, 0, s, a);
+    } else {
+        if (nu == 1) WQ_KLAUNCH(ps, (k_mg_updown_reg<double, 1, false, 1, 1, NW, kFuseRows>), grid, blk, 0, s, a);
+        else WQ_KLAUNCH(ps, (k_mg_updown_reg<double, 1, false, 2, 2, NW, kFuseRows>), grid, blk, 0, s, a);
+    }
+}
+
+// Level-0 fusion state of one cycle inside a batch (FP64 only).
+struct FuseCtl {
+    bool skip_down0 = false;  // the level-0 down pass ran fused into the previous cycle
+    bool fuse_up0 = false;    // the level-0 up pass fuses with the next cycle's down pass
+    int next_slot = -1;       // norm slot of the next cycle's incoming iterate
+    int cur = 0;              // level-0 pre-smoothed iterate in um (0) or um2 (1)
+};
+
 template <typename E>
 struct Hier {
     E* u0[2];
@@ -1750,7 +1976,7 @@ int nu_pre_at(const wandqs_ctx* c, int l) { return l >= kFullPreLevels ? 1 : c->
 // norm_slot >= 0 (double only) records the residual of the incoming iterate.
 template <typename E>
 void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess, int norm_slot,
-            int up_norm_slot = -1, double* const* corr = nullptr) {
+            int up_norm_slot = -1, double* const* corr = nullptr, const FuseCtl* fz = nullptr) {
     hipStream_t s = c->stream;
     const int lc = c->lc;
     const double eb = sizeof(E);
@@ -1766,7 +1992,13 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
     const double om = helm ? c->cfg.mg_omega_helm : c->cfg.mg_omega;
     const double h2max = helm ? kOmegaH2N0 / c->cfg.n0 : std::numeric_limits<double>::infinity();
     auto omega_of = [&](double h) { return h * h > h2max ? 1.0 : om; };
+    // the level-0 pre-smoothed iterate (the fused passes alternate two buffers)
+    auto um0 = [&](int r) -> E* {
+        if (fz && fz->cur) return reinterpret_cast<E*>(c->lev[0].um2[r]);
+        return lev_um<E>(c->lev[0], r);
+    };
     for (int l = 0; l < lb; ++l) {
+        if (l == 0 && fz && fz->skip_down0) continue;
         wq::Level& L = c->lev[l];
         DownArgs<E> a{};
         a.omega = omega_of(L.h);
@@ -1777,7 +2009,7 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
         for (int r = 0; r < R; ++r) {
             a.u_in[r] = (l == 0 && !zero_guess) ? hz.u0[r] : nullptr;
             a.f[r] = F(l, r);
-            a.u_out[r] = lev_um<E>(L, r);
+            a.u_out[r] = l == 0 ? um0(r) : lev_um<E>(L, r);
             a.f_c[r] = F(l + 1, r);
         }
         a.k2 = helm ? K(l) : nullptr;
@@ -1871,6 +2103,38 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
     }
     for (int l = lb - 1; l >= 0; --l) {
         wq::Level& L = c->lev[l];
+        if constexpr (std::is_same<E, double>::value) {
+            if (l == 0 && fz && fz->fuse_up0) {
+                // up pass fused with the next cycle's down pass: into the other
+                // buffer, recording the norms of the next cycle's incoming iterate
+                FuseArgs<double> a{};
+                a.N = L.N;
+                a.h = L.h;
+                a.pitch = L.pitch;
+                a.pitch_c = c->lev[1].pitch;
+                a.omega = omega_of(L.h);
+                for (int r = 0; r < R; ++r) {
+                    a.u_mid[r] = um0(r);
+                    a.e_c[r] = U(1, r);
+                    a.f[r] = F(0, r);
+                    a.u_out[r] = fz->cur ? L.um[r] : L.um2[r];
+                    a.f_c[r] = F(1, r);
+                }
+                a.k2 = helm ? K(0) : nullptr;
+                const dim3 g = fuse_grid(c, R);
+                a.nblk = g.x * g.y;
+                a.norm_part = c->norm_part + (size_t)fz->next_slot * kNormVec * c->max_tiles;
+                const double nodes = (double)L.N * L.N;
+                char nm[64];
+                prof_name(c, nm, sizeof nm, "k_mg_updown_reg<double, 1, %s, %d, %d, %d>@%d",
+                          helm ? "true" : "false", c->cfg.nu_pre, c->cfg.nu_post, kRegWaves, L.N);
+                // per owned node and right-hand side: smoothed u, 1/4 coarse e,
+                // f, new smoothed u, 1/4 coarse f; k2 once
+                ProfScope ps(c, nm, nodes * (R * (8.0 + 2.0 + 8.0 + 8.0 + 2.0) + (helm ? 8.0 : 0.0)));
+                launch_updown_reg(a, helm, c->cfg.nu_pre, g, s, ps);
+                continue;
+            }
+        }
         UpArgs<E> a{};
         a.omega = omega_of(L.h);
         a.N = L.N;
@@ -1878,7 +2142,7 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
         a.pitch = L.pitch;
         a.pitch_c = c->lev[l + 1].pitch;
         for (int r = 0; r < R; ++r) {
-            a.u_mid[r] = lev_um<E>(L, r);
+            a.u_mid[r] = l == 0 ? um0(r) : lev_um<E>(L, r);
             a.e_c[r] = U(l + 1, r);
             a.f[r] = F(l, r);
             a.u_out[r] = U(l, r);
@@ -2067,12 +2331,13 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
     hipError_t gerr = hipSuccess;
     // upslot >= 0 (FP64, register tiles on level 0): the cycle's finest up pass
     // records the norms of its result in slot upslot
-    auto cycle = [&](int slot, int upslot) {
+    auto cycle = [&](int slot, int upslot, const FuseCtl& fz) {
+        const int fk = (fz.skip_down0 ? 1 : 0) | (fz.fuse_up0 ? 2 : 0) | (fz.cur ? 4 : 0);
         const CycleKey key{{hz.u0[0], hz.u0[1], hz.f0[0], hz.f0[1], hz.k2}, R, helm, mixed, slot,
-                           upslot};
+                           upslot, fk};
         const hipError_t e = run_cycle(c, key, [&] {
             if (mixed) mixed_iteration(c, R, helm, hz, slot);
-            else vcycle<double>(c, R, helm, hz, false, slot, upslot);
+            else vcycle<double>(c, R, helm, hz, false, slot, upslot, nullptr, &fz);
         });
         if (gerr == hipSuccess) gerr = e;
     };
@@ -2086,7 +2351,7 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
     const bool separate_norm = !mixed && c->lc == 0;
     const int maxc = c->cfg.mg_max_cycles;
     if (!(c->cfg.mg_rtol > 0.0)) {
-        for (int k = 0; k < maxc; ++k) cycle(mixed ? 0 : -1, -1);
+        for (int k = 0; k < maxc; ++k) cycle(mixed ? 0 : -1, -1, FuseCtl{});
         if (graph_check() != WANDQS_OK) return WANDQS_E_HIP;
         WQ_LAUNCH_CHECK();
         if (res) *res = SolveResult{maxc, {-1.0, -1.0}};
@@ -2103,6 +2368,12 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
     const PassGeom gu = pass_geom(c, N, c->cfg.nu_post, false, true);
     const bool up_norms = !mixed && !separate_norm && gu.reg;
     const int nblk_up = gu.grid.x * gu.grid.y;
+    // inside a batch, each cycle's level-0 up pass but the last fuses with the
+    // next cycle's down pass; their norm slots have the fused launch's tiles
+    const bool fuse = !mixed && up_norms && fuse_possible(c);
+    const dim3 fg = fuse_grid(c, R);
+    const int nblk_fuse = fg.x * fg.y;
+    int cur = 0;
     int done = 0;
     int pred = c->pred[kind] < 1 ? 1 : c->pred[kind];
     double* hr = c->h_pin;  // [kMaxSlots][kNormVec] + flags
@@ -2115,7 +2386,13 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
         if (done + b > maxc) b = maxc - done;
         for (int k = 0; k < b; ++k) {
             const int cyc = done + k;
-            cycle(mixed || c->lc > 0 ? cyc : -1, up_norms && k == b - 1 ? cyc + 1 : -1);
+            FuseCtl fz;
+            fz.skip_down0 = fuse && k > 0;
+            fz.fuse_up0 = fuse && k < b - 1;
+            fz.next_slot = cyc + 1;
+            fz.cur = cur;
+            cycle(mixed || c->lc > 0 ? cyc : -1, up_norms && k == b - 1 ? cyc + 1 : -1, fz);
+            if (fz.fuse_up0) cur ^= 1;
             if (separate_norm) resnorm(c, R, helm, hz, cyc + 1, nullptr);
         }
         if (!separate_norm && !up_norms) resnorm(c, R, helm, hz, done + b, nullptr);
@@ -2125,7 +2402,8 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
             ProfScope ps(c, "k_reduce_slots", 8.0 * ns * 3 * R * (nblk + 1));
             WQ_KLAUNCH(ps, k_reduce_slots, dim3(ns * 3 * R), dim3(kThreads), 0, s,
                                c->norm_part, V * c->max_tiles, nblk, s0, 3 * R, c->norm_red,
-                               up_norms ? done + b : -1, nblk_up);
+                               up_norms ? done + b : -1, nblk_up, fuse ? done + 1 : 0,
+                               fuse ? done + b : 0, nblk_fuse);
         }
         if (graph_check() != WANDQS_OK) return WANDQS_E_HIP;
         WQ_LAUNCH_CHECK();

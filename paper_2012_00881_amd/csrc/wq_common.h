@@ -53,6 +53,9 @@ struct Level {
     int pitch = 0;
     double* u[2] = {nullptr, nullptr};   // solution (level 0) or coarse correction
     double* um[2] = {nullptr, nullptr};  // pre-smoothed iterate written by the down pass
+    // level 0 on register tiles: the second buffer of the pre-smoothed iterate,
+    // which the fused up-and-down passes write alternately with um
+    double* um2[2] = {nullptr, nullptr};
     double* f[2] = {nullptr, nullptr};   // right-hand side
     double* k2 = nullptr;                // Helmholtz coefficient (restricted)
     // float buffers of the mixed form's inner cycles (level 0: error e, its
@@ -152,11 +155,13 @@ struct SolveResult {
 struct CycleKey {
     const void* p[5];
     int R, helm, mixed, slot, upslot;
+    int fuse;  // 1: the level-0 down pass was fused into the last cycle; 2: the
+               // level-0 up pass fuses with the next down pass; 4: um2 is current
     bool operator==(const CycleKey& o) const {
         for (int i = 0; i < 5; ++i)
             if (p[i] != o.p[i]) return false;
         return R == o.R && helm == o.helm && mixed == o.mixed && slot == o.slot &&
-               upslot == o.upslot;
+               upslot == o.upslot && fuse == o.fuse;
     }
 };
 struct CycleGraph {
@@ -199,6 +204,10 @@ struct wandqs_ctx {
     // every workgroup; reg, split on the register-tile levels only; lds, on the
     // LDS-tile levels only; the same bits in every case)
     bool reg_split = true, lds_split = true;
+    // inside a batch of V-cycles the level-0 up pass of one cycle and the down
+    // pass of the next run as one fused launch (environment WANDQS_MG_FUSE=0 at
+    // init: never; the same bits either way)
+    bool mg_fuse = true;
     // LDS tiles of 16 x 16 owned nodes on the levels N <= small_tile_max
     // (environment WANDQS_MG_SMALL at init), 32 x 32 or 64 x 64 above
     int small_tile_max = 0;

@@ -418,6 +418,48 @@ def test_register_tiles_bitwise_equal_lds_tiles(torch_cuda, monkeypatch, precisi
             assert np.array_equal(a, b), float(np.abs(a - b).max())
 
 
+def test_fused_passes_bitwise_equal_separate(torch_cuda, monkeypatch):
+    """Inside a batch of V-cycles the finest level's up pass and the next
+    cycle's down pass run as one fused launch; with WANDQS_MG_FUSE=0 they run
+    separately.  Solves to the tolerance (batches of several cycles) on 1024^2
+    and 2048^2, Poisson and Helmholtz, and six C5 slices give the same bits,
+    cycle counts and residuals."""
+    outs = []
+    for fuse in (None, "0"):
+        monkeypatch.delenv("WANDQS_MG_FUSE", raising=False)
+        if fuse is not None:
+            monkeypatch.setenv("WANDQS_MG_FUSE", fuse)
+        res = []
+        for N in (1024, 2048):
+            for helm in (False, True):
+                cfg = wi.scaled(wi.config("C1"), n_cells=N, half_width=6.0)
+                sim = _sim(cfg)
+                f = _rand_rhs(N, N + 3, 2)
+                k2 = np.random.default_rng(9).uniform(0.0, 30.0, (N + 1, N + 1)) if helm else None
+                # the second solve's first batch is the first's cycle count
+                for rep in range(2):
+                    u0 = 0.1 * _rand_rhs(N, N + 4 + rep, 2)
+                    st, u, cyc, rr = sim.mg_solve(f, u0=u0, k2=k2)
+                    assert st == 0
+                    print(f"fuse={fuse} N={N} helm={helm}: cycles {cyc}")
+                    res += [u.cpu().numpy().copy(), np.array([cyc]), np.array(rr)]
+                sim.close()
+        cfg = wi.config("C5")
+        state = wi.synthetic_state(cfg, seed=17, p_max=0.5, xi=2.0, field_amp=0.01)
+        sim = _sim(cfg, n_slices=6)
+        sim.set_state(particles=_particles(state), fields=state["fields"], xi=state["xi"],
+                      dxi=state["dxi"])
+        infos, _ = sim.run(6, infos=True)
+        got = sim.get_state()
+        res += [got["fields"].cpu().numpy().copy(), got["particles"].cpu().numpy().copy(),
+                np.array([i["vcycles"] for i in infos])]
+        print(f"fuse={fuse} C5 cycles", [i["vcycles"] for i in infos])
+        sim.close()
+        outs.append(res)
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b), float(np.abs(a - b).max())
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_graph_replay_bitwise_equal_direct_launches(torch_cuda, monkeypatch, precision):
     """Multigrid cycles replayed as HIP graphs (WANDQS_GRAPHS=1) against
