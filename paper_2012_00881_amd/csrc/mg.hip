@@ -2126,8 +2126,9 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
                 a.norm_part = c->norm_part + (size_t)fz->next_slot * kNormVec * c->max_tiles;
                 const double nodes = (double)L.N * L.N;
                 char nm[64];
-                prof_name(c, nm, sizeof nm, "k_mg_updown_reg<double, 1, %s, %d, %d, %d>@%d",
-                          helm ? "true" : "false", c->cfg.nu_pre, c->cfg.nu_post, kRegWaves, L.N);
+                prof_name(c, nm, sizeof nm, "k_mg_updown_reg<double, 1, %s, %d, %d, %d, %d>@%d",
+                          helm ? "true" : "false", c->cfg.nu_pre, c->cfg.nu_post, kRegWaves,
+                          kFuseRows, L.N);
                 // per owned node and right-hand side: smoothed u, 1/4 coarse e,
                 // f, new smoothed u, 1/4 coarse f; k2 once
                 ProfScope ps(c, nm, nodes * (R * (8.0 + 2.0 + 8.0 + 8.0 + 2.0) + (helm ? 8.0 : 0.0)));
