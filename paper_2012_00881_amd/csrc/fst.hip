@@ -46,11 +46,48 @@ struct FstArgs {
     double scale;       // (2 / n)^2
 };
 
-// In-register DFT of length R (2 or 4), natural order in and out.
+// cos and sin of 2 pi m / 16 (m < 8)
+__device__ __forceinline__ constexpr double cos16(int m) {
+    return m == 0   ? 1.0
+           : m == 1 ? 0.9238795325112867561281831893967883
+           : m == 2 ? 0.7071067811865475244008443621048490
+           : m == 3 ? 0.3826834323650897717284599840303988
+           : m == 4 ? 0.0
+           : m == 5 ? -0.3826834323650897717284599840303988
+           : m == 6 ? -0.7071067811865475244008443621048490
+                    : -0.9238795325112867561281831893967883;
+}
+__device__ __forceinline__ constexpr double sin16(int m) { return m <= 4 ? cos16(4 - m) : cos16(m - 4); }
+
+// In-register DFT of length R (2, 4, 8 or 16), natural order in and out:
+// radix 2 and 4 written out, 8 and 16 by one radix-2 decimation-in-time step
+// over two half-length DFTs.
 template <int R>
 __device__ __forceinline__ void dft(double (&re)[R], double (&im)[R]) {
-    static_assert(R == 2 || R == 4, "radix");
-    if constexpr (R == 2) {
+    static_assert(R == 2 || R == 4 || R == 8 || R == 16, "radix");
+    if constexpr (R >= 8) {
+        constexpr int H = R / 2;
+        double er[H], ei[H], orr[H], oi[H];
+#pragma unroll
+        for (int q = 0; q < H; ++q) {
+            er[q] = re[2 * q];
+            ei[q] = im[2 * q];
+            orr[q] = re[2 * q + 1];
+            oi[q] = im[2 * q + 1];
+        }
+        dft<H>(er, ei);
+        dft<H>(orr, oi);
+#pragma unroll
+        for (int q = 0; q < H; ++q) {
+            // W_R^q = cos(2 pi q / R) - i sin(2 pi q / R)
+            const double wr = cos16(q * (16 / R)), wi = -sin16(q * (16 / R));
+            const double tr = wr * orr[q] - wi * oi[q], ti = wr * oi[q] + wi * orr[q];
+            re[q] = er[q] + tr;
+            im[q] = ei[q] + ti;
+            re[q + H] = er[q] - tr;
+            im[q + H] = ei[q] - ti;
+        }
+    } else if constexpr (R == 2) {
         const double ar = re[0], ai = im[0];
         re[0] = ar + re[1];
         im[0] = ai + im[1];
@@ -73,11 +110,22 @@ __device__ __forceinline__ void dft(double (&re)[R], double (&im)[R]) {
     }
 }
 
-// Radix of the stage whose input span is NS: 4, and 2 for the last stage of
-// an odd power of two.
+// Radix of the full stages: WQ_FST_RADIX, at most L / 64 (so that one
+// butterfly per thread takes a whole wavefront at least).  Radix 16 (one
+// wavefront per FFT of 1024, three stages) measured slower than radix 4 (256
+// threads, five stages): 12.5 / 7.8 / 7.1 against 9.5 / 6.5 / 5.2 us for the
+// y / x inverse / x passes at 512^2.
+#ifndef WQ_FST_RADIX
+#define WQ_FST_RADIX 4
+#endif
+template <int L>
+constexpr int fst_radix() { return L / 64 < WQ_FST_RADIX ? L / 64 : WQ_FST_RADIX; }
+
+// Radix of the stage whose input span is NS: the full radix, and what is left
+// for the last stage.
 template <int L, int NS>
 constexpr int stage_radix() {
-    return L / NS >= 4 ? 4 : 2;
+    return L / NS >= fst_radix<L>() ? fst_radix<L>() : L / NS;
 }
 
 // LDS slot of element i of a padded buffer
@@ -86,10 +134,10 @@ __device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
 template <int L>
 constexpr int padded_len() { return L + L / 16; }
 
-// Threads of the workgroup that computes one FFT of length L: one radix-4
-// butterfly each per stage, at most 256.
+// Threads of the workgroup that computes one FFT of length L: one butterfly
+// of a full stage each, at most 256.
 template <int L>
-constexpr int fst_threads() { return L / 4 < 256 ? L / 4 : 256; }
+constexpr int fst_threads() { return L / fst_radix<L>() < 256 ? L / fst_radix<L>() : 256; }
 
 // Twiddle W_L^m (m < L) from the table of W_L^m, m < L / 2 (TW2) or of all m.
 template <int L, bool TW2>
