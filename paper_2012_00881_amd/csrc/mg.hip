@@ -1927,14 +1927,18 @@ bool fuse_possible(const wandqs_ctx* c) {
 #define WQ_FUSE_ROWS 8
 #endif
 constexpr int kFuseRows = WQ_FUSE_ROWS;  // rows per wavefront of the fused tiles
+#ifndef WQ_FUSE_WAVES
+#define WQ_FUSE_WAVES 8
+#endif
+constexpr int kFuseWaves = WQ_FUSE_WAVES;  // wavefronts of a fused tile
 dim3 fuse_grid(const wandqs_ctx* c, int R) {
     const int hl = 4 * c->cfg.nu_pre + 2;
-    const int TX = 128 - 2 * hl, TY = kFuseRows * kRegWaves - 2 * hl, N = c->N;
+    const int TX = 128 - 2 * hl, TY = kFuseRows * kFuseWaves - 2 * hl, N = c->N;
     return dim3((N + TX - 1) / TX, (N + TY - 1) / TY, R);
 }
 void launch_updown_reg(const FuseArgs<double>& a, bool helm, int nu, dim3 grid, hipStream_t s,
                        const ProfScope& ps) {
-    constexpr int NW = kRegWaves;
+    constexpr int NW = kFuseWaves;
     const dim3 blk(64 * NW);
     if (helm) {
         if (nu == 1) WQ_KLAUNCH(ps, (k_mg_updown_reg<double, 1, true, 1, 1, NW, kFuseRows>), grid, blk, 0, s, a);
@@ -2127,7 +2131,7 @@ void vcycle(wandqs_ctx* c, int R, bool helm, const Hier<E>& hz, bool zero_guess,
                 const double nodes = (double)L.N * L.N;
                 char nm[64];
                 prof_name(c, nm, sizeof nm, "k_mg_updown_reg<double, 1, %s, %d, %d, %d, %d>@%d",
-                          helm ? "true" : "false", c->cfg.nu_pre, c->cfg.nu_post, kRegWaves,
+                          helm ? "true" : "false", c->cfg.nu_pre, c->cfg.nu_post, kFuseWaves,
                           kFuseRows, L.N);
                 // per owned node and right-hand side: smoothed u, 1/4 coarse e,
                 // f, new smoothed u, 1/4 coarse f; k2 once
