@@ -69,7 +69,7 @@ def measured_traffic(kernel: str):
 
 
 # the multigrid (V-cycle) kernels: passes, coarse solves, norms, transfers
-VCYCLE_PREFIXES = ("k_mg_", "k_coarse", "k_dst", "k_fst", "k_resnorm", "k_reduce_slots", "k_restrict_fw",
+VCYCLE_PREFIXES = ("k_mg_", "k_coarse", "k_dst", "k_fst", "k_resnorm", "k_reduce_publish", "k_restrict_fw",
                    "k_correct")
 
 

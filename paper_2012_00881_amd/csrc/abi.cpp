@@ -457,7 +457,7 @@ size_t wq::carve(wandqs_ctx* c, char* base) {
     c->vmax_part = (double*)take(sizeof(double) * c->n_push_blocks);
     c->flags = (int32_t*)take(sizeof(int32_t) * 4);
     c->norm_part = (double*)take(sizeof(double) * kMaxSlots * kNormVec * (size_t)c->max_tiles);
-    c->norm_red = (double*)take(sizeof(double) * kMaxSlots * kNormVec);
+    c->pub_count = (uint32_t*)take(sizeof(uint32_t));
     c->rec = (double*)take(sizeof(double) * 4 * (size_t)c->rec_cap);
     c->probe_acc = (double*)take(sizeof(double) * kMaxProbes);
     c->bins_dev = (double*)take(sizeof(double) * (size_t)(c->n_bins_total + 1));
@@ -556,7 +556,7 @@ size_t wq::carve_solver(wandqs_ctx* c, char* base) {
             }
     }
     c->norm_part = (double*)take(sizeof(double) * kNormVec * (size_t)c->max_tiles);
-    c->norm_red = (double*)take(sizeof(double) * kNormVec);
+    c->pub_count = (uint32_t*)take(sizeof(uint32_t));
     return (off + 255) & ~(size_t)255;
 }
 

@@ -1728,13 +1728,17 @@ __global__ void k_correct(int N, int pitch, int pitch32, double* __restrict__ u0
     if (u1) u1[(size_t)b * pitch + a] += (double)e1[(size_t)b * pitch32 + a];
 }
 
-// out[s*kNormVec + k] = sum_b part[s][k][b]: one block per (slot, k), fixed order.
-// Slot up_slot holds nblk_up partials (written by an up pass), the others nblk.
-__global__ __launch_bounds__(kThreads) void k_reduce_slots(const double* part, int stride,
-                                                           int nblk, int s0, int nvec,
-                                                           double* out, int up_slot, int nblk_up,
-                                                           int fuse_lo, int fuse_hi,
-                                                           int nblk_fuse) {
+// The norms of a batch of V-cycles to the host: one workgroup per slot and
+// sum adds the slot's per-tile partials (in a fixed order) and writes the sum
+// into the host's coherent pinned array dst; the last workgroup to finish
+// (device-scope counter, which it resets) then copies the flags word and
+// publishes the sequence number with a system-scope release, after which the
+// host reads the sums.  Slot up_slot has nblk_up tiles, the slots in
+// [fuse_lo, fuse_hi) nblk_fuse (fused passes), the others nblk.
+__global__ __launch_bounds__(kThreads) void k_reduce_publish(
+    const double* part, int stride, int nblk, int s0, int nvec, int up_slot, int nblk_up,
+    int fuse_lo, int fuse_hi, int nblk_fuse, double* dst, const int32_t* __restrict__ flags,
+    int32_t* dst_flags, uint32_t* dst_seq, uint32_t seq, uint32_t* count) {
     __shared__ double red[kThreads / 64];
     const int s = s0 + blockIdx.x / nvec, k = blockIdx.x % nvec;
     if (s == up_slot) nblk = nblk_up;
@@ -1743,22 +1747,15 @@ __global__ __launch_bounds__(kThreads) void k_reduce_slots(const double* part, i
     double acc[1] = {0.0};
     for (int b = threadIdx.x; b < nblk; b += kThreads) acc[0] += p[b];
     block_sum<1, kThreads>(acc, red);
-    if (threadIdx.x == 0) out[s * kNormVec + k] = acc[0];
-}
-
-// Publishes n reduced norms and the flags word into the host's coherent pinned
-// buffer, then, after a system-scope release, the sequence number seq: the
-// host waits for seq instead of synchronising the stream.
-__global__ __launch_bounds__(64) void k_publish(const double* __restrict__ src, int n,
-                                                const int32_t* __restrict__ flags,
-                                                double* dst, int32_t* dst_flags, uint32_t* dst_seq,
-                                                uint32_t seq) {
-    for (int i = threadIdx.x; i < n; i += 64) dst[i] = src[i];
-    if (threadIdx.x == 0) *dst_flags = *flags;
-    __syncthreads();
     if (threadIdx.x == 0) {
+        dst[s * kNormVec + k] = acc[0];
         __threadfence_system();
-        __hip_atomic_store(dst_seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (atomicAdd(count, 1u) == gridDim.x - 1) {
+            *count = 0;
+            *dst_flags = *flags;
+            __threadfence_system();
+            __hip_atomic_store(dst_seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
     }
 }
 
@@ -2281,7 +2278,7 @@ hipError_t run_cycle(wandqs_ctx* c, const CycleKey& key, F&& body) {
     return hipSuccess;
 }
 
-// Waits until the device has published sequence number seq (k_publish): a
+// Waits until the device has published sequence number seq (k_reduce_publish): a
 // bounded spin on the coherent host word, then a stream synchronisation,
 // which also reports a failed kernel.
 wandqs_status wait_published(wandqs_ctx* c, const uint32_t* h_seq, uint32_t seq) {
@@ -2403,22 +2400,17 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
         if (!separate_norm && !up_norms) resnorm(c, R, helm, hz, done + b, nullptr);
         const int s0 = done == 0 ? 0 : done + 1;
         const int ns = done + b + 1 - s0;
-        {
-            ProfScope ps(c, "k_reduce_slots", 8.0 * ns * 3 * R * (nblk + 1));
-            WQ_KLAUNCH(ps, k_reduce_slots, dim3(ns * 3 * R), dim3(kThreads), 0, s,
-                               c->norm_part, V * c->max_tiles, nblk, s0, 3 * R, c->norm_red,
-                               up_norms ? done + b : -1, nblk_up, fuse ? done + 1 : 0,
-                               fuse ? done + b : 0, nblk_fuse);
-        }
         if (graph_check() != WANDQS_OK) return WANDQS_E_HIP;
         WQ_LAUNCH_CHECK();
         int32_t* h_flags = reinterpret_cast<int32_t*>(hr + V * kMaxSlots);
         uint32_t* h_seq = reinterpret_cast<uint32_t*>(hr + V * kMaxSlots + 1);
         const uint32_t seq = ++c->pub_seq;
         {
-            ProfScope ps(c, "k_publish", 8.0 * V * ns);
-            WQ_KLAUNCH(ps, k_publish, dim3(1), dim3(64), 0, s, c->norm_red + V * s0, V * ns,
-                               c->flags, hr + V * s0, h_flags, h_seq, seq);
+            ProfScope ps(c, "k_reduce_publish", 8.0 * ns * 3 * R * (nblk + 1));
+            WQ_KLAUNCH(ps, k_reduce_publish, dim3(ns * 3 * R), dim3(kThreads), 0, s,
+                       c->norm_part, V * c->max_tiles, nblk, s0, 3 * R, up_norms ? done + b : -1,
+                       nblk_up, fuse ? done + 1 : 0, fuse ? done + b : 0, nblk_fuse, hr, c->flags,
+                       h_flags, h_seq, seq, c->pub_count);
         }
         WQ_LAUNCH_CHECK();
         if (wait_published(c, h_seq, seq) != WANDQS_OK) return WANDQS_E_HIP;

@@ -309,7 +309,7 @@ struct wandqs_ctx {
     int n_push_blocks = 0;
     int32_t* flags = nullptr;
     double* norm_part = nullptr;  // [kMaxSlots][kNormVec][max_tiles]
-    double* norm_red = nullptr;   // [kMaxSlots][kNormVec]
+    uint32_t* pub_count = nullptr;  // workgroups of k_reduce_publish done (0 between batches)
     int max_tiles = 0;
     double* rec = nullptr;        // [rec_cap][4] : xi, dxi, vmax, flags
     double* probe_acc = nullptr;  // [kMaxProbes]
