@@ -113,6 +113,32 @@ __device__ __forceinline__ double2 resid_at(const double2* u, const double2* f, 
 constexpr int kLTX = 32, kLTY = 16, kLH = 8;
 constexpr int kLRX = kLTX + 2 * kLH, kLRY = kLTY + 2 * kLH;
 constexpr int kLTThreads = 512;
+constexpr int kLIt = (kLRX * kLRY + kLTThreads - 1) / kLTThreads;  // tile nodes per thread
+
+// Node q of this thread in a tile of RW x RH nodes at (ax0, by0): its LDS
+// slot, its grid node and its index clamped into the grid (threads past the
+// tile redo its last node).  The tile loads read every node unconditionally
+// and mask the values (every value loaded is finite): a load the compiler
+// moves behind a lane-dependent branch is waited for before the branch ends,
+// which would serialize the tile's loads.
+struct LasTileNode {
+    int lx, ly, a, b;
+    size_t g;
+    bool in, inner;  // inside [0, n]^2; interior
+};
+__device__ __forceinline__ LasTileNode las_node(int q, int RW, int RH, int ax0, int by0, int n,
+                                                int pitch) {
+    LasTileNode nd;
+    const int t = min((int)threadIdx.x + q * kLTThreads, RW * RH - 1);
+    nd.lx = t % RW;
+    nd.ly = t / RW;
+    nd.a = ax0 + nd.lx;
+    nd.b = by0 + nd.ly;
+    nd.in = nd.a >= 0 && nd.b >= 0 && nd.a <= n && nd.b <= n;
+    nd.inner = nd.a > 0 && nd.b > 0 && nd.a < n && nd.b < n;
+    nd.g = (size_t)min(max(nd.b, 0), n) * pitch + min(max(nd.a, 0), n);
+    return nd;
+}
 
 // Red-black Gauss-Seidel sweeps on the tile's region in LDS: a node with its
 // four neighbours in the region and inside the domain takes (sum of the
@@ -152,18 +178,23 @@ __global__ __launch_bounds__(kLTThreads) void k_las_down(int n, double h, int pi
     const int x0 = blockIdx.x * kLTX, y0 = blockIdx.y * kLTY;
     const int ax0 = x0 - H, by0 = y0 - H, RW = kLTX + 2 * H, RH = kLTY + 2 * H;
     const double2 z = make_double2(0.0, 0.0);
-    for (int t = threadIdx.x; t < RW * RH; t += kLTThreads) {
-        const int lx = t % RW, ly = t / RW, a = ax0 + lx, b = by0 + ly;
-        double2 uu = z, ff = z, kk = z;
-        if (a >= 0 && b >= 0 && a <= n && b <= n) {
-            const size_t g = (size_t)b * pitch + a;
-            ff = f[g];
-            kk = k[g];
-            if (a > 0 && b > 0 && a < n && b < n) uu = u_in[g];
+    {
+        double2 uu[kLIt], ff[kLIt], kk[kLIt];
+#pragma unroll
+        for (int q = 0; q < kLIt; ++q) {
+            const LasTileNode nd = las_node(q, RW, RH, ax0, by0, n, pitch);
+            const double2 uv = u_in[nd.g], fv = f[nd.g], kv = k[nd.g];
+            uu[q] = cscl(nd.inner ? 1.0 : 0.0, uv);
+            ff[q] = cscl(nd.in ? 1.0 : 0.0, fv);
+            kk[q] = cscl(nd.in ? 1.0 : 0.0, kv);
         }
-        U[ly][lx] = uu;
-        F[ly][lx] = ff;
-        K[ly][lx] = kk;
+#pragma unroll
+        for (int q = 0; q < kLIt; ++q) {
+            const LasTileNode nd = las_node(q, RW, RH, ax0, by0, n, pitch);
+            U[nd.ly][nd.lx] = uu[q];
+            F[nd.ly][nd.lx] = ff[q];
+            K[nd.ly][nd.lx] = kk[q];
+        }
     }
     __syncthreads();
     const double h2 = h * h;
@@ -210,28 +241,36 @@ __global__ __launch_bounds__(kLTThreads) void k_las_up(int n, double h, int pitc
     const int H = 2 * nu;
     const int x0 = blockIdx.x * kLTX, y0 = blockIdx.y * kLTY;
     const int ax0 = x0 - H, by0 = y0 - H, RW = kLTX + 2 * H, RH = kLTY + 2 * H;
-    const double2 z = make_double2(0.0, 0.0);
-    for (int t = threadIdx.x; t < RW * RH; t += kLTThreads) {
-        const int lx = t % RW, ly = t / RW, a = ax0 + lx, b = by0 + ly;
-        double2 uu = z, ff = z, kk = z;
-        if (a >= 0 && b >= 0 && a <= n && b <= n) {
-            const size_t g = (size_t)b * pitch + a;
-            ff = f[g];
-            kk = k[g];
-            if (a > 0 && b > 0 && a < n && b < n) {
-                const int I = a >> 1, J = b >> 1;
-                const size_t cc = (size_t)J * pc + I;
-                double2 e;
-                if (!(a & 1) && !(b & 1)) e = uc[cc];
-                else if (a & 1 && !(b & 1)) e = cscl(0.5, cadd(uc[cc], uc[cc + 1]));
-                else if (!(a & 1)) e = cscl(0.5, cadd(uc[cc], uc[cc + pc]));
-                else e = cscl(0.25, cadd(cadd(uc[cc], uc[cc + 1]), cadd(uc[cc + pc], uc[cc + pc + 1])));
-                uu = cadd(um[g], e);
-            }
+    {
+        const int nc = n / 2;
+        double2 uu[kLIt], ff[kLIt], kk[kLIt];
+#pragma unroll
+        for (int q = 0; q < kLIt; ++q) {
+            const LasTileNode nd = las_node(q, RW, RH, ax0, by0, n, pitch);
+            const double2 fv = f[nd.g], kv = k[nd.g], mv = um[nd.g];
+            // the coarse cell's four corners (indices clamped into the coarse
+            // grid; a node outside the interior is masked below)
+            const int I = min(max(nd.a >> 1, 0), nc - 1), J = min(max(nd.b >> 1, 0), nc - 1);
+            const size_t cc = (size_t)J * pc + I;
+            const double2 c00 = uc[cc], c10 = uc[cc + 1], c01 = uc[cc + pc], c11 = uc[cc + pc + 1];
+            // the four bilinear forms, one selected by the node's parity (no
+            // branch, so the next node's loads are not held back)
+            const bool ox = nd.a & 1, oy = nd.b & 1;
+            const double2 e_oe = cscl(0.5, cadd(c00, c10)), e_eo = cscl(0.5, cadd(c00, c01));
+            const double2 e_oo = cscl(0.25, cadd(cadd(c00, c10), cadd(c01, c11)));
+            const double2 e_o = oy ? e_oo : e_oe, e_e = oy ? e_eo : c00;
+            const double2 e = ox ? e_o : e_e;
+            uu[q] = cscl(nd.inner ? 1.0 : 0.0, cadd(mv, e));
+            ff[q] = cscl(nd.in ? 1.0 : 0.0, fv);
+            kk[q] = cscl(nd.in ? 1.0 : 0.0, kv);
         }
-        U[ly][lx] = uu;
-        F[ly][lx] = ff;
-        K[ly][lx] = kk;
+#pragma unroll
+        for (int q = 0; q < kLIt; ++q) {
+            const LasTileNode nd = las_node(q, RW, RH, ax0, by0, n, pitch);
+            U[nd.ly][nd.lx] = uu[q];
+            F[nd.ly][nd.lx] = ff[q];
+            K[nd.ly][nd.lx] = kk[q];
+        }
     }
     __syncthreads();
     tile_sweeps(U, F, K, RW, RH, ax0, by0, n, h * h, nu);
