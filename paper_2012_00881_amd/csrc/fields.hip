@@ -93,14 +93,13 @@ __global__ void k_jz(int N, double L, double h, int pitch, const double* __restr
     const int b = blockIdx.y;
     if (a > N) return;
     const size_t i = (size_t)b * pitch + a;
-    double v = 0.0;
-    if (n[i] > 0.0) {
-        const double g = 1.0 + psi[i];
-        if (!(g > 0.0)) atomicOr(flags, 1);
-        const double q = a2 ? 0.5 * a2[i] : 0.0;
-        const double G = (n[i] * (1.0 + g * g + q) + g * g * (txx[i] + tyy[i])) / (2.0 * g);
-        v = G / g - n[i];
-    }
+    // every load unconditional and the plasma term selected after (a load
+    // behind the n* > 0 branch would be waited for inside it)
+    const double ni = n[i], g = 1.0 + psi[i], tt = txx[i] + tyy[i];
+    const double q = a2 ? 0.5 * a2[i] : 0.0;
+    if (ni > 0.0 && !(g > 0.0)) atomicOr(flags, 1);
+    const double G = (ni * (1.0 + g * g + q) + g * g * tt) / (2.0 * g);
+    const double v = ni > 0.0 ? G / g - ni : 0.0;
     jz[i] = v + beam_density(beams, -L + a * h, -L + b * h, (size_t)b * (N + 1) + a, st[0]) +
             driver_current(drv, i, st[0]);
 }

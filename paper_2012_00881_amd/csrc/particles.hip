@@ -410,20 +410,22 @@ __global__ __launch_bounds__(kDepThreadsJ) void k_deposit_jT(int N, double L, do
 }
 
 // d psi / dx at node (a, b): central inside, one-sided on the boundary columns
-// (ih = 1/h, ih2 = 1/(2h)).
+// (ih = 1/h, ih2 = 1/(2h)).  The three values are loaded unconditionally
+// (indices clamped into the row) and the formula selected after, so that no
+// load waits behind a branch.
 __device__ __forceinline__ double grad_x(const double* psi, int pitch, int N, double ih,
                                          double ih2, int a, int b) {
-    const size_t r = (size_t)b * pitch;
-    if (a == 0) return (psi[r + 1] - psi[r]) * ih;
-    if (a == N) return (psi[r + N] - psi[r + N - 1]) * ih;
-    return (psi[r + a + 1] - psi[r + a - 1]) * ih2;
+    const double* r = psi + (size_t)b * pitch;
+    const double pl = r[a > 0 ? a - 1 : 0], pc = r[a], pr = r[a < N ? a + 1 : N];
+    return a == 0 ? (pr - pc) * ih : (a == N ? (pc - pl) * ih : (pr - pl) * ih2);
 }
 
 __device__ __forceinline__ double grad_y(const double* psi, int pitch, int N, double ih,
                                          double ih2, int a, int b) {
-    if (b == 0) return (psi[(size_t)pitch + a] - psi[a]) * ih;
-    if (b == N) return (psi[(size_t)N * pitch + a] - psi[(size_t)(N - 1) * pitch + a]) * ih;
-    return (psi[(size_t)(b + 1) * pitch + a] - psi[(size_t)(b - 1) * pitch + a]) * ih2;
+    const double pl = psi[(size_t)(b > 0 ? b - 1 : 0) * pitch + a];
+    const double pc = psi[(size_t)b * pitch + a];
+    const double pr = psi[(size_t)(b < N ? b + 1 : N) * pitch + a];
+    return b == 0 ? (pr - pc) * ih : (b == N ? (pc - pl) * ih : (pr - pl) * ih2);
 }
 
 // grad psi at every node (grad_x, grad_y above) into two node arrays, once per
