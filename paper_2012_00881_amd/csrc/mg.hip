@@ -1116,19 +1116,43 @@ constexpr int coarse_nodes() {
     return t;
 }
 
-// Level operations with the level size as a compile-time constant.  FAST
-// (float LDS copies, which leave room in LDS): the restriction computes each
-// fine residual once into a buffer, and the Helmholtz sweeps multiply by a
-// stored 1/D instead of dividing.
-template <typename E, bool HELM, int n, bool FAST>
+// Levels of at most WQ_COARSE_WAVE_N cells a side run in the first wavefront
+// alone: a phase there has a few dozen nodes, and ordering its LDS traffic
+// inside one wavefront (whose LDS operations complete in order) costs no
+// workgroup barrier.  0: every level uses the whole workgroup.  The results
+// are the same bits for any value (the nodes of one colour are independent);
+// the Helmholtz coarse kernel measured 22.9 / 23.5 / 24.6 / 31.3 us with 8 /
+// 0 / 16 / 32: the phases are LDS latency chains more than barrier waits.
+#ifndef WQ_COARSE_WAVE_N
+#define WQ_COARSE_WAVE_N 8
+#endif
+constexpr int kCoarseWaveN = WQ_COARSE_WAVE_N;
+
+// Orders the LDS accesses of one wavefront around this point: the compiler
+// keeps them in program order and the hardware completes them in order.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Level operations with the level size as a compile-time constant, run by NT
+// threads (the workgroup, or the first wavefront when NT = 64).  FAST (float
+// LDS copies, which leave room in LDS): the restriction computes each fine
+// residual once into a buffer, and the Helmholtz sweeps multiply by a stored
+// 1/D instead of dividing.
+template <typename E, bool HELM, int n, bool FAST, int NT>
 struct LdsLevel {
     static constexpr int W = n + 1;
     static constexpr int HALF = n / 2;                // node slots of one colour per interior row
     static constexpr int ITEMS = (n - 1) * HALF;
-    static constexpr int NTH = kCoarseThreads;
+    static constexpr int NTH = NT;
     static constexpr int PER = (ITEMS + NTH - 1) / NTH;
 
-    static __device__ __forceinline__ void sync() { __syncthreads(); }
+    static __device__ __forceinline__ void sync() {
+        if constexpr (NT == 64) wave_sync();
+        else __syncthreads();
+    }
 
     // nu over-relaxed red-black sweeps (sor_update); iD (FAST and HELM) =
     // 1 / (4 + h2 k2); iDf (HELM, not FAST) = the same in float, refined by one
@@ -1228,15 +1252,27 @@ struct LdsLevel {
     }
 };
 
-// Level dispatch: runtime level size -> compile-time specialisation.
-template <typename E, bool HELM, bool FAST, typename Fn>
+// Level dispatch: runtime level size -> compile-time specialisation (for the
+// first wavefront alone only the sizes it runs).
+template <typename E, bool HELM, bool FAST, int NT, typename Fn>
 __device__ __forceinline__ void with_level(int n, Fn&& fn) {
+    constexpr int NMAX = NT == 64 ? kCoarseWaveN : 64;
     switch (n) {
-        case 64: fn(LdsLevel<E, HELM, 64, FAST>{}); break;
-        case 32: fn(LdsLevel<E, HELM, 32, FAST>{}); break;
-        case 16: fn(LdsLevel<E, HELM, 16, FAST>{}); break;
-        case 8: fn(LdsLevel<E, HELM, 8, FAST>{}); break;
-        default: fn(LdsLevel<E, HELM, 4, FAST>{}); break;
+        case 64:
+            if constexpr (NMAX >= 64) fn(LdsLevel<E, HELM, 64, FAST, NT>{});
+            break;
+        case 32:
+            if constexpr (NMAX >= 32) fn(LdsLevel<E, HELM, 32, FAST, NT>{});
+            break;
+        case 16:
+            if constexpr (NMAX >= 16) fn(LdsLevel<E, HELM, 16, FAST, NT>{});
+            break;
+        case 8:
+            if constexpr (NMAX >= 8) fn(LdsLevel<E, HELM, 8, FAST, NT>{});
+            break;
+        default:
+            if constexpr (NMAX >= 4) fn(LdsLevel<E, HELM, 4, FAST, NT>{});
+            break;
     }
 }
 
@@ -1348,39 +1384,52 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(CoarseArgs<E> a) {
     }
     __syncthreads();
 
-    auto down = [&](int l) {
+    auto down = [&](int l, auto nt) {
+        constexpr int NT = decltype(nt)::value;
         const double hl = a.h * (double)(1 << l);
         C* u = su + off[l];
         C* f = sf + off[l];
         const C* k2 = sk + (HELM ? off[l] : 0);
         const C* iD = siD + ((HELM && FAST) ? off[l] : 0);
         const float* iDf = siDf + ((HELM && !FAST) ? off[l] : 0);
-        with_level<C, HELM, FAST>(Ns[l], [&](auto L) {
+        with_level<C, HELM, FAST, NT>(Ns[l], [&](auto L) {
             L.smooth(u, f, k2, iD, iDf, (C)(hl * hl), (C)(HELM && hl * hl > a.h2max ? 1.0 : a.omega), a.nu1);
             L.restrict_to(u, f, k2, (C)(1.0 / (hl * hl)), su + off[l + 1], sf + off[l + 1], sr);
         });
     };
-    auto up = [&](int l) {
+    auto up = [&](int l, auto nt) {
+        constexpr int NT = decltype(nt)::value;
         const double hl = a.h * (double)(1 << l);
         C* u = su + off[l];
-        with_level<C, HELM, FAST>(Ns[l], [&](auto L) {
+        with_level<C, HELM, FAST, NT>(Ns[l], [&](auto L) {
             L.prolong_add(u, su + off[l + 1]);
             L.smooth(u, sf + off[l], sk + (HELM ? off[l] : 0), siD + ((HELM && FAST) ? off[l] : 0),
                      siDf + ((HELM && !FAST) ? off[l] : 0), (C)(hl * hl),
                      (C)(HELM && hl * hl > a.h2max ? 1.0 : a.omega), a.nu2);
         });
     };
+    const std::integral_constant<int, kCoarseThreads> all{};
+    const std::integral_constant<int, 64> wave{};
+    // levels lw and below (at most kCoarseWaveN cells a side) in the first
+    // wavefront; the workgroup's barriers before and after hand the LDS over
+    int lw = 0;
+    while (lw < nl - 1 && Ns[lw] > kCoarseWaveN) ++lw;
     for (int cyc = 0; cyc < a.ncycles; ++cyc) {
-        for (int l = 0; l < nl - 1; ++l) down(l);
-        if (tid == 0) {  // 2x2 cells: one unknown, four zero neighbours
-            const int l = nl - 1;
-            const double hl = a.h * (double)(1 << l);
-            const int c = 1 * 3 + 1;
-            const double k2c = HELM ? (double)sk[off[l] + c] : 0.0;
-            su[off[l] + c] = (C)(-(double)sf[off[l] + c] / (4.0 / (hl * hl) + k2c));
+        for (int l = 0; l < lw; ++l) down(l, all);
+        if (tid < 64) {
+            for (int l = lw; l < nl - 1; ++l) down(l, wave);
+            if (tid == 0) {  // 2x2 cells: one unknown, four zero neighbours
+                const int l = nl - 1;
+                const double hl = a.h * (double)(1 << l);
+                const int c = 1 * 3 + 1;
+                const double k2c = HELM ? (double)sk[off[l] + c] : 0.0;
+                su[off[l] + c] = (C)(-(double)sf[off[l] + c] / (4.0 / (hl * hl) + k2c));
+            }
+            wave_sync();
+            for (int l = nl - 2; l >= lw; --l) up(l, wave);
         }
         __syncthreads();
-        for (int l = nl - 2; l >= 0; --l) up(l);
+        for (int l = lw - 1; l >= 0; --l) up(l, all);
     }
     for (int i = tid; i < (N + 1) * (N + 1); i += kCoarseThreads) {
         const int y = i / (N + 1), x = i - y * (N + 1);
