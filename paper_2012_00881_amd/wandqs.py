@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libwandqs.so")
+# WANDQS_LIB names another build of the same library (the host code built with
+# the address and undefined-behaviour sanitizers, for the CPU tests)
+LIB_PATH = os.environ.get("WANDQS_LIB") or os.path.join(_HERE, "libwandqs.so")
 
 OK, E_INVALID, E_NOMEM, E_HIP, E_NOCONV, E_NONPHYS, E_STATE = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_HIP", -4: "E_NOCONV",
