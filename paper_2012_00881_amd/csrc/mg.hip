@@ -1128,14 +1128,6 @@ constexpr int coarse_nodes() {
 #endif
 constexpr int kCoarseWaveN = WQ_COARSE_WAVE_N;
 
-// Orders the LDS accesses of one wavefront around this point: the compiler
-// keeps them in program order and the hardware completes them in order.
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Level operations with the level size as a compile-time constant, run by NT
 // threads (the workgroup, or the first wavefront when NT = 64).  FAST (float
 // LDS copies, which leave room in LDS): the restriction computes each fine

@@ -92,6 +92,14 @@ __device__ __forceinline__ void tile_rhs_of_block(int& bx, int& by, int& z) {
     bx = tile - by * gx;
 }
 
+// Orders the LDS accesses of one wavefront around this point: the compiler
+// keeps them in program order and the hardware completes them in order.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 enum SolveKind {
     kSolvePsi = 0,
     kSolveEB = 1,
