@@ -597,8 +597,9 @@ def main():
                        "grid": cfg["n_cells"], "particles": P, "slices": K,
                        "precision": args.precision, "mg_rtol": cfg["mg_rtol"],
                        "coarse_corrections": "the FP64 form's Helmholtz coarse levels (<= 64^2) "
-                                             "sweep in FP32 and its Poisson coarse level is solved "
-                                             "by an FP32 sine transform; the FP64 fine levels' "
+                                             "sweep in FP32; its Poisson cycles end on level 1 "
+                                             "with an FP64 fast-sine-transform solve (an FP32 one "
+                                             "at 64^2 on 128^2 grids); the FP64 fine levels' "
                                              "residuals carry the answer to the FP64 rounding floor",
                        "lead_in_slices": lead, "xi_start": win["xi"], "xi_end": final["xi"],
                        "mean_vcycles": [round(c, 3) for c in cyc]},
