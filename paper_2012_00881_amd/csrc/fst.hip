@@ -23,16 +23,16 @@
 // (one radix-2 stage last for an odd power of two) whose stages exchange
 // through LDS (one pad slot per 16 doubles) with no workgroup barrier, since a
 // wavefront's LDS operations complete in order.  Three launches; T1 and T2 are
-// stored transposed, so that every pass reads whole rows and only its writes
-// are scattered:
+// stored transposed, so that every pass reads whole rows and only the writes
+// of the first two are scattered (two rows per workgroup, written in pairs):
 //   x: row g of f -> column g of T1 (T1[k-1][g-1] = coefficient k);
 //   y: row k-1 of T1 -> transform, divide by lambda, transform back ->
 //      column k-1 of T2 (T2[j-1][k-1], j the y-node);
 //   x inverse: row j-1 of T2 -> row j of u.
 // A first form with two rows packed into one complex FFT of length 2n (the
 // odd extensions; 256 threads and a barrier per stage) measured 9.7 / 6.6 /
-// 5.3 us for the y / x inverse / x passes at n = 512, this one 8.3 / 5.5 /
-// 6.2 (its x pass pays for the scattered writes).
+// 5.3 us for the y / x inverse / x passes at n = 512, this one 7.5 / 5.4 /
+// 5.4.
 #include <cstdio>
 
 #include "wq_common.h"
@@ -112,7 +112,7 @@ __device__ __forceinline__ void wstage(const Src& src, double* yr, double* yi, c
     constexpr int NBF = H / R, NBL = (NBF + 63) / 64;
 #pragma unroll
     for (int b = 0; b < NBL; ++b) {
-        const int j = threadIdx.x + 64 * b;
+        const int j = (threadIdx.x & 63) + 64 * b;
         if (NBF % 64 != 0 && j >= NBF) break;
         const int k = j & (NS - 1);
         double vr[R], vi[R];
@@ -166,7 +166,7 @@ __device__ __forceinline__ void wdst(const Get& get, const double (&sn)[FstSize<
                                      double (&xe)[FstSize<LOGN>::PER], double (&xo)[FstSize<LOGN>::PER]) {
     using F = FstSize<LOGN>;
     constexpr int n = F::n, H = F::H, NB = F::NB, PER = F::PER, LP = F::LP;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     // first-stage inputs z_m, m = min(lane + 64 b, H/4 - 1) + s H/4; every load
     // issued before any is used (indices clamped, zero ends masked after)
     double xa[NB][4][2], xb[NB][4][2];
@@ -234,17 +234,24 @@ __device__ __forceinline__ void wdst(const Get& get, const double (&sn)[FstSize<
     wave_sync();  // the caller may overwrite buf next
 }
 
-// MODE 0: x pass; MODE 1: y pass; MODE 2: x inverse (see above).  Workgroup
-// = one wavefront = row p (0-based interior) of right-hand side r.
-template <typename E, int LOGN, int MODE>
-__global__ __launch_bounds__(64) void k_fst(FstArgs<E> a) {
+// MODE 0: x pass; MODE 1: y pass; MODE 2: x inverse (see above).  A
+// workgroup holds RW wavefronts, wavefront w transforming row RW b + w
+// (0-based interior; b the block) of right-hand side r; a wavefront past the
+// last row transforms the last row again and writes nothing.  With RW > 1 the
+// transposed writes of MODE 0 and 1 go through LDS, RW consecutive rows'
+// values of one coefficient written together.
+template <typename E, int LOGN, int MODE, int RW>
+__global__ __launch_bounds__(64 * RW) void k_fst(FstArgs<E> a) {
     using F = FstSize<LOGN>;
     constexpr int n = F::n, H = F::H, NB = F::NB, PER = F::PER, LP = F::LP;
-    __shared__ double buf[4 * LP];
+    __shared__ double bufs[RW][4 * LP];
     __shared__ double2 T[H];
-    int p, r;
-    tile_of_block(p, r);
-    const int lane = threadIdx.x;
+    int pb, r;
+    tile_of_block(pb, r);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const bool live = pb * RW + w < n - 1;
+    const int p = live ? pb * RW + w : n - 2;
+    double* buf = bufs[w];
     // tables: W_n^m (m < H) = W_2n^2m into LDS; the lane's sin(pi j / n) =
     // -Im W_2n^j; for MODE 1 its sin^2(pi l / 2n) and that of k = p + 1
     double2 tv[PER];
@@ -296,7 +303,7 @@ __global__ __launch_bounds__(64) void k_fst(FstArgs<E> a) {
         const auto get = [=](int j) { return V[j]; };
         wdst<LOGN, false>(get, sn, buf, T, tv, xe, xo);
     }
-    if (MODE < 2) {
+    if (MODE < 2 && RW == 1) {
         // coefficient c (1 .. n-1) of this row to T[c - 1][p]
         double* Tt = (MODE == 0 ? a.t1 : a.t2)[r] + p;
 #pragma unroll
@@ -304,6 +311,20 @@ __global__ __launch_bounds__(64) void k_fst(FstArgs<E> a) {
             const int c = 2 * (lane * PER + q);
             if (c >= 1) Tt[(size_t)(c - 1) * ld] = xe[q];
             Tt[(size_t)c * ld] = xo[q];
+        }
+    } else if (MODE < 2) {
+        // the RW rows' coefficients through LDS: T[c - 1][RW b .. RW b + RW - 1]
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int k = lane * PER + q;
+            buf[2 * k] = xe[q];
+            buf[2 * k + 1] = xo[q];
+        }
+        __syncthreads();
+        double* Tt = (MODE == 0 ? a.t1 : a.t2)[r] + pb * RW;
+        for (int i = threadIdx.x; i < (n - 1) * RW; i += 64 * RW) {
+            const int c = 1 + i / RW, ww = i % RW;
+            if (pb * RW + ww < n - 1) Tt[(size_t)(c - 1) * ld + ww] = bufs[ww][c];
         }
     } else {
         E* u = a.u[r];
@@ -324,27 +345,35 @@ __global__ __launch_bounds__(64) void k_fst(FstArgs<E> a) {
     }
 }
 
+// Rows per workgroup of the x and y passes, whose transposed writes then go
+// out in 16-byte pieces: at n = 512 they measured 5.4 / 7.5 us with 2 rows,
+// 6.1 / 8.0 with 1 and 5.7 / 8.0 with 4 (the same bits in every case)
+#ifndef WQ_FST_ROWS
+#define WQ_FST_ROWS 2
+#endif
+
 template <typename E, int LOGN>
 void launch_fst(wandqs_ctx* c, const FstArgs<E>& a, int R, const char* tname) {
     constexpr int n = 1 << LOGN;
-    const dim3 g(n - 1, R);
+    constexpr int RW = LOGN <= 10 ? WQ_FST_ROWS : 1;
+    const dim3 g(n - 1, R), gw((n - 1 + RW - 1) / RW, R);
     const double nodes = (double)(n - 1) * (n - 1) * R;
     const double eb = sizeof(E);
     char nm[64];
     {
         std::snprintf(nm, sizeof nm, "k_fst<%s, x>@%d", tname, n);
         ProfScope ps(c, nm, nodes * (eb + 8.0));
-        WQ_KLAUNCH(ps, (k_fst<E, LOGN, 0>), g, dim3(64), 0, c->stream, a);
+        WQ_KLAUNCH(ps, (k_fst<E, LOGN, 0, RW>), gw, dim3(64 * RW), 0, c->stream, a);
     }
     {
         std::snprintf(nm, sizeof nm, "k_fst<%s, y>@%d", tname, n);
         ProfScope ps(c, nm, nodes * 16.0);
-        WQ_KLAUNCH(ps, (k_fst<E, LOGN, 1>), g, dim3(64), 0, c->stream, a);
+        WQ_KLAUNCH(ps, (k_fst<E, LOGN, 1, RW>), gw, dim3(64 * RW), 0, c->stream, a);
     }
     {
         std::snprintf(nm, sizeof nm, "k_fst<%s, xinv>@%d", tname, n);
         ProfScope ps(c, nm, nodes * (8.0 + eb));
-        WQ_KLAUNCH(ps, (k_fst<E, LOGN, 2>), g, dim3(64), 0, c->stream, a);
+        WQ_KLAUNCH(ps, (k_fst<E, LOGN, 2, 1>), g, dim3(64), 0, c->stream, a);
     }
 }
 
