@@ -527,24 +527,26 @@ __device__ __forceinline__ void reg_load(E (&u)[R][K][2], E (&f)[R][K][2], E (&D
         const int gy = gy0 + k;
         const bool in = gy >= 0 && gy <= N && gx >= 0 && gx <= N;
         const bool in1 = in && gx + 1 <= N;  // gx + 1 <= pitch - 1: the load stays in the row
+        // every row's loads issued without a lane-dependent branch (a node
+        // past the grid loads node 0 and is masked by a product with 0: the
+        // values are finite), so that the rows' loads are in flight together
         const size_t g = in ? (size_t)gy * pitch + gx : 0;
+        const E m0 = in ? E(1) : E(0), m1 = in1 ? E(1) : E(0);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            V2 uv{E(0), E(0)}, fv{E(0), E(0)};
-            if (in) {
-                if (uin[r]) uv = *reinterpret_cast<const V2*>(uin[r] + g);
-                fv = *reinterpret_cast<const V2*>(fin[r] + g);
-            }
-            u[r][k][0] = uv.x;
-            u[r][k][1] = in1 ? uv.y : E(0);
-            f[r][k][0] = fv.x;
-            f[r][k][1] = in1 ? fv.y : E(0);
+            V2 uv{E(0), E(0)};
+            if (uin[r]) uv = *reinterpret_cast<const V2*>(uin[r] + g);  // uniform
+            const V2 fv = *reinterpret_cast<const V2*>(fin[r] + g);
+            u[r][k][0] = uv.x * m0;
+            u[r][k][1] = uv.y * m1;
+            f[r][k][0] = fv.x * m0;
+            f[r][k][1] = fv.y * m1;
         }
         double q0 = 0.0, q1 = 0.0;
-        if (HELM && in) {
+        if (HELM) {
             const double2 kv = *reinterpret_cast<const double2*>(k2 + g);
-            q0 = kv.x;
-            q1 = in1 ? kv.y : 0.0;
+            q0 = kv.x * (double)m0;
+            q1 = kv.y * (double)m1;
         }
         const double D0 = fmad(h2, q0, 4.0), D1 = fmad(h2, q1, 4.0);
         D[k][0] = (E)D0;
@@ -809,10 +811,14 @@ __global__ __launch_bounds__(64 * NW) void k_mg_up_reg(UpArgs<E> a) {
         const int J = J0 + m;
         const bool inJ = J >= 0 && J <= Nc;
         const bool inL = inJ && I >= 0 && I <= Nc, inR = inJ && I + 1 >= 0 && I + 1 <= Nc;
+        // indices clamped into the coarse grid, values masked after (no load
+        // behind a lane-dependent branch)
+        const size_t row = (size_t)min(max(J, 0), Nc) * a.pitch_c;
+        const int iL = min(max(I, 0), Nc), iR = min(max(I + 1, 0), Nc);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            eL[r][m] = inL ? a.e_c[r + z][(size_t)J * a.pitch_c + I] : E(0);
-            eR[r][m] = inR ? a.e_c[r + z][(size_t)J * a.pitch_c + I + 1] : E(0);
+            eL[r][m] = a.e_c[r + z][row + iL] * (inL ? E(1) : E(0));
+            eR[r][m] = a.e_c[r + z][row + iR] * (inR ? E(1) : E(0));
         }
     }
 
@@ -965,10 +971,14 @@ __global__ __launch_bounds__(64 * NW) void k_mg_updown_reg(FuseArgs<E> a) {
         const int J = J0 + m;
         const bool inJ = J >= 0 && J <= Nc;
         const bool inL = inJ && I >= 0 && I <= Nc, inR = inJ && I + 1 >= 0 && I + 1 <= Nc;
+        // indices clamped into the coarse grid, values masked after (no load
+        // behind a lane-dependent branch)
+        const size_t row = (size_t)min(max(J, 0), Nc) * a.pitch_c;
+        const int iL = min(max(I, 0), Nc), iR = min(max(I + 1, 0), Nc);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            eL[r][m] = inL ? a.e_c[r + z][(size_t)J * a.pitch_c + I] : E(0);
-            eR[r][m] = inR ? a.e_c[r + z][(size_t)J * a.pitch_c + I + 1] : E(0);
+            eL[r][m] = a.e_c[r + z][row + iL] * (inL ? E(1) : E(0));
+            eR[r][m] = a.e_c[r + z][row + iR] * (inR ? E(1) : E(0));
         }
     }
     bool upd[K][2], dom[K][2], own[K];
