@@ -267,15 +267,29 @@ wandqs_status do_slice(wandqs_ctx* c, int rec_slot, int64_t probe_slice, bool ta
     if ((s = deposit_n(c)) != WANDQS_OK) return s;  // Collect_Source: n*
     double* u1[2] = {c->fields[0], nullptr};
     double* f1[2] = {L0.f[0], nullptr};
-    if ((s = mg_solve(c, kSolvePsi, 1, false, u1, f1, nullptr, &c->last[0])) != WANDQS_OK) return s;
-    if ((s = deposit_jT(c)) != WANDQS_OK) return s;  // Collect_Source: j, T
+    // the j, T deposit (Collect_Source) reads psi only: it runs behind the psi
+    // solve's first batch while the host waits for that batch's norms (and
+    // again after any further cycle; its 1 + psi <= 0 flag on the first
+    // batch's iterate, which differs from the solution by the last cycles'
+    // corrections, marks a state at breakdown either way)
+    if ((s = mg_solve(c, kSolvePsi, 1, false, u1, f1, nullptr, &c->last[0],
+                      [c] { return deposit_jT(c); })) != WANDQS_OK)
+        return s;
     if ((s = rhs_EB(c)) != WANDQS_OK) return s;
     double* u2[2] = {c->fields[1], c->fields[2]};
     double* f2[2] = {L0.f[0], L0.f[1]};
-    if ((s = mg_solve(c, kSolveEB, 2, false, u2, f2, nullptr, &c->last[1])) != WANDQS_OK) return s;
-    if ((s = assemble(c)) != WANDQS_OK) return s;
+    // j_z does not read E_z or B_z: it runs behind the E_z / B_z solve's first batch
+    if ((s = mg_solve(c, kSolveEB, 2, false, u2, f2, nullptr, &c->last[1],
+                      [c] { return plasma_jz(c); })) != WANDQS_OK)
+        return s;
+    if ((s = assemble(c, true)) != WANDQS_OK) return s;
     double* u3[2] = {c->fields[3], c->fields[4]};
-    if ((s = mg_solve(c, kSolveBperp, 2, true, u3, f2, L0.k2, &c->last[2])) != WANDQS_OK) return s;
+    // grad psi for the push does not read B_perp: it runs behind the B_perp
+    // solve's first batch
+    if ((s = mg_solve(c, kSolveBperp, 2, true, u3, f2, L0.k2, &c->last[2],
+                      [c] { return node_gradient(c, c->fields[0], c->gpsi[0], c->gpsi[1]); })) !=
+        WANDQS_OK)
+        return s;
     if (rec) {
         const size_t nb = node_bytes(c);
         for (int q = 0; q < 5; ++q)
@@ -286,7 +300,7 @@ wandqs_status do_slice(wandqs_ctx* c, int rec_slot, int64_t probe_slice, bool ta
         if ((s = copy_d2d(c, rec->st, c->st, 2 * sizeof(double))) != WANDQS_OK) return s;
     }
     if (!c->probes.empty() && (s = probes_accumulate(c, probe_slice)) != WANDQS_OK) return s;
-    if ((s = push_and_step(c, rec_slot)) != WANDQS_OK) return s;  // Push_Trajectory + Step_Size_Refinement
+    if ((s = push_and_step(c, rec_slot, true)) != WANDQS_OK) return s;  // Push_Trajectory + Step_Size_Refinement
     if (c->drv_active) {
         // the driver particles whose mid-step xi lies between the previous
         // slice and this one take their wake from the two; this slice's

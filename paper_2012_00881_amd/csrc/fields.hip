@@ -283,7 +283,7 @@ wandqs_status rhs_EB(wandqs_ctx* c) {
     return WANDQS_OK;
 }
 
-wandqs_status assemble(wandqs_ctx* c) {
+wandqs_status plasma_jz(wandqs_ctx* c) {
     const Level& L0 = c->lev[0];
     {
         const DriverPlanes drv{c->drv_active ? c->drv_planes : nullptr, c->drv_nz, c->cfg.driver_xi0,
@@ -292,6 +292,17 @@ wandqs_status assemble(wandqs_ctx* c) {
         WQ_KLAUNCH(ps, k_jz, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->L, c->h, L0.pitch,
                            c->mom[0], c->mom[3], c->mom[5], c->fields[0],
                            c->las_on ? c->las_a2 : nullptr, c->st, c->beamset, drv, c->jz, c->flags);
+    }
+    WQ_LAUNCH_CHECK();
+    return WANDQS_OK;
+}
+
+// jz_ready: plasma_jz has run already (it does not read E_z or B_z).
+wandqs_status assemble(wandqs_ctx* c, bool jz_ready) {
+    const Level& L0 = c->lev[0];
+    if (!jz_ready) {
+        const wandqs_status s = plasma_jz(c);
+        if (s != WANDQS_OK) return s;
     }
     {
         ProfScope ps(c, "k_assemble", (double)(c->N + 1) * (c->N + 1) * 104.0);

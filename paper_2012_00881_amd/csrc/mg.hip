@@ -2357,7 +2357,8 @@ wandqs_status wait_published(wandqs_ctx* c, const uint32_t* h_seq, uint32_t seq)
 // residual.
 // Fixed mode runs mg_max_cycles cycles without any host synchronisation.
 wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const u[2],
-                       double* const f[2], const double* k2, SolveResult* res) {
+                       double* const f[2], const double* k2, SolveResult* res,
+                       const std::function<wandqs_status()>& ahead) {
     hipStream_t s = c->stream;
     Hier<double> hz{{u[0], R > 1 ? u[1] : nullptr}, {f[0], R > 1 ? f[1] : nullptr}, k2};
     const bool mixed = c->cfg.precision == WANDQS_MIXED;
@@ -2408,7 +2409,7 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
         if (graph_check() != WANDQS_OK) return WANDQS_E_HIP;
         WQ_LAUNCH_CHECK();
         if (res) *res = SolveResult{maxc, {-1.0, -1.0}};
-        return WANDQS_OK;
+        return ahead ? ahead() : WANDQS_OK;
     }
     const int N = c->N;
     const double atol = c->cfg.mg_atol * std::sqrt((double)(N - 1) * (N - 1));
@@ -2464,6 +2465,13 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
                        h_flags, h_seq, seq, c->pub_count);
         }
         WQ_LAUNCH_CHECK();
+        // behind the first batch: the caller's follow-up work, on the device
+        // while the host waits for the norms
+        const bool first = done == 0;
+        if (first && ahead) {
+            const wandqs_status st = ahead();
+            if (st != WANDQS_OK) return st;
+        }
         if (wait_published(c, h_seq, seq) != WANDQS_OK) return WANDQS_E_HIP;
         done += b;
         const int32_t fl = __atomic_load_n(h_flags, __ATOMIC_ACQUIRE);
@@ -2511,6 +2519,9 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
                 return WANDQS_E_NOCONV;
             }
             c->pred[kind] = need < 1 ? 1 : need;
+            // further cycles ran after the follow-up work: it reads the final
+            // iterate only when enqueued again
+            if (!first && ahead) return ahead();
             return WANDQS_OK;
         }
     }

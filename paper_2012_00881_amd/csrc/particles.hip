@@ -804,9 +804,10 @@ wandqs_status deposit_jT(wandqs_ctx* c) {
     return WANDQS_OK;
 }
 
-wandqs_status push_and_step(wandqs_ctx* c, int rec_slot) {
+// grad_ready: grad psi (gpsi) is made already (node_gradient of fields[0]).
+wandqs_status push_and_step(wandqs_ctx* c, int rec_slot, bool grad_ready) {
     const int k = c->cur;
-    {
+    if (!grad_ready) {
         ProfScope pg(c, "k_grad_psi", (double)(c->N + 1) * (c->N + 1) * 24.0);
         WQ_KLAUNCH(pg, k_grad_psi, dim3((c->N + 1 + 127) / 128, c->N + 1), dim3(128), 0, c->stream,
                            c->N, c->h, c->lev[0].pitch, c->fields[0], c->gpsi[0], c->gpsi[1]);

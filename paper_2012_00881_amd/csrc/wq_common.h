@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -381,16 +382,22 @@ template <typename E>
 void fst_solve(wandqs_ctx* c, int R, const E* const* f, E* const* u);
 
 // multigrid (mg.hip)
+// ahead (optional): work that reads the solution but does not change what the
+// solve reads, enqueued behind the first batch of cycles while the host waits
+// for its residual norms (so that the device does not idle), and enqueued once
+// more behind the last cycle when further cycles follow.
 wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const u[2],
-                       double* const f[2], const double* k2, SolveResult* res);
+                       double* const f[2], const double* k2, SolveResult* res,
+                       const std::function<wandqs_status()>& ahead = {});
 
 // particles and fields (particles.hip, fields.hip)
 wandqs_status slice_sort(wandqs_ctx* c);
 wandqs_status deposit_n(wandqs_ctx* c);
 wandqs_status deposit_jT(wandqs_ctx* c);
 wandqs_status rhs_EB(wandqs_ctx* c);
-wandqs_status assemble(wandqs_ctx* c);
-wandqs_status push_and_step(wandqs_ctx* c, int rec_slot);
+wandqs_status plasma_jz(wandqs_ctx* c);
+wandqs_status assemble(wandqs_ctx* c, bool jz_ready = false);
+wandqs_status push_and_step(wandqs_ctx* c, int rec_slot, bool grad_ready = false);
 wandqs_status probes_accumulate(wandqs_ctx* c, int64_t slice);
 wandqs_status pack_fields(wandqs_ctx* c, double* const* src, int n, double* dst);
 wandqs_status unpack_fields(wandqs_ctx* c, const double* src, int n, double* const* dst);
