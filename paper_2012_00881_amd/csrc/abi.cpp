@@ -278,17 +278,20 @@ wandqs_status do_slice(wandqs_ctx* c, int rec_slot, int64_t probe_slice, bool ta
     if ((s = rhs_EB(c)) != WANDQS_OK) return s;
     double* u2[2] = {c->fields[1], c->fields[2]};
     double* f2[2] = {L0.f[0], L0.f[1]};
-    // j_z does not read E_z or B_z: it runs behind the E_z / B_z solve's first batch
-    if ((s = mg_solve(c, kSolveEB, 2, false, u2, f2, nullptr, &c->last[1],
-                      [c] { return plasma_jz(c); })) != WANDQS_OK)
+    // j_z and k2 = n*/g (with its coarser levels for the B_perp multigrid) do
+    // not read E_z or B_z: they run behind the E_z / B_z solve's first batch
+    if ((s = mg_solve(c, kSolveEB, 2, false, u2, f2, nullptr, &c->last[1], [c, &L0] {
+             const wandqs_status st = plasma_jz(c);
+             return st != WANDQS_OK ? st : helm_levels(c, L0.k2);
+         })) != WANDQS_OK)
         return s;
     if ((s = assemble(c, true)) != WANDQS_OK) return s;
     double* u3[2] = {c->fields[3], c->fields[4]};
     // grad psi for the push does not read B_perp: it runs behind the B_perp
     // solve's first batch
     if ((s = mg_solve(c, kSolveBperp, 2, true, u3, f2, L0.k2, &c->last[2],
-                      [c] { return node_gradient(c, c->fields[0], c->gpsi[0], c->gpsi[1]); })) !=
-        WANDQS_OK)
+                      [c] { return node_gradient(c, c->fields[0], c->gpsi[0], c->gpsi[1]); },
+                      true)) != WANDQS_OK)
         return s;
     if (rec) {
         const size_t nb = node_bytes(c);

@@ -88,7 +88,8 @@ __global__ void k_jz(int N, double L, double h, int pitch, const double* __restr
                      const double* __restrict__ txx, const double* __restrict__ tyy,
                      const double* __restrict__ psi, const double* __restrict__ a2,
                      const double* __restrict__ st, BeamSet beams, DriverPlanes drv,
-                     double* __restrict__ jz, int32_t* __restrict__ flags) {
+                     double* __restrict__ jz, double* __restrict__ k2,
+                     int32_t* __restrict__ flags) {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
     if (a > N) return;
@@ -102,9 +103,13 @@ __global__ void k_jz(int N, double L, double h, int pitch, const double* __restr
     const double v = ni > 0.0 ? G / g - ni : 0.0;
     jz[i] = v + beam_density(beams, -L + a * h, -L + b * h, (size_t)b * (N + 1) + a, st[0]) +
             driver_current(drv, i, st[0]);
+    // k2 = n* / g of the B_perp Helmholtz system (eqs. (18)-(19)) on the
+    // interior nodes (it reads neither E_z nor B_z)
+    const bool interior = a >= 1 && b >= 1 && a <= N - 1 && b <= N - 1;
+    k2[i] = interior && ni > 0.0 ? ni / g : 0.0;
 }
 
-// k2 = n* / g and the B_perp right-hand sides on the interior nodes:
+// The B_perp right-hand sides on the interior nodes (k_jz writes k2 = n* / g):
 //   f_Bx = D_y(j_z - Tyy) - D_x Txy + (jx Bz - jy Ez)/g + (G/g^2 - Tyy/g) psi_y - (Txy/g) psi_x
 //          - n* D_y(a2/4)/g^2
 //   f_By = D_x(Txx - j_z) + D_y Txy + (jy Bz + jx Ez)/g - (G/g^2 - Txx/g) psi_x + (Txy/g) psi_y
@@ -117,13 +122,12 @@ __global__ void k_assemble(int N, double h, int pitch, const double* __restrict_
                            const double* __restrict__ tyy, const double* __restrict__ psi,
                            const double* __restrict__ Ez, const double* __restrict__ Bz,
                            const double* __restrict__ jz, const double* __restrict__ a2,
-                           double* __restrict__ k2, double* __restrict__ fBx,
-                           double* __restrict__ fBy) {
+                           double* __restrict__ fBx, double* __restrict__ fBy) {
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
     if (a > N) return;
     const size_t i = (size_t)b * pitch + a;
-    double k = 0.0, fx = 0.0, fy = 0.0;
+    double fx = 0.0, fy = 0.0;
     if (a >= 1 && b >= 1 && a <= N - 1 && b <= N - 1) {
         const double i2h = 1.0 / (2.0 * h);
         const size_t e = i + 1, w = i - 1, nn = i + pitch, s = i - pitch;
@@ -134,7 +138,6 @@ __global__ void k_assemble(int N, double h, int pitch, const double* __restrict_
         if (n[i] > 0.0) {
             const double q = a2 ? 0.5 * a2[i] : 0.0;
             const double G = (n[i] * (1.0 + g * g + q) + g * g * (txx[i] + tyy[i])) / (2.0 * g);
-            k = n[i] / g;
             fx += (jx[i] * Bz[i] - jy[i] * Ez[i]) / g + (G / (g * g) - tyy[i] / g) * psy -
                   (txy[i] / g) * psx;
             fy += (jy[i] * Bz[i] + jx[i] * Ez[i]) / g - (G / (g * g) - txx[i] / g) * psx +
@@ -145,7 +148,6 @@ __global__ void k_assemble(int N, double h, int pitch, const double* __restrict_
             }
         }
     }
-    k2[i] = k;
     fBx[i] = fx;
     fBy[i] = fy;
 }
@@ -288,10 +290,11 @@ wandqs_status plasma_jz(wandqs_ctx* c) {
     {
         const DriverPlanes drv{c->drv_active ? c->drv_planes : nullptr, c->drv_nz, c->cfg.driver_xi0,
                                c->cfg.driver_dz, (size_t)(c->N + 1) * L0.pitch};
-        ProfScope ps(c, "k_jz", (double)(c->N + 1) * (c->N + 1) * 40.0);
+        ProfScope ps(c, "k_jz", (double)(c->N + 1) * (c->N + 1) * 48.0);
         WQ_KLAUNCH(ps, k_jz, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->L, c->h, L0.pitch,
                            c->mom[0], c->mom[3], c->mom[5], c->fields[0],
-                           c->las_on ? c->las_a2 : nullptr, c->st, c->beamset, drv, c->jz, c->flags);
+                           c->las_on ? c->las_a2 : nullptr, c->st, c->beamset, drv, c->jz, L0.k2,
+                           c->flags);
     }
     WQ_LAUNCH_CHECK();
     return WANDQS_OK;
@@ -305,11 +308,11 @@ wandqs_status assemble(wandqs_ctx* c, bool jz_ready) {
         if (s != WANDQS_OK) return s;
     }
     {
-        ProfScope ps(c, "k_assemble", (double)(c->N + 1) * (c->N + 1) * 104.0);
+        ProfScope ps(c, "k_assemble", (double)(c->N + 1) * (c->N + 1) * 96.0);
         WQ_KLAUNCH(ps, k_assemble, node_grid(c->N), dim3(128), 0, c->stream, c->N, c->h, L0.pitch,
                            c->mom[0], c->mom[1], c->mom[2], c->mom[3], c->mom[4], c->mom[5],
                            c->fields[0], c->fields[1], c->fields[2], c->jz,
-                           c->las_on ? c->las_a2 : nullptr, L0.k2, L0.f[0], L0.f[1]);
+                           c->las_on ? c->las_a2 : nullptr, L0.f[0], L0.f[1]);
     }
     WQ_LAUNCH_CHECK();
     return WANDQS_OK;

@@ -2356,13 +2356,9 @@ wandqs_status wait_published(wandqs_ctx* c, const uint32_t* h_seq, uint32_t seq)
 // longer halves ||r|| once ||r|| <= 1e-9 max(||f||, ||r_0||), r_0 the initial
 // residual.
 // Fixed mode runs mg_max_cycles cycles without any host synchronisation.
-wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const u[2],
-                       double* const f[2], const double* k2, SolveResult* res,
-                       const std::function<wandqs_status()>& ahead) {
+wandqs_status helm_levels(wandqs_ctx* c, const double* k2) {
     hipStream_t s = c->stream;
-    Hier<double> hz{{u[0], R > 1 ? u[1] : nullptr}, {f[0], R > 1 ? f[1] : nullptr}, k2};
-    const bool mixed = c->cfg.precision == WANDQS_MIXED;
-    if (helm) {  // k2 on the tile levels 1..lc
+    {  // k2 on the tile levels 1..lc
         for (int l = 1; l <= c->lc; ++l) {
             const wq::Level& F = c->lev[l - 1];
             const wq::Level& C = c->lev[l];
@@ -2379,6 +2375,20 @@ wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const 
         ProfScope ps(c, "k_coarse_k2", 24.0 * tot);
         WQ_KLAUNCH(ps, k_coarse_k2, dim3(1), dim3(kCoarseThreads), 0, s, T.N, T.pitch, T.h, top,
                            c->k2lev, c->k2levf, c->idlevf);
+    }
+    WQ_LAUNCH_CHECK();
+    return WANDQS_OK;
+}
+
+wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const u[2],
+                       double* const f[2], const double* k2, SolveResult* res,
+                       const std::function<wandqs_status()>& ahead, bool k2_levels_ready) {
+    hipStream_t s = c->stream;
+    Hier<double> hz{{u[0], R > 1 ? u[1] : nullptr}, {f[0], R > 1 ? f[1] : nullptr}, k2};
+    const bool mixed = c->cfg.precision == WANDQS_MIXED;
+    if (helm && !k2_levels_ready) {
+        const wandqs_status st = helm_levels(c, k2);
+        if (st != WANDQS_OK) return st;
     }
     // one "cycle" is a V-cycle (FP64) or an outer defect-correction iteration
     // (mixed) that records its residual norms in `slot` (FP64: -1, none)

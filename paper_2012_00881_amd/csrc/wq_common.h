@@ -386,9 +386,14 @@ void fst_solve(wandqs_ctx* c, int R, const E* const* f, E* const* u);
 // solve reads, enqueued behind the first batch of cycles while the host waits
 // for its residual norms (so that the device does not idle), and enqueued once
 // more behind the last cycle when further cycles follow.
+// k2_levels_ready: helm_levels(c, k2) has run already for this k2.
 wandqs_status mg_solve(wandqs_ctx* c, int kind, int R, bool helm, double* const u[2],
                        double* const f[2], const double* k2, SolveResult* res,
-                       const std::function<wandqs_status()>& ahead = {});
+                       const std::function<wandqs_status()>& ahead = {},
+                       bool k2_levels_ready = false);
+// The Helmholtz operator's k2 on the coarser levels (full weighting level by
+// level, then the coarse kernel's dense levels), from the finest level's k2.
+wandqs_status helm_levels(wandqs_ctx* c, const double* k2);
 
 // particles and fields (particles.hip, fields.hip)
 wandqs_status slice_sort(wandqs_ctx* c);
