@@ -146,16 +146,27 @@ __device__ __forceinline__ LasTileNode las_node(int q, int RW, int RH, int ax0, 
 // so each half sweep leaves one more layer inside it exact.
 __device__ void tile_sweeps(double2 (*U)[kLRX], const double2 (*F)[kLRX], const double2 (*K)[kLRX],
                             int RW, int RH, int ax0, int by0, int n, double h2, int nu) {
+    // a thread visits the same nodes in every half sweep: their 1 / (4 + h^2 k)
+    // formed once, in registers
+    double2 idg[kLIt];
+#pragma unroll
+    for (int q = 0; q < kLIt; ++q) {
+        const int t = min((int)threadIdx.x + q * kLTThreads, RW * RH - 1);
+        const double2 kk = K[t / RW][t % RW];
+        idg[q] = cdiv(make_double2(1.0, 0.0), make_double2(4.0 + h2 * kk.x, h2 * kk.y));
+    }
     for (int s = 0; s < nu; ++s)
         for (int color = 0; color < 2; ++color) {
-            for (int t = threadIdx.x; t < RW * RH; t += kLTThreads) {
+#pragma unroll
+            for (int q = 0; q < kLIt; ++q) {
+                const int t = threadIdx.x + q * kLTThreads;
+                if (t >= RW * RH) break;
                 const int lx = t % RW, ly = t / RW;
                 const int a = ax0 + lx, b = by0 + ly;
                 if (lx < 1 || ly < 1 || lx > RW - 2 || ly > RH - 2) continue;
                 if (a < 1 || b < 1 || a > n - 1 || b > n - 1 || ((a + b) & 1) != color) continue;
                 const double2 nb = cadd(cadd(U[ly][lx - 1], U[ly][lx + 1]), cadd(U[ly - 1][lx], U[ly + 1][lx]));
-                const double2 kk = K[ly][lx];
-                U[ly][lx] = cdiv(csub(nb, cscl(h2, F[ly][lx])), make_double2(4.0 + h2 * kk.x, h2 * kk.y));
+                U[ly][lx] = cmul(csub(nb, cscl(h2, F[ly][lx])), idg[q]);
             }
             __syncthreads();
         }
